@@ -1,0 +1,436 @@
+"""CPU oracle for the SieveJoin hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. The GPU library never loads it and shares
+no code with it.
+
+What it computes (arXiv 2308.16370):
+
+* ``hash_join``  -- the exact multi-way join result by a plain left-deep binary
+  hash-join plan with no filters (the enumeration phase of Section 2.2 with the
+  pruning switched off), as sorted row-id tuples plus count and checksum.
+* ``join_tree_dp`` -- count and checksum of an acyclic join by the sum-product
+  recursion over the join tree (Yannakakis-style, the paper's reference list
+  includes it); independent of ``hash_join``.
+* ``bf_*``       -- the blocked Bloom filter (Section 2.1 step 1, Bloom's bit vector
+  in its cache-blocked form) under the hash/bit-pattern reading stated in
+  ``oracle.c``.
+* ``sieve``      -- the pruning phase (Section 2.2): one backward pass from the
+  right-most relation to the root, each relation probed by the filters of the
+  relations after it and building the filter on its own join attribute from its
+  survivors; the closing-edge filter of cyclic queries (Section 2.3); and the
+  optional forward pass (the dotted arrow of Fig. 2) that sieves the relations on
+  the right with filters of their already-pruned left neighbours.
+
+The checksum of a result is sum over tuples of prod_i (mix64((i << 32) | rid_i) | 1)
+modulo 2^64, with mix64 the SplitMix64 output function.
+
+Every function here is pinned by tests/test_oracle_*.py against brute force, closed
+forms, the paper's worked example and the filter's probability laws.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+U64 = np.uint64
+MASK64 = (1 << 64) - 1
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc into liboracle.so (plain -O2, no vectorisation flags)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            L = ctypes.CDLL(_LIB)
+            c_u32p = ctypes.POINTER(ctypes.c_uint32)
+            L.orc_fmix32.argtypes = [ctypes.c_uint32]
+            L.orc_fmix32.restype = ctypes.c_uint32
+            L.orc_mix64.argtypes = [ctypes.c_uint64]
+            L.orc_mix64.restype = ctypes.c_uint64
+            L.orc_chk_factor.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+            L.orc_chk_factor.restype = ctypes.c_uint64
+            L.orc_bf_nblocks.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int]
+            L.orc_bf_nblocks.restype = ctypes.c_uint64
+            L.orc_bf_pattern.argtypes = [ctypes.c_int32, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_uint32, c_u32p]
+            L.orc_bf_pattern.restype = ctypes.c_uint32
+            L.orc_bf_build.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                       ctypes.c_uint32, ctypes.c_int, ctypes.c_int, ctypes.c_uint32]
+            L.orc_bf_build.restype = None
+            L.orc_bf_probe.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                       ctypes.c_uint32, ctypes.c_int, ctypes.c_int, ctypes.c_uint32,
+                                       ctypes.c_void_p]
+            L.orc_bf_probe.restype = None
+            ip = ctypes.POINTER(ctypes.c_int)
+            L.orc_hash_join.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_int, ip, ip, ip, ip, ctypes.c_int,
+                                        ip, ip, ip, ip, ip]
+            L.orc_hash_join.restype = ctypes.c_void_p
+            L.orc_result_count.argtypes = [ctypes.c_void_p]
+            L.orc_result_count.restype = ctypes.c_int64
+            L.orc_result_checksum.argtypes = [ctypes.c_void_p]
+            L.orc_result_checksum.restype = ctypes.c_uint64
+            L.orc_result_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+            L.orc_result_copy.restype = None
+            L.orc_result_free.argtypes = [ctypes.c_void_p]
+            L.orc_result_free.restype = None
+            _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------- mixers / checksum
+
+def fmix32(x: int) -> int:
+    return int(lib().orc_fmix32(x & 0xFFFFFFFF))
+
+
+def mix64(x: int) -> int:
+    return int(lib().orc_mix64(x & MASK64))
+
+
+def mix64_np(z: np.ndarray) -> np.ndarray:
+    """SplitMix64 output function on a uint64 array (wrapping arithmetic)."""
+    z = z.astype(U64, copy=True)
+    z ^= z >> U64(30)
+    z *= U64(0xBF58476D1CE4E5B9)
+    z ^= z >> U64(27)
+    z *= U64(0x94D049BB133111EB)
+    z ^= z >> U64(31)
+    return z
+
+
+def chk_factor_np(rel: int, rids: np.ndarray) -> np.ndarray:
+    """mix64((rel << 32) | rid) | 1 for every rid."""
+    z = (U64(rel) << U64(32)) | rids.astype(U64)
+    return mix64_np(z) | U64(1)
+
+
+def filter_seed(seed: int) -> int:
+    """The 32-bit filter hash seed derived from the 64-bit user seed."""
+    return mix64(seed) & 0xFFFFFFFF
+
+
+# ---------------------------------------------------------------- Bloom filter
+
+def log2_block(block_bits: int) -> int:
+    lb = int(block_bits).bit_length() - 1
+    if block_bits not in (256, 512, 1024):
+        raise ValueError("block_bits must be 256, 512 or 1024")
+    return lb
+
+
+def bf_nblocks(n: int, bits_per_key: int, block_bits: int = 512) -> int:
+    return int(lib().orc_bf_nblocks(int(n), int(bits_per_key), log2_block(block_bits)))
+
+
+def bf_pattern(key: int, nblocks: int, k: int, block_bits: int, seed32: int) -> Tuple[int, List[int]]:
+    pos = (ctypes.c_uint32 * 64)()
+    b = lib().orc_bf_pattern(int(np.int32(key)), nblocks, k, log2_block(block_bits), seed32, pos)
+    return int(b), [int(pos[i]) for i in range(k)]
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def bf_build(keys: np.ndarray, rows: Optional[np.ndarray], nblocks: int, k: int,
+             block_bits: int, seed32: int) -> np.ndarray:
+    """Filter words (uint32, nblocks * block_bits/32) holding keys[rows] (or all keys)."""
+    keys = np.ascontiguousarray(keys, dtype=np.int32)
+    words = np.zeros(nblocks * (block_bits // 32), dtype=np.uint32)
+    n = keys.shape[0] if rows is None else rows.shape[0]
+    if rows is not None:
+        rows = np.ascontiguousarray(rows, dtype=np.uint32)
+    lib().orc_bf_build(_ptr(keys), _ptr(rows), n, _ptr(words), nblocks, k, log2_block(block_bits), seed32)
+    return words
+
+
+def bf_probe(words: np.ndarray, keys: np.ndarray, rows: Optional[np.ndarray], nblocks: int, k: int,
+             block_bits: int, seed32: int) -> np.ndarray:
+    """Boolean array: does the filter report keys[rows[i]] (or keys[i]) present."""
+    keys = np.ascontiguousarray(keys, dtype=np.int32)
+    n = keys.shape[0] if rows is None else rows.shape[0]
+    if rows is not None:
+        rows = np.ascontiguousarray(rows, dtype=np.uint32)
+    out = np.zeros(n, dtype=np.uint8)
+    lib().orc_bf_probe(_ptr(keys), _ptr(rows), n, _ptr(np.ascontiguousarray(words, dtype=np.uint32)),
+                       nblocks, k, log2_block(block_bits), seed32, _ptr(out))
+    return out.astype(bool)
+
+
+# ---------------------------------------------------------------- join graph
+
+class JoinTree:
+    """Root, spanning tree and closing edges of a join graph.
+
+    The tree is found by depth-first search from the root that follows each
+    relation's edges in input order; edges not taken by the search are closing
+    edges. For a closing edge, ``u`` is the end visited first (preorder) and ``v``
+    the other.
+    """
+
+    def __init__(self, nrels: int, edges: Sequence[Tuple[int, int, int, int]], root: int = 0):
+        self.n = nrels
+        self.root = root
+        adj: List[List[Tuple[int, int, int, int]]] = [[] for _ in range(nrels)]
+        for ei, (ra, ca, rb, cb) in enumerate(edges):
+            if not (0 <= ra < nrels and 0 <= rb < nrels) or ra == rb:
+                raise ValueError("bad edge %r" % (edges[ei],))
+            adj[ra].append((ei, rb, ca, cb))
+            adj[rb].append((ei, ra, cb, ca))
+        self.parent = [-1] * nrels
+        self.pcol = [-1] * nrels     # column of the parent on the tree edge to this relation
+        self.mycol = [-1] * nrels    # this relation's column on its tree edge to the parent
+        self.children: List[List[int]] = [[] for _ in range(nrels)]
+        self.preorder: List[int] = []
+        tree_edges = set()
+        seen = [False] * nrels
+
+        def dfs(u):
+            seen[u] = True
+            self.preorder.append(u)
+            for ei, v, cu, cv in adj[u]:
+                if not seen[v]:
+                    tree_edges.add(ei)
+                    self.parent[v], self.pcol[v], self.mycol[v] = u, cu, cv
+                    self.children[u].append(v)
+                    dfs(v)
+
+        dfs(root)
+        if not all(seen):
+            raise ValueError("join graph is not connected")
+        pre = {r: i for i, r in enumerate(self.preorder)}
+        self.closing = []            # (u, col_u, v, col_v) in input order
+        for ei, (ra, ca, rb, cb) in enumerate(edges):
+            if ei in tree_edges:
+                continue
+            if pre[ra] < pre[rb]:
+                self.closing.append((ra, ca, rb, cb))
+            else:
+                self.closing.append((rb, cb, ra, ca))
+        self.postorder: List[int] = []
+
+        def post(u):
+            for c in self.children[u]:
+                post(c)
+            self.postorder.append(u)
+
+        post(root)
+
+
+def eligible(rel) -> np.ndarray:
+    """Ascending row ids that pass the relation's predicate lo <= v < hi."""
+    n = rel.nrows
+    if rel.pred is None:
+        return np.arange(n, dtype=np.uint32)
+    c, lo, hi = rel.pred
+    v = rel.cols[c].astype(np.int64)
+    return np.nonzero((v >= lo) & (v < hi))[0].astype(np.uint32)
+
+
+# ---------------------------------------------------------------- hash join
+
+def hash_join(query, root: Optional[int] = None):
+    """Sorted result row-id tuples (uint32 [count, nrels]), count, checksum."""
+    root = query.root if root is None else root
+    n = len(query.rels)
+    t = JoinTree(n, query.edges, root)
+    maxcols = max(len(r.cols) for r in query.rels)
+    keep = []
+    colptrs = (ctypes.c_void_p * (n * maxcols))()
+    for r, rel in enumerate(query.rels):
+        for c, col in enumerate(rel.cols):
+            a = np.ascontiguousarray(col, dtype=np.int32)
+            keep.append(a)
+            colptrs[r * maxcols + c] = a.ctypes.data
+    sels = [eligible(rel) for rel in query.rels]
+    selptrs = (ctypes.c_void_p * n)(*[s.ctypes.data if s.size else None for s in sels])
+    nsel = (ctypes.c_int64 * n)(*[int(s.shape[0]) for s in sels])
+    order = t.preorder
+    steps = order[1:]
+    IA = ctypes.c_int * max(1, n - 1)
+    child = IA(*steps)
+    ccol = IA(*[t.mycol[c] for c in steps])
+    par = IA(*[t.parent[c] for c in steps])
+    pcol = IA(*[t.pcol[c] for c in steps])
+    pos = {r: i for i, r in enumerate(order)}
+    nc = len(t.closing)
+    CA = ctypes.c_int * max(1, nc)
+    after = [max(pos[u], pos[v]) - 1 for (u, _, v, _) in t.closing]
+    res = lib().orc_hash_join(n, maxcols, colptrs, selptrs, nsel, root, child, ccol, par, pcol, nc,
+                              CA(*[c[0] for c in t.closing]), CA(*[c[1] for c in t.closing]),
+                              CA(*[c[2] for c in t.closing]), CA(*[c[3] for c in t.closing]),
+                              CA(*after))
+    if not res:
+        raise MemoryError("oracle hash join ran out of memory")
+    try:
+        cnt = int(lib().orc_result_count(res))
+        chk = int(lib().orc_result_checksum(res))
+        out = np.empty((cnt, n), dtype=np.uint32)
+        lib().orc_result_copy(res, out.ctypes.data_as(ctypes.c_void_p))
+    finally:
+        lib().orc_result_free(res)
+    return out, cnt, chk
+
+
+def checksum_of(tuples: np.ndarray) -> int:
+    """Checksum of a [count, nrels] row-id tuple array."""
+    if tuples.shape[0] == 0:
+        return 0
+    f = np.ones(tuples.shape[0], dtype=U64)
+    for r in range(tuples.shape[1]):
+        f *= chk_factor_np(r, tuples[:, r])
+    return int(np.sum(f, dtype=U64))
+
+
+# ---------------------------------------------------------------- join-tree DP
+
+def _group_sum(keys: np.ndarray, vals: List[np.ndarray]):
+    """Distinct sorted keys and the (wrapping uint64) sum of each value array per key."""
+    if keys.shape[0] == 0:
+        return keys.astype(np.int64), [np.zeros(0, dtype=U64) for _ in vals]
+    order = np.argsort(keys, kind="stable")
+    ks = keys[order]
+    starts = np.concatenate([[0], np.nonzero(ks[1:] != ks[:-1])[0] + 1])
+    return ks[starts].astype(np.int64), [np.add.reduceat(v[order], starts, dtype=U64) for v in vals]
+
+
+def _lookup(ukeys: np.ndarray, sums: np.ndarray, q: np.ndarray) -> np.ndarray:
+    if ukeys.shape[0] == 0:
+        return np.zeros(q.shape[0], dtype=U64)
+    i = np.searchsorted(ukeys, q.astype(np.int64))
+    i = np.minimum(i, ukeys.shape[0] - 1)
+    hit = ukeys[i] == q
+    return np.where(hit, sums[i], U64(0))
+
+
+def join_tree_dp(query, root: Optional[int] = None, sels: Optional[List[np.ndarray]] = None):
+    """(count, checksum) of an acyclic join by the sum-product recursion over its tree.
+
+    Leaves up: a row's weight is the product over its children c of the summed
+    weights of c's rows that match it; the checksum weight multiplies in the row's
+    own factor mix64((rel << 32) | rid) | 1. ``sels`` optionally restricts each
+    relation to the given rows (default: the predicate's eligible rows).
+    """
+    root = query.root if root is None else root
+    n = len(query.rels)
+    t = JoinTree(n, query.edges, root)
+    if t.closing:
+        raise ValueError("join-tree DP needs an acyclic join graph")
+    if sels is None:
+        sels = [eligible(r) for r in query.rels]
+    agg = {}
+    for j in t.postorder:
+        rel = query.rels[j]
+        sel = sels[j]
+        cnt = np.ones(sel.shape[0], dtype=U64)
+        val = chk_factor_np(j, sel)
+        for c in t.children[j]:
+            keys = rel.cols[t.pcol[c]][sel]
+            uk, (ws, vs) = agg[c]
+            cnt *= _lookup(uk, ws, keys)
+            val *= _lookup(uk, vs, keys)
+        if j == root:
+            return int(np.sum(cnt, dtype=U64)), int(np.sum(val, dtype=U64))
+        uk, sums = _group_sum(rel.cols[t.mycol[j]][sel], [cnt, val])
+        agg[j] = (uk, sums)
+    raise AssertionError("unreachable")
+
+
+# ---------------------------------------------------------------- pruning phase
+
+class _BloomFactory:
+    def __init__(self, bits_per_key, k, block_bits, seed):
+        self.bpk, self.k, self.B = bits_per_key, k, block_bits
+        self.seed32 = filter_seed(seed)
+
+    def build(self, keys, rows, n_elig):
+        nb = bf_nblocks(n_elig, self.bpk, self.B)
+        return (bf_build(keys, rows, nb, self.k, self.B, self.seed32), nb)
+
+    def probe(self, f, keys, rows):
+        words, nb = f
+        return bf_probe(words, keys, rows, nb, self.k, self.B, self.seed32)
+
+
+class _ExactFactory:
+    """Exact key sets in place of filters (for the full-reducer pins)."""
+
+    def build(self, keys, rows, n_elig):
+        return np.unique(keys[rows].astype(np.int64))
+
+    def probe(self, f, keys, rows):
+        return np.isin(keys[rows].astype(np.int64), f)
+
+
+def sieve(query, bits_per_key: int = 8, k: int = 6, block_bits: int = 512, passes: int = 2,
+          seed: int = 0, root: Optional[int] = None, exact: bool = False):
+    """Survivor row ids of every relation after the pruning phase, and the filters.
+
+    Returns ``(survivors, filters)``: survivors[r] is an ascending uint32 array;
+    filters maps ('bwd', j) / ('fwd', j) / ('close', e) to (words, nblocks) -- or to
+    a key set when ``exact``. A filter built on relation x's column is sized for
+    x's predicate-eligible row count at ``bits_per_key``.
+    """
+    root = query.root if root is None else root
+    rels = query.rels
+    t = JoinTree(len(rels), query.edges, root)
+    fac = _ExactFactory() if exact else _BloomFactory(bits_per_key, k, block_bits, seed)
+    elig = [eligible(r) for r in rels]
+    nel = [int(e.shape[0]) for e in elig]
+    S: Dict[int, np.ndarray] = {}
+    F: Dict[tuple, object] = {}
+
+    # backward pass: right-most relations first, each sieved by its children's filters
+    for j in t.postorder:
+        rows = elig[j]
+        for c in t.children[j]:
+            rows = rows[fac.probe(F[("bwd", c)], rels[j].cols[t.pcol[c]], rows)]
+        S[j] = rows
+        if j != root:
+            F[("bwd", j)] = fac.build(rels[j].cols[t.mycol[j]], rows, nel[j])
+
+    if passes == 1:
+        # closing edges: filter on the earlier end's survivors sieves the later end
+        for e, (u, cu, v, cv) in enumerate(t.closing):
+            F[("close", e)] = fac.build(rels[u].cols[cu], S[u], nel[u])
+            S[v] = S[v][fac.probe(F[("close", e)], rels[v].cols[cv], S[v])]
+    elif passes == 2:
+        # forward pass: root to leaves, each relation sieved by its parent's survivors
+        for x in t.preorder:
+            if x != root:
+                rows = S[x]
+                rows = rows[fac.probe(F[("fwd", x)], rels[x].cols[t.mycol[x]], rows)]
+                for e, (u, cu, v, cv) in enumerate(t.closing):
+                    if v == x:
+                        rows = rows[fac.probe(F[("close", e)], rels[x].cols[cv], rows)]
+                S[x] = rows
+            for c in t.children[x]:
+                F[("fwd", c)] = fac.build(rels[x].cols[t.pcol[c]], S[x], nel[x])
+            for e, (u, cu, v, cv) in enumerate(t.closing):
+                if u == x:
+                    F[("close", e)] = fac.build(rels[x].cols[cu], S[x], nel[x])
+    else:
+        raise ValueError("passes must be 1 or 2")
+    return [S[r] for r in range(len(rels))], F

@@ -1,0 +1,329 @@
+/*
+ * CPU oracle for the SieveJoin hot path -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, single-threaded C. Nothing here is tuned; every routine follows the
+ * definition it implements as literally as possible so that a reader can check it
+ * against the paper (arXiv 2308.16370, "SieveJoin: Boosting Multi-Way Joins with
+ * Reusable Bloom Filters") by eye. Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library; the GPU path never does.
+ *
+ * Contents
+ *   1. Hash mixers (published definitions, see each function).
+ *   2. The blocked Bloom filter: build (set bits) and probe (contains), i.e. the
+ *      filter of Section 2.1 step 1 ("by the linear scanning and hashing of every
+ *      tuple ... the corresponding bit ... is set to 1") in its cache-blocked form.
+ *      The paper does not fix a hash family or bit pattern; the reading used here is:
+ *        h     = fmix32((u32)key ^ seed)
+ *        block = floor(h * nblocks / 2^32)
+ *        g     = h * 0x9E3779B1 (mod 2^32),  g = g ^ (g >> 16)
+ *        bit i = the top logB bits of g * M_i (mod 2^32), i = 0 .. k-1, k <= 12,
+ *                with M_i the odd constants of bf_mult[] below
+ *      i.e. k independent, uniformly placed bits inside one block of B bits (two
+ *      of a key's bits may coincide). Block b occupies 32-bit words
+ *      [b*B/32, (b+1)*B/32); bit p of a block is bit (p mod 32) of word (p / 32).
+ *   3. The multi-way join result by a plain left-deep binary hash-join plan with no
+ *      filters (the enumeration phase of Section 2.2 without pruning), sorted, plus
+ *      its count and checksum.
+ *
+ * Parity pins for everything in this file live in tests/test_oracle_*.py.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- 1. mixers */
+
+/* MurmurHash3 32-bit finaliser (Austin Appleby, public domain). */
+uint32_t orc_fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+/* SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014). */
+uint64_t orc_mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+/* Per-tuple checksum factor of relation i's row id: mix64((i << 32) | rid) | 1. */
+uint64_t orc_chk_factor(uint32_t rel, uint32_t rid)
+{
+    return orc_mix64(((uint64_t)rel << 32) | (uint64_t)rid) | 1ull;
+}
+
+/* ------------------------------------------------------- 2. blocked Bloom filter */
+
+/* Odd multipliers that spread the second hash word over the k bit positions. */
+static const uint32_t bf_mult[12] = {
+    0x85EBCA77u, 0xC2B2AE3Du, 0x27D4EB2Fu, 0x165667B1u, 0xD3A2646Du, 0xFD7046C5u,
+    0xB55A4F09u, 0x2545F491u, 0x9E6C63D1u, 0x7FEB352Du, 0x846CA68Bu, 0x68E31DA5u,
+};
+
+/* The k bit positions (0..B-1) of `key` and the index of its block. */
+static uint32_t bf_pattern(int32_t key, uint32_t nblocks, int k, int logB, uint32_t seed,
+                           uint32_t *pos)
+{
+    uint32_t h = orc_fmix32((uint32_t)key ^ seed);
+    uint32_t block = (uint32_t)(((uint64_t)h * (uint64_t)nblocks) >> 32);
+    uint32_t g = h * 0x9E3779B1u;
+    g ^= g >> 16;
+    for (int i = 0; i < k; i++)
+        pos[i] = (g * bf_mult[i]) >> (32 - logB);
+    return block;
+}
+
+/* Number of blocks for n keys at bits_per_key: ceil(bpk * n / B), at least 1. */
+uint64_t orc_bf_nblocks(uint64_t n, uint32_t bits_per_key, int logB)
+{
+    uint64_t B = 1ull << logB;
+    uint64_t nb = (n * (uint64_t)bits_per_key + B - 1) / B;
+    return nb ? nb : 1;
+}
+
+/* Block index and bit positions of one key (exported for the pattern tests). */
+uint32_t orc_bf_pattern(int32_t key, uint32_t nblocks, int k, int logB, uint32_t seed,
+                        uint32_t *pos_out)
+{
+    return bf_pattern(key, nblocks, k, logB, seed, pos_out);
+}
+
+/* Insert keys[rows[i]] (or keys[i] when rows is NULL) for i < n into the filter. */
+void orc_bf_build(const int32_t *keys, const uint32_t *rows, int64_t n, uint32_t *words,
+                  uint32_t nblocks, int k, int logB, uint32_t seed)
+{
+    uint32_t pos[64];
+    uint32_t wpb = (1u << logB) / 32u;
+    for (int64_t i = 0; i < n; i++) {
+        int32_t key = rows ? keys[rows[i]] : keys[i];
+        uint32_t b = bf_pattern(key, nblocks, k, logB, seed, pos);
+        for (int j = 0; j < k; j++)
+            words[(uint64_t)b * wpb + pos[j] / 32u] |= 1u << (pos[j] % 32u);
+    }
+}
+
+/* out[i] = 1 when every bit of keys[rows[i]]'s pattern is set, else 0. */
+void orc_bf_probe(const int32_t *keys, const uint32_t *rows, int64_t n, const uint32_t *words,
+                  uint32_t nblocks, int k, int logB, uint32_t seed, uint8_t *out)
+{
+    uint32_t pos[64];
+    uint32_t wpb = (1u << logB) / 32u;
+    for (int64_t i = 0; i < n; i++) {
+        int32_t key = rows ? keys[rows[i]] : keys[i];
+        uint32_t b = bf_pattern(key, nblocks, k, logB, seed, pos);
+        uint8_t hit = 1;
+        for (int j = 0; j < k; j++)
+            if (!(words[(uint64_t)b * wpb + pos[j] / 32u] & (1u << (pos[j] % 32u))))
+                hit = 0;
+        out[i] = hit;
+    }
+}
+
+/* ------------------------------------------------- 3. binary hash-join plan */
+
+/*
+ * One join step s = 1..nsteps: bind relation child[s] through the equality
+ *     R_child[child_col] == R_parent[parent_col]
+ * where parent was bound by an earlier step (step 0 binds the root). After the
+ * step, every closing equality listed for it is checked on the new tuples.
+ *
+ * Relations are given as flat arrays: nrows[r], the column pointer table
+ * cols[r*maxcols + c], and the predicate (pred_col[r] < 0: none; keep
+ * lo <= v < hi). Only the rows of `sel[r]` (ascending row ids, nsel[r] of them)
+ * take part -- the caller evaluates the predicates.
+ */
+typedef struct {
+    uint32_t *t;      /* tuples, row-major, width w */
+    int64_t n, cap;
+    int w;
+} tupbuf;
+
+static int tb_push(tupbuf *b, const uint32_t *src, int w, int slot, uint32_t rid)
+{
+    if (b->n == b->cap) {
+        int64_t nc = b->cap ? b->cap * 2 : 1024;
+        uint32_t *p = (uint32_t *)realloc(b->t, (size_t)nc * (size_t)w * sizeof(uint32_t));
+        if (!p)
+            return -1;
+        b->t = p;
+        b->cap = nc;
+    }
+    uint32_t *d = b->t + b->n * w;
+    memcpy(d, src, (size_t)w * sizeof(uint32_t));
+    d[slot] = rid;
+    b->n++;
+    return 0;
+}
+
+/* Chained hash table: distinct keys in open-addressed slots, rows chained in
+ * ascending row-id order through next[]. */
+typedef struct {
+    int32_t *skey;
+    int64_t *shead;   /* -1: empty slot */
+    int64_t *next;    /* index into the selection, -1 ends a chain */
+    uint64_t mask;
+} chtab;
+
+static uint64_t slot_of(int32_t key, uint64_t mask)
+{
+    return orc_mix64((uint64_t)(uint32_t)key) & mask;
+}
+
+static int ch_build(chtab *h, const int32_t *col, const uint32_t *sel, int64_t nsel)
+{
+    uint64_t cap = 16;
+    while (cap < 2ull * (uint64_t)nsel + 1)
+        cap <<= 1;
+    h->mask = cap - 1;
+    h->skey = (int32_t *)calloc(cap, sizeof(int32_t));
+    h->shead = (int64_t *)malloc(cap * sizeof(int64_t));
+    h->next = (int64_t *)malloc(((size_t)nsel + 1) * sizeof(int64_t));
+    if (!h->skey || !h->shead || !h->next)
+        return -1;
+    for (uint64_t i = 0; i < cap; i++)
+        h->shead[i] = -1;
+    /* insert in descending order and push at the head: chains end up ascending */
+    for (int64_t i = nsel - 1; i >= 0; i--) {
+        int32_t key = col[sel[i]];
+        uint64_t s = slot_of(key, h->mask);
+        while (h->shead[s] >= 0 && h->skey[s] != key)
+            s = (s + 1) & h->mask;
+        if (h->shead[s] < 0)
+            h->skey[s] = key;
+        h->next[i] = h->shead[s];
+        h->shead[s] = i;
+    }
+    return 0;
+}
+
+static int64_t ch_find(const chtab *h, int32_t key)
+{
+    uint64_t s = slot_of(key, h->mask);
+    while (h->shead[s] >= 0) {
+        if (h->skey[s] == key)
+            return h->shead[s];
+        s = (s + 1) & h->mask;
+    }
+    return -1;
+}
+
+static void ch_free(chtab *h)
+{
+    free(h->skey);
+    free(h->shead);
+    free(h->next);
+}
+
+static int cmp_w;
+static int tuple_cmp(const void *a, const void *b)
+{
+    const uint32_t *x = (const uint32_t *)a, *y = (const uint32_t *)b;
+    for (int i = 0; i < cmp_w; i++) {
+        if (x[i] != y[i])
+            return x[i] < y[i] ? -1 : 1;
+    }
+    return 0;
+}
+
+typedef struct {
+    uint32_t *tuples;
+    int64_t count;
+    uint64_t checksum;
+    int nrels;
+} orc_result;
+
+/*
+ * Returns a heap result (free with orc_result_free) or NULL on allocation failure.
+ *   nrels, maxcols, cols[nrels*maxcols], sel[nrels], nsel[nrels]
+ *   root; nsteps = nrels-1; step arrays child/child_col/parent/parent_col [nsteps]
+ *   nclose closing equalities (ca_rel, ca_col, cb_rel, cb_col), each applied after
+ *   step close_after[i] (the first step where both relations are bound).
+ */
+orc_result *orc_hash_join(int nrels, int maxcols, const int32_t *const *cols,
+                          const uint32_t *const *sel, const int64_t *nsel, int root,
+                          const int *child, const int *child_col, const int *parent,
+                          const int *parent_col, int nclose, const int *ca_rel,
+                          const int *ca_col, const int *cb_rel, const int *cb_col,
+                          const int *close_after)
+{
+    int w = nrels;
+    tupbuf cur = {0}, nxt = {0};
+    cur.w = nxt.w = w;
+    uint32_t *zero = (uint32_t *)calloc((size_t)w, sizeof(uint32_t));
+    orc_result *res = (orc_result *)calloc(1, sizeof(orc_result));
+    if (!zero || !res)
+        return NULL;
+    for (int64_t i = 0; i < nsel[root]; i++)
+        if (tb_push(&cur, zero, w, root, sel[root][i]))
+            return NULL;
+    for (int s = 0; s < nrels - 1; s++) {
+        int c = child[s], cc = child_col[s], p = parent[s], pc = parent_col[s];
+        const int32_t *ccol = cols[c * maxcols + cc];
+        const int32_t *pcol = cols[p * maxcols + pc];
+        chtab h;
+        if (ch_build(&h, ccol, sel[c], nsel[c]))
+            return NULL;
+        nxt.n = 0;
+        for (int64_t i = 0; i < cur.n; i++) {
+            const uint32_t *t = cur.t + i * w;
+            for (int64_t j = ch_find(&h, pcol[t[p]]); j >= 0; j = h.next[j]) {
+                /* extend, then apply the closing equalities that become checkable */
+                if (tb_push(&nxt, t, w, c, sel[c][j]))
+                    return NULL;
+                const uint32_t *u = nxt.t + (nxt.n - 1) * w;
+                for (int e = 0; e < nclose; e++) {
+                    if (close_after[e] != s)
+                        continue;
+                    int32_t va = cols[ca_rel[e] * maxcols + ca_col[e]][u[ca_rel[e]]];
+                    int32_t vb = cols[cb_rel[e] * maxcols + cb_col[e]][u[cb_rel[e]]];
+                    if (va != vb) {
+                        nxt.n--;
+                        break;
+                    }
+                }
+            }
+        }
+        ch_free(&h);
+        tupbuf tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    free(nxt.t);
+    free(zero);
+    cmp_w = w;
+    if (cur.n > 1)
+        qsort(cur.t, (size_t)cur.n, (size_t)w * sizeof(uint32_t), tuple_cmp);
+    uint64_t chk = 0;
+    for (int64_t i = 0; i < cur.n; i++) {
+        uint64_t f = 1;
+        for (int r = 0; r < w; r++)
+            f *= orc_chk_factor((uint32_t)r, cur.t[i * w + r]);
+        chk += f;
+    }
+    res->tuples = cur.t;
+    res->count = cur.n;
+    res->checksum = chk;
+    res->nrels = w;
+    return res;
+}
+
+int64_t orc_result_count(const orc_result *r) { return r->count; }
+uint64_t orc_result_checksum(const orc_result *r) { return r->checksum; }
+void orc_result_copy(const orc_result *r, uint32_t *out)
+{
+    if (r->count)
+        memcpy(out, r->tuples, (size_t)r->count * (size_t)r->nrels * sizeof(uint32_t));
+}
+void orc_result_free(orc_result *r)
+{
+    if (r) {
+        free(r->tuples);
+        free(r);
+    }
+}
