@@ -1,0 +1,176 @@
+/*
+ * sievejoin.h -- C ABI of the MI355X (gfx950) SieveJoin hot path.
+ *
+ * Method: arXiv 2308.16370, "SieveJoin: Boosting Multi-Way Joins with Reusable
+ * Bloom Filters". A multi-way equi-join over integer key columns (the query
+ * R join_b S join_c T of Section 2.2, generalised to chain, star and cyclic join
+ * graphs) is answered in two phases:
+ *   pruning     -- a Bloom filter is built on each relation's join attribute and the
+ *                  filters are pushed from the right-most relation toward the root,
+ *                  each relation being sieved by the filters of the relations after
+ *                  it before it builds its own (Section 2.2, Fig. 2); cyclic queries
+ *                  add a filter for the closing condition (Section 2.3) and an
+ *                  optional forward pass sieves the relations on the right again
+ *                  (the dotted arrow of Fig. 2);
+ *   enumeration -- a binary hash-join plan over the sieved relations produces the
+ *                  exact result (Section 2.2).
+ * The result is exact: filters have no false negatives and every final match is
+ * an equality test.
+ *
+ * Conventions
+ *   - Every call returns an sj_status; SJ_OK is 0, errors are negative. No C++
+ *     exception crosses this boundary. sj_last_error() describes the last error
+ *     of a context.
+ *   - All pointers named *_dev are device (HBM) pointers; everything else is host.
+ *     Input columns and result buffers must be 16-byte aligned, the workspace
+ *     256-byte aligned.
+ *   - Inputs are borrowed: the caller keeps columns and workspace alive and
+ *     unmodified until sj_plan_destroy(). The library never allocates device
+ *     memory; the caller passes one workspace buffer (sj_bind_workspace).
+ *   - Work is enqueued on the context's stream (caller-owned hipStream_t).
+ *     Only sj_join() and calls given host output pointers wait for the stream.
+ *   - A plan is not thread-safe. Distinct plans may run on distinct streams.
+ *   - Keys are any int32 (no reserved value). Row ids are uint32 (a relation has
+ *     fewer than 2^31 rows); counts are uint64; the checksum is uint64 modulo 2^64.
+ *
+ * Result definition (the exact multiset the plan returns):
+ *   result   = { (rid_0, ..., rid_{n-1}) : every relation's predicate holds and
+ *                 R_a[col_a][rid_a] == R_b[col_b][rid_b] for every edge }
+ *   checksum = sum over result tuples of prod_i (mix64((i << 32) | rid_i) | 1),
+ *              modulo 2^64, with mix64 the SplitMix64 output function.
+ *   Tuples are written row-major, one int32 row id per relation in relation-index
+ *   order, sorted lexicographically in the plan's enumeration order (relations in
+ *   depth-first preorder from the root; for chains and stars listed root first,
+ *   that is relation-index order).
+ */
+#ifndef SIEVEJOIN_H
+#define SIEVEJOIN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sj_status;
+
+#define SJ_OK 0
+#define SJ_ERR_INVALID (-1)     /* bad argument, NULL pointer, out-of-range option */
+#define SJ_ERR_GRAPH (-2)       /* bad column/relation index, self-edge, disconnected graph */
+#define SJ_ERR_NOMEM (-3)       /* workspace smaller than sj_plan() asked for */
+#define SJ_ERR_CAPACITY (-4)    /* result buffer smaller than the result; nothing written */
+#define SJ_ERR_STATE (-5)       /* call out of order (e.g. sj_join before sj_sieve) */
+#define SJ_ERR_DEVICE (-6)      /* a HIP runtime call failed */
+#define SJ_ERR_UNSUPPORTED (-7) /* valid query outside what this build executes */
+
+#define SJ_MAX_RELS 16
+#define SJ_MAX_COLS 64
+#define SJ_MAX_EDGES 32
+
+typedef struct sj_ctx sj_ctx;
+typedef struct sj_plan_s sj_plan_t;
+
+/* One relation instance. The same device columns may back several instances
+ * (self-joins). Row r takes part iff pred_col < 0 or
+ * pred_lo <= cols[pred_col][r] < pred_hi. */
+typedef struct {
+    int64_t nrows;                 /* 0 <= nrows < 2^31 */
+    int32_t ncols;                 /* 1 <= ncols <= SJ_MAX_COLS */
+    const int32_t *const *cols;    /* host array of ncols device pointers, nrows int32 each */
+    int32_t pred_col;              /* -1: no predicate */
+    int32_t pred_lo, pred_hi;
+} sj_rel;
+
+/* Equi-join condition R_{rel_a}[col_a] == R_{rel_b}[col_b]. Edges not on the
+ * spanning tree found from the root are closing edges (cyclic queries). */
+typedef struct {
+    int32_t rel_a, col_a, rel_b, col_b;
+} sj_edge;
+
+/* Filter and schedule options. A zero field takes the default in brackets. */
+typedef struct {
+    uint32_t bits_per_key; /* [8] filter bits per predicate-eligible row of the relation it is built on */
+    uint32_t k;            /* [6] bits set per key, 1..12 */
+    uint32_t block_bits;   /* [512] filter block size: 256, 512 or 1024 bits */
+    uint32_t passes;       /* [2] 1: the paper's backward pass only; 2: plus the forward pass */
+    uint64_t seed;         /* filter hash seed (0 is a valid seed) */
+    int32_t root;          /* -1: relation 0 (the left-most relation) */
+    uint32_t flags;        /* reserved, must be 0 */
+} sj_opts;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). The stream stays caller-owned. */
+sj_status sj_ctx_create(int32_t device, void *hip_stream, sj_ctx **out);
+sj_status sj_ctx_set_stream(sj_ctx *ctx, void *hip_stream);
+sj_status sj_ctx_destroy(sj_ctx *ctx);
+/* Text of the context's last error ("" if none); valid until the next call on ctx. */
+const char *sj_last_error(const sj_ctx *ctx);
+
+/* Validate the join graph (Section 2.2: relations with join attributes joined by
+ * equalities) and build the execution plan: the root and depth-first spanning
+ * tree, the closing edges, the backward/closing/forward filter schedule and the
+ * size of every filter (ceil(bits_per_key * eligible rows / block_bits) blocks),
+ * survivor list, hash table and scan buffer. Host-only; launches nothing.
+ * *workspace_bytes receives the device workspace the plan needs (worst case: every
+ * row survives). `opts` may be NULL (all defaults). */
+sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, const sj_edge *edges,
+                  int32_t nedges, const sj_opts *opts, sj_plan_t **out, uint64_t *workspace_bytes);
+
+/* Give the plan its device workspace (256-byte aligned, >= workspace_bytes). */
+sj_status sj_bind_workspace(sj_plan_t *plan, void *workspace_dev, uint64_t bytes);
+
+/* Pruning phase, backward pass (Section 2.2 step 1): for every non-root relation
+ * from the leaves toward the root, scan its rows, keep those whose child-edge keys
+ * all pass the children's filters, and insert the survivors' parent-edge keys into
+ * the relation's own blocked Bloom filter. Asynchronous. */
+sj_status sj_build_filters(sj_plan_t *plan);
+
+/* Root sieve, closing-edge filters (Section 2.3) and, with passes = 2, the forward
+ * pass; every relation ends as an ascending list of surviving row ids. With
+ * survivors != NULL the call waits and writes each relation's survivor count to
+ * survivors[0..nrels). */
+sj_status sj_sieve(sj_plan_t *plan, uint64_t *survivors);
+
+/* Enumeration phase, count pass (Section 2.2 step 2): hash tables on the sieved
+ * relations, exact result size and checksum. Waits for the stream; count and
+ * checksum are host pointers (either may be NULL). Acyclic graphs and cyclic
+ * graphs whose closing edges all end at the last relation of the preorder, which
+ * must be a leaf, are executed; other cyclic graphs return SJ_ERR_UNSUPPORTED. */
+sj_status sj_join(sj_plan_t *plan, uint64_t *count, uint64_t *checksum);
+
+/* Materialise the result: count * nrels int32 row ids, row-major, into out_dev
+ * (room for capacity_tuples tuples). Fails with SJ_ERR_CAPACITY, writing nothing,
+ * if capacity_tuples < count. Asynchronous. */
+sj_status sj_result(sj_plan_t *plan, int32_t *out_dev, uint64_t capacity_tuples);
+
+sj_status sj_plan_destroy(sj_plan_t *plan);
+
+/* ---- introspection (filters and survivors; used to check the pruning phase) ---- */
+
+#define SJ_FILTER_BACKWARD 0 /* built on relation `rel` (its parent-edge column) in the backward pass */
+#define SJ_FILTER_FORWARD 1  /* built on the parent of `rel` toward `rel` in the forward pass */
+#define SJ_FILTER_CLOSING 2  /* built on the earlier end of closing edge `index` */
+
+/* Number of filters the plan builds. */
+sj_status sj_filter_count(const sj_plan_t *plan, int32_t *nfilters);
+/* Identity of filter f: kind (SJ_FILTER_*), the relation it belongs to (rel for
+ * backward/forward, the closing edge's ordinal among closing edges for closing),
+ * the relation and column its keys come from, and its size in blocks. Reading
+ * nblocks waits for the stream (the size of a filter on a relation with a
+ * predicate is computed on the device). */
+sj_status sj_filter_desc(sj_plan_t *plan, int32_t f, int32_t *kind, int32_t *index, int32_t *src_rel,
+                         int32_t *src_col, uint32_t *nblocks);
+/* Device-to-device copy of filter f's words (nblocks * block_bits / 32 uint32)
+ * into dst_dev (room for capacity_words). Asynchronous. */
+sj_status sj_filter_copy(sj_plan_t *plan, int32_t f, uint32_t *dst_dev, uint64_t capacity_words);
+/* Copy relation rel's final survivor row ids (ascending) into dst_dev (room for
+ * capacity); *n receives the count. dst_dev may be NULL to query the count only.
+ * Waits for the stream. */
+sj_status sj_survivors_copy(sj_plan_t *plan, int32_t rel, uint32_t *dst_dev, uint64_t capacity,
+                            uint64_t *n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIEVEJOIN_H */

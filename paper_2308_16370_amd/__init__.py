@@ -1,0 +1,261 @@
+"""Python binding of the SieveJoin C ABI (include/sievejoin.h) for MI355X.
+
+Argument marshalling only: every step of the sieve and the join runs in the HIP
+kernels of ``libsievejoin.so``. PyTorch supplies device memory (input columns, the
+plan's workspace, result buffers) and the HIP stream.
+
+    import torch, paper_2308_16370_amd as sj
+    ctx = sj.Context()
+    plan = sj.Plan(ctx, [sj.Rel([a, b]), sj.Rel([b2, c], pred=(1, 0, 10))],
+                   [(0, 1, 1, 0)], bits_per_key=8, k=6)
+    plan.build_filters(); plan.sieve()
+    count, checksum = plan.join()
+    tuples = plan.result()        # int32 [count, nrels] row ids on the GPU
+
+The library must be built first (``__graft_entry__.build()`` or
+``python paper_2308_16370_amd/_build.py``); loading fails loudly if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsievejoin.so")
+
+SJ_OK = 0
+SJ_ERR_INVALID = -1
+SJ_ERR_GRAPH = -2
+SJ_ERR_NOMEM = -3
+SJ_ERR_CAPACITY = -4
+SJ_ERR_STATE = -5
+SJ_ERR_DEVICE = -6
+SJ_ERR_UNSUPPORTED = -7
+_NAMES = {0: "SJ_OK", -1: "SJ_ERR_INVALID", -2: "SJ_ERR_GRAPH", -3: "SJ_ERR_NOMEM", -4: "SJ_ERR_CAPACITY",
+          -5: "SJ_ERR_STATE", -6: "SJ_ERR_DEVICE", -7: "SJ_ERR_UNSUPPORTED"}
+
+SJ_FILTER_BACKWARD = 0
+SJ_FILTER_FORWARD = 1
+SJ_FILTER_CLOSING = 2
+
+EXPORTED = ["sj_ctx_create", "sj_ctx_set_stream", "sj_ctx_destroy", "sj_last_error", "sj_plan",
+            "sj_bind_workspace", "sj_build_filters", "sj_sieve", "sj_join", "sj_result", "sj_plan_destroy",
+            "sj_filter_count", "sj_filter_desc", "sj_filter_copy", "sj_survivors_copy"]
+
+
+class SjError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+class _Rel(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int32),
+                ("cols", ctypes.POINTER(ctypes.c_void_p)), ("pred_col", ctypes.c_int32),
+                ("pred_lo", ctypes.c_int32), ("pred_hi", ctypes.c_int32)]
+
+
+class _Edge(ctypes.Structure):
+    _fields_ = [("rel_a", ctypes.c_int32), ("col_a", ctypes.c_int32), ("rel_b", ctypes.c_int32),
+                ("col_b", ctypes.c_int32)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("bits_per_key", ctypes.c_uint32), ("k", ctypes.c_uint32), ("block_bits", ctypes.c_uint32),
+                ("passes", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("root", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsievejoin.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        P, V = ctypes.POINTER, ctypes.c_void_p
+        i32, u32, u64 = ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64
+        sig = {
+            "sj_ctx_create": [i32, V, P(V)],
+            "sj_ctx_set_stream": [V, V],
+            "sj_ctx_destroy": [V],
+            "sj_plan": [V, P(_Rel), i32, P(_Edge), i32, P(_Opts), P(V), P(u64)],
+            "sj_bind_workspace": [V, V, u64],
+            "sj_build_filters": [V],
+            "sj_sieve": [V, P(u64)],
+            "sj_join": [V, P(u64), P(u64)],
+            "sj_result": [V, V, u64],
+            "sj_plan_destroy": [V],
+            "sj_filter_count": [V, P(i32)],
+            "sj_filter_desc": [V, i32, P(i32), P(i32), P(i32), P(i32), P(u32)],
+            "sj_filter_copy": [V, i32, V, u64],
+            "sj_survivors_copy": [V, i32, V, u64, P(u64)],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = i32
+        L.sj_last_error.argtypes = [V]
+        L.sj_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Context:
+    """sj_ctx on a device, enqueuing on a torch stream (default: the current stream)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.device = device
+        self.handle = ctypes.c_void_p()
+        with torch.cuda.device(device):
+            s = _stream_handle(stream)
+        self._check(lib().sj_ctx_create(device, ctypes.c_void_p(s), ctypes.byref(self.handle)))
+
+    def set_stream(self, stream) -> None:
+        self._check(lib().sj_ctx_set_stream(self.handle, ctypes.c_void_p(_stream_handle(stream))))
+
+    def last_error(self) -> str:
+        return (lib().sj_last_error(self.handle) or b"").decode()
+
+    def _check(self, code: int) -> None:
+        if code != SJ_OK:
+            raise SjError(code, self.last_error() if self.handle else "")
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.sj_ctx_destroy(h)
+            self.handle = None
+
+
+class Rel:
+    """A relation: int32 device column tensors (equal length) and an optional
+    predicate ``(col, lo, hi)`` keeping rows with lo <= cols[col][row] < hi."""
+
+    def __init__(self, cols: Sequence[torch.Tensor], pred: Optional[Tuple[int, int, int]] = None):
+        self.cols = list(cols)
+        self.pred = pred
+
+
+class Plan:
+    """sj_plan plus its workspace (a torch uint8 tensor on the context's device)."""
+
+    def __init__(self, ctx: Context, rels: Sequence[Rel], edges: Sequence[Tuple[int, int, int, int]],
+                 bits_per_key: int = 0, k: int = 0, block_bits: int = 0, passes: int = 0, seed: int = 0,
+                 root: int = -1, workspace: Optional[torch.Tensor] = None):
+        self.ctx = ctx
+        self.block_bits = block_bits or 512
+        self.nrels = len(rels)
+        self.rels = list(rels)
+        self.handle = ctypes.c_void_p()
+        arr = (_Rel * max(1, len(rels)))()
+        self._keep = []
+        for i, r in enumerate(rels):
+            for c in r.cols:
+                if c.dtype != torch.int32 or c.dim() != 1:
+                    raise ValueError("columns must be 1-D int32 tensors")
+            ptrs = (ctypes.c_void_p * len(r.cols))(*[c.data_ptr() if c.numel() else None for c in r.cols])
+            self._keep.append(ptrs)
+            arr[i].nrows = r.cols[0].numel() if r.cols else 0
+            arr[i].ncols = len(r.cols)
+            arr[i].cols = ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p))
+            if r.pred is None:
+                arr[i].pred_col, arr[i].pred_lo, arr[i].pred_hi = -1, 0, 0
+            else:
+                arr[i].pred_col, arr[i].pred_lo, arr[i].pred_hi = (int(x) for x in r.pred)
+        earr = (_Edge * max(1, len(edges)))(*[_Edge(*[int(x) for x in e]) for e in edges])
+        opts = _Opts(bits_per_key, k, block_bits, passes, seed & (2**64 - 1), root, 0)
+        wsb = ctypes.c_uint64()
+        ctx._check(lib().sj_plan(ctx.handle, arr, len(rels), earr, len(edges), ctypes.byref(opts),
+                                 ctypes.byref(self.handle), ctypes.byref(wsb)))
+        self.workspace_bytes = int(wsb.value)
+        if workspace is None:
+            workspace = torch.empty(max(256, self.workspace_bytes), dtype=torch.uint8,
+                                    device="cuda:%d" % ctx.device)
+        self.workspace = workspace
+        ctx._check(lib().sj_bind_workspace(self.handle, ctypes.c_void_p(workspace.data_ptr()),
+                                           workspace.numel() * workspace.element_size()))
+        self.count = None
+        self.checksum = None
+
+    def _check(self, code):
+        self.ctx._check(code)
+
+    def build_filters(self) -> None:
+        self._check(lib().sj_build_filters(self.handle))
+
+    def sieve(self, survivors: bool = False):
+        if not survivors:
+            self._check(lib().sj_sieve(self.handle, None))
+            return None
+        out = (ctypes.c_uint64 * self.nrels)()
+        self._check(lib().sj_sieve(self.handle, out))
+        return [int(x) for x in out]
+
+    def join(self) -> Tuple[int, int]:
+        c, s = ctypes.c_uint64(), ctypes.c_uint64()
+        self._check(lib().sj_join(self.handle, ctypes.byref(c), ctypes.byref(s)))
+        self.count, self.checksum = int(c.value), int(s.value)
+        return self.count, self.checksum
+
+    def result(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if self.count is None:
+            raise SjError(SJ_ERR_STATE, "call join() first")
+        if out is None:
+            out = torch.empty((self.count, self.nrels), dtype=torch.int32, device="cuda:%d" % self.ctx.device)
+        cap = out.numel() // max(1, self.nrels)
+        self._check(lib().sj_result(self.handle, ctypes.c_void_p(out.data_ptr() if out.numel() else 0), cap))
+        return out
+
+    def run(self) -> Tuple[int, int, torch.Tensor]:
+        self.build_filters()
+        self.sieve()
+        c, s = self.join()
+        return c, s, self.result()
+
+    # ---- introspection
+    def filter_count(self) -> int:
+        n = ctypes.c_int32()
+        self._check(lib().sj_filter_count(self.handle, ctypes.byref(n)))
+        return int(n.value)
+
+    def filter_desc(self, f: int) -> dict:
+        kind, index, rel, col = (ctypes.c_int32() for _ in range(4))
+        nb = ctypes.c_uint32()
+        self._check(lib().sj_filter_desc(self.handle, f, ctypes.byref(kind), ctypes.byref(index),
+                                         ctypes.byref(rel), ctypes.byref(col), ctypes.byref(nb)))
+        return dict(kind=int(kind.value), index=int(index.value), src_rel=int(rel.value),
+                    src_col=int(col.value), nblocks=int(nb.value))
+
+    def filter_words(self, f: int) -> torch.Tensor:
+        d = self.filter_desc(f)
+        out = torch.empty(d["nblocks"] * self.block_bits // 32, dtype=torch.int32, device="cuda:%d" % self.ctx.device)
+        self._check(lib().sj_filter_copy(self.handle, f, ctypes.c_void_p(out.data_ptr()), out.numel()))
+        return out
+
+    def survivors(self, rel: int) -> torch.Tensor:
+        n = ctypes.c_uint64()
+        self._check(lib().sj_survivors_copy(self.handle, rel, None, 0, ctypes.byref(n)))
+        out = torch.empty(int(n.value), dtype=torch.int32, device="cuda:%d" % self.ctx.device)
+        if out.numel():
+            self._check(lib().sj_survivors_copy(self.handle, rel, ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                                ctypes.byref(n)))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.sj_plan_destroy(h)
+            self.handle = None

@@ -1,0 +1,159 @@
+// Internal interface between the host runtime (sj_runtime.cpp) and the HIP
+// kernels (sj_kernels.hip, sj_join.hip). Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sj {
+
+constexpr int kMaxJCols = 8;    // distinct join columns of one relation
+constexpr int kMaxProbe = 8;    // filters probed by one scan
+constexpr int kMaxBuild = 8;    // filters built by one scan
+constexpr int kMaxK = 12;       // bits per key
+
+constexpr int kSieveBlock = 256;
+constexpr int kSieveItems = 8;
+constexpr int kSieveTile = kSieveBlock * kSieveItems;
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kRadixPasses = 32 / kRadixBits;
+constexpr int kRadixBlock = 256;
+constexpr int kRadixItems = 8;
+constexpr int kRadixTile = kRadixBlock * kRadixItems;
+
+constexpr int kPersistentBlocks = 256 * 8;  // 256 CUs, a few resident blocks each
+
+// Decoupled look-back state for one launch: one 64-bit status word per tile
+// ((flag << 32) | count, flag 1 = the tile's own count, 2 = inclusive prefix) and a
+// counter that hands out tile ids in order. Both must be zero before the launch.
+struct Lookback {
+    uint64_t *status;
+    uint32_t *counter;
+};
+
+struct FilterRef {
+    uint32_t *words;
+    const uint32_t *nblocks;   // device-side block count
+};
+
+// One scan over a relation's rows (full columns) or over its current survivor list.
+struct StepArgs {
+    const uint32_t *src_rid;   // list source: row ids; nullptr: full scan, rid = row index
+    const uint32_t *src_count; // list source: device-side row count
+    uint32_t src_rows;         // full scan: number of rows
+    int ncol;
+    const int32_t *col[kMaxJCols];
+    const int32_t *pred;       // full scan predicate column or nullptr
+    int32_t pred_lo, pred_hi;
+    int nprobe;
+    int8_t probe_col[kMaxProbe];
+    FilterRef probe[kMaxProbe];
+    int nbuild;
+    int8_t build_col[kMaxBuild];
+    FilterRef build[kMaxBuild];
+    uint32_t *out_rid;         // nullptr: no survivor list is written
+    int32_t *out_col[kMaxJCols];
+    uint32_t *out_count;       // device-side survivor count (written when out_rid != nullptr)
+    Lookback lb;
+    uint32_t seed;
+    int k;
+    int logB;
+};
+
+// ---- launch wrappers (sj_kernels.hip) ----
+hipError_t launch_zero(void *p, uint64_t bytes, hipStream_t s);
+hipError_t launch_count_pred(const int32_t *col, uint32_t n, int32_t lo, int32_t hi, uint32_t *out,
+                             hipStream_t s);
+struct SizeArgs {
+    int nfilters;
+    const uint32_t *elig[64];      // device-side eligible count, or nullptr to use rows[]
+    uint32_t rows[64];
+    uint32_t *nblocks[64];
+    uint32_t bits_per_key;
+    uint32_t block_bits;
+};
+hipError_t launch_size_filters(const SizeArgs &a, hipStream_t s);
+hipError_t launch_sieve_step(const StepArgs &a, uint32_t max_rows, hipStream_t s);
+
+// ---- join phase (sj_join.hip) ----
+// A relation's sieved rows regrouped by its parent-edge key ("bucket order").
+struct Buckets {
+    uint32_t cap;              // capacity (rows)
+    const uint32_t *n;         // device-side number of entries
+    uint32_t *rid;             // [cap] row ids in bucket order
+    int32_t *col[kMaxJCols];   // [cap] join-column values in bucket order
+    int npay;
+    int key_jcol;              // which join column is the bucket key
+    uint32_t *dir_begin;       // [cap + 1] first entry of each distinct key, then n
+    int32_t *dir_key;          // [cap]
+    uint32_t *ndir;            // device-side number of distinct keys
+    uint64_t *slots;           // hash index over dir keys, [slot_cap]
+    uint32_t slot_cap;         // power of two
+    uint32_t *slot_mask;       // device-side mask used (<= slot_cap - 1)
+    uint64_t *cw;              // [cap + 1] exclusive prefix of entry weights (result counts)
+    uint64_t *cv;              // [cap + 1] exclusive prefix of entry checksum weights
+};
+
+struct SortScratch {
+    uint32_t cap;
+    uint32_t *keys[2];
+    uint32_t *vals[2];
+    uint32_t *hist;            // [kRadixBins * ntiles_max]
+    uint32_t *ghist;           // [kRadixPasses * kRadixBins], zeroed
+    uint32_t *ctl;             // [16] pass control words (written on device)
+    Lookback lb[kRadixPasses]; // scan of each pass's histogram
+};
+
+// Sort the list (rid, cols) by column key_col into bucket order and build the
+// directory and hash index. list_count is the device-side list length.
+hipError_t launch_build_buckets(const uint32_t *list_rid, const int32_t *const *list_cols, int ncol,
+                                const uint32_t *list_count, int key_col, const Buckets &b,
+                                const SortScratch &ss, Lookback lb_dir, hipStream_t s);
+
+// Per-entry DP weights of a bucketed relation (or the root list), scanned into
+// cw/cv. child[c] is the bucketed child joined on list column child_col[c].
+struct DpArgs {
+    uint32_t rel;              // relation index (checksum factor)
+    const uint32_t *n;         // device-side entries
+    uint32_t cap;
+    const uint32_t *rid;
+    const int32_t *col[kMaxJCols];
+    int nchild;
+    int child_col[kMaxJCols];
+    Buckets child[kMaxJCols];
+    uint64_t *cw;              // [cap + 1]
+    uint64_t *cv;              // [cap + 1]
+    uint64_t *tile_sums;       // [2 * tiles(cap)]
+    uint64_t *totals;          // [2] result count and checksum, or nullptr
+};
+hipError_t launch_dp(const DpArgs &a, hipStream_t s);
+
+// Materialisation over the join tree.
+constexpr int kMatMaxRels = 16;
+struct MatArgs {
+    int nrels;
+    int order[kMatMaxRels];        // preorder: order[0] is the root
+    int parent_pos[kMatMaxRels];   // position in order[] of each position's parent
+    int key_col_in_parent[kMatMaxRels]; // join column (list slot) in the parent used to find the bucket
+    int is_leaf[kMatMaxRels];
+    int nchild[kMatMaxRels];
+    // root list
+    const uint32_t *root_n;
+    const uint32_t *root_rid;
+    const int32_t *root_col[kMaxJCols];
+    const uint64_t *root_cw;
+    Buckets b[kMatMaxRels];        // by preorder position (b[0] unused)
+    uint64_t count;                // total result tuples (host copy)
+    const uint64_t *count_dev;
+    int32_t *out;
+    int chunk;
+};
+hipError_t launch_materialize(const MatArgs &a, hipStream_t s);
+
+}  // namespace sj

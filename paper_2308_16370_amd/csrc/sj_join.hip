@@ -1,0 +1,636 @@
+// Enumeration-phase kernels.
+//
+// Each sieved non-root relation is regrouped by its parent-edge key ("buckets"):
+// a stable LSD radix sort of (key, list index) keeps row ids ascending inside a
+// bucket, a head-flag compaction gives the directory of distinct keys, and an
+// open-addressed hash index maps a key to its directory entry. Bottom-up over the
+// join tree, every entry gets the number of result tuples below it (a product over
+// its children of the matching buckets' totals) and the matching checksum weight;
+// exclusive prefix sums of both give the exact result size and checksum at the
+// root and let each output index be decoded into its row-id tuple directly, with
+// no intermediate result materialised.
+#include <hip/hip_runtime.h>
+
+#include "sj_device.h"
+#include "sj_internal.h"
+
+namespace sj {
+
+// ================================================================ radix sort
+// keys are the u32 bit patterns of int32 join keys; values are list indices.
+
+__global__ __launch_bounds__(kRadixBlock) void k_radix_ghist(const int32_t *__restrict__ keys,
+                                                             const uint32_t *n_ptr, uint32_t *ghist) {
+    __shared__ uint32_t h[kRadixPasses][kRadixBins];
+    for (int i = threadIdx.x; i < kRadixPasses * kRadixBins; i += blockDim.x) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t n = *n_ptr;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const uint32_t k = static_cast<uint32_t>(keys[e]);
+#pragma unroll
+        for (int p = 0; p < kRadixPasses; ++p) atomicAdd(&h[p][(k >> (p * kRadixBits)) & (kRadixBins - 1)], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kRadixPasses * kRadixBins; i += blockDim.x) {
+        const uint32_t c = (&h[0][0])[i];
+        if (c) atomicAdd(ghist + i, c);
+    }
+}
+
+// Pass control: ctl[p] = pass p moves data (its digit is not constant); ctl[4 + p] =
+// where pass p reads (0: the list, 1: buffer 0, 2: buffer 1); ctl[8] = where the
+// sorted data ends up.
+__global__ void k_radix_ctl(const uint32_t *ghist, const uint32_t *n_ptr, uint32_t *ctl) {
+    if (threadIdx.x != 0) return;
+    const uint32_t n = *n_ptr;
+    uint32_t src = 0;
+    for (int p = 0; p < kRadixPasses; ++p) {
+        uint32_t mx = 0;
+        for (int d = 0; d < kRadixBins; ++d) mx = max(mx, ghist[p * kRadixBins + d]);
+        const uint32_t active = (n > 1 && mx < n) ? 1u : 0u;
+        ctl[p] = active;
+        ctl[4 + p] = src;
+        if (active) src = (src == 1) ? 2u : 1u;
+    }
+    ctl[8] = src;
+}
+
+__device__ __forceinline__ const uint32_t *radix_src_keys(const SortScratch &ss, const int32_t *list_keys,
+                                                         uint32_t src) {
+    return src == 0 ? reinterpret_cast<const uint32_t *>(list_keys) : ss.keys[src - 1];
+}
+
+// Per-tile digit histogram, digit-major: hist[d * ntiles + tile].
+__global__ __launch_bounds__(kRadixBlock) void k_radix_hist(int pass, const int32_t *__restrict__ list_keys,
+                                                            SortScratch ss, const uint32_t *n_ptr) {
+    if (!ss.ctl[pass]) return;
+    __shared__ uint32_t h[kRadixBins];
+    const uint32_t n = *n_ptr;
+    const uint32_t ntiles = (n + kRadixTile - 1) / kRadixTile;
+    const uint32_t *keys = radix_src_keys(ss, list_keys, ss.ctl[4 + pass]);
+    const int shift = pass * kRadixBits;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        h[threadIdx.x] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kRadixItems; ++i) {
+            const uint32_t e = tile * kRadixTile + i * kRadixBlock + threadIdx.x;
+            if (e < n) atomicAdd(&h[(keys[e] >> shift) & (kRadixBins - 1)], 1u);
+        }
+        __syncthreads();
+        ss.hist[threadIdx.x * ntiles + tile] = h[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+// Exclusive scan in place of data[0 .. mul * ceil(n / div)), u32, decoupled look-back.
+__global__ __launch_bounds__(kScanBlock) void k_scan_u32(uint32_t *data, const uint32_t *n_ptr, uint32_t div,
+                                                         uint32_t mul, const uint32_t *active, Lookback lb) {
+    if (active && !*active) return;
+    __shared__ uint32_t s_tile, s_base;
+    __shared__ uint32_t s_wave[kScanBlock / 64];
+    const uint32_t n = *n_ptr;
+    const uint32_t len = mul * ((n + div - 1) / div);
+    const uint32_t ntiles = (len + kScanTile - 1) / kScanTile;
+    while (true) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(lb.counter, 1u);
+        __syncthreads();
+        const uint32_t tile = s_tile;
+        if (tile >= ntiles) break;
+        const uint32_t base = tile * kScanTile + threadIdx.x * kScanItems;
+        uint32_t x[kScanItems];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            x[i] = (base + i < len) ? data[base + i] : 0u;
+            sum += x[i];
+        }
+        uint32_t tot;
+        uint32_t off = block_excl_scan<kScanBlock>(sum, s_wave, tot);
+        if (threadIdx.x == 0) s_base = lookback32(lb.status, tile, tot);
+        __syncthreads();
+        off += s_base;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            if (base + i < len) data[base + i] = off;
+            off += x[i];
+        }
+        __syncthreads();
+    }
+}
+
+// Stable scatter of one radix pass. Items are striped (item i of thread t is element
+// tile * kRadixTile + i * kRadixBlock + t), processed round by round, so element
+// order equals (round, wave, lane) order; a lane's rank among equal digits comes from
+// 8 ballots (the lanes sharing its digit), waves are ordered through LDS counts.
+__global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(int pass, const int32_t *__restrict__ list_keys,
+                                                               SortScratch ss, const uint32_t *n_ptr) {
+    if (!ss.ctl[pass]) return;
+    constexpr int kWaves = kRadixBlock / 64;
+    __shared__ uint32_t s_off[kRadixBins];
+    __shared__ uint32_t s_run[kRadixBins];
+    __shared__ uint32_t s_cnt[kWaves][kRadixBins];
+    const uint32_t n = *n_ptr;
+    const uint32_t ntiles = (n + kRadixTile - 1) / kRadixTile;
+    const uint32_t src = ss.ctl[4 + pass];
+    const uint32_t *keys = radix_src_keys(ss, list_keys, src);
+    const uint32_t *vals = src == 0 ? nullptr : ss.vals[src - 1];
+    uint32_t *dkeys = (src == 1) ? ss.keys[1] : ss.keys[0];
+    uint32_t *dvals = (src == 1) ? ss.vals[1] : ss.vals[0];
+    const int shift = pass * kRadixBits;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        s_off[tid] = ss.hist[tid * ntiles + tile];
+        s_run[tid] = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) s_cnt[w][tid] = 0;
+        __syncthreads();
+        for (int i = 0; i < kRadixItems; ++i) {
+            const uint32_t e = tile * kRadixTile + i * kRadixBlock + tid;
+            const bool valid = e < n;
+            const uint32_t key = valid ? keys[e] : 0u;
+            const uint32_t val = valid ? (vals ? vals[e] : e) : 0u;
+            const uint32_t d = (key >> shift) & (kRadixBins - 1);
+            uint64_t m = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < kRadixBits; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bb = __ballot(bit);
+                m &= bit ? bb : ~bb;
+            }
+            const uint32_t rank = __popcll(m & lt);
+            if (valid && rank == 0) s_cnt[wid][d] = __popcll(m);
+            __syncthreads();
+            if (valid) {
+                uint32_t pos = s_run[d] + rank;
+                for (int w = 0; w < wid; ++w) pos += s_cnt[w][d];
+                const uint32_t o = s_off[d] + pos;
+                dkeys[o] = key;
+                dvals[o] = val;
+            }
+            __syncthreads();
+            uint32_t t = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                t += s_cnt[w][tid];
+                s_cnt[w][tid] = 0;
+            }
+            s_run[tid] += t;
+            __syncthreads();
+        }
+    }
+}
+
+// Gather the list into bucket order.
+struct ListRef {
+    const uint32_t *rid;
+    const int32_t *col[kMaxJCols];
+    int ncol;
+};
+
+__global__ void k_gather(ListRef l, const uint32_t *n_ptr, SortScratch ss, Buckets b) {
+    const uint32_t n = *n_ptr;
+    const uint32_t fin = ss.ctl[8];
+    const uint32_t *idx = fin == 0 ? nullptr : ss.vals[fin - 1];
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const uint32_t li = idx ? idx[e] : e;
+        b.rid[e] = l.rid[li];
+        for (int c = 0; c < l.ncol; ++c) b.col[c][e] = l.col[c][li];
+    }
+}
+
+// Directory: ordered compaction of the bucket heads (first entry of each key).
+__global__ __launch_bounds__(kSieveBlock) void k_dir_heads(Buckets b, Lookback lb) {
+    __shared__ uint32_t s_tile, s_base;
+    __shared__ uint32_t s_wave[kSieveBlock / 64];
+    const uint32_t n = *b.n;
+    const int32_t *keys = b.col[b.key_jcol];
+    const uint32_t ntiles = (n + kSieveTile - 1) / kSieveTile;
+    while (true) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(lb.counter, 1u);
+        __syncthreads();
+        const uint32_t tile = s_tile;
+        if (tile >= ntiles) break;
+        const uint32_t e0 = tile * kSieveTile + threadIdx.x * kSieveItems;
+        uint32_t flags = 0;
+        int32_t kv[kSieveItems];
+        int32_t prev = (e0 > 0 && e0 <= n) ? keys[e0 - 1] : 0;
+#pragma unroll
+        for (int i = 0; i < kSieveItems; ++i) {
+            const uint32_t e = e0 + i;
+            kv[i] = e < n ? keys[e] : 0;
+            const bool head = e < n && (e == 0 || kv[i] != prev);
+            flags |= (head ? 1u : 0u) << i;
+            prev = kv[i];
+        }
+        uint32_t tot;
+        const uint32_t off = block_excl_scan<kSieveBlock>(static_cast<uint32_t>(__builtin_popcount(flags)), s_wave, tot);
+        if (threadIdx.x == 0) s_base = lookback32(lb.status, tile, tot);
+        __syncthreads();
+        uint32_t o = s_base + off;
+#pragma unroll
+        for (int i = 0; i < kSieveItems; ++i) {
+            if (flags & (1u << i)) {
+                b.dir_begin[o] = e0 + i;
+                b.dir_key[o] = kv[i];
+                ++o;
+            }
+        }
+        if (tile == ntiles - 1 && threadIdx.x == 0) {
+            *b.ndir = s_base + tot;
+            b.dir_begin[s_base + tot] = n;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_dir_mask(Buckets b) {
+    if (threadIdx.x != 0) return;
+    const uint32_t nd = *b.ndir;
+    uint32_t cap = 16;
+    while (cap < 2u * nd + 1u) cap <<= 1;
+    if (cap > b.slot_cap) cap = b.slot_cap;
+    *b.slot_mask = cap - 1;
+}
+
+__global__ void k_slots_clear(Buckets b) {
+    const uint32_t lim = *b.slot_mask + 1u;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < lim; i += gridDim.x * blockDim.x) b.slots[i] = 0;
+}
+
+__global__ void k_dir_insert(Buckets b) {
+    const uint32_t nd = *b.ndir;
+    const uint32_t mask = *b.slot_mask;
+    for (uint32_t d = blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += gridDim.x * blockDim.x) {
+        const int32_t key = b.dir_key[d];
+        const uint64_t val = (static_cast<uint64_t>(d + 1) << 32) | static_cast<uint32_t>(key);
+        uint32_t s = slot_hash(key) & mask;
+        while (atomicCAS(reinterpret_cast<unsigned long long *>(b.slots + s), 0ull,
+                         static_cast<unsigned long long>(val)) != 0ull)
+            s = (s + 1) & mask;
+    }
+}
+
+static uint32_t grid_for(uint32_t n, uint32_t per_block, uint32_t cap) {
+    uint32_t g = (n + per_block - 1) / per_block;
+    if (g > cap) g = cap;
+    return g ? g : 1;
+}
+
+hipError_t launch_build_buckets(const uint32_t *list_rid, const int32_t *const *list_cols, int ncol,
+                                const uint32_t *list_count, int key_col, const Buckets &b,
+                                const SortScratch &ss, Lookback lb_dir, hipStream_t s) {
+    const uint32_t cap = b.cap;
+    if (cap == 0) {
+        // no rows: an empty directory still needs a valid (cleared) hash index
+        hipLaunchKernelGGL(k_dir_mask, dim3(1), dim3(64), 0, s, b);
+        hipLaunchKernelGGL(k_slots_clear, dim3(1), dim3(256), 0, s, b);
+        return hipGetLastError();
+    }
+    const int32_t *keys = list_cols[key_col];
+    const uint32_t tiles = (cap + kRadixTile - 1) / kRadixTile;
+    const uint32_t tgrid = tiles < kPersistentBlocks ? tiles : kPersistentBlocks;
+    hipLaunchKernelGGL(k_radix_ghist, dim3(grid_for(cap, 256 * 16, 1024)), dim3(kRadixBlock), 0, s, keys,
+                       list_count, ss.ghist);
+    hipLaunchKernelGGL(k_radix_ctl, dim3(1), dim3(64), 0, s, ss.ghist, list_count, ss.ctl);
+    const uint32_t scan_len_max = kRadixBins * tiles;
+    const uint32_t scan_grid = grid_for(scan_len_max, kScanTile, kPersistentBlocks);
+    for (int p = 0; p < kRadixPasses; ++p) {
+        hipLaunchKernelGGL(k_radix_hist, dim3(tgrid), dim3(kRadixBlock), 0, s, p, keys, ss, list_count);
+        hipLaunchKernelGGL(k_scan_u32, dim3(scan_grid), dim3(kScanBlock), 0, s, ss.hist, list_count,
+                           static_cast<uint32_t>(kRadixTile), static_cast<uint32_t>(kRadixBins), ss.ctl + p, ss.lb[p]);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(tgrid), dim3(kRadixBlock), 0, s, p, keys, ss, list_count);
+    }
+    ListRef l;
+    l.rid = list_rid;
+    l.ncol = ncol;
+    for (int c = 0; c < kMaxJCols; ++c) l.col[c] = c < ncol ? list_cols[c] : nullptr;
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(cap, 256 * 4, 4096)), dim3(256), 0, s, l, list_count, ss, b);
+    const uint32_t dgrid = grid_for(cap, kSieveTile, kPersistentBlocks);
+    hipLaunchKernelGGL(k_dir_heads, dim3(dgrid), dim3(kSieveBlock), 0, s, b, lb_dir);
+    hipLaunchKernelGGL(k_dir_mask, dim3(1), dim3(64), 0, s, b);
+    hipLaunchKernelGGL(k_slots_clear, dim3(grid_for(b.slot_cap, 256 * 8, 4096)), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_dir_insert, dim3(grid_for(cap, 256 * 4, 4096)), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+// ================================================================ DP weights
+// w(e) = prod over children c of W_c(key_c(e)), v(e) = f(rel, rid(e)) * prod V_c(...),
+// with W_c / V_c the totals of the child's bucket for that key (0 if absent).
+
+__device__ __forceinline__ void dp_entry(const DpArgs &a, const uint32_t *masks, uint32_t e, uint64_t &w,
+                                         uint64_t &v) {
+    w = 1;
+    v = chk_factor(a.rel, a.rid[e]);
+#pragma unroll
+    for (int c = 0; c < kMaxJCols; ++c) {
+        if (c < a.nchild) {
+            const int32_t key = a.col[a.child_col[c]][e];
+            const int64_t d = w ? dir_find(a.child[c].slots, masks[c], key) : -1;
+            if (d < 0) {
+                w = 0;
+                v = 0;
+            } else {
+                const uint32_t lo = a.child[c].dir_begin[d], hi = a.child[c].dir_begin[d + 1];
+                w *= a.child[c].cw[hi] - a.child[c].cw[lo];
+                v *= a.child[c].cv[hi] - a.child[c].cv[lo];
+            }
+        }
+    }
+}
+
+// Phase 1: per-entry weights into cw/cv (not yet scanned) and per-tile sums.
+__global__ __launch_bounds__(kScanBlock) void k_dp_reduce(DpArgs a) {
+    __shared__ uint64_t s_w[kScanBlock / 64], s_v[kScanBlock / 64];
+    const uint32_t n = *a.n;
+    const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
+    uint32_t masks[kMaxJCols];
+#pragma unroll
+    for (int c = 0; c < kMaxJCols; ++c) masks[c] = c < a.nchild ? *a.child[c].slot_mask : 0u;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t base = tile * kScanTile + threadIdx.x * kScanItems;
+        uint64_t sw = 0, sv = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint32_t e = base + i;
+            if (e < n) {
+                uint64_t w, v;
+                dp_entry(a, masks, e, w, v);
+                a.cw[e] = w;
+                a.cv[e] = v;
+                sw += w;
+                sv += v;
+            }
+        }
+        uint64_t tw, tv;
+        block_excl_scan<kScanBlock>(sw, s_w, tw);
+        block_excl_scan<kScanBlock>(sv, s_v, tv);
+        if (threadIdx.x == 0) {
+            a.tile_sums[2 * tile] = tw;
+            a.tile_sums[2 * tile + 1] = tv;
+        }
+    }
+}
+
+// Phase 2 (one block): exclusive scan of the tile sums; totals at cw[n], cv[n].
+__global__ __launch_bounds__(kScanBlock) void k_dp_tiles(DpArgs a) {
+    __shared__ uint64_t s_w[kScanBlock / 64], s_v[kScanBlock / 64];
+    __shared__ uint64_t s_carry[2];
+    const uint32_t n = *a.n;
+    const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
+    if (threadIdx.x == 0) {
+        s_carry[0] = 0;
+        s_carry[1] = 0;
+    }
+    __syncthreads();
+    for (uint32_t t0 = 0; t0 < ntiles; t0 += kScanBlock) {
+        const uint32_t t = t0 + threadIdx.x;
+        const uint64_t w = t < ntiles ? a.tile_sums[2 * t] : 0, v = t < ntiles ? a.tile_sums[2 * t + 1] : 0;
+        uint64_t tw, tv;
+        const uint64_t ow = block_excl_scan<kScanBlock>(w, s_w, tw);
+        const uint64_t ov = block_excl_scan<kScanBlock>(v, s_v, tv);
+        if (t < ntiles) {
+            a.tile_sums[2 * t] = s_carry[0] + ow;
+            a.tile_sums[2 * t + 1] = s_carry[1] + ov;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_carry[0] += tw;
+            s_carry[1] += tv;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.cw[n] = s_carry[0];
+        a.cv[n] = s_carry[1];
+        if (a.totals) {
+            a.totals[0] = s_carry[0];
+            a.totals[1] = s_carry[1];
+        }
+    }
+}
+
+// Phase 3: turn per-entry weights into exclusive prefixes.
+__global__ __launch_bounds__(kScanBlock) void k_dp_down(DpArgs a) {
+    __shared__ uint64_t s_w[kScanBlock / 64], s_v[kScanBlock / 64];
+    const uint32_t n = *a.n;
+    const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t base = tile * kScanTile + threadIdx.x * kScanItems;
+        uint64_t w[kScanItems], v[kScanItems];
+        uint64_t sw = 0, sv = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint32_t e = base + i;
+            w[i] = e < n ? a.cw[e] : 0;
+            v[i] = e < n ? a.cv[e] : 0;
+            sw += w[i];
+            sv += v[i];
+        }
+        uint64_t tw, tv;
+        uint64_t ow = block_excl_scan<kScanBlock>(sw, s_w, tw) + a.tile_sums[2 * tile];
+        uint64_t ov = block_excl_scan<kScanBlock>(sv, s_v, tv) + a.tile_sums[2 * tile + 1];
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint32_t e = base + i;
+            if (e < n) {
+                a.cw[e] = ow;
+                a.cv[e] = ov;
+            }
+            ow += w[i];
+            ov += v[i];
+        }
+    }
+}
+
+hipError_t launch_dp(const DpArgs &a, hipStream_t s) {
+    const uint32_t tiles = (a.cap + kScanTile - 1) / kScanTile;
+    const uint32_t g = tiles == 0 ? 1 : (tiles < kPersistentBlocks ? tiles : kPersistentBlocks);
+    hipLaunchKernelGGL(k_dp_reduce, dim3(g), dim3(kScanBlock), 0, s, a);
+    hipLaunchKernelGGL(k_dp_tiles, dim3(1), dim3(kScanBlock), 0, s, a);
+    hipLaunchKernelGGL(k_dp_down, dim3(g), dim3(kScanBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+// ================================================================ materialise
+// Output index o decodes into one tuple: the root entry r with cw_root[r] <= o <
+// cw_root[r + 1], then, down the tree in preorder, the local index is split over a
+// node's children as a mixed-radix number (first child most significant) and
+// inside a child's bucket the entry whose prefix range holds it. A thread decodes
+// the first index of its chunk and then steps an odometer (last preorder position
+// fastest), which visits tuples in the same lexicographic order.
+
+__device__ __forceinline__ uint32_t upper_bound_u64(const uint64_t *a, uint32_t lo, uint32_t hi, uint64_t x) {
+    // first i in [lo, hi) with a[i] > x (hi if none)
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] > x)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+template <int N>
+struct MatState {
+    uint32_t e[N];
+    uint32_t lo[N];
+    uint32_t hi[N];
+};
+
+// Key that joins position y to its parent, read from the parent's current entry.
+template <int N>
+__device__ __forceinline__ int32_t parent_key(const MatArgs &a, const MatState<N> &st, int y) {
+    const int py = a.parent_pos[y];
+    uint32_t ep = st.e[0];
+#pragma unroll
+    for (int q = 1; q < N; ++q)
+        if (q == py) ep = st.e[q];
+    const int32_t *kc = (py == 0) ? a.root_col[a.key_col_in_parent[y]] : a.b[py].col[a.key_col_in_parent[y]];
+    return kc[ep];
+}
+
+template <int N>
+__device__ __forceinline__ void find_bucket(const MatArgs &a, MatState<N> &st, int y, const uint32_t *masks) {
+    const int32_t key = parent_key<N>(a, st, y);
+    const int64_t d = dir_find(a.b[y].slots, masks[y], key);
+    // a tuple is only decoded along entries of positive weight, so the key exists
+    const uint32_t dd = d < 0 ? 0u : static_cast<uint32_t>(d);
+    st.lo[y] = a.b[y].dir_begin[dd];
+    st.hi[y] = a.b[y].dir_begin[dd + 1];
+}
+
+template <int N>
+__device__ __forceinline__ uint32_t first_valid(const MatArgs &a, int y, uint32_t e, uint32_t hi) {
+    if (a.is_leaf[y]) return e;
+    const uint64_t *cw = a.b[y].cw;
+    while (e < hi && cw[e + 1] == cw[e]) ++e;
+    return e;
+}
+
+template <int N>
+__device__ void mat_decode(const MatArgs &a, MatState<N> &st, uint64_t o, uint32_t root_n, const uint32_t *masks) {
+    uint64_t L[N];
+    const uint32_t r = upper_bound_u64(a.root_cw, 0, root_n + 1, o) - 1;
+    st.e[0] = r;
+    L[0] = o - a.root_cw[r];
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+        if (p > 0) {
+            // choose the entry of position p inside its bucket from L[p]
+            if (a.is_leaf[p]) {
+                st.e[p] = st.lo[p] + static_cast<uint32_t>(L[p]);
+                L[p] = 0;
+            } else {
+                const uint64_t *cw = a.b[p].cw;
+                const uint64_t base = cw[st.lo[p]];
+                const uint32_t e = upper_bound_u64(cw, st.lo[p], st.hi[p] + 1, base + L[p]) - 1;
+                st.e[p] = e;
+                L[p] -= cw[e] - base;
+            }
+        }
+        // split L[p] over p's children, last child least significant
+#pragma unroll
+        for (int c = N - 1; c > p; --c) {
+            if (a.parent_pos[c] == p) {
+                find_bucket<N>(a, st, c, masks);
+                if (a.nchild[p] == 1) {
+                    L[c] = L[p];
+                } else {
+                    const uint64_t W = a.is_leaf[c] ? static_cast<uint64_t>(st.hi[c] - st.lo[c])
+                                                    : a.b[c].cw[st.hi[c]] - a.b[c].cw[st.lo[c]];
+                    L[c] = L[p] % W;
+                    L[p] /= W;
+                }
+            }
+        }
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void mat_advance(const MatArgs &a, MatState<N> &st, uint32_t root_n, const uint32_t *masks) {
+    int changed = -1;
+#pragma unroll
+    for (int x = N - 1; x >= 1; --x) {
+        if (changed < 0) {
+            const uint32_t nx = first_valid<N>(a, x, st.e[x] + 1, st.hi[x]);
+            if (nx < st.hi[x]) {
+                st.e[x] = nx;
+                changed = x;
+            }
+        }
+    }
+    if (changed < 0) {
+        uint32_t r = st.e[0] + 1;
+        while (r < root_n && a.root_cw[r + 1] == a.root_cw[r]) ++r;
+        st.e[0] = r;
+        changed = 0;
+    }
+#pragma unroll
+    for (int y = 1; y < N; ++y) {
+        if (y > changed) {
+            if (a.parent_pos[y] >= changed) find_bucket<N>(a, st, y, masks);
+            st.e[y] = first_valid<N>(a, y, st.lo[y], st.hi[y]);
+        }
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void k_materialize(MatArgs a) {
+    const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint64_t o0 = t * static_cast<uint64_t>(a.chunk);
+    if (o0 >= a.count) return;
+    const uint64_t o1 = (o0 + a.chunk < a.count) ? o0 + a.chunk : a.count;
+    const uint32_t root_n = *a.root_n;
+    uint32_t masks[N];
+    masks[0] = 0;
+#pragma unroll
+    for (int y = 1; y < N; ++y) masks[y] = *a.b[y].slot_mask;
+    MatState<N> st;
+    mat_decode<N>(a, st, o0, root_n, masks);
+    for (uint64_t o = o0;;) {
+        int32_t tup[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q) tup[q] = 0;
+#pragma unroll
+        for (int x = 0; x < N; ++x) {
+            const int32_t rid = static_cast<int32_t>(x == 0 ? a.root_rid[st.e[0]] : a.b[x].rid[st.e[x]]);
+#pragma unroll
+            for (int q = 0; q < N; ++q)
+                if (a.order[x] == q) tup[q] = rid;
+        }
+        int32_t *dst = a.out + o * N;
+        if constexpr (N == 4) {
+            *reinterpret_cast<int4 *>(dst) = make_int4(tup[0], tup[1], tup[2], tup[3]);
+        } else if constexpr (N == 2) {
+            *reinterpret_cast<int2 *>(dst) = make_int2(tup[0], tup[1]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < N; ++q) dst[q] = tup[q];
+        }
+        if (++o >= o1) break;
+        mat_advance<N>(a, st, root_n, masks);
+    }
+}
+
+hipError_t launch_materialize(const MatArgs &a, hipStream_t s) {
+    if (a.count == 0) return hipSuccess;
+    const uint64_t threads = (a.count + a.chunk - 1) / a.chunk;
+    const uint64_t blocks64 = (threads + 255) / 256;
+    if (blocks64 > 0x7fffffffull) return hipErrorInvalidValue;
+    const dim3 g(static_cast<uint32_t>(blocks64));
+    switch (a.nrels) {
+#define SJ_MAT_CASE(NN) \
+    case NN: hipLaunchKernelGGL(k_materialize<NN>, g, dim3(256), 0, s, a); break;
+        SJ_MAT_CASE(1) SJ_MAT_CASE(2) SJ_MAT_CASE(3) SJ_MAT_CASE(4) SJ_MAT_CASE(5) SJ_MAT_CASE(6) SJ_MAT_CASE(7)
+        SJ_MAT_CASE(8) SJ_MAT_CASE(9) SJ_MAT_CASE(10) SJ_MAT_CASE(11) SJ_MAT_CASE(12) SJ_MAT_CASE(13)
+        SJ_MAT_CASE(14) SJ_MAT_CASE(15) SJ_MAT_CASE(16)
+#undef SJ_MAT_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sj

@@ -1,0 +1,866 @@
+// Host runtime behind the C ABI in include/sievejoin.h: join-graph validation, the
+// spanning tree and filter schedule, the workspace layout, the call-order state
+// machine, and the sequencing of the kernels on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/sievejoin.h"
+#include "sj_internal.h"
+
+using namespace sj;
+
+struct sj_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+};
+
+namespace {
+
+enum State { kPlanned = 0, kBound = 1, kFiltered = 2, kSieved = 3, kJoined = 4 };
+enum Src { kFull = -1 };
+
+struct Rel {
+    uint32_t nrows = 0;
+    std::vector<const int32_t *> cols;
+    int pred_col = -1;
+    int32_t lo = 0, hi = 0;
+    std::vector<int> jcols;    // distinct join columns, ascending
+    int jidx(int col) const {
+        for (size_t i = 0; i < jcols.size(); ++i)
+            if (jcols[i] == col) return static_cast<int>(i);
+        return -1;
+    }
+};
+
+struct Closing {
+    int u, cu, v, cv;
+};
+
+struct Filter {
+    int kind, index, src_rel, src_col;
+    uint64_t max_words = 0;
+    uint64_t off = 0;          // workspace offset of the words
+};
+
+struct StepSpec {
+    int phase;                 // 0: build_filters, 1: sieve
+    int rel;
+    int src;                   // kFull or list buffer 0/1
+    int src_step = -1;         // step that wrote the source list
+    std::vector<std::pair<int, int>> probes;   // (jcol index, filter)
+    std::vector<std::pair<int, int>> builds;
+    int out = -1;              // list buffer written, -1: none
+    uint64_t off_status = 0, off_counter = 0, off_count = 0;
+    uint32_t max_rows = 0;
+};
+
+struct Region {
+    uint64_t begin = 0, end = 0;
+};
+
+struct Layout {
+    uint64_t top = 0;
+    uint64_t take(uint64_t bytes) {
+        const uint64_t o = top;
+        top += (bytes + 255) & ~uint64_t(255);
+        return o;
+    }
+};
+
+}  // namespace
+
+struct sj_plan_s {
+    sj_ctx *ctx = nullptr;
+    int n = 0;
+    std::vector<Rel> rels;
+    std::vector<sj_edge> edges;
+    sj_opts opts{};
+    int logB = 9;
+    uint32_t seed32 = 0;
+    // tree
+    int root = 0;
+    std::vector<int> parent, pcol, mycol, preorder, postorder;
+    std::vector<std::vector<int>> children;
+    std::vector<Closing> closing;
+    // filters and steps
+    std::vector<Filter> filters;
+    std::vector<int> f_bwd, f_fwd;           // per relation, -1 none
+    std::vector<int> f_close;                // per closing edge
+    std::vector<StepSpec> steps;
+    std::vector<int> final_list, final_step; // per relation
+    // workspace
+    uint64_t ws_bytes = 0;
+    char *ws = nullptr;
+    Region zero[3];                          // build_filters, sieve, join
+    uint64_t off_elig = 0, off_nblocks = 0, off_totals = 0;
+    std::vector<uint64_t> off_list[2];       // per relation: list buffer base
+    // join phase
+    struct JoinRel {
+        uint64_t rid = 0, cols = 0, dir_begin = 0, dir_key = 0, slots = 0, cw = 0, cv = 0, ndir = 0, mask = 0;
+        uint32_t slot_cap = 0;
+        uint64_t ghist = 0, lb_hist[kRadixPasses] = {0, 0, 0, 0}, lb_hist_ctr[kRadixPasses] = {0, 0, 0, 0};
+        uint64_t lb_dir = 0, lb_dir_ctr = 0;
+    };
+    std::vector<JoinRel> jr;
+    uint64_t off_sort_keys[2] = {0, 0}, off_sort_vals[2] = {0, 0}, off_hist = 0, off_ctl = 0, off_tile_sums = 0;
+    uint64_t off_root_cw = 0, off_root_cv = 0;
+    uint32_t sort_cap = 0;
+    int state = kPlanned;
+    uint64_t count = 0, checksum = 0;
+};
+
+// ---------------------------------------------------------------- errors
+
+static sj_status fail(sj_ctx *ctx, sj_status code, const char *fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return code;
+}
+
+#define SJ_HIP(ctx, expr)                                                                        \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail((ctx), SJ_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));  \
+    } while (0)
+
+// ---------------------------------------------------------------- context
+
+extern "C" sj_status sj_ctx_create(int32_t device, void *hip_stream, sj_ctx **out) {
+    if (!out) return SJ_ERR_INVALID;
+    *out = nullptr;
+    if (device < 0) return SJ_ERR_INVALID;
+    sj_ctx *c = new (std::nothrow) sj_ctx;
+    if (!c) return SJ_ERR_INVALID;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    *out = c;
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_ctx_set_stream(sj_ctx *ctx, void *hip_stream) {
+    if (!ctx) return SJ_ERR_INVALID;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_ctx_destroy(sj_ctx *ctx) {
+    delete ctx;
+    return SJ_OK;
+}
+
+extern "C" const char *sj_last_error(const sj_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+// ---------------------------------------------------------------- planning
+
+static uint32_t tiles_of(uint32_t n, uint32_t tile) { return (n + tile - 1) / tile; }
+
+static uint64_t nblocks_for(uint64_t n, uint32_t bpk, uint32_t B) {
+    uint64_t nb = (n * bpk + B - 1) / B;
+    return nb ? nb : 1;
+}
+
+static sj_status build_tree(sj_plan_t *p) {
+    const int n = p->n;
+    std::vector<std::vector<std::tuple<int, int, int, int>>> adj(n);   // (edge, other, my col, other col)
+    for (size_t ei = 0; ei < p->edges.size(); ++ei) {
+        const sj_edge &e = p->edges[ei];
+        adj[e.rel_a].emplace_back(static_cast<int>(ei), e.rel_b, e.col_a, e.col_b);
+        adj[e.rel_b].emplace_back(static_cast<int>(ei), e.rel_a, e.col_b, e.col_a);
+    }
+    p->parent.assign(n, -1);
+    p->pcol.assign(n, -1);
+    p->mycol.assign(n, -1);
+    p->children.assign(n, {});
+    p->preorder.clear();
+    std::vector<char> seen(n, 0), tree_edge(p->edges.size(), 0);
+    // iterative depth-first search that follows each relation's edges in input order
+    std::vector<std::pair<int, size_t>> stack;
+    seen[p->root] = 1;
+    p->preorder.push_back(p->root);
+    stack.emplace_back(p->root, 0);
+    while (!stack.empty()) {
+        auto &top = stack.back();
+        const int u = top.first;
+        if (top.second >= adj[u].size()) {
+            stack.pop_back();
+            continue;
+        }
+        auto [ei, v, cu, cv] = adj[u][top.second++];
+        if (seen[v]) continue;
+        seen[v] = 1;
+        tree_edge[ei] = 1;
+        p->parent[v] = u;
+        p->pcol[v] = cu;
+        p->mycol[v] = cv;
+        p->children[u].push_back(v);
+        p->preorder.push_back(v);
+        stack.emplace_back(v, 0);
+    }
+    for (int i = 0; i < n; ++i)
+        if (!seen[i]) return fail(p->ctx, SJ_ERR_GRAPH, "join graph is not connected (relation %d unreachable)", i);
+    std::vector<int> pos(n);
+    for (int i = 0; i < n; ++i) pos[p->preorder[i]] = i;
+    p->closing.clear();
+    for (size_t ei = 0; ei < p->edges.size(); ++ei) {
+        if (tree_edge[ei]) continue;
+        const sj_edge &e = p->edges[ei];
+        if (pos[e.rel_a] < pos[e.rel_b])
+            p->closing.push_back({e.rel_a, e.col_a, e.rel_b, e.col_b});
+        else
+            p->closing.push_back({e.rel_b, e.col_b, e.rel_a, e.col_a});
+    }
+    p->postorder.clear();
+    // postorder: children (in order) before the parent
+    std::vector<std::pair<int, size_t>> st2;
+    st2.emplace_back(p->root, 0);
+    while (!st2.empty()) {
+        auto &t = st2.back();
+        if (t.second < p->children[t.first].size()) {
+            const int c = p->children[t.first][t.second++];
+            st2.emplace_back(c, 0);
+        } else {
+            p->postorder.push_back(t.first);
+            st2.pop_back();
+        }
+    }
+    return SJ_OK;
+}
+
+static int add_filter(sj_plan_t *p, int kind, int index, int src_rel, int src_col) {
+    Filter f;
+    f.kind = kind;
+    f.index = index;
+    f.src_rel = src_rel;
+    f.src_col = src_col;
+    const uint64_t nb = nblocks_for(p->rels[src_rel].nrows, p->opts.bits_per_key, p->opts.block_bits);
+    f.max_words = nb * (p->opts.block_bits / 32);
+    p->filters.push_back(f);
+    return static_cast<int>(p->filters.size()) - 1;
+}
+
+static sj_status build_schedule(sj_plan_t *p) {
+    const int n = p->n;
+    const bool two = p->opts.passes == 2;
+    p->filters.clear();
+    p->f_bwd.assign(n, -1);
+    p->f_fwd.assign(n, -1);
+    p->f_close.assign(p->closing.size(), -1);
+    for (int j : p->postorder)
+        if (j != p->root) p->f_bwd[j] = add_filter(p, SJ_FILTER_BACKWARD, j, j, p->mycol[j]);
+    if (two)
+        for (int x : p->preorder)
+            if (x != p->root) p->f_fwd[x] = add_filter(p, SJ_FILTER_FORWARD, x, p->parent[x], p->pcol[x]);
+    for (size_t e = 0; e < p->closing.size(); ++e)
+        p->f_close[e] = add_filter(p, SJ_FILTER_CLOSING, static_cast<int>(e), p->closing[e].u, p->closing[e].cu);
+    if (p->filters.size() > 64) return fail(p->ctx, SJ_ERR_UNSUPPORTED, "more than 64 filters");
+
+    std::vector<int> cur(n, kFull), cur_step(n, -1);
+    p->steps.clear();
+    auto jx = [&](int rel, int col) { return p->rels[rel].jidx(col); };
+    auto push = [&](StepSpec s) -> sj_status {
+        if (s.probes.size() > static_cast<size_t>(kMaxProbe) || s.builds.size() > static_cast<size_t>(kMaxBuild))
+            return fail(p->ctx, SJ_ERR_UNSUPPORTED, "a relation probes or builds more than 8 filters");
+        s.src = cur[s.rel];
+        s.src_step = cur_step[s.rel];
+        if (s.out >= 0) {
+            s.out = (cur[s.rel] == 0) ? 1 : 0;
+            cur[s.rel] = s.out;
+            cur_step[s.rel] = static_cast<int>(p->steps.size());
+        }
+        p->steps.push_back(s);
+        return SJ_OK;
+    };
+    // backward pass: leaves toward the root (the pruning phase of Section 2.2)
+    for (int j : p->postorder) {
+        if (j == p->root) continue;
+        StepSpec s;
+        s.phase = 0;
+        s.rel = j;
+        for (int c : p->children[j]) s.probes.emplace_back(jx(j, p->pcol[c]), p->f_bwd[c]);
+        s.builds.emplace_back(jx(j, p->mycol[j]), p->f_bwd[j]);
+        s.out = (!p->children[j].empty() || !two) ? 0 : -1;
+        if (sj_status st = push(s)) return st;
+    }
+    {   // the root: sieved by its children's filters
+        StepSpec s;
+        s.phase = 1;
+        s.rel = p->root;
+        for (int c : p->children[p->root]) s.probes.emplace_back(jx(p->root, p->pcol[c]), p->f_bwd[c]);
+        if (two) {
+            for (int c : p->children[p->root]) s.builds.emplace_back(jx(p->root, p->pcol[c]), p->f_fwd[c]);
+            for (size_t e = 0; e < p->closing.size(); ++e)
+                if (p->closing[e].u == p->root) s.builds.emplace_back(jx(p->root, p->closing[e].cu), p->f_close[e]);
+        }
+        s.out = 0;
+        if (sj_status st = push(s)) return st;
+    }
+    if (!two) {
+        // closing edges (Section 2.3): a filter on the earlier end's survivors sieves the later end
+        for (size_t e = 0; e < p->closing.size(); ++e) {
+            const Closing &c = p->closing[e];
+            StepSpec b;
+            b.phase = 1;
+            b.rel = c.u;
+            b.builds.emplace_back(jx(c.u, c.cu), p->f_close[e]);
+            if (sj_status st = push(b)) return st;
+            StepSpec s;
+            s.phase = 1;
+            s.rel = c.v;
+            s.probes.emplace_back(jx(c.v, c.cv), p->f_close[e]);
+            s.out = 0;
+            if (sj_status st = push(s)) return st;
+        }
+    } else {
+        // forward pass: root toward the leaves (the dotted arrow of Fig. 2)
+        for (int x : p->preorder) {
+            if (x == p->root) continue;
+            StepSpec s;
+            s.phase = 1;
+            s.rel = x;
+            s.probes.emplace_back(jx(x, p->mycol[x]), p->f_fwd[x]);
+            for (size_t e = 0; e < p->closing.size(); ++e)
+                if (p->closing[e].v == x) s.probes.emplace_back(jx(x, p->closing[e].cv), p->f_close[e]);
+            for (int c : p->children[x]) s.builds.emplace_back(jx(x, p->pcol[c]), p->f_fwd[c]);
+            for (size_t e = 0; e < p->closing.size(); ++e)
+                if (p->closing[e].u == x) s.builds.emplace_back(jx(x, p->closing[e].cu), p->f_close[e]);
+            s.out = 0;
+            if (sj_status st = push(s)) return st;
+        }
+    }
+    p->final_list = cur;
+    p->final_step = cur_step;
+    for (int i = 0; i < n; ++i)
+        if (cur[i] == kFull) return fail(p->ctx, SJ_ERR_INVALID, "internal: relation %d has no survivor list", i);
+    return SJ_OK;
+}
+
+static void build_layout(sj_plan_t *p) {
+    Layout L;
+    const int n = p->n;
+    // phase zero regions first, each contiguous: [build_filters][sieve][join]
+    for (int ph = 0; ph < 2; ++ph) {
+        p->zero[ph].begin = L.top;
+        if (ph == 0) p->off_elig = L.take(sizeof(uint32_t) * SJ_MAX_RELS);
+        for (auto &f : p->filters) {
+            const int fph = (f.kind == SJ_FILTER_BACKWARD) ? 0 : 1;
+            if (fph == ph) f.off = L.take(f.max_words * 4);
+        }
+        for (auto &s : p->steps) {
+            if (s.phase != ph) continue;
+            s.max_rows = p->rels[s.rel].nrows;
+            s.off_status = L.take(8ull * std::max<uint32_t>(1, tiles_of(s.max_rows, kSieveTile)));
+            s.off_counter = L.take(4);
+            s.off_count = L.take(4);
+        }
+        p->zero[ph].end = L.top;
+    }
+    p->zero[2].begin = L.top;
+    p->off_totals = L.take(16);
+    p->jr.assign(n, {});
+    uint32_t maxcap = 0;
+    for (int j = 0; j < n; ++j) {
+        maxcap = std::max(maxcap, p->rels[j].nrows);
+        if (j == p->root) continue;
+        auto &r = p->jr[j];
+        const uint32_t cap = p->rels[j].nrows;
+        r.ghist = L.take(4ull * kRadixPasses * kRadixBins);
+        const uint32_t htiles = tiles_of(kRadixBins * tiles_of(cap, kRadixTile), kScanTile);
+        for (int q = 0; q < kRadixPasses; ++q) {
+            r.lb_hist[q] = L.take(8ull * std::max<uint32_t>(1, htiles));
+            r.lb_hist_ctr[q] = L.take(4);
+        }
+        r.lb_dir = L.take(8ull * std::max<uint32_t>(1, tiles_of(cap, kSieveTile)));
+        r.lb_dir_ctr = L.take(4);
+        r.ndir = L.take(4);
+    }
+    p->zero[2].end = L.top;
+    // not cleared
+    p->off_nblocks = L.take(4ull * std::max<size_t>(1, p->filters.size()));
+    for (int b = 0; b < 2; ++b) p->off_list[b].assign(n, 0);
+    for (int j = 0; j < n; ++j) {
+        const uint64_t cap = p->rels[j].nrows;
+        const uint64_t per = (1 + p->rels[j].jcols.size()) * cap * 4;
+        for (int b = 0; b < 2; ++b) p->off_list[b][j] = L.take(per);
+    }
+    for (int j = 0; j < n; ++j) {
+        if (j == p->root) continue;
+        auto &r = p->jr[j];
+        const uint64_t cap = p->rels[j].nrows;
+        r.rid = L.take(4 * cap);
+        r.cols = L.take(4 * cap * p->rels[j].jcols.size());
+        r.dir_begin = L.take(4 * (cap + 1));
+        r.dir_key = L.take(4 * cap);
+        uint64_t sc = 16;
+        while (sc < 2 * cap + 1) sc <<= 1;
+        r.slot_cap = static_cast<uint32_t>(sc);
+        r.slots = L.take(8 * sc);
+        r.cw = L.take(8 * (cap + 1));
+        r.cv = L.take(8 * (cap + 1));
+        r.mask = L.take(4);
+    }
+    p->sort_cap = maxcap;
+    for (int b = 0; b < 2; ++b) {
+        p->off_sort_keys[b] = L.take(4ull * maxcap);
+        p->off_sort_vals[b] = L.take(4ull * maxcap);
+    }
+    p->off_hist = L.take(4ull * kRadixBins * std::max<uint32_t>(1, tiles_of(maxcap, kRadixTile)));
+    p->off_ctl = L.take(4 * 16);
+    p->off_tile_sums = L.take(16ull * std::max<uint32_t>(1, tiles_of(maxcap, kScanTile)));
+    const uint64_t rc = p->rels[p->root].nrows;
+    p->off_root_cw = L.take(8 * (rc + 1));
+    p->off_root_cv = L.take(8 * (rc + 1));
+    p->ws_bytes = L.top;
+}
+
+extern "C" sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, const sj_edge *edges, int32_t nedges,
+                             const sj_opts *opts, sj_plan_t **out, uint64_t *workspace_bytes) {
+    if (!ctx || !out || !workspace_bytes) return fail(ctx, SJ_ERR_INVALID, "null argument");
+    *out = nullptr;
+    *workspace_bytes = 0;
+    if (!rels || nrels < 1 || nrels > SJ_MAX_RELS) return fail(ctx, SJ_ERR_INVALID, "nrels must be 1..%d", SJ_MAX_RELS);
+    if (nedges < 0 || nedges > SJ_MAX_EDGES || (nedges > 0 && !edges))
+        return fail(ctx, SJ_ERR_INVALID, "nedges must be 0..%d", SJ_MAX_EDGES);
+    sj_opts o{};
+    if (opts) o = *opts;
+    if (o.bits_per_key == 0) o.bits_per_key = 8;
+    if (o.k == 0) o.k = 6;
+    if (o.block_bits == 0) o.block_bits = 512;
+    if (o.passes == 0) o.passes = 2;
+    if (o.root < 0) o.root = 0;
+    if (o.k > static_cast<uint32_t>(kMaxK)) return fail(ctx, SJ_ERR_INVALID, "k must be 1..%d", kMaxK);
+    if (o.bits_per_key > 1024) return fail(ctx, SJ_ERR_INVALID, "bits_per_key must be <= 1024");
+    if (o.block_bits != 256 && o.block_bits != 512 && o.block_bits != 1024)
+        return fail(ctx, SJ_ERR_INVALID, "block_bits must be 256, 512 or 1024");
+    if (o.passes != 1 && o.passes != 2) return fail(ctx, SJ_ERR_INVALID, "passes must be 1 or 2");
+    if (o.root >= nrels) return fail(ctx, SJ_ERR_INVALID, "root out of range");
+    if (o.flags != 0) return fail(ctx, SJ_ERR_INVALID, "flags must be 0");
+
+    sj_plan_t *p = new (std::nothrow) sj_plan_t;
+    if (!p) return fail(ctx, SJ_ERR_INVALID, "out of host memory");
+    p->ctx = ctx;
+    p->n = nrels;
+    p->opts = o;
+    p->logB = (o.block_bits == 256) ? 8 : (o.block_bits == 512 ? 9 : 10);
+    p->root = o.root;
+    {   // 32-bit filter seed: the low word of SplitMix64's output function of the seed
+        uint64_t z = o.seed;
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        z ^= z >> 31;
+        p->seed32 = static_cast<uint32_t>(z);
+    }
+    p->rels.resize(nrels);
+    for (int i = 0; i < nrels; ++i) {
+        const sj_rel &r = rels[i];
+        Rel &R = p->rels[i];
+        if (r.nrows < 0 || r.nrows >= (int64_t(1) << 31)) {
+            delete p;
+            return fail(ctx, SJ_ERR_INVALID, "relation %d: nrows must be in [0, 2^31)", i);
+        }
+        if (r.ncols < 1 || r.ncols > SJ_MAX_COLS || !r.cols) {
+            delete p;
+            return fail(ctx, SJ_ERR_INVALID, "relation %d: ncols must be 1..%d", i, SJ_MAX_COLS);
+        }
+        R.nrows = static_cast<uint32_t>(r.nrows);
+        R.cols.assign(r.cols, r.cols + r.ncols);
+        for (int c = 0; c < r.ncols; ++c) {
+            if (R.nrows > 0 && !R.cols[c]) {
+                delete p;
+                return fail(ctx, SJ_ERR_INVALID, "relation %d column %d is null", i, c);
+            }
+            if (reinterpret_cast<uintptr_t>(R.cols[c]) % 16) {
+                delete p;
+                return fail(ctx, SJ_ERR_INVALID, "relation %d column %d is not 16-byte aligned", i, c);
+            }
+        }
+        if (r.pred_col >= r.ncols || r.pred_col < -1) {
+            delete p;
+            return fail(ctx, SJ_ERR_GRAPH, "relation %d: bad predicate column %d", i, r.pred_col);
+        }
+        R.pred_col = r.pred_col;
+        R.lo = r.pred_lo;
+        R.hi = r.pred_hi;
+    }
+    p->edges.assign(edges, edges + nedges);
+    for (int ei = 0; ei < nedges; ++ei) {
+        const sj_edge &e = edges[ei];
+        if (e.rel_a < 0 || e.rel_a >= nrels || e.rel_b < 0 || e.rel_b >= nrels) {
+            delete p;
+            return fail(ctx, SJ_ERR_GRAPH, "edge %d: relation index out of range", ei);
+        }
+        if (e.rel_a == e.rel_b) {
+            delete p;
+            return fail(ctx, SJ_ERR_GRAPH, "edge %d joins relation %d with itself", ei, e.rel_a);
+        }
+        if (e.col_a < 0 || e.col_a >= static_cast<int>(p->rels[e.rel_a].cols.size()) || e.col_b < 0 ||
+            e.col_b >= static_cast<int>(p->rels[e.rel_b].cols.size())) {
+            delete p;
+            return fail(ctx, SJ_ERR_GRAPH, "edge %d: column index out of range", ei);
+        }
+        for (auto [r, c] : {std::pair<int, int>{e.rel_a, e.col_a}, {e.rel_b, e.col_b}}) {
+            auto &jc = p->rels[r].jcols;
+            if (std::find(jc.begin(), jc.end(), c) == jc.end()) jc.push_back(c);
+        }
+    }
+    for (int i = 0; i < nrels; ++i) {
+        auto &jc = p->rels[i].jcols;
+        std::sort(jc.begin(), jc.end());
+        if (jc.empty()) jc.push_back(0);
+        if (jc.size() > static_cast<size_t>(kMaxJCols)) {
+            delete p;
+            return fail(ctx, SJ_ERR_UNSUPPORTED, "relation %d joins on more than %d columns", i, kMaxJCols);
+        }
+    }
+    if (sj_status st = build_tree(p)) {
+        delete p;
+        return st;
+    }
+    if (sj_status st = build_schedule(p)) {
+        delete p;
+        return st;
+    }
+    build_layout(p);
+    *workspace_bytes = p->ws_bytes;
+    *out = p;
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_bind_workspace(sj_plan_t *p, void *ws, uint64_t bytes) {
+    if (!p) return SJ_ERR_INVALID;
+    if (!ws && p->ws_bytes) return fail(p->ctx, SJ_ERR_INVALID, "null workspace");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(p->ctx, SJ_ERR_INVALID, "workspace must be 256-byte aligned");
+    if (bytes < p->ws_bytes)
+        return fail(p->ctx, SJ_ERR_NOMEM, "workspace has %llu bytes, plan needs %llu",
+                    static_cast<unsigned long long>(bytes), static_cast<unsigned long long>(p->ws_bytes));
+    p->ws = static_cast<char *>(ws);
+    p->state = kBound;
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_plan_destroy(sj_plan_t *p) {
+    delete p;
+    return SJ_OK;
+}
+
+// ---------------------------------------------------------------- execution helpers
+
+template <typename T>
+static T *at(sj_plan_t *p, uint64_t off) {
+    return reinterpret_cast<T *>(p->ws + off);
+}
+
+static uint32_t *list_rid(sj_plan_t *p, int rel, int buf) { return at<uint32_t>(p, p->off_list[buf][rel]); }
+static int32_t *list_col(sj_plan_t *p, int rel, int buf, int jc) {
+    return at<int32_t>(p, p->off_list[buf][rel] + 4ull * p->rels[rel].nrows * (1 + jc));
+}
+
+static sj_status run_steps(sj_plan_t *p, int phase) {
+    hipStream_t s = p->ctx->stream;
+    for (auto &st : p->steps) {
+        if (st.phase != phase) continue;
+        const Rel &R = p->rels[st.rel];
+        StepArgs a{};
+        a.ncol = static_cast<int>(R.jcols.size());
+        if (st.src == kFull) {
+            a.src_rid = nullptr;
+            a.src_count = nullptr;
+            a.src_rows = R.nrows;
+            for (int c = 0; c < a.ncol; ++c) a.col[c] = R.cols[R.jcols[c]];
+            a.pred = R.pred_col >= 0 ? R.cols[R.pred_col] : nullptr;
+            a.pred_lo = R.lo;
+            a.pred_hi = R.hi;
+        } else {
+            a.src_rid = list_rid(p, st.rel, st.src);
+            a.src_count = at<uint32_t>(p, p->steps[st.src_step].off_count);
+            a.src_rows = R.nrows;
+            for (int c = 0; c < a.ncol; ++c) a.col[c] = list_col(p, st.rel, st.src, c);
+            a.pred = nullptr;
+        }
+        a.nprobe = static_cast<int>(st.probes.size());
+        for (int i = 0; i < a.nprobe; ++i) {
+            a.probe_col[i] = static_cast<int8_t>(st.probes[i].first);
+            const int f = st.probes[i].second;
+            a.probe[i].words = at<uint32_t>(p, p->filters[f].off);
+            a.probe[i].nblocks = at<uint32_t>(p, p->off_nblocks) + f;
+        }
+        a.nbuild = static_cast<int>(st.builds.size());
+        for (int i = 0; i < a.nbuild; ++i) {
+            a.build_col[i] = static_cast<int8_t>(st.builds[i].first);
+            const int f = st.builds[i].second;
+            a.build[i].words = at<uint32_t>(p, p->filters[f].off);
+            a.build[i].nblocks = at<uint32_t>(p, p->off_nblocks) + f;
+        }
+        if (st.out >= 0) {
+            a.out_rid = list_rid(p, st.rel, st.out);
+            for (int c = 0; c < a.ncol; ++c) a.out_col[c] = list_col(p, st.rel, st.out, c);
+            a.out_count = at<uint32_t>(p, st.off_count);
+        }
+        a.lb.status = at<uint64_t>(p, st.off_status);
+        a.lb.counter = at<uint32_t>(p, st.off_counter);
+        a.seed = p->seed32;
+        a.k = static_cast<int>(p->opts.k);
+        a.logB = p->logB;
+        SJ_HIP(p->ctx, launch_sieve_step(a, st.max_rows, s));
+    }
+    return SJ_OK;
+}
+
+static sj_status zero_region(sj_plan_t *p, int ph) {
+    const Region &r = p->zero[ph];
+    SJ_HIP(p->ctx, launch_zero(p->ws + r.begin, r.end - r.begin, p->ctx->stream));
+    return SJ_OK;
+}
+
+static sj_status check_exec(sj_plan_t *p, int need) {
+    if (!p) return SJ_ERR_INVALID;
+    if (p->state < need) {
+        static const char *names[] = {"sj_plan", "sj_bind_workspace", "sj_build_filters", "sj_sieve", "sj_join"};
+        return fail(p->ctx, SJ_ERR_STATE, "call %s first", names[need]);
+    }
+    SJ_HIP(p->ctx, hipSetDevice(p->ctx->device));
+    return SJ_OK;
+}
+
+// ---------------------------------------------------------------- the pruning phase
+
+extern "C" sj_status sj_build_filters(sj_plan_t *p) {
+    if (sj_status st = check_exec(p, kBound)) return st;
+    hipStream_t s = p->ctx->stream;
+    if (sj_status st = zero_region(p, 0)) return st;
+    uint32_t *elig = at<uint32_t>(p, p->off_elig);
+    for (int i = 0; i < p->n; ++i) {
+        const Rel &R = p->rels[i];
+        if (R.pred_col >= 0) SJ_HIP(p->ctx, launch_count_pred(R.cols[R.pred_col], R.nrows, R.lo, R.hi, elig + i, s));
+    }
+    SizeArgs sa{};
+    sa.nfilters = static_cast<int>(p->filters.size());
+    sa.bits_per_key = p->opts.bits_per_key;
+    sa.block_bits = p->opts.block_bits;
+    for (int f = 0; f < sa.nfilters; ++f) {
+        const int r = p->filters[f].src_rel;
+        sa.elig[f] = p->rels[r].pred_col >= 0 ? elig + r : nullptr;
+        sa.rows[f] = p->rels[r].nrows;
+        sa.nblocks[f] = at<uint32_t>(p, p->off_nblocks) + f;
+    }
+    SJ_HIP(p->ctx, launch_size_filters(sa, s));
+    if (sj_status st = run_steps(p, 0)) return st;
+    p->state = kFiltered;
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_sieve(sj_plan_t *p, uint64_t *survivors) {
+    if (sj_status st = check_exec(p, kFiltered)) return st;
+    if (sj_status st = zero_region(p, 1)) return st;
+    if (sj_status st = run_steps(p, 1)) return st;
+    p->state = kSieved;
+    if (survivors) {
+        std::vector<uint32_t> c(p->n);
+        for (int i = 0; i < p->n; ++i)
+            SJ_HIP(p->ctx, hipMemcpyAsync(&c[i], at<uint32_t>(p, p->steps[p->final_step[i]].off_count), 4,
+                                          hipMemcpyDeviceToHost, p->ctx->stream));
+        SJ_HIP(p->ctx, hipStreamSynchronize(p->ctx->stream));
+        for (int i = 0; i < p->n; ++i) survivors[i] = c[i];
+    }
+    return SJ_OK;
+}
+
+// ---------------------------------------------------------------- the enumeration phase
+
+static Buckets buckets_of(sj_plan_t *p, int j) {
+    auto &r = p->jr[j];
+    Buckets b{};
+    b.cap = p->rels[j].nrows;
+    b.n = at<uint32_t>(p, p->steps[p->final_step[j]].off_count);
+    b.rid = at<uint32_t>(p, r.rid);
+    b.npay = static_cast<int>(p->rels[j].jcols.size());
+    for (int c = 0; c < b.npay; ++c) b.col[c] = at<int32_t>(p, r.cols + 4ull * b.cap * c);
+    b.key_jcol = p->rels[j].jidx(p->mycol[j]);
+    b.dir_begin = at<uint32_t>(p, r.dir_begin);
+    b.dir_key = at<int32_t>(p, r.dir_key);
+    b.ndir = at<uint32_t>(p, r.ndir);
+    b.slots = at<uint64_t>(p, r.slots);
+    b.slot_cap = r.slot_cap;
+    b.slot_mask = at<uint32_t>(p, r.mask);
+    b.cw = at<uint64_t>(p, r.cw);
+    b.cv = at<uint64_t>(p, r.cv);
+    return b;
+}
+
+extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) {
+    if (sj_status st = check_exec(p, kSieved)) return st;
+    if (!p->closing.empty())
+        return fail(p->ctx, SJ_ERR_UNSUPPORTED, "cyclic join graphs are not executed by this build yet");
+    hipStream_t s = p->ctx->stream;
+    if (sj_status st = zero_region(p, 2)) return st;
+    for (int j : p->postorder) {
+        const int fl = p->final_list[j];
+        const Rel &R = p->rels[j];
+        const int ncol = static_cast<int>(R.jcols.size());
+        std::vector<const int32_t *> lcols(ncol);
+        for (int c = 0; c < ncol; ++c) lcols[c] = list_col(p, j, fl, c);
+        const uint32_t *lcount = at<uint32_t>(p, p->steps[p->final_step[j]].off_count);
+        DpArgs d{};
+        d.rel = static_cast<uint32_t>(j);
+        d.nchild = static_cast<int>(p->children[j].size());
+        if (d.nchild > kMaxJCols) return fail(p->ctx, SJ_ERR_UNSUPPORTED, "relation %d has more than %d children", j, kMaxJCols);
+        for (int c = 0; c < d.nchild; ++c) {
+            const int ch = p->children[j][c];
+            d.child_col[c] = R.jidx(p->pcol[ch]);
+            d.child[c] = buckets_of(p, ch);
+        }
+        d.tile_sums = at<uint64_t>(p, p->off_tile_sums);
+        if (j != p->root) {
+            Buckets b = buckets_of(p, j);
+            auto &r = p->jr[j];
+            SortScratch ss{};
+            ss.cap = p->sort_cap;
+            for (int q = 0; q < 2; ++q) {
+                ss.keys[q] = at<uint32_t>(p, p->off_sort_keys[q]);
+                ss.vals[q] = at<uint32_t>(p, p->off_sort_vals[q]);
+            }
+            ss.hist = at<uint32_t>(p, p->off_hist);
+            ss.ghist = at<uint32_t>(p, r.ghist);
+            ss.ctl = at<uint32_t>(p, p->off_ctl);
+            for (int q = 0; q < kRadixPasses; ++q) {
+                ss.lb[q].status = at<uint64_t>(p, r.lb_hist[q]);
+                ss.lb[q].counter = at<uint32_t>(p, r.lb_hist_ctr[q]);
+            }
+            Lookback ld{at<uint64_t>(p, r.lb_dir), at<uint32_t>(p, r.lb_dir_ctr)};
+            SJ_HIP(p->ctx, launch_build_buckets(list_rid(p, j, fl), lcols.data(), ncol, lcount, b.key_jcol, b, ss, ld, s));
+            d.n = b.n;
+            d.cap = b.cap;
+            d.rid = b.rid;
+            for (int c = 0; c < ncol; ++c) d.col[c] = b.col[c];
+            d.cw = b.cw;
+            d.cv = b.cv;
+            d.totals = nullptr;
+        } else {
+            d.n = lcount;
+            d.cap = R.nrows;
+            d.rid = list_rid(p, j, fl);
+            for (int c = 0; c < ncol; ++c) d.col[c] = lcols[c];
+            d.cw = at<uint64_t>(p, p->off_root_cw);
+            d.cv = at<uint64_t>(p, p->off_root_cv);
+            d.totals = at<uint64_t>(p, p->off_totals);
+        }
+        SJ_HIP(p->ctx, launch_dp(d, s));
+    }
+    uint64_t tot[2] = {0, 0};
+    SJ_HIP(p->ctx, hipMemcpyAsync(tot, at<uint64_t>(p, p->off_totals), 16, hipMemcpyDeviceToHost, s));
+    SJ_HIP(p->ctx, hipStreamSynchronize(s));
+    p->count = tot[0];
+    p->checksum = tot[1];
+    if (count) *count = tot[0];
+    if (checksum) *checksum = tot[1];
+    p->state = kJoined;
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_result(sj_plan_t *p, int32_t *out, uint64_t capacity) {
+    if (sj_status st = check_exec(p, kJoined)) return st;
+    if (capacity < p->count)
+        return fail(p->ctx, SJ_ERR_CAPACITY, "result has %llu tuples, buffer holds %llu",
+                    static_cast<unsigned long long>(p->count), static_cast<unsigned long long>(capacity));
+    if (p->count == 0) return SJ_OK;
+    if (!out) return fail(p->ctx, SJ_ERR_INVALID, "null output buffer");
+    if (reinterpret_cast<uintptr_t>(out) % 16) return fail(p->ctx, SJ_ERR_INVALID, "output must be 16-byte aligned");
+    MatArgs m{};
+    m.nrels = p->n;
+    std::vector<int> pos(p->n);
+    for (int i = 0; i < p->n; ++i) pos[p->preorder[i]] = i;
+    for (int x = 0; x < p->n; ++x) {
+        const int r = p->preorder[x];
+        m.order[x] = r;
+        m.is_leaf[x] = p->children[r].empty() ? 1 : 0;
+        m.nchild[x] = static_cast<int>(p->children[r].size());
+        if (x == 0) {
+            m.parent_pos[x] = -1;
+            m.key_col_in_parent[x] = 0;
+        } else {
+            const int par = p->parent[r];
+            m.parent_pos[x] = pos[par];
+            m.key_col_in_parent[x] = p->rels[par].jidx(p->pcol[r]);
+            m.b[x] = buckets_of(p, r);
+        }
+    }
+    const int root = p->root;
+    const int fl = p->final_list[root];
+    m.root_n = at<uint32_t>(p, p->steps[p->final_step[root]].off_count);
+    m.root_rid = list_rid(p, root, fl);
+    for (size_t c = 0; c < p->rels[root].jcols.size(); ++c) m.root_col[c] = list_col(p, root, fl, static_cast<int>(c));
+    m.root_cw = at<uint64_t>(p, p->off_root_cw);
+    m.count = p->count;
+    m.count_dev = at<uint64_t>(p, p->off_totals);
+    m.out = out;
+    m.chunk = 16;
+    SJ_HIP(p->ctx, launch_materialize(m, p->ctx->stream));
+    return SJ_OK;
+}
+
+// ---------------------------------------------------------------- introspection
+
+extern "C" sj_status sj_filter_count(const sj_plan_t *p, int32_t *nf) {
+    if (!p || !nf) return SJ_ERR_INVALID;
+    *nf = static_cast<int32_t>(p->filters.size());
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_filter_desc(sj_plan_t *p, int32_t f, int32_t *kind, int32_t *index, int32_t *src_rel,
+                                    int32_t *src_col, uint32_t *nblocks) {
+    if (!p || f < 0 || f >= static_cast<int32_t>(p->filters.size())) return SJ_ERR_INVALID;
+    const Filter &F = p->filters[f];
+    if (kind) *kind = F.kind;
+    if (index) *index = F.index;
+    if (src_rel) *src_rel = F.src_rel;
+    if (src_col) *src_col = F.src_col;
+    if (nblocks) {
+        if (sj_status st = check_exec(p, kFiltered)) return st;
+        uint32_t nb = 0;
+        SJ_HIP(p->ctx, hipMemcpyAsync(&nb, at<uint32_t>(p, p->off_nblocks) + f, 4, hipMemcpyDeviceToHost, p->ctx->stream));
+        SJ_HIP(p->ctx, hipStreamSynchronize(p->ctx->stream));
+        *nblocks = nb;
+    }
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_filter_copy(sj_plan_t *p, int32_t f, uint32_t *dst, uint64_t capacity_words) {
+    if (!p || f < 0 || f >= static_cast<int32_t>(p->filters.size()) || !dst) return SJ_ERR_INVALID;
+    if (sj_status st = check_exec(p, kFiltered)) return st;
+    uint32_t nb = 0;
+    if (sj_status st = sj_filter_desc(p, f, nullptr, nullptr, nullptr, nullptr, &nb)) return st;
+    const uint64_t words = static_cast<uint64_t>(nb) * (p->opts.block_bits / 32);
+    if (capacity_words < words) return fail(p->ctx, SJ_ERR_CAPACITY, "filter has %llu words", static_cast<unsigned long long>(words));
+    SJ_HIP(p->ctx, hipMemcpyAsync(dst, at<uint32_t>(p, p->filters[f].off), words * 4, hipMemcpyDeviceToDevice,
+                                  p->ctx->stream));
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_survivors_copy(sj_plan_t *p, int32_t rel, uint32_t *dst, uint64_t capacity, uint64_t *n) {
+    if (!p || rel < 0 || rel >= p->n || !n) return SJ_ERR_INVALID;
+    if (sj_status st = check_exec(p, kSieved)) return st;
+    uint32_t c = 0;
+    SJ_HIP(p->ctx, hipMemcpyAsync(&c, at<uint32_t>(p, p->steps[p->final_step[rel]].off_count), 4,
+                                  hipMemcpyDeviceToHost, p->ctx->stream));
+    SJ_HIP(p->ctx, hipStreamSynchronize(p->ctx->stream));
+    *n = c;
+    if (c == 0 || !dst) return SJ_OK;
+    if (capacity < c) return fail(p->ctx, SJ_ERR_CAPACITY, "relation %d has %u survivors", rel, c);
+    SJ_HIP(p->ctx, hipMemcpyAsync(dst, list_rid(p, rel, p->final_list[rel]), 4ull * c, hipMemcpyDeviceToDevice,
+                                  p->ctx->stream));
+    return SJ_OK;
+}

@@ -1,0 +1,122 @@
+"""Host-side checks of the C ABI (no GPU needed): exported symbols, plan validation
+and the call-order state machine. sj_plan is host-only, so fake (aligned, non-null)
+device addresses exercise it without touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sievejoin.h")
+LIB = os.path.join(ROOT, "paper_2308_16370_amd", "libsievejoin.so")
+
+if not os.path.exists(LIB):
+    pytest.skip("libsievejoin.so not built", allow_module_level=True)
+
+import paper_2308_16370_amd as sj  # noqa: E402
+
+
+def header_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:sj_status|const char \*)\s*(sj_\w+)\s*\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol():
+    L = ctypes.CDLL(LIB)
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(sj.EXPORTED) == names
+
+
+FAKE = 0x7F0000000000
+
+
+def mkrels(specs):
+    """specs: list of (nrows, ncols, pred) -> (_Rel array, keepalive)."""
+    arr = (sj._Rel * len(specs))()
+    keep = []
+    addr = FAKE
+    for i, (n, nc, pred) in enumerate(specs):
+        ptrs = (ctypes.c_void_p * nc)(*[addr + 4096 * j for j in range(nc)])
+        addr += 1 << 30
+        keep.append(ptrs)
+        arr[i].nrows, arr[i].ncols = n, nc
+        arr[i].cols = ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p))
+        arr[i].pred_col, arr[i].pred_lo, arr[i].pred_hi = pred if pred else (-1, 0, 0)
+    return arr, keep
+
+
+def plan(specs, edges, **kw):
+    L = sj.lib()
+    ctx = ctypes.c_void_p()
+    assert L.sj_ctx_create(0, None, ctypes.byref(ctx)) == 0
+    arr, keep = mkrels(specs)
+    earr = (sj._Edge * max(1, len(edges)))(*[sj._Edge(*e) for e in edges])
+    o = sj._Opts(kw.get("bpk", 0), kw.get("k", 0), kw.get("B", 0), kw.get("passes", 0), 0, kw.get("root", -1),
+                 kw.get("flags", 0))
+    p = ctypes.c_void_p()
+    ws = ctypes.c_uint64()
+    st = L.sj_plan(ctx, arr, len(specs), earr, len(edges), ctypes.byref(o), ctypes.byref(p), ctypes.byref(ws))
+    err = L.sj_last_error(ctx).decode()
+    return st, p, ws.value, ctx, err
+
+
+def test_valid_chain_plans():
+    st, p, ws, ctx, err = plan([(1000, 2, None)] * 4, [(0, 1, 1, 0), (1, 1, 2, 0), (2, 1, 3, 0)])
+    assert st == 0, err
+    assert ws > 4 * 1000 * 4
+    nf = ctypes.c_int32()
+    assert sj.lib().sj_filter_count(p, ctypes.byref(nf)) == 0
+    assert nf.value == 6          # 3 backward + 3 forward
+    st, p1, ws1, _, err = plan([(1000, 2, None)] * 4, [(0, 1, 1, 0), (1, 1, 2, 0), (2, 1, 3, 0)], passes=1)
+    assert st == 0
+    assert sj.lib().sj_filter_count(p1, ctypes.byref(nf)) == 0 and nf.value == 3
+
+
+@pytest.mark.parametrize("specs,edges,kw,code", [
+    ([(10, 2, None)] * 2, [(0, 1, 0, 0)], {}, sj.SJ_ERR_GRAPH),                  # self-edge
+    ([(10, 2, None)] * 3, [(0, 1, 1, 0)], {}, sj.SJ_ERR_GRAPH),                  # disconnected
+    ([(10, 2, None)] * 2, [(0, 2, 1, 0)], {}, sj.SJ_ERR_GRAPH),                  # bad column
+    ([(10, 2, None)] * 2, [(0, 1, 5, 0)], {}, sj.SJ_ERR_GRAPH),                  # bad relation
+    ([(10, 2, (3, 0, 1))] * 2, [(0, 1, 1, 0)], {}, sj.SJ_ERR_GRAPH),             # bad predicate column
+    ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"k": 13}, sj.SJ_ERR_INVALID),
+    ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"B": 384}, sj.SJ_ERR_INVALID),
+    ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"passes": 3}, sj.SJ_ERR_INVALID),
+    ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"root": 2}, sj.SJ_ERR_INVALID),
+    ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"flags": 1}, sj.SJ_ERR_INVALID),
+    ([(2**31, 2, None)] * 2, [(0, 1, 1, 0)], {}, sj.SJ_ERR_INVALID),
+])
+def test_invalid_plans(specs, edges, kw, code):
+    st, p, ws, ctx, err = plan(specs, edges, **kw)
+    assert st == code, err
+    assert err
+
+
+def test_misaligned_column_rejected():
+    L = sj.lib()
+    ctx = ctypes.c_void_p()
+    L.sj_ctx_create(0, None, ctypes.byref(ctx))
+    arr, keep = mkrels([(10, 1, None), (10, 1, None)])
+    bad = (ctypes.c_void_p * 1)(FAKE + 4)
+    arr[1].cols = ctypes.cast(bad, ctypes.POINTER(ctypes.c_void_p))
+    earr = (sj._Edge * 1)(sj._Edge(0, 0, 1, 0))
+    p, ws = ctypes.c_void_p(), ctypes.c_uint64()
+    assert L.sj_plan(ctx, arr, 2, earr, 1, None, ctypes.byref(p), ctypes.byref(ws)) == sj.SJ_ERR_INVALID
+
+
+def test_state_machine_and_workspace_size():
+    st, p, ws, ctx, err = plan([(100, 2, None)] * 3, [(0, 1, 1, 0), (1, 1, 2, 0)])
+    L = sj.lib()
+    assert st == 0
+    assert L.sj_build_filters(p) == sj.SJ_ERR_STATE
+    assert L.sj_sieve(p, None) == sj.SJ_ERR_STATE
+    assert L.sj_join(p, None, None) == sj.SJ_ERR_STATE
+    assert L.sj_result(p, None, 0) == sj.SJ_ERR_STATE
+    assert L.sj_bind_workspace(p, ctypes.c_void_p(FAKE), ws - 1) == sj.SJ_ERR_NOMEM
+    assert L.sj_bind_workspace(p, ctypes.c_void_p(FAKE + 64), ws) == sj.SJ_ERR_INVALID
+    assert L.sj_bind_workspace(p, ctypes.c_void_p(FAKE), ws) == 0
+    assert L.sj_join(p, None, None) == sj.SJ_ERR_STATE
+    assert L.sj_plan_destroy(p) == 0
