@@ -365,8 +365,9 @@ class _BloomFactory:
         self.bpk, self.k, self.B = bits_per_key, k, block_bits
         self.seed32 = filter_seed(seed)
 
-    def build(self, keys, rows, n_elig):
-        nb = bf_nblocks(n_elig, self.bpk, self.B)
+    def build(self, keys, rows):
+        # sized for the keys it receives: ceil(bits_per_key * |rows| / B) blocks
+        nb = bf_nblocks(rows.shape[0], self.bpk, self.B)
         return (bf_build(keys, rows, nb, self.k, self.B, self.seed32), nb)
 
     def probe(self, f, keys, rows):
@@ -377,7 +378,7 @@ class _BloomFactory:
 class _ExactFactory:
     """Exact key sets in place of filters (for the full-reducer pins)."""
 
-    def build(self, keys, rows, n_elig):
+    def build(self, keys, rows):
         return np.unique(keys[rows].astype(np.int64))
 
     def probe(self, f, keys, rows):
@@ -390,15 +391,16 @@ def sieve(query, bits_per_key: int = 8, k: int = 6, block_bits: int = 512, passe
 
     Returns ``(survivors, filters)``: survivors[r] is an ascending uint32 array;
     filters maps ('bwd', j) / ('fwd', j) / ('close', e) to (words, nblocks) -- or to
-    a key set when ``exact``. A filter built on relation x's column is sized for
-    x's predicate-eligible row count at ``bits_per_key``.
+    a key set when ``exact``. A filter is sized for the rows it receives: Bloomjoin
+    (Section 2.1 step 2) sizes the filter per tuple of the relation whose keys it
+    holds, so a filter holding n survivors' keys gets ceil(bits_per_key * n / B)
+    blocks.
     """
     root = query.root if root is None else root
     rels = query.rels
     t = JoinTree(len(rels), query.edges, root)
     fac = _ExactFactory() if exact else _BloomFactory(bits_per_key, k, block_bits, seed)
     elig = [eligible(r) for r in rels]
-    nel = [int(e.shape[0]) for e in elig]
     S: Dict[int, np.ndarray] = {}
     F: Dict[tuple, object] = {}
 
@@ -409,12 +411,12 @@ def sieve(query, bits_per_key: int = 8, k: int = 6, block_bits: int = 512, passe
             rows = rows[fac.probe(F[("bwd", c)], rels[j].cols[t.pcol[c]], rows)]
         S[j] = rows
         if j != root:
-            F[("bwd", j)] = fac.build(rels[j].cols[t.mycol[j]], rows, nel[j])
+            F[("bwd", j)] = fac.build(rels[j].cols[t.mycol[j]], rows)
 
     if passes == 1:
         # closing edges: filter on the earlier end's survivors sieves the later end
         for e, (u, cu, v, cv) in enumerate(t.closing):
-            F[("close", e)] = fac.build(rels[u].cols[cu], S[u], nel[u])
+            F[("close", e)] = fac.build(rels[u].cols[cu], S[u])
             S[v] = S[v][fac.probe(F[("close", e)], rels[v].cols[cv], S[v])]
     elif passes == 2:
         # forward pass: root to leaves, each relation sieved by its parent's survivors
@@ -427,10 +429,10 @@ def sieve(query, bits_per_key: int = 8, k: int = 6, block_bits: int = 512, passe
                         rows = rows[fac.probe(F[("close", e)], rels[x].cols[cv], rows)]
                 S[x] = rows
             for c in t.children[x]:
-                F[("fwd", c)] = fac.build(rels[x].cols[t.pcol[c]], S[x], nel[x])
+                F[("fwd", c)] = fac.build(rels[x].cols[t.pcol[c]], S[x])
             for e, (u, cu, v, cv) in enumerate(t.closing):
                 if u == x:
-                    F[("close", e)] = fac.build(rels[x].cols[cu], S[x], nel[x])
+                    F[("close", e)] = fac.build(rels[x].cols[cu], S[x])
     else:
         raise ValueError("passes must be 1 or 2")
     return [S[r] for r in range(len(rels))], F
