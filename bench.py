@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark of the SieveJoin hot path on one MI355X.
+
+Workload: 4-way chain R1(a,b) join R2(b,c) join R3(c,d) join R4(d,e), 10M rows per
+table, int32 keys Zipf(s=1.1) over 2^22 values with an independent random
+rank->key permutation per (table, column); blocked Bloom filters of 8 bits per
+key, k = 6, 512-bit blocks; backward and forward pruning passes; exact result
+count, checksum and materialised int32 row-id tuples.
+
+One step = sj_build_filters + sj_sieve + sj_join + sj_result on a plan whose
+inputs and workspace are already resident in HBM. The metric is input tuples per
+second (the sum of the four relations' rows divided by the step time).
+
+Printed: one JSON line with the contract's fields plus
+  roofline      -- the dominant kernel's algorithmic bytes per launch over its
+                   HIP-event-timed average duration, against 8 TB/s HBM;
+  cpu_baseline  -- the CPU oracle (plain single-threaded binary hash join) on the
+                   same input, timed on this host.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def lib_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2308_16370_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(label_kernel):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was taken
+    on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except Exception:
+        return None
+    if t.get("source_hash") != lib_source_hash():
+        return None
+    return t.get("bytes_per_launch", {}).get(label_kernel)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=lambda x: int(x, 0), default=0x5EED0002)
+    ap.add_argument("--scale", type=float, default=1.0, help="shrink rows and key domain together (tests)")
+    ap.add_argument("--profile-steps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (asked for %d GPUs)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2308_16370_amd as sj
+    import workloads as W
+
+    t_gen = time.perf_counter()
+    q = W.config2(seed=args.seed, scale=args.scale)
+    t_gen = time.perf_counter() - t_gen
+    print("# generated %s: %d relations x %d rows in %.1fs" % (q.name, len(q.rels), q.rels[0].nrows, t_gen),
+          file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    rels = [sj.Rel([torch.from_numpy(c).to(dev) for c in r.cols], r.pred) for r in q.rels]
+    opts = dict(bits_per_key=8, k=6, block_bits=512, passes=2, seed=args.seed)
+    ctx = sj.Context(0)
+    plan = sj.Plan(ctx, rels, q.edges, **opts)
+
+    plan.build_filters()
+    plan.sieve()
+    cnt, chk = plan.join()
+    out = torch.empty((max(cnt, 1), len(q.rels)), dtype=torch.int32, device=dev)
+    plan.result(out)
+    torch.cuda.synchronize()
+
+    def step():
+        plan.build_filters()
+        plan.sieve()
+        c = plan.join()
+        plan.result(out)
+        return c
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        c = step()
+        if c != (cnt, chk):
+            raise RuntimeError("result changed between steps: %r vs %r" % (c, (cnt, chk)))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) / args.steps * 1e3
+    value = q.input_tuples / (ms / 1e3)
+    print("# %d steps, %.3f ms/step, count %d" % (args.steps, ms, cnt), file=sys.stderr, flush=True)
+
+    # phase times with torch events (the plan launches on torch's current stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    phases = {"build_filters": 0.0, "sieve": 0.0, "join": 0.0, "result": 0.0}
+    for _ in range(args.profile_steps):
+        ev[0].record()
+        plan.build_filters()
+        ev[1].record()
+        plan.sieve()
+        ev[2].record()
+        plan.join()
+        ev[3].record()
+        plan.result(out)
+        ev[4].record()
+        torch.cuda.synchronize()
+        for i, k in enumerate(phases):
+            phases[k] += ev[i].elapsed_time(ev[i + 1]) / args.profile_steps
+
+    # per-kernel HIP-event timings on the same stream, same workspace
+    pplan = sj.Plan(ctx, rels, q.edges, workspace=plan.workspace, profile=True, **opts)
+    for i in range(args.profile_steps + 1):
+        pplan.build_filters()
+        pplan.sieve()
+        pplan.join()
+        pplan.result(out)
+        if i == 0:
+            pplan.profile(reset=True)
+    prof = pplan.profile()
+    del pplan
+    kernels = sorted(prof, key=lambda e: -e["total_ms"])
+    modelled = [e for e in kernels if e["alg_bytes"] > 0]
+    dom = modelled[0] if modelled else None
+    roofline = None
+    if dom:
+        avg_s = dom["total_ms"] / dom["launches"] / 1e3
+        achieved = dom["alg_bytes"] / avg_s / 1e9
+        traffic = load_traffic(dom["label"])
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom["label"],
+                    "alg_bytes_per_launch": dom["alg_bytes"], "avg_us": round(avg_s * 1e6, 2)}
+
+    cpu = None
+    check = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t = time.perf_counter()
+        _, rcnt, rchk = oracle.hash_join(q)
+        t = time.perf_counter() - t
+        cpu = {"value": q.input_tuples / t, "unit": "tuples/s", "cores": 1, "kind": "oracle",
+               "sample": "the full workload (4 x %d rows), single-threaded binary hash join, %.2f s"
+                         % (q.rels[0].nrows, t)}
+        check = "count and checksum equal the oracle" if (rcnt, rchk) == (cnt, chk) else "MISMATCH"
+        if check == "MISMATCH":
+            print("# oracle mismatch: gpu %r oracle %r" % ((cnt, chk), (rcnt, rchk)), file=sys.stderr)
+
+    res = {
+        "metric": "input tuples/s through sieve+join (4-way chain)",
+        "value": value,
+        "unit": "tuples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "chain4: 4 x %d rows, int32 keys Zipf(1.1) over %d, per-column permutation, "
+                               "blocked Bloom 8 bits/key k=6 512-bit blocks, 2 passes, tuples materialised"
+                               % (q.rels[0].nrows, q.meta["domain"]),
+                   "input_tuples": q.input_tuples, "result_tuples": cnt, "seed": args.seed},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "check": check,
+        "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "kernels": [{"label": e["label"], "avg_us": round(e["total_ms"] / max(1, e["launches"]) * 1e3, 2),
+                     "alg_bytes": e["alg_bytes"]} for e in kernels[:12]],
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

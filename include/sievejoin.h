@@ -89,14 +89,18 @@ typedef struct {
 
 /* Filter and schedule options. A zero field takes the default in brackets. */
 typedef struct {
-    uint32_t bits_per_key; /* [8] filter bits per predicate-eligible row of the relation it is built on */
+    uint32_t bits_per_key; /* [8] filter bits per key inserted into the filter */
     uint32_t k;            /* [6] bits set per key, 1..12 */
     uint32_t block_bits;   /* [512] filter block size: 256, 512 or 1024 bits */
     uint32_t passes;       /* [2] 1: the paper's backward pass only; 2: plus the forward pass */
     uint64_t seed;         /* filter hash seed (0 is a valid seed) */
     int32_t root;          /* -1: relation 0 (the left-most relation) */
-    uint32_t flags;        /* reserved, must be 0 */
+    uint32_t flags;        /* SJ_FLAG_* bits; other bits must be 0 */
 } sj_opts;
+
+/* Record a HIP event pair around every launch group on the context's stream
+ * (costs a few microseconds per group); read with sj_profile_*(). */
+#define SJ_FLAG_PROFILE 1u
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
  * (a hipStream_t; NULL = the null stream). The stream stays caller-owned. */
@@ -108,9 +112,11 @@ const char *sj_last_error(const sj_ctx *ctx);
 
 /* Validate the join graph (Section 2.2: relations with join attributes joined by
  * equalities) and build the execution plan: the root and depth-first spanning
- * tree, the closing edges, the backward/closing/forward filter schedule and the
- * size of every filter (ceil(bits_per_key * eligible rows / block_bits) blocks),
- * survivor list, hash table and scan buffer. Host-only; launches nothing.
+ * tree, the closing edges, the backward/closing/forward filter schedule, and the
+ * workspace for every filter, survivor list, hash table and scan buffer. A filter
+ * gets ceil(bits_per_key * n / block_bits) blocks for the n keys inserted into it
+ * (the sizing of Bloomjoin, Section 2.1: bits per inserted tuple), computed on the
+ * device once n is known. Host-only; launches nothing.
  * *workspace_bytes receives the device workspace the plan needs (worst case: every
  * row survives). `opts` may be NULL (all defaults). */
 sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, const sj_edge *edges,
@@ -168,6 +174,23 @@ sj_status sj_filter_copy(sj_plan_t *plan, int32_t f, uint32_t *dst_dev, uint64_t
  * Waits for the stream. */
 sj_status sj_survivors_copy(sj_plan_t *plan, int32_t rel, uint32_t *dst_dev, uint64_t capacity,
                             uint64_t *n);
+
+/* ---- profiling (plans created with SJ_FLAG_PROFILE) ---- */
+
+/* Wait for the stream and add the elapsed time of every launch group recorded since
+ * the last collect to its label's total. Without SJ_FLAG_PROFILE this does nothing. */
+sj_status sj_profile_collect(sj_plan_t *plan);
+/* Number of distinct launch-group labels seen so far. */
+sj_status sj_profile_count(const sj_plan_t *plan, int32_t *n);
+/* Label i (valid until the plan is destroyed), its total milliseconds and launch
+ * count, and the algorithmic bytes of its last launch (0 where not modelled): for a
+ * sieve step, the join columns (plus the row ids of a survivor-list source and the
+ * predicate column of a full scan) read, the survivors written and each filter it
+ * probes or builds counted once; for "materialize", the result tuples written. */
+sj_status sj_profile_entry(const sj_plan_t *plan, int32_t i, const char **label, double *total_ms,
+                           uint64_t *launches, uint64_t *alg_bytes);
+/* Collect, then zero every total. */
+sj_status sj_profile_reset(sj_plan_t *plan);
 
 #ifdef __cplusplus
 }

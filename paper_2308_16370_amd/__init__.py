@@ -43,7 +43,9 @@ SJ_FILTER_CLOSING = 2
 
 EXPORTED = ["sj_ctx_create", "sj_ctx_set_stream", "sj_ctx_destroy", "sj_last_error", "sj_plan",
             "sj_bind_workspace", "sj_build_filters", "sj_sieve", "sj_join", "sj_result", "sj_plan_destroy",
-            "sj_filter_count", "sj_filter_desc", "sj_filter_copy", "sj_survivors_copy"]
+            "sj_filter_count", "sj_filter_desc", "sj_filter_copy", "sj_survivors_copy", "sj_profile_collect",
+            "sj_profile_count", "sj_profile_entry", "sj_profile_reset"]
+SJ_FLAG_PROFILE = 1
 
 
 class SjError(RuntimeError):
@@ -96,6 +98,10 @@ def lib():
             "sj_filter_desc": [V, i32, P(i32), P(i32), P(i32), P(i32), P(u32)],
             "sj_filter_copy": [V, i32, V, u64],
             "sj_survivors_copy": [V, i32, V, u64, P(u64)],
+            "sj_profile_collect": [V],
+            "sj_profile_count": [V, P(i32)],
+            "sj_profile_entry": [V, i32, P(ctypes.c_char_p), P(ctypes.c_double), P(u64), P(u64)],
+            "sj_profile_reset": [V],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -154,7 +160,7 @@ class Plan:
 
     def __init__(self, ctx: Context, rels: Sequence[Rel], edges: Sequence[Tuple[int, int, int, int]],
                  bits_per_key: int = 0, k: int = 0, block_bits: int = 0, passes: int = 0, seed: int = 0,
-                 root: int = -1, workspace: Optional[torch.Tensor] = None):
+                 root: int = -1, workspace: Optional[torch.Tensor] = None, profile: bool = False):
         self.ctx = ctx
         self.block_bits = block_bits or 512
         self.nrels = len(rels)
@@ -176,7 +182,8 @@ class Plan:
             else:
                 arr[i].pred_col, arr[i].pred_lo, arr[i].pred_hi = (int(x) for x in r.pred)
         earr = (_Edge * max(1, len(edges)))(*[_Edge(*[int(x) for x in e]) for e in edges])
-        opts = _Opts(bits_per_key, k, block_bits, passes, seed & (2**64 - 1), root, 0)
+        opts = _Opts(bits_per_key, k, block_bits, passes, seed & (2**64 - 1), root,
+                     SJ_FLAG_PROFILE if profile else 0)
         wsb = ctypes.c_uint64()
         ctx._check(lib().sj_plan(ctx.handle, arr, len(rels), earr, len(edges), ctypes.byref(opts),
                                  ctypes.byref(self.handle), ctypes.byref(wsb)))
@@ -252,6 +259,22 @@ class Plan:
         if out.numel():
             self._check(lib().sj_survivors_copy(self.handle, rel, ctypes.c_void_p(out.data_ptr()), out.numel(),
                                                 ctypes.byref(n)))
+        return out
+
+    def profile(self, reset: bool = False) -> List[dict]:
+        """Per launch-group event timings (plans made with profile=True)."""
+        self._check(lib().sj_profile_collect(self.handle))
+        n = ctypes.c_int32()
+        self._check(lib().sj_profile_count(self.handle, ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            lab, ms, cnt, by = ctypes.c_char_p(), ctypes.c_double(), ctypes.c_uint64(), ctypes.c_uint64()
+            self._check(lib().sj_profile_entry(self.handle, i, ctypes.byref(lab), ctypes.byref(ms),
+                                               ctypes.byref(cnt), ctypes.byref(by)))
+            out.append(dict(label=lab.value.decode(), total_ms=ms.value, launches=int(cnt.value),
+                            alg_bytes=int(by.value)))
+        if reset:
+            self._check(lib().sj_profile_reset(self.handle))
         return out
 
     def __del__(self):

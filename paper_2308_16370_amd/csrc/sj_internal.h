@@ -54,9 +54,6 @@ struct StepArgs {
     int nprobe;
     int8_t probe_col[kMaxProbe];
     FilterRef probe[kMaxProbe];
-    int nbuild;
-    int8_t build_col[kMaxBuild];
-    FilterRef build[kMaxBuild];
     uint32_t *out_rid;         // nullptr: no survivor list is written
     int32_t *out_col[kMaxJCols];
     uint32_t *out_count;       // device-side survivor count (written when out_rid != nullptr)
@@ -70,16 +67,38 @@ struct StepArgs {
 hipError_t launch_zero(void *p, uint64_t bytes, hipStream_t s);
 hipError_t launch_count_pred(const int32_t *col, uint32_t n, int32_t lo, int32_t hi, uint32_t *out,
                              hipStream_t s);
-struct SizeArgs {
-    int nfilters;
-    const uint32_t *elig[64];      // device-side eligible count, or nullptr to use rows[]
-    uint32_t rows[64];
-    uint32_t *nblocks[64];
-    uint32_t bits_per_key;
-    uint32_t block_bits;
-};
-hipError_t launch_size_filters(const SizeArgs &a, hipStream_t s);
 hipError_t launch_sieve_step(const StepArgs &a, uint32_t max_rows, hipStream_t s);
+
+// Partitioned build of one filter from a key column (full column with an optional
+// predicate, or a survivor-list column with a device-side length).
+constexpr int kBuildBlock = 256;
+constexpr int kBuildTile = kBuildBlock * 64;
+constexpr uint32_t kRegionBytes = 32 * 1024;   // LDS per region workgroup
+constexpr int kRegionThreads = 512;
+struct BuildArgs {
+    const int32_t *keys;
+    const uint32_t *n_dev;     // list source: device-side length; nullptr: use n
+    uint32_t n;
+    uint32_t n_max;            // capacity of the source
+    const int32_t *pred;       // full-column source: predicate column or nullptr
+    int32_t pred_lo, pred_hi;
+    const uint32_t *nkeys_dev; // keys inserted (sizes the filter); nullptr: the source length
+    uint32_t bits_per_key;
+    uint32_t *words;
+    uint32_t *nblocks;         // device-side filter size in blocks (written by the build)
+    uint32_t nblocks_max;
+    uint32_t region_blocks;    // kRegionBytes / (block bytes)
+    uint32_t *hist;            // [regions * tiles] counts, then their exclusive prefix
+    uint64_t *keep;            // [tiles * kBuildTile / 64] bit e: element e is staged
+    uint32_t *stage_block;     // [n_max] staged keys: block index
+    uint32_t *stage_g;         // [n_max] staged keys: second hash word
+    uint32_t *total_dev;       // number of staged keys (zeroed before)
+    Lookback lb;               // scan state (zeroed before)
+    uint32_t seed;
+    int k;
+    int logB;
+};
+hipError_t launch_filter_build(const BuildArgs &a, hipStream_t s);
 
 // ---- join phase (sj_join.hip) ----
 // A relation's sieved rows regrouped by its parent-edge key ("bucket order").
@@ -129,28 +148,29 @@ struct DpArgs {
     Buckets child[kMaxJCols];
     uint64_t *cw;              // [cap + 1]
     uint64_t *cv;              // [cap + 1]
+    uint32_t *blo[kMaxJCols];  // [cap] per child: first entry of the matching child bucket
+    uint32_t *bhi[kMaxJCols];  // [cap] per child: one past its last entry (lo = hi: none)
     uint64_t *tile_sums;       // [2 * tiles(cap)]
     uint64_t *totals;          // [2] result count and checksum, or nullptr
 };
 hipError_t launch_dp(const DpArgs &a, hipStream_t s);
 
-// Materialisation over the join tree.
+// Materialisation over the join tree. Position x is the x-th relation in preorder
+// (position 0 is the root); its entries are the root's survivor list or a bucketed
+// relation's entries in bucket order.
 constexpr int kMatMaxRels = 16;
 struct MatArgs {
     int nrels;
-    int order[kMatMaxRels];        // preorder: order[0] is the root
-    int parent_pos[kMatMaxRels];   // position in order[] of each position's parent
-    int key_col_in_parent[kMatMaxRels]; // join column (list slot) in the parent used to find the bucket
+    int order[kMatMaxRels];        // relation index at each position
+    int parent_pos[kMatMaxRels];
     int is_leaf[kMatMaxRels];
     int nchild[kMatMaxRels];
-    // root list
+    const uint32_t *rid[kMatMaxRels];   // row id of each entry
+    const uint64_t *cw[kMatMaxRels];    // exclusive prefix of entry weights ([n + 1])
+    const uint32_t *blo[kMatMaxRels];   // bucket of position x inside the parent's entry e:
+    const uint32_t *bhi[kMatMaxRels];   //   [blo[x][e], bhi[x][e])
     const uint32_t *root_n;
-    const uint32_t *root_rid;
-    const int32_t *root_col[kMaxJCols];
-    const uint64_t *root_cw;
-    Buckets b[kMatMaxRels];        // by preorder position (b[0] unused)
     uint64_t count;                // total result tuples (host copy)
-    const uint64_t *count_dev;
     int32_t *out;
     int chunk;
 };

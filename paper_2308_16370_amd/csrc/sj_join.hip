@@ -327,15 +327,16 @@ __device__ __forceinline__ void dp_entry(const DpArgs &a, const uint32_t *masks,
     for (int c = 0; c < kMaxJCols; ++c) {
         if (c < a.nchild) {
             const int32_t key = a.col[a.child_col[c]][e];
-            const int64_t d = w ? dir_find(a.child[c].slots, masks[c], key) : -1;
-            if (d < 0) {
-                w = 0;
-                v = 0;
-            } else {
-                const uint32_t lo = a.child[c].dir_begin[d], hi = a.child[c].dir_begin[d + 1];
-                w *= a.child[c].cw[hi] - a.child[c].cw[lo];
-                v *= a.child[c].cv[hi] - a.child[c].cv[lo];
+            const int64_t d = dir_find(a.child[c].slots, masks[c], key);
+            uint32_t lo = 0, hi = 0;
+            if (d >= 0) {
+                lo = a.child[c].dir_begin[d];
+                hi = a.child[c].dir_begin[d + 1];
             }
+            a.blo[c][e] = lo;
+            a.bhi[c][e] = hi;
+            w *= a.child[c].cw[hi] - a.child[c].cw[lo];
+            v *= a.child[c].cv[hi] - a.child[c].cv[lo];
         }
     }
 }
@@ -480,51 +481,40 @@ struct MatState {
     uint32_t hi[N];
 };
 
-// Key that joins position y to its parent, read from the parent's current entry.
+// Bucket of position y below its parent's current entry.
 template <int N>
-__device__ __forceinline__ int32_t parent_key(const MatArgs &a, const MatState<N> &st, int y) {
+__device__ __forceinline__ void find_bucket(const MatArgs &a, MatState<N> &st, int y) {
     const int py = a.parent_pos[y];
     uint32_t ep = st.e[0];
 #pragma unroll
     for (int q = 1; q < N; ++q)
         if (q == py) ep = st.e[q];
-    const int32_t *kc = (py == 0) ? a.root_col[a.key_col_in_parent[y]] : a.b[py].col[a.key_col_in_parent[y]];
-    return kc[ep];
-}
-
-template <int N>
-__device__ __forceinline__ void find_bucket(const MatArgs &a, MatState<N> &st, int y, const uint32_t *masks) {
-    const int32_t key = parent_key<N>(a, st, y);
-    const int64_t d = dir_find(a.b[y].slots, masks[y], key);
-    // a tuple is only decoded along entries of positive weight, so the key exists
-    const uint32_t dd = d < 0 ? 0u : static_cast<uint32_t>(d);
-    st.lo[y] = a.b[y].dir_begin[dd];
-    st.hi[y] = a.b[y].dir_begin[dd + 1];
+    st.lo[y] = a.blo[y][ep];
+    st.hi[y] = a.bhi[y][ep];
 }
 
 template <int N>
 __device__ __forceinline__ uint32_t first_valid(const MatArgs &a, int y, uint32_t e, uint32_t hi) {
     if (a.is_leaf[y]) return e;
-    const uint64_t *cw = a.b[y].cw;
+    const uint64_t *cw = a.cw[y];
     while (e < hi && cw[e + 1] == cw[e]) ++e;
     return e;
 }
 
 template <int N>
-__device__ void mat_decode(const MatArgs &a, MatState<N> &st, uint64_t o, uint32_t root_n, const uint32_t *masks) {
+__device__ void mat_decode(const MatArgs &a, MatState<N> &st, uint32_t r, uint64_t L0) {
     uint64_t L[N];
-    const uint32_t r = upper_bound_u64(a.root_cw, 0, root_n + 1, o) - 1;
     st.e[0] = r;
-    L[0] = o - a.root_cw[r];
+    L[0] = L0;
 #pragma unroll
     for (int p = 0; p < N; ++p) {
         if (p > 0) {
-            // choose the entry of position p inside its bucket from L[p]
+            // the entry of position p inside its bucket that holds local index L[p]
             if (a.is_leaf[p]) {
                 st.e[p] = st.lo[p] + static_cast<uint32_t>(L[p]);
                 L[p] = 0;
             } else {
-                const uint64_t *cw = a.b[p].cw;
+                const uint64_t *cw = a.cw[p];
                 const uint64_t base = cw[st.lo[p]];
                 const uint32_t e = upper_bound_u64(cw, st.lo[p], st.hi[p] + 1, base + L[p]) - 1;
                 st.e[p] = e;
@@ -535,12 +525,12 @@ __device__ void mat_decode(const MatArgs &a, MatState<N> &st, uint64_t o, uint32
 #pragma unroll
         for (int c = N - 1; c > p; --c) {
             if (a.parent_pos[c] == p) {
-                find_bucket<N>(a, st, c, masks);
+                find_bucket<N>(a, st, c);
                 if (a.nchild[p] == 1) {
                     L[c] = L[p];
                 } else {
                     const uint64_t W = a.is_leaf[c] ? static_cast<uint64_t>(st.hi[c] - st.lo[c])
-                                                    : a.b[c].cw[st.hi[c]] - a.b[c].cw[st.lo[c]];
+                                                    : a.cw[c][st.hi[c]] - a.cw[c][st.lo[c]];
                     L[c] = L[p] % W;
                     L[p] /= W;
                 }
@@ -550,7 +540,7 @@ __device__ void mat_decode(const MatArgs &a, MatState<N> &st, uint64_t o, uint32
 }
 
 template <int N>
-__device__ __forceinline__ void mat_advance(const MatArgs &a, MatState<N> &st, uint32_t root_n, const uint32_t *masks) {
+__device__ __forceinline__ void mat_advance(const MatArgs &a, MatState<N> &st, uint32_t root_n) {
     int changed = -1;
 #pragma unroll
     for (int x = N - 1; x >= 1; --x) {
@@ -563,40 +553,65 @@ __device__ __forceinline__ void mat_advance(const MatArgs &a, MatState<N> &st, u
         }
     }
     if (changed < 0) {
+        const uint64_t *cw = a.cw[0];
         uint32_t r = st.e[0] + 1;
-        while (r < root_n && a.root_cw[r + 1] == a.root_cw[r]) ++r;
+        while (r < root_n && cw[r + 1] == cw[r]) ++r;
         st.e[0] = r;
         changed = 0;
     }
 #pragma unroll
     for (int y = 1; y < N; ++y) {
         if (y > changed) {
-            if (a.parent_pos[y] >= changed) find_bucket<N>(a, st, y, masks);
+            if (a.parent_pos[y] >= changed) find_bucket<N>(a, st, y);
             st.e[y] = first_valid<N>(a, y, st.lo[y], st.hi[y]);
         }
     }
 }
 
+// A block owns the outputs [t0, t1) = 256 * chunk consecutive indices; thread t
+// decodes the first index of its chunk and steps the odometer through the rest. The
+// root entries covering the block are located once and their prefix weights staged
+// in LDS, so each thread's root search runs in LDS.
+constexpr int kMatWin = 2048;
+
 template <int N>
 __global__ __launch_bounds__(256) void k_materialize(MatArgs a) {
-    const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const uint64_t o0 = t * static_cast<uint64_t>(a.chunk);
-    if (o0 >= a.count) return;
-    const uint64_t o1 = (o0 + a.chunk < a.count) ? o0 + a.chunk : a.count;
+    __shared__ uint64_t s_cw[kMatWin + 1];
+    __shared__ uint32_t s_r[2];
+    const uint64_t per = 256ull * a.chunk;
+    const uint64_t t0 = static_cast<uint64_t>(blockIdx.x) * per;
+    const uint64_t t1 = (t0 + per < a.count) ? t0 + per : a.count;
     const uint32_t root_n = *a.root_n;
-    uint32_t masks[N];
-    masks[0] = 0;
-#pragma unroll
-    for (int y = 1; y < N; ++y) masks[y] = *a.b[y].slot_mask;
+    const uint64_t *rcw = a.cw[0];
+    if (threadIdx.x < 2) {
+        const uint64_t o = threadIdx.x == 0 ? t0 : t1 - 1;
+        s_r[threadIdx.x] = upper_bound_u64(rcw, 0, root_n + 1, o) - 1;
+    }
+    __syncthreads();
+    const uint32_t r0 = s_r[0], r1 = s_r[1];
+    const bool in_lds = r1 - r0 + 2 <= kMatWin + 1;
+    if (in_lds)
+        for (uint32_t i = threadIdx.x; i < r1 - r0 + 2; i += 256) s_cw[i] = rcw[r0 + i];
+    __syncthreads();
+    const uint64_t o0 = t0 + static_cast<uint64_t>(threadIdx.x) * a.chunk;
+    if (o0 >= t1) return;
+    const uint64_t o1 = (o0 + a.chunk < t1) ? o0 + a.chunk : t1;
+    uint32_t r;
+    uint64_t L0;
+    if (in_lds) {
+        r = r0 + upper_bound_u64(s_cw, 0, r1 - r0 + 2, o0) - 1;
+        L0 = o0 - s_cw[r - r0];
+    } else {
+        r = upper_bound_u64(rcw, r0, r1 + 2, o0) - 1;
+        L0 = o0 - rcw[r];
+    }
     MatState<N> st;
-    mat_decode<N>(a, st, o0, root_n, masks);
+    mat_decode<N>(a, st, r, L0);
     for (uint64_t o = o0;;) {
         int32_t tup[N];
 #pragma unroll
-        for (int q = 0; q < N; ++q) tup[q] = 0;
-#pragma unroll
         for (int x = 0; x < N; ++x) {
-            const int32_t rid = static_cast<int32_t>(x == 0 ? a.root_rid[st.e[0]] : a.b[x].rid[st.e[x]]);
+            const int32_t rid = static_cast<int32_t>(a.rid[x][st.e[x]]);
 #pragma unroll
             for (int q = 0; q < N; ++q)
                 if (a.order[x] == q) tup[q] = rid;
@@ -611,19 +626,22 @@ __global__ __launch_bounds__(256) void k_materialize(MatArgs a) {
             for (int q = 0; q < N; ++q) dst[q] = tup[q];
         }
         if (++o >= o1) break;
-        mat_advance<N>(a, st, root_n, masks);
+        mat_advance<N>(a, st, root_n);
     }
 }
 
-hipError_t launch_materialize(const MatArgs &a, hipStream_t s) {
-    if (a.count == 0) return hipSuccess;
-    const uint64_t threads = (a.count + a.chunk - 1) / a.chunk;
-    const uint64_t blocks64 = (threads + 255) / 256;
+hipError_t launch_materialize(const MatArgs &a0, hipStream_t s) {
+    if (a0.count == 0) return hipSuccess;
+    MatArgs a = a0;
+    a.chunk = 16;
+    const uint64_t per_block = 256ull * a.chunk;
+    const uint64_t blocks64 = (a.count + per_block - 1) / per_block;
     if (blocks64 > 0x7fffffffull) return hipErrorInvalidValue;
     const dim3 g(static_cast<uint32_t>(blocks64));
+    const size_t lds = 0;
     switch (a.nrels) {
 #define SJ_MAT_CASE(NN) \
-    case NN: hipLaunchKernelGGL(k_materialize<NN>, g, dim3(256), 0, s, a); break;
+    case NN: hipLaunchKernelGGL(k_materialize<NN>, g, dim3(256), lds, s, a); break;
         SJ_MAT_CASE(1) SJ_MAT_CASE(2) SJ_MAT_CASE(3) SJ_MAT_CASE(4) SJ_MAT_CASE(5) SJ_MAT_CASE(6) SJ_MAT_CASE(7)
         SJ_MAT_CASE(8) SJ_MAT_CASE(9) SJ_MAT_CASE(10) SJ_MAT_CASE(11) SJ_MAT_CASE(12) SJ_MAT_CASE(13)
         SJ_MAT_CASE(14) SJ_MAT_CASE(15) SJ_MAT_CASE(16)

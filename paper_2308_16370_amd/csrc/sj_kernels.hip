@@ -1,6 +1,6 @@
-// Pruning-phase kernels: workspace clearing, predicate counts, filter sizing and
-// the fused sieve step (probe incoming filters, build outgoing filters, write the
-// ordered survivor list).
+// Pruning-phase kernels: workspace clearing, predicate counts, filter sizing, the
+// sieve step (probe the incoming filters, write the ordered survivor list) and the
+// partitioned filter build.
 #include <hip/hip_runtime.h>
 
 #include "sj_device.h"
@@ -52,44 +52,41 @@ hipError_t launch_count_pred(const int32_t *col, uint32_t n, int32_t lo, int32_t
     return hipGetLastError();
 }
 
-// ---- filter sizes: nblocks = max(1, ceil(bits_per_key * eligible / B)) --------------
-__global__ void k_size_filters(SizeArgs a) {
-    const int f = threadIdx.x;
-    if (f >= a.nfilters) return;
-    const uint64_t n = a.elig[f] ? *a.elig[f] : a.rows[f];
-    uint64_t nb = (n * a.bits_per_key + a.block_bits - 1) / a.block_bits;
-    if (nb == 0) nb = 1;
-    *a.nblocks[f] = static_cast<uint32_t>(nb);
-}
-
-hipError_t launch_size_filters(const SizeArgs &a, hipStream_t s) {
-    if (a.nfilters == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_size_filters, dim3(1), dim3(64), 0, s, a);
-    return hipGetLastError();
-}
-
-// ---- the fused sieve step ----------------------------------------------------------
+// ---- the sieve step ------------------------------------------------------------------
 // Persistent blocks take tiles of kSieveTile consecutive rows in order. Thread t of a
-// tile owns rows [t * kSieveItems, (t + 1) * kSieveItems) of it, so a thread's
-// survivors are contiguous in row order and one block-wide exclusive scan of the
-// per-thread counts plus the tile's look-back prefix places every survivor.
-template <int NCOL>
+// tile owns rows [t * kSieveItems, (t + 1) * kSieveItems) of it, so its survivors are
+// contiguous in row order; one block-wide exclusive scan of the per-thread counts plus
+// the tile's look-back prefix places every survivor.
+//
+// A probe touches one filter block: the k words of all items of a batch are loaded
+// before any is tested, so a thread keeps many independent loads in flight.
+// Zipf-skewed columns repeat a few keys very often: each block keeps a direct-mapped
+// LDS cache key -> contains(key) per probed filter (the first kMaxCached of them);
+// the filter is read-only during the scan, so a cached answer is exact.
+constexpr int kMaxCached = 4;
+constexpr int kCacheLog = 10;
+constexpr uint32_t kCacheValid = 0x80000000u;
+constexpr int kProbeBatch = 4;
+
+__device__ __forceinline__ uint32_t cache_slot(int32_t key) {
+    return (static_cast<uint32_t>(key) * 0x9E3779B1u) >> (32 - kCacheLog);
+}
+
+template <int NCOL, int KMAX>
 __global__ __launch_bounds__(kSieveBlock) void k_sieve_step(StepArgs a) {
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_base;
     __shared__ uint32_t s_wave[kSieveBlock / 64];
+    __shared__ uint64_t s_cache[kMaxCached][1 << kCacheLog];
+    for (int i = threadIdx.x; i < kMaxCached * (1 << kCacheLog); i += kSieveBlock) (&s_cache[0][0])[i] = 0;
+    __syncthreads();
 
     const bool list = a.src_rid != nullptr;
     const uint32_t n = list ? *a.src_count : a.src_rows;
     const uint32_t ntiles = (n + kSieveTile - 1) / kSieveTile;
     const int tid = threadIdx.x;
-
-    uint32_t pnb[kMaxProbe], bnb[kMaxBuild];
-#pragma unroll
-    for (int p = 0; p < kMaxProbe; ++p) pnb[p] = (p < a.nprobe) ? *a.probe[p].nblocks : 0u;
-#pragma unroll
-    for (int b = 0; b < kMaxBuild; ++b) bnb[b] = (b < a.nbuild) ? *a.build[b].nblocks : 0u;
     const uint32_t wpb_shift = static_cast<uint32_t>(a.logB) - 5u;   // words per block = 1 << wpb_shift
+    const uint32_t sh = 32u - static_cast<uint32_t>(a.logB);
 
     while (true) {
         if (tid == 0) s_tile = atomicAdd(a.lb.counter, 1u);
@@ -100,7 +97,7 @@ __global__ __launch_bounds__(kSieveBlock) void k_sieve_step(StepArgs a) {
 
         int32_t v[NCOL][kSieveItems];
         uint32_t rid[kSieveItems];
-        bool full = row0 + kSieveItems <= n;
+        const bool full = row0 + kSieveItems <= n;
         if (full) {
 #pragma unroll
             for (int c = 0; c < NCOL; ++c) {
@@ -140,31 +137,73 @@ __global__ __launch_bounds__(kSieveBlock) void k_sieve_step(StepArgs a) {
                 const int32_t pv = a.pred[r];
                 ok = pv >= a.pred_lo && pv < a.pred_hi;
             }
+            flags |= (ok ? 1u : 0u) << i;
+        }
+
 #pragma unroll
-            for (int p = 0; p < kMaxProbe; ++p) {
-                if (p < a.nprobe && ok) {
-                    int32_t key = v[0][i];
+        for (int p = 0; p < kMaxProbe; ++p) {
+            if (p < a.nprobe) {
+                const uint32_t nb = *a.probe[p].nblocks;
+                const uint32_t *words = a.probe[p].words;
 #pragma unroll
-                    for (int c = 1; c < NCOL; ++c)
-                        if (a.probe_col[p] == c) key = v[c][i];
-                    const BfKey h = bf_hash(key, a.seed, pnb[p]);
-                    ok = bf_test(a.probe[p].words + (static_cast<uint64_t>(h.block) << wpb_shift), h.g, a.k, a.logB);
-                }
-            }
-            if (ok) {
+                for (int i0 = 0; i0 < kSieveItems; i0 += kProbeBatch) {
+                    uint32_t blk[kProbeBatch], g[kProbeBatch], slot[kProbeBatch];
+                    int32_t key[kProbeBatch];
+                    uint32_t need = 0;
 #pragma unroll
-                for (int b = 0; b < kMaxBuild; ++b) {
-                    if (b < a.nbuild) {
-                        int32_t key = v[0][i];
+                    for (int ii = 0; ii < kProbeBatch; ++ii) {
+                        const int i = i0 + ii;
+                        key[ii] = v[0][i];
 #pragma unroll
                         for (int c = 1; c < NCOL; ++c)
-                            if (a.build_col[b] == c) key = v[c][i];
-                        const BfKey h = bf_hash(key, a.seed, bnb[b]);
-                        bf_set(a.build[b].words + (static_cast<uint64_t>(h.block) << wpb_shift), h.g, a.k, a.logB);
+                            if (a.probe_col[p] == c) key[ii] = v[c][i];
+                        slot[ii] = cache_slot(key[ii]);
+                        blk[ii] = 0;
+                        g[ii] = 0;
+                        if (flags & (1u << i)) {
+                            bool hit = false;
+                            if (p < kMaxCached) {
+                                const uint64_t e = s_cache[p < kMaxCached ? p : 0][slot[ii]];
+                                if (static_cast<uint32_t>(e >> 32) == static_cast<uint32_t>(key[ii]) &&
+                                    (static_cast<uint32_t>(e) & kCacheValid)) {
+                                    hit = true;
+                                    if (!(e & 1u)) flags &= ~(1u << i);
+                                }
+                            }
+                            if (!hit) {
+                                const BfKey h = bf_hash(key[ii], a.seed, nb);
+                                blk[ii] = h.block;
+                                g[ii] = h.g;
+                                need |= 1u << ii;
+                            }
+                        }
+                    }
+                    uint32_t w[kProbeBatch][KMAX];
+#pragma unroll
+                    for (int ii = 0; ii < kProbeBatch; ++ii) {
+                        if (need & (1u << ii)) {
+                            const uint32_t *b = words + (static_cast<uint64_t>(blk[ii]) << wpb_shift);
+#pragma unroll
+                            for (int j = 0; j < KMAX; ++j)
+                                if (j < a.k) w[ii][j] = b[((g[ii] * bf_mult(j)) >> sh) >> 5];
+                        }
+                    }
+#pragma unroll
+                    for (int ii = 0; ii < kProbeBatch; ++ii) {
+                        if (need & (1u << ii)) {
+                            uint32_t ok = 1u;
+#pragma unroll
+                            for (int j = 0; j < KMAX; ++j)
+                                if (j < a.k) ok &= w[ii][j] >> (((g[ii] * bf_mult(j)) >> sh) & 31u);
+                            ok &= 1u;
+                            if (!ok) flags &= ~(1u << (i0 + ii));
+                            if (p < kMaxCached)
+                                s_cache[p < kMaxCached ? p : 0][slot[ii]] =
+                                    (static_cast<uint64_t>(static_cast<uint32_t>(key[ii])) << 32) | kCacheValid | ok;
+                        }
                     }
                 }
             }
-            flags |= (ok ? 1u : 0u) << i;
         }
 
         if (a.out_rid) {
@@ -189,21 +228,223 @@ __global__ __launch_bounds__(kSieveBlock) void k_sieve_step(StepArgs a) {
     }
 }
 
-hipError_t launch_sieve_step(const StepArgs &a, uint32_t max_rows, hipStream_t s) {
-    if (max_rows == 0) return hipSuccess;
-    uint32_t tiles = (max_rows + kSieveTile - 1) / kSieveTile;
-    uint32_t blocks = tiles < kPersistentBlocks ? tiles : kPersistentBlocks;
+template <int KMAX>
+static hipError_t launch_sieve_k(const StepArgs &a, dim3 g, hipStream_t s) {
     switch (a.ncol) {
-        case 1: hipLaunchKernelGGL(k_sieve_step<1>, dim3(blocks), dim3(kSieveBlock), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(k_sieve_step<2>, dim3(blocks), dim3(kSieveBlock), 0, s, a); break;
-        case 3: hipLaunchKernelGGL(k_sieve_step<3>, dim3(blocks), dim3(kSieveBlock), 0, s, a); break;
-        case 4: hipLaunchKernelGGL(k_sieve_step<4>, dim3(blocks), dim3(kSieveBlock), 0, s, a); break;
-        case 5: hipLaunchKernelGGL(k_sieve_step<5>, dim3(blocks), dim3(kSieveBlock), 0, s, a); break;
-        case 6: hipLaunchKernelGGL(k_sieve_step<6>, dim3(blocks), dim3(kSieveBlock), 0, s, a); break;
-        case 7: hipLaunchKernelGGL(k_sieve_step<7>, dim3(blocks), dim3(kSieveBlock), 0, s, a); break;
-        case 8: hipLaunchKernelGGL(k_sieve_step<8>, dim3(blocks), dim3(kSieveBlock), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_sieve_step<1, KMAX>), g, dim3(kSieveBlock), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_sieve_step<2, KMAX>), g, dim3(kSieveBlock), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_sieve_step<3, KMAX>), g, dim3(kSieveBlock), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_sieve_step<4, KMAX>), g, dim3(kSieveBlock), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_sieve_step<5, KMAX>), g, dim3(kSieveBlock), 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_sieve_step<6, KMAX>), g, dim3(kSieveBlock), 0, s, a); break;
+        case 7: hipLaunchKernelGGL((k_sieve_step<7, KMAX>), g, dim3(kSieveBlock), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((k_sieve_step<8, KMAX>), g, dim3(kSieveBlock), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_sieve_step(const StepArgs &a, uint32_t max_rows, hipStream_t s) {
+    if (max_rows == 0) return hipSuccess;
+    // persistent blocks: as many as fit at once (the LDS caches allow 4 blocks per CU)
+    constexpr uint32_t kSieveGrid = 256 * 4;
+    const uint32_t tiles = (max_rows + kSieveTile - 1) / kSieveTile;
+    const dim3 g(tiles < kSieveGrid ? tiles : kSieveGrid);
+    return a.k <= 8 ? launch_sieve_k<8>(a, g, s) : launch_sieve_k<kMaxK>(a, g, s);
+}
+
+// ---- partitioned filter build ----------------------------------------------------------
+// Global atomics serialise at the device's atomic units (about 2.7e10 per second on
+// MI355X whatever the footprint), so a filter is built by region: a region is a run of
+// consecutive blocks small enough for one workgroup's LDS. (1) every tile counts its
+// keys per region; (2) an exclusive scan over (region, tile) gives each tile its slice
+// of every region's bucket; (3) each key's block and second hash word are scattered
+// into its region's bucket; (4) one workgroup per region sets the bits of its bucket
+// with LDS atomics and writes the region out with plain coalesced stores, which also
+// clears the bits no key sets.
+
+__device__ __forceinline__ bool bfb_take(const BuildArgs &a, uint32_t e, int32_t &key) {
+    if (a.pred) {
+        const int32_t pv = a.pred[e];
+        if (pv < a.pred_lo || pv >= a.pred_hi) return false;
+    }
+    key = a.keys[e];
+    return true;
+}
+
+struct BfbShape {
+    uint32_t n, nb, nreg, ntiles;
+};
+
+__device__ __forceinline__ BfbShape bfb_shape(const BuildArgs &a) {
+    BfbShape s;
+    s.n = a.n_dev ? *a.n_dev : a.n;
+    const uint64_t nkeys = a.nkeys_dev ? *a.nkeys_dev : s.n;
+    // the filter is sized for the keys it receives: ceil(bits_per_key * nkeys / B) blocks
+    const uint64_t B = 1ull << a.logB;
+    uint64_t nb = (nkeys * a.bits_per_key + B - 1) / B;
+    s.nb = nb ? static_cast<uint32_t>(nb) : 1u;
+    s.nreg = (s.nb + a.region_blocks - 1) / a.region_blocks;
+    s.ntiles = (s.n + kBuildTile - 1) / kBuildTile;
+    return s;
+}
+
+// (1) Per-tile region counts. A key repeated inside a tile is staged once: a
+// direct-mapped LDS cache of the tile's keys drops repeats (Zipf heavy hitters would
+// otherwise pile millions of identical entries into one region). Which copies are kept
+// is recorded in a bitmap (bit e: element e is staged) that the scatter pass follows,
+// so both passes agree whatever the order the cache updates landed in.
+constexpr int kDedupLog = 11;
+
+__global__ __launch_bounds__(kBuildBlock) void k_bfb_hist(BuildArgs a) {
+    extern __shared__ uint32_t s_hist[];   // [nreg]
+    __shared__ uint32_t s_seen[1 << kDedupLog];
+    __shared__ uint32_t s_seen_ok[1 << kDedupLog];
+    const BfbShape sh = bfb_shape(a);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.nblocks = sh.nb;
+    for (uint32_t tile = blockIdx.x; tile < sh.ntiles; tile += gridDim.x) {
+        for (uint32_t r = threadIdx.x; r < sh.nreg; r += kBuildBlock) s_hist[r] = 0;
+        for (uint32_t i = threadIdx.x; i < (1u << kDedupLog); i += kBuildBlock) s_seen_ok[i] = 0;
+        __syncthreads();
+        const uint32_t t0 = tile * kBuildTile;
+        for (uint32_t j = 0; j < kBuildTile; j += kBuildBlock) {
+            const uint32_t e = t0 + j + threadIdx.x;
+            bool keep = false;
+            int32_t key = 0;
+            if (e < sh.n && bfb_take(a, e, key)) {
+                const uint32_t slot = (static_cast<uint32_t>(key) * 0x9E3779B1u) >> (32 - kDedupLog);
+                keep = !(s_seen_ok[slot] && s_seen[slot] == static_cast<uint32_t>(key));
+                if (keep) {
+                    s_seen[slot] = static_cast<uint32_t>(key);
+                    s_seen_ok[slot] = 1;
+                    const BfKey h = bf_hash(key, a.seed, sh.nb);
+                    atomicAdd(&s_hist[h.block / a.region_blocks], 1u);
+                }
+            }
+            const uint64_t m = __ballot(keep);
+            if (lane_id() == 0) a.keep[(t0 + j + threadIdx.x) >> 6] = m;
+        }
+        __syncthreads();
+        for (uint32_t r = threadIdx.x; r < sh.nreg; r += kBuildBlock) a.hist[r * sh.ntiles + tile] = s_hist[r];
+        __syncthreads();
+    }
+}
+
+// Exclusive scan in place of hist[0 .. nreg * ntiles) (decoupled look-back); the
+// grand total (the number of staged keys) goes to *total_dev.
+__global__ __launch_bounds__(kScanBlock) void k_bfb_scan(BuildArgs a) {
+    __shared__ uint32_t s_tile, s_base;
+    __shared__ uint32_t s_wave[kScanBlock / 64];
+    const BfbShape sh = bfb_shape(a);
+    const uint32_t len = sh.nreg * sh.ntiles;
+    const uint32_t ntiles = (len + kScanTile - 1) / kScanTile;
+    while (true) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(a.lb.counter, 1u);
+        __syncthreads();
+        const uint32_t tile = s_tile;
+        if (tile >= ntiles) break;
+        const uint32_t base = tile * kScanTile + threadIdx.x * kScanItems;
+        uint32_t x[kScanItems];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            x[i] = (base + i < len) ? a.hist[base + i] : 0u;
+            sum += x[i];
+        }
+        uint32_t tot;
+        uint32_t off = block_excl_scan<kScanBlock>(sum, s_wave, tot);
+        if (threadIdx.x == 0) s_base = lookback32(a.lb.status, tile, tot);
+        __syncthreads();
+        if (tile == ntiles - 1 && threadIdx.x == 0) *a.total_dev = s_base + tot;
+        off += s_base;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            if (base + i < len) a.hist[base + i] = off;
+            off += x[i];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBuildBlock) void k_bfb_scatter(BuildArgs a) {
+    extern __shared__ uint32_t s_off[];    // [nreg]
+    const BfbShape sh = bfb_shape(a);
+    for (uint32_t tile = blockIdx.x; tile < sh.ntiles; tile += gridDim.x) {
+        for (uint32_t r = threadIdx.x; r < sh.nreg; r += kBuildBlock) s_off[r] = a.hist[r * sh.ntiles + tile];
+        __syncthreads();
+        const uint32_t t0 = tile * kBuildTile;
+        for (uint32_t j = 0; j < kBuildTile; j += kBuildBlock) {
+            const uint32_t e = t0 + j + threadIdx.x;
+            const uint64_t m = a.keep[e >> 6];
+            if (e < sh.n && ((m >> (e & 63)) & 1ull)) {
+                const BfKey h = bf_hash(a.keys[e], a.seed, sh.nb);
+                const uint32_t pos = atomicAdd(&s_off[h.block / a.region_blocks], 1u);
+                a.stage_block[pos] = h.block;
+                a.stage_g[pos] = h.g;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kRegionThreads) void k_bfb_region(BuildArgs a) {
+    extern __shared__ uint32_t s_words[];  // [region_blocks * words per block]
+    const BfbShape sh = bfb_shape(a);
+    const uint32_t wpb_shift = static_cast<uint32_t>(a.logB) - 5u;
+    const uint32_t hs = 32u - static_cast<uint32_t>(a.logB);
+    const uint32_t total = *a.total_dev;
+    constexpr int U = 4;
+    for (uint32_t r = blockIdx.x; r < sh.nreg; r += gridDim.x) {
+        const uint32_t b0 = r * a.region_blocks;
+        const uint32_t nbr = min(a.region_blocks, sh.nb - b0);
+        const uint32_t nw = nbr << wpb_shift;
+        for (uint32_t i = threadIdx.x; i < nw; i += kRegionThreads) s_words[i] = 0;
+        __syncthreads();
+        const uint32_t beg = sh.ntiles ? a.hist[r * sh.ntiles] : 0u;
+        const uint32_t end = (r + 1 < sh.nreg && sh.ntiles) ? a.hist[(r + 1) * sh.ntiles] : total;
+        for (uint32_t e0 = beg + threadIdx.x; e0 < end; e0 += kRegionThreads * U) {
+            uint32_t bb[U], gg[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t e = e0 + u * kRegionThreads;
+                bb[u] = e < end ? a.stage_block[e] - b0 : 0xFFFFFFFFu;
+                gg[u] = e < end ? a.stage_g[e] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (bb[u] != 0xFFFFFFFFu) {
+                    uint32_t *w = s_words + (bb[u] << wpb_shift);
+#pragma unroll
+                    for (int j = 0; j < kMaxK; ++j) {
+                        if (j < a.k) {
+                            const uint32_t p = (gg[u] * bf_mult(j)) >> hs;
+                            const uint32_t bit = 1u << (p & 31u);
+                            if (!(w[p >> 5] & bit)) atomicOr(w + (p >> 5), bit);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        uint32_t *dst = a.words + (static_cast<uint64_t>(b0) << wpb_shift);
+        for (uint32_t i = threadIdx.x; i < nw; i += kRegionThreads) dst[i] = s_words[i];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_filter_build(const BuildArgs &a, hipStream_t s) {
+    const uint32_t ntiles_max = (a.n_max + kBuildTile - 1) / kBuildTile;
+    const uint32_t nreg_max = (a.nblocks_max + a.region_blocks - 1) / a.region_blocks;
+    const size_t lds_hist = 4ull * (nreg_max ? nreg_max : 1);
+    const size_t lds_region = 4ull * a.region_blocks * (1u << (a.logB - 5));
+    const uint32_t tgrid = ntiles_max == 0 ? 1 : (ntiles_max < 2048 ? ntiles_max : 2048);
+    hipLaunchKernelGGL(k_bfb_hist, dim3(tgrid), dim3(kBuildBlock), lds_hist, s, a);
+    const uint32_t scan_tiles = (nreg_max * ntiles_max + kScanTile - 1) / kScanTile;
+    const uint32_t sgrid = scan_tiles == 0 ? 1 : (scan_tiles < kPersistentBlocks ? scan_tiles : kPersistentBlocks);
+    hipLaunchKernelGGL(k_bfb_scan, dim3(sgrid), dim3(kScanBlock), 0, s, a);
+    hipLaunchKernelGGL(k_bfb_scatter, dim3(tgrid), dim3(kBuildBlock), lds_hist, s, a);
+    const uint32_t rgrid = nreg_max == 0 ? 1 : (nreg_max < 2048 ? nreg_max : 2048);
+    hipLaunchKernelGGL(k_bfb_region, dim3(rgrid), dim3(kRegionThreads), lds_region, s, a);
     return hipGetLastError();
 }
 

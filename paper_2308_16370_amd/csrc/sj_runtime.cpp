@@ -60,6 +60,7 @@ struct StepSpec {
     int out = -1;              // list buffer written, -1: none
     uint64_t off_status = 0, off_counter = 0, off_count = 0;
     uint32_t max_rows = 0;
+    std::vector<uint64_t> off_bstatus, off_bcounter, off_btotal;   // per build
 };
 
 struct Region {
@@ -101,6 +102,8 @@ struct sj_plan_s {
     char *ws = nullptr;
     Region zero[3];                          // build_filters, sieve, join
     uint64_t off_elig = 0, off_nblocks = 0, off_totals = 0;
+    uint32_t region_blocks = 0;
+    uint64_t off_bhist = 0, off_stage[2] = {0, 0}, off_keep = 0;
     std::vector<uint64_t> off_list[2];       // per relation: list buffer base
     // join phase
     struct JoinRel {
@@ -112,10 +115,36 @@ struct sj_plan_s {
     std::vector<JoinRel> jr;
     uint64_t off_sort_keys[2] = {0, 0}, off_sort_vals[2] = {0, 0}, off_hist = 0, off_ctl = 0, off_tile_sums = 0;
     uint64_t off_root_cw = 0, off_root_cv = 0;
+    std::vector<std::vector<uint64_t>> off_blo, off_bhi;   // [relation][child]
     uint32_t sort_cap = 0;
     int state = kPlanned;
     uint64_t count = 0, checksum = 0;
+    // event profiling (SJ_FLAG_PROFILE): one event pair per launch group
+    bool profile = false;
+    struct ProfRec {
+        int label;
+        hipEvent_t a, b;
+        int step;              // sieve step index, -1 otherwise
+    };
+    std::vector<ProfRec> prof_pending;
+    std::vector<hipEvent_t> prof_free;
+    struct ProfAcc {
+        std::string label;
+        double ms = 0;
+        uint64_t n = 0;
+        uint64_t bytes = 0;    // algorithmic bytes of the last launch, 0 if not modelled
+    };
+    std::vector<ProfAcc> prof_acc;
+    ~sj_plan_s();
 };
+
+sj_plan_s::~sj_plan_s() {
+    for (auto &r : prof_pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : prof_free) (void)hipEventDestroy(e);
+}
 
 // ---------------------------------------------------------------- errors
 
@@ -353,22 +382,39 @@ static void build_layout(sj_plan_t *p) {
     Layout L;
     const int n = p->n;
     // phase zero regions first, each contiguous: [build_filters][sieve][join]
+    uint32_t max_build_rows = 0;
+    uint64_t max_hist = 1;
     for (int ph = 0; ph < 2; ++ph) {
         p->zero[ph].begin = L.top;
         if (ph == 0) p->off_elig = L.take(sizeof(uint32_t) * SJ_MAX_RELS);
-        for (auto &f : p->filters) {
-            const int fph = (f.kind == SJ_FILTER_BACKWARD) ? 0 : 1;
-            if (fph == ph) f.off = L.take(f.max_words * 4);
-        }
         for (auto &s : p->steps) {
             if (s.phase != ph) continue;
             s.max_rows = p->rels[s.rel].nrows;
             s.off_status = L.take(8ull * std::max<uint32_t>(1, tiles_of(s.max_rows, kSieveTile)));
             s.off_counter = L.take(4);
             s.off_count = L.take(4);
+            s.off_bstatus.clear();
+            s.off_bcounter.clear();
+            s.off_btotal.clear();
+            for (auto &b : s.builds) {
+                const Filter &f = p->filters[b.second];
+                const uint64_t nbm = f.max_words / (p->opts.block_bits / 32);
+                const uint64_t nreg = (nbm + p->region_blocks - 1) / p->region_blocks;
+                const uint64_t hl = nreg * tiles_of(s.max_rows, kBuildTile);
+                max_hist = std::max<uint64_t>(max_hist, hl);
+                max_build_rows = std::max(max_build_rows, s.max_rows);
+                s.off_bstatus.push_back(L.take(8ull * std::max<uint64_t>(1, (hl + kScanTile - 1) / kScanTile)));
+                s.off_bcounter.push_back(L.take(4));
+                s.off_btotal.push_back(L.take(4));
+            }
         }
         p->zero[ph].end = L.top;
     }
+    for (auto &f : p->filters) f.off = L.take(f.max_words * 4);
+    p->off_bhist = L.take(4 * max_hist);
+    p->off_stage[0] = L.take(4ull * std::max<uint32_t>(1, max_build_rows));
+    p->off_stage[1] = L.take(4ull * std::max<uint32_t>(1, max_build_rows));
+    p->off_keep = L.take(8ull * (tiles_of(std::max<uint32_t>(1, max_build_rows), kBuildTile) * (kBuildTile / 64)));
     p->zero[2].begin = L.top;
     p->off_totals = L.take(16);
     p->jr.assign(n, {});
@@ -424,6 +470,14 @@ static void build_layout(sj_plan_t *p) {
     const uint64_t rc = p->rels[p->root].nrows;
     p->off_root_cw = L.take(8 * (rc + 1));
     p->off_root_cv = L.take(8 * (rc + 1));
+    p->off_blo.assign(n, {});
+    p->off_bhi.assign(n, {});
+    for (int j = 0; j < n; ++j) {
+        for (size_t c = 0; c < p->children[j].size(); ++c) {
+            p->off_blo[j].push_back(L.take(4ull * p->rels[j].nrows));
+            p->off_bhi[j].push_back(L.take(4ull * p->rels[j].nrows));
+        }
+    }
     p->ws_bytes = L.top;
 }
 
@@ -448,7 +502,7 @@ extern "C" sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, con
         return fail(ctx, SJ_ERR_INVALID, "block_bits must be 256, 512 or 1024");
     if (o.passes != 1 && o.passes != 2) return fail(ctx, SJ_ERR_INVALID, "passes must be 1 or 2");
     if (o.root >= nrels) return fail(ctx, SJ_ERR_INVALID, "root out of range");
-    if (o.flags != 0) return fail(ctx, SJ_ERR_INVALID, "flags must be 0");
+    if (o.flags & ~static_cast<uint32_t>(SJ_FLAG_PROFILE)) return fail(ctx, SJ_ERR_INVALID, "unknown flags");
 
     sj_plan_t *p = new (std::nothrow) sj_plan_t;
     if (!p) return fail(ctx, SJ_ERR_INVALID, "out of host memory");
@@ -457,6 +511,7 @@ extern "C" sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, con
     p->opts = o;
     p->logB = (o.block_bits == 256) ? 8 : (o.block_bits == 512 ? 9 : 10);
     p->root = o.root;
+    p->profile = (o.flags & SJ_FLAG_PROFILE) != 0;
     {   // 32-bit filter seed: the low word of SplitMix64's output function of the seed
         uint64_t z = o.seed;
         z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
@@ -534,6 +589,14 @@ extern "C" sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, con
         delete p;
         return st;
     }
+    p->region_blocks = kRegionBytes / (o.block_bits / 8);
+    for (auto &f : p->filters) {
+        const uint64_t nbm = f.max_words / (o.block_bits / 32);
+        if ((nbm + p->region_blocks - 1) / p->region_blocks > 16384) {
+            delete p;
+            return fail(ctx, SJ_ERR_UNSUPPORTED, "a filter of more than %u blocks", 16384u * p->region_blocks);
+        }
+    }
     build_layout(p);
     *workspace_bytes = p->ws_bytes;
     *out = p;
@@ -569,6 +632,49 @@ static int32_t *list_col(sj_plan_t *p, int rel, int buf, int jc) {
     return at<int32_t>(p, p->off_list[buf][rel] + 4ull * p->rels[rel].nrows * (1 + jc));
 }
 
+// ---------------------------------------------------------------- profiling
+
+static int prof_label(sj_plan_t *p, const std::string &label) {
+    for (size_t i = 0; i < p->prof_acc.size(); ++i)
+        if (p->prof_acc[i].label == label) return static_cast<int>(i);
+    p->prof_acc.push_back({label, 0.0, 0, 0});
+    return static_cast<int>(p->prof_acc.size()) - 1;
+}
+
+static hipEvent_t prof_event(sj_plan_t *p) {
+    if (!p->prof_free.empty()) {
+        hipEvent_t e = p->prof_free.back();
+        p->prof_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records an event before the launches of its scope and one after them.
+struct ProfScope {
+    sj_plan_t *p;
+    long idx = -1;
+    ProfScope(sj_plan_t *pp, const std::string &label, int step = -1) : p(pp) {
+        if (!p->profile) return;
+        hipEvent_t a = prof_event(p), b = prof_event(p);
+        if (!a || !b) return;
+        (void)hipEventRecord(a, p->ctx->stream);
+        p->prof_pending.push_back({prof_label(p, label), a, b, step});
+        idx = static_cast<long>(p->prof_pending.size()) - 1;
+    }
+    ~ProfScope() {
+        if (idx >= 0) (void)hipEventRecord(p->prof_pending[idx].b, p->ctx->stream);
+    }
+};
+
+static const char *rel_name(int r) {
+    static char buf[SJ_MAX_RELS][8];
+    snprintf(buf[r], sizeof buf[r], "R%d", r);
+    return buf[r];
+}
+
 static sj_status run_steps(sj_plan_t *p, int phase) {
     hipStream_t s = p->ctx->stream;
     for (auto &st : p->steps) {
@@ -598,13 +704,6 @@ static sj_status run_steps(sj_plan_t *p, int phase) {
             a.probe[i].words = at<uint32_t>(p, p->filters[f].off);
             a.probe[i].nblocks = at<uint32_t>(p, p->off_nblocks) + f;
         }
-        a.nbuild = static_cast<int>(st.builds.size());
-        for (int i = 0; i < a.nbuild; ++i) {
-            a.build_col[i] = static_cast<int8_t>(st.builds[i].first);
-            const int f = st.builds[i].second;
-            a.build[i].words = at<uint32_t>(p, p->filters[f].off);
-            a.build[i].nblocks = at<uint32_t>(p, p->off_nblocks) + f;
-        }
         if (st.out >= 0) {
             a.out_rid = list_rid(p, st.rel, st.out);
             for (int c = 0; c < a.ncol; ++c) a.out_col[c] = list_col(p, st.rel, st.out, c);
@@ -615,13 +714,56 @@ static sj_status run_steps(sj_plan_t *p, int phase) {
         a.seed = p->seed32;
         a.k = static_cast<int>(p->opts.k);
         a.logB = p->logB;
-        SJ_HIP(p->ctx, launch_sieve_step(a, st.max_rows, s));
+        const std::string tag = std::string(st.phase == 0 ? "bwd" : "sieve") + ":" + rel_name(st.rel) + ":" +
+                                std::to_string(&st - p->steps.data());
+        if (a.nprobe > 0 || st.out >= 0) {
+            ProfScope ps(p, "sieve_step:" + tag, static_cast<int>(&st - p->steps.data()));
+            SJ_HIP(p->ctx, launch_sieve_step(a, st.max_rows, s));
+        }
+        for (size_t b = 0; b < st.builds.size(); ++b) {
+            const int f = st.builds[b].second;
+            const int jc = st.builds[b].first;
+            BuildArgs ba{};
+            if (st.out >= 0) {          // the step's survivors
+                ba.keys = a.out_col[jc];
+                ba.n_dev = a.out_count;
+            } else if (st.src == kFull) {
+                ba.keys = R.cols[R.jcols[jc]];
+                ba.n = R.nrows;
+                ba.pred = a.pred;
+                ba.pred_lo = R.lo;
+                ba.pred_hi = R.hi;
+                if (R.pred_col >= 0) ba.nkeys_dev = at<uint32_t>(p, p->off_elig) + st.rel;
+            } else {
+                ba.keys = a.col[jc];
+                ba.n_dev = a.src_count;
+            }
+            ba.n_max = R.nrows;
+            ba.words = at<uint32_t>(p, p->filters[f].off);
+            ba.nblocks = at<uint32_t>(p, p->off_nblocks) + f;
+            ba.bits_per_key = p->opts.bits_per_key;
+            ba.nblocks_max = static_cast<uint32_t>(p->filters[f].max_words / (p->opts.block_bits / 32));
+            ba.region_blocks = p->region_blocks;
+            ba.hist = at<uint32_t>(p, p->off_bhist);
+            ba.stage_block = at<uint32_t>(p, p->off_stage[0]);
+            ba.stage_g = at<uint32_t>(p, p->off_stage[1]);
+            ba.keep = at<uint64_t>(p, p->off_keep);
+            ba.total_dev = at<uint32_t>(p, st.off_btotal[b]);
+            ba.lb.status = at<uint64_t>(p, st.off_bstatus[b]);
+            ba.lb.counter = at<uint32_t>(p, st.off_bcounter[b]);
+            ba.seed = p->seed32;
+            ba.k = static_cast<int>(p->opts.k);
+            ba.logB = p->logB;
+            ProfScope ps(p, "filter_build:" + tag + ":f" + std::to_string(f), -3 - f);
+            SJ_HIP(p->ctx, launch_filter_build(ba, s));
+        }
     }
     return SJ_OK;
 }
 
 static sj_status zero_region(sj_plan_t *p, int ph) {
     const Region &r = p->zero[ph];
+    ProfScope ps(p, "zero:" + std::to_string(ph));
     SJ_HIP(p->ctx, launch_zero(p->ws + r.begin, r.end - r.begin, p->ctx->stream));
     return SJ_OK;
 }
@@ -636,6 +778,7 @@ static sj_status check_exec(sj_plan_t *p, int need) {
     return SJ_OK;
 }
 
+
 // ---------------------------------------------------------------- the pruning phase
 
 extern "C" sj_status sj_build_filters(sj_plan_t *p) {
@@ -645,19 +788,11 @@ extern "C" sj_status sj_build_filters(sj_plan_t *p) {
     uint32_t *elig = at<uint32_t>(p, p->off_elig);
     for (int i = 0; i < p->n; ++i) {
         const Rel &R = p->rels[i];
-        if (R.pred_col >= 0) SJ_HIP(p->ctx, launch_count_pred(R.cols[R.pred_col], R.nrows, R.lo, R.hi, elig + i, s));
+        if (R.pred_col >= 0) {
+            ProfScope ps(p, std::string("count_pred:") + rel_name(i));
+            SJ_HIP(p->ctx, launch_count_pred(R.cols[R.pred_col], R.nrows, R.lo, R.hi, elig + i, s));
+        }
     }
-    SizeArgs sa{};
-    sa.nfilters = static_cast<int>(p->filters.size());
-    sa.bits_per_key = p->opts.bits_per_key;
-    sa.block_bits = p->opts.block_bits;
-    for (int f = 0; f < sa.nfilters; ++f) {
-        const int r = p->filters[f].src_rel;
-        sa.elig[f] = p->rels[r].pred_col >= 0 ? elig + r : nullptr;
-        sa.rows[f] = p->rels[r].nrows;
-        sa.nblocks[f] = at<uint32_t>(p, p->off_nblocks) + f;
-    }
-    SJ_HIP(p->ctx, launch_size_filters(sa, s));
     if (sj_status st = run_steps(p, 0)) return st;
     p->state = kFiltered;
     return SJ_OK;
@@ -722,6 +857,8 @@ extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) 
             const int ch = p->children[j][c];
             d.child_col[c] = R.jidx(p->pcol[ch]);
             d.child[c] = buckets_of(p, ch);
+            d.blo[c] = at<uint32_t>(p, p->off_blo[j][c]);
+            d.bhi[c] = at<uint32_t>(p, p->off_bhi[j][c]);
         }
         d.tile_sums = at<uint64_t>(p, p->off_tile_sums);
         if (j != p->root) {
@@ -741,6 +878,7 @@ extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) 
                 ss.lb[q].counter = at<uint32_t>(p, r.lb_hist_ctr[q]);
             }
             Lookback ld{at<uint64_t>(p, r.lb_dir), at<uint32_t>(p, r.lb_dir_ctr)};
+            ProfScope ps(p, std::string("buckets:") + rel_name(j));
             SJ_HIP(p->ctx, launch_build_buckets(list_rid(p, j, fl), lcols.data(), ncol, lcount, b.key_jcol, b, ss, ld, s));
             d.n = b.n;
             d.cap = b.cap;
@@ -758,6 +896,7 @@ extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) 
             d.cv = at<uint64_t>(p, p->off_root_cv);
             d.totals = at<uint64_t>(p, p->off_totals);
         }
+        ProfScope ps(p, std::string("dp:") + rel_name(j));
         SJ_HIP(p->ctx, launch_dp(d, s));
     }
     uint64_t tot[2] = {0, 0};
@@ -783,6 +922,7 @@ extern "C" sj_status sj_result(sj_plan_t *p, int32_t *out, uint64_t capacity) {
     m.nrels = p->n;
     std::vector<int> pos(p->n);
     for (int i = 0; i < p->n; ++i) pos[p->preorder[i]] = i;
+    const int root = p->root;
     for (int x = 0; x < p->n; ++x) {
         const int r = p->preorder[x];
         m.order[x] = r;
@@ -790,24 +930,23 @@ extern "C" sj_status sj_result(sj_plan_t *p, int32_t *out, uint64_t capacity) {
         m.nchild[x] = static_cast<int>(p->children[r].size());
         if (x == 0) {
             m.parent_pos[x] = -1;
-            m.key_col_in_parent[x] = 0;
+            m.rid[x] = list_rid(p, root, p->final_list[root]);
+            m.cw[x] = at<uint64_t>(p, p->off_root_cw);
         } else {
             const int par = p->parent[r];
+            const size_t c = std::find(p->children[par].begin(), p->children[par].end(), r) - p->children[par].begin();
             m.parent_pos[x] = pos[par];
-            m.key_col_in_parent[x] = p->rels[par].jidx(p->pcol[r]);
-            m.b[x] = buckets_of(p, r);
+            const Buckets b = buckets_of(p, r);
+            m.rid[x] = b.rid;
+            m.cw[x] = b.cw;
+            m.blo[x] = at<uint32_t>(p, p->off_blo[par][c]);
+            m.bhi[x] = at<uint32_t>(p, p->off_bhi[par][c]);
         }
     }
-    const int root = p->root;
-    const int fl = p->final_list[root];
     m.root_n = at<uint32_t>(p, p->steps[p->final_step[root]].off_count);
-    m.root_rid = list_rid(p, root, fl);
-    for (size_t c = 0; c < p->rels[root].jcols.size(); ++c) m.root_col[c] = list_col(p, root, fl, static_cast<int>(c));
-    m.root_cw = at<uint64_t>(p, p->off_root_cw);
     m.count = p->count;
-    m.count_dev = at<uint64_t>(p, p->off_totals);
     m.out = out;
-    m.chunk = 16;
+    ProfScope ps(p, "materialize", -2);
     SJ_HIP(p->ctx, launch_materialize(m, p->ctx->stream));
     return SJ_OK;
 }
@@ -862,5 +1001,74 @@ extern "C" sj_status sj_survivors_copy(sj_plan_t *p, int32_t rel, uint32_t *dst,
     if (capacity < c) return fail(p->ctx, SJ_ERR_CAPACITY, "relation %d has %u survivors", rel, c);
     SJ_HIP(p->ctx, hipMemcpyAsync(dst, list_rid(p, rel, p->final_list[rel]), 4ull * c, hipMemcpyDeviceToDevice,
                                   p->ctx->stream));
+    return SJ_OK;
+}
+
+// ---------------------------------------------------------------- profiling ABI
+
+extern "C" sj_status sj_profile_collect(sj_plan_t *p) {
+    if (!p) return SJ_ERR_INVALID;
+    if (p->prof_pending.empty()) return SJ_OK;
+    SJ_HIP(p->ctx, hipStreamSynchronize(p->ctx->stream));
+    std::vector<uint32_t> nb(p->filters.size());
+    if (!nb.empty())
+        SJ_HIP(p->ctx, hipMemcpy(nb.data(), at<uint32_t>(p, p->off_nblocks), 4 * nb.size(), hipMemcpyDeviceToHost));
+    for (auto &r : p->prof_pending) {
+        float ms = 0;
+        SJ_HIP(p->ctx, hipEventElapsedTime(&ms, r.a, r.b));
+        auto &acc = p->prof_acc[r.label];
+        acc.ms += ms;
+        acc.n += 1;
+        if (r.step >= 0) {
+            // algorithmic bytes: columns (+ row ids of a list source, + predicate column) read,
+            // survivors written, and each filter touched read or written once
+            const StepSpec &st = p->steps[r.step];
+            const Rel &R = p->rels[st.rel];
+            const uint64_t ncol = R.jcols.size();
+            uint32_t nin = R.nrows, nout = 0;
+            if (st.src != kFull)
+                SJ_HIP(p->ctx, hipMemcpy(&nin, at<uint32_t>(p, p->steps[st.src_step].off_count), 4, hipMemcpyDeviceToHost));
+            if (st.out >= 0) SJ_HIP(p->ctx, hipMemcpy(&nout, at<uint32_t>(p, st.off_count), 4, hipMemcpyDeviceToHost));
+            uint64_t bytes = uint64_t(nin) * 4 * (ncol + (st.src != kFull ? 1 : 0) + (st.src == kFull && R.pred_col >= 0 ? 1 : 0));
+            bytes += uint64_t(nout) * 4 * (ncol + 1);
+            for (auto &pr : st.probes) bytes += uint64_t(nb[pr.second]) * (p->opts.block_bits / 8);
+            for (auto &bl : st.builds) bytes += uint64_t(nb[bl.second]) * (p->opts.block_bits / 8);
+            acc.bytes = bytes;
+        } else if (r.step == -2) {
+            acc.bytes = p->count * 4ull * p->n;   // result tuples written
+        } else if (r.step <= -3) {
+            acc.bytes = 0;                        // filter builds: bytes depend on survivors (not modelled)
+        }
+        p->prof_free.push_back(r.a);
+        p->prof_free.push_back(r.b);
+    }
+    p->prof_pending.clear();
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_profile_count(const sj_plan_t *p, int32_t *n) {
+    if (!p || !n) return SJ_ERR_INVALID;
+    *n = static_cast<int32_t>(p->prof_acc.size());
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_profile_entry(const sj_plan_t *p, int32_t i, const char **label, double *total_ms,
+                                      uint64_t *launches, uint64_t *alg_bytes) {
+    if (!p || i < 0 || i >= static_cast<int32_t>(p->prof_acc.size())) return SJ_ERR_INVALID;
+    const auto &a = p->prof_acc[i];
+    if (label) *label = a.label.c_str();
+    if (total_ms) *total_ms = a.ms;
+    if (launches) *launches = a.n;
+    if (alg_bytes) *alg_bytes = a.bytes;
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_profile_reset(sj_plan_t *p) {
+    if (!p) return SJ_ERR_INVALID;
+    if (sj_status st = sj_profile_collect(p)) return st;
+    for (auto &a : p->prof_acc) {
+        a.ms = 0;
+        a.n = 0;
+    }
     return SJ_OK;
 }
