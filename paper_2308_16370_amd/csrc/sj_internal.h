@@ -22,7 +22,7 @@ constexpr int kScanTile = kScanBlock * kScanItems;
 
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
-constexpr int kRadixPasses = 32 / kRadixBits;
+constexpr int kRadixPasses = 64 / kRadixBits;   // a 64-bit composite key at most
 constexpr int kRadixBlock = 256;
 constexpr int kRadixItems = 8;
 constexpr int kRadixTile = kRadixBlock * kRadixItems;
@@ -119,20 +119,24 @@ struct Buckets {
     uint64_t *cv;              // [cap + 1] exclusive prefix of entry checksum weights
 };
 
+// LSD radix sort of (key, list index) pairs; the key is one 32-bit column, or two
+// (primary, secondary) compared as the 64-bit (primary << 32) | secondary.
 struct SortScratch {
     uint32_t cap;
-    uint32_t *keys[2];
+    uint32_t *klo[2];          // ping-pong: low key word (the only word of 1-word keys)
+    uint32_t *khi[2];          //            high key word (2-word keys)
     uint32_t *vals[2];
     uint32_t *hist;            // [kRadixBins * ntiles_max]
     uint32_t *ghist;           // [kRadixPasses * kRadixBins], zeroed
-    uint32_t *ctl;             // [16] pass control words (written on device)
+    uint32_t *ctl;             // [32] pass control words (written on device)
     Lookback lb[kRadixPasses]; // scan of each pass's histogram
 };
 
-// Sort the list (rid, cols) by column key_col into bucket order and build the
-// directory and hash index. list_count is the device-side list length.
+// Sort the list (rid, cols) by column key_col (then by column sec_col when
+// sec_col >= 0) into bucket order and build the directory (on key_col) and its hash
+// index. list_count is the device-side list length.
 hipError_t launch_build_buckets(const uint32_t *list_rid, const int32_t *const *list_cols, int ncol,
-                                const uint32_t *list_count, int key_col, const Buckets &b,
+                                const uint32_t *list_count, int key_col, int sec_col, const Buckets &b,
                                 const SortScratch &ss, Lookback lb_dir, hipStream_t s);
 
 // Per-entry DP weights of a bucketed relation (or the root list), scanned into
@@ -150,6 +154,7 @@ struct DpArgs {
     uint64_t *cv;              // [cap + 1]
     uint32_t *blo[kMaxJCols];  // [cap] per child: first entry of the matching child bucket
     uint32_t *bhi[kMaxJCols];  // [cap] per child: one past its last entry (lo = hi: none)
+    uint32_t skip_mask;        // children whose totals are not multiplied in (bounds still kept)
     uint64_t *tile_sums;       // [2 * tiles(cap)]
     uint64_t *totals;          // [2] result count and checksum, or nullptr
 };
@@ -175,5 +180,33 @@ struct MatArgs {
     int chunk;
 };
 hipError_t launch_materialize(const MatArgs &a, hipStream_t s);
+
+// Cyclic joins whose closing edges all end at the last relation L of the preorder
+// (a leaf): the other relations form a tree (the "prefix") whose tuples are
+// enumerated; L is bucketed by (tree key, closing key), so a prefix's matches are the
+// run of its L bucket whose closing column equals the prefix's closing value(s).
+constexpr int kMaxClose = 4;
+struct CycArgs {
+    MatArgs m;                 // the prefix positions 0 .. n-2 (m.nrels = n - 1)
+    int nrels;                 // output width n
+    int L_rel;                 // relation index of L
+    int pos_P;                 // position of L's parent
+    const uint32_t *Lblo, *Lbhi;   // L's bucket below each entry of its parent
+    const uint32_t *Lrid;
+    const int32_t *Lclose;     // L's closing column in bucket order (ascending as u32 inside a bucket)
+    const uint64_t *Lcv;       // exclusive prefix of L's checksum factors
+    int nclose;
+    int cpos[kMaxClose];       // position of each closing edge's other end
+    const int32_t *ccol[kMaxClose];  // its closing column, entry-indexed
+    uint64_t wpre;             // number of prefixes
+    uint32_t G;                // threads; thread t takes an even share of the prefixes
+    uint64_t *cnt;             // [G] results per thread
+    uint64_t *chk;             // [G] checksum per thread
+    uint64_t *off;             // [G] exclusive prefix of cnt (write pass)
+    uint64_t *totals;          // [2] count, checksum
+    int32_t *out;
+};
+hipError_t launch_cyclic_count(const CycArgs &a, hipStream_t s);
+hipError_t launch_cyclic_write(const CycArgs &a, hipStream_t s);
 
 }  // namespace sj

@@ -16,66 +16,105 @@
 
 namespace sj {
 
-// ================================================================ radix sort
-// keys are the u32 bit patterns of int32 join keys; values are list indices.
+static uint32_t grid_for(uint32_t n, uint32_t per_block, uint32_t cap) {
+    uint32_t g = (n + per_block - 1) / per_block;
+    if (g > cap) g = cap;
+    return g ? g : 1;
+}
 
-__global__ __launch_bounds__(kRadixBlock) void k_radix_ghist(const int32_t *__restrict__ keys,
-                                                             const uint32_t *n_ptr, uint32_t *ghist) {
+// ================================================================ radix sort
+// Keys are u32 bit patterns of int32 join keys (any fixed order groups equal keys);
+// values are list indices. Pass p sorts on byte p of the key: bytes 0-3 of the low
+// word, then bytes 0-3 of the high word for 2-word keys.
+
+struct KeySrc {
+    const int32_t *lo;         // list column of the low key word
+    const int32_t *hi;         // list column of the high key word, or nullptr
+};
+
+__device__ __forceinline__ uint32_t radix_digit(uint32_t lo, uint32_t hi, int pass) {
+    const uint32_t w = pass < 4 ? lo : hi;
+    return (w >> ((pass & 3) * kRadixBits)) & (kRadixBins - 1);
+}
+
+__global__ __launch_bounds__(kRadixBlock) void k_radix_ghist(KeySrc ks, const uint32_t *n_ptr, uint32_t *ghist) {
     __shared__ uint32_t h[kRadixPasses][kRadixBins];
+    const int np = ks.hi ? 8 : 4;
     for (int i = threadIdx.x; i < kRadixPasses * kRadixBins; i += blockDim.x) (&h[0][0])[i] = 0;
     __syncthreads();
     const uint32_t n = *n_ptr;
     for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-        const uint32_t k = static_cast<uint32_t>(keys[e]);
-#pragma unroll
-        for (int p = 0; p < kRadixPasses; ++p) atomicAdd(&h[p][(k >> (p * kRadixBits)) & (kRadixBins - 1)], 1u);
+        const uint32_t lo = static_cast<uint32_t>(ks.lo[e]);
+        const uint32_t hi = ks.hi ? static_cast<uint32_t>(ks.hi[e]) : 0u;
+        for (int p = 0; p < np; ++p) atomicAdd(&h[p][radix_digit(lo, hi, p)], 1u);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kRadixPasses * kRadixBins; i += blockDim.x) {
+    for (int i = threadIdx.x; i < np * kRadixBins; i += blockDim.x) {
         const uint32_t c = (&h[0][0])[i];
         if (c) atomicAdd(ghist + i, c);
     }
 }
 
-// Pass control: ctl[p] = pass p moves data (its digit is not constant); ctl[4 + p] =
-// where pass p reads (0: the list, 1: buffer 0, 2: buffer 1); ctl[8] = where the
-// sorted data ends up.
-__global__ void k_radix_ctl(const uint32_t *ghist, const uint32_t *n_ptr, uint32_t *ctl) {
-    if (threadIdx.x != 0) return;
+// Pass control: ctl[p] = pass p moves data (its digit is not constant); ctl[8 + p] =
+// where pass p reads (0: the list, 1: buffer 0, 2: buffer 1); ctl[16] = where the
+// sorted data ends up. One thread per pass finds whether a bin holds every key.
+__global__ void k_radix_ctl(const uint32_t *ghist, const uint32_t *n_ptr, int npasses, uint32_t *ctl) {
+    __shared__ uint32_t s_act[kRadixPasses];
     const uint32_t n = *n_ptr;
-    uint32_t src = 0;
-    for (int p = 0; p < kRadixPasses; ++p) {
-        uint32_t mx = 0;
-        for (int d = 0; d < kRadixBins; ++d) mx = max(mx, ghist[p * kRadixBins + d]);
-        const uint32_t active = (n > 1 && mx < n) ? 1u : 0u;
-        ctl[p] = active;
-        ctl[4 + p] = src;
-        if (active) src = (src == 1) ? 2u : 1u;
+    const int p = threadIdx.x >> 5, l = threadIdx.x & 31;   // 32 threads per pass
+    uint32_t mx = 0;
+    if (p < npasses)
+        for (int d = l; d < kRadixBins; d += 32) mx = max(mx, ghist[p * kRadixBins + d]);
+#pragma unroll
+    for (int o = 16; o >= 1; o >>= 1) mx = max(mx, static_cast<uint32_t>(__shfl_xor(static_cast<int>(mx), o, 32)));
+    if (l == 0 && p < kRadixPasses) s_act[p] = (p < npasses && n > 1 && mx < n) ? 1u : 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t src = 0;
+        for (int q = 0; q < kRadixPasses; ++q) {
+            ctl[q] = s_act[q];
+            ctl[8 + q] = src;
+            if (s_act[q]) src = (src == 1) ? 2u : 1u;
+        }
+        ctl[16] = src;
     }
-    ctl[8] = src;
 }
 
-__device__ __forceinline__ const uint32_t *radix_src_keys(const SortScratch &ss, const int32_t *list_keys,
-                                                         uint32_t src) {
-    return src == 0 ? reinterpret_cast<const uint32_t *>(list_keys) : ss.keys[src - 1];
+struct RadixIo {
+    const uint32_t *slo, *shi, *sval;   // source (sval nullptr: the list index)
+    uint32_t *dlo, *dhi, *dval;
+};
+
+__device__ __forceinline__ RadixIo radix_io(const SortScratch &ss, const KeySrc &ks, int pass) {
+    const uint32_t src = ss.ctl[8 + pass];
+    RadixIo io;
+    io.slo = src == 0 ? reinterpret_cast<const uint32_t *>(ks.lo) : ss.klo[src - 1];
+    io.shi = src == 0 ? reinterpret_cast<const uint32_t *>(ks.hi) : (ks.hi ? ss.khi[src - 1] : nullptr);
+    io.sval = src == 0 ? nullptr : ss.vals[src - 1];
+    const int d = (src == 1) ? 1 : 0;
+    io.dlo = ss.klo[d];
+    io.dhi = ks.hi ? ss.khi[d] : nullptr;
+    io.dval = ss.vals[d];
+    return io;
 }
 
 // Per-tile digit histogram, digit-major: hist[d * ntiles + tile].
-__global__ __launch_bounds__(kRadixBlock) void k_radix_hist(int pass, const int32_t *__restrict__ list_keys,
-                                                            SortScratch ss, const uint32_t *n_ptr) {
+__global__ __launch_bounds__(kRadixBlock) void k_radix_hist(int pass, KeySrc ks, SortScratch ss,
+                                                            const uint32_t *n_ptr) {
     if (!ss.ctl[pass]) return;
     __shared__ uint32_t h[kRadixBins];
     const uint32_t n = *n_ptr;
     const uint32_t ntiles = (n + kRadixTile - 1) / kRadixTile;
-    const uint32_t *keys = radix_src_keys(ss, list_keys, ss.ctl[4 + pass]);
-    const int shift = pass * kRadixBits;
+    const RadixIo io = radix_io(ss, ks, pass);
+    const uint32_t *w = pass < 4 ? io.slo : io.shi;
+    const int shift = (pass & 3) * kRadixBits;
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         h[threadIdx.x] = 0;
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kRadixItems; ++i) {
             const uint32_t e = tile * kRadixTile + i * kRadixBlock + threadIdx.x;
-            if (e < n) atomicAdd(&h[(keys[e] >> shift) & (kRadixBins - 1)], 1u);
+            if (e < n) atomicAdd(&h[(w[e] >> shift) & (kRadixBins - 1)], 1u);
         }
         __syncthreads();
         ss.hist[threadIdx.x * ntiles + tile] = h[threadIdx.x];
@@ -123,8 +162,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_u32(uint32_t *data, const u
 // tile * kRadixTile + i * kRadixBlock + t), processed round by round, so element
 // order equals (round, wave, lane) order; a lane's rank among equal digits comes from
 // 8 ballots (the lanes sharing its digit), waves are ordered through LDS counts.
-__global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(int pass, const int32_t *__restrict__ list_keys,
-                                                               SortScratch ss, const uint32_t *n_ptr) {
+__global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(int pass, KeySrc ks, SortScratch ss,
+                                                               const uint32_t *n_ptr) {
     if (!ss.ctl[pass]) return;
     constexpr int kWaves = kRadixBlock / 64;
     __shared__ uint32_t s_off[kRadixBins];
@@ -132,12 +171,8 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(int pass, const i
     __shared__ uint32_t s_cnt[kWaves][kRadixBins];
     const uint32_t n = *n_ptr;
     const uint32_t ntiles = (n + kRadixTile - 1) / kRadixTile;
-    const uint32_t src = ss.ctl[4 + pass];
-    const uint32_t *keys = radix_src_keys(ss, list_keys, src);
-    const uint32_t *vals = src == 0 ? nullptr : ss.vals[src - 1];
-    uint32_t *dkeys = (src == 1) ? ss.keys[1] : ss.keys[0];
-    uint32_t *dvals = (src == 1) ? ss.vals[1] : ss.vals[0];
-    const int shift = pass * kRadixBits;
+    const RadixIo io = radix_io(ss, ks, pass);
+    const int shift = (pass & 3) * kRadixBits;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const uint64_t lt = (1ull << lane) - 1ull;
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -149,9 +184,10 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(int pass, const i
         for (int i = 0; i < kRadixItems; ++i) {
             const uint32_t e = tile * kRadixTile + i * kRadixBlock + tid;
             const bool valid = e < n;
-            const uint32_t key = valid ? keys[e] : 0u;
-            const uint32_t val = valid ? (vals ? vals[e] : e) : 0u;
-            const uint32_t d = (key >> shift) & (kRadixBins - 1);
+            const uint32_t klo = valid ? io.slo[e] : 0u;
+            const uint32_t khi = (valid && io.shi) ? io.shi[e] : 0u;
+            const uint32_t val = valid ? (io.sval ? io.sval[e] : e) : 0u;
+            const uint32_t d = ((pass < 4 ? klo : khi) >> shift) & (kRadixBins - 1);
             uint64_t m = __ballot(valid);
 #pragma unroll
             for (int b = 0; b < kRadixBits; ++b) {
@@ -166,8 +202,9 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(int pass, const i
                 uint32_t pos = s_run[d] + rank;
                 for (int w = 0; w < wid; ++w) pos += s_cnt[w][d];
                 const uint32_t o = s_off[d] + pos;
-                dkeys[o] = key;
-                dvals[o] = val;
+                io.dlo[o] = klo;
+                if (io.dhi) io.dhi[o] = khi;
+                io.dval[o] = val;
             }
             __syncthreads();
             uint32_t t = 0;
@@ -191,7 +228,7 @@ struct ListRef {
 
 __global__ void k_gather(ListRef l, const uint32_t *n_ptr, SortScratch ss, Buckets b) {
     const uint32_t n = *n_ptr;
-    const uint32_t fin = ss.ctl[8];
+    const uint32_t fin = ss.ctl[16];
     const uint32_t *idx = fin == 0 ? nullptr : ss.vals[fin - 1];
     for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
         const uint32_t li = idx ? idx[e] : e;
@@ -272,14 +309,8 @@ __global__ void k_dir_insert(Buckets b) {
     }
 }
 
-static uint32_t grid_for(uint32_t n, uint32_t per_block, uint32_t cap) {
-    uint32_t g = (n + per_block - 1) / per_block;
-    if (g > cap) g = cap;
-    return g ? g : 1;
-}
-
 hipError_t launch_build_buckets(const uint32_t *list_rid, const int32_t *const *list_cols, int ncol,
-                                const uint32_t *list_count, int key_col, const Buckets &b,
+                                const uint32_t *list_count, int key_col, int sec_col, const Buckets &b,
                                 const SortScratch &ss, Lookback lb_dir, hipStream_t s) {
     const uint32_t cap = b.cap;
     if (cap == 0) {
@@ -288,19 +319,22 @@ hipError_t launch_build_buckets(const uint32_t *list_rid, const int32_t *const *
         hipLaunchKernelGGL(k_slots_clear, dim3(1), dim3(256), 0, s, b);
         return hipGetLastError();
     }
-    const int32_t *keys = list_cols[key_col];
+    KeySrc ks;
+    ks.lo = list_cols[sec_col >= 0 ? sec_col : key_col];
+    ks.hi = sec_col >= 0 ? list_cols[key_col] : nullptr;
+    const int npasses = sec_col >= 0 ? 8 : 4;
     const uint32_t tiles = (cap + kRadixTile - 1) / kRadixTile;
     const uint32_t tgrid = tiles < kPersistentBlocks ? tiles : kPersistentBlocks;
-    hipLaunchKernelGGL(k_radix_ghist, dim3(grid_for(cap, 256 * 16, 1024)), dim3(kRadixBlock), 0, s, keys,
+    hipLaunchKernelGGL(k_radix_ghist, dim3(grid_for(cap, 256 * 16, 1024)), dim3(kRadixBlock), 0, s, ks,
                        list_count, ss.ghist);
-    hipLaunchKernelGGL(k_radix_ctl, dim3(1), dim3(64), 0, s, ss.ghist, list_count, ss.ctl);
+    hipLaunchKernelGGL(k_radix_ctl, dim3(1), dim3(256), 0, s, ss.ghist, list_count, npasses, ss.ctl);
     const uint32_t scan_len_max = kRadixBins * tiles;
     const uint32_t scan_grid = grid_for(scan_len_max, kScanTile, kPersistentBlocks);
-    for (int p = 0; p < kRadixPasses; ++p) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(tgrid), dim3(kRadixBlock), 0, s, p, keys, ss, list_count);
+    for (int p = 0; p < npasses; ++p) {
+        hipLaunchKernelGGL(k_radix_hist, dim3(tgrid), dim3(kRadixBlock), 0, s, p, ks, ss, list_count);
         hipLaunchKernelGGL(k_scan_u32, dim3(scan_grid), dim3(kScanBlock), 0, s, ss.hist, list_count,
                            static_cast<uint32_t>(kRadixTile), static_cast<uint32_t>(kRadixBins), ss.ctl + p, ss.lb[p]);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(tgrid), dim3(kRadixBlock), 0, s, p, keys, ss, list_count);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(tgrid), dim3(kRadixBlock), 0, s, p, ks, ss, list_count);
     }
     ListRef l;
     l.rid = list_rid;
@@ -335,8 +369,10 @@ __device__ __forceinline__ void dp_entry(const DpArgs &a, const uint32_t *masks,
             }
             a.blo[c][e] = lo;
             a.bhi[c][e] = hi;
-            w *= a.child[c].cw[hi] - a.child[c].cw[lo];
-            v *= a.child[c].cv[hi] - a.child[c].cv[lo];
+            if (!(a.skip_mask & (1u << c))) {
+                w *= a.child[c].cw[hi] - a.child[c].cw[lo];
+                v *= a.child[c].cv[hi] - a.child[c].cv[lo];
+            }
         }
     }
 }
@@ -650,5 +686,154 @@ hipError_t launch_materialize(const MatArgs &a0, hipStream_t s) {
     }
     return hipGetLastError();
 }
+
+// ================================================================ cyclic joins
+
+__device__ __forceinline__ uint32_t lower_bound_u32(const int32_t *a, uint32_t lo, uint32_t hi, uint32_t x) {
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (static_cast<uint32_t>(a[mid]) < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t upper_bound_u32(const int32_t *a, uint32_t lo, uint32_t hi, uint32_t x) {
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (static_cast<uint32_t>(a[mid]) <= x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// The run of L entries matching the current prefix: [r0, r1) (empty if the closing
+// values disagree).
+template <int N>
+__device__ __forceinline__ void cyc_run(const CycArgs &a, const MatState<N> &st, uint32_t &r0, uint32_t &r1) {
+    uint32_t ep = st.e[0];
+#pragma unroll
+    for (int q = 1; q < N; ++q)
+        if (q == a.pos_P) ep = st.e[q];
+    const uint32_t lo = a.Lblo[ep], hi = a.Lbhi[ep];
+    r0 = r1 = lo;
+    if (lo == hi) return;
+    uint32_t val = 0;
+    bool agree = true;
+#pragma unroll
+    for (int c = 0; c < kMaxClose; ++c) {
+        if (c < a.nclose) {
+            uint32_t eu = st.e[0];
+#pragma unroll
+            for (int q = 1; q < N; ++q)
+                if (q == a.cpos[c]) eu = st.e[q];
+            const uint32_t x = static_cast<uint32_t>(a.ccol[c][eu]);
+            if (c == 0)
+                val = x;
+            else if (x != val)
+                agree = false;
+        }
+    }
+    if (!agree) return;
+    r0 = lower_bound_u32(a.Lclose, lo, hi, val);
+    r1 = upper_bound_u32(a.Lclose, r0, hi, val);
+}
+
+template <int N>
+__device__ __forceinline__ uint64_t prefix_factor(const CycArgs &a, const MatState<N> &st) {
+    uint64_t f = 1;
+#pragma unroll
+    for (int x = 0; x < N; ++x) f *= chk_factor(static_cast<uint32_t>(a.m.order[x]), a.m.rid[x][st.e[x]]);
+    return f;
+}
+
+template <int N, bool WRITE>
+__global__ __launch_bounds__(256) void k_cyclic(CycArgs a) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.G) return;
+    const uint64_t q = a.wpre / a.G, rem = a.wpre % a.G;
+    const uint64_t s = q * t + (t < rem ? t : rem);
+    const uint64_t e = s + q + (t < rem ? 1 : 0);
+    uint64_t cnt = 0, chk = 0;
+    if (s < e) {
+        const uint32_t root_n = *a.m.root_n;
+        const uint32_t r = upper_bound_u64(a.m.cw[0], 0, root_n + 1, s) - 1;
+        MatState<N> st;
+        mat_decode<N>(a.m, st, r, s - a.m.cw[0][r]);
+        uint64_t o = WRITE ? a.off[t] : 0;
+        for (uint64_t i = s;;) {
+            uint32_t r0, r1;
+            cyc_run<N>(a, st, r0, r1);
+            if (r1 > r0) {
+                if (WRITE) {
+                    for (uint32_t j = r0; j < r1; ++j, ++o) {
+                        int32_t *dst = a.out + o * a.nrels;
+#pragma unroll
+                        for (int x = 0; x < N; ++x) dst[a.m.order[x]] = static_cast<int32_t>(a.m.rid[x][st.e[x]]);
+                        dst[a.L_rel] = static_cast<int32_t>(a.Lrid[j]);
+                    }
+                } else {
+                    cnt += r1 - r0;
+                    chk += prefix_factor<N>(a, st) * (a.Lcv[r1] - a.Lcv[r0]);
+                }
+            }
+            if (++i >= e) break;
+            mat_advance<N>(a.m, st, root_n);
+        }
+    }
+    if (!WRITE) {
+        a.cnt[t] = cnt;
+        a.chk[t] = chk;
+    }
+}
+
+// One block: totals of cnt/chk and the exclusive prefix of cnt.
+__global__ __launch_bounds__(1024) void k_cyclic_scan(CycArgs a) {
+    __shared__ uint64_t s_w[1024 / 64], s_v[1024 / 64];
+    const uint32_t per = (a.G + 1023) / 1024;
+    const uint32_t b = threadIdx.x * per, e = min(a.G, b + per);
+    uint64_t c = 0, v = 0;
+    for (uint32_t i = b; i < e; ++i) {
+        c += a.cnt[i];
+        v += a.chk[i];
+    }
+    uint64_t tc, tv;
+    uint64_t off = block_excl_scan<1024>(c, s_w, tc);
+    block_excl_scan<1024>(v, s_v, tv);
+    for (uint32_t i = b; i < e; ++i) {
+        a.off[i] = off;
+        off += a.cnt[i];
+    }
+    if (threadIdx.x == 0) {
+        a.totals[0] = tc;
+        a.totals[1] = tv;
+    }
+}
+
+template <bool WRITE>
+static hipError_t launch_cyclic(const CycArgs &a, hipStream_t s) {
+    if (a.G == 0) return hipSuccess;
+    const dim3 g((a.G + 255) / 256);
+    switch (a.m.nrels) {
+#define SJ_CYC_CASE(NN) \
+    case NN: hipLaunchKernelGGL((k_cyclic<NN, WRITE>), g, dim3(256), 0, s, a); break;
+        SJ_CYC_CASE(1) SJ_CYC_CASE(2) SJ_CYC_CASE(3) SJ_CYC_CASE(4) SJ_CYC_CASE(5) SJ_CYC_CASE(6) SJ_CYC_CASE(7)
+#undef SJ_CYC_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cyclic_count(const CycArgs &a, hipStream_t s) {
+    if (hipError_t e = launch_cyclic<false>(a, s)) return e;
+    if (a.G) hipLaunchKernelGGL(k_cyclic_scan, dim3(1), dim3(1024), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cyclic_write(const CycArgs &a, hipStream_t s) { return launch_cyclic<true>(a, s); }
 
 }  // namespace sj

@@ -109,13 +109,20 @@ struct sj_plan_s {
     struct JoinRel {
         uint64_t rid = 0, cols = 0, dir_begin = 0, dir_key = 0, slots = 0, cw = 0, cv = 0, ndir = 0, mask = 0;
         uint32_t slot_cap = 0;
-        uint64_t ghist = 0, lb_hist[kRadixPasses] = {0, 0, 0, 0}, lb_hist_ctr[kRadixPasses] = {0, 0, 0, 0};
+        uint64_t ghist = 0, lb_hist[kRadixPasses] = {}, lb_hist_ctr[kRadixPasses] = {};
         uint64_t lb_dir = 0, lb_dir_ctr = 0;
     };
     std::vector<JoinRel> jr;
-    uint64_t off_sort_keys[2] = {0, 0}, off_sort_vals[2] = {0, 0}, off_hist = 0, off_ctl = 0, off_tile_sums = 0;
+    uint64_t off_sort_klo[2] = {0, 0}, off_sort_khi[2] = {0, 0}, off_sort_vals[2] = {0, 0};
+    uint64_t off_hist = 0, off_ctl = 0, off_tile_sums = 0;
     uint64_t off_root_cw = 0, off_root_cv = 0;
     std::vector<std::vector<uint64_t>> off_blo, off_bhi;   // [relation][child]
+    // cyclic graphs: closing edges all end at L = the last relation of the preorder
+    bool cyclic = false, cyc_ok = true;
+    int L = -1, cyc_cv = -1;
+    uint64_t off_cnt = 0, off_chk = 0, off_off = 0;
+    uint32_t cyc_G = 0;
+    uint64_t wpre = 0;
     uint32_t sort_cap = 0;
     int state = kPlanned;
     uint64_t count = 0, checksum = 0;
@@ -197,6 +204,8 @@ extern "C" const char *sj_last_error(const sj_ctx *ctx) { return ctx ? ctx->err.
 // ---------------------------------------------------------------- planning
 
 static uint32_t tiles_of(uint32_t n, uint32_t tile) { return (n + tile - 1) / tile; }
+
+constexpr uint32_t kCycThreads = 1u << 18;   // threads that share a cyclic join's prefixes
 
 static uint64_t nblocks_for(uint64_t n, uint32_t bpk, uint32_t B) {
     uint64_t nb = (n * bpk + B - 1) / B;
@@ -461,15 +470,19 @@ static void build_layout(sj_plan_t *p) {
     }
     p->sort_cap = maxcap;
     for (int b = 0; b < 2; ++b) {
-        p->off_sort_keys[b] = L.take(4ull * maxcap);
+        p->off_sort_klo[b] = L.take(4ull * maxcap);
+        p->off_sort_khi[b] = L.take(4ull * maxcap);
         p->off_sort_vals[b] = L.take(4ull * maxcap);
     }
     p->off_hist = L.take(4ull * kRadixBins * std::max<uint32_t>(1, tiles_of(maxcap, kRadixTile)));
-    p->off_ctl = L.take(4 * 16);
+    p->off_ctl = L.take(4 * 32);
     p->off_tile_sums = L.take(16ull * std::max<uint32_t>(1, tiles_of(maxcap, kScanTile)));
     const uint64_t rc = p->rels[p->root].nrows;
     p->off_root_cw = L.take(8 * (rc + 1));
     p->off_root_cv = L.take(8 * (rc + 1));
+    p->off_cnt = L.take(8ull * kCycThreads);
+    p->off_chk = L.take(8ull * kCycThreads);
+    p->off_off = L.take(8ull * kCycThreads);
     p->off_blo.assign(n, {});
     p->off_bhi.assign(n, {});
     for (int j = 0; j < n; ++j) {
@@ -588,6 +601,13 @@ extern "C" sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, con
     if (sj_status st = build_schedule(p)) {
         delete p;
         return st;
+    }
+    p->L = p->preorder.back();
+    p->cyclic = !p->closing.empty();
+    if (p->closing.size() > static_cast<size_t>(kMaxClose) || (p->cyclic && nrels > 8)) p->cyc_ok = false;
+    for (const Closing &c : p->closing) {
+        if (c.v != p->L || (p->cyc_cv >= 0 && c.cv != p->cyc_cv)) p->cyc_ok = false;
+        p->cyc_cv = c.cv;
     }
     p->region_blocks = kRegionBytes / (o.block_bits / 8);
     for (auto &f : p->filters) {
@@ -836,10 +856,84 @@ static Buckets buckets_of(sj_plan_t *p, int j) {
     return b;
 }
 
+// Materialisation arguments for preorder positions 0 .. npos-1 (npos = n: the whole
+// tree; npos = n - 1: the prefix tree of a cyclic join, without L).
+static MatArgs mat_args(sj_plan_t *p, int npos) {
+    MatArgs m{};
+    m.nrels = npos;
+    std::vector<int> pos(p->n);
+    for (int i = 0; i < p->n; ++i) pos[p->preorder[i]] = i;
+    const int root = p->root;
+    for (int x = 0; x < npos; ++x) {
+        const int r = p->preorder[x];
+        int nch = 0;
+        for (int c : p->children[r])
+            if (pos[c] < npos) ++nch;
+        m.order[x] = r;
+        m.is_leaf[x] = nch == 0 ? 1 : 0;
+        m.nchild[x] = nch;
+        if (x == 0) {
+            m.parent_pos[x] = -1;
+            m.rid[x] = list_rid(p, root, p->final_list[root]);
+            m.cw[x] = at<uint64_t>(p, p->off_root_cw);
+        } else {
+            const int par = p->parent[r];
+            const size_t c = std::find(p->children[par].begin(), p->children[par].end(), r) - p->children[par].begin();
+            m.parent_pos[x] = pos[par];
+            const Buckets b = buckets_of(p, r);
+            m.rid[x] = b.rid;
+            m.cw[x] = b.cw;
+            m.blo[x] = at<uint32_t>(p, p->off_blo[par][c]);
+            m.bhi[x] = at<uint32_t>(p, p->off_bhi[par][c]);
+        }
+    }
+    m.root_n = at<uint32_t>(p, p->steps[p->final_step[root]].off_count);
+    return m;
+}
+
+static CycArgs cyc_args(sj_plan_t *p, int32_t *out) {
+    CycArgs c{};
+    c.m = mat_args(p, p->n - 1);
+    c.nrels = p->n;
+    const int L = p->L, P = p->parent[L];
+    std::vector<int> pos(p->n);
+    for (int i = 0; i < p->n; ++i) pos[p->preorder[i]] = i;
+    c.L_rel = L;
+    c.pos_P = pos[P];
+    const size_t ci = std::find(p->children[P].begin(), p->children[P].end(), L) - p->children[P].begin();
+    c.Lblo = at<uint32_t>(p, p->off_blo[P][ci]);
+    c.Lbhi = at<uint32_t>(p, p->off_bhi[P][ci]);
+    const Buckets bl = buckets_of(p, L);
+    c.Lrid = bl.rid;
+    c.Lclose = bl.col[p->rels[L].jidx(p->cyc_cv)];
+    c.Lcv = bl.cv;
+    c.nclose = static_cast<int>(p->closing.size());
+    for (int e = 0; e < c.nclose && e < kMaxClose; ++e) {
+        const Closing &cl = p->closing[e];
+        c.cpos[e] = pos[cl.u];
+        const int jc = p->rels[cl.u].jidx(cl.cu);
+        if (cl.u == p->root)
+            c.ccol[e] = list_col(p, cl.u, p->final_list[cl.u], jc);
+        else
+            c.ccol[e] = buckets_of(p, cl.u).col[jc];
+    }
+    c.wpre = p->wpre;
+    c.G = p->cyc_G;
+    c.cnt = at<uint64_t>(p, p->off_cnt);
+    c.chk = at<uint64_t>(p, p->off_chk);
+    c.off = at<uint64_t>(p, p->off_off);
+    c.totals = at<uint64_t>(p, p->off_totals);
+    c.out = out;
+    return c;
+}
+
 extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) {
     if (sj_status st = check_exec(p, kSieved)) return st;
-    if (!p->closing.empty())
-        return fail(p->ctx, SJ_ERR_UNSUPPORTED, "cyclic join graphs are not executed by this build yet");
+    if (!p->cyc_ok)
+        return fail(p->ctx, SJ_ERR_UNSUPPORTED,
+                    "cyclic join: every closing edge must end at the last relation of the preorder (relation %d), "
+                    "on one column",
+                    p->L);
     hipStream_t s = p->ctx->stream;
     if (sj_status st = zero_region(p, 2)) return st;
     for (int j : p->postorder) {
@@ -859,6 +953,7 @@ extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) 
             d.child[c] = buckets_of(p, ch);
             d.blo[c] = at<uint32_t>(p, p->off_blo[j][c]);
             d.bhi[c] = at<uint32_t>(p, p->off_bhi[j][c]);
+            if (p->cyclic && ch == p->L) d.skip_mask |= 1u << c;
         }
         d.tile_sums = at<uint64_t>(p, p->off_tile_sums);
         if (j != p->root) {
@@ -867,7 +962,8 @@ extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) 
             SortScratch ss{};
             ss.cap = p->sort_cap;
             for (int q = 0; q < 2; ++q) {
-                ss.keys[q] = at<uint32_t>(p, p->off_sort_keys[q]);
+                ss.klo[q] = at<uint32_t>(p, p->off_sort_klo[q]);
+                ss.khi[q] = at<uint32_t>(p, p->off_sort_khi[q]);
                 ss.vals[q] = at<uint32_t>(p, p->off_sort_vals[q]);
             }
             ss.hist = at<uint32_t>(p, p->off_hist);
@@ -878,8 +974,10 @@ extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) 
                 ss.lb[q].counter = at<uint32_t>(p, r.lb_hist_ctr[q]);
             }
             Lookback ld{at<uint64_t>(p, r.lb_dir), at<uint32_t>(p, r.lb_dir_ctr)};
+            int sec = -1;   // L of a cyclic join is ordered by its closing column inside each bucket
+            if (p->cyclic && j == p->L && p->cyc_cv != p->mycol[j]) sec = R.jidx(p->cyc_cv);
             ProfScope ps(p, std::string("buckets:") + rel_name(j));
-            SJ_HIP(p->ctx, launch_build_buckets(list_rid(p, j, fl), lcols.data(), ncol, lcount, b.key_jcol, b, ss, ld, s));
+            SJ_HIP(p->ctx, launch_build_buckets(list_rid(p, j, fl), lcols.data(), ncol, lcount, b.key_jcol, sec, b, ss, ld, s));
             d.n = b.n;
             d.cap = b.cap;
             d.rid = b.rid;
@@ -902,6 +1000,22 @@ extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) 
     uint64_t tot[2] = {0, 0};
     SJ_HIP(p->ctx, hipMemcpyAsync(tot, at<uint64_t>(p, p->off_totals), 16, hipMemcpyDeviceToHost, s));
     SJ_HIP(p->ctx, hipStreamSynchronize(s));
+    if (p->cyclic) {
+        // tot[0] counted the prefixes; now count their matches in L
+        p->wpre = tot[0];
+        uint64_t g = (p->wpre + 31) / 32;
+        p->cyc_G = static_cast<uint32_t>(std::min<uint64_t>(g, kCycThreads));
+        CycArgs c = cyc_args(p, nullptr);
+        {
+            ProfScope ps(p, "cyclic_count");
+            SJ_HIP(p->ctx, launch_cyclic_count(c, s));
+        }
+        tot[0] = tot[1] = 0;
+        if (p->cyc_G) {
+            SJ_HIP(p->ctx, hipMemcpyAsync(tot, at<uint64_t>(p, p->off_totals), 16, hipMemcpyDeviceToHost, s));
+            SJ_HIP(p->ctx, hipStreamSynchronize(s));
+        }
+    }
     p->count = tot[0];
     p->checksum = tot[1];
     if (count) *count = tot[0];
@@ -918,32 +1032,13 @@ extern "C" sj_status sj_result(sj_plan_t *p, int32_t *out, uint64_t capacity) {
     if (p->count == 0) return SJ_OK;
     if (!out) return fail(p->ctx, SJ_ERR_INVALID, "null output buffer");
     if (reinterpret_cast<uintptr_t>(out) % 16) return fail(p->ctx, SJ_ERR_INVALID, "output must be 16-byte aligned");
-    MatArgs m{};
-    m.nrels = p->n;
-    std::vector<int> pos(p->n);
-    for (int i = 0; i < p->n; ++i) pos[p->preorder[i]] = i;
-    const int root = p->root;
-    for (int x = 0; x < p->n; ++x) {
-        const int r = p->preorder[x];
-        m.order[x] = r;
-        m.is_leaf[x] = p->children[r].empty() ? 1 : 0;
-        m.nchild[x] = static_cast<int>(p->children[r].size());
-        if (x == 0) {
-            m.parent_pos[x] = -1;
-            m.rid[x] = list_rid(p, root, p->final_list[root]);
-            m.cw[x] = at<uint64_t>(p, p->off_root_cw);
-        } else {
-            const int par = p->parent[r];
-            const size_t c = std::find(p->children[par].begin(), p->children[par].end(), r) - p->children[par].begin();
-            m.parent_pos[x] = pos[par];
-            const Buckets b = buckets_of(p, r);
-            m.rid[x] = b.rid;
-            m.cw[x] = b.cw;
-            m.blo[x] = at<uint32_t>(p, p->off_blo[par][c]);
-            m.bhi[x] = at<uint32_t>(p, p->off_bhi[par][c]);
-        }
+    if (p->cyclic) {
+        CycArgs c = cyc_args(p, out);
+        ProfScope ps(p, "cyclic_write", -2);
+        SJ_HIP(p->ctx, launch_cyclic_write(c, p->ctx->stream));
+        return SJ_OK;
     }
-    m.root_n = at<uint32_t>(p, p->steps[p->final_step[root]].off_count);
+    MatArgs m = mat_args(p, p->n);
     m.count = p->count;
     m.out = out;
     ProfScope ps(p, "materialize", -2);

@@ -41,13 +41,37 @@ def test_tiny_random_acyclic(seed):
                     block_bits=[256, 512, 1024][(seed // 3) % 3], passes=1 + seed % 2, seed=seed)
 
 
-@pytest.mark.parametrize("seed", range(30))
-def test_tiny_random_cyclic_sieve(seed):
+@pytest.mark.parametrize("seed", range(60))
+def test_tiny_random_cyclic(seed):
     q = W.tiny_random(8000 + seed, kind=["triangle", "cycle4", "selfjoin"][seed % 3])
-    plan = make_plan(q, bits_per_key=4, k=3, passes=1 + seed % 2, seed=seed)
+    passes = 1 + seed % 2
+    plan = make_plan(q, bits_per_key=4, k=3, passes=passes, seed=seed)
     plan.build_filters()
     plan.sieve()
-    check_sieve(q, plan, 4, 3, 512, 1 + seed % 2, seed)
+    check_sieve(q, plan, 4, 3, 512, passes, seed)
+    try:
+        cnt, chk = plan.join()
+    except sj.SjError as e:
+        # closing edges that do not all end at the last relation of the preorder
+        assert e.code == sj.SJ_ERR_UNSUPPORTED
+        return
+    ref, rcnt, rchk = oracle.hash_join(q)
+    assert (cnt, chk) == (rcnt, rchk)
+    tup = plan.result().cpu().numpy().astype(np.uint32)
+    assert np.array_equal(lexsort_rows(tup), ref)
+
+
+def test_triangle_small():
+    q = W.triangle(6000, 1500, 2.1, seed=9)
+    plan, tup = run_and_compare(q, seed=4)
+    assert tup.shape[0] > 1000 and tup.shape[0] % 3 == 0
+
+
+def test_psyn_with_redundant_closing_edge():
+    q = W.psyn(20000, 100, 3, seed=6)
+    q.edges.append((0, 0, 2, 0))      # R.x = T.x is implied; it becomes a closing edge
+    plan, tup = run_and_compare(q, seed=2)
+    assert tup.shape[0] == 100 * 27
 
 
 def test_config1_full_scale():
