@@ -99,8 +99,15 @@ typedef struct {
 } sj_opts;
 
 /* Record a HIP event pair around every launch group on the context's stream
- * (costs a few microseconds per group); read with sj_profile_*(). */
+ * (costs a few microseconds per group); read with sj_profile_*(). Implies
+ * SJ_FLAG_EAGER. */
 #define SJ_FLAG_PROFILE 1u
+/* Launch every kernel of sj_build_filters, sj_sieve and sj_join one by one. By
+ * default the first call of each of these on a plan records its launches into a
+ * HIP graph (on a private stream of the plan) and every call replays that graph on
+ * the context's stream; the launches and their arguments are the same either way,
+ * and so are the results. sj_bind_workspace drops the recorded graphs. */
+#define SJ_FLAG_EAGER 2u
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
  * (a hipStream_t; NULL = the null stream). The stream stays caller-owned. */

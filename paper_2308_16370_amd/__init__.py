@@ -46,6 +46,7 @@ EXPORTED = ["sj_ctx_create", "sj_ctx_set_stream", "sj_ctx_destroy", "sj_last_err
             "sj_filter_count", "sj_filter_desc", "sj_filter_copy", "sj_survivors_copy", "sj_profile_collect",
             "sj_profile_count", "sj_profile_entry", "sj_profile_reset"]
 SJ_FLAG_PROFILE = 1
+SJ_FLAG_EAGER = 2
 
 
 class SjError(RuntimeError):
@@ -160,7 +161,8 @@ class Plan:
 
     def __init__(self, ctx: Context, rels: Sequence[Rel], edges: Sequence[Tuple[int, int, int, int]],
                  bits_per_key: int = 0, k: int = 0, block_bits: int = 0, passes: int = 0, seed: int = 0,
-                 root: int = -1, workspace: Optional[torch.Tensor] = None, profile: bool = False):
+                 root: int = -1, workspace: Optional[torch.Tensor] = None, profile: bool = False,
+                 eager: bool = False):
         self.ctx = ctx
         self.block_bits = block_bits or 512
         self.nrels = len(rels)
@@ -183,7 +185,7 @@ class Plan:
                 arr[i].pred_col, arr[i].pred_lo, arr[i].pred_hi = (int(x) for x in r.pred)
         earr = (_Edge * max(1, len(edges)))(*[_Edge(*[int(x) for x in e]) for e in edges])
         opts = _Opts(bits_per_key, k, block_bits, passes, seed & (2**64 - 1), root,
-                     SJ_FLAG_PROFILE if profile else 0)
+                     (SJ_FLAG_PROFILE if profile else 0) | (SJ_FLAG_EAGER if eager else 0))
         wsb = ctypes.c_uint64()
         ctx._check(lib().sj_plan(ctx.handle, arr, len(rels), earr, len(edges), ctypes.byref(opts),
                                  ctypes.byref(self.handle), ctypes.byref(wsb)))

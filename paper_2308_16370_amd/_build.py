@@ -16,13 +16,15 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source (in parallel) and link the shared library; returns its path."""
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile every source (in parallel) and link the shared library; returns its path.
+
+    ``defines`` are extra ``-D`` tuning macros (the defaults are the tuned values)."""
     with tempfile.TemporaryDirectory(prefix="sjbuild") as tmp:
         def compile_one(src):
             obj = os.path.join(tmp, os.path.splitext(src)[0] + ".o")
             lang = ["-x", "hip"] if src.endswith(".cpp") else []
-            cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [HIPCC, *FLAGS, *["-D" + d for d in defines], *lang, "-c", os.path.join(CSRC, src), "-o", obj]
             r = subprocess.run(cmd, capture_output=True, text=True)
             if r.returncode != 0:
                 raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr[-4000:]))
@@ -32,13 +34,13 @@ def build(verbose: bool = False) -> str:
 
         with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
             objs = list(ex.map(compile_one, SOURCES))
-        out_tmp = LIB + ".tmp%d" % os.getpid()
+        out_tmp = out + ".tmp%d" % os.getpid()
         cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out_tmp, *objs]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("link failed:\n%s" % r.stderr[-4000:])
-        os.replace(out_tmp, LIB)
-    return LIB
+        os.replace(out_tmp, out)
+    return out
 
 
 if __name__ == "__main__":

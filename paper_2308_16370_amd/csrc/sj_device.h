@@ -179,6 +179,45 @@ __device__ __forceinline__ uint32_t lookback32(uint64_t *status, uint32_t tile, 
     return excl;
 }
 
+// The same protocol run by a whole wave: each step reads the 64 preceding status
+// words at once and stops at the nearest inclusive prefix, so a tile waits for at
+// most ceil(distance / 64) rounds instead of one round per predecessor. Called by all
+// 64 lanes of one wave; returns the exclusive prefix in every lane.
+__device__ __forceinline__ uint32_t lookback32_wave(uint64_t *status, uint32_t tile, uint32_t agg) {
+    constexpr uint64_t kAgg = 1ull << 32, kIncl = 2ull << 32;
+    const int lane = lane_id();
+    if (tile == 0) {
+        if (lane == 0) __hip_atomic_store(status, kIncl | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return 0;
+    }
+    if (lane == 0) __hip_atomic_store(status + tile, kAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t excl = 0;
+    int64_t j = static_cast<int64_t>(tile) - 1;   // this round reads tiles j, j-1, ..., j-63
+    while (true) {
+        const int64_t idx = j - lane;
+        const uint64_t s =
+            idx >= 0 ? __hip_atomic_load(status + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kIncl;
+        const uint32_t f = static_cast<uint32_t>(s >> 32);
+        const uint64_t incl = __ballot(f == 2);
+        const uint64_t empty = __ballot(f == 0);
+        const int first = incl ? __ffsll(static_cast<long long>(incl)) - 1 : 64;   // nearest inclusive prefix
+        const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1ull);        // lanes 0 .. first
+        if (empty & need) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        uint32_t v = lane <= first ? static_cast<uint32_t>(s) : 0u;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) v += static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), d, 64));
+        excl += v;
+        if (first < 64) break;
+        j -= 64;
+    }
+    if (lane == 0)
+        __hip_atomic_store(status + tile, kIncl | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return excl;
+}
+
 // ---- hash index over a bucketed relation's distinct keys ------------------------
 // Slot word: ((dir + 1) << 32) | key; 0 marks an empty slot (dir + 1 >= 1).
 

@@ -15,6 +15,7 @@ constexpr int kMaxK = 12;       // bits per key
 constexpr int kSieveBlock = 256;
 constexpr int kSieveItems = 8;
 constexpr int kSieveTile = kSieveBlock * kSieveItems;
+constexpr uint32_t kSieveGrid = 1024;   // workgroups of a sieve scan; workgroup b owns a contiguous run of tiles
 
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;
@@ -57,7 +58,8 @@ struct StepArgs {
     uint32_t *out_rid;         // nullptr: no survivor list is written
     int32_t *out_col[kMaxJCols];
     uint32_t *out_count;       // device-side survivor count (written when out_rid != nullptr)
-    Lookback lb;
+    uint8_t *bits;             // [ceil(rows / 8)] survivor flags of the scan, 8 rows per byte
+    uint32_t *counts;          // [kSieveGrid] survivors per workgroup
     uint32_t seed;
     int k;
     int logB;
@@ -72,8 +74,16 @@ hipError_t launch_sieve_step(const StepArgs &a, uint32_t max_rows, hipStream_t s
 // Partitioned build of one filter from a key column (full column with an optional
 // predicate, or a survivor-list column with a device-side length).
 constexpr int kBuildBlock = 256;
-constexpr int kBuildTile = kBuildBlock * 64;
-constexpr uint32_t kRegionBytes = 32 * 1024;   // LDS per region workgroup
+// A build tile holds tile_of(n) keys: at least kBuildTileMin, and few enough that at
+// most kBuildMaxTiles tiles cover the input (keeps the (region, tile) table small).
+constexpr uint32_t kBuildTileMin = kBuildBlock * 8;
+constexpr uint32_t kBuildMaxTiles = 2048;
+__host__ __device__ inline uint32_t build_tile_of(uint32_t n) {
+    const uint32_t per = (n + kBuildMaxTiles - 1) / kBuildMaxTiles;
+    const uint32_t t = (per + kBuildTileMin - 1) / kBuildTileMin * kBuildTileMin;
+    return t > kBuildTileMin ? t : kBuildTileMin;
+}
+constexpr uint32_t kRegionBytes = 16 * 1024;   // LDS per region workgroup
 constexpr int kRegionThreads = 512;
 struct BuildArgs {
     const int32_t *keys;
@@ -89,9 +99,8 @@ struct BuildArgs {
     uint32_t nblocks_max;
     uint32_t region_blocks;    // kRegionBytes / (block bytes)
     uint32_t *hist;            // [regions * tiles] counts, then their exclusive prefix
-    uint64_t *keep;            // [tiles * kBuildTile / 64] bit e: element e is staged
-    uint32_t *stage_block;     // [n_max] staged keys: block index
-    uint32_t *stage_g;         // [n_max] staged keys: second hash word
+    uint64_t *keep;            // [(n_max + tile) / 64] bit e: element e is staged
+    uint2 *stage;              // [n_max] staged keys: (block index, second hash word)
     uint32_t *total_dev;       // number of staged keys (zeroed before)
     Lookback lb;               // scan state (zeroed before)
     uint32_t seed;

@@ -146,7 +146,10 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_u32(uint32_t *data, const u
         }
         uint32_t tot;
         uint32_t off = block_excl_scan<kScanBlock>(sum, s_wave, tot);
-        if (threadIdx.x == 0) s_base = lookback32(lb.status, tile, tot);
+        if (threadIdx.x < 64) {
+            const uint32_t b = lookback32_wave(lb.status, tile, tot);
+            if (threadIdx.x == 0) s_base = b;
+        }
         __syncthreads();
         off += s_base;
 #pragma unroll
@@ -263,7 +266,10 @@ __global__ __launch_bounds__(kSieveBlock) void k_dir_heads(Buckets b, Lookback l
         }
         uint32_t tot;
         const uint32_t off = block_excl_scan<kSieveBlock>(static_cast<uint32_t>(__builtin_popcount(flags)), s_wave, tot);
-        if (threadIdx.x == 0) s_base = lookback32(lb.status, tile, tot);
+        if (threadIdx.x < 64) {
+            const uint32_t b = lookback32_wave(lb.status, tile, tot);
+            if (threadIdx.x == 0) s_base = b;
+        }
         __syncthreads();
         uint32_t o = s_base + off;
 #pragma unroll
@@ -325,11 +331,12 @@ hipError_t launch_build_buckets(const uint32_t *list_rid, const int32_t *const *
     const int npasses = sec_col >= 0 ? 8 : 4;
     const uint32_t tiles = (cap + kRadixTile - 1) / kRadixTile;
     const uint32_t tgrid = tiles < kPersistentBlocks ? tiles : kPersistentBlocks;
-    hipLaunchKernelGGL(k_radix_ghist, dim3(grid_for(cap, 256 * 16, 1024)), dim3(kRadixBlock), 0, s, ks,
+    // few workgroups: every workgroup adds its histogram to the same 256 x passes counters
+    hipLaunchKernelGGL(k_radix_ghist, dim3(grid_for(cap, 256 * 16, 128)), dim3(kRadixBlock), 0, s, ks,
                        list_count, ss.ghist);
     hipLaunchKernelGGL(k_radix_ctl, dim3(1), dim3(256), 0, s, ss.ghist, list_count, npasses, ss.ctl);
     const uint32_t scan_len_max = kRadixBins * tiles;
-    const uint32_t scan_grid = grid_for(scan_len_max, kScanTile, kPersistentBlocks);
+    const uint32_t scan_grid = grid_for(scan_len_max, kScanTile, 256);
     for (int p = 0; p < npasses; ++p) {
         hipLaunchKernelGGL(k_radix_hist, dim3(tgrid), dim3(kRadixBlock), 0, s, p, ks, ss, list_count);
         hipLaunchKernelGGL(k_scan_u32, dim3(scan_grid), dim3(kScanBlock), 0, s, ss.hist, list_count,
@@ -341,7 +348,7 @@ hipError_t launch_build_buckets(const uint32_t *list_rid, const int32_t *const *
     l.ncol = ncol;
     for (int c = 0; c < kMaxJCols; ++c) l.col[c] = c < ncol ? list_cols[c] : nullptr;
     hipLaunchKernelGGL(k_gather, dim3(grid_for(cap, 256 * 4, 4096)), dim3(256), 0, s, l, list_count, ss, b);
-    const uint32_t dgrid = grid_for(cap, kSieveTile, kPersistentBlocks);
+    const uint32_t dgrid = grid_for(cap, kSieveTile, 256);   // each workgroup claims tiles from one counter
     hipLaunchKernelGGL(k_dir_heads, dim3(dgrid), dim3(kSieveBlock), 0, s, b, lb_dir);
     hipLaunchKernelGGL(k_dir_mask, dim3(1), dim3(64), 0, s, b);
     hipLaunchKernelGGL(k_slots_clear, dim3(grid_for(b.slot_cap, 256 * 8, 4096)), dim3(256), 0, s, b);

@@ -30,8 +30,9 @@ hipError_t launch_zero(void *p, uint64_t bytes, hipStream_t s) {
 }
 
 // ---- number of rows passing lo <= v < hi -----------------------------------------
-__global__ void k_count_pred(const int32_t *__restrict__ col, uint32_t n, int32_t lo, int32_t hi,
-                             uint32_t *out) {
+__global__ __launch_bounds__(256) void k_count_pred(const int32_t *__restrict__ col, uint32_t n, int32_t lo,
+                                                    int32_t hi, uint32_t *out) {
+    __shared__ uint32_t s_w[4];
     uint32_t c = 0;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -40,63 +41,81 @@ __global__ void k_count_pred(const int32_t *__restrict__ col, uint32_t n, int32_
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
-    if (lane_id() == 0 && c) atomicAdd(out, c);
+    if (lane_id() == 0) s_w[threadIdx.x >> 6] = c;
+    __syncthreads();
+    // one atomic per workgroup: atomics on one address serialise device-wide
+    if (threadIdx.x == 0) {
+        const uint32_t t = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        if (t) atomicAdd(out, t);
+    }
 }
 
 hipError_t launch_count_pred(const int32_t *col, uint32_t n, int32_t lo, int32_t hi, uint32_t *out,
                              hipStream_t s) {
     if (n == 0) return hipSuccess;
     uint32_t blocks = (n + 256 * 16 - 1) / (256 * 16);
-    if (blocks > 2048) blocks = 2048;
+    if (blocks > 256) blocks = 256;
     hipLaunchKernelGGL(k_count_pred, dim3(blocks), dim3(256), 0, s, col, n, lo, hi, out);
     return hipGetLastError();
 }
 
 // ---- the sieve step ------------------------------------------------------------------
-// Persistent blocks take tiles of kSieveTile consecutive rows in order. Thread t of a
-// tile owns rows [t * kSieveItems, (t + 1) * kSieveItems) of it, so its survivors are
-// contiguous in row order; one block-wide exclusive scan of the per-thread counts plus
-// the tile's look-back prefix places every survivor.
+// Two passes with no inter-workgroup waiting. Workgroup b of kSieveGrid owns the rows
+// [b * R, (b + 1) * R), R a multiple of kSieveTile. (1) k_sieve_step probes every row
+// and records a survivor bit per row and a survivor count per workgroup. (2)
+// k_sieve_compact sums the counts of the workgroups before it and writes its survivors
+// (row id and join columns, ascending row order) from the bits. (A single pass with a
+// dynamic tile counter and look-back would put thousands of same-address atomics, about
+// 11 ns each on MI355X and serialised, on the critical path.)
 //
 // A probe touches one filter block: the k words of all items of a batch are loaded
 // before any is tested, so a thread keeps many independent loads in flight.
 // Zipf-skewed columns repeat a few keys very often: each block keeps a direct-mapped
 // LDS cache key -> contains(key) per probed filter (the first kMaxCached of them);
 // the filter is read-only during the scan, so a cached answer is exact.
-constexpr int kMaxCached = 4;
-constexpr int kCacheLog = 10;
+#ifndef SJ_MAX_CACHED
+#define SJ_MAX_CACHED 4
+#endif
+#ifndef SJ_CACHE_LOG
+#define SJ_CACHE_LOG 10
+#endif
+#ifndef SJ_PROBE_BATCH
+#define SJ_PROBE_BATCH 4
+#endif
+constexpr int kMaxCached = SJ_MAX_CACHED;
+constexpr int kCacheLog = SJ_CACHE_LOG;
 constexpr uint32_t kCacheValid = 0x80000000u;
-constexpr int kProbeBatch = 4;
+constexpr int kProbeBatch = SJ_PROBE_BATCH;
 
 __device__ __forceinline__ uint32_t cache_slot(int32_t key) {
     return (static_cast<uint32_t>(key) * 0x9E3779B1u) >> (32 - kCacheLog);
 }
 
+__device__ __forceinline__ uint32_t sieve_rows_per_group(uint32_t n) {
+    const uint32_t per = (n + kSieveGrid - 1) / kSieveGrid;
+    return (per + kSieveTile - 1) / kSieveTile * kSieveTile;
+}
+
 template <int NCOL, int KMAX>
 __global__ __launch_bounds__(kSieveBlock) void k_sieve_step(StepArgs a) {
-    __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_base;
     __shared__ uint32_t s_wave[kSieveBlock / 64];
-    __shared__ uint64_t s_cache[kMaxCached][1 << kCacheLog];
+    __shared__ uint64_t s_cache[kMaxCached > 0 ? kMaxCached : 1][1 << kCacheLog];
     for (int i = threadIdx.x; i < kMaxCached * (1 << kCacheLog); i += kSieveBlock) (&s_cache[0][0])[i] = 0;
     __syncthreads();
 
     const bool list = a.src_rid != nullptr;
     const uint32_t n = list ? *a.src_count : a.src_rows;
-    const uint32_t ntiles = (n + kSieveTile - 1) / kSieveTile;
+    const uint32_t per = sieve_rows_per_group(n);
+    const uint32_t r_end = min(n, (blockIdx.x + 1) * per);
     const int tid = threadIdx.x;
+    uint32_t survivors = 0;
     const uint32_t wpb_shift = static_cast<uint32_t>(a.logB) - 5u;   // words per block = 1 << wpb_shift
     const uint32_t sh = 32u - static_cast<uint32_t>(a.logB);
 
-    while (true) {
-        if (tid == 0) s_tile = atomicAdd(a.lb.counter, 1u);
-        __syncthreads();
-        const uint32_t tile = s_tile;
-        if (tile >= ntiles) break;
-        const uint32_t row0 = tile * kSieveTile + tid * kSieveItems;
+    for (uint32_t t0 = blockIdx.x * per; t0 < r_end; t0 += kSieveTile) {
+        const uint32_t row0 = t0 + tid * kSieveItems;
 
         int32_t v[NCOL][kSieveItems];
-        uint32_t rid[kSieveItems];
         const bool full = row0 + kSieveItems <= n;
         if (full) {
 #pragma unroll
@@ -107,16 +126,6 @@ __global__ __launch_bounds__(kSieveBlock) void k_sieve_step(StepArgs a) {
                 v[c][0] = x0.x; v[c][1] = x0.y; v[c][2] = x0.z; v[c][3] = x0.w;
                 v[c][4] = x1.x; v[c][5] = x1.y; v[c][6] = x1.z; v[c][7] = x1.w;
             }
-            if (list) {
-                const v4u *src = reinterpret_cast<const v4u *>(a.src_rid + row0);
-                const v4u r0 = __builtin_nontemporal_load(src);
-                const v4u r1 = __builtin_nontemporal_load(src + 1);
-                rid[0] = r0.x; rid[1] = r0.y; rid[2] = r0.z; rid[3] = r0.w;
-                rid[4] = r1.x; rid[5] = r1.y; rid[6] = r1.z; rid[7] = r1.w;
-            } else {
-#pragma unroll
-                for (int i = 0; i < kSieveItems; ++i) rid[i] = row0 + i;
-            }
         } else {
 #pragma unroll
             for (int i = 0; i < kSieveItems; ++i) {
@@ -124,7 +133,6 @@ __global__ __launch_bounds__(kSieveBlock) void k_sieve_step(StepArgs a) {
                 const bool in = r < n;
 #pragma unroll
                 for (int c = 0; c < NCOL; ++c) v[c][i] = in ? a.col[c][r] : 0;
-                rid[i] = in ? (list ? a.src_rid[r] : r) : 0u;
             }
         }
 
@@ -206,39 +214,90 @@ __global__ __launch_bounds__(kSieveBlock) void k_sieve_step(StepArgs a) {
             }
         }
 
-        if (a.out_rid) {
-            const uint32_t cnt = __builtin_popcount(flags);
-            uint32_t tot;
-            const uint32_t off = block_excl_scan<kSieveBlock>(cnt, s_wave, tot);
-            if (tid == 0) s_base = lookback32(a.lb.status, tile, tot);
-            __syncthreads();
-            uint32_t o = s_base + off;
-            if (tile == ntiles - 1 && tid == 0) *a.out_count = s_base + tot;
+        if (row0 < n) a.bits[row0 >> 3] = static_cast<uint8_t>(flags);
+        survivors += __builtin_popcount(flags);
+    }
+    uint32_t tot;
+    block_excl_scan<kSieveBlock>(survivors, s_wave, tot);
+    if (tid == 0) a.counts[blockIdx.x] = tot;
+}
+
+
+// Survivors of workgroup b's rows, written after those of workgroups 0 .. b-1.
+template <int NCOL>
+__global__ __launch_bounds__(kSieveBlock) void k_sieve_compact(StepArgs a) {
+    __shared__ uint32_t s_wave[kSieveBlock / 64];
+    const bool list = a.src_rid != nullptr;
+    const uint32_t n = list ? *a.src_count : a.src_rows;
+    const uint32_t per = sieve_rows_per_group(n);
+    const int tid = threadIdx.x;
+    uint32_t before = 0;
+    for (uint32_t g = tid; g < blockIdx.x; g += kSieveBlock) before += a.counts[g];
+    uint32_t tot;
+    block_excl_scan<kSieveBlock>(before, s_wave, tot);
+    uint32_t base = tot;
+    if (blockIdx.x == gridDim.x - 1 && tid == 0) *a.out_count = base + a.counts[blockIdx.x];
+    const uint32_t r_end = min(n, (blockIdx.x + 1) * per);
+    for (uint32_t t0 = blockIdx.x * per; t0 < r_end; t0 += kSieveTile) {
+        const uint32_t row0 = t0 + tid * kSieveItems;
+        const uint32_t flags = row0 < n ? a.bits[row0 >> 3] : 0u;
+        uint32_t ttot;
+        uint32_t o = base + block_excl_scan<kSieveBlock>(static_cast<uint32_t>(__builtin_popcount(flags)), s_wave, ttot);
+        base += ttot;
+        if (!flags) continue;
+        int32_t v[NCOL][kSieveItems];
+        uint32_t rid[kSieveItems];
+        if (row0 + kSieveItems <= n) {
+#pragma unroll
+            for (int c = 0; c < NCOL; ++c) {
+                const v4i *src = reinterpret_cast<const v4i *>(a.col[c] + row0);
+                const v4i x0 = src[0], x1 = src[1];
+                v[c][0] = x0.x; v[c][1] = x0.y; v[c][2] = x0.z; v[c][3] = x0.w;
+                v[c][4] = x1.x; v[c][5] = x1.y; v[c][6] = x1.z; v[c][7] = x1.w;
+            }
+            if (list) {
+                const v4u *src = reinterpret_cast<const v4u *>(a.src_rid + row0);
+                const v4u r0 = src[0], r1 = src[1];
+                rid[0] = r0.x; rid[1] = r0.y; rid[2] = r0.z; rid[3] = r0.w;
+                rid[4] = r1.x; rid[5] = r1.y; rid[6] = r1.z; rid[7] = r1.w;
+            } else {
+#pragma unroll
+                for (int i = 0; i < kSieveItems; ++i) rid[i] = row0 + i;
+            }
+        } else {
 #pragma unroll
             for (int i = 0; i < kSieveItems; ++i) {
-                if (flags & (1u << i)) {
-                    a.out_rid[o] = rid[i];
+                const uint32_t r = row0 + i;
+                const bool in = r < n;
 #pragma unroll
-                    for (int c = 0; c < NCOL; ++c) a.out_col[c][o] = v[c][i];
-                    ++o;
-                }
+                for (int c = 0; c < NCOL; ++c) v[c][i] = in ? a.col[c][r] : 0;
+                rid[i] = in ? (list ? a.src_rid[r] : r) : 0u;
             }
         }
-        __syncthreads();   // s_tile / s_base / s_wave are rewritten by the next tile
+#pragma unroll
+        for (int i = 0; i < kSieveItems; ++i) {
+            if (flags & (1u << i)) {
+                a.out_rid[o] = rid[i];
+#pragma unroll
+                for (int c = 0; c < NCOL; ++c) a.out_col[c][o] = v[c][i];
+                ++o;
+            }
+        }
     }
 }
 
 template <int KMAX>
-static hipError_t launch_sieve_k(const StepArgs &a, dim3 g, hipStream_t s) {
+static hipError_t launch_sieve_k(const StepArgs &a, hipStream_t s) {
+    const dim3 g(kSieveGrid), b(kSieveBlock);
     switch (a.ncol) {
-        case 1: hipLaunchKernelGGL((k_sieve_step<1, KMAX>), g, dim3(kSieveBlock), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_sieve_step<2, KMAX>), g, dim3(kSieveBlock), 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_sieve_step<3, KMAX>), g, dim3(kSieveBlock), 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_sieve_step<4, KMAX>), g, dim3(kSieveBlock), 0, s, a); break;
-        case 5: hipLaunchKernelGGL((k_sieve_step<5, KMAX>), g, dim3(kSieveBlock), 0, s, a); break;
-        case 6: hipLaunchKernelGGL((k_sieve_step<6, KMAX>), g, dim3(kSieveBlock), 0, s, a); break;
-        case 7: hipLaunchKernelGGL((k_sieve_step<7, KMAX>), g, dim3(kSieveBlock), 0, s, a); break;
-        case 8: hipLaunchKernelGGL((k_sieve_step<8, KMAX>), g, dim3(kSieveBlock), 0, s, a); break;
+#define SJ_SIEVE_CASE(NC)                                                             \
+    case NC:                                                                          \
+        hipLaunchKernelGGL((k_sieve_step<NC, KMAX>), g, b, 0, s, a);                  \
+        if (a.out_rid) hipLaunchKernelGGL((k_sieve_compact<NC>), g, b, 0, s, a);      \
+        break;
+        SJ_SIEVE_CASE(1) SJ_SIEVE_CASE(2) SJ_SIEVE_CASE(3) SJ_SIEVE_CASE(4)
+        SJ_SIEVE_CASE(5) SJ_SIEVE_CASE(6) SJ_SIEVE_CASE(7) SJ_SIEVE_CASE(8)
+#undef SJ_SIEVE_CASE
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -246,11 +305,7 @@ static hipError_t launch_sieve_k(const StepArgs &a, dim3 g, hipStream_t s) {
 
 hipError_t launch_sieve_step(const StepArgs &a, uint32_t max_rows, hipStream_t s) {
     if (max_rows == 0) return hipSuccess;
-    // persistent blocks: as many as fit at once (the LDS caches allow 4 blocks per CU)
-    constexpr uint32_t kSieveGrid = 256 * 4;
-    const uint32_t tiles = (max_rows + kSieveTile - 1) / kSieveTile;
-    const dim3 g(tiles < kSieveGrid ? tiles : kSieveGrid);
-    return a.k <= 8 ? launch_sieve_k<8>(a, g, s) : launch_sieve_k<kMaxK>(a, g, s);
+    return a.k <= 8 ? launch_sieve_k<8>(a, s) : launch_sieve_k<kMaxK>(a, s);
 }
 
 // ---- partitioned filter build ----------------------------------------------------------
@@ -273,7 +328,7 @@ __device__ __forceinline__ bool bfb_take(const BuildArgs &a, uint32_t e, int32_t
 }
 
 struct BfbShape {
-    uint32_t n, nb, nreg, ntiles;
+    uint32_t n, nb, nreg, tile, ntiles;
 };
 
 __device__ __forceinline__ BfbShape bfb_shape(const BuildArgs &a) {
@@ -285,7 +340,8 @@ __device__ __forceinline__ BfbShape bfb_shape(const BuildArgs &a) {
     uint64_t nb = (nkeys * a.bits_per_key + B - 1) / B;
     s.nb = nb ? static_cast<uint32_t>(nb) : 1u;
     s.nreg = (s.nb + a.region_blocks - 1) / a.region_blocks;
-    s.ntiles = (s.n + kBuildTile - 1) / kBuildTile;
+    s.tile = build_tile_of(s.n);
+    s.ntiles = (s.n + s.tile - 1) / s.tile;
     return s;
 }
 
@@ -295,6 +351,8 @@ __device__ __forceinline__ BfbShape bfb_shape(const BuildArgs &a) {
 // is recorded in a bitmap (bit e: element e is staged) that the scatter pass follows,
 // so both passes agree whatever the order the cache updates landed in.
 constexpr int kDedupLog = 11;
+
+constexpr int kBuildBatch = 8;   // elements per thread whose loads are issued together
 
 __global__ __launch_bounds__(kBuildBlock) void k_bfb_hist(BuildArgs a) {
     extern __shared__ uint32_t s_hist[];   // [nreg]
@@ -306,23 +364,36 @@ __global__ __launch_bounds__(kBuildBlock) void k_bfb_hist(BuildArgs a) {
         for (uint32_t r = threadIdx.x; r < sh.nreg; r += kBuildBlock) s_hist[r] = 0;
         for (uint32_t i = threadIdx.x; i < (1u << kDedupLog); i += kBuildBlock) s_seen_ok[i] = 0;
         __syncthreads();
-        const uint32_t t0 = tile * kBuildTile;
-        for (uint32_t j = 0; j < kBuildTile; j += kBuildBlock) {
-            const uint32_t e = t0 + j + threadIdx.x;
-            bool keep = false;
-            int32_t key = 0;
-            if (e < sh.n && bfb_take(a, e, key)) {
-                const uint32_t slot = (static_cast<uint32_t>(key) * 0x9E3779B1u) >> (32 - kDedupLog);
-                keep = !(s_seen_ok[slot] && s_seen[slot] == static_cast<uint32_t>(key));
-                if (keep) {
-                    s_seen[slot] = static_cast<uint32_t>(key);
-                    s_seen_ok[slot] = 1;
-                    const BfKey h = bf_hash(key, a.seed, sh.nb);
-                    atomicAdd(&s_hist[h.block / a.region_blocks], 1u);
+        const uint32_t t0 = tile * sh.tile;
+        for (uint32_t j0 = 0; j0 < sh.tile; j0 += kBuildBlock * kBuildBatch) {
+            int32_t key[kBuildBatch];
+            bool take[kBuildBatch];
+#pragma unroll
+            for (int u = 0; u < kBuildBatch; ++u) {
+                const uint32_t e = t0 + j0 + u * kBuildBlock + threadIdx.x;
+                take[u] = e < sh.n;
+                key[u] = take[u] ? a.keys[e] : 0;
+                if (take[u] && a.pred) {
+                    const int32_t pv = a.pred[e];
+                    take[u] = pv >= a.pred_lo && pv < a.pred_hi;
                 }
             }
-            const uint64_t m = __ballot(keep);
-            if (lane_id() == 0) a.keep[(t0 + j + threadIdx.x) >> 6] = m;
+#pragma unroll
+            for (int u = 0; u < kBuildBatch; ++u) {
+                bool keep = false;
+                if (take[u]) {
+                    const uint32_t slot = (static_cast<uint32_t>(key[u]) * 0x9E3779B1u) >> (32 - kDedupLog);
+                    keep = !(s_seen_ok[slot] && s_seen[slot] == static_cast<uint32_t>(key[u]));
+                    if (keep) {
+                        s_seen[slot] = static_cast<uint32_t>(key[u]);
+                        s_seen_ok[slot] = 1;
+                        const BfKey h = bf_hash(key[u], a.seed, sh.nb);
+                        atomicAdd(&s_hist[h.block / a.region_blocks], 1u);
+                    }
+                }
+                const uint64_t m = __ballot(keep);
+                if (lane_id() == 0) a.keep[(t0 + j0 + u * kBuildBlock + threadIdx.x) >> 6] = m;
+            }
         }
         __syncthreads();
         for (uint32_t r = threadIdx.x; r < sh.nreg; r += kBuildBlock) a.hist[r * sh.ntiles + tile] = s_hist[r];
@@ -353,7 +424,10 @@ __global__ __launch_bounds__(kScanBlock) void k_bfb_scan(BuildArgs a) {
         }
         uint32_t tot;
         uint32_t off = block_excl_scan<kScanBlock>(sum, s_wave, tot);
-        if (threadIdx.x == 0) s_base = lookback32(a.lb.status, tile, tot);
+        if (threadIdx.x < 64) {
+            const uint32_t b = lookback32_wave(a.lb.status, tile, tot);
+            if (threadIdx.x == 0) s_base = b;
+        }
         __syncthreads();
         if (tile == ntiles - 1 && threadIdx.x == 0) *a.total_dev = s_base + tot;
         off += s_base;
@@ -372,15 +446,24 @@ __global__ __launch_bounds__(kBuildBlock) void k_bfb_scatter(BuildArgs a) {
     for (uint32_t tile = blockIdx.x; tile < sh.ntiles; tile += gridDim.x) {
         for (uint32_t r = threadIdx.x; r < sh.nreg; r += kBuildBlock) s_off[r] = a.hist[r * sh.ntiles + tile];
         __syncthreads();
-        const uint32_t t0 = tile * kBuildTile;
-        for (uint32_t j = 0; j < kBuildTile; j += kBuildBlock) {
-            const uint32_t e = t0 + j + threadIdx.x;
-            const uint64_t m = a.keep[e >> 6];
-            if (e < sh.n && ((m >> (e & 63)) & 1ull)) {
-                const BfKey h = bf_hash(a.keys[e], a.seed, sh.nb);
-                const uint32_t pos = atomicAdd(&s_off[h.block / a.region_blocks], 1u);
-                a.stage_block[pos] = h.block;
-                a.stage_g[pos] = h.g;
+        const uint32_t t0 = tile * sh.tile;
+        for (uint32_t j0 = 0; j0 < sh.tile; j0 += kBuildBlock * kBuildBatch) {
+            int32_t key[kBuildBatch];
+            bool take[kBuildBatch];
+#pragma unroll
+            for (int u = 0; u < kBuildBatch; ++u) {
+                const uint32_t e = t0 + j0 + u * kBuildBlock + threadIdx.x;
+                const uint64_t m = a.keep[e >> 6];
+                take[u] = e < sh.n && ((m >> (e & 63)) & 1ull);
+                key[u] = take[u] ? a.keys[e] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kBuildBatch; ++u) {
+                if (take[u]) {
+                    const BfKey h = bf_hash(key[u], a.seed, sh.nb);
+                    const uint32_t pos = atomicAdd(&s_off[h.block / a.region_blocks], 1u);
+                    a.stage[pos] = make_uint2(h.block, h.g);
+                }
             }
         }
         __syncthreads();
@@ -407,19 +490,32 @@ __global__ __launch_bounds__(kRegionThreads) void k_bfb_region(BuildArgs a) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint32_t e = e0 + u * kRegionThreads;
-                bb[u] = e < end ? a.stage_block[e] - b0 : 0xFFFFFFFFu;
-                gg[u] = e < end ? a.stage_g[e] : 0u;
+                const uint2 st = e < end ? a.stage[e] : make_uint2(0u, 0u);
+                bb[u] = e < end ? st.x - b0 : 0xFFFFFFFFu;
+                gg[u] = st.y;
+            }
+            // read every word the batch touches first, then OR only the bits still clear:
+            // heavy-hitter keys staged by many tiles find their bits set and cost no atomic
+            uint32_t w[U][kMaxK];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (bb[u] != 0xFFFFFFFFu) {
+                    const uint32_t *wb = s_words + (bb[u] << wpb_shift);
+#pragma unroll
+                    for (int j = 0; j < kMaxK; ++j)
+                        if (j < a.k) w[u][j] = wb[((gg[u] * bf_mult(j)) >> hs) >> 5];
+                }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (bb[u] != 0xFFFFFFFFu) {
-                    uint32_t *w = s_words + (bb[u] << wpb_shift);
+                    uint32_t *wb = s_words + (bb[u] << wpb_shift);
 #pragma unroll
                     for (int j = 0; j < kMaxK; ++j) {
                         if (j < a.k) {
                             const uint32_t p = (gg[u] * bf_mult(j)) >> hs;
                             const uint32_t bit = 1u << (p & 31u);
-                            if (!(w[p >> 5] & bit)) atomicOr(w + (p >> 5), bit);
+                            if (!(w[u][j] & bit)) atomicOr(wb + (p >> 5), bit);
                         }
                     }
                 }
@@ -433,14 +529,15 @@ __global__ __launch_bounds__(kRegionThreads) void k_bfb_region(BuildArgs a) {
 }
 
 hipError_t launch_filter_build(const BuildArgs &a, hipStream_t s) {
-    const uint32_t ntiles_max = (a.n_max + kBuildTile - 1) / kBuildTile;
+    const uint32_t ntiles_max = min(kBuildMaxTiles, (a.n_max + kBuildTileMin - 1) / kBuildTileMin);
     const uint32_t nreg_max = (a.nblocks_max + a.region_blocks - 1) / a.region_blocks;
     const size_t lds_hist = 4ull * (nreg_max ? nreg_max : 1);
     const size_t lds_region = 4ull * a.region_blocks * (1u << (a.logB - 5));
     const uint32_t tgrid = ntiles_max == 0 ? 1 : (ntiles_max < 2048 ? ntiles_max : 2048);
     hipLaunchKernelGGL(k_bfb_hist, dim3(tgrid), dim3(kBuildBlock), lds_hist, s, a);
+    // every workgroup claims at least one tile from a single counter: size the grid to the work
     const uint32_t scan_tiles = (nreg_max * ntiles_max + kScanTile - 1) / kScanTile;
-    const uint32_t sgrid = scan_tiles == 0 ? 1 : (scan_tiles < kPersistentBlocks ? scan_tiles : kPersistentBlocks);
+    const uint32_t sgrid = scan_tiles == 0 ? 1 : (scan_tiles < 256 ? scan_tiles : 256);
     hipLaunchKernelGGL(k_bfb_scan, dim3(sgrid), dim3(kScanBlock), 0, s, a);
     hipLaunchKernelGGL(k_bfb_scatter, dim3(tgrid), dim3(kBuildBlock), lds_hist, s, a);
     const uint32_t rgrid = nreg_max == 0 ? 1 : (nreg_max < 2048 ? nreg_max : 2048);

@@ -58,7 +58,7 @@ struct StepSpec {
     std::vector<std::pair<int, int>> probes;   // (jcol index, filter)
     std::vector<std::pair<int, int>> builds;
     int out = -1;              // list buffer written, -1: none
-    uint64_t off_status = 0, off_counter = 0, off_count = 0;
+    uint64_t off_count = 0;
     uint32_t max_rows = 0;
     std::vector<uint64_t> off_bstatus, off_bcounter, off_btotal;   // per build
 };
@@ -104,6 +104,7 @@ struct sj_plan_s {
     uint64_t off_elig = 0, off_nblocks = 0, off_totals = 0;
     uint32_t region_blocks = 0;
     uint64_t off_bhist = 0, off_stage[2] = {0, 0}, off_keep = 0;
+    uint64_t off_sbits = 0, off_scounts = 0;   // sieve scratch: survivor bits, per-workgroup counts
     std::vector<uint64_t> off_list[2];       // per relation: list buffer base
     // join phase
     struct JoinRel {
@@ -142,10 +143,28 @@ struct sj_plan_s {
         uint64_t bytes = 0;    // algorithmic bytes of the last launch, 0 if not modelled
     };
     std::vector<ProfAcc> prof_acc;
+    // Each launch phase (filter build, sieve, join count pass) is recorded once into a
+    // HIP graph on a private stream and replayed on the context's stream afterwards:
+    // every grid and argument is fixed once the workspace is bound, and the replay
+    // removes the host's per-launch cost between the many short kernels.
+    bool eager = false;                  // profiling plans and SJ_FLAG_EAGER launch one by one
+    hipStream_t ls = nullptr;            // stream the launch helpers enqueue on
+    hipStream_t cap_stream = nullptr;    // capture stream (created on first use)
+    hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
+    void drop_graphs();
     ~sj_plan_s();
 };
 
+void sj_plan_s::drop_graphs() {
+    for (auto &g : gexec) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
 sj_plan_s::~sj_plan_s() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto &r : prof_pending) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -399,8 +418,6 @@ static void build_layout(sj_plan_t *p) {
         for (auto &s : p->steps) {
             if (s.phase != ph) continue;
             s.max_rows = p->rels[s.rel].nrows;
-            s.off_status = L.take(8ull * std::max<uint32_t>(1, tiles_of(s.max_rows, kSieveTile)));
-            s.off_counter = L.take(4);
             s.off_count = L.take(4);
             s.off_bstatus.clear();
             s.off_bcounter.clear();
@@ -409,7 +426,8 @@ static void build_layout(sj_plan_t *p) {
                 const Filter &f = p->filters[b.second];
                 const uint64_t nbm = f.max_words / (p->opts.block_bits / 32);
                 const uint64_t nreg = (nbm + p->region_blocks - 1) / p->region_blocks;
-                const uint64_t hl = nreg * tiles_of(s.max_rows, kBuildTile);
+                // tiles of any input of up to max_rows keys (build_tile_of keeps them <= kBuildMaxTiles)
+                const uint64_t hl = nreg * std::min<uint32_t>(kBuildMaxTiles, tiles_of(s.max_rows, kBuildTileMin));
                 max_hist = std::max<uint64_t>(max_hist, hl);
                 max_build_rows = std::max(max_build_rows, s.max_rows);
                 s.off_bstatus.push_back(L.take(8ull * std::max<uint64_t>(1, (hl + kScanTile - 1) / kScanTile)));
@@ -420,10 +438,13 @@ static void build_layout(sj_plan_t *p) {
         p->zero[ph].end = L.top;
     }
     for (auto &f : p->filters) f.off = L.take(f.max_words * 4);
+    uint32_t max_rows = 1;
+    for (const Rel &R : p->rels) max_rows = std::max(max_rows, R.nrows);
+    p->off_sbits = L.take(max_rows / 8 + 16);
+    p->off_scounts = L.take(4ull * kSieveGrid);
     p->off_bhist = L.take(4 * max_hist);
-    p->off_stage[0] = L.take(4ull * std::max<uint32_t>(1, max_build_rows));
-    p->off_stage[1] = L.take(4ull * std::max<uint32_t>(1, max_build_rows));
-    p->off_keep = L.take(8ull * (tiles_of(std::max<uint32_t>(1, max_build_rows), kBuildTile) * (kBuildTile / 64)));
+    p->off_stage[0] = L.take(8ull * std::max<uint32_t>(1, max_build_rows));
+    p->off_keep = L.take(8ull * ((uint64_t(max_build_rows) + 2 * build_tile_of(max_build_rows)) / 64 + 1));
     p->zero[2].begin = L.top;
     p->off_totals = L.take(16);
     p->jr.assign(n, {});
@@ -515,7 +536,8 @@ extern "C" sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, con
         return fail(ctx, SJ_ERR_INVALID, "block_bits must be 256, 512 or 1024");
     if (o.passes != 1 && o.passes != 2) return fail(ctx, SJ_ERR_INVALID, "passes must be 1 or 2");
     if (o.root >= nrels) return fail(ctx, SJ_ERR_INVALID, "root out of range");
-    if (o.flags & ~static_cast<uint32_t>(SJ_FLAG_PROFILE)) return fail(ctx, SJ_ERR_INVALID, "unknown flags");
+    if (o.flags & ~static_cast<uint32_t>(SJ_FLAG_PROFILE | SJ_FLAG_EAGER))
+        return fail(ctx, SJ_ERR_INVALID, "unknown flags");
 
     sj_plan_t *p = new (std::nothrow) sj_plan_t;
     if (!p) return fail(ctx, SJ_ERR_INVALID, "out of host memory");
@@ -525,6 +547,7 @@ extern "C" sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, con
     p->logB = (o.block_bits == 256) ? 8 : (o.block_bits == 512 ? 9 : 10);
     p->root = o.root;
     p->profile = (o.flags & SJ_FLAG_PROFILE) != 0;
+    p->eager = p->profile || (o.flags & SJ_FLAG_EAGER) != 0;
     {   // 32-bit filter seed: the low word of SplitMix64's output function of the seed
         uint64_t z = o.seed;
         z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
@@ -631,6 +654,7 @@ extern "C" sj_status sj_bind_workspace(sj_plan_t *p, void *ws, uint64_t bytes) {
         return fail(p->ctx, SJ_ERR_NOMEM, "workspace has %llu bytes, plan needs %llu",
                     static_cast<unsigned long long>(bytes), static_cast<unsigned long long>(p->ws_bytes));
     p->ws = static_cast<char *>(ws);
+    p->drop_graphs();   // recorded launches point into the previous workspace
     p->state = kBound;
     return SJ_OK;
 }
@@ -696,7 +720,7 @@ static const char *rel_name(int r) {
 }
 
 static sj_status run_steps(sj_plan_t *p, int phase) {
-    hipStream_t s = p->ctx->stream;
+    hipStream_t s = p->ls;
     for (auto &st : p->steps) {
         if (st.phase != phase) continue;
         const Rel &R = p->rels[st.rel];
@@ -729,8 +753,8 @@ static sj_status run_steps(sj_plan_t *p, int phase) {
             for (int c = 0; c < a.ncol; ++c) a.out_col[c] = list_col(p, st.rel, st.out, c);
             a.out_count = at<uint32_t>(p, st.off_count);
         }
-        a.lb.status = at<uint64_t>(p, st.off_status);
-        a.lb.counter = at<uint32_t>(p, st.off_counter);
+        a.bits = at<uint8_t>(p, p->off_sbits);
+        a.counts = at<uint32_t>(p, p->off_scounts);
         a.seed = p->seed32;
         a.k = static_cast<int>(p->opts.k);
         a.logB = p->logB;
@@ -765,8 +789,7 @@ static sj_status run_steps(sj_plan_t *p, int phase) {
             ba.nblocks_max = static_cast<uint32_t>(p->filters[f].max_words / (p->opts.block_bits / 32));
             ba.region_blocks = p->region_blocks;
             ba.hist = at<uint32_t>(p, p->off_bhist);
-            ba.stage_block = at<uint32_t>(p, p->off_stage[0]);
-            ba.stage_g = at<uint32_t>(p, p->off_stage[1]);
+            ba.stage = at<uint2>(p, p->off_stage[0]);
             ba.keep = at<uint64_t>(p, p->off_keep);
             ba.total_dev = at<uint32_t>(p, st.off_btotal[b]);
             ba.lb.status = at<uint64_t>(p, st.off_bstatus[b]);
@@ -784,7 +807,7 @@ static sj_status run_steps(sj_plan_t *p, int phase) {
 static sj_status zero_region(sj_plan_t *p, int ph) {
     const Region &r = p->zero[ph];
     ProfScope ps(p, "zero:" + std::to_string(ph));
-    SJ_HIP(p->ctx, launch_zero(p->ws + r.begin, r.end - r.begin, p->ctx->stream));
+    SJ_HIP(p->ctx, launch_zero(p->ws + r.begin, r.end - r.begin, p->ls));
     return SJ_OK;
 }
 
@@ -799,11 +822,40 @@ static sj_status check_exec(sj_plan_t *p, int need) {
 }
 
 
+// Enqueue one launch phase on the context's stream: eagerly, or by replaying the
+// phase's graph, recorded from `enqueue` on the first call.
+static sj_status run_phase(sj_plan_t *p, int ph, sj_status (*enqueue)(sj_plan_t *)) {
+    if (p->eager) {
+        p->ls = p->ctx->stream;
+        return enqueue(p);
+    }
+    if (!p->gexec[ph]) {
+        if (!p->cap_stream) SJ_HIP(p->ctx, hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+        p->ls = p->cap_stream;
+        SJ_HIP(p->ctx, hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+        const sj_status st = enqueue(p);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+        if (st != SJ_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            if (st != SJ_OK) return st;
+            SJ_HIP(p->ctx, e);
+        }
+        const hipError_t ei = hipGraphInstantiate(&p->gexec[ph], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            p->gexec[ph] = nullptr;
+            SJ_HIP(p->ctx, ei);
+        }
+    }
+    SJ_HIP(p->ctx, hipGraphLaunch(p->gexec[ph], p->ctx->stream));
+    return SJ_OK;
+}
+
 // ---------------------------------------------------------------- the pruning phase
 
-extern "C" sj_status sj_build_filters(sj_plan_t *p) {
-    if (sj_status st = check_exec(p, kBound)) return st;
-    hipStream_t s = p->ctx->stream;
+static sj_status enqueue_build(sj_plan_t *p) {
+    hipStream_t s = p->ls;
     if (sj_status st = zero_region(p, 0)) return st;
     uint32_t *elig = at<uint32_t>(p, p->off_elig);
     for (int i = 0; i < p->n; ++i) {
@@ -813,15 +865,24 @@ extern "C" sj_status sj_build_filters(sj_plan_t *p) {
             SJ_HIP(p->ctx, launch_count_pred(R.cols[R.pred_col], R.nrows, R.lo, R.hi, elig + i, s));
         }
     }
-    if (sj_status st = run_steps(p, 0)) return st;
+    return run_steps(p, 0);
+}
+
+extern "C" sj_status sj_build_filters(sj_plan_t *p) {
+    if (sj_status st = check_exec(p, kBound)) return st;
+    if (sj_status st = run_phase(p, 0, enqueue_build)) return st;
     p->state = kFiltered;
     return SJ_OK;
 }
 
+static sj_status enqueue_sieve(sj_plan_t *p) {
+    if (sj_status st = zero_region(p, 1)) return st;
+    return run_steps(p, 1);
+}
+
 extern "C" sj_status sj_sieve(sj_plan_t *p, uint64_t *survivors) {
     if (sj_status st = check_exec(p, kFiltered)) return st;
-    if (sj_status st = zero_region(p, 1)) return st;
-    if (sj_status st = run_steps(p, 1)) return st;
+    if (sj_status st = run_phase(p, 1, enqueue_sieve)) return st;
     p->state = kSieved;
     if (survivors) {
         std::vector<uint32_t> c(p->n);
@@ -927,14 +988,10 @@ static CycArgs cyc_args(sj_plan_t *p, int32_t *out) {
     return c;
 }
 
-extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) {
-    if (sj_status st = check_exec(p, kSieved)) return st;
-    if (!p->cyc_ok)
-        return fail(p->ctx, SJ_ERR_UNSUPPORTED,
-                    "cyclic join: every closing edge must end at the last relation of the preorder (relation %d), "
-                    "on one column",
-                    p->L);
-    hipStream_t s = p->ctx->stream;
+// Count pass of the enumeration: bucket every non-root relation and run the join-tree
+// DP from the leaves up; the root's totals land in the workspace.
+static sj_status enqueue_join(sj_plan_t *p) {
+    hipStream_t s = p->ls;
     if (sj_status st = zero_region(p, 2)) return st;
     for (int j : p->postorder) {
         const int fl = p->final_list[j];
@@ -997,6 +1054,18 @@ extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) 
         ProfScope ps(p, std::string("dp:") + rel_name(j));
         SJ_HIP(p->ctx, launch_dp(d, s));
     }
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) {
+    if (sj_status st = check_exec(p, kSieved)) return st;
+    if (!p->cyc_ok)
+        return fail(p->ctx, SJ_ERR_UNSUPPORTED,
+                    "cyclic join: every closing edge must end at the last relation of the preorder (relation %d), "
+                    "on one column",
+                    p->L);
+    hipStream_t s = p->ctx->stream;
+    if (sj_status st = run_phase(p, 2, enqueue_join)) return st;
     uint64_t tot[2] = {0, 0};
     SJ_HIP(p->ctx, hipMemcpyAsync(tot, at<uint64_t>(p, p->off_totals), 16, hipMemcpyDeviceToHost, s));
     SJ_HIP(p->ctx, hipStreamSynchronize(s));
