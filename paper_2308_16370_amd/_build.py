@@ -9,6 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsievejoin.so")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 SOURCES = ["sj_kernels.hip", "sj_join.hip", "sj_runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -16,15 +17,16 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+def build(verbose: bool = False, out: str = LIB, defines=(), csrc: str = CSRC) -> str:
     """Compile every source (in parallel) and link the shared library; returns its path.
 
-    ``defines`` are extra ``-D`` tuning macros (the defaults are the tuned values)."""
+    ``defines`` are extra ``-D`` tuning macros (the defaults are the tuned values);
+    ``csrc`` is the source directory."""
     with tempfile.TemporaryDirectory(prefix="sjbuild") as tmp:
         def compile_one(src):
             obj = os.path.join(tmp, os.path.splitext(src)[0] + ".o")
             lang = ["-x", "hip"] if src.endswith(".cpp") else []
-            cmd = [HIPCC, *FLAGS, *["-D" + d for d in defines], *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [HIPCC, *FLAGS, "-I" + INCLUDE, *["-D" + d for d in defines], *lang, "-c", os.path.join(csrc, src), "-o", obj]
             r = subprocess.run(cmd, capture_output=True, text=True)
             if r.returncode != 0:
                 raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr[-4000:]))

@@ -347,22 +347,36 @@ __device__ __forceinline__ BfbShape bfb_shape(const BuildArgs &a) {
 
 // (1) Per-tile region counts. A key repeated inside a tile is staged once: a
 // direct-mapped LDS cache of the tile's keys drops repeats (Zipf heavy hitters would
-// otherwise pile millions of identical entries into one region). Which copies are kept
-// is recorded in a bitmap (bit e: element e is staged) that the scatter pass follows,
-// so both passes agree whatever the order the cache updates landed in.
-constexpr int kDedupLog = 11;
+// otherwise pile millions of identical entries into one region). The cache is updated
+// by exchange, so copies of one key that arrive together in a wave are ordered by the
+// exchanges and only the first is kept. Which copies are kept is recorded in a bitmap
+// (bit e: element e is staged) that the scatter pass follows, so both passes agree.
+constexpr int kDedupLog = 12;
+constexpr uint32_t kDedupMul = 0x9E3779B1u;
 
 constexpr int kBuildBatch = 8;   // elements per thread whose loads are issued together
+
+__host__ __device__ constexpr uint32_t inv_odd32(uint32_t a) {
+    uint32_t x = a;                       // Newton's iteration for the inverse mod 2^32
+    for (int i = 0; i < 5; ++i) x *= 2u - a * x;
+    return x;
+}
+static_assert(kDedupMul * inv_odd32(kDedupMul) == 1u, "multiplier inverse");
+
+__device__ __forceinline__ uint32_t dedup_slot(uint32_t key) { return (key * kDedupMul) >> (32 - kDedupLog); }
+// An empty slot s holds a key whose own slot is s ^ 1, which no key looked up in s equals.
+__device__ __forceinline__ uint32_t dedup_empty(uint32_t s) {
+    return ((s ^ 1u) << (32 - kDedupLog)) * inv_odd32(kDedupMul);
+}
 
 __global__ __launch_bounds__(kBuildBlock) void k_bfb_hist(BuildArgs a) {
     extern __shared__ uint32_t s_hist[];   // [nreg]
     __shared__ uint32_t s_seen[1 << kDedupLog];
-    __shared__ uint32_t s_seen_ok[1 << kDedupLog];
     const BfbShape sh = bfb_shape(a);
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.nblocks = sh.nb;
     for (uint32_t tile = blockIdx.x; tile < sh.ntiles; tile += gridDim.x) {
         for (uint32_t r = threadIdx.x; r < sh.nreg; r += kBuildBlock) s_hist[r] = 0;
-        for (uint32_t i = threadIdx.x; i < (1u << kDedupLog); i += kBuildBlock) s_seen_ok[i] = 0;
+        for (uint32_t i = threadIdx.x; i < (1u << kDedupLog); i += kBuildBlock) s_seen[i] = dedup_empty(i);
         __syncthreads();
         const uint32_t t0 = tile * sh.tile;
         for (uint32_t j0 = 0; j0 < sh.tile; j0 += kBuildBlock * kBuildBatch) {
@@ -382,11 +396,9 @@ __global__ __launch_bounds__(kBuildBlock) void k_bfb_hist(BuildArgs a) {
             for (int u = 0; u < kBuildBatch; ++u) {
                 bool keep = false;
                 if (take[u]) {
-                    const uint32_t slot = (static_cast<uint32_t>(key[u]) * 0x9E3779B1u) >> (32 - kDedupLog);
-                    keep = !(s_seen_ok[slot] && s_seen[slot] == static_cast<uint32_t>(key[u]));
+                    const uint32_t kk = static_cast<uint32_t>(key[u]);
+                    keep = atomicExch(&s_seen[dedup_slot(kk)], kk) != kk;
                     if (keep) {
-                        s_seen[slot] = static_cast<uint32_t>(key[u]);
-                        s_seen_ok[slot] = 1;
                         const BfKey h = bf_hash(key[u], a.seed, sh.nb);
                         atomicAdd(&s_hist[h.block / a.region_blocks], 1u);
                     }

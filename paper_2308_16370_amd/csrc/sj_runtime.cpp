@@ -11,7 +11,7 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/sievejoin.h"
+#include "sievejoin.h"
 #include "sj_internal.h"
 
 using namespace sj;
