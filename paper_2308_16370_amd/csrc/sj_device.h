@@ -118,6 +118,18 @@ __device__ __forceinline__ void bf_set(uint32_t *__restrict__ blk, uint32_t g, i
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// The chip dispatches workgroup b of a launch to XCD b % 8, and each XCD has its own
+// L2. For b < n this maps b to a work item so that each XCD takes one contiguous
+// range of [0, n) (a bijection on [0, n)): partial cache lines that neighbouring items
+// write then meet in one L2 instead of being written back from eight.
+constexpr uint32_t kXcds = 8;
+__host__ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t n) {
+    const uint32_t per = (n + kXcds - 1) / kXcds;      // items of the larger XCD ranges
+    const uint32_t tall = n % kXcds ? n % kXcds : kXcds; // XCDs that take `per` items
+    const uint32_t x = b % kXcds, i = b / kXcds;
+    return x < tall ? x * per + i : tall * per + (x - tall) * (per - 1) + i;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T x) {
     const int lane = lane_id();

@@ -186,7 +186,6 @@ struct MatArgs {
     const uint32_t *root_n;
     uint64_t count;                // total result tuples (host copy)
     int32_t *out;
-    int chunk;
 };
 hipError_t launch_materialize(const MatArgs &a, hipStream_t s);
 

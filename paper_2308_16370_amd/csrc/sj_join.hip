@@ -108,7 +108,8 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_hist(int pass, KeySrc ks,
     const RadixIo io = radix_io(ss, ks, pass);
     const uint32_t *w = pass < 4 ? io.slo : io.shi;
     const int shift = (pass & 3) * kRadixBits;
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (uint32_t b = blockIdx.x; b < ntiles; b += gridDim.x) {
+        const uint32_t tile = gridDim.x >= ntiles ? xcd_contiguous(b, ntiles) : b;
         h[threadIdx.x] = 0;
         __syncthreads();
 #pragma unroll
@@ -178,7 +179,8 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(int pass, KeySrc 
     const int shift = (pass & 3) * kRadixBits;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const uint64_t lt = (1ull << lane) - 1ull;
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (uint32_t b = blockIdx.x; b < ntiles; b += gridDim.x) {
+        const uint32_t tile = gridDim.x >= ntiles ? xcd_contiguous(b, ntiles) : b;
         s_off[tid] = ss.hist[tid * ntiles + tile];
         s_run[tid] = 0;
 #pragma unroll
@@ -517,26 +519,35 @@ __device__ __forceinline__ uint32_t upper_bound_u64(const uint64_t *a, uint32_t 
     return lo;
 }
 
+// Odometer state. Every array is indexed by compile-time positions only (the tree's
+// shape is a run-time argument, so parent links are followed by per-position tests
+// rather than by indexing), which keeps the state in registers.
 template <int N>
 struct MatState {
-    uint32_t e[N];
-    uint32_t lo[N];
+    uint32_t e[N];     // current entry of each position
+    uint32_t lo[N];    // bucket of each position below its parent's current entry
     uint32_t hi[N];
+    uint32_t pe[N];    // current entry of each position's parent
+    int32_t rid[N];    // row id of each position's current entry
 };
+
+template <int N>
+__device__ __forceinline__ void set_entry(const MatArgs &a, MatState<N> &st, int x, uint32_t v) {
+    st.e[x] = v;
+    st.rid[x] = static_cast<int32_t>(a.rid[x][v]);
+#pragma unroll
+    for (int y = 1; y < N; ++y)
+        if (y > x && a.parent_pos[y] == x) st.pe[y] = v;
+}
 
 // Bucket of position y below its parent's current entry.
 template <int N>
 __device__ __forceinline__ void find_bucket(const MatArgs &a, MatState<N> &st, int y) {
-    const int py = a.parent_pos[y];
-    uint32_t ep = st.e[0];
-#pragma unroll
-    for (int q = 1; q < N; ++q)
-        if (q == py) ep = st.e[q];
-    st.lo[y] = a.blo[y][ep];
-    st.hi[y] = a.bhi[y][ep];
+    st.lo[y] = a.blo[y][st.pe[y]];
+    st.hi[y] = a.bhi[y][st.pe[y]];
 }
 
-template <int N>
+// First entry at or after e (below hi) with a nonzero weight; leaves weigh 1 each.
 __device__ __forceinline__ uint32_t first_valid(const MatArgs &a, int y, uint32_t e, uint32_t hi) {
     if (a.is_leaf[y]) return e;
     const uint64_t *cw = a.cw[y];
@@ -547,22 +558,25 @@ __device__ __forceinline__ uint32_t first_valid(const MatArgs &a, int y, uint32_
 template <int N>
 __device__ void mat_decode(const MatArgs &a, MatState<N> &st, uint32_t r, uint64_t L0) {
     uint64_t L[N];
-    st.e[0] = r;
+#pragma unroll
+    for (int p = 0; p < N; ++p) L[p] = 0;
+    set_entry<N>(a, st, 0, r);
     L[0] = L0;
 #pragma unroll
     for (int p = 0; p < N; ++p) {
         if (p > 0) {
             // the entry of position p inside its bucket that holds local index L[p]
+            uint32_t e;
             if (a.is_leaf[p]) {
-                st.e[p] = st.lo[p] + static_cast<uint32_t>(L[p]);
+                e = st.lo[p] + static_cast<uint32_t>(L[p]);
                 L[p] = 0;
             } else {
                 const uint64_t *cw = a.cw[p];
                 const uint64_t base = cw[st.lo[p]];
-                const uint32_t e = upper_bound_u64(cw, st.lo[p], st.hi[p] + 1, base + L[p]) - 1;
-                st.e[p] = e;
+                e = upper_bound_u64(cw, st.lo[p], st.hi[p] + 1, base + L[p]) - 1;
                 L[p] -= cw[e] - base;
             }
+            set_entry<N>(a, st, p, e);
         }
         // split L[p] over p's children, last child least significant
 #pragma unroll
@@ -588,9 +602,9 @@ __device__ __forceinline__ void mat_advance(const MatArgs &a, MatState<N> &st, u
 #pragma unroll
     for (int x = N - 1; x >= 1; --x) {
         if (changed < 0) {
-            const uint32_t nx = first_valid<N>(a, x, st.e[x] + 1, st.hi[x]);
+            const uint32_t nx = first_valid(a, x, st.e[x] + 1, st.hi[x]);
             if (nx < st.hi[x]) {
-                st.e[x] = nx;
+                set_entry<N>(a, st, x, nx);
                 changed = x;
             }
         }
@@ -599,31 +613,41 @@ __device__ __forceinline__ void mat_advance(const MatArgs &a, MatState<N> &st, u
         const uint64_t *cw = a.cw[0];
         uint32_t r = st.e[0] + 1;
         while (r < root_n && cw[r + 1] == cw[r]) ++r;
-        st.e[0] = r;
+        set_entry<N>(a, st, 0, r);
         changed = 0;
     }
 #pragma unroll
     for (int y = 1; y < N; ++y) {
         if (y > changed) {
             if (a.parent_pos[y] >= changed) find_bucket<N>(a, st, y);
-            st.e[y] = first_valid<N>(a, y, st.lo[y], st.hi[y]);
+            set_entry<N>(a, st, y, first_valid(a, y, st.lo[y], st.hi[y]));
         }
     }
 }
 
-// A block owns the outputs [t0, t1) = 256 * chunk consecutive indices; thread t
-// decodes the first index of its chunk and steps the odometer through the rest. The
-// root entries covering the block are located once and their prefix weights staged
-// in LDS, so each thread's root search runs in LDS.
-constexpr int kMatWin = 2048;
+// Tuples per thread: a thread's C tuples of N row ids take at most 32 words of LDS.
+template <int N>
+constexpr int mat_chunk() {
+    return N <= 2 ? 16 : 32 / N;
+}
 
+// A block owns the outputs [t0, t1) = 256 * C consecutive indices; thread t decodes
+// the first index of its chunk and steps the odometer through the rest. The root
+// entries covering the block are located once and their prefix weights staged in LDS,
+// so each thread's root search runs in LDS. Tuples are assembled in an LDS tile (row
+// pitch C * N + 1 words, so the threads' rows fall in distinct banks) and the tile is
+// copied to the output with coalesced 16-byte stores.
 template <int N>
 __global__ __launch_bounds__(256) void k_materialize(MatArgs a) {
-    __shared__ uint64_t s_cw[kMatWin + 1];
+    constexpr int C = mat_chunk<N>();
+    constexpr uint32_t ROW = C * N, PITCH = ROW + 1;
+    constexpr uint32_t PER = 256u * C;
+    constexpr uint32_t WIN = PER + 2;
+    __shared__ uint64_t s_cw[WIN];
+    __shared__ int32_t s_out[256 * PITCH];
     __shared__ uint32_t s_r[2];
-    const uint64_t per = 256ull * a.chunk;
-    const uint64_t t0 = static_cast<uint64_t>(blockIdx.x) * per;
-    const uint64_t t1 = (t0 + per < a.count) ? t0 + per : a.count;
+    const uint64_t t0 = static_cast<uint64_t>(blockIdx.x) * PER;
+    const uint64_t t1 = (t0 + PER < a.count) ? t0 + PER : a.count;
     const uint32_t root_n = *a.root_n;
     const uint64_t *rcw = a.cw[0];
     if (threadIdx.x < 2) {
@@ -632,59 +656,69 @@ __global__ __launch_bounds__(256) void k_materialize(MatArgs a) {
     }
     __syncthreads();
     const uint32_t r0 = s_r[0], r1 = s_r[1];
-    const bool in_lds = r1 - r0 + 2 <= kMatWin + 1;
+    const bool in_lds = r1 - r0 + 2 <= WIN;   // zero-weight root entries can widen the range
     if (in_lds)
         for (uint32_t i = threadIdx.x; i < r1 - r0 + 2; i += 256) s_cw[i] = rcw[r0 + i];
     __syncthreads();
-    const uint64_t o0 = t0 + static_cast<uint64_t>(threadIdx.x) * a.chunk;
-    if (o0 >= t1) return;
-    const uint64_t o1 = (o0 + a.chunk < t1) ? o0 + a.chunk : t1;
-    uint32_t r;
-    uint64_t L0;
-    if (in_lds) {
-        r = r0 + upper_bound_u64(s_cw, 0, r1 - r0 + 2, o0) - 1;
-        L0 = o0 - s_cw[r - r0];
-    } else {
-        r = upper_bound_u64(rcw, r0, r1 + 2, o0) - 1;
-        L0 = o0 - rcw[r];
-    }
-    MatState<N> st;
-    mat_decode<N>(a, st, r, L0);
-    for (uint64_t o = o0;;) {
-        int32_t tup[N];
-#pragma unroll
-        for (int x = 0; x < N; ++x) {
-            const int32_t rid = static_cast<int32_t>(a.rid[x][st.e[x]]);
-#pragma unroll
-            for (int q = 0; q < N; ++q)
-                if (a.order[x] == q) tup[q] = rid;
-        }
-        int32_t *dst = a.out + o * N;
-        if constexpr (N == 4) {
-            *reinterpret_cast<int4 *>(dst) = make_int4(tup[0], tup[1], tup[2], tup[3]);
-        } else if constexpr (N == 2) {
-            *reinterpret_cast<int2 *>(dst) = make_int2(tup[0], tup[1]);
+    const uint64_t o0 = t0 + static_cast<uint64_t>(threadIdx.x) * C;
+    if (o0 < t1) {
+        uint32_t r;
+        uint64_t L0;
+        if (in_lds) {
+            r = r0 + upper_bound_u64(s_cw, 0, r1 - r0 + 2, o0) - 1;
+            L0 = o0 - s_cw[r - r0];
         } else {
-#pragma unroll
-            for (int q = 0; q < N; ++q) dst[q] = tup[q];
+            r = upper_bound_u64(rcw, r0, r1 + 2, o0) - 1;
+            L0 = o0 - rcw[r];
         }
-        if (++o >= o1) break;
-        mat_advance<N>(a, st, root_n);
+        MatState<N> st;
+        mat_decode<N>(a, st, r, L0);
+        const uint32_t nloc = static_cast<uint32_t>(min(static_cast<uint64_t>(C), t1 - o0));
+        int32_t *row = s_out + threadIdx.x * PITCH;
+        for (uint32_t i = 0;;) {
+#pragma unroll
+            for (int x = 0; x < N; ++x) row[i * N + a.order[x]] = st.rid[x];
+            if (++i >= nloc) break;
+            mat_advance<N>(a, st, root_n);
+        }
+    }
+    __syncthreads();
+    // word w of the block's output is word w % ROW of thread w / ROW's row
+    const uint64_t words = (t1 - t0) * N;
+    int32_t *dst = a.out + t0 * N;
+    for (uint32_t w = threadIdx.x * 4; w < words; w += 256 * 4) {
+        int32_t v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t ww = w + j;
+            v[j] = s_out[(ww / ROW) * PITCH + ww % ROW];
+        }
+        if (w + 4 <= words) {
+            *reinterpret_cast<int4 *>(dst + w) = make_int4(v[0], v[1], v[2], v[3]);
+        } else {
+            for (uint32_t j = 0; w + j < words; ++j) dst[w + j] = v[j];
+        }
     }
 }
 
-hipError_t launch_materialize(const MatArgs &a0, hipStream_t s) {
-    if (a0.count == 0) return hipSuccess;
-    MatArgs a = a0;
-    a.chunk = 16;
-    const uint64_t per_block = 256ull * a.chunk;
-    const uint64_t blocks64 = (a.count + per_block - 1) / per_block;
+hipError_t launch_materialize(const MatArgs &a, hipStream_t s) {
+    if (a.count == 0) return hipSuccess;
+    uint32_t per = 0;
+    switch (a.nrels) {
+#define SJ_MAT_PER(NN) \
+    case NN: per = 256u * mat_chunk<NN>(); break;
+        SJ_MAT_PER(1) SJ_MAT_PER(2) SJ_MAT_PER(3) SJ_MAT_PER(4) SJ_MAT_PER(5) SJ_MAT_PER(6) SJ_MAT_PER(7)
+        SJ_MAT_PER(8) SJ_MAT_PER(9) SJ_MAT_PER(10) SJ_MAT_PER(11) SJ_MAT_PER(12) SJ_MAT_PER(13)
+        SJ_MAT_PER(14) SJ_MAT_PER(15) SJ_MAT_PER(16)
+#undef SJ_MAT_PER
+        default: return hipErrorInvalidValue;
+    }
+    const uint64_t blocks64 = (a.count + per - 1) / per;
     if (blocks64 > 0x7fffffffull) return hipErrorInvalidValue;
     const dim3 g(static_cast<uint32_t>(blocks64));
-    const size_t lds = 0;
     switch (a.nrels) {
 #define SJ_MAT_CASE(NN) \
-    case NN: hipLaunchKernelGGL(k_materialize<NN>, g, dim3(256), lds, s, a); break;
+    case NN: hipLaunchKernelGGL(k_materialize<NN>, g, dim3(256), 0, s, a); break;
         SJ_MAT_CASE(1) SJ_MAT_CASE(2) SJ_MAT_CASE(3) SJ_MAT_CASE(4) SJ_MAT_CASE(5) SJ_MAT_CASE(6) SJ_MAT_CASE(7)
         SJ_MAT_CASE(8) SJ_MAT_CASE(9) SJ_MAT_CASE(10) SJ_MAT_CASE(11) SJ_MAT_CASE(12) SJ_MAT_CASE(13)
         SJ_MAT_CASE(14) SJ_MAT_CASE(15) SJ_MAT_CASE(16)
@@ -754,7 +788,7 @@ template <int N>
 __device__ __forceinline__ uint64_t prefix_factor(const CycArgs &a, const MatState<N> &st) {
     uint64_t f = 1;
 #pragma unroll
-    for (int x = 0; x < N; ++x) f *= chk_factor(static_cast<uint32_t>(a.m.order[x]), a.m.rid[x][st.e[x]]);
+    for (int x = 0; x < N; ++x) f *= chk_factor(static_cast<uint32_t>(a.m.order[x]), static_cast<uint32_t>(st.rid[x]));
     return f;
 }
 
@@ -780,7 +814,7 @@ __global__ __launch_bounds__(256) void k_cyclic(CycArgs a) {
                     for (uint32_t j = r0; j < r1; ++j, ++o) {
                         int32_t *dst = a.out + o * a.nrels;
 #pragma unroll
-                        for (int x = 0; x < N; ++x) dst[a.m.order[x]] = static_cast<int32_t>(a.m.rid[x][st.e[x]]);
+                        for (int x = 0; x < N; ++x) dst[a.m.order[x]] = st.rid[x];
                         dst[a.L_rel] = static_cast<int32_t>(a.Lrid[j]);
                     }
                 } else {

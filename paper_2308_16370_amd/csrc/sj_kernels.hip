@@ -374,7 +374,9 @@ __global__ __launch_bounds__(kBuildBlock) void k_bfb_hist(BuildArgs a) {
     __shared__ uint32_t s_seen[1 << kDedupLog];
     const BfbShape sh = bfb_shape(a);
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.nblocks = sh.nb;
-    for (uint32_t tile = blockIdx.x; tile < sh.ntiles; tile += gridDim.x) {
+    for (uint32_t b = blockIdx.x; b < sh.ntiles; b += gridDim.x) {
+        // one tile per workgroup when the grid covers the tiles (it does up to kBuildMaxTiles)
+        const uint32_t tile = gridDim.x >= sh.ntiles ? xcd_contiguous(b, sh.ntiles) : b;
         for (uint32_t r = threadIdx.x; r < sh.nreg; r += kBuildBlock) s_hist[r] = 0;
         for (uint32_t i = threadIdx.x; i < (1u << kDedupLog); i += kBuildBlock) s_seen[i] = dedup_empty(i);
         __syncthreads();
@@ -455,7 +457,9 @@ __global__ __launch_bounds__(kScanBlock) void k_bfb_scan(BuildArgs a) {
 __global__ __launch_bounds__(kBuildBlock) void k_bfb_scatter(BuildArgs a) {
     extern __shared__ uint32_t s_off[];    // [nreg]
     const BfbShape sh = bfb_shape(a);
-    for (uint32_t tile = blockIdx.x; tile < sh.ntiles; tile += gridDim.x) {
+    for (uint32_t b = blockIdx.x; b < sh.ntiles; b += gridDim.x) {
+        // one tile per workgroup when the grid covers the tiles (it does up to kBuildMaxTiles)
+        const uint32_t tile = gridDim.x >= sh.ntiles ? xcd_contiguous(b, sh.ntiles) : b;
         for (uint32_t r = threadIdx.x; r < sh.nreg; r += kBuildBlock) s_off[r] = a.hist[r * sh.ntiles + tile];
         __syncthreads();
         const uint32_t t0 = tile * sh.tile;
