@@ -528,13 +528,11 @@ struct MatState {
     uint32_t lo[N];    // bucket of each position below its parent's current entry
     uint32_t hi[N];
     uint32_t pe[N];    // current entry of each position's parent
-    int32_t rid[N];    // row id of each position's current entry
 };
 
 template <int N>
 __device__ __forceinline__ void set_entry(const MatArgs &a, MatState<N> &st, int x, uint32_t v) {
     st.e[x] = v;
-    st.rid[x] = static_cast<int32_t>(a.rid[x][v]);
 #pragma unroll
     for (int y = 1; y < N; ++y)
         if (y > x && a.parent_pos[y] == x) st.pe[y] = v;
@@ -625,18 +623,20 @@ __device__ __forceinline__ void mat_advance(const MatArgs &a, MatState<N> &st, u
     }
 }
 
-// Tuples per thread: a thread's C tuples of N row ids take at most 32 words of LDS.
+// Tuples per thread: a thread's C tuples of N entries take at most 16 words of LDS.
 template <int N>
 constexpr int mat_chunk() {
-    return N <= 2 ? 16 : 32 / N;
+    return N <= 2 ? 8 : (16 / N > 0 ? 16 / N : 1);
 }
 
 // A block owns the outputs [t0, t1) = 256 * C consecutive indices; thread t decodes
 // the first index of its chunk and steps the odometer through the rest. The root
 // entries covering the block are located once and their prefix weights staged in LDS,
-// so each thread's root search runs in LDS. Tuples are assembled in an LDS tile (row
-// pitch C * N + 1 words, so the threads' rows fall in distinct banks) and the tile is
-// copied to the output with coalesced 16-byte stores.
+// so each thread's root search runs in LDS. The odometer writes each tuple's entry
+// indices into an LDS tile (row pitch C * N + 1 words, so the threads' rows fall in
+// distinct banks); a leaf step then needs no memory access. The copy-out turns
+// entries into row ids with independent gathers and writes the tile with coalesced
+// 16-byte stores.
 template <int N>
 __global__ __launch_bounds__(256) void k_materialize(MatArgs a) {
     constexpr int C = mat_chunk<N>();
@@ -644,8 +644,9 @@ __global__ __launch_bounds__(256) void k_materialize(MatArgs a) {
     constexpr uint32_t PER = 256u * C;
     constexpr uint32_t WIN = PER + 2;
     __shared__ uint64_t s_cw[WIN];
-    __shared__ int32_t s_out[256 * PITCH];
+    __shared__ uint32_t s_out[256 * PITCH];
     __shared__ uint32_t s_r[2];
+    __shared__ const uint32_t *s_rid[N];   // row ids of output column q's position
     const uint64_t t0 = static_cast<uint64_t>(blockIdx.x) * PER;
     const uint64_t t1 = (t0 + PER < a.count) ? t0 + PER : a.count;
     const uint32_t root_n = *a.root_n;
@@ -653,6 +654,10 @@ __global__ __launch_bounds__(256) void k_materialize(MatArgs a) {
     if (threadIdx.x < 2) {
         const uint64_t o = threadIdx.x == 0 ? t0 : t1 - 1;
         s_r[threadIdx.x] = upper_bound_u64(rcw, 0, root_n + 1, o) - 1;
+    }
+    if (threadIdx.x == 64) {
+#pragma unroll
+        for (int x = 0; x < N; ++x) s_rid[a.order[x]] = a.rid[x];
     }
     __syncthreads();
     const uint32_t r0 = s_r[0], r1 = s_r[1];
@@ -674,10 +679,10 @@ __global__ __launch_bounds__(256) void k_materialize(MatArgs a) {
         MatState<N> st;
         mat_decode<N>(a, st, r, L0);
         const uint32_t nloc = static_cast<uint32_t>(min(static_cast<uint64_t>(C), t1 - o0));
-        int32_t *row = s_out + threadIdx.x * PITCH;
+        uint32_t *row = s_out + threadIdx.x * PITCH;
         for (uint32_t i = 0;;) {
 #pragma unroll
-            for (int x = 0; x < N; ++x) row[i * N + a.order[x]] = st.rid[x];
+            for (int x = 0; x < N; ++x) row[i * N + a.order[x]] = st.e[x];
             if (++i >= nloc) break;
             mat_advance<N>(a, st, root_n);
         }
@@ -691,7 +696,7 @@ __global__ __launch_bounds__(256) void k_materialize(MatArgs a) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t ww = w + j;
-            v[j] = s_out[(ww / ROW) * PITCH + ww % ROW];
+            v[j] = ww < words ? static_cast<int32_t>(s_rid[ww % N][s_out[(ww / ROW) * PITCH + ww % ROW]]) : 0;
         }
         if (w + 4 <= words) {
             *reinterpret_cast<int4 *>(dst + w) = make_int4(v[0], v[1], v[2], v[3]);
@@ -788,7 +793,7 @@ template <int N>
 __device__ __forceinline__ uint64_t prefix_factor(const CycArgs &a, const MatState<N> &st) {
     uint64_t f = 1;
 #pragma unroll
-    for (int x = 0; x < N; ++x) f *= chk_factor(static_cast<uint32_t>(a.m.order[x]), static_cast<uint32_t>(st.rid[x]));
+    for (int x = 0; x < N; ++x) f *= chk_factor(static_cast<uint32_t>(a.m.order[x]), a.m.rid[x][st.e[x]]);
     return f;
 }
 
@@ -814,7 +819,7 @@ __global__ __launch_bounds__(256) void k_cyclic(CycArgs a) {
                     for (uint32_t j = r0; j < r1; ++j, ++o) {
                         int32_t *dst = a.out + o * a.nrels;
 #pragma unroll
-                        for (int x = 0; x < N; ++x) dst[a.m.order[x]] = st.rid[x];
+                        for (int x = 0; x < N; ++x) dst[a.m.order[x]] = static_cast<int32_t>(a.m.rid[x][st.e[x]]);
                         dst[a.L_rel] = static_cast<int32_t>(a.Lrid[j]);
                     }
                 } else {
