@@ -72,24 +72,29 @@ hipError_t launch_count_pred(const int32_t *col, uint32_t n, int32_t lo, int32_t
 // before any is tested, so a thread keeps many independent loads in flight.
 // Zipf-skewed columns repeat a few keys very often: each block keeps a direct-mapped
 // LDS cache key -> contains(key) per probed filter (the first kMaxCached of them);
-// the filter is read-only during the scan, so a cached answer is exact.
+// the filter is read-only during the scan, so a cached answer is exact. A key's slot is
+// the top kCacheLog bits of c = key * kCacheMul (odd, so key <-> c is a bijection); the
+// entry holds the remaining bits of c and two flags, so one 32-bit store publishes a
+// consistent entry and a tag match identifies the key exactly.
 #ifndef SJ_MAX_CACHED
 #define SJ_MAX_CACHED 4
 #endif
 #ifndef SJ_CACHE_LOG
-#define SJ_CACHE_LOG 10
+#define SJ_CACHE_LOG 11
 #endif
 #ifndef SJ_PROBE_BATCH
 #define SJ_PROBE_BATCH 4
 #endif
 constexpr int kMaxCached = SJ_MAX_CACHED;
 constexpr int kCacheLog = SJ_CACHE_LOG;
-constexpr uint32_t kCacheValid = 0x80000000u;
 constexpr int kProbeBatch = SJ_PROBE_BATCH;
+constexpr uint32_t kCacheMul = 0x9E3779B1u;
+constexpr uint32_t kCacheOk = 1u, kCacheValid = 2u;
+constexpr uint32_t kCacheFlags = (1u << kCacheLog) - 1u;
+static_assert(kCacheLog >= 2 && kCacheLog <= 16, "cache entry layout");
 
-__device__ __forceinline__ uint32_t cache_slot(int32_t key) {
-    return (static_cast<uint32_t>(key) * 0x9E3779B1u) >> (32 - kCacheLog);
-}
+__device__ __forceinline__ uint32_t cache_slot(uint32_t c) { return c >> (32 - kCacheLog); }
+__device__ __forceinline__ uint32_t cache_tag(uint32_t c) { return c << kCacheLog; }
 
 __device__ __forceinline__ uint32_t sieve_rows_per_group(uint32_t n) {
     const uint32_t per = (n + kSieveGrid - 1) / kSieveGrid;
@@ -99,7 +104,7 @@ __device__ __forceinline__ uint32_t sieve_rows_per_group(uint32_t n) {
 template <int NCOL, int KMAX>
 __global__ __launch_bounds__(kSieveBlock) void k_sieve_step(StepArgs a) {
     __shared__ uint32_t s_wave[kSieveBlock / 64];
-    __shared__ uint64_t s_cache[kMaxCached > 0 ? kMaxCached : 1][1 << kCacheLog];
+    __shared__ uint32_t s_cache[kMaxCached > 0 ? kMaxCached : 1][1 << kCacheLog];
     for (int i = threadIdx.x; i < kMaxCached * (1 << kCacheLog); i += kSieveBlock) (&s_cache[0][0])[i] = 0;
     __syncthreads();
 
@@ -111,6 +116,10 @@ __global__ __launch_bounds__(kSieveBlock) void k_sieve_step(StepArgs a) {
     uint32_t survivors = 0;
     const uint32_t wpb_shift = static_cast<uint32_t>(a.logB) - 5u;   // words per block = 1 << wpb_shift
     const uint32_t sh = 32u - static_cast<uint32_t>(a.logB);
+    uint32_t used = 0;   // columns some filter probes (the compaction reads the others)
+#pragma unroll
+    for (int p = 0; p < kMaxProbe; ++p)
+        if (p < a.nprobe) used |= 1u << a.probe_col[p];
 
     for (uint32_t t0 = blockIdx.x * per; t0 < r_end; t0 += kSieveTile) {
         const uint32_t row0 = t0 + tid * kSieveItems;
@@ -120,6 +129,11 @@ __global__ __launch_bounds__(kSieveBlock) void k_sieve_step(StepArgs a) {
         if (full) {
 #pragma unroll
             for (int c = 0; c < NCOL; ++c) {
+                if (!((used >> c) & 1u)) {
+#pragma unroll
+                    for (int i = 0; i < kSieveItems; ++i) v[c][i] = 0;
+                    continue;
+                }
                 const v4i *src = reinterpret_cast<const v4i *>(a.col[c] + row0);
                 const v4i x0 = __builtin_nontemporal_load(src);
                 const v4i x1 = __builtin_nontemporal_load(src + 1);
@@ -132,7 +146,7 @@ __global__ __launch_bounds__(kSieveBlock) void k_sieve_step(StepArgs a) {
                 const uint32_t r = row0 + i;
                 const bool in = r < n;
 #pragma unroll
-                for (int c = 0; c < NCOL; ++c) v[c][i] = in ? a.col[c][r] : 0;
+                for (int c = 0; c < NCOL; ++c) v[c][i] = (in && ((used >> c) & 1u)) ? a.col[c][r] : 0;
             }
         }
 
@@ -155,7 +169,7 @@ __global__ __launch_bounds__(kSieveBlock) void k_sieve_step(StepArgs a) {
                 const uint32_t *words = a.probe[p].words;
 #pragma unroll
                 for (int i0 = 0; i0 < kSieveItems; i0 += kProbeBatch) {
-                    uint32_t blk[kProbeBatch], g[kProbeBatch], slot[kProbeBatch];
+                    uint32_t blk[kProbeBatch], g[kProbeBatch], kc[kProbeBatch];
                     int32_t key[kProbeBatch];
                     uint32_t need = 0;
 #pragma unroll
@@ -165,17 +179,16 @@ __global__ __launch_bounds__(kSieveBlock) void k_sieve_step(StepArgs a) {
 #pragma unroll
                         for (int c = 1; c < NCOL; ++c)
                             if (a.probe_col[p] == c) key[ii] = v[c][i];
-                        slot[ii] = cache_slot(key[ii]);
+                        kc[ii] = static_cast<uint32_t>(key[ii]) * kCacheMul;
                         blk[ii] = 0;
                         g[ii] = 0;
                         if (flags & (1u << i)) {
                             bool hit = false;
                             if (p < kMaxCached) {
-                                const uint64_t e = s_cache[p < kMaxCached ? p : 0][slot[ii]];
-                                if (static_cast<uint32_t>(e >> 32) == static_cast<uint32_t>(key[ii]) &&
-                                    (static_cast<uint32_t>(e) & kCacheValid)) {
+                                const uint32_t e = s_cache[p < kMaxCached ? p : 0][cache_slot(kc[ii])];
+                                if ((e & ~kCacheFlags) == cache_tag(kc[ii]) && (e & kCacheValid)) {
                                     hit = true;
-                                    if (!(e & 1u)) flags &= ~(1u << i);
+                                    if (!(e & kCacheOk)) flags &= ~(1u << i);
                                 }
                             }
                             if (!hit) {
@@ -206,8 +219,7 @@ __global__ __launch_bounds__(kSieveBlock) void k_sieve_step(StepArgs a) {
                             ok &= 1u;
                             if (!ok) flags &= ~(1u << (i0 + ii));
                             if (p < kMaxCached)
-                                s_cache[p < kMaxCached ? p : 0][slot[ii]] =
-                                    (static_cast<uint64_t>(static_cast<uint32_t>(key[ii])) << 32) | kCacheValid | ok;
+                                s_cache[p < kMaxCached ? p : 0][cache_slot(kc[ii])] = cache_tag(kc[ii]) | kCacheValid | ok;
                         }
                     }
                 }
