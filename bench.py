@@ -12,10 +12,20 @@ inputs and workspace are already resident in HBM. The metric is input tuples per
 second (the sum of the four relations' rows divided by the step time).
 
 Printed: one JSON line with the contract's fields plus
-  roofline      -- the dominant kernel's algorithmic bytes per launch over its
-                   HIP-event-timed average duration, against 8 TB/s HBM;
+  roofline      -- for the kernel launch with the longest average duration among those
+                   with an algorithmic-byte model: its bytes per launch over its
+                   HIP-event-timed average duration, against 8 TB/s HBM; traffic is the
+                   HBM bytes per launch from the committed rocprofv3 counter summary
+                   (profiles/traffic.json) when it was taken on the current sources;
   cpu_baseline  -- the CPU oracle (plain single-threaded binary hash join) on the
                    same input, timed on this host.
+
+The per-launch event timings come from a second plan on the same workspace that
+launches eagerly with an event pair around each kernel (the timed plan replays
+recorded graphs); the kernels and data are the same.
+
+--copy-mib N appends one plain device-to-device copy of N MiB (after the JSON line
+is printed) so that a counter run can calibrate FETCH_SIZE / WRITE_SIZE.
 """
 import argparse
 import hashlib
@@ -40,9 +50,9 @@ def lib_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(label_kernel):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was taken
-    on the current kernel sources; else None."""
+def load_traffic(label):
+    """HBM bytes per launch of the launch `label` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -50,9 +60,9 @@ def load_traffic(label_kernel):
         t = json.load(open(path))
     except Exception:
         return None
-    if t.get("source_hash") != lib_source_hash():
+    if t.get("source_hash") != lib_source_hash() or t.get("label") != label:
         return None
-    return t.get("bytes_per_launch", {}).get(label_kernel)
+    return t.get("bytes_per_launch")
 
 
 def main():
@@ -64,6 +74,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="shrink rows and key domain together (tests)")
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0, help="append a plain copy of this many MiB")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -144,7 +155,7 @@ def main():
             pplan.profile(reset=True)
     prof = pplan.profile()
     del pplan
-    kernels = sorted(prof, key=lambda e: -e["total_ms"])
+    kernels = sorted(prof, key=lambda e: -e["total_ms"] / max(1, e["launches"]))
     modelled = [e for e in kernels if e["alg_bytes"] > 0]
     dom = modelled[0] if modelled else None
     roofline = None
@@ -194,7 +205,13 @@ def main():
         "kernels": [{"label": e["label"], "avg_us": round(e["total_ms"] / max(1, e["launches"]) * 1e3, 2),
                      "alg_bytes": e["alg_bytes"]} for e in kernels[:12]],
     }
-    print(json.dumps(res))
+    print(json.dumps(res), flush=True)
+    if args.copy_mib:
+        x = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device=dev)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

@@ -190,10 +190,18 @@ sj_status sj_profile_collect(sj_plan_t *plan);
 /* Number of distinct launch-group labels seen so far. */
 sj_status sj_profile_count(const sj_plan_t *plan, int32_t *n);
 /* Label i (valid until the plan is destroyed), its total milliseconds and launch
- * count, and the algorithmic bytes of its last launch (0 where not modelled): for a
- * sieve step, the join columns (plus the row ids of a survivor-list source and the
- * predicate column of a full scan) read, the survivors written and each filter it
- * probes or builds counted once; for "materialize", the result tuples written. */
+ * count, and the algorithmic bytes of its last launch (0 where not modelled). Labels
+ * name one kernel each where a byte model exists:
+ *   "probe:..."         probed columns (and the predicate column of a full scan) read,
+ *                       one survivor bit per row written, each probed filter read once;
+ *   "compact:..."       survivor bits read, each survivor's columns (and the row id of
+ *                       a survivor-list source) read, its row id and columns written;
+ *   "bfb_hist:..."      filter build, region counts: the inserted keys (and the
+ *                       predicate column of a full scan) read;
+ *   "bfb_scatter:..."   the keys read again, one 8-byte staged entry per kept key
+ *                       written;
+ *   "bfb_region:..."    the staged entries read, the filter written once;
+ *   "materialize"       the result tuples written. */
 sj_status sj_profile_entry(const sj_plan_t *plan, int32_t i, const char **label, double *total_ms,
                            uint64_t *launches, uint64_t *alg_bytes);
 /* Collect, then zero every total. */

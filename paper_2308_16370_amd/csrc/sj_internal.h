@@ -69,15 +69,20 @@ struct StepArgs {
 hipError_t launch_zero(void *p, uint64_t bytes, hipStream_t s);
 hipError_t launch_count_pred(const int32_t *col, uint32_t n, int32_t lo, int32_t hi, uint32_t *out,
                              hipStream_t s);
-hipError_t launch_sieve_step(const StepArgs &a, uint32_t max_rows, hipStream_t s);
+// A sieve step is two launches: the probe scan (survivor bits and per-workgroup counts)
+// and, when the step writes a survivor list, the compaction.
+hipError_t launch_sieve_probe(const StepArgs &a, uint32_t max_rows, hipStream_t s);
+hipError_t launch_sieve_compact(const StepArgs &a, uint32_t max_rows, hipStream_t s);
 
 // Partitioned build of one filter from a key column (full column with an optional
 // predicate, or a survivor-list column with a device-side length).
-constexpr int kBuildBlock = 256;
+constexpr int kBuildBlock = 1024;
 // A build tile holds tile_of(n) keys: at least kBuildTileMin, and few enough that at
-// most kBuildMaxTiles tiles cover the input (keeps the (region, tile) table small).
+// most kBuildMaxTiles tiles cover the input. Few large tiles keep the scatter's runs
+// per (region, tile) long (each such run costs about one partly written cache line)
+// and let the tile's dedup cache drop more repeats.
 constexpr uint32_t kBuildTileMin = kBuildBlock * 8;
-constexpr uint32_t kBuildMaxTiles = 2048;
+constexpr uint32_t kBuildMaxTiles = 512;
 __host__ __device__ inline uint32_t build_tile_of(uint32_t n) {
     const uint32_t per = (n + kBuildMaxTiles - 1) / kBuildMaxTiles;
     const uint32_t t = (per + kBuildTileMin - 1) / kBuildTileMin * kBuildTileMin;
@@ -107,7 +112,10 @@ struct BuildArgs {
     int k;
     int logB;
 };
-hipError_t launch_filter_build(const BuildArgs &a, hipStream_t s);
+// The build's four launches, in order: 0 region counts per tile, 1 their scan, 2 the
+// scatter into region buckets, 3 the per-region bit setting.
+constexpr int kBuildStages = 4;
+hipError_t launch_filter_build_stage(const BuildArgs &a, int stage, hipStream_t s);
 
 // ---- join phase (sj_join.hip) ----
 // A relation's sieved rows regrouped by its parent-edge key ("bucket order").

@@ -299,25 +299,36 @@ __global__ __launch_bounds__(kSieveBlock) void k_sieve_compact(StepArgs a) {
 }
 
 template <int KMAX>
-static hipError_t launch_sieve_k(const StepArgs &a, hipStream_t s) {
+static hipError_t launch_probe_k(const StepArgs &a, hipStream_t s) {
     const dim3 g(kSieveGrid), b(kSieveBlock);
     switch (a.ncol) {
-#define SJ_SIEVE_CASE(NC)                                                             \
-    case NC:                                                                          \
-        hipLaunchKernelGGL((k_sieve_step<NC, KMAX>), g, b, 0, s, a);                  \
-        if (a.out_rid) hipLaunchKernelGGL((k_sieve_compact<NC>), g, b, 0, s, a);      \
-        break;
-        SJ_SIEVE_CASE(1) SJ_SIEVE_CASE(2) SJ_SIEVE_CASE(3) SJ_SIEVE_CASE(4)
-        SJ_SIEVE_CASE(5) SJ_SIEVE_CASE(6) SJ_SIEVE_CASE(7) SJ_SIEVE_CASE(8)
-#undef SJ_SIEVE_CASE
+#define SJ_PROBE_CASE(NC) \
+    case NC: hipLaunchKernelGGL((k_sieve_step<NC, KMAX>), g, b, 0, s, a); break;
+        SJ_PROBE_CASE(1) SJ_PROBE_CASE(2) SJ_PROBE_CASE(3) SJ_PROBE_CASE(4)
+        SJ_PROBE_CASE(5) SJ_PROBE_CASE(6) SJ_PROBE_CASE(7) SJ_PROBE_CASE(8)
+#undef SJ_PROBE_CASE
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_sieve_step(const StepArgs &a, uint32_t max_rows, hipStream_t s) {
+hipError_t launch_sieve_probe(const StepArgs &a, uint32_t max_rows, hipStream_t s) {
     if (max_rows == 0) return hipSuccess;
-    return a.k <= 8 ? launch_sieve_k<8>(a, s) : launch_sieve_k<kMaxK>(a, s);
+    return a.k <= 8 ? launch_probe_k<8>(a, s) : launch_probe_k<kMaxK>(a, s);
+}
+
+hipError_t launch_sieve_compact(const StepArgs &a, uint32_t max_rows, hipStream_t s) {
+    if (max_rows == 0 || !a.out_rid) return hipSuccess;
+    const dim3 g(kSieveGrid), b(kSieveBlock);
+    switch (a.ncol) {
+#define SJ_COMPACT_CASE(NC) \
+    case NC: hipLaunchKernelGGL((k_sieve_compact<NC>), g, b, 0, s, a); break;
+        SJ_COMPACT_CASE(1) SJ_COMPACT_CASE(2) SJ_COMPACT_CASE(3) SJ_COMPACT_CASE(4)
+        SJ_COMPACT_CASE(5) SJ_COMPACT_CASE(6) SJ_COMPACT_CASE(7) SJ_COMPACT_CASE(8)
+#undef SJ_COMPACT_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 // ---- partitioned filter build ----------------------------------------------------------
@@ -363,7 +374,7 @@ __device__ __forceinline__ BfbShape bfb_shape(const BuildArgs &a) {
 // by exchange, so copies of one key that arrive together in a wave are ordered by the
 // exchanges and only the first is kept. Which copies are kept is recorded in a bitmap
 // (bit e: element e is staged) that the scatter pass follows, so both passes agree.
-constexpr int kDedupLog = 12;
+constexpr int kDedupLog = 13;
 constexpr uint32_t kDedupMul = 0x9E3779B1u;
 
 constexpr int kBuildBatch = 8;   // elements per thread whose loads are issued together
@@ -556,20 +567,33 @@ __global__ __launch_bounds__(kRegionThreads) void k_bfb_region(BuildArgs a) {
     }
 }
 
-hipError_t launch_filter_build(const BuildArgs &a, hipStream_t s) {
+hipError_t launch_filter_build_stage(const BuildArgs &a, int stage, hipStream_t s) {
     const uint32_t ntiles_max = min(kBuildMaxTiles, (a.n_max + kBuildTileMin - 1) / kBuildTileMin);
     const uint32_t nreg_max = (a.nblocks_max + a.region_blocks - 1) / a.region_blocks;
     const size_t lds_hist = 4ull * (nreg_max ? nreg_max : 1);
     const size_t lds_region = 4ull * a.region_blocks * (1u << (a.logB - 5));
     const uint32_t tgrid = ntiles_max == 0 ? 1 : (ntiles_max < 2048 ? ntiles_max : 2048);
-    hipLaunchKernelGGL(k_bfb_hist, dim3(tgrid), dim3(kBuildBlock), lds_hist, s, a);
-    // every workgroup claims at least one tile from a single counter: size the grid to the work
-    const uint32_t scan_tiles = (nreg_max * ntiles_max + kScanTile - 1) / kScanTile;
-    const uint32_t sgrid = scan_tiles == 0 ? 1 : (scan_tiles < 256 ? scan_tiles : 256);
-    hipLaunchKernelGGL(k_bfb_scan, dim3(sgrid), dim3(kScanBlock), 0, s, a);
-    hipLaunchKernelGGL(k_bfb_scatter, dim3(tgrid), dim3(kBuildBlock), lds_hist, s, a);
-    const uint32_t rgrid = nreg_max == 0 ? 1 : (nreg_max < 2048 ? nreg_max : 2048);
-    hipLaunchKernelGGL(k_bfb_region, dim3(rgrid), dim3(kRegionThreads), lds_region, s, a);
+    switch (stage) {
+        case 0:
+            hipLaunchKernelGGL(k_bfb_hist, dim3(tgrid), dim3(kBuildBlock), lds_hist, s, a);
+            break;
+        case 1: {
+            // every workgroup claims at least one tile from a single counter: size the grid to the work
+            const uint32_t scan_tiles = (nreg_max * ntiles_max + kScanTile - 1) / kScanTile;
+            const uint32_t sgrid = scan_tiles == 0 ? 1 : (scan_tiles < 256 ? scan_tiles : 256);
+            hipLaunchKernelGGL(k_bfb_scan, dim3(sgrid), dim3(kScanBlock), 0, s, a);
+            break;
+        }
+        case 2:
+            hipLaunchKernelGGL(k_bfb_scatter, dim3(tgrid), dim3(kBuildBlock), lds_hist, s, a);
+            break;
+        case 3: {
+            const uint32_t rgrid = nreg_max == 0 ? 1 : (nreg_max < 2048 ? nreg_max : 2048);
+            hipLaunchKernelGGL(k_bfb_region, dim3(rgrid), dim3(kRegionThreads), lds_region, s, a);
+            break;
+        }
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

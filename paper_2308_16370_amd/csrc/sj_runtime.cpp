@@ -132,7 +132,8 @@ struct sj_plan_s {
     struct ProfRec {
         int label;
         hipEvent_t a, b;
-        int step;              // sieve step index, -1 otherwise
+        int step;              // sieve step index (probe, compaction, build), -1 otherwise
+        int kind;              // ProfKind
     };
     std::vector<ProfRec> prof_pending;
     std::vector<hipEvent_t> prof_free;
@@ -697,15 +698,18 @@ static hipEvent_t prof_event(sj_plan_t *p) {
 }
 
 // Records an event before the launches of its scope and one after them.
+// What a profiled launch group is, for its algorithmic-byte model.
+enum ProfKind { kProfOther = 0, kProfProbe = 1, kProfCompact = 2, kProfResult = 3, kProfBuild0 = 16 };
+
 struct ProfScope {
     sj_plan_t *p;
     long idx = -1;
-    ProfScope(sj_plan_t *pp, const std::string &label, int step = -1) : p(pp) {
+    ProfScope(sj_plan_t *pp, const std::string &label, int step = -1, int kind = kProfOther) : p(pp) {
         if (!p->profile) return;
         hipEvent_t a = prof_event(p), b = prof_event(p);
         if (!a || !b) return;
         (void)hipEventRecord(a, p->ctx->stream);
-        p->prof_pending.push_back({prof_label(p, label), a, b, step});
+        p->prof_pending.push_back({prof_label(p, label), a, b, step, kind});
         idx = static_cast<long>(p->prof_pending.size()) - 1;
     }
     ~ProfScope() {
@@ -760,9 +764,14 @@ static sj_status run_steps(sj_plan_t *p, int phase) {
         a.logB = p->logB;
         const std::string tag = std::string(st.phase == 0 ? "bwd" : "sieve") + ":" + rel_name(st.rel) + ":" +
                                 std::to_string(&st - p->steps.data());
+        const int si = static_cast<int>(&st - p->steps.data());
         if (a.nprobe > 0 || st.out >= 0) {
-            ProfScope ps(p, "sieve_step:" + tag, static_cast<int>(&st - p->steps.data()));
-            SJ_HIP(p->ctx, launch_sieve_step(a, st.max_rows, s));
+            {
+                ProfScope ps(p, "probe:" + tag, si, kProfProbe);
+                SJ_HIP(p->ctx, launch_sieve_probe(a, st.max_rows, s));
+            }
+            ProfScope ps(p, "compact:" + tag, si, kProfCompact);
+            SJ_HIP(p->ctx, launch_sieve_compact(a, st.max_rows, s));
         }
         for (size_t b = 0; b < st.builds.size(); ++b) {
             const int f = st.builds[b].second;
@@ -797,8 +806,12 @@ static sj_status run_steps(sj_plan_t *p, int phase) {
             ba.seed = p->seed32;
             ba.k = static_cast<int>(p->opts.k);
             ba.logB = p->logB;
-            ProfScope ps(p, "filter_build:" + tag + ":f" + std::to_string(f), -3 - f);
-            SJ_HIP(p->ctx, launch_filter_build(ba, s));
+            static const char *stage_name[kBuildStages] = {"bfb_hist", "bfb_scan", "bfb_scatter", "bfb_region"};
+            for (int stg = 0; stg < kBuildStages; ++stg) {
+                ProfScope ps(p, std::string(stage_name[stg]) + ":" + tag + ":f" + std::to_string(f), si,
+                             kProfBuild0 + kBuildStages * static_cast<int>(b) + stg);
+                SJ_HIP(p->ctx, launch_filter_build_stage(ba, stg, s));
+            }
         }
     }
     return SJ_OK;
@@ -1103,14 +1116,14 @@ extern "C" sj_status sj_result(sj_plan_t *p, int32_t *out, uint64_t capacity) {
     if (reinterpret_cast<uintptr_t>(out) % 16) return fail(p->ctx, SJ_ERR_INVALID, "output must be 16-byte aligned");
     if (p->cyclic) {
         CycArgs c = cyc_args(p, out);
-        ProfScope ps(p, "cyclic_write", -2);
+        ProfScope ps(p, "cyclic_write", -1, kProfResult);
         SJ_HIP(p->ctx, launch_cyclic_write(c, p->ctx->stream));
         return SJ_OK;
     }
     MatArgs m = mat_args(p, p->n);
     m.count = p->count;
     m.out = out;
-    ProfScope ps(p, "materialize", -2);
+    ProfScope ps(p, "materialize", -1, kProfResult);
     SJ_HIP(p->ctx, launch_materialize(m, p->ctx->stream));
     return SJ_OK;
 }
@@ -1184,24 +1197,47 @@ extern "C" sj_status sj_profile_collect(sj_plan_t *p) {
         acc.ms += ms;
         acc.n += 1;
         if (r.step >= 0) {
-            // algorithmic bytes: columns (+ row ids of a list source, + predicate column) read,
-            // survivors written, and each filter touched read or written once
             const StepSpec &st = p->steps[r.step];
             const Rel &R = p->rels[st.rel];
             const uint64_t ncol = R.jcols.size();
+            const bool listsrc = st.src != kFull;
             uint32_t nin = R.nrows, nout = 0;
-            if (st.src != kFull)
+            if (listsrc)
                 SJ_HIP(p->ctx, hipMemcpy(&nin, at<uint32_t>(p, p->steps[st.src_step].off_count), 4, hipMemcpyDeviceToHost));
             if (st.out >= 0) SJ_HIP(p->ctx, hipMemcpy(&nout, at<uint32_t>(p, st.off_count), 4, hipMemcpyDeviceToHost));
-            uint64_t bytes = uint64_t(nin) * 4 * (ncol + (st.src != kFull ? 1 : 0) + (st.src == kFull && R.pred_col >= 0 ? 1 : 0));
-            bytes += uint64_t(nout) * 4 * (ncol + 1);
-            for (auto &pr : st.probes) bytes += uint64_t(nb[pr.second]) * (p->opts.block_bits / 8);
-            for (auto &bl : st.builds) bytes += uint64_t(nb[bl.second]) * (p->opts.block_bits / 8);
+            const uint64_t fbytes = p->opts.block_bits / 8;
+            uint64_t bytes = 0;
+            if (r.kind == kProfProbe) {
+                // probed columns (+ the predicate column of a full scan) read, survivor
+                // bits written, each probed filter read once
+                uint32_t used = 0;
+                for (auto &pr : st.probes) used |= 1u << pr.first;
+                const uint64_t cols = __builtin_popcount(used) + (!listsrc && R.pred_col >= 0 ? 1 : 0);
+                bytes = uint64_t(nin) * 4 * cols + (uint64_t(nin) + 7) / 8;
+                for (auto &pr : st.probes) bytes += uint64_t(nb[pr.second]) * fbytes;
+            } else if (r.kind == kProfCompact) {
+                // survivor bits read; each survivor's columns (+ row id of a list source)
+                // read and its row id and columns written
+                bytes = (uint64_t(nin) + 7) / 8 + uint64_t(nout) * 4 * (ncol + (listsrc ? 1 : 0)) +
+                        uint64_t(nout) * 4 * (ncol + 1);
+            } else if (r.kind >= kProfBuild0) {
+                // keys read once (with the predicate column of a full scan): by the count and
+                // the scatter stages; the staged (block, hash word) pairs: written by the
+                // scatter, read by the region stage, which writes the filter once
+                const int bi = (r.kind - kProfBuild0) / kBuildStages, stg = (r.kind - kProfBuild0) % kBuildStages;
+                const auto &bl = st.builds[static_cast<size_t>(bi)];
+                const uint64_t n = st.out >= 0 ? nout : nin;
+                const uint64_t keys = n * 4 * (1 + (!listsrc && st.out < 0 && R.pred_col >= 0 ? 1 : 0));
+                uint32_t staged = 0;
+                SJ_HIP(p->ctx, hipMemcpy(&staged, at<uint32_t>(p, st.off_btotal[static_cast<size_t>(bi)]), 4,
+                                         hipMemcpyDeviceToHost));
+                if (stg == 0) bytes = keys;
+                else if (stg == 2) bytes = keys + uint64_t(staged) * 8;
+                else if (stg == 3) bytes = uint64_t(staged) * 8 + uint64_t(nb[bl.second]) * fbytes;
+            }
             acc.bytes = bytes;
-        } else if (r.step == -2) {
+        } else if (r.kind == kProfResult) {
             acc.bytes = p->count * 4ull * p->n;   // result tuples written
-        } else if (r.step <= -3) {
-            acc.bytes = 0;                        // filter builds: bytes depend on survivors (not modelled)
         }
         p->prof_free.push_back(r.a);
         p->prof_free.push_back(r.b);

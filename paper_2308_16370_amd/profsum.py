@@ -1,0 +1,146 @@
+"""Summaries of rocprofv3 output databases (rocpd SQLite) for the profiles folder.
+
+    python -m paper_2308_16370_amd.profsum stats RUN.db [--cmd TEXT]
+        Markdown: the per-kernel totals rocprofv3 --stats reports, then each kernel's
+        launches by their position inside a step (a step ends with the launch of the
+        kernel named by --step-end), averaged over the steady steps.
+
+    python -m paper_2308_16370_amd.profsum traffic FETCH.db WRITE.db --kernel NAME
+            --occurrence I --copy-kernel NAME --copy-bytes N [--cmd TEXT]
+        JSON: HBM bytes per launch of occurrence I of kernel NAME from FETCH_SIZE and
+        WRITE_SIZE (KiB per dispatch), each scaled by bytes / counter of a plain copy
+        kernel of N bytes read and N bytes written in the same run.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sqlite3
+import statistics
+import sys
+
+
+def _short(name: str) -> str:
+    n = name.replace("void ", "").replace("sj::", "")
+    return n.split("(")[0]
+
+
+def _dispatches(db):
+    return db.execute("select name, start, end, grid_x, workgroup_x from kernels order by start").fetchall()
+
+
+def _steps(rows, step_end: str):
+    """Split the dispatch list into steps, each ending with a `step_end` launch."""
+    steps, cur = [], []
+    for r in rows:
+        cur.append(r)
+        if step_end in r[0]:
+            steps.append(cur)
+            cur = []
+    return steps
+
+
+def occurrence_table(rows, step_end: str, skip: int = 1):
+    """{(kernel, i): [durations in us]} for the i-th launch of each kernel per step."""
+    steps = _steps(rows, step_end)[skip:]
+    table = {}
+    for st in steps:
+        seen = {}
+        for name, s, e, _, _ in st:
+            k = _short(name)
+            i = seen.get(k, 0)
+            seen[k] = i + 1
+            table.setdefault((k, i), []).append((e - s) / 1e3)
+    return table, len(steps)
+
+
+def cmd_stats(args):
+    db = sqlite3.connect(args.db)
+    out = []
+    if args.cmd:
+        out.append("Command: `%s`\n" % args.cmd)
+    out.append("| kernel | calls | total us | average us | % |")
+    out.append("|---|---:|---:|---:|---:|")
+    for name, calls, tot, avg, pct in db.execute(
+            "select name, total_calls, total_duration, average, percentage from top_kernels "
+            "order by total_duration desc limit %d" % args.top):
+        out.append("| %s | %d | %.1f | %.2f | %.2f |" % (_short(name), calls, tot, avg, pct))
+    rows = _dispatches(db)
+    table, nsteps = occurrence_table(rows, args.step_end)
+    if nsteps:
+        out.append("")
+        out.append("Launches by position in a step (%d steady steps, each ending with %s):\n"
+                   % (nsteps, args.step_end))
+        out.append("| kernel | occurrence | launches | mean us | median us |")
+        out.append("|---|---:|---:|---:|---:|")
+        for (k, i), d in sorted(table.items(), key=lambda kv: -statistics.mean(kv[1])):
+            if statistics.mean(d) < args.min_us:
+                continue
+            out.append("| %s | %d | %d | %.2f | %.2f |" % (k, i, len(d), statistics.mean(d), statistics.median(d)))
+    print("\n".join(out))
+
+
+def _counter_per_dispatch(db, counter: str):
+    """[(kernel name, dispatch start, value)] of one PMC counter, in dispatch order."""
+    return db.execute("select name, start, counter_value from pmc_events where counter_name = ? order by start",
+                      (counter,)).fetchall()
+
+
+def _pick(vals, kernel: str, occurrence: int, step_end: str):
+    """Mean counter value of the occurrence-th launch of `kernel` per step."""
+    steps, cur = [], []
+    for name, _, v in vals:
+        cur.append((name, v))
+        if step_end in name:
+            steps.append(cur)
+            cur = []
+    picked = []
+    for st in steps:
+        n = [v for name, v in st if kernel in name]
+        if len(n) > occurrence:
+            picked.append(n[occurrence])
+    return statistics.mean(picked) if picked else None, len(picked)
+
+
+def cmd_traffic(args):
+    out = {"command": args.cmd, "kernel": args.kernel, "occurrence": args.occurrence}
+    for counter, path in (("FETCH_SIZE", args.fetch_db), ("WRITE_SIZE", args.write_db)):
+        db = sqlite3.connect(path)
+        vals = _counter_per_dispatch(db, counter)
+        kv, n = _pick(vals, args.kernel, args.occurrence, args.step_end)
+        copies = [v for name, _, v in vals if args.copy_kernel in name]
+        cv = max(copies) if copies else None
+        scale = args.copy_bytes / (cv * 1024.0) if cv else None
+        out[counter] = {"kib_per_launch": kv, "launches": n, "copy_kib": cv,
+                        "scale": scale, "bytes_per_launch": kv * 1024.0 * scale if (kv and scale) else None}
+    f, w = out["FETCH_SIZE"]["bytes_per_launch"], out["WRITE_SIZE"]["bytes_per_launch"]
+    out["bytes_per_launch"] = f + w if (f is not None and w is not None) else None
+    print(json.dumps(out, indent=1))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    sub = ap.add_subparsers(dest="cmd_name", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("db")
+    s.add_argument("--cmd", default="")
+    s.add_argument("--top", type=int, default=30)
+    s.add_argument("--step-end", default="k_materialize")
+    s.add_argument("--min-us", type=float, default=5.0)
+    s.set_defaults(fn=cmd_stats)
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_db")
+    t.add_argument("write_db")
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--occurrence", type=int, default=0)
+    t.add_argument("--copy-kernel", default="copyBuffer")
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--step-end", default="k_materialize")
+    t.add_argument("--cmd", default="")
+    t.set_defaults(fn=cmd_traffic)
+    args = ap.parse_args(argv)
+    args.fn(args)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
