@@ -198,9 +198,8 @@ sj_status sj_profile_count(const sj_plan_t *plan, int32_t *n);
  *                       a survivor-list source) read, its row id and columns written;
  *   "bfb_hist:..."      filter build, region counts: the inserted keys (and the
  *                       predicate column of a full scan) read;
- *   "bfb_scatter:..."   the keys read again, one 8-byte staged entry per kept key
- *                       written;
- *   "bfb_region:..."    the staged entries read, the filter written once;
+ *   "bfb_scatter:..."   the keys read again, each kept key staged (4 bytes);
+ *   "bfb_region:..."    the staged keys read, the filter written once;
  *   "materialize"       the result tuples written. */
 sj_status sj_profile_entry(const sj_plan_t *plan, int32_t i, const char **label, double *total_ms,
                            uint64_t *launches, uint64_t *alg_bytes);

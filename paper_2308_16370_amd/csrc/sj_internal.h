@@ -105,7 +105,7 @@ struct BuildArgs {
     uint32_t region_blocks;    // kRegionBytes / (block bytes)
     uint32_t *hist;            // [regions * tiles] counts, then their exclusive prefix
     uint64_t *keep;            // [(n_max + tile) / 64] bit e: element e is staged
-    uint2 *stage;              // [n_max] staged keys: (block index, second hash word)
+    uint32_t *stage;           // [n_max] staged keys, grouped by region
     uint32_t *total_dev;       // number of staged keys (zeroed before)
     Lookback lb;               // scan state (zeroed before)
     uint32_t seed;

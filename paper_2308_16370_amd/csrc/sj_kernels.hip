@@ -336,10 +336,10 @@ hipError_t launch_sieve_compact(const StepArgs &a, uint32_t max_rows, hipStream_
 // MI355X whatever the footprint), so a filter is built by region: a region is a run of
 // consecutive blocks small enough for one workgroup's LDS. (1) every tile counts its
 // keys per region; (2) an exclusive scan over (region, tile) gives each tile its slice
-// of every region's bucket; (3) each key's block and second hash word are scattered
-// into its region's bucket; (4) one workgroup per region sets the bits of its bucket
-// with LDS atomics and writes the region out with plain coalesced stores, which also
-// clears the bits no key sets.
+// of every region's bucket; (3) each kept key is scattered into its region's bucket;
+// (4) one workgroup per region rehashes its bucket's keys, sets their bits with LDS
+// atomics and writes the region out with plain coalesced stores, which also clears
+// the bits no key sets.
 
 __device__ __forceinline__ bool bfb_take(const BuildArgs &a, uint32_t e, int32_t &key) {
     if (a.pred) {
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(kBuildBlock) void k_bfb_scatter(BuildArgs a) {
                 if (take[u]) {
                     const BfKey h = bf_hash(key[u], a.seed, sh.nb);
                     const uint32_t pos = atomicAdd(&s_off[h.block / a.region_blocks], 1u);
-                    a.stage[pos] = make_uint2(h.block, h.g);
+                    a.stage[pos] = static_cast<uint32_t>(key[u]);
                 }
             }
         }
@@ -529,9 +529,10 @@ __global__ __launch_bounds__(kRegionThreads) void k_bfb_region(BuildArgs a) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint32_t e = e0 + u * kRegionThreads;
-                const uint2 st = e < end ? a.stage[e] : make_uint2(0u, 0u);
-                bb[u] = e < end ? st.x - b0 : 0xFFFFFFFFu;
-                gg[u] = st.y;
+                // the staged key's block (inside this region) and second hash word, recomputed
+                const BfKey h = bf_hash(static_cast<int32_t>(e < end ? a.stage[e] : 0u), a.seed, sh.nb);
+                bb[u] = e < end ? h.block - b0 : 0xFFFFFFFFu;
+                gg[u] = h.g;
             }
             // read every word the batch touches first, then OR only the bits still clear:
             // heavy-hitter keys staged by many tiles find their bits set and cost no atomic

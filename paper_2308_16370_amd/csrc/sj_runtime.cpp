@@ -444,7 +444,7 @@ static void build_layout(sj_plan_t *p) {
     p->off_sbits = L.take(max_rows / 8 + 16);
     p->off_scounts = L.take(4ull * kSieveGrid);
     p->off_bhist = L.take(4 * max_hist);
-    p->off_stage[0] = L.take(8ull * std::max<uint32_t>(1, max_build_rows));
+    p->off_stage[0] = L.take(4ull * std::max<uint32_t>(1, max_build_rows));
     p->off_keep = L.take(8ull * ((uint64_t(max_build_rows) + 2 * build_tile_of(max_build_rows)) / 64 + 1));
     p->zero[2].begin = L.top;
     p->off_totals = L.take(16);
@@ -798,7 +798,7 @@ static sj_status run_steps(sj_plan_t *p, int phase) {
             ba.nblocks_max = static_cast<uint32_t>(p->filters[f].max_words / (p->opts.block_bits / 32));
             ba.region_blocks = p->region_blocks;
             ba.hist = at<uint32_t>(p, p->off_bhist);
-            ba.stage = at<uint2>(p, p->off_stage[0]);
+            ba.stage = at<uint32_t>(p, p->off_stage[0]);
             ba.keep = at<uint64_t>(p, p->off_keep);
             ba.total_dev = at<uint32_t>(p, st.off_btotal[b]);
             ba.lb.status = at<uint64_t>(p, st.off_bstatus[b]);
@@ -1222,8 +1222,8 @@ extern "C" sj_status sj_profile_collect(sj_plan_t *p) {
                         uint64_t(nout) * 4 * (ncol + 1);
             } else if (r.kind >= kProfBuild0) {
                 // keys read once (with the predicate column of a full scan): by the count and
-                // the scatter stages; the staged (block, hash word) pairs: written by the
-                // scatter, read by the region stage, which writes the filter once
+                // the scatter stages; the staged keys: written by the scatter, read by the
+                // region stage, which writes the filter once
                 const int bi = (r.kind - kProfBuild0) / kBuildStages, stg = (r.kind - kProfBuild0) % kBuildStages;
                 const auto &bl = st.builds[static_cast<size_t>(bi)];
                 const uint64_t n = st.out >= 0 ? nout : nin;
@@ -1232,8 +1232,8 @@ extern "C" sj_status sj_profile_collect(sj_plan_t *p) {
                 SJ_HIP(p->ctx, hipMemcpy(&staged, at<uint32_t>(p, st.off_btotal[static_cast<size_t>(bi)]), 4,
                                          hipMemcpyDeviceToHost));
                 if (stg == 0) bytes = keys;
-                else if (stg == 2) bytes = keys + uint64_t(staged) * 8;
-                else if (stg == 3) bytes = uint64_t(staged) * 8 + uint64_t(nb[bl.second]) * fbytes;
+                else if (stg == 2) bytes = keys + uint64_t(staged) * 4;
+                else if (stg == 3) bytes = uint64_t(staged) * 4 + uint64_t(nb[bl.second]) * fbytes;
             }
             acc.bytes = bytes;
         } else if (r.kind == kProfResult) {
