@@ -362,28 +362,65 @@ hipError_t launch_build_buckets(const uint32_t *list_rid, const int32_t *const *
 // w(e) = prod over children c of W_c(key_c(e)), v(e) = f(rel, rid(e)) * prod V_c(...),
 // with W_c / V_c the totals of the child's bucket for that key (0 if absent).
 
-__device__ __forceinline__ void dp_entry(const DpArgs &a, const uint32_t *masks, uint32_t e, uint64_t &w,
-                                         uint64_t &v) {
-    w = 1;
-    v = chk_factor(a.rel, a.rid[e]);
+// The kScanItems entries of a thread go through each lookup stage together, so the
+// loads of a stage are independent and in flight at once (key, hash slot, directory
+// bounds, child prefix weights); a slot that holds another key (rare: the index is at
+// most half full) is resolved by linear probing afterwards.
+__device__ __forceinline__ void dp_entries(const DpArgs &a, const uint32_t *masks, uint32_t base, uint32_t n,
+                                           uint64_t *w, uint64_t *v) {
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const uint32_t e = base + i;
+        w[i] = 1;
+        v[i] = e < n ? chk_factor(a.rel, a.rid[e]) : 0;
+    }
 #pragma unroll
     for (int c = 0; c < kMaxJCols; ++c) {
         if (c < a.nchild) {
-            const int32_t key = a.col[a.child_col[c]][e];
-            const int64_t d = dir_find(a.child[c].slots, masks[c], key);
-            uint32_t lo = 0, hi = 0;
-            if (d >= 0) {
-                lo = a.child[c].dir_begin[d];
-                hi = a.child[c].dir_begin[d + 1];
+            const int32_t *col = a.col[a.child_col[c]];
+            const uint64_t *slots = a.child[c].slots;
+            int32_t key[kScanItems];
+            uint32_t sl[kScanItems];
+            uint64_t sv[kScanItems];
+#pragma unroll
+            for (int i = 0; i < kScanItems; ++i) key[i] = base + i < n ? col[base + i] : 0;
+#pragma unroll
+            for (int i = 0; i < kScanItems; ++i) {
+                sl[i] = slot_hash(key[i]) & masks[c];
+                sv[i] = slots[sl[i]];
             }
-            a.blo[c][e] = lo;
-            a.bhi[c][e] = hi;
+            uint32_t lo[kScanItems], hi[kScanItems];
+#pragma unroll
+            for (int i = 0; i < kScanItems; ++i) {
+                while (sv[i] != 0 && static_cast<uint32_t>(sv[i]) != static_cast<uint32_t>(key[i])) {
+                    sl[i] = (sl[i] + 1) & masks[c];
+                    sv[i] = slots[sl[i]];
+                }
+                const uint32_t d = static_cast<uint32_t>(sv[i] >> 32);   // directory index + 1, 0: absent
+                lo[i] = d ? a.child[c].dir_begin[d - 1] : 0u;
+                hi[i] = d ? a.child[c].dir_begin[d] : 0u;
+            }
+#pragma unroll
+            for (int i = 0; i < kScanItems; ++i) {
+                const uint32_t e = base + i;
+                if (e < n) {
+                    a.blo[c][e] = lo[i];
+                    a.bhi[c][e] = hi[i];
+                }
+            }
             if (!(a.skip_mask & (1u << c))) {
-                w *= a.child[c].cw[hi] - a.child[c].cw[lo];
-                v *= a.child[c].cv[hi] - a.child[c].cv[lo];
+                const uint64_t *cw = a.child[c].cw, *cv = a.child[c].cv;
+#pragma unroll
+                for (int i = 0; i < kScanItems; ++i) {
+                    w[i] *= cw[hi[i]] - cw[lo[i]];
+                    v[i] *= cv[hi[i]] - cv[lo[i]];
+                }
             }
         }
     }
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i)
+        if (base + i >= n) w[i] = v[i] = 0;
 }
 
 // Phase 1: per-entry weights into cw/cv (not yet scanned) and per-tile sums.
@@ -396,18 +433,17 @@ __global__ __launch_bounds__(kScanBlock) void k_dp_reduce(DpArgs a) {
     for (int c = 0; c < kMaxJCols; ++c) masks[c] = c < a.nchild ? *a.child[c].slot_mask : 0u;
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const uint32_t base = tile * kScanTile + threadIdx.x * kScanItems;
+        uint64_t w[kScanItems], v[kScanItems];
+        dp_entries(a, masks, base, n, w, v);
         uint64_t sw = 0, sv = 0;
 #pragma unroll
         for (int i = 0; i < kScanItems; ++i) {
-            const uint32_t e = base + i;
-            if (e < n) {
-                uint64_t w, v;
-                dp_entry(a, masks, e, w, v);
-                a.cw[e] = w;
-                a.cv[e] = v;
-                sw += w;
-                sv += v;
+            if (base + i < n) {
+                a.cw[base + i] = w[i];
+                a.cv[base + i] = v[i];
             }
+            sw += w[i];
+            sv += v[i];
         }
         uint64_t tw, tv;
         block_excl_scan<kScanBlock>(sw, s_w, tw);
