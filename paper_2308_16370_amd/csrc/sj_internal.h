@@ -15,7 +15,14 @@ constexpr int kMaxK = 12;       // bits per key
 constexpr int kSieveBlock = 256;
 constexpr int kSieveItems = 8;
 constexpr int kSieveTile = kSieveBlock * kSieveItems;
-constexpr uint32_t kSieveGrid = 1024;   // workgroups of a sieve scan; workgroup b owns a contiguous run of tiles
+
+// Sieve scans (probe and compaction) run one 1024-thread workgroup per CU, so a
+// workgroup can hold a filter of up to kLdsFilterBytes in LDS; workgroup b owns a
+// contiguous run of tiles.
+constexpr int kProbeBlock = 1024;
+constexpr uint32_t kProbeGrid = 256;
+constexpr int kProbeTile = kProbeBlock * kSieveItems;
+constexpr uint32_t kLdsFilterBytes = 124 * 1024;
 
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;
@@ -59,7 +66,8 @@ struct StepArgs {
     int32_t *out_col[kMaxJCols];
     uint32_t *out_count;       // device-side survivor count (written when out_rid != nullptr)
     uint8_t *bits;             // [ceil(rows / 8)] survivor flags of the scan, 8 rows per byte
-    uint32_t *counts;          // [kSieveGrid] survivors per workgroup
+    uint32_t *counts;          // [kProbeGrid] survivors per workgroup
+    uint32_t lds_words;        // LDS words set aside for one probed filter (0: none)
     uint32_t seed;
     int k;
     int logB;

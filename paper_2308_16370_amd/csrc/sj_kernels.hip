@@ -60,8 +60,8 @@ hipError_t launch_count_pred(const int32_t *col, uint32_t n, int32_t lo, int32_t
 }
 
 // ---- the sieve step ------------------------------------------------------------------
-// Two passes with no inter-workgroup waiting. Workgroup b of kSieveGrid owns the rows
-// [b * R, (b + 1) * R), R a multiple of kSieveTile. (1) k_sieve_step probes every row
+// Two passes with no inter-workgroup waiting. Workgroup b of kProbeGrid owns the rows
+// [b * R, (b + 1) * R), R a multiple of kProbeTile. (1) k_sieve_step probes every row
 // and records a survivor bit per row and a survivor count per workgroup. (2)
 // k_sieve_compact sums the counts of the workgroups before it and writes its survivors
 // (row id and join columns, ascending row order) from the bits. (A single pass with a
@@ -77,7 +77,7 @@ hipError_t launch_count_pred(const int32_t *col, uint32_t n, int32_t lo, int32_t
 // entry holds the remaining bits of c and two flags, so one 32-bit store publishes a
 // consistent entry and a tag match identifies the key exactly.
 #ifndef SJ_MAX_CACHED
-#define SJ_MAX_CACHED 4
+#define SJ_MAX_CACHED 2
 #endif
 #ifndef SJ_CACHE_LOG
 #define SJ_CACHE_LOG 11
@@ -87,7 +87,7 @@ hipError_t launch_count_pred(const int32_t *col, uint32_t n, int32_t lo, int32_t
 #endif
 constexpr int kMaxCached = SJ_MAX_CACHED;
 constexpr int kCacheLog = SJ_CACHE_LOG;
-constexpr int kProbeBatch = SJ_PROBE_BATCH;
+constexpr int kProbeBatchMax = SJ_PROBE_BATCH;
 constexpr uint32_t kCacheMul = 0x9E3779B1u;
 constexpr uint32_t kCacheOk = 1u, kCacheValid = 2u;
 constexpr uint32_t kCacheFlags = (1u << kCacheLog) - 1u;
@@ -97,15 +97,137 @@ __device__ __forceinline__ uint32_t cache_slot(uint32_t c) { return c >> (32 - k
 __device__ __forceinline__ uint32_t cache_tag(uint32_t c) { return c << kCacheLog; }
 
 __device__ __forceinline__ uint32_t sieve_rows_per_group(uint32_t n) {
-    const uint32_t per = (n + kSieveGrid - 1) / kSieveGrid;
-    return (per + kSieveTile - 1) / kSieveTile * kSieveTile;
+    const uint32_t per = (n + kProbeGrid - 1) / kProbeGrid;
+    return (per + kProbeTile - 1) / kProbeTile * kProbeTile;
 }
 
+// Order a wave's LDS writes before its later LDS reads by other lanes of the wave.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The kSieveItems keys of rows row0 .. row0 + 7 of a column (0 past the end).
+__device__ __forceinline__ void load_keys(const int32_t *col, uint32_t row0, uint32_t n, bool full, int32_t *k) {
+    if (full) {
+        const v4i *src = reinterpret_cast<const v4i *>(col + row0);
+        const v4i x0 = __builtin_nontemporal_load(src);
+        const v4i x1 = __builtin_nontemporal_load(src + 1);
+        k[0] = x0.x; k[1] = x0.y; k[2] = x0.z; k[3] = x0.w;
+        k[4] = x1.x; k[5] = x1.y; k[6] = x1.z; k[7] = x1.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < kSieveItems; ++i) k[i] = row0 + i < n ? col[row0 + i] : 0;
+    }
+}
+
+// One probe of a batch of keys against a filter in memory, through the LDS answer
+// cache of probe slot `cslot` (no cache when cslot < 0). live[ii]: the key needs an
+// answer; on return, live[ii] is cleared for keys the filter rejects.
+template <int B, int KMAX>
+__device__ __forceinline__ void probe_global(const StepArgs &a, const uint32_t *words, uint32_t nb,
+                                             uint32_t *cache, const int32_t *keys, bool *live,
+                                             uint32_t wpb_shift, uint32_t sh) {
+    uint32_t blk[B], g[B], kc[B];
+    uint32_t need = 0;
+#pragma unroll
+    for (int ii = 0; ii < B; ++ii) {
+        kc[ii] = static_cast<uint32_t>(keys[ii]) * kCacheMul;
+        blk[ii] = 0;
+        g[ii] = 0;
+        if (live[ii]) {
+            bool hit = false;
+            if (cache) {
+                const uint32_t e = cache[cache_slot(kc[ii])];
+                if ((e & ~kCacheFlags) == cache_tag(kc[ii]) && (e & kCacheValid)) {
+                    hit = true;
+                    if (!(e & kCacheOk)) live[ii] = false;
+                }
+            }
+            if (!hit) {
+                const BfKey h = bf_hash(keys[ii], a.seed, nb);
+                blk[ii] = h.block;
+                g[ii] = h.g;
+                need |= 1u << ii;
+            }
+        }
+    }
+    uint32_t w[B][KMAX];
+#pragma unroll
+    for (int ii = 0; ii < B; ++ii) {
+        if (need & (1u << ii)) {
+            const uint32_t *b = words + (static_cast<uint64_t>(blk[ii]) << wpb_shift);
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j)
+                if (j < a.k) w[ii][j] = b[((g[ii] * bf_mult(j)) >> sh) >> 5];
+        }
+    }
+#pragma unroll
+    for (int ii = 0; ii < B; ++ii) {
+        if (need & (1u << ii)) {
+            uint32_t ok = 1u;
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j)
+                if (j < a.k) ok &= w[ii][j] >> (((g[ii] * bf_mult(j)) >> sh) & 31u);
+            ok &= 1u;
+            if (!ok) live[ii] = false;
+            if (cache) cache[cache_slot(kc[ii])] = cache_tag(kc[ii]) | kCacheValid | ok;
+        }
+    }
+}
+
+// A wave's list of live rows: entry = the row's index inside the wave's rows (9 bits)
+// plus a dead flag.
+constexpr uint16_t kListDead = 0x8000;
+
 template <int NCOL, int KMAX>
-__global__ __launch_bounds__(kSieveBlock) void k_sieve_step(StepArgs a) {
-    __shared__ uint32_t s_wave[kSieveBlock / 64];
+__global__ __launch_bounds__(kProbeBlock) void k_sieve_step(StepArgs a) {
+    // keys whose k words are in flight together (fewer for k > 8, to stay in registers)
+    constexpr int kProbeBatch = KMAX > 8 ? kProbeBatchMax / 2 : kProbeBatchMax;
+    constexpr int kWaveRows = 64 * kSieveItems;
+    __shared__ uint32_t s_wave[kProbeBlock / 64];
     __shared__ uint32_t s_cache[kMaxCached > 0 ? kMaxCached : 1][1 << kCacheLog];
-    for (int i = threadIdx.x; i < kMaxCached * (1 << kCacheLog); i += kSieveBlock) (&s_cache[0][0])[i] = 0;
+    __shared__ uint16_t s_list[kProbeBlock / 64][kWaveRows];
+    extern __shared__ v4u s_filter4[];   // [a.lds_words / 4]
+    const uint32_t *s_filter = reinterpret_cast<const uint32_t *>(s_filter4);
+    for (int i = threadIdx.x; i < kMaxCached * (1 << kCacheLog); i += kProbeBlock) (&s_cache[0][0])[i] = 0;
+    const uint32_t wpb_shift = static_cast<uint32_t>(a.logB) - 5u;   // words per block = 1 << wpb_shift
+    const uint32_t sh = 32u - static_cast<uint32_t>(a.logB);
+    // The smallest probed filter that fits the LDS set aside is copied there. The first
+    // probe (that filter, else probe 0 from memory) covers every row; the others are
+    // probed from memory for the rows still alive, gathered densely per wave.
+    int pl = -1;
+    uint32_t nb_l = 0, best = 0xFFFFFFFFu;
+    const uint32_t *lsrc = nullptr;
+    if (a.lds_words) {
+#pragma unroll
+        for (int p = 0; p < kMaxProbe; ++p) {
+            if (p < a.nprobe) {
+                const uint32_t nbp = *a.probe[p].nblocks;
+                const uint32_t words = nbp << wpb_shift;
+                if (words <= a.lds_words && words < best) {
+                    best = words;
+                    pl = p;
+                    nb_l = nbp;
+                    lsrc = a.probe[p].words;
+                }
+            }
+        }
+        if (pl >= 0)
+            for (uint32_t w = threadIdx.x; w < best / 4; w += kProbeBlock)
+                s_filter4[w] = reinterpret_cast<const v4u *>(lsrc)[w];
+    }
+    const int first = pl >= 0 ? pl : 0;   // the probe that covers every row
+    // column each probe reads (selected once: no run-time indexing of the argument block)
+    const int32_t *pcol[kMaxProbe];
+#pragma unroll
+    for (int p = 0; p < kMaxProbe; ++p) {
+        pcol[p] = a.col[0];
+#pragma unroll
+        for (int c = 1; c < NCOL; ++c)
+            if (p < a.nprobe && a.probe_col[p] == c) pcol[p] = a.col[c];
+    }
     __syncthreads();
 
     const bool list = a.src_rid != nullptr;
@@ -113,42 +235,14 @@ __global__ __launch_bounds__(kSieveBlock) void k_sieve_step(StepArgs a) {
     const uint32_t per = sieve_rows_per_group(n);
     const uint32_t r_end = min(n, (blockIdx.x + 1) * per);
     const int tid = threadIdx.x;
+    const int lane = lane_id();
+    uint16_t *wl = s_list[tid >> 6];
     uint32_t survivors = 0;
-    const uint32_t wpb_shift = static_cast<uint32_t>(a.logB) - 5u;   // words per block = 1 << wpb_shift
-    const uint32_t sh = 32u - static_cast<uint32_t>(a.logB);
-    uint32_t used = 0;   // columns some filter probes (the compaction reads the others)
-#pragma unroll
-    for (int p = 0; p < kMaxProbe; ++p)
-        if (p < a.nprobe) used |= 1u << a.probe_col[p];
 
-    for (uint32_t t0 = blockIdx.x * per; t0 < r_end; t0 += kSieveTile) {
+    for (uint32_t t0 = blockIdx.x * per; t0 < r_end; t0 += kProbeTile) {
         const uint32_t row0 = t0 + tid * kSieveItems;
-
-        int32_t v[NCOL][kSieveItems];
+        const uint32_t wrow0 = t0 + (tid & ~63) * kSieveItems;   // the wave's first row
         const bool full = row0 + kSieveItems <= n;
-        if (full) {
-#pragma unroll
-            for (int c = 0; c < NCOL; ++c) {
-                if (!((used >> c) & 1u)) {
-#pragma unroll
-                    for (int i = 0; i < kSieveItems; ++i) v[c][i] = 0;
-                    continue;
-                }
-                const v4i *src = reinterpret_cast<const v4i *>(a.col[c] + row0);
-                const v4i x0 = __builtin_nontemporal_load(src);
-                const v4i x1 = __builtin_nontemporal_load(src + 1);
-                v[c][0] = x0.x; v[c][1] = x0.y; v[c][2] = x0.z; v[c][3] = x0.w;
-                v[c][4] = x1.x; v[c][5] = x1.y; v[c][6] = x1.z; v[c][7] = x1.w;
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < kSieveItems; ++i) {
-                const uint32_t r = row0 + i;
-                const bool in = r < n;
-#pragma unroll
-                for (int c = 0; c < NCOL; ++c) v[c][i] = (in && ((used >> c) & 1u)) ? a.col[c][r] : 0;
-            }
-        }
 
         uint32_t flags = 0;
 #pragma unroll
@@ -162,99 +256,129 @@ __global__ __launch_bounds__(kSieveBlock) void k_sieve_step(StepArgs a) {
             flags |= (ok ? 1u : 0u) << i;
         }
 
+        // (1) the first probe, per lane over its rows
+        if (a.nprobe > 0 && flags) {
+            int32_t key[kSieveItems];
 #pragma unroll
-        for (int p = 0; p < kMaxProbe; ++p) {
-            if (p < a.nprobe) {
-                const uint32_t nb = *a.probe[p].nblocks;
-                const uint32_t *words = a.probe[p].words;
+            for (int p = 0; p < kMaxProbe; ++p)
+                if (p == first) load_keys(pcol[p], row0, n, full, key);
+            if (pl >= 0) {
+                // the LDS filter: all k words of a batch's keys are read before any is tested
 #pragma unroll
                 for (int i0 = 0; i0 < kSieveItems; i0 += kProbeBatch) {
-                    uint32_t blk[kProbeBatch], g[kProbeBatch], kc[kProbeBatch];
-                    int32_t key[kProbeBatch];
-                    uint32_t need = 0;
+                    uint32_t w[kProbeBatch][KMAX], g[kProbeBatch];
 #pragma unroll
                     for (int ii = 0; ii < kProbeBatch; ++ii) {
-                        const int i = i0 + ii;
-                        key[ii] = v[0][i];
+                        const BfKey h = bf_hash(key[i0 + ii], a.seed, nb_l);
+                        g[ii] = h.g;
+                        const uint32_t *b = s_filter + (h.block << wpb_shift);
 #pragma unroll
-                        for (int c = 1; c < NCOL; ++c)
-                            if (a.probe_col[p] == c) key[ii] = v[c][i];
-                        kc[ii] = static_cast<uint32_t>(key[ii]) * kCacheMul;
-                        blk[ii] = 0;
-                        g[ii] = 0;
-                        if (flags & (1u << i)) {
-                            bool hit = false;
-                            if (p < kMaxCached) {
-                                const uint32_t e = s_cache[p < kMaxCached ? p : 0][cache_slot(kc[ii])];
-                                if ((e & ~kCacheFlags) == cache_tag(kc[ii]) && (e & kCacheValid)) {
-                                    hit = true;
-                                    if (!(e & kCacheOk)) flags &= ~(1u << i);
-                                }
-                            }
-                            if (!hit) {
-                                const BfKey h = bf_hash(key[ii], a.seed, nb);
-                                blk[ii] = h.block;
-                                g[ii] = h.g;
-                                need |= 1u << ii;
-                            }
-                        }
-                    }
-                    uint32_t w[kProbeBatch][KMAX];
-#pragma unroll
-                    for (int ii = 0; ii < kProbeBatch; ++ii) {
-                        if (need & (1u << ii)) {
-                            const uint32_t *b = words + (static_cast<uint64_t>(blk[ii]) << wpb_shift);
-#pragma unroll
-                            for (int j = 0; j < KMAX; ++j)
-                                if (j < a.k) w[ii][j] = b[((g[ii] * bf_mult(j)) >> sh) >> 5];
-                        }
+                        for (int j = 0; j < KMAX; ++j)
+                            if (j < a.k) w[ii][j] = b[((h.g * bf_mult(j)) >> sh) >> 5];
                     }
 #pragma unroll
                     for (int ii = 0; ii < kProbeBatch; ++ii) {
-                        if (need & (1u << ii)) {
-                            uint32_t ok = 1u;
+                        uint32_t ok = 1u;
 #pragma unroll
-                            for (int j = 0; j < KMAX; ++j)
-                                if (j < a.k) ok &= w[ii][j] >> (((g[ii] * bf_mult(j)) >> sh) & 31u);
-                            ok &= 1u;
-                            if (!ok) flags &= ~(1u << (i0 + ii));
-                            if (p < kMaxCached)
-                                s_cache[p < kMaxCached ? p : 0][cache_slot(kc[ii])] = cache_tag(kc[ii]) | kCacheValid | ok;
-                        }
+                        for (int j = 0; j < KMAX; ++j)
+                            if (j < a.k) ok &= w[ii][j] >> (((g[ii] * bf_mult(j)) >> sh) & 31u);
+                        if (!(ok & 1u)) flags &= ~(1u << (i0 + ii));
                     }
                 }
+            } else {
+                const uint32_t nb0 = *a.probe[0].nblocks;
+#pragma unroll
+                for (int i0 = 0; i0 < kSieveItems; i0 += kProbeBatch) {
+                    bool live[kProbeBatch];
+#pragma unroll
+                    for (int ii = 0; ii < kProbeBatch; ++ii) live[ii] = (flags >> (i0 + ii)) & 1u;
+                    probe_global<kProbeBatch, KMAX>(a, a.probe[0].words, nb0, kMaxCached > 0 ? s_cache[0] : nullptr,
+                                                    key + i0, live, wpb_shift, sh);
+#pragma unroll
+                    for (int ii = 0; ii < kProbeBatch; ++ii)
+                        if (!live[ii]) flags &= ~(1u << (i0 + ii));
+                }
             }
+        }
+
+        // (2) the other probes, over the wave's live rows gathered into a dense list
+        if (a.nprobe > 1) {
+            const uint32_t cnt = __builtin_popcount(flags);
+            const uint32_t incl = wave_incl_scan(cnt);
+            const uint32_t total = __shfl(incl, 63, 64);
+            {
+                uint32_t j = incl - cnt;
+#pragma unroll
+                for (int i = 0; i < kSieveItems; ++i)
+                    if (flags & (1u << i)) wl[j++] = static_cast<uint16_t>(lane * kSieveItems + i);
+            }
+            wave_lds_sync();
+#pragma unroll
+            for (int p = 0; p < kMaxProbe; ++p) {
+                if (p < a.nprobe && p != first && total) {
+                    const uint32_t nbp = *a.probe[p].nblocks;
+                    for (uint32_t e0 = lane; e0 < total; e0 += 64u * kProbeBatch) {
+                        int32_t keys[kProbeBatch];
+                        bool live[kProbeBatch];
+                        uint16_t ent[kProbeBatch];
+#pragma unroll
+                        for (int ii = 0; ii < kProbeBatch; ++ii) {
+                            const uint32_t e = e0 + ii * 64u;
+                            ent[ii] = e < total ? wl[e] : kListDead;
+                            live[ii] = !(ent[ii] & kListDead);
+                            keys[ii] = live[ii] ? pcol[p][wrow0 + (ent[ii] & (kWaveRows - 1))] : 0;
+                        }
+                        probe_global<kProbeBatch, KMAX>(a, a.probe[p].words, nbp,
+                                                        (p < kMaxCached) ? s_cache[p < kMaxCached ? p : 0] : nullptr,
+                                                        keys, live, wpb_shift, sh);
+#pragma unroll
+                        for (int ii = 0; ii < kProbeBatch; ++ii) {
+                            const uint32_t e = e0 + ii * 64u;
+                            if (e < total && !(ent[ii] & kListDead) && !live[ii]) wl[e] = ent[ii] | kListDead;
+                        }
+                    }
+                    wave_lds_sync();
+                }
+            }
+            {
+                uint32_t j = incl - cnt;
+#pragma unroll
+                for (int i = 0; i < kSieveItems; ++i)
+                    if (flags & (1u << i))
+                        if (wl[j++] & kListDead) flags &= ~(1u << i);
+            }
+            wave_lds_sync();
         }
 
         if (row0 < n) a.bits[row0 >> 3] = static_cast<uint8_t>(flags);
         survivors += __builtin_popcount(flags);
     }
     uint32_t tot;
-    block_excl_scan<kSieveBlock>(survivors, s_wave, tot);
+    block_excl_scan<kProbeBlock>(survivors, s_wave, tot);
     if (tid == 0) a.counts[blockIdx.x] = tot;
 }
 
 
 // Survivors of workgroup b's rows, written after those of workgroups 0 .. b-1.
 template <int NCOL>
-__global__ __launch_bounds__(kSieveBlock) void k_sieve_compact(StepArgs a) {
-    __shared__ uint32_t s_wave[kSieveBlock / 64];
+__global__ __launch_bounds__(kProbeBlock) void k_sieve_compact(StepArgs a) {
+    __shared__ uint32_t s_wave[kProbeBlock / 64];
     const bool list = a.src_rid != nullptr;
     const uint32_t n = list ? *a.src_count : a.src_rows;
     const uint32_t per = sieve_rows_per_group(n);
     const int tid = threadIdx.x;
     uint32_t before = 0;
-    for (uint32_t g = tid; g < blockIdx.x; g += kSieveBlock) before += a.counts[g];
+    for (uint32_t g = tid; g < blockIdx.x; g += kProbeBlock) before += a.counts[g];
     uint32_t tot;
-    block_excl_scan<kSieveBlock>(before, s_wave, tot);
+    block_excl_scan<kProbeBlock>(before, s_wave, tot);
     uint32_t base = tot;
     if (blockIdx.x == gridDim.x - 1 && tid == 0) *a.out_count = base + a.counts[blockIdx.x];
     const uint32_t r_end = min(n, (blockIdx.x + 1) * per);
-    for (uint32_t t0 = blockIdx.x * per; t0 < r_end; t0 += kSieveTile) {
+    for (uint32_t t0 = blockIdx.x * per; t0 < r_end; t0 += kProbeTile) {
         const uint32_t row0 = t0 + tid * kSieveItems;
         const uint32_t flags = row0 < n ? a.bits[row0 >> 3] : 0u;
         uint32_t ttot;
-        uint32_t o = base + block_excl_scan<kSieveBlock>(static_cast<uint32_t>(__builtin_popcount(flags)), s_wave, ttot);
+        uint32_t o = base + block_excl_scan<kProbeBlock>(static_cast<uint32_t>(__builtin_popcount(flags)), s_wave, ttot);
         base += ttot;
         if (!flags) continue;
         int32_t v[NCOL][kSieveItems];
@@ -300,10 +424,11 @@ __global__ __launch_bounds__(kSieveBlock) void k_sieve_compact(StepArgs a) {
 
 template <int KMAX>
 static hipError_t launch_probe_k(const StepArgs &a, hipStream_t s) {
-    const dim3 g(kSieveGrid), b(kSieveBlock);
+    const dim3 g(kProbeGrid), b(kProbeBlock);
+    const size_t lds = 4ull * a.lds_words;
     switch (a.ncol) {
 #define SJ_PROBE_CASE(NC) \
-    case NC: hipLaunchKernelGGL((k_sieve_step<NC, KMAX>), g, b, 0, s, a); break;
+    case NC: hipLaunchKernelGGL((k_sieve_step<NC, KMAX>), g, b, lds, s, a); break;
         SJ_PROBE_CASE(1) SJ_PROBE_CASE(2) SJ_PROBE_CASE(3) SJ_PROBE_CASE(4)
         SJ_PROBE_CASE(5) SJ_PROBE_CASE(6) SJ_PROBE_CASE(7) SJ_PROBE_CASE(8)
 #undef SJ_PROBE_CASE
@@ -319,7 +444,7 @@ hipError_t launch_sieve_probe(const StepArgs &a, uint32_t max_rows, hipStream_t 
 
 hipError_t launch_sieve_compact(const StepArgs &a, uint32_t max_rows, hipStream_t s) {
     if (max_rows == 0 || !a.out_rid) return hipSuccess;
-    const dim3 g(kSieveGrid), b(kSieveBlock);
+    const dim3 g(kProbeGrid), b(kProbeBlock);
     switch (a.ncol) {
 #define SJ_COMPACT_CASE(NC) \
     case NC: hipLaunchKernelGGL((k_sieve_compact<NC>), g, b, 0, s, a); break;

@@ -442,7 +442,7 @@ static void build_layout(sj_plan_t *p) {
     uint32_t max_rows = 1;
     for (const Rel &R : p->rels) max_rows = std::max(max_rows, R.nrows);
     p->off_sbits = L.take(max_rows / 8 + 16);
-    p->off_scounts = L.take(4ull * kSieveGrid);
+    p->off_scounts = L.take(4ull * kProbeGrid);
     p->off_bhist = L.take(4 * max_hist);
     p->off_stage[0] = L.take(4ull * std::max<uint32_t>(1, max_build_rows));
     p->off_keep = L.take(8ull * ((uint64_t(max_build_rows) + 2 * build_tile_of(max_build_rows)) / 64 + 1));
@@ -757,6 +757,11 @@ static sj_status run_steps(sj_plan_t *p, int phase) {
             for (int c = 0; c < a.ncol; ++c) a.out_col[c] = list_col(p, st.rel, st.out, c);
             a.out_count = at<uint32_t>(p, st.off_count);
         }
+        // LDS for the smallest probed filter that fits (sizes are known on the device only)
+        a.lds_words = 0;
+        for (auto &pr : st.probes)
+            a.lds_words = std::max<uint32_t>(a.lds_words, static_cast<uint32_t>(std::min<uint64_t>(
+                                                               p->filters[pr.second].max_words, kLdsFilterBytes / 4)));
         a.bits = at<uint8_t>(p, p->off_sbits);
         a.counts = at<uint32_t>(p, p->off_scounts);
         a.seed = p->seed32;
