@@ -206,6 +206,68 @@ sj_status sj_profile_entry(const sj_plan_t *plan, int32_t i, const char **label,
 /* Collect, then zero every total. */
 sj_status sj_profile_reset(sj_plan_t *plan);
 
+/* ---- serving: continuous admission of join queries (extension) ----
+ *
+ * A server runs many queries of the kind sj_plan accepts on one GPU at once. It owns
+ * a caller-provided device arena (borrowed, 256-byte aligned, untouched by anyone
+ * else while the server lives) and `slots` worker threads, each with its own HIP
+ * stream (default priority). A query is admitted when a slot is free and its
+ * workspace fits in the free arena; the oldest queued query that fits goes first, so
+ * a later one may pass a query that does not fit yet. Once the exact count is known
+ * the result's bytes are taken from the arena (SJ_ERR_CAPACITY if they can never fit
+ * beside the workspace, SJ_ERR_NOMEM if no memory frees up within 2 s). The workspace
+ * is freed when the query finishes; the result stays until sj_server_release. When no
+ * query is running and no queued query fits for 2 s (the arena is held by results not
+ * yet released), the oldest queued query fails with SJ_ERR_NOMEM, so every query
+ * finishes or fails: callers release results as they consume them. Queries
+ * on different slots overlap on the device. Each query's count, checksum and tuples
+ * equal those of running it alone through sj_plan (same options): the kernels, inputs
+ * and schedule are the same. The relations' device columns are borrowed until the
+ * query is released. All server calls are thread-safe. */
+
+#define SJ_MAX_SLOTS 16
+
+#define SJ_QUERY_QUEUED 0
+#define SJ_QUERY_RUNNING 1
+#define SJ_QUERY_DONE 2
+#define SJ_QUERY_FAILED 3
+
+#define SJ_RESULT_TUPLES 0 /* materialise the tuples into the arena */
+#define SJ_RESULT_COUNT 1  /* count and checksum only */
+
+typedef struct sj_server sj_server;
+
+typedef struct {
+    int32_t state;           /* SJ_QUERY_* */
+    sj_status status;        /* SJ_OK, or the error that failed the query */
+    uint64_t count, checksum;
+    uint64_t result_offset;  /* byte offset of the count * nrels int32 tuples in the arena (DONE, tuples) */
+    uint64_t workspace_bytes;
+    int64_t t_submit_ns, t_admit_ns, t_done_ns; /* steady clock; 0 until reached */
+    int32_t slot;            /* worker that ran it, -1 before admission */
+    char error[160];         /* why the query failed ("" otherwise) */
+} sj_query_info;
+
+/* Start a server on HIP device `device` over arena [arena_dev, arena_dev + arena_bytes)
+ * with 1..SJ_MAX_SLOTS workers. */
+sj_status sj_server_create(int32_t device, void *arena_dev, uint64_t arena_bytes, int32_t slots, sj_server **out);
+/* Validate and queue a query (same arguments as sj_plan; `opts` may be NULL). A graph
+ * error or a workspace larger than the whole arena is returned here, and no ticket is
+ * issued; sj_server_last_error describes it. */
+sj_status sj_server_submit(sj_server *server, const sj_rel *rels, int32_t nrels, const sj_edge *edges,
+                           int32_t nedges, const sj_opts *opts, int32_t result_mode, uint64_t *ticket);
+/* State of a query; with wait != 0, block until it is DONE or FAILED. */
+sj_status sj_server_query(sj_server *server, uint64_t ticket, int32_t wait, sj_query_info *info);
+/* Forget a finished query and free its result (SJ_ERR_STATE while it is queued or running). */
+sj_status sj_server_release(sj_server *server, uint64_t ticket);
+/* Arena bytes in use and the peak so far, queries waiting for admission and running. */
+sj_status sj_server_stats(sj_server *server, uint64_t *arena_used, uint64_t *arena_peak, int32_t *queued,
+                          int32_t *running);
+/* Text of the last submit error. */
+const char *sj_server_last_error(const sj_server *server);
+/* Fail the queued queries, wait for the running ones and stop the workers. */
+sj_status sj_server_destroy(sj_server *server);
+
 #ifdef __cplusplus
 }
 #endif

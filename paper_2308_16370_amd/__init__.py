@@ -44,9 +44,14 @@ SJ_FILTER_CLOSING = 2
 EXPORTED = ["sj_ctx_create", "sj_ctx_set_stream", "sj_ctx_destroy", "sj_last_error", "sj_plan",
             "sj_bind_workspace", "sj_build_filters", "sj_sieve", "sj_join", "sj_result", "sj_plan_destroy",
             "sj_filter_count", "sj_filter_desc", "sj_filter_copy", "sj_survivors_copy", "sj_profile_collect",
-            "sj_profile_count", "sj_profile_entry", "sj_profile_reset"]
+            "sj_profile_count", "sj_profile_entry", "sj_profile_reset", "sj_server_create", "sj_server_submit",
+            "sj_server_query", "sj_server_release", "sj_server_stats", "sj_server_last_error",
+            "sj_server_destroy"]
 SJ_FLAG_PROFILE = 1
 SJ_FLAG_EAGER = 2
+SJ_MAX_SLOTS = 16
+SJ_QUERY_QUEUED, SJ_QUERY_RUNNING, SJ_QUERY_DONE, SJ_QUERY_FAILED = 0, 1, 2, 3
+SJ_RESULT_TUPLES, SJ_RESULT_COUNT = 0, 1
 
 
 class SjError(RuntimeError):
@@ -70,6 +75,14 @@ class _Opts(ctypes.Structure):
     _fields_ = [("bits_per_key", ctypes.c_uint32), ("k", ctypes.c_uint32), ("block_bits", ctypes.c_uint32),
                 ("passes", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("root", ctypes.c_int32),
                 ("flags", ctypes.c_uint32)]
+
+
+class _QueryInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("count", ctypes.c_uint64),
+                ("checksum", ctypes.c_uint64), ("result_offset", ctypes.c_uint64),
+                ("workspace_bytes", ctypes.c_uint64), ("t_submit_ns", ctypes.c_int64),
+                ("t_admit_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64), ("slot", ctypes.c_int32),
+                ("error", ctypes.c_char * 160)]
 
 
 _lib = None
@@ -103,6 +116,12 @@ def lib():
             "sj_profile_count": [V, P(i32)],
             "sj_profile_entry": [V, i32, P(ctypes.c_char_p), P(ctypes.c_double), P(u64), P(u64)],
             "sj_profile_reset": [V],
+            "sj_server_create": [i32, V, u64, i32, P(V)],
+            "sj_server_submit": [V, P(_Rel), i32, P(_Edge), i32, P(_Opts), i32, P(u64)],
+            "sj_server_query": [V, u64, i32, P(_QueryInfo)],
+            "sj_server_release": [V, u64],
+            "sj_server_stats": [V, P(u64), P(u64), P(i32), P(i32)],
+            "sj_server_destroy": [V],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -110,6 +129,8 @@ def lib():
             fn.restype = i32
         L.sj_last_error.argtypes = [V]
         L.sj_last_error.restype = ctypes.c_char_p
+        L.sj_server_last_error.argtypes = [V]
+        L.sj_server_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -156,6 +177,27 @@ class Rel:
         self.pred = pred
 
 
+def _marshal(rels: Sequence[Rel], edges: Sequence[Tuple[int, int, int, int]]):
+    """ctypes arrays of sj_rel and sj_edge, plus the pointer arrays they reference."""
+    arr = (_Rel * max(1, len(rels)))()
+    keep = []
+    for i, r in enumerate(rels):
+        for c in r.cols:
+            if c.dtype != torch.int32 or c.dim() != 1:
+                raise ValueError("columns must be 1-D int32 tensors")
+        ptrs = (ctypes.c_void_p * len(r.cols))(*[c.data_ptr() if c.numel() else None for c in r.cols])
+        keep.append(ptrs)
+        arr[i].nrows = r.cols[0].numel() if r.cols else 0
+        arr[i].ncols = len(r.cols)
+        arr[i].cols = ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p))
+        if r.pred is None:
+            arr[i].pred_col, arr[i].pred_lo, arr[i].pred_hi = -1, 0, 0
+        else:
+            arr[i].pred_col, arr[i].pred_lo, arr[i].pred_hi = (int(x) for x in r.pred)
+    earr = (_Edge * max(1, len(edges)))(*[_Edge(*[int(x) for x in e]) for e in edges])
+    return arr, earr, keep
+
+
 class Plan:
     """sj_plan plus its workspace (a torch uint8 tensor on the context's device)."""
 
@@ -168,22 +210,7 @@ class Plan:
         self.nrels = len(rels)
         self.rels = list(rels)
         self.handle = ctypes.c_void_p()
-        arr = (_Rel * max(1, len(rels)))()
-        self._keep = []
-        for i, r in enumerate(rels):
-            for c in r.cols:
-                if c.dtype != torch.int32 or c.dim() != 1:
-                    raise ValueError("columns must be 1-D int32 tensors")
-            ptrs = (ctypes.c_void_p * len(r.cols))(*[c.data_ptr() if c.numel() else None for c in r.cols])
-            self._keep.append(ptrs)
-            arr[i].nrows = r.cols[0].numel() if r.cols else 0
-            arr[i].ncols = len(r.cols)
-            arr[i].cols = ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p))
-            if r.pred is None:
-                arr[i].pred_col, arr[i].pred_lo, arr[i].pred_hi = -1, 0, 0
-            else:
-                arr[i].pred_col, arr[i].pred_lo, arr[i].pred_hi = (int(x) for x in r.pred)
-        earr = (_Edge * max(1, len(edges)))(*[_Edge(*[int(x) for x in e]) for e in edges])
+        arr, earr, self._keep = _marshal(rels, edges)
         opts = _Opts(bits_per_key, k, block_bits, passes, seed & (2**64 - 1), root,
                      (SJ_FLAG_PROFILE if profile else 0) | (SJ_FLAG_EAGER if eager else 0))
         wsb = ctypes.c_uint64()
@@ -284,3 +311,79 @@ class Plan:
         if h and _lib is not None:
             _lib.sj_plan_destroy(h)
             self.handle = None
+
+
+class Server:
+    """sj_server over a torch uint8 arena on `device` with `slots` workers.
+
+    submit() queues a query and returns its ticket; info(ticket, wait) returns its state
+    as a dict; result(ticket) is a zero-copy int32 [count, nrels] view of the arena;
+    release(ticket) frees it. Input tensors are kept alive until release."""
+
+    def __init__(self, arena_bytes: int, slots: int = 4, device: int = 0, arena: Optional[torch.Tensor] = None):
+        self.device = device
+        self.arena = arena if arena is not None else torch.empty(arena_bytes, dtype=torch.uint8,
+                                                                  device="cuda:%d" % device)
+        self.handle = ctypes.c_void_p()
+        self._alive = {}
+        torch.cuda.synchronize(device)   # the arena's allocation is complete before workers use it
+        code = lib().sj_server_create(device, ctypes.c_void_p(self.arena.data_ptr()),
+                                      self.arena.numel(), slots, ctypes.byref(self.handle))
+        if code != SJ_OK:
+            raise SjError(code, "sj_server_create")
+
+    def submit(self, rels: Sequence[Rel], edges: Sequence[Tuple[int, int, int, int]], bits_per_key: int = 0,
+               k: int = 0, block_bits: int = 0, passes: int = 0, seed: int = 0, root: int = -1,
+               count_only: bool = False) -> int:
+        arr, earr, keep = _marshal(rels, edges)
+        opts = _Opts(bits_per_key, k, block_bits, passes, seed & (2**64 - 1), root, 0)
+        t = ctypes.c_uint64()
+        code = lib().sj_server_submit(self.handle, arr, len(rels), earr, len(edges), ctypes.byref(opts),
+                                      SJ_RESULT_COUNT if count_only else SJ_RESULT_TUPLES, ctypes.byref(t))
+        if code != SJ_OK:
+            raise SjError(code, (lib().sj_server_last_error(self.handle) or b"").decode())
+        self._alive[int(t.value)] = (list(rels), len(rels), keep)
+        return int(t.value)
+
+    def info(self, ticket: int, wait: bool = False) -> dict:
+        q = _QueryInfo()
+        code = lib().sj_server_query(self.handle, ticket, 1 if wait else 0, ctypes.byref(q))
+        if code != SJ_OK:
+            raise SjError(code, "unknown ticket %d" % ticket)
+        return {"state": q.state, "status": q.status, "count": int(q.count), "checksum": int(q.checksum),
+                "result_offset": int(q.result_offset), "workspace_bytes": int(q.workspace_bytes),
+                "t_submit_ns": int(q.t_submit_ns), "t_admit_ns": int(q.t_admit_ns), "t_done_ns": int(q.t_done_ns),
+                "slot": int(q.slot), "error": q.error.decode()}
+
+    def result(self, ticket: int) -> torch.Tensor:
+        q = self.info(ticket, wait=True)
+        if q["state"] != SJ_QUERY_DONE:
+            raise SjError(q["status"], q["error"])
+        nrels = self._alive[ticket][1]
+        n = q["count"] * nrels
+        if n == 0:
+            return torch.empty((0, nrels), dtype=torch.int32, device=self.arena.device)
+        off = q["result_offset"]
+        return self.arena[off: off + 4 * n].view(torch.int32).view(q["count"], nrels)
+
+    def release(self, ticket: int) -> None:
+        code = lib().sj_server_release(self.handle, ticket)
+        if code != SJ_OK:
+            raise SjError(code, "release of ticket %d" % ticket)
+        self._alive.pop(ticket, None)
+
+    def stats(self) -> dict:
+        used, peak = ctypes.c_uint64(), ctypes.c_uint64()
+        queued, running = ctypes.c_int32(), ctypes.c_int32()
+        lib().sj_server_stats(self.handle, ctypes.byref(used), ctypes.byref(peak), ctypes.byref(queued),
+                              ctypes.byref(running))
+        return {"arena_used": int(used.value), "arena_peak": int(peak.value), "queued": int(queued.value),
+                "running": int(running.value)}
+
+    def close(self) -> None:
+        if self.handle and _lib is not None:
+            _lib.sj_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsievejoin.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
-SOURCES = ["sj_kernels.hip", "sj_join.hip", "sj_runtime.cpp"]
+SOURCES = ["sj_kernels.hip", "sj_join.hip", "sj_runtime.cpp", "sj_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # keep the compiler from emitting packed FP32 instructions
@@ -25,7 +25,7 @@ def build(verbose: bool = False, out: str = LIB, defines=(), csrc: str = CSRC) -
     with tempfile.TemporaryDirectory(prefix="sjbuild") as tmp:
         def compile_one(src):
             obj = os.path.join(tmp, os.path.splitext(src)[0] + ".o")
-            lang = ["-x", "hip"] if src.endswith(".cpp") else []
+            lang = ["-x", "hip", "-pthread"] if src.endswith(".cpp") else []
             cmd = [HIPCC, *FLAGS, "-I" + INCLUDE, *["-D" + d for d in defines], *lang, "-c", os.path.join(csrc, src), "-o", obj]
             r = subprocess.run(cmd, capture_output=True, text=True)
             if r.returncode != 0:
@@ -37,7 +37,7 @@ def build(verbose: bool = False, out: str = LIB, defines=(), csrc: str = CSRC) -
         with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
             objs = list(ex.map(compile_one, SOURCES))
         out_tmp = out + ".tmp%d" % os.getpid()
-        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out_tmp, *objs]
+        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", out_tmp, *objs]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("link failed:\n%s" % r.stderr[-4000:])

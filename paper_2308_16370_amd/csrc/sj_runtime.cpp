@@ -717,11 +717,7 @@ struct ProfScope {
     }
 };
 
-static const char *rel_name(int r) {
-    static char buf[SJ_MAX_RELS][8];
-    snprintf(buf[r], sizeof buf[r], "R%d", r);
-    return buf[r];
-}
+static std::string rel_name(int r) { return "R" + std::to_string(r); }
 
 static sj_status run_steps(sj_plan_t *p, int phase) {
     hipStream_t s = p->ls;

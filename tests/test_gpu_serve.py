@@ -1,0 +1,177 @@
+"""The serving extension: a query's result is the same alone and in a mix.
+
+A mix of small chain and star queries (the batched workload's distributions at
+small sizes, generated on the CPU) runs once alone, one plan at a time, and then
+through servers whose arena is small enough that admission has to wait: all queries
+at once, then staggered while others run. Count, checksum and every tuple must be
+identical; counts and checksums also equal the oracle's. Failure handling: a query
+whose workspace exceeds the arena is refused at submit, one whose result can never
+fit fails alone, and an unsupported cyclic shape fails while its neighbours finish.
+"""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2308_16370_amd as sj
+import workloads as W
+from workloads import serving as S
+from sjtest import to_device
+
+pytestmark = pytest.mark.gpu
+
+OPTS = dict(bits_per_key=8, k=6, block_bits=512, passes=2, seed=5)
+SEED = 0x5EED0005
+
+
+@pytest.fixture(scope="module")
+def mix():
+    specs = S.serving_specs(SEED, n=20, min_rows=500, max_rows=60_000)
+    out = []
+    ctx = sj.Context(0)
+    for sp in specs:
+        q = S.query_cpu(sp)
+        rels = to_device(q)
+        plan = sj.Plan(ctx, rels, q.edges, root=q.root, eager=True, **OPTS)
+        plan.build_filters()
+        plan.sieve()
+        cnt, chk = plan.join()
+        tup = plan.result().cpu().numpy().copy()
+        _, rcnt, rchk = oracle.hash_join(q)
+        assert (cnt, chk) == (rcnt, rchk), sp
+        out.append((sp, q, rels, (cnt, chk), tup, plan.workspace_bytes))
+    torch.cuda.synchronize()
+    return out
+
+
+def run_server(mix, arena_bytes, slots, stagger):
+    """Submit every query (optionally staggered), then collect each result as soon as
+    its query finishes and release it at once, as a serving client does."""
+    srv = sj.Server(arena_bytes, slots=slots)
+    try:
+        tickets = []
+        for i, (sp, q, rels, _, _, _) in enumerate(mix):
+            tickets.append(srv.submit(rels, q.edges, root=q.root, **OPTS))
+            if stagger and i % 3 == 2:
+                time.sleep(0.002)
+        results = {}
+        peak = 0
+        deadline = time.time() + 120
+        while len(results) < len(tickets):
+            assert time.time() < deadline, "queries did not finish"
+            progressed = False
+            for t in tickets:
+                if t in results:
+                    continue
+                info = srv.info(t)
+                if info["state"] in (sj.SJ_QUERY_DONE, sj.SJ_QUERY_FAILED):
+                    assert info["state"] == sj.SJ_QUERY_DONE, info
+                    results[t] = (info, srv.result(t).cpu().numpy().copy())
+                    peak = max(peak, srv.stats()["arena_peak"])
+                    srv.release(t)
+                    progressed = True
+            if not progressed:
+                time.sleep(0.001)
+        assert srv.stats()["arena_used"] == 0
+        return [results[t] for t in tickets], peak
+    finally:
+        srv.close()
+
+
+@pytest.mark.parametrize("slots,stagger", [(4, False), (3, True), (1, False)])
+def test_served_equals_alone(mix, slots, stagger):
+    biggest = max(m[5] for m in mix)
+    res_bytes = max(m[3][0] * len(m[1].rels) * 4 for m in mix)
+    arena = 2 * (biggest + res_bytes) + (1 << 20)   # at most a couple of queries at a time
+    results, peak = run_server(mix, arena, slots, stagger)
+    assert peak <= arena
+    for (sp, q, _, cc, tup, _), (info, got) in zip(mix, results):
+        assert (info["count"], info["checksum"]) == cc, sp
+        assert got.shape == tup.shape and np.array_equal(got, tup), sp
+        assert info["t_submit_ns"] <= info["t_admit_ns"] <= info["t_done_ns"]
+
+
+@pytest.fixture(scope="module")
+def bigq():
+    """A chain with a large result (about 2000^3 / 200^2 tuples) and its alone run."""
+    bq = W.chain(3, 2000, 200, 0.0, 77)
+    brels = to_device(bq)
+    bplan = sj.Plan(sj.Context(0), brels, bq.edges, root=bq.root, eager=True, **OPTS)
+    bplan.build_filters()
+    bplan.sieve()
+    bcc = bplan.join()
+    torch.cuda.synchronize()
+    assert bcc[0] * 3 * 4 > 65536
+    return (None, bq, brels, bcc, None, bplan.workspace_bytes)
+
+
+def test_server_count_only_and_failures(mix, bigq):
+    sp, q, rels, cc, _, wsb = mix[0]
+    # a workspace larger than the whole arena is refused at submit
+    tiny = sj.Server(1 << 16, slots=2)
+    try:
+        with pytest.raises(sj.SjError) as e:
+            tiny.submit(rels, q.edges, root=q.root, **OPTS)
+        assert e.value.code == sj.SJ_ERR_NOMEM
+    finally:
+        tiny.close()
+    # a result that can never fit beside its workspace fails alone; count-only and
+    # fitting neighbours finish with the right answers; an unsupported cyclic shape
+    # fails (or, if it is an executed shape, finishes)
+    big = bigq
+    arena = big[5] + 4096
+    fits = [m for m in mix if m[5] + m[3][0] * len(m[1].rels) * 4 + 512 <= arena]
+    counts_only = [m for m in mix if m[5] <= arena]
+    assert fits and counts_only
+    srv = sj.Server(arena, slots=1)
+    try:
+        t_big = srv.submit(big[2], big[1].edges, root=big[1].root, **OPTS)
+        t_fit = [(m, srv.submit(m[2], m[1].edges, root=m[1].root, **OPTS)) for m in fits[:4]]
+        t_cnt = [(m, srv.submit(m[2], m[1].edges, root=m[1].root, count_only=True, **OPTS)) for m in counts_only[:4]]
+        cyc = W.tiny_random(31, kind="cycle4")
+        t_cyc = srv.submit(to_device(cyc), cyc.edges, root=cyc.root, **OPTS)
+        i_big = srv.info(t_big, wait=True)
+        assert i_big["state"] == sj.SJ_QUERY_FAILED and i_big["status"] == sj.SJ_ERR_CAPACITY, i_big
+        assert (i_big["count"], i_big["checksum"]) == big[3]
+        srv.release(t_big)
+        for m, t in t_fit:   # each result is consumed and released before the next is awaited
+            info = srv.info(t, wait=True)
+            assert info["state"] == sj.SJ_QUERY_DONE, info
+            assert (info["count"], info["checksum"]) == m[3]
+            assert np.array_equal(srv.result(t).cpu().numpy(), m[4])
+            srv.release(t)
+        for m, t in t_cnt:
+            info = srv.info(t, wait=True)
+            assert info["state"] == sj.SJ_QUERY_DONE and (info["count"], info["checksum"]) == m[3], info
+            srv.release(t)
+        i_cyc = srv.info(t_cyc, wait=True)
+        if i_cyc["state"] == sj.SJ_QUERY_FAILED:
+            assert i_cyc["status"] == sj.SJ_ERR_UNSUPPORTED, i_cyc
+        else:
+            _, rc, rk = oracle.hash_join(cyc)
+            assert (i_cyc["count"], i_cyc["checksum"]) == (rc, rk)
+        srv.release(t_cyc)
+        assert srv.stats()["arena_used"] == 0
+    finally:
+        srv.close()
+
+
+def test_unreleased_results_fail_the_next_query_instead_of_hanging(bigq):
+    """A result the client does not release keeps the arena full: the next query gets
+    its workspace but no room for its result, and fails with SJ_ERR_NOMEM after the
+    bounded wait instead of waiting forever."""
+    m = bigq
+    arena = m[5] + m[3][0] * len(m[1].rels) * 4 + 4096
+    srv = sj.Server(arena, slots=1)
+    try:
+        t1 = srv.submit(m[2], m[1].edges, root=m[1].root, **OPTS)
+        assert srv.info(t1, wait=True)["state"] == sj.SJ_QUERY_DONE   # its result now holds the arena
+        t2 = srv.submit(m[2], m[1].edges, root=m[1].root, **OPTS)
+        i2 = srv.info(t2, wait=True)
+        assert i2["state"] == sj.SJ_QUERY_FAILED and i2["status"] == sj.SJ_ERR_NOMEM, i2
+        srv.release(t1)
+        srv.release(t2)
+    finally:
+        srv.close()
