@@ -75,6 +75,11 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0, help="append a plain copy of this many MiB")
+    ap.add_argument("--no-serve", action="store_true", help="skip the batched / served query mix")
+    ap.add_argument("--serve-queries", type=int, default=256)
+    ap.add_argument("--serve-max-rows", type=int, default=20_000_000)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-arena-gb", type=int, default=24)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -181,6 +186,15 @@ def main():
         if check == "MISMATCH":
             print("# oracle mismatch: gpu %r oracle %r" % ((cnt, chk), (rcnt, rchk)), file=sys.stderr)
 
+    serving = None
+    if not args.no_serve:
+        from paper_2308_16370_amd import servebench
+        del plan
+        torch.cuda.empty_cache()
+        serving = servebench.run(n=args.serve_queries, max_rows=args.serve_max_rows, slots=args.serve_slots,
+                                 arena_bytes=args.serve_arena_gb << 30,
+                                 log=lambda m: print(m, file=sys.stderr, flush=True))
+
     res = {
         "metric": "input tuples/s through sieve+join (4-way chain)",
         "value": value,
@@ -202,6 +216,7 @@ def main():
         "cpu_baseline": cpu,
         "check": check,
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "serving": serving,
         "kernels": [{"label": e["label"], "avg_us": round(e["total_ms"] / max(1, e["launches"]) * 1e3, 2),
                      "alg_bytes": e["alg_bytes"]} for e in kernels[:12]],
     }
