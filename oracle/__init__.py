@@ -15,6 +15,8 @@ What it computes (arXiv 2308.16370):
 * ``bf_*``       -- the blocked Bloom filter (Section 2.1 step 1, Bloom's bit vector
   in its cache-blocked form) under the hash/bit-pattern reading stated in
   ``oracle.c``.
+* ``triangle_cycles`` -- count and checksum of the directed 3-cycle query by
+  adjacency intersection (a textbook triangle count), independent of ``hash_join``.
 * ``sieve``      -- the pruning phase (Section 2.2): one backward pass from the
   right-most relation to the root, each relation probed by the filters of the
   relations after it and building the filter on its own join attribute from its
@@ -89,6 +91,9 @@ def lib():
             L.orc_hash_join.restype = ctypes.c_void_p
             L.orc_result_count.argtypes = [ctypes.c_void_p]
             L.orc_result_count.restype = ctypes.c_int64
+            L.orc_triangle_cycles.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64)]
+            L.orc_triangle_cycles.restype = ctypes.c_int
             L.orc_result_checksum.argtypes = [ctypes.c_void_p]
             L.orc_result_checksum.restype = ctypes.c_uint64
             L.orc_result_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
@@ -292,6 +297,19 @@ def hash_join(query, root: Optional[int] = None):
     finally:
         lib().orc_result_free(res)
     return out, cnt, chk
+
+
+def triangle_cycles(src: np.ndarray, dst: np.ndarray) -> Tuple[int, int]:
+    """Count and checksum of E1 join E2 join E3 on E1.dst = E2.src, E2.dst = E3.src,
+    E3.dst = E1.src over the edge list (src, dst) (the 3-cycle query, Section 2.3),
+    by adjacency intersection: for every edge a -> b, the out-edges of b and the
+    in-edges of a that meet in one vertex. Independent of ``hash_join``."""
+    s = np.ascontiguousarray(src, dtype=np.int32)
+    d = np.ascontiguousarray(dst, dtype=np.int32)
+    cnt, chk = ctypes.c_int64(), ctypes.c_uint64()
+    if lib().orc_triangle_cycles(s.shape[0], _ptr(s), _ptr(d), ctypes.byref(cnt), ctypes.byref(chk)) != 0:
+        raise MemoryError("orc_triangle_cycles")
+    return int(cnt.value), int(chk.value)
 
 
 def checksum_of(tuples: np.ndarray) -> int:

@@ -202,3 +202,30 @@ def test_edge_cases_empty_and_extremes():
     tup, cnt, chk = oracle.hash_join(q)
     assert cnt == 2 * 2 + 1 + 1
     assert (cnt, chk) == oracle.join_tree_dp(q)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_triangle_cycles_matches_hash_join(seed):
+    """The adjacency-intersection count agrees with the binary join plan and with
+    brute force, on graphs with parallel edges, self-loops and negative vertex ids."""
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(1, 60))
+    v = int(rng.integers(1, 9))
+    src = (rng.integers(0, v, n) - (v // 2 if seed % 3 == 0 else 0)).astype(np.int32)
+    dst = (rng.integers(0, v, n) - (v // 2 if seed % 3 == 0 else 0)).astype(np.int32)
+    if seed % 4 == 1:
+        src[:3] = dst[:3]                     # self-loops
+    q = W.Query("tri", [W.Relation("E%d" % i, [src, dst]) for i in range(3)],
+                [(0, 1, 1, 0), (1, 1, 2, 0), (2, 1, 0, 0)])
+    tup, cnt, chk = oracle.hash_join(q)
+    bf = [(i, j, k) for i in range(n) for j in range(n) for k in range(n)
+          if dst[i] == src[j] and dst[j] == src[k] and dst[k] == src[i]]
+    assert cnt == len(bf)
+    assert oracle.triangle_cycles(src, dst) == (cnt, chk)
+
+
+def test_triangle_cycles_generated_graph():
+    q = W.triangle(6000, 1500, 2.1, seed=9)
+    src, dst = q.rels[0].cols
+    tup, cnt, chk = oracle.hash_join(q)
+    assert oracle.triangle_cycles(src, dst) == (cnt, chk)
