@@ -239,10 +239,29 @@ __global__ __launch_bounds__(kProbeBlock) void k_sieve_step(StepArgs a) {
     uint16_t *wl = s_list[tid >> 6];
     uint32_t survivors = 0;
 
+    // The first probe's keys of the next tile are loaded while the current tile is
+    // probed, so the column's load latency overlaps the probing.
+    const int32_t *fcol = pcol[0];
+#pragma unroll
+    for (int p = 1; p < kMaxProbe; ++p)
+        if (p == first) fcol = pcol[p];
+    int32_t nxt[kSieveItems];
+    {
+        const uint32_t t0 = blockIdx.x * per, row0 = t0 + tid * kSieveItems;
+        if (t0 < r_end && a.nprobe > 0) load_keys(fcol, row0, n, row0 + kSieveItems <= n, nxt);
+    }
+
     for (uint32_t t0 = blockIdx.x * per; t0 < r_end; t0 += kProbeTile) {
         const uint32_t row0 = t0 + tid * kSieveItems;
         const uint32_t wrow0 = t0 + (tid & ~63) * kSieveItems;   // the wave's first row
         const bool full = row0 + kSieveItems <= n;
+        int32_t key[kSieveItems];
+#pragma unroll
+        for (int i = 0; i < kSieveItems; ++i) key[i] = nxt[i];
+        {
+            const uint32_t t1 = t0 + kProbeTile, row1 = t1 + tid * kSieveItems;
+            if (t1 < r_end && a.nprobe > 0) load_keys(fcol, row1, n, row1 + kSieveItems <= n, nxt);
+        }
 
         uint32_t flags = 0;
 #pragma unroll
@@ -258,10 +277,6 @@ __global__ __launch_bounds__(kProbeBlock) void k_sieve_step(StepArgs a) {
 
         // (1) the first probe, per lane over its rows
         if (a.nprobe > 0 && flags) {
-            int32_t key[kSieveItems];
-#pragma unroll
-            for (int p = 0; p < kMaxProbe; ++p)
-                if (p == first) load_keys(pcol[p], row0, n, full, key);
             if (pl >= 0) {
                 // the LDS filter: all k words of a batch's keys are read before any is tested
 #pragma unroll
