@@ -7,8 +7,11 @@ rank->key permutation per (table, column); blocked Bloom filters of 8 bits per
 key, k = 6, 512-bit blocks; backward and forward pruning passes; exact result
 count, checksum and materialised int32 row-id tuples.
 
-One step = sj_build_filters + sj_sieve + sj_join + sj_result on a plan whose
-inputs and workspace are already resident in HBM. The metric is input tuples per
+One step = sj_build_filters + sj_sieve + sj_join_async + sj_result_async on a plan
+whose inputs and workspace are already resident in HBM: the exact count stays on the
+device and the materialisation reads it there, so the steps queue back to back; the
+count, checksum and result status are checked after the warm-up steps and after the
+timed ones. The metric is input tuples per
 second (the sum of the four relations' rows divided by the step time).
 
 Printed: one JSON line with the contract's fields plus
@@ -112,22 +115,28 @@ def main():
     torch.cuda.synchronize()
 
     def step():
+        # the count stays on the device: the materialisation reads it there, so a step is
+        # four recorded graphs replayed back to back with no host round trip
         plan.build_filters()
         plan.sieve()
-        c = plan.join()
-        plan.result(out)
-        return c
+        plan.join_async()
+        plan.result_async(out)
+
+    def check():
+        c = plan.join_wait()
+        if c != (cnt, chk, sj.SJ_OK):
+            raise RuntimeError("result changed between steps: %r vs %r" % (c, (cnt, chk)))
 
     for _ in range(args.warmup):
         step()
+        check()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        c = step()
-        if c != (cnt, chk):
-            raise RuntimeError("result changed between steps: %r vs %r" % (c, (cnt, chk)))
+        step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    check()   # the last step's count, checksum and result status
     ms = (t1 - t0) / args.steps * 1e3
     value = q.input_tuples / (ms / 1e3)
     print("# %d steps, %.3f ms/step, count %d" % (args.steps, ms, cnt), file=sys.stderr, flush=True)

@@ -156,6 +156,23 @@ sj_status sj_join(sj_plan_t *plan, uint64_t *count, uint64_t *checksum);
  * if capacity_tuples < count. Asynchronous. */
 sj_status sj_result(sj_plan_t *plan, int32_t *out_dev, uint64_t capacity_tuples);
 
+/* Asynchronous variant of the enumeration (Section 2.2 step 2), for callers that do
+ * not need the count on the host before the tuples (a whole query then runs without
+ * a host round trip; every phase is replayed as a recorded graph). Acyclic plans only:
+ * a cyclic plan returns SJ_ERR_UNSUPPORTED (its count needs a host step).
+ *   sj_join_async    enqueues the count pass; the count stays on the device.
+ *   sj_result_async  enqueues the materialisation into out_dev (room for
+ *                    capacity_tuples tuples): the kernels read the count on the device
+ *                    and write nothing if it exceeds the capacity.
+ *   sj_join_wait     waits for the stream and returns count and checksum; with
+ *                    result_status != NULL, also SJ_ERR_CAPACITY if the last
+ *                    sj_result_async found its buffer too small (nothing was written),
+ *                    else SJ_OK.
+ * After sj_join_async, sj_result (the synchronous call) needs sj_join_wait first. */
+sj_status sj_join_async(sj_plan_t *plan);
+sj_status sj_result_async(sj_plan_t *plan, int32_t *out_dev, uint64_t capacity_tuples);
+sj_status sj_join_wait(sj_plan_t *plan, uint64_t *count, uint64_t *checksum, sj_status *result_status);
+
 sj_status sj_plan_destroy(sj_plan_t *plan);
 
 /* ---- introspection (filters and survivors; used to check the pruning phase) ---- */

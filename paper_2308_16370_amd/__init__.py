@@ -42,7 +42,8 @@ SJ_FILTER_FORWARD = 1
 SJ_FILTER_CLOSING = 2
 
 EXPORTED = ["sj_ctx_create", "sj_ctx_set_stream", "sj_ctx_destroy", "sj_last_error", "sj_plan",
-            "sj_bind_workspace", "sj_build_filters", "sj_sieve", "sj_join", "sj_result", "sj_plan_destroy",
+            "sj_bind_workspace", "sj_build_filters", "sj_sieve", "sj_join", "sj_result", "sj_join_async",
+            "sj_result_async", "sj_join_wait", "sj_plan_destroy",
             "sj_filter_count", "sj_filter_desc", "sj_filter_copy", "sj_survivors_copy", "sj_profile_collect",
             "sj_profile_count", "sj_profile_entry", "sj_profile_reset", "sj_server_create", "sj_server_submit",
             "sj_server_query", "sj_server_release", "sj_server_stats", "sj_server_last_error",
@@ -107,6 +108,9 @@ def lib():
             "sj_sieve": [V, P(u64)],
             "sj_join": [V, P(u64), P(u64)],
             "sj_result": [V, V, u64],
+            "sj_join_async": [V],
+            "sj_result_async": [V, V, u64],
+            "sj_join_wait": [V, P(u64), P(u64), P(i32)],
             "sj_plan_destroy": [V],
             "sj_filter_count": [V, P(i32)],
             "sj_filter_desc": [V, i32, P(i32), P(i32), P(i32), P(i32), P(u32)],
@@ -245,6 +249,25 @@ class Plan:
         self._check(lib().sj_join(self.handle, ctypes.byref(c), ctypes.byref(s)))
         self.count, self.checksum = int(c.value), int(s.value)
         return self.count, self.checksum
+
+    def join_async(self) -> None:
+        """Enqueue the count pass; the count stays on the device (see join_wait)."""
+        self._check(lib().sj_join_async(self.handle))
+        self.count = None
+
+    def result_async(self, out: torch.Tensor) -> torch.Tensor:
+        """Enqueue the materialisation into `out` (int32 [capacity, nrels]); nothing is
+        written if the result does not fit (join_wait reports it)."""
+        cap = out.numel() // max(1, self.nrels)
+        self._check(lib().sj_result_async(self.handle, ctypes.c_void_p(out.data_ptr() if out.numel() else 0), cap))
+        return out
+
+    def join_wait(self) -> Tuple[int, int, int]:
+        """(count, checksum, status of the last result_async) after waiting for the stream."""
+        c, k, st = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int32()
+        self._check(lib().sj_join_wait(self.handle, ctypes.byref(c), ctypes.byref(k), ctypes.byref(st)))
+        self.count, self.checksum = int(c.value), int(k.value)
+        return self.count, self.checksum, int(st.value)
 
     def result(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         if self.count is None:

@@ -200,9 +200,13 @@ struct MatArgs {
     const uint32_t *blo[kMatMaxRels];   // bucket of position x inside the parent's entry e:
     const uint32_t *bhi[kMatMaxRels];   //   [blo[x][e], bhi[x][e])
     const uint32_t *root_n;
-    uint64_t count;                // total result tuples (host copy)
+    uint64_t count;                // total result tuples (host copy), used when count_dev is null
+    const uint64_t *count_dev;     // device-side total, or nullptr
+    uint64_t capacity;             // tuples `out` holds: nothing is written if the total exceeds it
     int32_t *out;
 };
+// Grid: enough blocks for min(count, capacity) tuples when the count is on the host;
+// a fixed persistent grid over the output when it is read on the device.
 hipError_t launch_materialize(const MatArgs &a, hipStream_t s);
 
 // Cyclic joins whose closing edges all end at the last relation L of the preorder

@@ -659,6 +659,10 @@ __device__ __forceinline__ void mat_advance(const MatArgs &a, MatState<N> &st, u
     }
 }
 
+// Blocks of a materialisation whose count is read on the device (a grid-stride loop
+// over the output covers the rest).
+constexpr uint64_t kMatPersistentBlocks = 4096;
+
 // Tuples per thread: a thread's C tuples of N entries take at most 16 words of LDS.
 template <int N>
 constexpr int mat_chunk() {
@@ -683,67 +687,71 @@ __global__ __launch_bounds__(256) void k_materialize(MatArgs a) {
     __shared__ uint32_t s_out[256 * PITCH];
     __shared__ uint32_t s_r[2];
     __shared__ const uint32_t *s_rid[N];   // row ids of output column q's position
-    const uint64_t t0 = static_cast<uint64_t>(blockIdx.x) * PER;
-    const uint64_t t1 = (t0 + PER < a.count) ? t0 + PER : a.count;
+    const uint64_t count = a.count_dev ? *a.count_dev : a.count;
+    if (count > a.capacity) return;         // the caller's buffer is too small: write nothing
     const uint32_t root_n = *a.root_n;
     const uint64_t *rcw = a.cw[0];
-    if (threadIdx.x < 2) {
-        const uint64_t o = threadIdx.x == 0 ? t0 : t1 - 1;
-        s_r[threadIdx.x] = upper_bound_u64(rcw, 0, root_n + 1, o) - 1;
-    }
     if (threadIdx.x == 64) {
 #pragma unroll
         for (int x = 0; x < N; ++x) s_rid[a.order[x]] = a.rid[x];
     }
-    __syncthreads();
-    const uint32_t r0 = s_r[0], r1 = s_r[1];
-    const bool in_lds = r1 - r0 + 2 <= WIN;   // zero-weight root entries can widen the range
-    if (in_lds)
-        for (uint32_t i = threadIdx.x; i < r1 - r0 + 2; i += 256) s_cw[i] = rcw[r0 + i];
-    __syncthreads();
-    const uint64_t o0 = t0 + static_cast<uint64_t>(threadIdx.x) * C;
-    if (o0 < t1) {
-        uint32_t r;
-        uint64_t L0;
-        if (in_lds) {
-            r = r0 + upper_bound_u64(s_cw, 0, r1 - r0 + 2, o0) - 1;
-            L0 = o0 - s_cw[r - r0];
-        } else {
-            r = upper_bound_u64(rcw, r0, r1 + 2, o0) - 1;
-            L0 = o0 - rcw[r];
+    for (uint64_t blk = blockIdx.x; blk * PER < count; blk += gridDim.x) {
+        const uint64_t t0 = blk * PER;
+        const uint64_t t1 = (t0 + PER < count) ? t0 + PER : count;
+        if (threadIdx.x < 2) {
+            const uint64_t o = threadIdx.x == 0 ? t0 : t1 - 1;
+            s_r[threadIdx.x] = upper_bound_u64(rcw, 0, root_n + 1, o) - 1;
         }
-        MatState<N> st;
-        mat_decode<N>(a, st, r, L0);
-        const uint32_t nloc = static_cast<uint32_t>(min(static_cast<uint64_t>(C), t1 - o0));
-        uint32_t *row = s_out + threadIdx.x * PITCH;
-        for (uint32_t i = 0;;) {
-#pragma unroll
-            for (int x = 0; x < N; ++x) row[i * N + a.order[x]] = st.e[x];
-            if (++i >= nloc) break;
-            mat_advance<N>(a, st, root_n);
+        __syncthreads();
+        const uint32_t r0 = s_r[0], r1 = s_r[1];
+        const bool in_lds = r1 - r0 + 2 <= WIN;   // zero-weight root entries can widen the range
+        if (in_lds)
+            for (uint32_t i = threadIdx.x; i < r1 - r0 + 2; i += 256) s_cw[i] = rcw[r0 + i];
+        __syncthreads();
+        const uint64_t o0 = t0 + static_cast<uint64_t>(threadIdx.x) * C;
+        if (o0 < t1) {
+            uint32_t r;
+            uint64_t L0;
+            if (in_lds) {
+                r = r0 + upper_bound_u64(s_cw, 0, r1 - r0 + 2, o0) - 1;
+                L0 = o0 - s_cw[r - r0];
+            } else {
+                r = upper_bound_u64(rcw, r0, r1 + 2, o0) - 1;
+                L0 = o0 - rcw[r];
+            }
+            MatState<N> st;
+            mat_decode<N>(a, st, r, L0);
+            const uint32_t nloc = static_cast<uint32_t>(min(static_cast<uint64_t>(C), t1 - o0));
+            uint32_t *row = s_out + threadIdx.x * PITCH;
+            for (uint32_t i = 0;;) {
+    #pragma unroll
+                for (int x = 0; x < N; ++x) row[i * N + a.order[x]] = st.e[x];
+                if (++i >= nloc) break;
+                mat_advance<N>(a, st, root_n);
+            }
         }
-    }
-    __syncthreads();
-    // word w of the block's output is word w % ROW of thread w / ROW's row
-    const uint64_t words = (t1 - t0) * N;
-    int32_t *dst = a.out + t0 * N;
-    for (uint32_t w = threadIdx.x * 4; w < words; w += 256 * 4) {
-        int32_t v[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t ww = w + j;
-            v[j] = ww < words ? static_cast<int32_t>(s_rid[ww % N][s_out[(ww / ROW) * PITCH + ww % ROW]]) : 0;
+        __syncthreads();
+        // word w of the block's output is word w % ROW of thread w / ROW's row
+        const uint64_t words = (t1 - t0) * N;
+        int32_t *dst = a.out + t0 * N;
+        for (uint32_t w = threadIdx.x * 4; w < words; w += 256 * 4) {
+            int32_t v[4];
+    #pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t ww = w + j;
+                v[j] = ww < words ? static_cast<int32_t>(s_rid[ww % N][s_out[(ww / ROW) * PITCH + ww % ROW]]) : 0;
+            }
+            if (w + 4 <= words) {
+                *reinterpret_cast<int4 *>(dst + w) = make_int4(v[0], v[1], v[2], v[3]);
+            } else {
+                for (uint32_t j = 0; w + j < words; ++j) dst[w + j] = v[j];
+            }
         }
-        if (w + 4 <= words) {
-            *reinterpret_cast<int4 *>(dst + w) = make_int4(v[0], v[1], v[2], v[3]);
-        } else {
-            for (uint32_t j = 0; w + j < words; ++j) dst[w + j] = v[j];
-        }
+        __syncthreads();   // s_r, s_cw and s_out are reused by the next block of output
     }
 }
 
 hipError_t launch_materialize(const MatArgs &a, hipStream_t s) {
-    if (a.count == 0) return hipSuccess;
     uint32_t per = 0;
     switch (a.nrels) {
 #define SJ_MAT_PER(NN) \
@@ -754,7 +762,10 @@ hipError_t launch_materialize(const MatArgs &a, hipStream_t s) {
 #undef SJ_MAT_PER
         default: return hipErrorInvalidValue;
     }
-    const uint64_t blocks64 = (a.count + per - 1) / per;
+    const uint64_t tuples = a.count_dev ? a.capacity : min(a.count, a.capacity);
+    if (tuples == 0) return hipSuccess;
+    uint64_t blocks64 = (tuples + per - 1) / per;
+    if (a.count_dev && blocks64 > kMatPersistentBlocks) blocks64 = kMatPersistentBlocks;
     if (blocks64 > 0x7fffffffull) return hipErrorInvalidValue;
     const dim3 g(static_cast<uint32_t>(blocks64));
     switch (a.nrels) {

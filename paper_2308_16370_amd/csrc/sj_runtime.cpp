@@ -151,7 +151,12 @@ struct sj_plan_s {
     bool eager = false;                  // profiling plans and SJ_FLAG_EAGER launch one by one
     hipStream_t ls = nullptr;            // stream the launch helpers enqueue on
     hipStream_t cap_stream = nullptr;    // capture stream (created on first use)
-    hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
+    hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
+    // asynchronous count / result (sj_join_async, sj_result_async, sj_join_wait)
+    bool count_on_host = false;          // p->count / p->checksum hold the last count pass
+    bool async_result = false;           // a materialisation with a device-side count is queued
+    int32_t *res_out = nullptr;          // its buffer and capacity (the recorded graph uses them)
+    uint64_t res_cap = 0;
     void drop_graphs();
     ~sj_plan_s();
 };
@@ -1101,14 +1106,73 @@ extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) 
     }
     p->count = tot[0];
     p->checksum = tot[1];
+    p->count_on_host = true;
+    p->async_result = false;
     if (count) *count = tot[0];
     if (checksum) *checksum = tot[1];
     p->state = kJoined;
     return SJ_OK;
 }
 
+extern "C" sj_status sj_join_async(sj_plan_t *p) {
+    if (sj_status st = check_exec(p, kSieved)) return st;
+    if (!p->cyc_ok || p->cyclic)
+        return fail(p->ctx, SJ_ERR_UNSUPPORTED, "cyclic joins count in two host-driven steps: use sj_join");
+    if (sj_status st = run_phase(p, 2, enqueue_join)) return st;
+    p->count_on_host = false;
+    p->async_result = false;
+    p->state = kJoined;
+    return SJ_OK;
+}
+
+static sj_status enqueue_result_async(sj_plan_t *p) {
+    MatArgs m = mat_args(p, p->n);
+    m.count_dev = at<uint64_t>(p, p->off_totals);
+    m.capacity = p->res_cap;
+    m.out = p->res_out;
+    ProfScope ps(p, "materialize", -1, kProfResult);
+    SJ_HIP(p->ctx, launch_materialize(m, p->ls));
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_result_async(sj_plan_t *p, int32_t *out, uint64_t capacity) {
+    if (sj_status st = check_exec(p, kJoined)) return st;
+    if (p->cyclic) return fail(p->ctx, SJ_ERR_UNSUPPORTED, "cyclic joins: use sj_result");
+    if (capacity && !out) return fail(p->ctx, SJ_ERR_INVALID, "null output buffer");
+    if (reinterpret_cast<uintptr_t>(out) % 16) return fail(p->ctx, SJ_ERR_INVALID, "output must be 16-byte aligned");
+    if (out != p->res_out || capacity != p->res_cap) {   // the recorded launch names the buffer
+        if (p->gexec[3]) (void)hipGraphExecDestroy(p->gexec[3]);
+        p->gexec[3] = nullptr;
+        p->res_out = out;
+        p->res_cap = capacity;
+    }
+    if (sj_status st = run_phase(p, 3, enqueue_result_async)) return st;
+    p->async_result = true;
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_join_wait(sj_plan_t *p, uint64_t *count, uint64_t *checksum, sj_status *result_status) {
+    if (sj_status st = check_exec(p, kJoined)) return st;
+    if (!p->count_on_host) {
+        uint64_t tot[2] = {0, 0};
+        SJ_HIP(p->ctx, hipMemcpyAsync(tot, at<uint64_t>(p, p->off_totals), 16, hipMemcpyDeviceToHost, p->ctx->stream));
+        SJ_HIP(p->ctx, hipStreamSynchronize(p->ctx->stream));
+        p->count = tot[0];
+        p->checksum = tot[1];
+        p->count_on_host = true;
+    } else {
+        SJ_HIP(p->ctx, hipStreamSynchronize(p->ctx->stream));
+    }
+    if (count) *count = p->count;
+    if (checksum) *checksum = p->checksum;
+    if (result_status)
+        *result_status = !p->async_result ? SJ_OK : (p->count > p->res_cap ? SJ_ERR_CAPACITY : SJ_OK);
+    return SJ_OK;
+}
+
 extern "C" sj_status sj_result(sj_plan_t *p, int32_t *out, uint64_t capacity) {
     if (sj_status st = check_exec(p, kJoined)) return st;
+    if (!p->count_on_host) return fail(p->ctx, SJ_ERR_STATE, "call sj_join_wait first (the count is on the device)");
     if (capacity < p->count)
         return fail(p->ctx, SJ_ERR_CAPACITY, "result has %llu tuples, buffer holds %llu",
                     static_cast<unsigned long long>(p->count), static_cast<unsigned long long>(capacity));
@@ -1123,6 +1187,7 @@ extern "C" sj_status sj_result(sj_plan_t *p, int32_t *out, uint64_t capacity) {
     }
     MatArgs m = mat_args(p, p->n);
     m.count = p->count;
+    m.capacity = capacity;
     m.out = out;
     ProfScope ps(p, "materialize", -1, kProfResult);
     SJ_HIP(p->ctx, launch_materialize(m, p->ctx->stream));

@@ -104,3 +104,56 @@ def test_rebind_workspace_drops_graphs():
     old.fill_(0x5A)          # the old workspace is garbage now; a stale graph would read it
     for _ in range(2):
         same(snapshot(g, len(q.rels)), first)
+
+
+@pytest.mark.parametrize("seed,kind", [(9300 + i, k) for i, k in enumerate(["chain", "star", "tree", "pair"] * 2)])
+def test_async_count_and_result_match_sync(seed, kind):
+    """join_async + result_async + join_wait give the synchronous calls' count, checksum
+    and tuples, call after call (the count pass and the materialisation replay recorded
+    graphs); a new output buffer re-records the materialisation."""
+    q = W.tiny_random(seed, kind=kind)
+    ctx = sj.Context(0)
+    rels = to_device(q)
+    e = sj.Plan(ctx, rels, q.edges, root=q.root, eager=True, **OPTS)
+    ref = snapshot(e, len(q.rels))
+    a = sj.Plan(ctx, rels, q.edges, root=q.root, **OPTS)
+    cap = max(1, ref[2][0])
+    bufs = [torch.full((cap, len(q.rels)), -7, dtype=torch.int32, device="cuda:0") for _ in range(2)]
+    for i in range(4):
+        out = bufs[i // 2]
+        a.build_filters()
+        a.sieve()
+        a.join_async()
+        a.result_async(out)
+        cnt, chk, st = a.join_wait()
+        assert (cnt, chk) == ref[2] and st == sj.SJ_OK
+        assert np.array_equal(out[:cnt].cpu().numpy(), ref[3])
+
+
+def test_async_result_capacity_and_state():
+    q = W.config1(seed=5, scale=0.02)
+    ctx = sj.Context(0)
+    rels = to_device(q)
+    p = sj.Plan(ctx, rels, q.edges, root=q.root, **OPTS)
+    p.build_filters()
+    p.sieve()
+    cnt, chk = p.join()
+    assert cnt > 2
+    small = torch.full((cnt - 1, len(q.rels)), -7, dtype=torch.int32, device="cuda:0")
+    p.build_filters()
+    p.sieve()
+    p.join_async()
+    with pytest.raises(sj.SjError) as ex:   # the count is still on the device
+        p.result(small)
+    assert ex.value.code == sj.SJ_ERR_STATE
+    p.result_async(small)
+    c2, k2, st = p.join_wait()
+    assert (c2, k2) == (cnt, chk) and st == sj.SJ_ERR_CAPACITY
+    assert bool((small == -7).all())   # nothing written
+    cyc = W.tiny_random(31, kind="triangle")
+    pc = sj.Plan(ctx, to_device(cyc), cyc.edges, root=cyc.root, **OPTS)
+    pc.build_filters()
+    pc.sieve()
+    with pytest.raises(sj.SjError) as ex:
+        pc.join_async()
+    assert ex.value.code == sj.SJ_ERR_UNSUPPORTED
