@@ -285,6 +285,72 @@ const char *sj_server_last_error(const sj_server *server);
 /* Fail the queued queries, wait for the running ones and stop the workers. */
 sj_status sj_server_destroy(sj_server *server);
 
+/* ---- filter catalogue: backward filters reused across queries (Section 2.3,
+ *      "Reuse of Bloom Filters") ----
+ *
+ * A backward filter depends only on its relation's sub-tree of the join tree: the
+ * relation's rows and predicate, the column it is built on, the columns its
+ * children's filters are probed with, those filters (recursively) and the filter
+ * options (bits_per_key, k, block_bits, seed, passes). A catalogue keeps such
+ * filters resident in a caller-provided device arena (borrowed, 256-byte aligned,
+ * used by no one else while the catalogue lives), keyed by a canonical signature of
+ * exactly those inputs, in which relations are identified by their device column
+ * pointers, row counts and predicate bounds. A plan attached to a catalogue reuses
+ * every backward filter whose signature is resident: its build is dropped from the
+ * pruning phase and the resident words are probed in place. A query that contains a
+ * sub-join already answered (the paper's template Q1 inside an ad-hoc query Q2)
+ * therefore skips those filter builds. Forward and closing-condition filters depend
+ * on the whole query and are always built (for a cyclic query only the closing
+ * filter is regenerated, as Section 2.3 describes). Survivor lists, counts, checksums
+ * and tuples are identical with and without a catalogue: a reused filter holds the
+ * same bits the plan would build.
+ *
+ * A filter the plan has to build is built straight into a catalogue entry reserved at
+ * attach and is published once its build has been enqueued (later plans on other
+ * streams wait for it with a HIP event). When the arena is full, unreferenced entries
+ * are evicted least recently used first; a filter that still does not fit is built in
+ * the plan's own workspace as usual. Entries referenced by a plan are never evicted.
+ *
+ * The catalogue cannot see writes to the columns: after changing a column's contents
+ * in place, call sj_fcache_invalidate with its pointer (or sj_fcache_clear) and attach
+ * new plans; a plan already attached keeps the entries it holds. All catalogue calls
+ * are thread-safe; plans on different threads may share one catalogue. */
+
+typedef struct sj_fcache sj_fcache;
+
+typedef struct {
+    uint64_t capacity_bytes, used_bytes;
+    uint64_t entries;    /* resident (published) filters */
+    uint64_t pinned;     /* entries held by at least one plan */
+    uint64_t hits;       /* filters reused by an attaching plan */
+    uint64_t misses;     /* filters an attaching plan builds into a new entry */
+    uint64_t uncached;   /* misses with no room even after eviction (built in the workspace) */
+    uint64_t evictions;
+} sj_fcache_info;
+
+/* Create a catalogue on HIP device `device` over [arena_dev, arena_dev + arena_bytes). */
+sj_status sj_fcache_create(int32_t device, void *arena_dev, uint64_t arena_bytes, sj_fcache **out);
+/* Attach `plan` to `cache` (NULL detaches). Resolves every backward filter of the plan
+ * against the catalogue. A plan past sj_bind_workspace goes back to the bound state:
+ * call sj_build_filters again. The plan keeps its entries until it is detached,
+ * attached elsewhere or destroyed; the catalogue must outlive the attachment. */
+sj_status sj_plan_use_filter_cache(sj_plan_t *plan, sj_fcache *cache);
+/* How filter f of an attached plan is held: 0 in the plan's workspace, 1 reused from
+ * the catalogue, 2 built by this plan into a catalogue entry. */
+sj_status sj_plan_filter_cached(const sj_plan_t *plan, int32_t f, int32_t *how);
+/* Drop every entry built from a column at `column_dev` (any column the filter's
+ * sub-tree reads). Entries still held by plans leave the catalogue now and free their
+ * memory when the last plan lets go. */
+sj_status sj_fcache_invalidate(sj_fcache *cache, const void *column_dev);
+/* Drop every entry (held ones as in sj_fcache_invalidate). */
+sj_status sj_fcache_clear(sj_fcache *cache);
+sj_status sj_fcache_stats(sj_fcache *cache, sj_fcache_info *info);
+/* Destroy an empty-of-plans catalogue (SJ_ERR_STATE while a plan holds an entry).
+ * Waits for the device work that used its entries. */
+sj_status sj_fcache_destroy(sj_fcache *cache);
+/* Attach every query the server runs from now on to `cache` (NULL: none). */
+sj_status sj_server_use_filter_cache(sj_server *server, sj_fcache *cache);
+
 #ifdef __cplusplus
 }
 #endif

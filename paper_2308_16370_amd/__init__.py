@@ -47,7 +47,9 @@ EXPORTED = ["sj_ctx_create", "sj_ctx_set_stream", "sj_ctx_destroy", "sj_last_err
             "sj_filter_count", "sj_filter_desc", "sj_filter_copy", "sj_survivors_copy", "sj_profile_collect",
             "sj_profile_count", "sj_profile_entry", "sj_profile_reset", "sj_server_create", "sj_server_submit",
             "sj_server_query", "sj_server_release", "sj_server_stats", "sj_server_last_error",
-            "sj_server_destroy"]
+            "sj_server_destroy", "sj_fcache_create", "sj_plan_use_filter_cache", "sj_plan_filter_cached",
+            "sj_fcache_invalidate", "sj_fcache_clear", "sj_fcache_stats", "sj_fcache_destroy",
+            "sj_server_use_filter_cache"]
 SJ_FLAG_PROFILE = 1
 SJ_FLAG_EAGER = 2
 SJ_MAX_SLOTS = 16
@@ -84,6 +86,11 @@ class _QueryInfo(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_uint64), ("t_submit_ns", ctypes.c_int64),
                 ("t_admit_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64), ("slot", ctypes.c_int32),
                 ("error", ctypes.c_char * 160)]
+
+
+class _FcInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("capacity_bytes", "used_bytes", "entries", "pinned", "hits",
+                                              "misses", "uncached", "evictions")]
 
 
 _lib = None
@@ -126,6 +133,14 @@ def lib():
             "sj_server_release": [V, u64],
             "sj_server_stats": [V, P(u64), P(u64), P(i32), P(i32)],
             "sj_server_destroy": [V],
+            "sj_fcache_create": [i32, V, u64, P(V)],
+            "sj_plan_use_filter_cache": [V, V],
+            "sj_plan_filter_cached": [V, i32, P(i32)],
+            "sj_fcache_invalidate": [V, V],
+            "sj_fcache_clear": [V],
+            "sj_fcache_stats": [V, P(_FcInfo)],
+            "sj_fcache_destroy": [V],
+            "sj_server_use_filter_cache": [V, V],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -208,7 +223,7 @@ class Plan:
     def __init__(self, ctx: Context, rels: Sequence[Rel], edges: Sequence[Tuple[int, int, int, int]],
                  bits_per_key: int = 0, k: int = 0, block_bits: int = 0, passes: int = 0, seed: int = 0,
                  root: int = -1, workspace: Optional[torch.Tensor] = None, profile: bool = False,
-                 eager: bool = False):
+                 eager: bool = False, filter_cache: "Optional[FilterCache]" = None):
         self.ctx = ctx
         self.block_bits = block_bits or 512
         self.nrels = len(rels)
@@ -229,6 +244,20 @@ class Plan:
                                            workspace.numel() * workspace.element_size()))
         self.count = None
         self.checksum = None
+        self.filter_cache = None
+        if filter_cache is not None:
+            self.use_filter_cache(filter_cache)
+
+    def use_filter_cache(self, cache: "Optional[FilterCache]") -> None:
+        """Attach to a filter catalogue (None detaches); filters must be built again."""
+        self._check(lib().sj_plan_use_filter_cache(self.handle, cache.handle if cache is not None else None))
+        self.filter_cache = cache   # the catalogue outlives the attachment
+
+    def filter_cached(self, f: int) -> int:
+        """0: filter f is in the workspace, 1: reused from the catalogue, 2: built into it."""
+        how = ctypes.c_int32()
+        self._check(lib().sj_plan_filter_cached(self.handle, f, ctypes.byref(how)))
+        return int(how.value)
 
     def _check(self, code):
         self.ctx._check(code)
@@ -290,13 +319,17 @@ class Plan:
         self._check(lib().sj_filter_count(self.handle, ctypes.byref(n)))
         return int(n.value)
 
-    def filter_desc(self, f: int) -> dict:
+    def filter_desc(self, f: int, nblocks: bool = True) -> dict:
+        """Filter f's identity; its size in blocks (after build_filters) unless nblocks=False."""
         kind, index, rel, col = (ctypes.c_int32() for _ in range(4))
         nb = ctypes.c_uint32()
         self._check(lib().sj_filter_desc(self.handle, f, ctypes.byref(kind), ctypes.byref(index),
-                                         ctypes.byref(rel), ctypes.byref(col), ctypes.byref(nb)))
-        return dict(kind=int(kind.value), index=int(index.value), src_rel=int(rel.value),
-                    src_col=int(col.value), nblocks=int(nb.value))
+                                         ctypes.byref(rel), ctypes.byref(col),
+                                         ctypes.byref(nb) if nblocks else None))
+        d = dict(kind=int(kind.value), index=int(index.value), src_rel=int(rel.value), src_col=int(col.value))
+        if nblocks:
+            d["nblocks"] = int(nb.value)
+        return d
 
     def filter_words(self, f: int) -> torch.Tensor:
         d = self.filter_desc(f)
@@ -336,6 +369,56 @@ class Plan:
             self.handle = None
 
 
+class FilterCache:
+    """sj_fcache over a torch uint8 arena: backward filters kept resident across queries.
+
+    Plans attach with Plan(..., filter_cache=c) or plan.use_filter_cache(c); a server
+    with server.use_filter_cache(c). Attached plans and servers keep the catalogue
+    alive."""
+
+    def __init__(self, arena_bytes: int, device: int = 0, arena: Optional[torch.Tensor] = None):
+        self.device = device
+        self.arena = arena if arena is not None else torch.empty(arena_bytes, dtype=torch.uint8,
+                                                                  device="cuda:%d" % device)
+        self.handle = ctypes.c_void_p()
+        torch.cuda.synchronize(device)
+        code = lib().sj_fcache_create(device, ctypes.c_void_p(self.arena.data_ptr()), self.arena.numel(),
+                                      ctypes.byref(self.handle))
+        if code != SJ_OK:
+            raise SjError(code, "sj_fcache_create")
+
+    def stats(self) -> dict:
+        i = _FcInfo()
+        code = lib().sj_fcache_stats(self.handle, ctypes.byref(i))
+        if code != SJ_OK:
+            raise SjError(code, "sj_fcache_stats")
+        return {n: int(getattr(i, n)) for n, _ in _FcInfo._fields_}
+
+    def invalidate(self, column) -> None:
+        """Drop the entries built from `column` (a device tensor or pointer) after an in-place change."""
+        ptr = column.data_ptr() if isinstance(column, torch.Tensor) else int(column)
+        code = lib().sj_fcache_invalidate(self.handle, ctypes.c_void_p(ptr))
+        if code != SJ_OK:
+            raise SjError(code, "sj_fcache_invalidate")
+
+    def clear(self) -> None:
+        code = lib().sj_fcache_clear(self.handle)
+        if code != SJ_OK:
+            raise SjError(code, "sj_fcache_clear")
+
+    def close(self) -> None:
+        if self.handle and _lib is not None:
+            code = _lib.sj_fcache_destroy(self.handle)
+            if code != SJ_OK:
+                raise SjError(code, "sj_fcache_destroy: plans still hold entries")
+            self.handle = None
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            if _lib.sj_fcache_destroy(self.handle) == SJ_OK:
+                self.handle = None
+
+
 class Server:
     """sj_server over a torch uint8 arena on `device` with `slots` workers.
 
@@ -349,6 +432,7 @@ class Server:
                                                                   device="cuda:%d" % device)
         self.handle = ctypes.c_void_p()
         self._alive = {}
+        self.filter_cache = None
         torch.cuda.synchronize(device)   # the arena's allocation is complete before workers use it
         code = lib().sj_server_create(device, ctypes.c_void_p(self.arena.data_ptr()),
                                       self.arena.numel(), slots, ctypes.byref(self.handle))
@@ -388,6 +472,13 @@ class Server:
             return torch.empty((0, nrels), dtype=torch.int32, device=self.arena.device)
         off = q["result_offset"]
         return self.arena[off: off + 4 * n].view(torch.int32).view(q["count"], nrels)
+
+    def use_filter_cache(self, cache: Optional[FilterCache]) -> None:
+        """Attach every query admitted from now on to `cache` (None: none)."""
+        code = lib().sj_server_use_filter_cache(self.handle, cache.handle if cache is not None else None)
+        if code != SJ_OK:
+            raise SjError(code, "sj_server_use_filter_cache")
+        self.filter_cache = cache
 
     def release(self, ticket: int) -> None:
         code = lib().sj_server_release(self.handle, ticket)

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "sievejoin.h"
+#include "sj_fcache.h"
 #include "sj_internal.h"
 
 using namespace sj;
@@ -48,6 +49,12 @@ struct Filter {
     int kind, index, src_rel, src_col;
     uint64_t max_words = 0;
     uint64_t off = 0;          // workspace offset of the words
+    // filter catalogue: words and block count in a catalogue entry instead
+    FcEntry *fc = nullptr;
+    uint32_t *ext_words = nullptr, *ext_nblocks = nullptr;
+    int fc_how = 0;            // 0 workspace, 1 reused, 2 built by this plan into the entry
+    bool fc_pending = false;   // fc_how 2 and not built yet
+    bool resident() const { return fc_how == 1 || (fc_how == 2 && !fc_pending); }
 };
 
 struct StepSpec {
@@ -137,6 +144,10 @@ struct sj_plan_s {
     };
     std::vector<ProfRec> prof_pending;
     std::vector<hipEvent_t> prof_free;
+    // filter catalogue (sj_plan_use_filter_cache)
+    sj_fcache *fcache = nullptr;
+    std::vector<hipEvent_t> fc_wait;     // readiness of reused entries not yet seen complete
+    void fc_detach();
     struct ProfAcc {
         std::string label;
         double ms = 0;
@@ -168,7 +179,23 @@ void sj_plan_s::drop_graphs() {
     }
 }
 
+void sj_plan_s::fc_detach() {
+    for (auto &f : filters) {
+        if (f.fc) fc_release(fcache, f.fc, ctx->stream);
+        f.fc = nullptr;
+        f.ext_words = f.ext_nblocks = nullptr;
+        f.fc_how = 0;
+        f.fc_pending = false;
+    }
+    fc_wait.clear();
+    fcache = nullptr;
+}
+
 sj_plan_s::~sj_plan_s() {
+    if (fcache) {
+        (void)hipSetDevice(ctx->device);
+        fc_detach();
+    }
     drop_graphs();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto &r : prof_pending) {
@@ -678,6 +705,14 @@ static T *at(sj_plan_t *p, uint64_t off) {
 }
 
 static uint32_t *list_rid(sj_plan_t *p, int rel, int buf) { return at<uint32_t>(p, p->off_list[buf][rel]); }
+static uint32_t *fwords(sj_plan_t *p, int f) {
+    const Filter &F = p->filters[f];
+    return F.ext_words ? F.ext_words : at<uint32_t>(p, F.off);
+}
+static uint32_t *fnblocks(sj_plan_t *p, int f) {
+    const Filter &F = p->filters[f];
+    return F.ext_nblocks ? F.ext_nblocks : at<uint32_t>(p, p->off_nblocks) + f;
+}
 static int32_t *list_col(sj_plan_t *p, int rel, int buf, int jc) {
     return at<int32_t>(p, p->off_list[buf][rel] + 4ull * p->rels[rel].nrows * (1 + jc));
 }
@@ -750,8 +785,8 @@ static sj_status run_steps(sj_plan_t *p, int phase) {
         for (int i = 0; i < a.nprobe; ++i) {
             a.probe_col[i] = static_cast<int8_t>(st.probes[i].first);
             const int f = st.probes[i].second;
-            a.probe[i].words = at<uint32_t>(p, p->filters[f].off);
-            a.probe[i].nblocks = at<uint32_t>(p, p->off_nblocks) + f;
+            a.probe[i].words = fwords(p, f);
+            a.probe[i].nblocks = fnblocks(p, f);
         }
         if (st.out >= 0) {
             a.out_rid = list_rid(p, st.rel, st.out);
@@ -782,6 +817,7 @@ static sj_status run_steps(sj_plan_t *p, int phase) {
         for (size_t b = 0; b < st.builds.size(); ++b) {
             const int f = st.builds[b].second;
             const int jc = st.builds[b].first;
+            if (p->filters[f].resident()) continue;   // reused from the filter catalogue
             BuildArgs ba{};
             if (st.out >= 0) {          // the step's survivors
                 ba.keys = a.out_col[jc];
@@ -798,8 +834,8 @@ static sj_status run_steps(sj_plan_t *p, int phase) {
                 ba.n_dev = a.src_count;
             }
             ba.n_max = R.nrows;
-            ba.words = at<uint32_t>(p, p->filters[f].off);
-            ba.nblocks = at<uint32_t>(p, p->off_nblocks) + f;
+            ba.words = fwords(p, f);
+            ba.nblocks = fnblocks(p, f);
             ba.bits_per_key = p->opts.bits_per_key;
             ba.nblocks_max = static_cast<uint32_t>(p->filters[f].max_words / (p->opts.block_bits / 32));
             ba.region_blocks = p->region_blocks;
@@ -889,7 +925,29 @@ static sj_status enqueue_build(sj_plan_t *p) {
 
 extern "C" sj_status sj_build_filters(sj_plan_t *p) {
     if (sj_status st = check_exec(p, kBound)) return st;
+    // reused catalogue entries: wait for their producers' builds (once seen complete, never again)
+    for (size_t i = 0; i < p->fc_wait.size();) {
+        if (hipEventQuery(p->fc_wait[i]) == hipSuccess) {
+            p->fc_wait.erase(p->fc_wait.begin() + static_cast<long>(i));
+            continue;
+        }
+        SJ_HIP(p->ctx, hipStreamWaitEvent(p->ctx->stream, p->fc_wait[i], 0));
+        ++i;
+    }
     if (sj_status st = run_phase(p, 0, enqueue_build)) return st;
+    // filters built into new catalogue entries: publish them; later calls reuse them too
+    bool published = false;
+    for (auto &F : p->filters) {
+        if (!F.fc_pending) continue;
+        if (sj_status st = fc_publish(p->fcache, F.fc, p->ctx->stream))
+            return fail(p->ctx, st, "could not record a catalogue entry's readiness");
+        F.fc_pending = false;
+        published = true;
+    }
+    if (published && p->gexec[0]) {   // the recorded pruning phase still builds them
+        (void)hipGraphExecDestroy(p->gexec[0]);
+        p->gexec[0] = nullptr;
+    }
     p->state = kFiltered;
     return SJ_OK;
 }
@@ -1194,6 +1252,75 @@ extern "C" sj_status sj_result(sj_plan_t *p, int32_t *out, uint64_t capacity) {
     return SJ_OK;
 }
 
+// ---------------------------------------------------------------- filter catalogue
+
+// Canonical signature of relation j's backward filter: everything its bits depend on.
+// Its rows (count, build column, predicate), then each child's probe column with the
+// child's own signature, sorted, since the order of probes does not change the
+// survivors. `cols` collects the columns read, for invalidation.
+static std::string fc_sig(const sj_plan_t *p, int j, std::vector<const void *> &cols) {
+    const Rel &R = p->rels[j];
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "n%u:k%p", R.nrows, static_cast<const void *>(R.cols[p->mycol[j]]));
+    std::string s = buf;
+    cols.push_back(R.cols[p->mycol[j]]);
+    if (R.pred_col >= 0) {
+        std::snprintf(buf, sizeof buf, ":p%p:%d:%d", static_cast<const void *>(R.cols[R.pred_col]), R.lo, R.hi);
+        s += buf;
+        cols.push_back(R.cols[R.pred_col]);
+    }
+    std::vector<std::string> kids;
+    for (int c : p->children[j]) {
+        std::snprintf(buf, sizeof buf, "%p", static_cast<const void *>(R.cols[p->pcol[c]]));
+        cols.push_back(R.cols[p->pcol[c]]);
+        kids.push_back(std::string(buf) + "(" + fc_sig(p, c, cols) + ")");
+    }
+    std::sort(kids.begin(), kids.end());
+    s += "[";
+    for (auto &k : kids) s += k + ";";
+    return s + "]";
+}
+
+extern "C" sj_status sj_plan_use_filter_cache(sj_plan_t *p, sj_fcache *cache) {
+    if (!p) return SJ_ERR_INVALID;
+    if (cache && fc_device(cache) != p->ctx->device)
+        return fail(p->ctx, SJ_ERR_INVALID, "the filter catalogue is on device %d, the plan on %d", fc_device(cache),
+                    p->ctx->device);
+    if (p->fcache) {
+        SJ_HIP(p->ctx, hipSetDevice(p->ctx->device));
+        p->fc_detach();
+    }
+    p->drop_graphs();   // recorded launches name the previous filter locations
+    if (p->state > kBound) p->state = kBound;
+    if (!cache) return SJ_OK;
+    SJ_HIP(p->ctx, hipSetDevice(p->ctx->device));
+    p->fcache = cache;
+    char opt[96];
+    std::snprintf(opt, sizeof opt, "b%u,k%u,B%u,s%08x,p%u|", p->opts.bits_per_key, p->opts.k, p->opts.block_bits,
+                  p->seed32, p->opts.passes);
+    for (int j : p->postorder) {
+        if (j == p->root) continue;
+        Filter &F = p->filters[p->f_bwd[j]];
+        std::vector<const void *> cols;
+        const std::string sig = opt + fc_sig(p, j, cols);
+        const FcGrant g = fc_acquire(cache, sig, F.max_words, cols);
+        if (!g.entry) continue;   // no room: built in the workspace
+        F.fc = g.entry;
+        F.ext_words = g.words;
+        F.ext_nblocks = g.nblocks;
+        F.fc_how = g.hit ? 1 : 2;
+        F.fc_pending = !g.hit;
+        if (g.hit && g.ready) p->fc_wait.push_back(g.ready);
+    }
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_plan_filter_cached(const sj_plan_t *p, int32_t f, int32_t *how) {
+    if (!p || !how || f < 0 || f >= static_cast<int32_t>(p->filters.size())) return SJ_ERR_INVALID;
+    *how = p->filters[f].fc_how;
+    return SJ_OK;
+}
+
 // ---------------------------------------------------------------- introspection
 
 extern "C" sj_status sj_filter_count(const sj_plan_t *p, int32_t *nf) {
@@ -1213,7 +1340,7 @@ extern "C" sj_status sj_filter_desc(sj_plan_t *p, int32_t f, int32_t *kind, int3
     if (nblocks) {
         if (sj_status st = check_exec(p, kFiltered)) return st;
         uint32_t nb = 0;
-        SJ_HIP(p->ctx, hipMemcpyAsync(&nb, at<uint32_t>(p, p->off_nblocks) + f, 4, hipMemcpyDeviceToHost, p->ctx->stream));
+        SJ_HIP(p->ctx, hipMemcpyAsync(&nb, fnblocks(p, f), 4, hipMemcpyDeviceToHost, p->ctx->stream));
         SJ_HIP(p->ctx, hipStreamSynchronize(p->ctx->stream));
         *nblocks = nb;
     }
@@ -1227,7 +1354,7 @@ extern "C" sj_status sj_filter_copy(sj_plan_t *p, int32_t f, uint32_t *dst, uint
     if (sj_status st = sj_filter_desc(p, f, nullptr, nullptr, nullptr, nullptr, &nb)) return st;
     const uint64_t words = static_cast<uint64_t>(nb) * (p->opts.block_bits / 32);
     if (capacity_words < words) return fail(p->ctx, SJ_ERR_CAPACITY, "filter has %llu words", static_cast<unsigned long long>(words));
-    SJ_HIP(p->ctx, hipMemcpyAsync(dst, at<uint32_t>(p, p->filters[f].off), words * 4, hipMemcpyDeviceToDevice,
+    SJ_HIP(p->ctx, hipMemcpyAsync(dst, fwords(p, f), words * 4, hipMemcpyDeviceToDevice,
                                   p->ctx->stream));
     return SJ_OK;
 }
@@ -1254,8 +1381,8 @@ extern "C" sj_status sj_profile_collect(sj_plan_t *p) {
     if (p->prof_pending.empty()) return SJ_OK;
     SJ_HIP(p->ctx, hipStreamSynchronize(p->ctx->stream));
     std::vector<uint32_t> nb(p->filters.size());
-    if (!nb.empty())
-        SJ_HIP(p->ctx, hipMemcpy(nb.data(), at<uint32_t>(p, p->off_nblocks), 4 * nb.size(), hipMemcpyDeviceToHost));
+    for (size_t f = 0; f < nb.size(); ++f)
+        SJ_HIP(p->ctx, hipMemcpy(&nb[f], fnblocks(p, static_cast<int>(f)), 4, hipMemcpyDeviceToHost));
     for (auto &r : p->prof_pending) {
         float ms = 0;
         SJ_HIP(p->ctx, hipEventElapsedTime(&ms, r.a, r.b));

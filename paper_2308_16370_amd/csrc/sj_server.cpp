@@ -23,6 +23,10 @@
 #include <vector>
 
 #include "sievejoin.h"
+#include "sj_arena.h"
+
+using sj::Arena;
+using sj::round256;
 
 namespace {
 
@@ -30,55 +34,6 @@ int64_t now_ns() {
     return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
         .count();
 }
-
-uint64_t round256(uint64_t b) { return (b + 255) & ~uint64_t(255); }
-
-// First-fit allocator over [0, size) with coalescing of free neighbours.
-class Arena {
-   public:
-    explicit Arena(uint64_t size) : size_(size) {
-        if (size_) free_[0] = size_;
-    }
-    bool alloc(uint64_t bytes, uint64_t *off) {
-        bytes = round256(bytes ? bytes : 1);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const uint64_t rest = it->second - bytes, at = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[at] = rest;
-                used_ += bytes;
-                if (used_ > peak_) peak_ = used_;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(uint64_t off, uint64_t bytes) {
-        bytes = round256(bytes ? bytes : 1);
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    uint64_t size() const { return size_; }
-    uint64_t used() const { return used_; }
-    uint64_t peak() const { return peak_; }
-
-   private:
-    std::map<uint64_t, uint64_t> free_;
-    uint64_t size_, used_ = 0, peak_ = 0;
-};
 
 struct Request {
     uint64_t ticket = 0;
@@ -114,6 +69,7 @@ struct sj_server {
     int64_t stall_since = 0;      // when admission last found nothing running and nothing fitting
     bool stop = false;
     sj_status init_status = SJ_OK;
+    sj_fcache *fcache = nullptr;  // filter catalogue every admitted query attaches to
 };
 
 namespace {
@@ -140,6 +96,12 @@ sj_status execute(sj_server *s, Request &r, sj_ctx *ctx, hipStream_t stream, std
                            static_cast<int32_t>(r.edges.size()), &o, &plan, &wsb);
     if (st != SJ_OK) return done(st);
     if ((st = sj_bind_workspace(plan, s->base + r.ws_off, r.info.workspace_bytes)) != SJ_OK) return done(st);
+    sj_fcache *fc = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        fc = s->fcache;
+    }
+    if (fc && (st = sj_plan_use_filter_cache(plan, fc)) != SJ_OK) return done(st);
     if ((st = sj_build_filters(plan)) != SJ_OK) return done(st);
     if ((st = sj_sieve(plan, nullptr)) != SJ_OK) return done(st);
     uint64_t count = 0, checksum = 0;
@@ -353,6 +315,13 @@ extern "C" sj_status sj_server_stats(sj_server *s, uint64_t *arena_used, uint64_
     if (arena_peak) *arena_peak = s->arena.peak();
     if (queued) *queued = static_cast<int32_t>(s->queue.size());
     if (running) *running = s->running;
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_server_use_filter_cache(sj_server *s, sj_fcache *cache) {
+    if (!s) return SJ_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->fcache = cache;
     return SJ_OK;
 }
 
