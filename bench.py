@@ -27,6 +27,11 @@ The per-launch event timings come from a second plan on the same workspace that
 launches eagerly with an event pair around each kernel (the timed plan replays
 recorded graphs); the kernels and data are the same.
 
+filter_reuse  -- the same step on a plan attached to a filter catalogue, whose
+                 backward filters are built once and then reused (their builds drop
+                 out of the step); reported beside the headline value, which always
+                 builds every filter.
+
 --copy-mib N appends one plain device-to-device copy of N MiB (after the JSON line
 is printed) so that a counter run can calibrate FETCH_SIZE / WRITE_SIZE.
 """
@@ -181,6 +186,37 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom["label"],
                     "alg_bytes_per_launch": dom["alg_bytes"], "avg_us": round(avg_s * 1e6, 2)}
 
+    # the same step with the backward filters held in a filter catalogue (built on the
+    # first call, reused after): not the headline value, which builds every filter
+    cache = sj.FilterCache(256 << 20)
+    rplan = sj.Plan(ctx, rels, q.edges, workspace=plan.workspace, filter_cache=cache, **opts)
+    rplan.build_filters()
+    rplan.sieve()
+    if rplan.join() != (cnt, chk):
+        raise RuntimeError("the plan attached to the filter catalogue changed the result")
+    reused = sum(1 for f in range(rplan.filter_count()) if rplan.filter_cached(f) != 0)
+    for _ in range(args.warmup):
+        rplan.build_filters()
+        rplan.sieve()
+        rplan.join_async()
+        rplan.result_async(out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rplan.build_filters()
+        rplan.sieve()
+        rplan.join_async()
+        rplan.result_async(out)
+    torch.cuda.synchronize()
+    ms_reuse = (time.perf_counter() - t0) / args.steps * 1e3
+    if rplan.join_wait() != (cnt, chk, sj.SJ_OK):
+        raise RuntimeError("the plan attached to the filter catalogue changed the result")
+    filter_reuse = {"ms_per_step": round(ms_reuse, 4), "speedup": round(ms / ms_reuse, 3),
+                    "filters_in_catalogue": reused, "catalogue_bytes": cache.stats()["used_bytes"]}
+    print("# filter catalogue: %.3f ms/step with %d backward filters reused" % (ms_reuse, reused),
+          file=sys.stderr, flush=True)
+    del rplan
+
     cpu = None
     check = None
     if not args.no_cpu_baseline:
@@ -225,6 +261,7 @@ def main():
         "cpu_baseline": cpu,
         "check": check,
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "filter_reuse": filter_reuse,
         "serving": serving,
         "kernels": [{"label": e["label"], "avg_us": round(e["total_ms"] / max(1, e["launches"]) * 1e3, 2),
                      "alg_bytes": e["alg_bytes"]} for e in kernels[:12]],
