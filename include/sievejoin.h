@@ -108,6 +108,11 @@ typedef struct {
  * the context's stream; the launches and their arguments are the same either way,
  * and so are the results. sj_bind_workspace drops the recorded graphs. */
 #define SJ_FLAG_EAGER 2u
+/* Count a 3-cycle query (three relations joined in a cycle) with the binary plan, which
+ * expands every wedge of the spanning tree and then checks the closing edge, instead
+ * of the default intersection walk (see sj_join). The result is the same; for
+ * comparisons. */
+#define SJ_FLAG_BINARY_CYCLES 4u
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
  * (a hipStream_t; NULL = the null stream). The stream stays caller-owned. */
@@ -148,7 +153,14 @@ sj_status sj_sieve(sj_plan_t *plan, uint64_t *survivors);
  * relations, exact result size and checksum. Waits for the stream; count and
  * checksum are host pointers (either may be NULL). Acyclic graphs and cyclic
  * graphs whose closing edges all end at the last relation of the preorder, which
- * must be a leaf, are executed; other cyclic graphs return SJ_ERR_UNSUPPORTED. */
+ * must be a leaf, are executed; other cyclic graphs return SJ_ERR_UNSUPPORTED.
+ * A 3-cycle (root - P - L - root, one closing edge) is counted by intersection
+ * (the multi-way join that Section 3.1.3 pairs with the sieve): for each root
+ * survivor the smaller of P's rows joining it and L's rows closing on it is walked,
+ * and each one's partner key is looked up in a hash of the other relation's
+ * (key, key) pairs. Its tuples (sj_result) are still decoded from the binary plan's
+ * count pass, which sj_result runs first. SJ_FLAG_BINARY_CYCLES selects the binary
+ * plan for the count too. */
 sj_status sj_join(sj_plan_t *plan, uint64_t *count, uint64_t *checksum);
 
 /* Materialise the result: count * nrels int32 row ids, row-major, into out_dev
@@ -158,8 +170,9 @@ sj_status sj_result(sj_plan_t *plan, int32_t *out_dev, uint64_t capacity_tuples)
 
 /* Asynchronous variant of the enumeration (Section 2.2 step 2), for callers that do
  * not need the count on the host before the tuples (a whole query then runs without
- * a host round trip; every phase is replayed as a recorded graph). Acyclic plans only:
- * a cyclic plan returns SJ_ERR_UNSUPPORTED (its count needs a host step).
+ * a host round trip; every phase is replayed as a recorded graph). sj_join_async takes
+ * acyclic plans and 3-cycles counted by intersection; sj_result_async acyclic plans
+ * only. Other cyclic plans return SJ_ERR_UNSUPPORTED (their count needs a host step).
  *   sj_join_async    enqueues the count pass; the count stays on the device.
  *   sj_result_async  enqueues the materialisation into out_dev (room for
  *                    capacity_tuples tuples): the kernels read the count on the device

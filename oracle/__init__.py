@@ -91,7 +91,8 @@ def lib():
             L.orc_hash_join.restype = ctypes.c_void_p
             L.orc_result_count.argtypes = [ctypes.c_void_p]
             L.orc_result_count.restype = ctypes.c_int64
-            L.orc_triangle_cycles.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+            L.orc_triangle_cycles.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                              ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64)]
             L.orc_triangle_cycles.restype = ctypes.c_int
             L.orc_result_checksum.argtypes = [ctypes.c_void_p]
@@ -299,15 +300,26 @@ def hash_join(query, root: Optional[int] = None):
     return out, cnt, chk
 
 
-def triangle_cycles(src: np.ndarray, dst: np.ndarray) -> Tuple[int, int]:
+def triangle_cycles(src: np.ndarray, dst: np.ndarray, e1: Optional[Tuple[np.ndarray, np.ndarray]] = None
+                    ) -> Tuple[int, int]:
     """Count and checksum of E1 join E2 join E3 on E1.dst = E2.src, E2.dst = E3.src,
-    E3.dst = E1.src over the edge list (src, dst) (the 3-cycle query, Section 2.3),
-    by adjacency intersection: for every edge a -> b, the out-edges of b and the
-    in-edges of a that meet in one vertex. Independent of ``hash_join``."""
+    E3.dst = E1.src with E2 = E3 = the edge list (src, dst) (the 3-cycle query,
+    Section 2.3), by adjacency intersection: for every E1 edge a -> b, the out-edges
+    of b and the in-edges of a that meet in one vertex. E1 is the same edge list, or
+    ``e1 = (e1_src, e1_dst)`` (for instance a sample of its rows, numbered 0..m-1).
+    Independent of ``hash_join``."""
     s = np.ascontiguousarray(src, dtype=np.int32)
     d = np.ascontiguousarray(dst, dtype=np.int32)
+    if e1 is None:
+        s1, d1 = s, d
+    else:
+        s1 = np.ascontiguousarray(e1[0], dtype=np.int32)
+        d1 = np.ascontiguousarray(e1[1], dtype=np.int32)
+        if s1.shape != d1.shape:
+            raise ValueError("e1 columns differ in length")
     cnt, chk = ctypes.c_int64(), ctypes.c_uint64()
-    if lib().orc_triangle_cycles(s.shape[0], _ptr(s), _ptr(d), ctypes.byref(cnt), ctypes.byref(chk)) != 0:
+    if lib().orc_triangle_cycles(s.shape[0], _ptr(s), _ptr(d), s1.shape[0], _ptr(s1), _ptr(d1), ctypes.byref(cnt),
+                                 ctypes.byref(chk)) != 0:
         raise MemoryError("orc_triangle_cycles")
     return int(cnt.value), int(chk.value)
 

@@ -339,6 +339,8 @@ void orc_result_free(orc_result *r)
  * the same vertex c. Both adjacency lists are sorted by that vertex and merged; a
  * vertex shared by several parallel edges contributes every pair. The checksum uses
  * relation indices 0, 1, 2 for E1, E2, E3 (the definition in Section 3 above).
+ * E2 and E3 are the edge list (src, dst) of n rows; E1 is (e1_src, e1_dst) of m
+ * rows: the same list, or a subset of rows (row ids then number the subset).
  */
 typedef struct {
     int32_t key;   /* the vertex the list is grouped by */
@@ -376,7 +378,8 @@ static int64_t adj_upper(const adj_t *a, int64_t lo, int64_t hi, int32_t key)
     return lo;
 }
 
-int orc_triangle_cycles(int64_t n, const int32_t *src, const int32_t *dst, int64_t *count, uint64_t *checksum)
+int orc_triangle_cycles(int64_t n, const int32_t *src, const int32_t *dst, int64_t m, const int32_t *e1_src,
+                        const int32_t *e1_dst, int64_t *count, uint64_t *checksum)
 {
     adj_t *out = (adj_t *)malloc((size_t)(n ? n : 1) * sizeof(adj_t));   /* grouped by src, nbr = dst */
     adj_t *in = (adj_t *)malloc((size_t)(n ? n : 1) * sizeof(adj_t));    /* grouped by dst, nbr = src */
@@ -393,8 +396,8 @@ int orc_triangle_cycles(int64_t n, const int32_t *src, const int32_t *dst, int64
     qsort(in, (size_t)n, sizeof(adj_t), adj_cmp);
     int64_t cnt = 0;
     uint64_t chk = 0;
-    for (int64_t e1 = 0; e1 < n; ++e1) {
-        const int32_t a = src[e1], b = dst[e1];
+    for (int64_t e1 = 0; e1 < m; ++e1) {
+        const int32_t a = e1_src[e1], b = e1_dst[e1];
         int64_t i = adj_lower(out, 0, n, b), ie = adj_upper(out, i, n, b);   /* out-edges of b */
         int64_t j = adj_lower(in, 0, n, a), je = adj_upper(in, j, n, a);     /* in-edges of a */
         const uint64_t f1 = orc_chk_factor(0, (uint32_t)e1);

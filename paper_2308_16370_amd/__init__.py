@@ -52,6 +52,7 @@ EXPORTED = ["sj_ctx_create", "sj_ctx_set_stream", "sj_ctx_destroy", "sj_last_err
             "sj_server_use_filter_cache"]
 SJ_FLAG_PROFILE = 1
 SJ_FLAG_EAGER = 2
+SJ_FLAG_BINARY_CYCLES = 4
 SJ_MAX_SLOTS = 16
 SJ_QUERY_QUEUED, SJ_QUERY_RUNNING, SJ_QUERY_DONE, SJ_QUERY_FAILED = 0, 1, 2, 3
 SJ_RESULT_TUPLES, SJ_RESULT_COUNT = 0, 1
@@ -223,7 +224,7 @@ class Plan:
     def __init__(self, ctx: Context, rels: Sequence[Rel], edges: Sequence[Tuple[int, int, int, int]],
                  bits_per_key: int = 0, k: int = 0, block_bits: int = 0, passes: int = 0, seed: int = 0,
                  root: int = -1, workspace: Optional[torch.Tensor] = None, profile: bool = False,
-                 eager: bool = False, filter_cache: "Optional[FilterCache]" = None):
+                 eager: bool = False, filter_cache: "Optional[FilterCache]" = None, binary_cycles: bool = False):
         self.ctx = ctx
         self.block_bits = block_bits or 512
         self.nrels = len(rels)
@@ -231,7 +232,8 @@ class Plan:
         self.handle = ctypes.c_void_p()
         arr, earr, self._keep = _marshal(rels, edges)
         opts = _Opts(bits_per_key, k, block_bits, passes, seed & (2**64 - 1), root,
-                     (SJ_FLAG_PROFILE if profile else 0) | (SJ_FLAG_EAGER if eager else 0))
+                     (SJ_FLAG_PROFILE if profile else 0) | (SJ_FLAG_EAGER if eager else 0) |
+                     (SJ_FLAG_BINARY_CYCLES if binary_cycles else 0))
         wsb = ctypes.c_uint64()
         ctx._check(lib().sj_plan(ctx.handle, arr, len(rels), earr, len(edges), ctypes.byref(opts),
                                  ctypes.byref(self.handle), ctypes.byref(wsb)))

@@ -230,6 +230,18 @@ __device__ __forceinline__ uint32_t lookback32_wave(uint64_t *status, uint32_t t
     return excl;
 }
 
+__device__ __forceinline__ uint32_t upper_bound_u64(const uint64_t *a, uint32_t lo, uint32_t hi, uint64_t x) {
+    // first i in [lo, hi) with a[i] > x (hi if none)
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] > x)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
 // ---- hash index over a bucketed relation's distinct keys ------------------------
 // Slot word: ((dir + 1) << 32) | key; 0 marks an empty slot (dir + 1 >= 1).
 

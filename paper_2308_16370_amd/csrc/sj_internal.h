@@ -237,4 +237,50 @@ struct CycArgs {
 hipError_t launch_cyclic_count(const CycArgs &a, hipStream_t s);
 hipError_t launch_cyclic_write(const CycArgs &a, hipStream_t s);
 
+
+// Directed 3-cycles root - P - L - root (tree edges root-P and P-L, closing edge
+// L-root) counted by intersection instead of the binary plan's wedge expansion.
+// A pair hash maps a relation's (key, key) pair to its row count and the sum of its
+// rows' checksum factors. One slot past the table (index `cap`) holds the pair whose
+// 64-bit key equals the empty marker.
+struct PairHash {
+    uint64_t *keys;            // [cap + 1]
+    uint32_t *cnt;             // [cap + 1]
+    uint64_t *msum;            // [cap + 1]
+    uint32_t cap;              // power of two, >= 2 * rows + 1
+    uint32_t *mask;            // device-side mask used (sized from the entry count)
+};
+// Fill `h` from n_dev entries: pair (ca[e], cb[e]), checksum factor of (rel, rid[e]).
+hipError_t launch_pair_build(const PairHash &h, const uint32_t *n_dev, uint32_t cap_rows, const uint32_t *rid,
+                             const int32_t *ca, const int32_t *cb, uint32_t rel, hipStream_t s);
+
+constexpr uint32_t kTriBlocks = 2048;   // persistent grid of the intersection walk
+struct TriArgs {
+    // root survivors: x joins P's key, y joins L's closing column
+    const uint32_t *n_root;
+    uint32_t root_cap;
+    const uint32_t *root_rid;
+    const int32_t *root_x, *root_y;
+    uint32_t rel_root;
+    // P grouped by its key (x): directory and, per entry, row id and z (its key toward L)
+    const uint64_t *P_slots;
+    const uint32_t *P_mask, *P_begin, *P_rid;
+    const int32_t *P_z;
+    uint32_t rel_P;
+    // L grouped by its closing column (y): directory and, per entry, row id and its key toward P
+    const uint64_t *L_slots;
+    const uint32_t *L_mask, *L_begin, *L_rid;
+    const int32_t *L_z;
+    uint32_t rel_L;
+    PairHash HP;               // P's (x, z) pairs
+    PairHash HL;               // L's (y, z) pairs
+    uint32_t *w;               // [root_cap] walk length of each root entry | (walks L) << 31
+    uint32_t *beg;             // [root_cap] first entry of the walked group
+    uint64_t *off;             // [root_cap + 1] exclusive prefix of walk lengths
+    uint64_t *tile_sums;       // [tiles(root_cap)]
+    uint64_t *part;            // [2 * kTriBlocks] per-block count and checksum
+    uint64_t *totals;          // [2] count, checksum
+};
+hipError_t launch_tri_count(const TriArgs &a, hipStream_t s);
+
 }  // namespace sj

@@ -543,18 +543,6 @@ hipError_t launch_dp(const DpArgs &a, hipStream_t s) {
 // the first index of its chunk and then steps an odometer (last preorder position
 // fastest), which visits tuples in the same lexicographic order.
 
-__device__ __forceinline__ uint32_t upper_bound_u64(const uint64_t *a, uint32_t lo, uint32_t hi, uint64_t x) {
-    // first i in [lo, hi) with a[i] > x (hi if none)
-    while (lo < hi) {
-        const uint32_t mid = lo + ((hi - lo) >> 1);
-        if (a[mid] > x)
-            hi = mid;
-        else
-            lo = mid + 1;
-    }
-    return lo;
-}
-
 // Odometer state. Every array is indexed by compile-time positions only (the tree's
 // shape is a run-time argument, so parent links are followed by per-position tests
 // rather than by indexing), which keeps the state in registers.

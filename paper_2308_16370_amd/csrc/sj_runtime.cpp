@@ -131,6 +131,13 @@ struct sj_plan_s {
     uint64_t off_cnt = 0, off_chk = 0, off_off = 0;
     uint32_t cyc_G = 0;
     uint64_t wpre = 0;
+    // 3-cycles counted by intersection (sj_tri.hip): root - P - L - root
+    bool tri = false;
+    bool cyc_counted = false;                // the binary cyclic count pass ran since the last sieve
+    int tri_P = -1;
+    uint64_t off_tri_w = 0, off_tri_beg = 0, off_tri_off = 0, off_tri_tiles = 0, off_tri_part = 0;
+    uint64_t pair_cap[2] = {0, 0};           // P's and L's pair hashes
+    uint64_t off_pair_keys[2] = {0, 0}, off_pair_cnt[2] = {0, 0}, off_pair_msum[2] = {0, 0}, off_pair_mask[2] = {0, 0};
     uint32_t sort_cap = 0;
     int state = kPlanned;
     uint64_t count = 0, checksum = 0;
@@ -162,7 +169,7 @@ struct sj_plan_s {
     bool eager = false;                  // profiling plans and SJ_FLAG_EAGER launch one by one
     hipStream_t ls = nullptr;            // stream the launch helpers enqueue on
     hipStream_t cap_stream = nullptr;    // capture stream (created on first use)
-    hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipGraphExec_t gexec[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // build, sieve, join, result, 3-cycle count
     // asynchronous count / result (sj_join_async, sj_result_async, sj_join_wait)
     bool count_on_host = false;          // p->count / p->checksum hold the last count pass
     bool async_result = false;           // a materialisation with a device-side count is queued
@@ -545,6 +552,24 @@ static void build_layout(sj_plan_t *p) {
             p->off_bhi[j].push_back(L.take(4ull * p->rels[j].nrows));
         }
     }
+    if (p->tri) {
+        const uint64_t rn = std::max<uint64_t>(1, rc);
+        p->off_tri_w = L.take(4 * rn);
+        p->off_tri_beg = L.take(4 * rn);
+        p->off_tri_off = L.take(8 * (rc + 1));
+        p->off_tri_tiles = L.take(8ull * std::max<uint32_t>(1, tiles_of(static_cast<uint32_t>(rc), kScanTile)));
+        p->off_tri_part = L.take(16ull * kTriBlocks);
+        const int rel[2] = {p->tri_P, p->L};
+        for (int h = 0; h < 2; ++h) {
+            uint64_t cap = 16;
+            while (cap < 2ull * p->rels[rel[h]].nrows + 1) cap <<= 1;
+            p->pair_cap[h] = cap;
+            p->off_pair_keys[h] = L.take(8 * (cap + 1));
+            p->off_pair_cnt[h] = L.take(4 * (cap + 1));
+            p->off_pair_msum[h] = L.take(8 * (cap + 1));
+            p->off_pair_mask[h] = L.take(4);
+        }
+    }
     p->ws_bytes = L.top;
 }
 
@@ -569,7 +594,7 @@ extern "C" sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, con
         return fail(ctx, SJ_ERR_INVALID, "block_bits must be 256, 512 or 1024");
     if (o.passes != 1 && o.passes != 2) return fail(ctx, SJ_ERR_INVALID, "passes must be 1 or 2");
     if (o.root >= nrels) return fail(ctx, SJ_ERR_INVALID, "root out of range");
-    if (o.flags & ~static_cast<uint32_t>(SJ_FLAG_PROFILE | SJ_FLAG_EAGER))
+    if (o.flags & ~static_cast<uint32_t>(SJ_FLAG_PROFILE | SJ_FLAG_EAGER | SJ_FLAG_BINARY_CYCLES))
         return fail(ctx, SJ_ERR_INVALID, "unknown flags");
 
     sj_plan_t *p = new (std::nothrow) sj_plan_t;
@@ -664,6 +689,16 @@ extern "C" sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, con
     for (const Closing &c : p->closing) {
         if (c.v != p->L || (p->cyc_cv >= 0 && c.cv != p->cyc_cv)) p->cyc_ok = false;
         p->cyc_cv = c.cv;
+    }
+    if (p->cyclic && p->cyc_ok && nrels == 3 && p->closing.size() == 1 && !(o.flags & SJ_FLAG_BINARY_CYCLES)) {
+        // the 3-cycle root - P - L - root: counted by intersection when the pair hashes fit
+        const int r = p->root;
+        const int P = p->children[r].size() == 1 ? p->children[r][0] : -1;
+        if (P >= 0 && p->children[P].size() == 1 && p->children[P][0] == p->L && p->closing[0].u == r &&
+            p->closing[0].v == p->L && p->rels[P].nrows < (1u << 30) && p->rels[p->L].nrows < (1u << 30)) {
+            p->tri = true;
+            p->tri_P = P;
+        }
     }
     p->region_blocks = kRegionBytes / (o.block_bits / 8);
     for (auto &f : p->filters) {
@@ -1065,6 +1100,31 @@ static CycArgs cyc_args(sj_plan_t *p, int32_t *out) {
     return c;
 }
 
+// Radix-sort scratch and look-back words of relation j's bucketing (cleared with the
+// join phase's zero region; each relation has its own, the rest is shared).
+static SortScratch sort_scratch(sj_plan_t *p, int j) {
+    auto &r = p->jr[j];
+    SortScratch ss{};
+    ss.cap = p->sort_cap;
+    for (int q = 0; q < 2; ++q) {
+        ss.klo[q] = at<uint32_t>(p, p->off_sort_klo[q]);
+        ss.khi[q] = at<uint32_t>(p, p->off_sort_khi[q]);
+        ss.vals[q] = at<uint32_t>(p, p->off_sort_vals[q]);
+    }
+    ss.hist = at<uint32_t>(p, p->off_hist);
+    ss.ghist = at<uint32_t>(p, r.ghist);
+    ss.ctl = at<uint32_t>(p, p->off_ctl);
+    for (int q = 0; q < kRadixPasses; ++q) {
+        ss.lb[q].status = at<uint64_t>(p, r.lb_hist[q]);
+        ss.lb[q].counter = at<uint32_t>(p, r.lb_hist_ctr[q]);
+    }
+    return ss;
+}
+
+static Lookback dir_lookback(sj_plan_t *p, int j) {
+    return Lookback{at<uint64_t>(p, p->jr[j].lb_dir), at<uint32_t>(p, p->jr[j].lb_dir_ctr)};
+}
+
 // Count pass of the enumeration: bucket every non-root relation and run the join-tree
 // DP from the leaves up; the root's totals land in the workspace.
 static sj_status enqueue_join(sj_plan_t *p) {
@@ -1092,22 +1152,8 @@ static sj_status enqueue_join(sj_plan_t *p) {
         d.tile_sums = at<uint64_t>(p, p->off_tile_sums);
         if (j != p->root) {
             Buckets b = buckets_of(p, j);
-            auto &r = p->jr[j];
-            SortScratch ss{};
-            ss.cap = p->sort_cap;
-            for (int q = 0; q < 2; ++q) {
-                ss.klo[q] = at<uint32_t>(p, p->off_sort_klo[q]);
-                ss.khi[q] = at<uint32_t>(p, p->off_sort_khi[q]);
-                ss.vals[q] = at<uint32_t>(p, p->off_sort_vals[q]);
-            }
-            ss.hist = at<uint32_t>(p, p->off_hist);
-            ss.ghist = at<uint32_t>(p, r.ghist);
-            ss.ctl = at<uint32_t>(p, p->off_ctl);
-            for (int q = 0; q < kRadixPasses; ++q) {
-                ss.lb[q].status = at<uint64_t>(p, r.lb_hist[q]);
-                ss.lb[q].counter = at<uint32_t>(p, r.lb_hist_ctr[q]);
-            }
-            Lookback ld{at<uint64_t>(p, r.lb_dir), at<uint32_t>(p, r.lb_dir_ctr)};
+            const SortScratch ss = sort_scratch(p, j);
+            const Lookback ld = dir_lookback(p, j);
             int sec = -1;   // L of a cyclic join is ordered by its closing column inside each bucket
             if (p->cyclic && j == p->L && p->cyc_cv != p->mycol[j]) sec = R.jidx(p->cyc_cv);
             ProfScope ps(p, std::string("buckets:") + rel_name(j));
@@ -1134,6 +1180,104 @@ static sj_status enqueue_join(sj_plan_t *p) {
     return SJ_OK;
 }
 
+static PairHash pair_hash_of(sj_plan_t *p, int h) {
+    PairHash ph{};
+    ph.keys = at<uint64_t>(p, p->off_pair_keys[h]);
+    ph.cnt = at<uint32_t>(p, p->off_pair_cnt[h]);
+    ph.msum = at<uint64_t>(p, p->off_pair_msum[h]);
+    ph.cap = static_cast<uint32_t>(p->pair_cap[h]);
+    ph.mask = at<uint32_t>(p, p->off_pair_mask[h]);
+    return ph;
+}
+
+// Count pass of a 3-cycle root - P - L - root by intersection: P grouped by its key
+// toward the root, L grouped by its closing column, both relations' (key, key) pair
+// hashes, then the balanced walk.
+static sj_status enqueue_tri(sj_plan_t *p) {
+    hipStream_t s = p->ls;
+    if (sj_status st = zero_region(p, 2)) return st;
+    const int r = p->root, P = p->tri_P, L = p->L;
+    const Closing &cl = p->closing[0];
+    const int rel[2] = {P, L};
+    const int key_col[2] = {p->rels[P].jidx(p->mycol[P]), p->rels[L].jidx(cl.cv)};
+    const int z_col[2] = {p->rels[P].jidx(p->pcol[L]), p->rels[L].jidx(p->mycol[L])};
+    Buckets bk[2];
+    for (int h = 0; h < 2; ++h) {
+        const int j = rel[h];
+        const int fl = p->final_list[j];
+        const int ncol = static_cast<int>(p->rels[j].jcols.size());
+        std::vector<const int32_t *> lcols(ncol);
+        for (int c = 0; c < ncol; ++c) lcols[c] = list_col(p, j, fl, c);
+        bk[h] = buckets_of(p, j);
+        bk[h].key_jcol = key_col[h];
+        {
+            ProfScope ps(p, std::string("buckets:") + rel_name(j));
+            SJ_HIP(p->ctx, launch_build_buckets(list_rid(p, j, fl), lcols.data(), ncol, bk[h].n, key_col[h], -1, bk[h],
+                                                sort_scratch(p, j), dir_lookback(p, j), s));
+        }
+        ProfScope ps(p, std::string("pairs:") + rel_name(j));
+        SJ_HIP(p->ctx, launch_pair_build(pair_hash_of(p, h), bk[h].n, bk[h].cap, bk[h].rid, bk[h].col[key_col[h]],
+                                         bk[h].col[z_col[h]], static_cast<uint32_t>(j), s));
+    }
+    TriArgs a{};
+    const Rel &R = p->rels[r];
+    const int fl = p->final_list[r];
+    a.n_root = at<uint32_t>(p, p->steps[p->final_step[r]].off_count);
+    a.root_cap = R.nrows;
+    a.root_rid = list_rid(p, r, fl);
+    a.root_x = list_col(p, r, fl, R.jidx(p->pcol[P]));
+    a.root_y = list_col(p, r, fl, R.jidx(cl.cu));
+    a.rel_root = static_cast<uint32_t>(r);
+    a.P_slots = bk[0].slots;
+    a.P_mask = bk[0].slot_mask;
+    a.P_begin = bk[0].dir_begin;
+    a.P_rid = bk[0].rid;
+    a.P_z = bk[0].col[z_col[0]];
+    a.rel_P = static_cast<uint32_t>(P);
+    a.L_slots = bk[1].slots;
+    a.L_mask = bk[1].slot_mask;
+    a.L_begin = bk[1].dir_begin;
+    a.L_rid = bk[1].rid;
+    a.L_z = bk[1].col[z_col[1]];
+    a.rel_L = static_cast<uint32_t>(L);
+    a.HP = pair_hash_of(p, 0);
+    a.HL = pair_hash_of(p, 1);
+    a.w = at<uint32_t>(p, p->off_tri_w);
+    a.beg = at<uint32_t>(p, p->off_tri_beg);
+    a.off = at<uint64_t>(p, p->off_tri_off);
+    a.tile_sums = at<uint64_t>(p, p->off_tri_tiles);
+    a.part = at<uint64_t>(p, p->off_tri_part);
+    a.totals = at<uint64_t>(p, p->off_totals);
+    ProfScope ps(p, "tri_count");
+    SJ_HIP(p->ctx, launch_tri_count(a, s));
+    return SJ_OK;
+}
+
+// The binary plan's count pass of a cyclic join (tree DP, then the prefixes' matches
+// in L). Its per-thread offsets are what the write pass decodes.
+static sj_status binary_cyclic_count(sj_plan_t *p, uint64_t tot[2]) {
+    hipStream_t s = p->ctx->stream;
+    if (sj_status st = run_phase(p, 2, enqueue_join)) return st;
+    SJ_HIP(p->ctx, hipMemcpyAsync(tot, at<uint64_t>(p, p->off_totals), 16, hipMemcpyDeviceToHost, s));
+    SJ_HIP(p->ctx, hipStreamSynchronize(s));
+    // tot[0] counted the prefixes; now count their matches in L
+    p->wpre = tot[0];
+    uint64_t g = (p->wpre + 31) / 32;
+    p->cyc_G = static_cast<uint32_t>(std::min<uint64_t>(g, kCycThreads));
+    CycArgs c = cyc_args(p, nullptr);
+    {
+        ProfScope ps(p, "cyclic_count");
+        SJ_HIP(p->ctx, launch_cyclic_count(c, s));
+    }
+    tot[0] = tot[1] = 0;
+    if (p->cyc_G) {
+        SJ_HIP(p->ctx, hipMemcpyAsync(tot, at<uint64_t>(p, p->off_totals), 16, hipMemcpyDeviceToHost, s));
+        SJ_HIP(p->ctx, hipStreamSynchronize(s));
+    }
+    p->cyc_counted = true;
+    return SJ_OK;
+}
+
 extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) {
     if (sj_status st = check_exec(p, kSieved)) return st;
     if (!p->cyc_ok)
@@ -1142,25 +1286,18 @@ extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) 
                     "on one column",
                     p->L);
     hipStream_t s = p->ctx->stream;
-    if (sj_status st = run_phase(p, 2, enqueue_join)) return st;
     uint64_t tot[2] = {0, 0};
-    SJ_HIP(p->ctx, hipMemcpyAsync(tot, at<uint64_t>(p, p->off_totals), 16, hipMemcpyDeviceToHost, s));
-    SJ_HIP(p->ctx, hipStreamSynchronize(s));
-    if (p->cyclic) {
-        // tot[0] counted the prefixes; now count their matches in L
-        p->wpre = tot[0];
-        uint64_t g = (p->wpre + 31) / 32;
-        p->cyc_G = static_cast<uint32_t>(std::min<uint64_t>(g, kCycThreads));
-        CycArgs c = cyc_args(p, nullptr);
-        {
-            ProfScope ps(p, "cyclic_count");
-            SJ_HIP(p->ctx, launch_cyclic_count(c, s));
-        }
-        tot[0] = tot[1] = 0;
-        if (p->cyc_G) {
-            SJ_HIP(p->ctx, hipMemcpyAsync(tot, at<uint64_t>(p, p->off_totals), 16, hipMemcpyDeviceToHost, s));
-            SJ_HIP(p->ctx, hipStreamSynchronize(s));
-        }
+    p->cyc_counted = false;
+    if (p->tri) {
+        if (sj_status st = run_phase(p, 4, enqueue_tri)) return st;
+        SJ_HIP(p->ctx, hipMemcpyAsync(tot, at<uint64_t>(p, p->off_totals), 16, hipMemcpyDeviceToHost, s));
+        SJ_HIP(p->ctx, hipStreamSynchronize(s));
+    } else if (p->cyclic) {
+        if (sj_status st = binary_cyclic_count(p, tot)) return st;
+    } else {
+        if (sj_status st = run_phase(p, 2, enqueue_join)) return st;
+        SJ_HIP(p->ctx, hipMemcpyAsync(tot, at<uint64_t>(p, p->off_totals), 16, hipMemcpyDeviceToHost, s));
+        SJ_HIP(p->ctx, hipStreamSynchronize(s));
     }
     p->count = tot[0];
     p->checksum = tot[1];
@@ -1174,9 +1311,10 @@ extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) 
 
 extern "C" sj_status sj_join_async(sj_plan_t *p) {
     if (sj_status st = check_exec(p, kSieved)) return st;
-    if (!p->cyc_ok || p->cyclic)
-        return fail(p->ctx, SJ_ERR_UNSUPPORTED, "cyclic joins count in two host-driven steps: use sj_join");
-    if (sj_status st = run_phase(p, 2, enqueue_join)) return st;
+    if (!p->cyc_ok || (p->cyclic && !p->tri))
+        return fail(p->ctx, SJ_ERR_UNSUPPORTED, "this cyclic join counts in two host-driven steps: use sj_join");
+    p->cyc_counted = false;
+    if (sj_status st = p->tri ? run_phase(p, 4, enqueue_tri) : run_phase(p, 2, enqueue_join)) return st;
     p->count_on_host = false;
     p->async_result = false;
     p->state = kJoined;
@@ -1238,6 +1376,14 @@ extern "C" sj_status sj_result(sj_plan_t *p, int32_t *out, uint64_t capacity) {
     if (!out) return fail(p->ctx, SJ_ERR_INVALID, "null output buffer");
     if (reinterpret_cast<uintptr_t>(out) % 16) return fail(p->ctx, SJ_ERR_INVALID, "output must be 16-byte aligned");
     if (p->cyclic) {
+        if (!p->cyc_counted) {
+            // the count came from the intersection walk: the write pass decodes the
+            // binary plan's count pass, which must reach the same total
+            uint64_t tot[2] = {0, 0};
+            if (sj_status st = binary_cyclic_count(p, tot)) return st;
+            if (tot[0] != p->count || tot[1] != p->checksum)
+                return fail(p->ctx, SJ_ERR_DEVICE, "internal: the two cyclic count passes disagree");
+        }
         CycArgs c = cyc_args(p, out);
         ProfScope ps(p, "cyclic_write", -1, kProfResult);
         SJ_HIP(p->ctx, launch_cyclic_write(c, p->ctx->stream));

@@ -1,0 +1,315 @@
+// Directed 3-cycles by intersection.
+//
+// Section 3.1.3 pairs the sieve with a multi-way (worst-case-optimal) join for the
+// cyclic query; this is that enumeration for the 3-cycle root - P - L - root. A result
+// tuple (r, p, l) has P.key(p) = x(r), L.key(l) = z(p) and L.close(l) = y(r). For a
+// root survivor r the matches are the pairs (p, l) drawn from P's group of x(r) and
+// L's group of y(r) that agree on z. The walk takes the smaller group and looks each
+// member's z up in the other relation's pair hash, which returns how many rows hold
+// that (key, key) pair and the sum of their checksum factors, so one lookup accounts
+// for every copy of a repeated pair. The binary plan instead expands every wedge
+// (r, p) and then searches L; on power-law edge lists the wedges outnumber the walk
+// steps by two orders of magnitude.
+//
+// Balance: walk lengths per root entry are scanned, and each thread takes equal
+// chunks of consecutive walk steps (finding its entry by binary search over the
+// prefix), so a hub's long walk is split over many threads.
+#include <hip/hip_runtime.h>
+
+#include "sj_device.h"
+#include "sj_internal.h"
+
+namespace sj {
+
+namespace {
+
+constexpr uint64_t kPairEmpty = ~0ull;
+constexpr int kTriChunk = 32;        // walk steps per thread-chunk
+constexpr int kTriThreads = 256;
+
+__device__ __forceinline__ uint64_t pair_key(int32_t a, int32_t b) {
+    return (static_cast<uint64_t>(static_cast<uint32_t>(a)) << 32) | static_cast<uint32_t>(b);
+}
+
+__device__ __forceinline__ uint32_t pair_hash(uint64_t key) {
+    return static_cast<uint32_t>(mix64(key ^ 0x243F6A8885A308D3ull) >> 32);
+}
+
+__device__ __forceinline__ bool pair_find(const PairHash &h, uint32_t mask, uint64_t key, uint32_t &c,
+                                          uint64_t &ms) {
+    uint32_t s;
+    if (key == kPairEmpty) {
+        s = h.cap;
+    } else {
+        s = pair_hash(key) & mask;
+        while (true) {   // the table is at most half full: an empty slot ends every probe
+            const uint64_t k = h.keys[s];
+            if (k == key) break;
+            if (k == kPairEmpty) return false;
+            s = (s + 1) & mask;
+        }
+    }
+    c = h.cnt[s];
+    if (c == 0) return false;
+    ms = h.msum[s];
+    return true;
+}
+
+__global__ void k_pair_mask(PairHash h, const uint32_t *n_dev) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint32_t n = *n_dev;
+    uint32_t c = 16;
+    while (c < 2u * n + 1u && c < h.cap) c <<= 1;
+    *h.mask = c - 1;
+}
+
+__global__ void k_pair_clear(PairHash h) {
+    const uint32_t lim = *h.mask + 1u;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint32_t i = t; i < lim; i += gridDim.x * blockDim.x) {
+        h.keys[i] = kPairEmpty;
+        h.cnt[i] = 0;
+        h.msum[i] = 0;
+    }
+    if (t == 0) {
+        h.keys[h.cap] = kPairEmpty;
+        h.cnt[h.cap] = 0;
+        h.msum[h.cap] = 0;
+    }
+}
+
+// One insert per run of equal pairs in adjacent lanes (entries come grouped by their
+// first key, so repeated pairs are often neighbours); the run's count and factor sum
+// come from a wave prefix sum.
+__global__ __launch_bounds__(256) void k_pair_insert(PairHash h, const uint32_t *n_dev, const uint32_t *rid,
+                                                     const int32_t *ca, const int32_t *cb, uint32_t rel) {
+    const uint32_t n = *n_dev, mask = *h.mask;
+    const int lane = lane_id();
+    const uint32_t ngroups = (n + 63) / 64;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t g = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; g < ngroups; g += nwaves) {
+        const uint32_t e = g * 64 + static_cast<uint32_t>(lane);
+        const bool ok = e < n;
+        const uint64_t key = ok ? pair_key(ca[e], cb[e]) : 0;
+        const uint64_t m = ok ? chk_factor(rel, rid[e]) : 0;
+        const uint64_t prev = __shfl_up(key, 1, 64);
+        int start = (lane == 0 || key != prev) ? lane : 0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int o = __shfl_up(start, d, 64);
+            if (lane >= d && o > start) start = o;
+        }
+        const uint64_t pre = wave_incl_scan(m);
+        const uint64_t before = __shfl(pre, start > 0 ? start - 1 : 0, 64);
+        const uint64_t next = __shfl_down(key, 1, 64);
+        const bool tail = ok && (lane == 63 || e + 1 >= n || next != key);
+        if (!tail) continue;
+        const uint32_t c = static_cast<uint32_t>(lane - start + 1);
+        const uint64_t ms = pre - (start > 0 ? before : 0);
+        uint32_t s;
+        if (key == kPairEmpty) {
+            s = h.cap;
+        } else {
+            s = pair_hash(key) & mask;
+            while (true) {
+                const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long *>(h.keys + s),
+                                                         static_cast<unsigned long long>(kPairEmpty),
+                                                         static_cast<unsigned long long>(key));
+                if (old == kPairEmpty || old == key) break;
+                s = (s + 1) & mask;
+            }
+        }
+        atomicAdd(h.cnt + s, c);
+        atomicAdd(reinterpret_cast<unsigned long long *>(h.msum + s), static_cast<unsigned long long>(ms));
+    }
+}
+
+// Phase 1: each root entry's walk (the smaller of its two groups) and per-tile sums.
+__global__ __launch_bounds__(kScanBlock) void k_tri_rows(TriArgs a) {
+    __shared__ uint64_t s_w[kScanBlock / 64];
+    const uint32_t n = *a.n_root;
+    const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
+    const uint32_t pmask = *a.P_mask, lmask = *a.L_mask;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t base = tile * kScanTile + threadIdx.x * kScanItems;
+        uint64_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint32_t e = base + i;
+            if (e >= n) continue;
+            uint32_t bp = 0, np = 0, bl = 0, nl = 0;
+            const int64_t dp = dir_find(a.P_slots, pmask, a.root_x[e]);
+            if (dp >= 0) {
+                bp = a.P_begin[dp];
+                np = a.P_begin[dp + 1] - bp;
+            }
+            const int64_t dl = dir_find(a.L_slots, lmask, a.root_y[e]);
+            if (dl >= 0) {
+                bl = a.L_begin[dl];
+                nl = a.L_begin[dl + 1] - bl;
+            }
+            const bool walk_l = nl < np;
+            const uint32_t w = walk_l ? nl : np;
+            a.w[e] = w | (walk_l ? 0x80000000u : 0u);
+            a.beg[e] = walk_l ? bl : bp;
+            sum += w;
+        }
+        uint64_t tot;
+        block_excl_scan<kScanBlock>(sum, s_w, tot);
+        if (threadIdx.x == 0) a.tile_sums[tile] = tot;
+    }
+}
+
+// Phase 2 (one block): exclusive scan of the tile sums; the total lands in off[n].
+__global__ __launch_bounds__(kScanBlock) void k_tri_tiles(TriArgs a) {
+    __shared__ uint64_t s_w[kScanBlock / 64];
+    __shared__ uint64_t s_carry;
+    const uint32_t n = *a.n_root;
+    const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (uint32_t t0 = 0; t0 < ntiles; t0 += kScanBlock) {
+        const uint32_t t = t0 + threadIdx.x;
+        const uint64_t v = t < ntiles ? a.tile_sums[t] : 0;
+        uint64_t tot;
+        const uint64_t o = block_excl_scan<kScanBlock>(v, s_w, tot);
+        if (t < ntiles) a.tile_sums[t] = s_carry + o;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.off[n] = s_carry;
+}
+
+// Phase 3: per-entry exclusive prefixes.
+__global__ __launch_bounds__(kScanBlock) void k_tri_down(TriArgs a) {
+    __shared__ uint64_t s_w[kScanBlock / 64];
+    const uint32_t n = *a.n_root;
+    const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t base = tile * kScanTile + threadIdx.x * kScanItems;
+        uint64_t w[kScanItems];
+        uint64_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint32_t e = base + i;
+            w[i] = e < n ? (a.w[e] & 0x7FFFFFFFu) : 0;
+            sum += w[i];
+        }
+        uint64_t tot;
+        uint64_t o = block_excl_scan<kScanBlock>(sum, s_w, tot) + a.tile_sums[tile];
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint32_t e = base + i;
+            if (e < n) a.off[e] = o;
+            o += w[i];
+        }
+    }
+}
+
+// The walk: thread-chunks of kTriChunk consecutive steps over the scanned total.
+__global__ __launch_bounds__(kTriThreads) void k_tri_count(TriArgs a) {
+    __shared__ uint64_t s_c[kTriThreads / 64], s_k[kTriThreads / 64];
+    const uint32_t n = *a.n_root;
+    const uint64_t total = a.off[n];
+    const uint64_t nchunks = (total + kTriChunk - 1) / kTriChunk;
+    const uint32_t pm = *a.HP.mask, lm = *a.HL.mask;
+    uint64_t cnt = 0, chk = 0;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t c = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; c < nchunks; c += stride) {
+        uint64_t w = c * kTriChunk;
+        const uint64_t wend = w + kTriChunk < total ? w + kTriChunk : total;
+        // the entry whose walk holds step w: off[r] <= w < off[r + 1]
+        uint32_t r = upper_bound_u64(a.off, 0, n, w) - 1;
+        uint64_t r_lo = a.off[r], r_hi = a.off[r + 1];
+        bool walk_l = false;
+        uint32_t beg = 0;
+        int32_t x = 0, y = 0;
+        uint64_t m1 = 0;
+        bool loaded = false;
+        for (; w < wend; ++w) {
+            while (w >= r_hi) {   // the next entry with a non-empty walk
+                ++r;
+                r_lo = r_hi;
+                r_hi = a.off[r + 1];
+                loaded = false;
+            }
+            if (!loaded) {
+                const uint32_t wr = a.w[r];
+                walk_l = (wr >> 31) != 0;
+                beg = a.beg[r];
+                x = a.root_x[r];
+                y = a.root_y[r];
+                m1 = chk_factor(a.rel_root, a.root_rid[r]);
+                loaded = true;
+            }
+            const uint32_t e = beg + static_cast<uint32_t>(w - r_lo);
+            uint32_t hc;
+            uint64_t hm, mo;
+            bool hit;
+            if (!walk_l) {   // a row p of P's group of x: L rows with (y, z(p))
+                mo = chk_factor(a.rel_P, a.P_rid[e]);
+                hit = pair_find(a.HL, lm, pair_key(y, a.P_z[e]), hc, hm);
+            } else {         // a row l of L's group of y: P rows with (x, z(l))
+                mo = chk_factor(a.rel_L, a.L_rid[e]);
+                hit = pair_find(a.HP, pm, pair_key(x, a.L_z[e]), hc, hm);
+            }
+            if (hit) {
+                cnt += hc;
+                chk += m1 * mo * hm;
+            }
+        }
+    }
+    uint64_t tc, tk;
+    block_excl_scan<kTriThreads>(cnt, s_c, tc);
+    block_excl_scan<kTriThreads>(chk, s_k, tk);
+    if (threadIdx.x == 0) {
+        a.part[2 * blockIdx.x] = tc;
+        a.part[2 * blockIdx.x + 1] = tk;
+    }
+}
+
+__global__ __launch_bounds__(kTriThreads) void k_tri_final(TriArgs a, uint32_t nblocks) {
+    __shared__ uint64_t s_c[kTriThreads / 64], s_k[kTriThreads / 64];
+    uint64_t c = 0, k = 0;
+    for (uint32_t b = threadIdx.x; b < nblocks; b += blockDim.x) {
+        c += a.part[2 * b];
+        k += a.part[2 * b + 1];
+    }
+    uint64_t tc, tk;
+    block_excl_scan<kTriThreads>(c, s_c, tc);
+    block_excl_scan<kTriThreads>(k, s_k, tk);
+    if (threadIdx.x == 0) {
+        a.totals[0] = tc;
+        a.totals[1] = tk;
+    }
+}
+
+uint32_t blocks_for(uint64_t items, uint32_t per_block, uint32_t cap) {
+    const uint64_t g = (items + per_block - 1) / per_block;
+    return g == 0 ? 1u : static_cast<uint32_t>(g < cap ? g : cap);
+}
+
+}  // namespace
+
+hipError_t launch_pair_build(const PairHash &h, const uint32_t *n_dev, uint32_t cap_rows, const uint32_t *rid,
+                             const int32_t *ca, const int32_t *cb, uint32_t rel, hipStream_t s) {
+    hipLaunchKernelGGL(k_pair_mask, dim3(1), dim3(64), 0, s, h, n_dev);
+    hipLaunchKernelGGL(k_pair_clear, dim3(blocks_for(uint64_t(h.cap) + 1, 256, kPersistentBlocks)), dim3(256), 0, s, h);
+    if (cap_rows > 0)
+        hipLaunchKernelGGL(k_pair_insert, dim3(blocks_for(cap_rows, 256, kPersistentBlocks)), dim3(256), 0, s, h,
+                           n_dev, rid, ca, cb, rel);
+    return hipGetLastError();
+}
+
+hipError_t launch_tri_count(const TriArgs &a, hipStream_t s) {
+    const uint32_t tiles = blocks_for(a.root_cap, kScanTile, kPersistentBlocks);
+    hipLaunchKernelGGL(k_tri_rows, dim3(tiles), dim3(kScanBlock), 0, s, a);
+    hipLaunchKernelGGL(k_tri_tiles, dim3(1), dim3(kScanBlock), 0, s, a);
+    hipLaunchKernelGGL(k_tri_down, dim3(tiles), dim3(kScanBlock), 0, s, a);
+    hipLaunchKernelGGL(k_tri_count, dim3(kTriBlocks), dim3(kTriThreads), 0, s, a);
+    hipLaunchKernelGGL(k_tri_final, dim3(1), dim3(kTriThreads), 0, s, a, kTriBlocks);
+    return hipGetLastError();
+}
+
+}  // namespace sj

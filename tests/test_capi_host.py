@@ -86,7 +86,7 @@ def test_valid_chain_plans():
     ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"B": 384}, sj.SJ_ERR_INVALID),
     ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"passes": 3}, sj.SJ_ERR_INVALID),
     ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"root": 2}, sj.SJ_ERR_INVALID),
-    ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"flags": 4}, sj.SJ_ERR_INVALID),
+    ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"flags": 8}, sj.SJ_ERR_INVALID),
     ([(2**31, 2, None)] * 2, [(0, 1, 1, 0)], {}, sj.SJ_ERR_INVALID),
 ])
 def test_invalid_plans(specs, edges, kw, code):

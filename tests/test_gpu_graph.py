@@ -150,7 +150,7 @@ def test_async_result_capacity_and_state():
     c2, k2, st = p.join_wait()
     assert (c2, k2) == (cnt, chk) and st == sj.SJ_ERR_CAPACITY
     assert bool((small == -7).all())   # nothing written
-    cyc = W.tiny_random(31, kind="triangle")
+    cyc = W.tiny_random(31, kind="cycle4")   # counted in two host-driven steps
     pc = sj.Plan(ctx, to_device(cyc), cyc.edges, root=cyc.root, **OPTS)
     pc.build_filters()
     pc.sieve()

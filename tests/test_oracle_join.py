@@ -229,3 +229,25 @@ def test_triangle_cycles_generated_graph():
     src, dst = q.rels[0].cols
     tup, cnt, chk = oracle.hash_join(q)
     assert oracle.triangle_cycles(src, dst) == (cnt, chk)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_triangle_cycles_with_a_subset_as_first_relation(seed):
+    """E1 a subset of the rows (renumbered 0..m-1), E2 = E3 the whole list: equal to the
+    binary join plan on that query and to brute force; the subset of all rows in order
+    is the plain call."""
+    rng = np.random.default_rng(1700 + seed)
+    n = int(rng.integers(1, 70))
+    v = int(rng.integers(1, 8))
+    src = (rng.integers(0, v, n) - (3 if seed % 2 else 0)).astype(np.int32)
+    dst = (rng.integers(0, v, n) - (3 if seed % 2 else 0)).astype(np.int32)
+    idx = np.sort(rng.choice(n, int(rng.integers(0, n + 1)), replace=False))
+    s1, d1 = src[idx], dst[idx]
+    q = W.Query("sub", [W.Relation("S", [s1, d1]), W.Relation("E2", [src, dst]), W.Relation("E3", [src, dst])],
+                [(0, 1, 1, 0), (1, 1, 2, 0), (2, 1, 0, 0)])
+    _, cnt, chk = oracle.hash_join(q)
+    bf = [(i, j, k) for i in range(len(idx)) for j in range(n) for k in range(n)
+          if d1[i] == src[j] and dst[j] == src[k] and dst[k] == s1[i]]
+    assert cnt == len(bf)
+    assert oracle.triangle_cycles(src, dst, e1=(s1, d1)) == (cnt, chk)
+    assert oracle.triangle_cycles(src, dst, e1=(src, dst)) == oracle.triangle_cycles(src, dst)

@@ -148,12 +148,18 @@ def star(fact_rows: int, ndims: int, dim_rows: int, keep: float, seed: int,
     return Query(name, rels, edges, 0, dict(kind="star", keep=keep, seed=seed))
 
 
-def powerlaw_edges(nedges: int, nverts: int, gamma: float, seed: int) -> Tuple[np.ndarray, np.ndarray]:
+def powerlaw_edges(nedges: int, nverts: int, gamma: float, seed: int,
+                   device: Optional[str] = None) -> Tuple[np.ndarray, np.ndarray]:
     """Directed Chung-Lu edges: P(src = v), P(dst = v) proportional to (v+1)^(-1/(gamma-1)).
 
     Self-loops and repeated (src, dst) pairs are rejected; the first ``nedges``
     distinct pairs in draw order are kept, then vertex ids are randomly relabelled.
+    With ``device`` (a torch device name) the searches and the de-duplication run in
+    torch there; the random draws, the float64 CDF and every decision are the same,
+    so the edges are identical to the numpy path's.
     """
+    if device is not None:
+        return _powerlaw_edges_torch(nedges, nverts, gamma, seed, device)
     w = (np.arange(1, nverts + 1, dtype=np.float64)) ** (-1.0 / (gamma - 1.0))
     cdf = np.cumsum(w)
     cdf /= cdf[-1]
@@ -184,9 +190,49 @@ def powerlaw_edges(nedges: int, nverts: int, gamma: float, seed: int) -> Tuple[n
     return s, d
 
 
-def triangle(nedges: int, nverts: int, gamma: float, seed: int, name: str = "triangle") -> Query:
+def _powerlaw_edges_torch(nedges, nverts, gamma, seed, device):
+    import torch
+
+    w = (np.arange(1, nverts + 1, dtype=np.float64)) ** (-1.0 / (gamma - 1.0))
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    cdf_t = torch.from_numpy(cdf).to(device)
+    rng = rng_for(seed, 0, 0, 0)
+    keys = torch.empty(0, dtype=torch.int64, device=device)
+    drawn = 0
+    batch = int(nedges * 1.3) + 1024
+    while True:
+        u_src = torch.from_numpy(rng.random(batch)).to(device)
+        u_dst = torch.from_numpy(rng.random(batch)).to(device)
+        src = torch.clamp(torch.searchsorted(cdf_t, u_src, right=True), max=nverts - 1)
+        dst = torch.clamp(torch.searchsorted(cdf_t, u_dst, right=True), max=nverts - 1)
+        del u_src, u_dst
+        k = src * nverts + dst
+        keys = torch.cat([keys, k[src != dst]])
+        del src, dst, k
+        drawn += batch
+        # first occurrence of every distinct key, in draw order (a stable sort keeps
+        # equal keys in draw order)
+        sk, perm = torch.sort(keys, stable=True)
+        head = torch.ones_like(sk, dtype=torch.bool)
+        head[1:] = sk[1:] != sk[:-1]
+        first = torch.sort(perm[head]).values
+        del sk, perm, head
+        if first.shape[0] >= nedges:
+            sel = keys[first[:nedges]].cpu().numpy()
+            break
+        keys = keys[first]
+        batch = max(1024, int((nedges - first.shape[0]) * 1.5))
+    relabel = rng_for(seed, 0, 0, 1).permutation(nverts)
+    s = relabel[sel // nverts].astype(np.int32)
+    d = relabel[sel % nverts].astype(np.int32)
+    return s, d
+
+
+def triangle(nedges: int, nverts: int, gamma: float, seed: int, name: str = "triangle",
+             device: Optional[str] = None) -> Query:
     """E1(a,b) join E2(b,c) join E3(c,a) over one edge relation (three instances)."""
-    src, dst = powerlaw_edges(nedges, nverts, gamma, seed)
+    src, dst = powerlaw_edges(nedges, nverts, gamma, seed, device)
     rels = [Relation(f"E{i + 1}", [src, dst]) for i in range(3)]
     edges = [(0, 1, 1, 0), (1, 1, 2, 0), (2, 1, 0, 0)]
     return Query(name, rels, edges, 0, dict(kind="triangle", nverts=nverts, gamma=gamma, seed=seed))
@@ -237,9 +283,10 @@ def config3(seed: int = 0x5EED0003, scale: float = 1.0) -> Query:
                 name="star4")
 
 
-def config4(seed: int = 0x5EED0004, scale: float = 1.0) -> Query:
-    """Triangle over 50M power-law (gamma 2.1) edges on 2^22 vertices."""
-    return triangle(max(1, int(50_000_000 * scale)), max(8, int((1 << 22) * scale)), 2.1, seed)
+def config4(seed: int = 0x5EED0004, scale: float = 1.0, device: Optional[str] = None) -> Query:
+    """Triangle over 50M power-law (gamma 2.1) edges on 2^22 vertices (``device``: see
+    powerlaw_edges)."""
+    return triangle(max(1, int(50_000_000 * scale)), max(8, int((1 << 22) * scale)), 2.1, seed, device=device)
 
 
 def tiny_random(seed: int, kind: str = "any") -> Query:
