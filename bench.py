@@ -27,6 +27,9 @@ The per-launch event timings come from a second plan on the same workspace that
 launches eagerly with an event pair around each kernel (the timed plan replays
 recorded graphs); the kernels and data are the same.
 
+configs       -- the star (100M-row fact table) and the full-size triangle (50M
+                 edges, 3-cycles counted by intersection), timed the same way
+                 (paper_2308_16370_amd/configbench.py).
 filter_reuse  -- the same step on a plan attached to a filter catalogue, whose
                  backward filters are built once and then reused (their builds drop
                  out of the step); reported beside the headline value, which always
@@ -84,6 +87,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0, help="append a plain copy of this many MiB")
     ap.add_argument("--no-serve", action="store_true", help="skip the batched / served query mix")
+    ap.add_argument("--no-configs", action="store_true", help="skip the star and triangle workloads")
     ap.add_argument("--serve-queries", type=int, default=256)
     ap.add_argument("--serve-max-rows", type=int, default=20_000_000)
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -231,6 +235,23 @@ def main():
         if check == "MISMATCH":
             print("# oracle mismatch: gpu %r oracle %r" % ((cnt, chk), (rcnt, rchk)), file=sys.stderr)
 
+    configs = None
+    if not args.no_configs:
+        from paper_2308_16370_amd import configbench
+        logf = lambda m: print(m, file=sys.stderr, flush=True)
+        configs = {"star": configbench.star(log=logf), "triangle": configbench.triangle(log=logf)}
+        tri = configs["triangle"]
+        gold = os.path.join(ROOT, "tests", "golden", "triangle_cycles.json")
+        tri["check"] = "no stored oracle value at this size"
+        if os.path.exists(gold):
+            with open(gold) as fh:
+                cases = [c for c in json.load(fh)["cases"] if abs(c["scale"] - 1.0) < 1e-12]
+            if cases:
+                ok = (cases[0]["count"], cases[0]["checksum"]) == (tri["result_tuples"], tri["checksum"])
+                tri["check"] = "count and checksum equal the stored oracle value" if ok else "MISMATCH"
+        logf("# star %.3f ms/step, triangle %.1f ms/step (%s)" % (configs["star"]["ms_per_step"],
+                                                                  tri["ms_per_step"], tri["check"]))
+
     serving = None
     if not args.no_serve:
         from paper_2308_16370_amd import servebench
@@ -262,6 +283,7 @@ def main():
         "check": check,
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
         "filter_reuse": filter_reuse,
+        "configs": configs,
         "serving": serving,
         "kernels": [{"label": e["label"], "avg_us": round(e["total_ms"] / max(1, e["launches"]) * 1e3, 2),
                      "alg_bytes": e["alg_bytes"]} for e in kernels[:12]],

@@ -102,3 +102,23 @@ def test_triangle_one_16th_golden():
     cnt, chk = plan.join()
     assert (cnt, chk) == (case["count"], case["checksum"])
     _check_triangle_tuples(q, plan.result())
+
+
+def _golden_cases(min_scale):
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "triangle_cycles.json")))
+    return [pytest.param(c, id="scale-%g" % c["scale"]) for c in g["cases"] if c["scale"] >= min_scale]
+
+
+@pytest.mark.parametrize("case", _golden_cases(0.25))
+def test_triangle_count_at_large_scale_golden(case):
+    """The triangle workload at 1/4 size and above (generated on the GPU, identical to
+    the numpy generator's edges): the intersection count and checksum equal the
+    stored oracle values (tests/golden/triangle_cycles.json)."""
+    q = W.config4(scale=case["scale"], device="cuda:0")
+    assert q.rels[0].nrows == case["edges"]
+    plan = make_plan(q, bits_per_key=8, k=6, block_bits=512, passes=2, seed=0x5EED0004)
+    plan.build_filters()
+    plan.sieve()
+    assert plan.join() == (case["count"], case["checksum"])
