@@ -119,10 +119,11 @@ struct sj_plan_s {
         uint32_t slot_cap = 0;
         uint64_t ghist = 0, lb_hist[kRadixPasses] = {}, lb_hist_ctr[kRadixPasses] = {};
         uint64_t lb_dir = 0, lb_dir_ctr = 0;
+        // radix-sort scratch of its own (relations are bucketed concurrently)
+        uint64_t sklo[2] = {0, 0}, skhi[2] = {0, 0}, svals[2] = {0, 0}, shist = 0, sctl = 0;
     };
     std::vector<JoinRel> jr;
-    uint64_t off_sort_klo[2] = {0, 0}, off_sort_khi[2] = {0, 0}, off_sort_vals[2] = {0, 0};
-    uint64_t off_hist = 0, off_ctl = 0, off_tile_sums = 0;
+    uint64_t off_tile_sums = 0;
     uint64_t off_root_cw = 0, off_root_cv = 0;
     std::vector<std::vector<uint64_t>> off_blo, off_bhi;   // [relation][child]
     // cyclic graphs: closing edges all end at L = the last relation of the preorder
@@ -138,7 +139,6 @@ struct sj_plan_s {
     uint64_t off_tri_w = 0, off_tri_beg = 0, off_tri_off = 0, off_tri_tiles = 0, off_tri_part = 0;
     uint64_t pair_cap[2] = {0, 0};           // P's and L's pair hashes
     uint64_t off_pair_keys[2] = {0, 0}, off_pair_cnt[2] = {0, 0}, off_pair_msum[2] = {0, 0}, off_pair_mask[2] = {0, 0};
-    uint32_t sort_cap = 0;
     int state = kPlanned;
     uint64_t count = 0, checksum = 0;
     // event profiling (SJ_FLAG_PROFILE): one event pair per launch group
@@ -170,6 +170,11 @@ struct sj_plan_s {
     hipStream_t ls = nullptr;            // stream the launch helpers enqueue on
     hipStream_t cap_stream = nullptr;    // capture stream (created on first use)
     hipGraphExec_t gexec[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // build, sieve, join, result, 3-cycle count
+    // independent launch groups (the relations' bucketings) run on branch streams that
+    // fork from and join back into the launch stream through events
+    static constexpr int kBranches = 4;
+    hipStream_t branch[kBranches] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t fork_ev = nullptr, join_ev[kBranches] = {nullptr, nullptr, nullptr, nullptr};
     // asynchronous count / result (sj_join_async, sj_result_async, sj_join_wait)
     bool count_on_host = false;          // p->count / p->checksum hold the last count pass
     bool async_result = false;           // a materialisation with a device-side count is queued
@@ -205,6 +210,11 @@ sj_plan_s::~sj_plan_s() {
     }
     drop_graphs();
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (auto &b : branch)
+        if (b) (void)hipStreamDestroy(b);
+    for (auto &e : join_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
     for (auto &r : prof_pending) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -529,14 +539,19 @@ static void build_layout(sj_plan_t *p) {
         r.cv = L.take(8 * (cap + 1));
         r.mask = L.take(4);
     }
-    p->sort_cap = maxcap;
-    for (int b = 0; b < 2; ++b) {
-        p->off_sort_klo[b] = L.take(4ull * maxcap);
-        p->off_sort_khi[b] = L.take(4ull * maxcap);
-        p->off_sort_vals[b] = L.take(4ull * maxcap);
+    for (int j = 0; j < n; ++j) {
+        if (j == p->root) continue;
+        auto &r = p->jr[j];
+        const uint64_t cap = std::max<uint32_t>(1, p->rels[j].nrows);
+        const bool two_word = p->cyclic && j == p->L;   // bucketed by (tree key, closing key)
+        for (int b = 0; b < 2; ++b) {
+            r.sklo[b] = L.take(4 * cap);
+            r.skhi[b] = two_word ? L.take(4 * cap) : 0;
+            r.svals[b] = L.take(4 * cap);
+        }
+        r.shist = L.take(4ull * kRadixBins * std::max<uint32_t>(1, tiles_of(static_cast<uint32_t>(cap), kRadixTile)));
+        r.sctl = L.take(4 * 32);
     }
-    p->off_hist = L.take(4ull * kRadixBins * std::max<uint32_t>(1, tiles_of(maxcap, kRadixTile)));
-    p->off_ctl = L.take(4 * 32);
     p->off_tile_sums = L.take(16ull * std::max<uint32_t>(1, tiles_of(maxcap, kScanTile)));
     const uint64_t rc = p->rels[p->root].nrows;
     p->off_root_cw = L.take(8 * (rc + 1));
@@ -912,6 +927,42 @@ static sj_status check_exec(sj_plan_t *p, int need) {
 }
 
 
+// Branch streams and their events, created outside any capture.
+static sj_status ensure_branches(sj_plan_t *p) {
+    if (p->profile || p->fork_ev) return SJ_OK;
+    for (auto &b : p->branch) SJ_HIP(p->ctx, hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
+    for (auto &e : p->join_ev) SJ_HIP(p->ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    SJ_HIP(p->ctx, hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
+    return SJ_OK;
+}
+
+// Fork: branch i (of n) gets out[i], which starts after everything enqueued on the
+// launch stream so far. Profiled plans keep every launch on the launch stream, so that
+// each group's events time it alone.
+static sj_status fork_streams(sj_plan_t *p, int n, hipStream_t *out) {
+    if (p->profile || n <= 1) {
+        for (int i = 0; i < n; ++i) out[i] = p->ls;
+        return SJ_OK;
+    }
+    if (sj_status st = ensure_branches(p)) return st;
+    SJ_HIP(p->ctx, hipEventRecord(p->fork_ev, p->ls));
+    for (int i = 0; i < n; ++i) {
+        if (i < sj_plan_s::kBranches) SJ_HIP(p->ctx, hipStreamWaitEvent(p->branch[i], p->fork_ev, 0));
+        out[i] = p->branch[i % sj_plan_s::kBranches];
+    }
+    return SJ_OK;
+}
+
+// Join: the launch stream continues after every branch of the last fork of n.
+static sj_status join_streams(sj_plan_t *p, int n) {
+    if (p->profile || n <= 1) return SJ_OK;
+    for (int i = 0; i < n && i < sj_plan_s::kBranches; ++i) {
+        SJ_HIP(p->ctx, hipEventRecord(p->join_ev[i], p->branch[i]));
+        SJ_HIP(p->ctx, hipStreamWaitEvent(p->ls, p->join_ev[i], 0));
+    }
+    return SJ_OK;
+}
+
 // Enqueue one launch phase on the context's stream: eagerly, or by replaying the
 // phase's graph, recorded from `enqueue` on the first call.
 static sj_status run_phase(sj_plan_t *p, int ph, sj_status (*enqueue)(sj_plan_t *)) {
@@ -921,6 +972,7 @@ static sj_status run_phase(sj_plan_t *p, int ph, sj_status (*enqueue)(sj_plan_t 
     }
     if (!p->gexec[ph]) {
         if (!p->cap_stream) SJ_HIP(p->ctx, hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+        if (sj_status st = ensure_branches(p)) return st;
         p->ls = p->cap_stream;
         SJ_HIP(p->ctx, hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
         const sj_status st = enqueue(p);
@@ -1100,20 +1152,21 @@ static CycArgs cyc_args(sj_plan_t *p, int32_t *out) {
     return c;
 }
 
-// Radix-sort scratch and look-back words of relation j's bucketing (cleared with the
-// join phase's zero region; each relation has its own, the rest is shared).
+// Radix-sort scratch and look-back words of relation j's bucketing (the look-back
+// words and histogram are cleared with the join phase's zero region). Each relation
+// has its own, so that relations are bucketed concurrently.
 static SortScratch sort_scratch(sj_plan_t *p, int j) {
     auto &r = p->jr[j];
     SortScratch ss{};
-    ss.cap = p->sort_cap;
+    ss.cap = p->rels[j].nrows;
     for (int q = 0; q < 2; ++q) {
-        ss.klo[q] = at<uint32_t>(p, p->off_sort_klo[q]);
-        ss.khi[q] = at<uint32_t>(p, p->off_sort_khi[q]);
-        ss.vals[q] = at<uint32_t>(p, p->off_sort_vals[q]);
+        ss.klo[q] = at<uint32_t>(p, r.sklo[q]);
+        ss.khi[q] = r.skhi[q] ? at<uint32_t>(p, r.skhi[q]) : nullptr;
+        ss.vals[q] = at<uint32_t>(p, r.svals[q]);
     }
-    ss.hist = at<uint32_t>(p, p->off_hist);
+    ss.hist = at<uint32_t>(p, r.shist);
     ss.ghist = at<uint32_t>(p, r.ghist);
-    ss.ctl = at<uint32_t>(p, p->off_ctl);
+    ss.ctl = at<uint32_t>(p, r.sctl);
     for (int q = 0; q < kRadixPasses; ++q) {
         ss.lb[q].status = at<uint64_t>(p, r.lb_hist[q]);
         ss.lb[q].counter = at<uint32_t>(p, r.lb_hist_ctr[q]);
@@ -1130,6 +1183,29 @@ static Lookback dir_lookback(sj_plan_t *p, int j) {
 static sj_status enqueue_join(sj_plan_t *p) {
     hipStream_t s = p->ls;
     if (sj_status st = zero_region(p, 2)) return st;
+    // every non-root relation is bucketed on a branch of its own; the DP then runs
+    // bottom-up on the launch stream
+    std::vector<int> inner;
+    for (int j : p->postorder)
+        if (j != p->root) inner.push_back(j);
+    std::vector<hipStream_t> br(std::max<size_t>(1, inner.size()));
+    if (sj_status st = fork_streams(p, static_cast<int>(inner.size()), br.data())) return st;
+    for (size_t i = 0; i < inner.size(); ++i) {
+        const int j = inner[i];
+        const int fl = p->final_list[j];
+        const Rel &R = p->rels[j];
+        const int ncol = static_cast<int>(R.jcols.size());
+        std::vector<const int32_t *> lcols(ncol);
+        for (int c = 0; c < ncol; ++c) lcols[c] = list_col(p, j, fl, c);
+        const uint32_t *lcount = at<uint32_t>(p, p->steps[p->final_step[j]].off_count);
+        Buckets b = buckets_of(p, j);
+        int sec = -1;   // L of a cyclic join is ordered by its closing column inside each bucket
+        if (p->cyclic && j == p->L && p->cyc_cv != p->mycol[j]) sec = R.jidx(p->cyc_cv);
+        ProfScope ps(p, std::string("buckets:") + rel_name(j));
+        SJ_HIP(p->ctx, launch_build_buckets(list_rid(p, j, fl), lcols.data(), ncol, lcount, b.key_jcol, sec, b,
+                                            sort_scratch(p, j), dir_lookback(p, j), br[i]));
+    }
+    if (sj_status st = join_streams(p, static_cast<int>(inner.size()))) return st;
     for (int j : p->postorder) {
         const int fl = p->final_list[j];
         const Rel &R = p->rels[j];
@@ -1151,13 +1227,7 @@ static sj_status enqueue_join(sj_plan_t *p) {
         }
         d.tile_sums = at<uint64_t>(p, p->off_tile_sums);
         if (j != p->root) {
-            Buckets b = buckets_of(p, j);
-            const SortScratch ss = sort_scratch(p, j);
-            const Lookback ld = dir_lookback(p, j);
-            int sec = -1;   // L of a cyclic join is ordered by its closing column inside each bucket
-            if (p->cyclic && j == p->L && p->cyc_cv != p->mycol[j]) sec = R.jidx(p->cyc_cv);
-            ProfScope ps(p, std::string("buckets:") + rel_name(j));
-            SJ_HIP(p->ctx, launch_build_buckets(list_rid(p, j, fl), lcols.data(), ncol, lcount, b.key_jcol, sec, b, ss, ld, s));
+            const Buckets b = buckets_of(p, j);
             d.n = b.n;
             d.cap = b.cap;
             d.rid = b.rid;
@@ -1202,6 +1272,8 @@ static sj_status enqueue_tri(sj_plan_t *p) {
     const int key_col[2] = {p->rels[P].jidx(p->mycol[P]), p->rels[L].jidx(cl.cv)};
     const int z_col[2] = {p->rels[P].jidx(p->pcol[L]), p->rels[L].jidx(p->mycol[L])};
     Buckets bk[2];
+    hipStream_t br[2];
+    if (sj_status st = fork_streams(p, 2, br)) return st;
     for (int h = 0; h < 2; ++h) {
         const int j = rel[h];
         const int fl = p->final_list[j];
@@ -1213,12 +1285,13 @@ static sj_status enqueue_tri(sj_plan_t *p) {
         {
             ProfScope ps(p, std::string("buckets:") + rel_name(j));
             SJ_HIP(p->ctx, launch_build_buckets(list_rid(p, j, fl), lcols.data(), ncol, bk[h].n, key_col[h], -1, bk[h],
-                                                sort_scratch(p, j), dir_lookback(p, j), s));
+                                                sort_scratch(p, j), dir_lookback(p, j), br[h]));
         }
         ProfScope ps(p, std::string("pairs:") + rel_name(j));
         SJ_HIP(p->ctx, launch_pair_build(pair_hash_of(p, h), bk[h].n, bk[h].cap, bk[h].rid, bk[h].col[key_col[h]],
-                                         bk[h].col[z_col[h]], static_cast<uint32_t>(j), s));
+                                         bk[h].col[z_col[h]], static_cast<uint32_t>(j), br[h]));
     }
+    if (sj_status st = join_streams(p, 2)) return st;
     TriArgs a{};
     const Rel &R = p->rels[r];
     const int fl = p->final_list[r];
