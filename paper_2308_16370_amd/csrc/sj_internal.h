@@ -96,8 +96,17 @@ __host__ __device__ inline uint32_t build_tile_of(uint32_t n) {
     const uint32_t t = (per + kBuildTileMin - 1) / kBuildTileMin * kBuildTileMin;
     return t > kBuildTileMin ? t : kBuildTileMin;
 }
-constexpr uint32_t kRegionBytes = 16 * 1024;   // LDS per region workgroup
+constexpr uint32_t kRegionBytes = 16 * 1024;   // LDS per region workgroup (the largest region)
 constexpr int kRegionThreads = 512;
+// A filter is cut into at least kRegionsTarget regions when regions of kRegionMinShift
+// (log2 blocks) or more allow it, so small filters still spread over the chip; the
+// region count is then below max(blocks / largest region, 2 * kRegionsTarget).
+constexpr uint32_t kRegionsTarget = 256;
+constexpr uint32_t kRegionMinShift = 3;
+__host__ __device__ constexpr uint32_t region_count_cap(uint64_t nblocks_max, uint32_t region_blocks) {
+    const uint64_t big = (nblocks_max + region_blocks - 1) / region_blocks;
+    return static_cast<uint32_t>(big > 2 * kRegionsTarget ? big : 2 * kRegionsTarget);
+}
 struct BuildArgs {
     const int32_t *keys;
     const uint32_t *n_dev;     // list source: device-side length; nullptr: use n
@@ -110,7 +119,7 @@ struct BuildArgs {
     uint32_t *words;
     uint32_t *nblocks;         // device-side filter size in blocks (written by the build)
     uint32_t nblocks_max;
-    uint32_t region_blocks;    // kRegionBytes / (block bytes)
+    uint32_t region_blocks;    // kRegionBytes / (block bytes): the largest region (a power of two)
     uint32_t *hist;            // [regions * tiles] counts, then their exclusive prefix
     uint64_t *keep;            // [(n_max + tile) / 64] bit e: element e is staged
     uint32_t *stage;           // [n_max] staged keys, grouped by region

@@ -492,6 +492,7 @@ __device__ __forceinline__ bool bfb_take(const BuildArgs &a, uint32_t e, int32_t
 
 struct BfbShape {
     uint32_t n, nb, nreg, tile, ntiles;
+    uint32_t rshift;           // a region is 2^rshift blocks
 };
 
 __device__ __forceinline__ BfbShape bfb_shape(const BuildArgs &a) {
@@ -502,7 +503,10 @@ __device__ __forceinline__ BfbShape bfb_shape(const BuildArgs &a) {
     const uint64_t B = 1ull << a.logB;
     uint64_t nb = (nkeys * a.bits_per_key + B - 1) / B;
     s.nb = nb ? static_cast<uint32_t>(nb) : 1u;
-    s.nreg = (s.nb + a.region_blocks - 1) / a.region_blocks;
+    // the largest region unless that leaves fewer than kRegionsTarget regions
+    s.rshift = 31u - static_cast<uint32_t>(__builtin_clz(a.region_blocks));
+    while (s.rshift > kRegionMinShift && (s.nb >> s.rshift) < kRegionsTarget) --s.rshift;
+    s.nreg = (s.nb + (1u << s.rshift) - 1) >> s.rshift;
     s.tile = build_tile_of(s.n);
     s.ntiles = (s.n + s.tile - 1) / s.tile;
     return s;
@@ -565,7 +569,7 @@ __global__ __launch_bounds__(kBuildBlock) void k_bfb_hist(BuildArgs a) {
                     keep = atomicExch(&s_seen[dedup_slot(kk)], kk) != kk;
                     if (keep) {
                         const BfKey h = bf_hash(key[u], a.seed, sh.nb);
-                        atomicAdd(&s_hist[h.block / a.region_blocks], 1u);
+                        atomicAdd(&s_hist[h.block >> sh.rshift], 1u);
                     }
                 }
                 const uint64_t m = __ballot(keep);
@@ -640,7 +644,7 @@ __global__ __launch_bounds__(kBuildBlock) void k_bfb_scatter(BuildArgs a) {
             for (int u = 0; u < kBuildBatch; ++u) {
                 if (take[u]) {
                     const BfKey h = bf_hash(key[u], a.seed, sh.nb);
-                    const uint32_t pos = atomicAdd(&s_off[h.block / a.region_blocks], 1u);
+                    const uint32_t pos = atomicAdd(&s_off[h.block >> sh.rshift], 1u);
                     a.stage[pos] = static_cast<uint32_t>(key[u]);
                 }
             }
@@ -657,8 +661,8 @@ __global__ __launch_bounds__(kRegionThreads) void k_bfb_region(BuildArgs a) {
     const uint32_t total = *a.total_dev;
     constexpr int U = 4;
     for (uint32_t r = blockIdx.x; r < sh.nreg; r += gridDim.x) {
-        const uint32_t b0 = r * a.region_blocks;
-        const uint32_t nbr = min(a.region_blocks, sh.nb - b0);
+        const uint32_t b0 = r << sh.rshift;
+        const uint32_t nbr = min(1u << sh.rshift, sh.nb - b0);
         const uint32_t nw = nbr << wpb_shift;
         for (uint32_t i = threadIdx.x; i < nw; i += kRegionThreads) s_words[i] = 0;
         __syncthreads();
@@ -710,7 +714,7 @@ __global__ __launch_bounds__(kRegionThreads) void k_bfb_region(BuildArgs a) {
 
 hipError_t launch_filter_build_stage(const BuildArgs &a, int stage, hipStream_t s) {
     const uint32_t ntiles_max = min(kBuildMaxTiles, (a.n_max + kBuildTileMin - 1) / kBuildTileMin);
-    const uint32_t nreg_max = (a.nblocks_max + a.region_blocks - 1) / a.region_blocks;
+    const uint32_t nreg_max = region_count_cap(a.nblocks_max, a.region_blocks);
     const size_t lds_hist = 4ull * (nreg_max ? nreg_max : 1);
     const size_t lds_region = 4ull * a.region_blocks * (1u << (a.logB - 5));
     const uint32_t tgrid = ntiles_max == 0 ? 1 : (ntiles_max < 2048 ? ntiles_max : 2048);

@@ -475,7 +475,7 @@ static void build_layout(sj_plan_t *p) {
             for (auto &b : s.builds) {
                 const Filter &f = p->filters[b.second];
                 const uint64_t nbm = f.max_words / (p->opts.block_bits / 32);
-                const uint64_t nreg = (nbm + p->region_blocks - 1) / p->region_blocks;
+                const uint64_t nreg = region_count_cap(nbm, p->region_blocks);
                 // tiles of any input of up to max_rows keys (build_tile_of keeps them <= kBuildMaxTiles)
                 const uint64_t hl = nreg * std::min<uint32_t>(kBuildMaxTiles, tiles_of(s.max_rows, kBuildTileMin));
                 max_hist = std::max<uint64_t>(max_hist, hl);
