@@ -68,6 +68,8 @@ struct StepSpec {
     uint64_t off_count = 0;
     uint32_t max_rows = 0;
     std::vector<uint64_t> off_bstatus, off_bcounter, off_btotal;   // per build
+    int level = 0;             // steps of one phase and level are independent of each other
+    int branch = 0;            // its branch stream and scratch set inside the level
 };
 
 struct Region {
@@ -110,8 +112,12 @@ struct sj_plan_s {
     Region zero[3];                          // build_filters, sieve, join
     uint64_t off_elig = 0, off_nblocks = 0, off_totals = 0;
     uint32_t region_blocks = 0;
-    uint64_t off_bhist = 0, off_stage[2] = {0, 0}, off_keep = 0;
-    uint64_t off_sbits = 0, off_scounts = 0;   // sieve scratch: survivor bits, per-workgroup counts
+    // probe and build scratch, one set per branch: survivor bits, per-workgroup counts,
+    // region histogram, staged keys, kept-key bitmap
+    static constexpr int kSets = 4;
+    uint64_t off_sbits[kSets] = {}, off_scounts[kSets] = {}, off_bhist[kSets] = {}, off_stage[kSets] = {},
+             off_keep[kSets] = {};
+    std::vector<std::vector<int>> level_steps[2];   // per phase: the steps of each level
     std::vector<uint64_t> off_list[2];       // per relation: list buffer base
     // join phase
     struct JoinRel {
@@ -175,6 +181,7 @@ struct sj_plan_s {
     static constexpr int kBranches = 4;
     hipStream_t branch[kBranches] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t fork_ev = nullptr, join_ev[kBranches] = {nullptr, nullptr, nullptr, nullptr};
+    static_assert(kBranches == kSets, "one scratch set per branch");
     // asynchronous count / result (sj_join_async, sj_result_async, sj_join_wait)
     bool count_on_host = false;          // p->count / p->checksum hold the last count pass
     bool async_result = false;           // a materialisation with a device-side count is queued
@@ -456,18 +463,45 @@ static sj_status build_schedule(sj_plan_t *p) {
     return SJ_OK;
 }
 
+// Dependency levels of each phase's steps: a step follows the step that wrote its
+// source list and the steps that build the filters it probes (inside the same phase;
+// the previous phase has finished). Steps of one level run on separate branches.
+static void schedule_levels(sj_plan_t *p) {
+    std::vector<int> builder(p->filters.size(), -1);
+    for (int ph = 0; ph < 2; ++ph) {
+        p->level_steps[ph].clear();
+        for (size_t si = 0; si < p->steps.size(); ++si) {
+            StepSpec &st = p->steps[si];
+            if (st.phase != ph) continue;
+            int lvl = 0;
+            if (st.src_step >= 0 && p->steps[st.src_step].phase == ph) lvl = p->steps[st.src_step].level + 1;
+            for (auto &pr : st.probes) {
+                const int b = builder[pr.second];
+                if (b >= 0 && p->steps[b].phase == ph) lvl = std::max(lvl, p->steps[b].level + 1);
+            }
+            for (auto &bl : st.builds) builder[bl.second] = static_cast<int>(si);
+            st.level = lvl;
+            if (p->level_steps[ph].size() <= static_cast<size_t>(lvl)) p->level_steps[ph].resize(lvl + 1);
+            auto &lv = p->level_steps[ph][lvl];
+            st.branch = static_cast<int>(lv.size()) % sj_plan_s::kSets;
+            lv.push_back(static_cast<int>(si));
+        }
+    }
+}
+
 static void build_layout(sj_plan_t *p) {
     Layout L;
     const int n = p->n;
     // phase zero regions first, each contiguous: [build_filters][sieve][join]
-    uint32_t max_build_rows = 0;
-    uint64_t max_hist = 1;
+    uint32_t max_build_rows[sj_plan_s::kSets] = {}, max_rows[sj_plan_s::kSets] = {};
+    uint64_t max_hist[sj_plan_s::kSets] = {1, 1, 1, 1};
     for (int ph = 0; ph < 2; ++ph) {
         p->zero[ph].begin = L.top;
         if (ph == 0) p->off_elig = L.take(sizeof(uint32_t) * SJ_MAX_RELS);
         for (auto &s : p->steps) {
             if (s.phase != ph) continue;
             s.max_rows = p->rels[s.rel].nrows;
+            max_rows[s.branch] = std::max(max_rows[s.branch], s.max_rows);
             s.off_count = L.take(4);
             s.off_bstatus.clear();
             s.off_bcounter.clear();
@@ -478,8 +512,8 @@ static void build_layout(sj_plan_t *p) {
                 const uint64_t nreg = region_count_cap(nbm, p->region_blocks);
                 // tiles of any input of up to max_rows keys (build_tile_of keeps them <= kBuildMaxTiles)
                 const uint64_t hl = nreg * std::min<uint32_t>(kBuildMaxTiles, tiles_of(s.max_rows, kBuildTileMin));
-                max_hist = std::max<uint64_t>(max_hist, hl);
-                max_build_rows = std::max(max_build_rows, s.max_rows);
+                max_hist[s.branch] = std::max<uint64_t>(max_hist[s.branch], hl);
+                max_build_rows[s.branch] = std::max(max_build_rows[s.branch], s.max_rows);
                 s.off_bstatus.push_back(L.take(8ull * std::max<uint64_t>(1, (hl + kScanTile - 1) / kScanTile)));
                 s.off_bcounter.push_back(L.take(4));
                 s.off_btotal.push_back(L.take(4));
@@ -488,13 +522,14 @@ static void build_layout(sj_plan_t *p) {
         p->zero[ph].end = L.top;
     }
     for (auto &f : p->filters) f.off = L.take(f.max_words * 4);
-    uint32_t max_rows = 1;
-    for (const Rel &R : p->rels) max_rows = std::max(max_rows, R.nrows);
-    p->off_sbits = L.take(max_rows / 8 + 16);
-    p->off_scounts = L.take(4ull * kProbeGrid);
-    p->off_bhist = L.take(4 * max_hist);
-    p->off_stage[0] = L.take(4ull * std::max<uint32_t>(1, max_build_rows));
-    p->off_keep = L.take(8ull * ((uint64_t(max_build_rows) + 2 * build_tile_of(max_build_rows)) / 64 + 1));
+    for (int b = 0; b < sj_plan_s::kSets; ++b) {
+        const uint32_t br = std::max<uint32_t>(1, max_build_rows[b]);
+        p->off_sbits[b] = L.take(max_rows[b] / 8 + 16);
+        p->off_scounts[b] = L.take(4ull * kProbeGrid);
+        p->off_bhist[b] = L.take(4 * max_hist[b]);
+        p->off_stage[b] = L.take(4ull * br);
+        p->off_keep[b] = L.take(8ull * ((uint64_t(br) + 2 * build_tile_of(br)) / 64 + 1));
+    }
     p->zero[2].begin = L.top;
     p->off_totals = L.take(16);
     p->jr.assign(n, {});
@@ -698,6 +733,7 @@ extern "C" sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, con
         delete p;
         return st;
     }
+    schedule_levels(p);
     p->L = p->preorder.back();
     p->cyclic = !p->closing.empty();
     if (p->closing.size() > static_cast<size_t>(kMaxClose) || (p->cyclic && nrels > 8)) p->cyc_ok = false;
@@ -809,10 +845,9 @@ struct ProfScope {
 
 static std::string rel_name(int r) { return "R" + std::to_string(r); }
 
-static sj_status run_steps(sj_plan_t *p, int phase) {
-    hipStream_t s = p->ls;
-    for (auto &st : p->steps) {
-        if (st.phase != phase) continue;
+static sj_status run_step(sj_plan_t *p, StepSpec &st, hipStream_t s) {
+    const int set = st.branch;
+    {
         const Rel &R = p->rels[st.rel];
         StepArgs a{};
         a.ncol = static_cast<int>(R.jcols.size());
@@ -848,8 +883,8 @@ static sj_status run_steps(sj_plan_t *p, int phase) {
         for (auto &pr : st.probes)
             a.lds_words = std::max<uint32_t>(a.lds_words, static_cast<uint32_t>(std::min<uint64_t>(
                                                                p->filters[pr.second].max_words, kLdsFilterBytes / 4)));
-        a.bits = at<uint8_t>(p, p->off_sbits);
-        a.counts = at<uint32_t>(p, p->off_scounts);
+        a.bits = at<uint8_t>(p, p->off_sbits[set]);
+        a.counts = at<uint32_t>(p, p->off_scounts[set]);
         a.seed = p->seed32;
         a.k = static_cast<int>(p->opts.k);
         a.logB = p->logB;
@@ -889,9 +924,9 @@ static sj_status run_steps(sj_plan_t *p, int phase) {
             ba.bits_per_key = p->opts.bits_per_key;
             ba.nblocks_max = static_cast<uint32_t>(p->filters[f].max_words / (p->opts.block_bits / 32));
             ba.region_blocks = p->region_blocks;
-            ba.hist = at<uint32_t>(p, p->off_bhist);
-            ba.stage = at<uint32_t>(p, p->off_stage[0]);
-            ba.keep = at<uint64_t>(p, p->off_keep);
+            ba.hist = at<uint32_t>(p, p->off_bhist[set]);
+            ba.stage = at<uint32_t>(p, p->off_stage[set]);
+            ba.keep = at<uint64_t>(p, p->off_keep[set]);
             ba.total_dev = at<uint32_t>(p, st.off_btotal[b]);
             ba.lb.status = at<uint64_t>(p, st.off_bstatus[b]);
             ba.lb.counter = at<uint32_t>(p, st.off_bcounter[b]);
@@ -905,6 +940,24 @@ static sj_status run_steps(sj_plan_t *p, int phase) {
                 SJ_HIP(p->ctx, launch_filter_build_stage(ba, stg, s));
             }
         }
+    }
+    return SJ_OK;
+}
+
+static sj_status fork_streams(sj_plan_t *p, int n, hipStream_t *out);
+static sj_status join_streams(sj_plan_t *p, int n);
+
+// A phase's steps level by level; the steps of one level on branches of their own.
+static sj_status run_steps(sj_plan_t *p, int phase) {
+    for (const auto &lv : p->level_steps[phase]) {
+        const int nb = static_cast<int>(std::min<size_t>(lv.size(), sj_plan_s::kSets));
+        hipStream_t br[sj_plan_s::kSets];
+        if (sj_status st = fork_streams(p, nb, br)) return st;
+        for (int si : lv) {
+            StepSpec &st = p->steps[si];
+            if (sj_status e = run_step(p, st, br[st.branch])) return e;
+        }
+        if (sj_status st = join_streams(p, nb)) return st;
     }
     return SJ_OK;
 }
@@ -1000,13 +1053,20 @@ static sj_status enqueue_build(sj_plan_t *p) {
     hipStream_t s = p->ls;
     if (sj_status st = zero_region(p, 0)) return st;
     uint32_t *elig = at<uint32_t>(p, p->off_elig);
-    for (int i = 0; i < p->n; ++i) {
+    std::vector<int> withpred;
+    for (int i = 0; i < p->n; ++i)
+        if (p->rels[i].pred_col >= 0) withpred.push_back(i);
+    const int nb = static_cast<int>(std::min<size_t>(withpred.size(), sj_plan_s::kSets));
+    hipStream_t br[sj_plan_s::kSets];
+    if (sj_status st = fork_streams(p, nb, br)) return st;
+    for (size_t k = 0; k < withpred.size(); ++k) {
+        const int i = withpred[k];
         const Rel &R = p->rels[i];
-        if (R.pred_col >= 0) {
-            ProfScope ps(p, std::string("count_pred:") + rel_name(i));
-            SJ_HIP(p->ctx, launch_count_pred(R.cols[R.pred_col], R.nrows, R.lo, R.hi, elig + i, s));
-        }
+        ProfScope ps(p, std::string("count_pred:") + rel_name(i));
+        SJ_HIP(p->ctx, launch_count_pred(R.cols[R.pred_col], R.nrows, R.lo, R.hi, elig + i,
+                                         nb ? br[k % sj_plan_s::kSets] : s));
     }
+    if (sj_status st = join_streams(p, nb)) return st;
     return run_steps(p, 0);
 }
 
