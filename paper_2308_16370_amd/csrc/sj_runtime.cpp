@@ -70,6 +70,8 @@ struct StepSpec {
     std::vector<uint64_t> off_bstatus, off_bcounter, off_btotal;   // per build
     int level = 0;             // steps of one phase and level are independent of each other
     int branch = 0;            // its branch stream and scratch set inside the level
+    bool alone = false;        // the only step of its level: its builds take a branch each
+    int build_set(size_t b) const { return alone ? static_cast<int>(b % 4) : branch; }
 };
 
 struct Region {
@@ -486,6 +488,8 @@ static void schedule_levels(sj_plan_t *p) {
             st.branch = static_cast<int>(lv.size()) % sj_plan_s::kSets;
             lv.push_back(static_cast<int>(si));
         }
+        for (auto &lv : p->level_steps[ph])
+            for (int si : lv) p->steps[si].alone = lv.size() == 1;
     }
 }
 
@@ -506,14 +510,16 @@ static void build_layout(sj_plan_t *p) {
             s.off_bstatus.clear();
             s.off_bcounter.clear();
             s.off_btotal.clear();
-            for (auto &b : s.builds) {
+            for (size_t bi = 0; bi < s.builds.size(); ++bi) {
+                const auto &b = s.builds[bi];
+                const int set = s.build_set(bi);
                 const Filter &f = p->filters[b.second];
                 const uint64_t nbm = f.max_words / (p->opts.block_bits / 32);
                 const uint64_t nreg = region_count_cap(nbm, p->region_blocks);
                 // tiles of any input of up to max_rows keys (build_tile_of keeps them <= kBuildMaxTiles)
                 const uint64_t hl = nreg * std::min<uint32_t>(kBuildMaxTiles, tiles_of(s.max_rows, kBuildTileMin));
-                max_hist[s.branch] = std::max<uint64_t>(max_hist[s.branch], hl);
-                max_build_rows[s.branch] = std::max(max_build_rows[s.branch], s.max_rows);
+                max_hist[set] = std::max<uint64_t>(max_hist[set], hl);
+                max_build_rows[set] = std::max(max_build_rows[set], s.max_rows);
                 s.off_bstatus.push_back(L.take(8ull * std::max<uint64_t>(1, (hl + kScanTile - 1) / kScanTile)));
                 s.off_bcounter.push_back(L.take(4));
                 s.off_btotal.push_back(L.take(4));
@@ -845,6 +851,9 @@ struct ProfScope {
 
 static std::string rel_name(int r) { return "R" + std::to_string(r); }
 
+static sj_status fork_streams(sj_plan_t *p, int n, hipStream_t *out);
+static sj_status join_streams(sj_plan_t *p, int n);
+
 static sj_status run_step(sj_plan_t *p, StepSpec &st, hipStream_t s) {
     const int set = st.branch;
     {
@@ -899,10 +908,19 @@ static sj_status run_step(sj_plan_t *p, StepSpec &st, hipStream_t s) {
             ProfScope ps(p, "compact:" + tag, si, kProfCompact);
             SJ_HIP(p->ctx, launch_sieve_compact(a, st.max_rows, s));
         }
+        // a step alone in its level builds its filters side by side, one branch and scratch set each
+        int nbuild = 0;
+        for (auto &bl : st.builds) nbuild += p->filters[bl.second].resident() ? 0 : 1;
+        // (build b uses set b % kSets, as the layout sized them, whether or not others are reused)
+        const int nfork = (st.alone && nbuild > 1) ? static_cast<int>(std::min<size_t>(st.builds.size(), sj_plan_s::kSets)) : 0;
+        hipStream_t bs[sj_plan_s::kSets];
+        if (sj_status e = fork_streams(p, nfork, bs)) return e;
         for (size_t b = 0; b < st.builds.size(); ++b) {
             const int f = st.builds[b].second;
             const int jc = st.builds[b].first;
             if (p->filters[f].resident()) continue;   // reused from the filter catalogue
+            const int bset = st.build_set(b);
+            const hipStream_t bstream = nfork > 1 ? bs[bset] : s;
             BuildArgs ba{};
             if (st.out >= 0) {          // the step's survivors
                 ba.keys = a.out_col[jc];
@@ -924,9 +942,9 @@ static sj_status run_step(sj_plan_t *p, StepSpec &st, hipStream_t s) {
             ba.bits_per_key = p->opts.bits_per_key;
             ba.nblocks_max = static_cast<uint32_t>(p->filters[f].max_words / (p->opts.block_bits / 32));
             ba.region_blocks = p->region_blocks;
-            ba.hist = at<uint32_t>(p, p->off_bhist[set]);
-            ba.stage = at<uint32_t>(p, p->off_stage[set]);
-            ba.keep = at<uint64_t>(p, p->off_keep[set]);
+            ba.hist = at<uint32_t>(p, p->off_bhist[bset]);
+            ba.stage = at<uint32_t>(p, p->off_stage[bset]);
+            ba.keep = at<uint64_t>(p, p->off_keep[bset]);
             ba.total_dev = at<uint32_t>(p, st.off_btotal[b]);
             ba.lb.status = at<uint64_t>(p, st.off_bstatus[b]);
             ba.lb.counter = at<uint32_t>(p, st.off_bcounter[b]);
@@ -937,15 +955,14 @@ static sj_status run_step(sj_plan_t *p, StepSpec &st, hipStream_t s) {
             for (int stg = 0; stg < kBuildStages; ++stg) {
                 ProfScope ps(p, std::string(stage_name[stg]) + ":" + tag + ":f" + std::to_string(f), si,
                              kProfBuild0 + kBuildStages * static_cast<int>(b) + stg);
-                SJ_HIP(p->ctx, launch_filter_build_stage(ba, stg, s));
+                SJ_HIP(p->ctx, launch_filter_build_stage(ba, stg, bstream));
             }
         }
+        if (sj_status e = join_streams(p, nfork)) return e;
     }
     return SJ_OK;
 }
 
-static sj_status fork_streams(sj_plan_t *p, int n, hipStream_t *out);
-static sj_status join_streams(sj_plan_t *p, int n);
 
 // A phase's steps level by level; the steps of one level on branches of their own.
 static sj_status run_steps(sj_plan_t *p, int phase) {
