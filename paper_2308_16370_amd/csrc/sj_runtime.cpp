@@ -127,8 +127,8 @@ struct sj_plan_s {
         uint32_t slot_cap = 0;
         uint64_t ghist = 0, lb_hist[kRadixPasses] = {}, lb_hist_ctr[kRadixPasses] = {};
         uint64_t lb_dir = 0, lb_dir_ctr = 0;
-        // radix-sort scratch of its own (relations are bucketed concurrently)
-        uint64_t sklo[2] = {0, 0}, skhi[2] = {0, 0}, svals[2] = {0, 0}, shist = 0, sctl = 0;
+        // radix-sort and DP scan scratch of its own (relations are bucketed and weighed concurrently)
+        uint64_t sklo[2] = {0, 0}, skhi[2] = {0, 0}, svals[2] = {0, 0}, shist = 0, sctl = 0, tsums = 0;
     };
     std::vector<JoinRel> jr;
     uint64_t off_tile_sums = 0;
@@ -183,6 +183,7 @@ struct sj_plan_s {
     static constexpr int kBranches = 4;
     hipStream_t branch[kBranches] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t fork_ev = nullptr, join_ev[kBranches] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t dp_ev[SJ_MAX_RELS] = {};  // a relation's DP weights are complete
     static_assert(kBranches == kSets, "one scratch set per branch");
     // asynchronous count / result (sj_join_async, sj_result_async, sj_join_wait)
     bool count_on_host = false;          // p->count / p->checksum hold the last count pass
@@ -222,6 +223,8 @@ sj_plan_s::~sj_plan_s() {
     for (auto &b : branch)
         if (b) (void)hipStreamDestroy(b);
     for (auto &e : join_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : dp_ev)
         if (e) (void)hipEventDestroy(e);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
     for (auto &r : prof_pending) {
@@ -592,6 +595,7 @@ static void build_layout(sj_plan_t *p) {
         }
         r.shist = L.take(4ull * kRadixBins * std::max<uint32_t>(1, tiles_of(static_cast<uint32_t>(cap), kRadixTile)));
         r.sctl = L.take(4 * 32);
+        r.tsums = L.take(16ull * std::max<uint32_t>(1, tiles_of(static_cast<uint32_t>(cap), kScanTile)));
     }
     p->off_tile_sums = L.take(16ull * std::max<uint32_t>(1, tiles_of(maxcap, kScanTile)));
     const uint64_t rc = p->rels[p->root].nrows;
@@ -1002,6 +1006,7 @@ static sj_status ensure_branches(sj_plan_t *p) {
     if (p->profile || p->fork_ev) return SJ_OK;
     for (auto &b : p->branch) SJ_HIP(p->ctx, hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
     for (auto &e : p->join_ev) SJ_HIP(p->ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto &e : p->dp_ev) SJ_HIP(p->ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     SJ_HIP(p->ctx, hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
     return SJ_OK;
 }
@@ -1260,8 +1265,9 @@ static Lookback dir_lookback(sj_plan_t *p, int j) {
 static sj_status enqueue_join(sj_plan_t *p) {
     hipStream_t s = p->ls;
     if (sj_status st = zero_region(p, 2)) return st;
-    // every non-root relation is bucketed on a branch of its own; the DP then runs
-    // bottom-up on the launch stream
+    // every non-root relation is bucketed on a branch of its own, and its DP weights follow
+    // there once its children's are complete (an event per relation); the root's DP runs
+    // on the launch stream after the branches join
     std::vector<int> inner;
     for (int j : p->postorder)
         if (j != p->root) inner.push_back(j);
@@ -1282,8 +1288,16 @@ static sj_status enqueue_join(sj_plan_t *p) {
         SJ_HIP(p->ctx, launch_build_buckets(list_rid(p, j, fl), lcols.data(), ncol, lcount, b.key_jcol, sec, b,
                                             sort_scratch(p, j), dir_lookback(p, j), br[i]));
     }
-    if (sj_status st = join_streams(p, static_cast<int>(inner.size()))) return st;
+    const bool use_ev = !p->profile && inner.size() > 1;
+    std::vector<hipStream_t> strm(p->n, s);
+    for (size_t i = 0; i < inner.size(); ++i) strm[inner[i]] = br[i];
     for (int j : p->postorder) {
+        if (j == p->root) {
+            if (sj_status st = join_streams(p, static_cast<int>(inner.size()))) return st;
+        } else if (use_ev) {
+            for (int ch : p->children[j])
+                if (strm[ch] != strm[j]) SJ_HIP(p->ctx, hipStreamWaitEvent(strm[j], p->dp_ev[ch], 0));
+        }
         const int fl = p->final_list[j];
         const Rel &R = p->rels[j];
         const int ncol = static_cast<int>(R.jcols.size());
@@ -1302,7 +1316,7 @@ static sj_status enqueue_join(sj_plan_t *p) {
             d.bhi[c] = at<uint32_t>(p, p->off_bhi[j][c]);
             if (p->cyclic && ch == p->L) d.skip_mask |= 1u << c;
         }
-        d.tile_sums = at<uint64_t>(p, p->off_tile_sums);
+        d.tile_sums = at<uint64_t>(p, j == p->root ? p->off_tile_sums : p->jr[j].tsums);
         if (j != p->root) {
             const Buckets b = buckets_of(p, j);
             d.n = b.n;
@@ -1321,8 +1335,11 @@ static sj_status enqueue_join(sj_plan_t *p) {
             d.cv = at<uint64_t>(p, p->off_root_cv);
             d.totals = at<uint64_t>(p, p->off_totals);
         }
-        ProfScope ps(p, std::string("dp:") + rel_name(j));
-        SJ_HIP(p->ctx, launch_dp(d, s));
+        {
+            ProfScope ps(p, std::string("dp:") + rel_name(j));
+            SJ_HIP(p->ctx, launch_dp(d, strm[j]));
+        }
+        if (use_ev && j != p->root) SJ_HIP(p->ctx, hipEventRecord(p->dp_ev[j], strm[j]));
     }
     return SJ_OK;
 }
