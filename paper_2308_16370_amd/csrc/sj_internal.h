@@ -258,6 +258,9 @@ struct PairHash {
     uint64_t *msum;            // [cap + 1]
     uint32_t cap;              // power of two, >= 2 * rows + 1
     uint32_t *mask;            // device-side mask used (sized from the entry count)
+    // membership bitmap in front of the table: 4 bits per slot in use (>= 8 per pair),
+    // one bit per pair; a clear bit answers "absent" without touching the table
+    uint32_t *sig;             // [cap / 8] words
 };
 // Fill `h` from n_dev entries: pair (ca[e], cb[e]), checksum factor of (rel, rid[e]).
 hipError_t launch_pair_build(const PairHash &h, const uint32_t *n_dev, uint32_t cap_rows, const uint32_t *rid,

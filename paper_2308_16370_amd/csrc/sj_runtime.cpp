@@ -147,6 +147,7 @@ struct sj_plan_s {
     uint64_t off_tri_w = 0, off_tri_beg = 0, off_tri_off = 0, off_tri_tiles = 0, off_tri_part = 0;
     uint64_t pair_cap[2] = {0, 0};           // P's and L's pair hashes
     uint64_t off_pair_keys[2] = {0, 0}, off_pair_cnt[2] = {0, 0}, off_pair_msum[2] = {0, 0}, off_pair_mask[2] = {0, 0};
+    uint64_t off_pair_sig[2] = {0, 0};
     int state = kPlanned;
     uint64_t count = 0, checksum = 0;
     // event profiling (SJ_FLAG_PROFILE): one event pair per launch group
@@ -628,6 +629,7 @@ static void build_layout(sj_plan_t *p) {
             p->off_pair_cnt[h] = L.take(4 * (cap + 1));
             p->off_pair_msum[h] = L.take(8 * (cap + 1));
             p->off_pair_mask[h] = L.take(4);
+            p->off_pair_sig[h] = L.take(4 * (cap / 8));
         }
     }
     p->ws_bytes = L.top;
@@ -1351,6 +1353,7 @@ static PairHash pair_hash_of(sj_plan_t *p, int h) {
     ph.msum = at<uint64_t>(p, p->off_pair_msum[h]);
     ph.cap = static_cast<uint32_t>(p->pair_cap[h]);
     ph.mask = at<uint32_t>(p, p->off_pair_mask[h]);
+    ph.sig = at<uint32_t>(p, p->off_pair_sig[h]);
     return ph;
 }
 

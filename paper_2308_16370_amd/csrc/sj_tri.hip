@@ -31,17 +31,24 @@ __device__ __forceinline__ uint64_t pair_key(int32_t a, int32_t b) {
     return (static_cast<uint64_t>(static_cast<uint32_t>(a)) << 32) | static_cast<uint32_t>(b);
 }
 
-__device__ __forceinline__ uint32_t pair_hash(uint64_t key) {
-    return static_cast<uint32_t>(mix64(key ^ 0x243F6A8885A308D3ull) >> 32);
+// One 64-bit mix of the pair: the high word picks the table slot, the low word the
+// membership bit (4 bits per slot in use).
+__device__ __forceinline__ uint64_t pair_mix(uint64_t key) { return mix64(key ^ 0x243F6A8885A308D3ull); }
+__device__ __forceinline__ uint32_t pair_slot(uint64_t hm, uint32_t mask) { return static_cast<uint32_t>(hm >> 32) & mask; }
+__device__ __forceinline__ uint32_t pair_bit(uint64_t hm, uint32_t mask) {
+    return static_cast<uint32_t>(hm) & (4u * mask + 3u);
 }
 
 __device__ __forceinline__ bool pair_find(const PairHash &h, uint32_t mask, uint64_t key, uint32_t &c,
                                           uint64_t &ms) {
+    const uint64_t hm = pair_mix(key);
+    const uint32_t b = pair_bit(hm, mask);
+    if (!((h.sig[b >> 5] >> (b & 31u)) & 1u)) return false;   // absent: the table is not read
     uint32_t s;
     if (key == kPairEmpty) {
         s = h.cap;
     } else {
-        s = pair_hash(key) & mask;
+        s = pair_slot(hm, mask);
         while (true) {   // the table is at most half full: an empty slot ends every probe
             const uint64_t k = h.keys[s];
             if (k == key) break;
@@ -70,6 +77,7 @@ __global__ void k_pair_clear(PairHash h) {
         h.keys[i] = kPairEmpty;
         h.cnt[i] = 0;
         h.msum[i] = 0;
+        if (i < lim / 8u) h.sig[i] = 0;   // 4 bits per slot: lim / 8 words
     }
     if (t == 0) {
         h.keys[h.cap] = kPairEmpty;
@@ -106,11 +114,14 @@ __global__ __launch_bounds__(256) void k_pair_insert(PairHash h, const uint32_t 
         if (!tail) continue;
         const uint32_t c = static_cast<uint32_t>(lane - start + 1);
         const uint64_t ms = pre - (start > 0 ? before : 0);
+        const uint64_t hm = pair_mix(key);
+        const uint32_t b = pair_bit(hm, mask);
+        if (!((h.sig[b >> 5] >> (b & 31u)) & 1u)) atomicOr(h.sig + (b >> 5), 1u << (b & 31u));
         uint32_t s;
         if (key == kPairEmpty) {
             s = h.cap;
         } else {
-            s = pair_hash(key) & mask;
+            s = pair_slot(hm, mask);
             while (true) {
                 const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long *>(h.keys + s),
                                                          static_cast<unsigned long long>(kPairEmpty),
