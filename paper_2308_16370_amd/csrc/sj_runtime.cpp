@@ -184,7 +184,6 @@ struct sj_plan_s {
     static constexpr int kBranches = 4;
     hipStream_t branch[kBranches] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t fork_ev = nullptr, join_ev[kBranches] = {nullptr, nullptr, nullptr, nullptr};
-    hipEvent_t dp_ev[SJ_MAX_RELS] = {};  // a relation's DP weights are complete
     static_assert(kBranches == kSets, "one scratch set per branch");
     // asynchronous count / result (sj_join_async, sj_result_async, sj_join_wait)
     bool count_on_host = false;          // p->count / p->checksum hold the last count pass
@@ -224,8 +223,6 @@ sj_plan_s::~sj_plan_s() {
     for (auto &b : branch)
         if (b) (void)hipStreamDestroy(b);
     for (auto &e : join_ev)
-        if (e) (void)hipEventDestroy(e);
-    for (auto &e : dp_ev)
         if (e) (void)hipEventDestroy(e);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
     for (auto &r : prof_pending) {
@@ -1008,7 +1005,6 @@ static sj_status ensure_branches(sj_plan_t *p) {
     if (p->profile || p->fork_ev) return SJ_OK;
     for (auto &b : p->branch) SJ_HIP(p->ctx, hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
     for (auto &e : p->join_ev) SJ_HIP(p->ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    for (auto &e : p->dp_ev) SJ_HIP(p->ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     SJ_HIP(p->ctx, hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
     return SJ_OK;
 }
@@ -1267,9 +1263,8 @@ static Lookback dir_lookback(sj_plan_t *p, int j) {
 static sj_status enqueue_join(sj_plan_t *p) {
     hipStream_t s = p->ls;
     if (sj_status st = zero_region(p, 2)) return st;
-    // every non-root relation is bucketed on a branch of its own, and its DP weights follow
-    // there once its children's are complete (an event per relation); the root's DP runs
-    // on the launch stream after the branches join
+    // every non-root relation is bucketed on a branch of its own; after the branches join,
+    // the DP runs bottom-up on the launch stream
     std::vector<int> inner;
     for (int j : p->postorder)
         if (j != p->root) inner.push_back(j);
@@ -1290,16 +1285,8 @@ static sj_status enqueue_join(sj_plan_t *p) {
         SJ_HIP(p->ctx, launch_build_buckets(list_rid(p, j, fl), lcols.data(), ncol, lcount, b.key_jcol, sec, b,
                                             sort_scratch(p, j), dir_lookback(p, j), br[i]));
     }
-    const bool use_ev = !p->profile && inner.size() > 1;
-    std::vector<hipStream_t> strm(p->n, s);
-    for (size_t i = 0; i < inner.size(); ++i) strm[inner[i]] = br[i];
+    if (sj_status st = join_streams(p, static_cast<int>(inner.size()))) return st;
     for (int j : p->postorder) {
-        if (j == p->root) {
-            if (sj_status st = join_streams(p, static_cast<int>(inner.size()))) return st;
-        } else if (use_ev) {
-            for (int ch : p->children[j])
-                if (strm[ch] != strm[j]) SJ_HIP(p->ctx, hipStreamWaitEvent(strm[j], p->dp_ev[ch], 0));
-        }
         const int fl = p->final_list[j];
         const Rel &R = p->rels[j];
         const int ncol = static_cast<int>(R.jcols.size());
@@ -1337,11 +1324,8 @@ static sj_status enqueue_join(sj_plan_t *p) {
             d.cv = at<uint64_t>(p, p->off_root_cv);
             d.totals = at<uint64_t>(p, p->off_totals);
         }
-        {
-            ProfScope ps(p, std::string("dp:") + rel_name(j));
-            SJ_HIP(p->ctx, launch_dp(d, strm[j]));
-        }
-        if (use_ev && j != p->root) SJ_HIP(p->ctx, hipEventRecord(p->dp_ev[j], strm[j]));
+        ProfScope ps(p, std::string("dp:") + rel_name(j));
+        SJ_HIP(p->ctx, launch_dp(d, s));
     }
     return SJ_OK;
 }
