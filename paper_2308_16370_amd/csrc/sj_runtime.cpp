@@ -1000,9 +1000,12 @@ static sj_status check_exec(sj_plan_t *p, int need) {
 }
 
 
-// Branch streams and their events, created outside any capture.
+// Branch streams and their events, created outside any capture. Only recorded graphs
+// fork: an eager plan (one-shot queries, profiling) keeps every launch on one stream,
+// where stream creation and the extra event calls would cost more host time than
+// the overlap saves.
 static sj_status ensure_branches(sj_plan_t *p) {
-    if (p->profile || p->fork_ev) return SJ_OK;
+    if (p->eager || p->fork_ev) return SJ_OK;
     for (auto &b : p->branch) SJ_HIP(p->ctx, hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
     for (auto &e : p->join_ev) SJ_HIP(p->ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     SJ_HIP(p->ctx, hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
@@ -1010,10 +1013,10 @@ static sj_status ensure_branches(sj_plan_t *p) {
 }
 
 // Fork: branch i (of n) gets out[i], which starts after everything enqueued on the
-// launch stream so far. Profiled plans keep every launch on the launch stream, so that
-// each group's events time it alone.
+// launch stream so far. Eager plans (profiled ones among them, so that each group's
+// events time it alone) keep every launch on the launch stream.
 static sj_status fork_streams(sj_plan_t *p, int n, hipStream_t *out) {
-    if (p->profile || n <= 1) {
+    if (p->eager || n <= 1) {
         for (int i = 0; i < n; ++i) out[i] = p->ls;
         return SJ_OK;
     }
@@ -1028,7 +1031,7 @@ static sj_status fork_streams(sj_plan_t *p, int n, hipStream_t *out) {
 
 // Join: the launch stream continues after every branch of the last fork of n.
 static sj_status join_streams(sj_plan_t *p, int n) {
-    if (p->profile || n <= 1) return SJ_OK;
+    if (p->eager || n <= 1) return SJ_OK;
     for (int i = 0; i < n && i < sj_plan_s::kBranches; ++i) {
         SJ_HIP(p->ctx, hipEventRecord(p->join_ev[i], p->branch[i]));
         SJ_HIP(p->ctx, hipStreamWaitEvent(p->ls, p->join_ev[i], 0));
