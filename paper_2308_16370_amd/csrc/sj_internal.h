@@ -252,10 +252,17 @@ hipError_t launch_cyclic_write(const CycArgs &a, hipStream_t s);
 // A pair hash maps a relation's (key, key) pair to its row count and the sum of its
 // rows' checksum factors. One slot past the table (index `cap`) holds the pair whose
 // 64-bit key equals the empty marker.
+// One 16-byte slot: the pair (a << 32 | b), how many rows hold it, and the first of them,
+// so a lookup reads one slot; the factor sum is read only for a pair held by several rows.
+struct alignas(16) PairSlot {
+    uint64_t key;
+    uint32_t cnt;
+    uint32_t rid;
+};
 struct PairHash {
-    uint64_t *keys;            // [cap + 1]
-    uint32_t *cnt;             // [cap + 1]
-    uint64_t *msum;            // [cap + 1]
+    PairSlot *slot;            // [cap + 1]
+    uint64_t *msum;            // [cap + 1] sum of the rows' checksum factors
+    uint32_t rel;              // relation the rows belong to (their checksum factors)
     uint32_t cap;              // power of two, >= 2 * rows + 1
     uint32_t *mask;            // device-side mask used (sized from the entry count)
     // membership bitmap in front of the table: 4 bits per slot in use (>= 8 per pair),

@@ -146,7 +146,7 @@ struct sj_plan_s {
     int tri_P = -1;
     uint64_t off_tri_w = 0, off_tri_beg = 0, off_tri_off = 0, off_tri_tiles = 0, off_tri_part = 0;
     uint64_t pair_cap[2] = {0, 0};           // P's and L's pair hashes
-    uint64_t off_pair_keys[2] = {0, 0}, off_pair_cnt[2] = {0, 0}, off_pair_msum[2] = {0, 0}, off_pair_mask[2] = {0, 0};
+    uint64_t off_pair_slot[2] = {0, 0}, off_pair_msum[2] = {0, 0}, off_pair_mask[2] = {0, 0};
     uint64_t off_pair_sig[2] = {0, 0};
     int state = kPlanned;
     uint64_t count = 0, checksum = 0;
@@ -622,8 +622,7 @@ static void build_layout(sj_plan_t *p) {
             uint64_t cap = 16;
             while (cap < 2ull * p->rels[rel[h]].nrows + 1) cap <<= 1;
             p->pair_cap[h] = cap;
-            p->off_pair_keys[h] = L.take(8 * (cap + 1));
-            p->off_pair_cnt[h] = L.take(4 * (cap + 1));
+            p->off_pair_slot[h] = L.take(16 * (cap + 1));
             p->off_pair_msum[h] = L.take(8 * (cap + 1));
             p->off_pair_mask[h] = L.take(4);
             p->off_pair_sig[h] = L.take(4 * (cap / 8));
@@ -1335,8 +1334,8 @@ static sj_status enqueue_join(sj_plan_t *p) {
 
 static PairHash pair_hash_of(sj_plan_t *p, int h) {
     PairHash ph{};
-    ph.keys = at<uint64_t>(p, p->off_pair_keys[h]);
-    ph.cnt = at<uint32_t>(p, p->off_pair_cnt[h]);
+    ph.slot = at<PairSlot>(p, p->off_pair_slot[h]);
+    ph.rel = static_cast<uint32_t>(h == 0 ? p->tri_P : p->L);
     ph.msum = at<uint64_t>(p, p->off_pair_msum[h]);
     ph.cap = static_cast<uint32_t>(p->pair_cap[h]);
     ph.mask = at<uint32_t>(p, p->off_pair_mask[h]);

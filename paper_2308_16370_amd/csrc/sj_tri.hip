@@ -11,9 +11,10 @@
 // (r, p) and then searches L; on power-law edge lists the wedges outnumber the walk
 // steps by two orders of magnitude.
 //
-// Balance: walk lengths per root entry are scanned, and each thread takes equal
-// chunks of consecutive walk steps (finding its entry by binary search over the
-// prefix), so a hub's long walk is split over many threads.
+// Balance: walk lengths per root entry are scanned, and each wave takes equal chunks
+// of consecutive walk steps, lane j every 64th step from the j-th (each lane finds its
+// entry by binary search over the prefix, then gallops forward), so a hub's long walk
+// is split over many waves and the group members a wave reads are consecutive.
 #include <hip/hip_runtime.h>
 
 #include "sj_device.h"
@@ -24,7 +25,6 @@ namespace sj {
 namespace {
 
 constexpr uint64_t kPairEmpty = ~0ull;
-constexpr int kTriChunk = 32;        // walk steps per thread-chunk
 constexpr int kTriThreads = 256;
 
 __device__ __forceinline__ uint64_t pair_key(int32_t a, int32_t b) {
@@ -44,25 +44,23 @@ __device__ __forceinline__ bool pair_find(const PairHash &h, uint32_t mask, uint
     const uint64_t hm = pair_mix(key);
     const uint32_t b = pair_bit(hm, mask);
     if (!((h.sig[b >> 5] >> (b & 31u)) & 1u)) return false;   // absent: the table is not read
-    uint32_t s;
-    if (key == kPairEmpty) {
-        s = h.cap;
-    } else {
-        s = pair_slot(hm, mask);
-        while (true) {   // the table is at most half full: an empty slot ends every probe
-            const uint64_t k = h.keys[s];
-            if (k == key) break;
-            if (k == kPairEmpty) return false;
-            s = (s + 1) & mask;
-        }
+    uint32_t s = key == kPairEmpty ? h.cap : pair_slot(hm, mask);
+    uint4 v;
+    while (true) {   // the table is at most half full: an empty slot ends every probe
+        v = *reinterpret_cast<const uint4 *>(h.slot + s);
+        const uint64_t k = (static_cast<uint64_t>(v.y) << 32) | v.x;
+        if (k == key) break;
+        if (k == kPairEmpty || s == h.cap) return false;
+        s = (s + 1) & mask;
     }
-    c = h.cnt[s];
+    c = v.z;
     if (c == 0) return false;
-    ms = h.msum[s];
+    ms = c == 1 ? chk_factor(h.rel, v.w) : h.msum[s];
     return true;
 }
 
 __global__ void k_pair_mask(PairHash h, const uint32_t *n_dev) {
+    static_assert(sizeof(PairSlot) == 16, "one 16-byte load per slot");
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const uint32_t n = *n_dev;
     uint32_t c = 16;
@@ -73,15 +71,14 @@ __global__ void k_pair_mask(PairHash h, const uint32_t *n_dev) {
 __global__ void k_pair_clear(PairHash h) {
     const uint32_t lim = *h.mask + 1u;
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const PairSlot empty{kPairEmpty, 0u, 0u};
     for (uint32_t i = t; i < lim; i += gridDim.x * blockDim.x) {
-        h.keys[i] = kPairEmpty;
-        h.cnt[i] = 0;
+        h.slot[i] = empty;
         h.msum[i] = 0;
         if (i < lim / 8u) h.sig[i] = 0;   // 4 bits per slot: lim / 8 words
     }
     if (t == 0) {
-        h.keys[h.cap] = kPairEmpty;
-        h.cnt[h.cap] = 0;
+        h.slot[h.cap] = empty;
         h.msum[h.cap] = 0;
     }
 }
@@ -99,7 +96,8 @@ __global__ __launch_bounds__(256) void k_pair_insert(PairHash h, const uint32_t 
         const uint32_t e = g * 64 + static_cast<uint32_t>(lane);
         const bool ok = e < n;
         const uint64_t key = ok ? pair_key(ca[e], cb[e]) : 0;
-        const uint64_t m = ok ? chk_factor(rel, rid[e]) : 0;
+        const uint32_t my_rid = ok ? rid[e] : 0u;
+        const uint64_t m = ok ? chk_factor(rel, my_rid) : 0;
         const uint64_t prev = __shfl_up(key, 1, 64);
         int start = (lane == 0 || key != prev) ? lane : 0;
 #pragma unroll
@@ -109,6 +107,7 @@ __global__ __launch_bounds__(256) void k_pair_insert(PairHash h, const uint32_t 
         }
         const uint64_t pre = wave_incl_scan(m);
         const uint64_t before = __shfl(pre, start > 0 ? start - 1 : 0, 64);
+        const uint32_t first_rid = __shfl(my_rid, start, 64);
         const uint64_t next = __shfl_down(key, 1, 64);
         const bool tail = ok && (lane == 63 || e + 1 >= n || next != key);
         if (!tail) continue;
@@ -123,14 +122,15 @@ __global__ __launch_bounds__(256) void k_pair_insert(PairHash h, const uint32_t 
         } else {
             s = pair_slot(hm, mask);
             while (true) {
-                const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long *>(h.keys + s),
+                const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long *>(&h.slot[s].key),
                                                          static_cast<unsigned long long>(kPairEmpty),
                                                          static_cast<unsigned long long>(key));
                 if (old == kPairEmpty || old == key) break;
                 s = (s + 1) & mask;
             }
         }
-        atomicAdd(h.cnt + s, c);
+        // the first rows to arrive leave their first row id (read when the pair has one row)
+        if (atomicAdd(&h.slot[s].cnt, c) == 0u) h.slot[s].rid = first_rid;
         atomicAdd(reinterpret_cast<unsigned long long *>(h.msum + s), static_cast<unsigned long long>(ms));
     }
 }
@@ -218,30 +218,40 @@ __global__ __launch_bounds__(kScanBlock) void k_tri_down(TriArgs a) {
     }
 }
 
-// The walk: thread-chunks of kTriChunk consecutive steps over the scanned total.
+// The walk: each wave takes chunks of 64 * kTriIters consecutive steps; lane j takes
+// steps base + 64 * i + j, so the group members a wave reads are consecutive.
+constexpr int kTriIters = 32;
 __global__ __launch_bounds__(kTriThreads) void k_tri_count(TriArgs a) {
     __shared__ uint64_t s_c[kTriThreads / 64], s_k[kTriThreads / 64];
     const uint32_t n = *a.n_root;
     const uint64_t total = a.off[n];
-    const uint64_t nchunks = (total + kTriChunk - 1) / kTriChunk;
+    constexpr uint64_t kWaveSteps = 64ull * kTriIters;
+    const uint64_t nchunks = (total + kWaveSteps - 1) / kWaveSteps;
     const uint32_t pm = *a.HP.mask, lm = *a.HL.mask;
+    const uint32_t lane = static_cast<uint32_t>(lane_id());
     uint64_t cnt = 0, chk = 0;
-    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (uint64_t c = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; c < nchunks; c += stride) {
-        uint64_t w = c * kTriChunk;
-        const uint64_t wend = w + kTriChunk < total ? w + kTriChunk : total;
-        // the entry whose walk holds step w: off[r] <= w < off[r + 1]
+    const uint64_t nwaves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
+    for (uint64_t c = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; c < nchunks; c += nwaves) {
+        uint64_t w = c * kWaveSteps + lane;
+        if (w >= total) continue;
         uint32_t r = upper_bound_u64(a.off, 0, n, w) - 1;
         uint64_t r_lo = a.off[r], r_hi = a.off[r + 1];
+        bool loaded = false;
         bool walk_l = false;
         uint32_t beg = 0;
         int32_t x = 0, y = 0;
         uint64_t m1 = 0;
-        bool loaded = false;
-        for (; w < wend; ++w) {
-            while (w >= r_hi) {   // the next entry with a non-empty walk
-                ++r;
-                r_lo = r_hi;
+        for (int it = 0; it < kTriIters && w < total; ++it, w += 64) {
+            if (w >= r_hi) {
+                // gallop from r + 1 to an entry past w, then search: off[r] <= w < off[r + 1]
+                uint32_t lo = r + 1, step = 1, hi = lo;
+                while (hi < n && a.off[hi + 1] <= w) {
+                    lo = hi + 1;
+                    hi = min(n - 1, hi + step);
+                    step <<= 1;
+                }
+                r = upper_bound_u64(a.off, lo, hi + 1, w) - 1;
+                r_lo = a.off[r];
                 r_hi = a.off[r + 1];
                 loaded = false;
             }
@@ -258,10 +268,10 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_count(TriArgs a) {
             uint32_t hc;
             uint64_t hm, mo;
             bool hit;
-            if (!walk_l) {   // a row p of P's group of x: L rows with (y, z(p))
+            if (!walk_l) {
                 mo = chk_factor(a.rel_P, a.P_rid[e]);
                 hit = pair_find(a.HL, lm, pair_key(y, a.P_z[e]), hc, hm);
-            } else {         // a row l of L's group of y: P rows with (x, z(l))
+            } else {
                 mo = chk_factor(a.rel_L, a.L_rid[e]);
                 hit = pair_find(a.HP, pm, pair_key(x, a.L_z[e]), hc, hm);
             }
