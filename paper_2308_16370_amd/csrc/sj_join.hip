@@ -365,12 +365,14 @@ hipError_t launch_build_buckets(const uint32_t *list_rid, const int32_t *const *
 // The kScanItems entries of a thread go through each lookup stage together, so the
 // loads of a stage are independent and in flight at once (key, hash slot, directory
 // bounds, child prefix weights); a slot that holds another key (rare: the index is at
-// most half full) is resolved by linear probing afterwards.
+// most half full) is resolved by linear probing afterwards. A thread's entries are
+// kScanBlock apart (entry tile * kScanTile + i * kScanBlock + thread), so the loads of
+// one stage are consecutive across a wave; only the tile's total is scanned here.
 __device__ __forceinline__ void dp_entries(const DpArgs &a, const uint32_t *masks, uint32_t base, uint32_t n,
                                            uint64_t *w, uint64_t *v) {
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
-        const uint32_t e = base + i;
+        const uint32_t e = base + i * kScanBlock;
         w[i] = 1;
         v[i] = e < n ? chk_factor(a.rel, a.rid[e]) : 0;
     }
@@ -383,7 +385,7 @@ __device__ __forceinline__ void dp_entries(const DpArgs &a, const uint32_t *mask
             uint32_t sl[kScanItems];
             uint64_t sv[kScanItems];
 #pragma unroll
-            for (int i = 0; i < kScanItems; ++i) key[i] = base + i < n ? col[base + i] : 0;
+            for (int i = 0; i < kScanItems; ++i) key[i] = base + i * kScanBlock < n ? col[base + i * kScanBlock] : 0;
 #pragma unroll
             for (int i = 0; i < kScanItems; ++i) {
                 sl[i] = slot_hash(key[i]) & masks[c];
@@ -402,7 +404,7 @@ __device__ __forceinline__ void dp_entries(const DpArgs &a, const uint32_t *mask
             }
 #pragma unroll
             for (int i = 0; i < kScanItems; ++i) {
-                const uint32_t e = base + i;
+                const uint32_t e = base + i * kScanBlock;
                 if (e < n) {
                     a.blo[c][e] = lo[i];
                     a.bhi[c][e] = hi[i];
@@ -420,7 +422,7 @@ __device__ __forceinline__ void dp_entries(const DpArgs &a, const uint32_t *mask
     }
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i)
-        if (base + i >= n) w[i] = v[i] = 0;
+        if (base + i * kScanBlock >= n) w[i] = v[i] = 0;
 }
 
 // Phase 1: per-entry weights into cw/cv (not yet scanned) and per-tile sums.
@@ -432,15 +434,15 @@ __global__ __launch_bounds__(kScanBlock) void k_dp_reduce(DpArgs a) {
 #pragma unroll
     for (int c = 0; c < kMaxJCols; ++c) masks[c] = c < a.nchild ? *a.child[c].slot_mask : 0u;
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t base = tile * kScanTile + threadIdx.x * kScanItems;
+        const uint32_t base = tile * kScanTile + threadIdx.x;
         uint64_t w[kScanItems], v[kScanItems];
         dp_entries(a, masks, base, n, w, v);
         uint64_t sw = 0, sv = 0;
 #pragma unroll
         for (int i = 0; i < kScanItems; ++i) {
-            if (base + i < n) {
-                a.cw[base + i] = w[i];
-                a.cv[base + i] = v[i];
+            if (base + i * kScanBlock < n) {
+                a.cw[base + i * kScanBlock] = w[i];
+                a.cv[base + i * kScanBlock] = v[i];
             }
             sw += w[i];
             sv += v[i];
