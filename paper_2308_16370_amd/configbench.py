@@ -122,3 +122,23 @@ def triangle(steps: int = 3, warmup: int = 1, scale: float = 1.0, log=print) -> 
                         "count and checksum" % (q.rels[0].nrows, q.meta["nverts"]),
             "input_tuples": q.input_tuples, "ms_per_step": round(dt * 1e3, 3), "tuples_per_s": q.input_tuples / dt,
             "result_tuples": ref[0], "checksum": ref[1], "intersection_walk_ms": round(walk_ms, 3)}
+
+
+def main(argv=None) -> int:
+    """python -m paper_2308_16370_amd.configbench star|triangle [--steps K]: one workload, one JSON line."""
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description="time the star or the triangle workload")
+    ap.add_argument("workload", choices=["star", "triangle"])
+    ap.add_argument("--steps", type=int, default=None)
+    args = ap.parse_args(argv)
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    fn = star if args.workload == "star" else triangle
+    res = fn(log=log) if args.steps is None else fn(steps=args.steps, log=log)
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
