@@ -21,7 +21,7 @@ import sys
 
 
 def _short(name: str) -> str:
-    n = name.replace("void ", "").replace("sj::", "")
+    n = name.replace("void ", "").replace("sj::", "").replace("(anonymous namespace)::", "")
     return n.split("(")[0]
 
 
