@@ -206,6 +206,25 @@ sj_status sj_filter_desc(sj_plan_t *plan, int32_t f, int32_t *kind, int32_t *ind
 /* Device-to-device copy of filter f's words (nblocks * block_bits / 32 uint32)
  * into dst_dev (room for capacity_words). Asynchronous. */
 sj_status sj_filter_copy(sj_plan_t *plan, int32_t f, uint32_t *dst_dev, uint64_t capacity_words);
+/* Inserts into a built filter (Section 2.4: a tuple inserted into a relation changes
+ * the relation's filter only when the filter does not contain its key yet).
+ * sj_filter_probe writes contained_dev[i] = 1 if filter f reports keys_dev[i] present,
+ * else 0 (n bytes, caller-provided); *missing (host, may be NULL) receives how many
+ * were not contained. sj_filter_insert does the same against the filter as it is
+ * before the call and then sets the bits of every key found missing, in place: the
+ * filter keeps its block count (its false-positive rate rises with the keys added) and
+ * from then on contains every inserted key. Those missing keys are the ones whose
+ * tuples may now join and must be propagated to the adjacent relations' filters (a
+ * parent's rows with a matching key can now pass, and their keys go into the parent's
+ * filter the same way). Backward filters can be updated after sj_build_filters,
+ * forward and closing filters after sj_sieve; the next sj_build_filters or sj_sieve
+ * rebuilds a filter from the relations and drops its inserts. A filter held in a
+ * filter catalogue is shared and cannot be inserted into (SJ_ERR_STATE). Both calls
+ * are asynchronous unless missing / inserted is non-NULL. */
+sj_status sj_filter_probe(sj_plan_t *plan, int32_t f, const int32_t *keys_dev, uint64_t n, uint8_t *contained_dev,
+                          uint64_t *missing);
+sj_status sj_filter_insert(sj_plan_t *plan, int32_t f, const int32_t *keys_dev, uint64_t n, uint8_t *contained_dev,
+                           uint64_t *inserted);
 /* Copy relation rel's final survivor row ids (ascending) into dst_dev (room for
  * capacity); *n receives the count. dst_dev may be NULL to query the count only.
  * Waits for the stream. */

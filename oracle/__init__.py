@@ -185,6 +185,17 @@ def bf_probe(words: np.ndarray, keys: np.ndarray, rows: Optional[np.ndarray], nb
     return out.astype(bool)
 
 
+def bf_insert(words: np.ndarray, keys: np.ndarray, nblocks: int, k: int, block_bits: int,
+              seed32: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Insert keys into a built filter (Section 2.4): which keys it contained before
+    (those change nothing), and the filter with every key's pattern bits set (the
+    block count is kept). Setting a contained key's bits again changes nothing, so the
+    new words are the old ones OR the words of a filter of the keys alone."""
+    contained = bf_probe(words, keys, None, nblocks, k, block_bits, seed32)
+    new = np.asarray(words, dtype=np.uint32) | bf_build(keys, None, nblocks, k, block_bits, seed32)
+    return new, contained
+
+
 # ---------------------------------------------------------------- join graph
 
 class JoinTree:

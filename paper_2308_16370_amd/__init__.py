@@ -49,7 +49,7 @@ EXPORTED = ["sj_ctx_create", "sj_ctx_set_stream", "sj_ctx_destroy", "sj_last_err
             "sj_server_query", "sj_server_release", "sj_server_stats", "sj_server_last_error",
             "sj_server_destroy", "sj_fcache_create", "sj_plan_use_filter_cache", "sj_plan_filter_cached",
             "sj_fcache_invalidate", "sj_fcache_clear", "sj_fcache_stats", "sj_fcache_destroy",
-            "sj_server_use_filter_cache"]
+            "sj_server_use_filter_cache", "sj_filter_probe", "sj_filter_insert"]
 SJ_FLAG_PROFILE = 1
 SJ_FLAG_EAGER = 2
 SJ_FLAG_BINARY_CYCLES = 4
@@ -142,6 +142,8 @@ def lib():
             "sj_fcache_stats": [V, P(_FcInfo)],
             "sj_fcache_destroy": [V],
             "sj_server_use_filter_cache": [V, V],
+            "sj_filter_probe": [V, i32, V, u64, V, P(u64)],
+            "sj_filter_insert": [V, i32, V, u64, V, P(u64)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -338,6 +340,23 @@ class Plan:
         out = torch.empty(d["nblocks"] * self.block_bits // 32, dtype=torch.int32, device="cuda:%d" % self.ctx.device)
         self._check(lib().sj_filter_copy(self.handle, f, ctypes.c_void_p(out.data_ptr()), out.numel()))
         return out
+
+    def _filter_update(self, fn, f: int, keys: torch.Tensor):
+        if keys.dtype != torch.int32 or keys.dim() != 1 or not keys.is_contiguous():
+            raise ValueError("keys must be a contiguous 1-D int32 tensor")
+        flags = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+        cnt = ctypes.c_uint64()
+        self._check(fn(self.handle, f, ctypes.c_void_p(keys.data_ptr()), keys.numel(),
+                       ctypes.c_void_p(flags.data_ptr()), ctypes.byref(cnt)))
+        return flags.bool(), int(cnt.value)
+
+    def filter_probe(self, f: int, keys: torch.Tensor):
+        """(contained bool tensor, number of keys filter f does not contain)."""
+        return self._filter_update(lib().sj_filter_probe, f, keys)
+
+    def filter_insert(self, f: int, keys: torch.Tensor):
+        """Insert keys into filter f in place: (contained before the call, number inserted)."""
+        return self._filter_update(lib().sj_filter_insert, f, keys)
 
     def survivors(self, rel: int) -> torch.Tensor:
         n = ctypes.c_uint64()

@@ -75,6 +75,22 @@ struct StepArgs {
 
 // ---- launch wrappers (sj_kernels.hip) ----
 hipError_t launch_zero(void *p, uint64_t bytes, hipStream_t s);
+
+// Inserts into a built filter (Section 2.4): probe a batch of keys against the
+// filter as it is (contained[i], and the count of keys it does not contain added to
+// *missing); with `set`, the keys found missing then set their bits in place.
+struct FilterUpdate {
+    uint32_t *words;
+    const uint32_t *nblocks;   // device-side block count (unchanged by inserts)
+    const int32_t *keys;
+    uint64_t n;
+    uint8_t *contained;
+    unsigned long long *missing;
+    uint32_t seed;
+    int k;
+    int logB;
+};
+hipError_t launch_filter_update(const FilterUpdate &u, bool set, hipStream_t s);
 hipError_t launch_count_pred(const int32_t *col, uint32_t n, int32_t lo, int32_t hi, uint32_t *out,
                              hipStream_t s);
 // A sieve step is two launches: the probe scan (survivor bits and per-workgroup counts)

@@ -59,6 +59,46 @@ hipError_t launch_count_pred(const int32_t *col, uint32_t n, int32_t lo, int32_t
     return hipGetLastError();
 }
 
+// ---- inserts into a built filter (Section 2.4) ----
+
+__global__ __launch_bounds__(256) void k_filter_probe(FilterUpdate u) {
+    __shared__ uint64_t s_w[4];
+    const uint32_t nb = *u.nblocks;
+    const uint32_t wpb_shift = static_cast<uint32_t>(u.logB) - 5u;
+    uint64_t miss = 0;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < u.n; i += stride) {
+        const BfKey h = bf_hash(u.keys[i], u.seed, nb);
+        const bool ok = bf_test(u.words + (static_cast<uint64_t>(h.block) << wpb_shift), h.g, u.k, u.logB);
+        u.contained[i] = ok ? 1 : 0;
+        miss += ok ? 0 : 1;
+    }
+    uint64_t tot;
+    block_excl_scan<256>(miss, s_w, tot);
+    if (threadIdx.x == 0 && tot) atomicAdd(u.missing, static_cast<unsigned long long>(tot));
+}
+
+// The keys the probe found missing set their bits (a bit already seen set is not written).
+__global__ __launch_bounds__(256) void k_filter_set(FilterUpdate u) {
+    const uint32_t nb = *u.nblocks;
+    const uint32_t wpb_shift = static_cast<uint32_t>(u.logB) - 5u;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < u.n; i += stride) {
+        if (u.contained[i]) continue;
+        const BfKey h = bf_hash(u.keys[i], u.seed, nb);
+        bf_set(u.words + (static_cast<uint64_t>(h.block) << wpb_shift), h.g, u.k, u.logB);
+    }
+}
+
+hipError_t launch_filter_update(const FilterUpdate &u, bool set, hipStream_t s) {
+    if (u.n == 0) return hipSuccess;
+    const uint64_t want = (u.n + 255) / 256;
+    const uint32_t grid = static_cast<uint32_t>(want < 1024 ? want : 1024);
+    hipLaunchKernelGGL(k_filter_probe, dim3(grid), dim3(256), 0, s, u);
+    if (set) hipLaunchKernelGGL(k_filter_set, dim3(grid), dim3(256), 0, s, u);
+    return hipGetLastError();
+}
+
 // ---- the sieve step ------------------------------------------------------------------
 // Two passes with no inter-workgroup waiting. Workgroup b of kProbeGrid owns the rows
 // [b * R, (b + 1) * R), R a multiple of kProbeTile. (1) k_sieve_step probes every row

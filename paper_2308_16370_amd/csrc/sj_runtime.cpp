@@ -113,6 +113,7 @@ struct sj_plan_s {
     char *ws = nullptr;
     Region zero[3];                          // build_filters, sieve, join
     uint64_t off_elig = 0, off_nblocks = 0, off_totals = 0;
+    uint64_t off_upd = 0;                    // missing-key counter of sj_filter_probe / sj_filter_insert
     uint32_t region_blocks = 0;
     // probe and build scratch, one set per branch: survivor bits, per-workgroup counts,
     // region histogram, staged keys, kept-key bitmap
@@ -559,6 +560,7 @@ static void build_layout(sj_plan_t *p) {
     p->zero[2].end = L.top;
     // not cleared
     p->off_nblocks = L.take(4ull * std::max<size_t>(1, p->filters.size()));
+    p->off_upd = L.take(8);
     for (int b = 0; b < 2; ++b) p->off_list[b].assign(n, 0);
     for (int j = 0; j < n; ++j) {
         const uint64_t cap = p->rels[j].nrows;
@@ -1659,6 +1661,47 @@ extern "C" sj_status sj_filter_copy(sj_plan_t *p, int32_t f, uint32_t *dst, uint
     SJ_HIP(p->ctx, hipMemcpyAsync(dst, fwords(p, f), words * 4, hipMemcpyDeviceToDevice,
                                   p->ctx->stream));
     return SJ_OK;
+}
+
+// Section 2.4: a new tuple's key goes into a relation's filter only if the filter does
+// not contain it already; the keys that were missing are the ones to propagate.
+static sj_status filter_update(sj_plan_t *p, int32_t f, const int32_t *keys, uint64_t n, uint8_t *contained,
+                               uint64_t *missing, bool set) {
+    if (!p || f < 0 || f >= static_cast<int32_t>(p->filters.size())) return SJ_ERR_INVALID;
+    const Filter &F = p->filters[f];
+    // backward filters exist after sj_build_filters, forward and closing ones after sj_sieve
+    if (sj_status st = check_exec(p, F.kind == SJ_FILTER_BACKWARD ? kFiltered : kSieved)) return st;
+    if (n > 0 && (!keys || !contained)) return fail(p->ctx, SJ_ERR_INVALID, "null keys or flags");
+    if (set && F.fc_how != 0)
+        return fail(p->ctx, SJ_ERR_STATE, "filter %d is held in a filter catalogue and shared with other plans", f);
+    FilterUpdate u{};
+    u.words = fwords(p, f);
+    u.nblocks = fnblocks(p, f);
+    u.keys = keys;
+    u.n = n;
+    u.contained = contained;
+    u.missing = at<unsigned long long>(p, p->off_upd);
+    u.seed = p->seed32;
+    u.k = static_cast<int>(p->opts.k);
+    u.logB = p->logB;
+    hipStream_t s = p->ctx->stream;
+    SJ_HIP(p->ctx, launch_zero(u.missing, 8, s));
+    SJ_HIP(p->ctx, launch_filter_update(u, set, s));
+    if (missing) {
+        SJ_HIP(p->ctx, hipMemcpyAsync(missing, u.missing, 8, hipMemcpyDeviceToHost, s));
+        SJ_HIP(p->ctx, hipStreamSynchronize(s));
+    }
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_filter_probe(sj_plan_t *p, int32_t f, const int32_t *keys, uint64_t n, uint8_t *contained,
+                                     uint64_t *missing) {
+    return filter_update(p, f, keys, n, contained, missing, false);
+}
+
+extern "C" sj_status sj_filter_insert(sj_plan_t *p, int32_t f, const int32_t *keys, uint64_t n, uint8_t *contained,
+                                      uint64_t *inserted) {
+    return filter_update(p, f, keys, n, contained, inserted, true);
 }
 
 extern "C" sj_status sj_survivors_copy(sj_plan_t *p, int32_t rel, uint32_t *dst, uint64_t capacity, uint64_t *n) {

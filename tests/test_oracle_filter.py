@@ -134,3 +134,29 @@ def test_sequential_keys_spread():
     rate = oracle.bf_probe(w, q, None, nb, k, B, SEED32).mean()
     cond = float(np.mean((_popcounts(w, B) / B) ** k))
     assert abs(rate - cond) <= 5 * math.sqrt(cond / 1_000_000)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_bf_insert_properties(seed):
+    """Inserts into a built filter (Section 2.4), pinned against the plain build: into an
+    empty filter they equal the build; A then B equals the build of A and B; every
+    inserted key is found afterwards; keys already present change nothing and are
+    reported contained."""
+    rng = np.random.default_rng(300 + seed)
+    k, B, seed32 = [(6, 512, 7), (3, 256, 99), (8, 1024, 12345)][seed % 3]
+    nb = int(rng.integers(1, 40))
+    a = rng.integers(-2**31, 2**31, int(rng.integers(0, 300)), dtype=np.int64).astype(np.int32)
+    b = rng.integers(-50, 50, int(rng.integers(1, 300)), dtype=np.int64).astype(np.int32)
+    empty = np.zeros(nb * B // 32, dtype=np.uint32)
+    wa, ca = oracle.bf_insert(empty, a, nb, k, B, seed32)
+    assert np.array_equal(wa, oracle.bf_build(a, None, nb, k, B, seed32))
+    wab, cb = oracle.bf_insert(wa, b, nb, k, B, seed32)
+    assert np.array_equal(wab, oracle.bf_build(np.concatenate([a, b]), None, nb, k, B, seed32))
+    assert oracle.bf_probe(wab, np.concatenate([a, b]), None, nb, k, B, seed32).all()
+    again, c2 = oracle.bf_insert(wab, a, nb, k, B, seed32)
+    assert np.array_equal(again, wab) and c2.all()
+    # a key reported missing sets at least one new bit when inserted alone; a key
+    # reported contained sets none
+    for key, was in list(zip(b, cb))[:40]:
+        w1, _ = oracle.bf_insert(wa, np.array([key], dtype=np.int32), nb, k, B, seed32)
+        assert np.array_equal(w1, wa) == bool(was)
