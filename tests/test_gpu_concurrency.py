@@ -81,3 +81,11 @@ def test_twelve_relation_chain():
 def test_one_pass_wide_star():
     q = W.star(40000, 6, 2000, 0.5, 0x5EED00C4)
     run_modes(q, dict(OPTS, passes=1))
+
+
+def test_binary_tree_of_seven():
+    """Root with two children, each with two children: interior relations with several
+    children, and six relations bucketed on four branches."""
+    parents = [-1, 0, 0, 1, 1, 2, 2]
+    q = random_tree(parents, [2500, 800, 900, 500, 600, 400, 700], 300, 0x5EED00C5, npreds=4)
+    assert run_modes(q) > 0
