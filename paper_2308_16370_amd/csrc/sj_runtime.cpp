@@ -1262,13 +1262,54 @@ static Lookback dir_lookback(sj_plan_t *p, int j) {
     return Lookback{at<uint64_t>(p, p->jr[j].lb_dir), at<uint32_t>(p, p->jr[j].lb_dir_ctr)};
 }
 
+// DP arguments of relation j: its own buckets (or the root's survivor list), its
+// children's buckets and bounds, and its own scan scratch.
+static sj_status dp_args(sj_plan_t *p, int j, DpArgs &d) {
+    const int fl = p->final_list[j];
+    const Rel &R = p->rels[j];
+    const int ncol = static_cast<int>(R.jcols.size());
+    d = DpArgs{};
+    d.rel = static_cast<uint32_t>(j);
+    d.nchild = static_cast<int>(p->children[j].size());
+    if (d.nchild > kMaxJCols) return fail(p->ctx, SJ_ERR_UNSUPPORTED, "relation %d has more than %d children", j, kMaxJCols);
+    for (int c = 0; c < d.nchild; ++c) {
+        const int ch = p->children[j][c];
+        d.child_col[c] = R.jidx(p->pcol[ch]);
+        d.child[c] = buckets_of(p, ch);
+        d.blo[c] = at<uint32_t>(p, p->off_blo[j][c]);
+        d.bhi[c] = at<uint32_t>(p, p->off_bhi[j][c]);
+        if (p->cyclic && ch == p->L) d.skip_mask |= 1u << c;
+    }
+    d.tile_sums = at<uint64_t>(p, j == p->root ? p->off_tile_sums : p->jr[j].tsums);
+    if (j != p->root) {
+        const Buckets b = buckets_of(p, j);
+        d.n = b.n;
+        d.cap = b.cap;
+        d.rid = b.rid;
+        for (int c = 0; c < ncol; ++c) d.col[c] = b.col[c];
+        d.cw = b.cw;
+        d.cv = b.cv;
+        d.totals = nullptr;
+    } else {
+        d.n = at<uint32_t>(p, p->steps[p->final_step[j]].off_count);
+        d.cap = R.nrows;
+        d.rid = list_rid(p, j, fl);
+        for (int c = 0; c < ncol; ++c) d.col[c] = list_col(p, j, fl, c);
+        d.cw = at<uint64_t>(p, p->off_root_cw);
+        d.cv = at<uint64_t>(p, p->off_root_cv);
+        d.totals = at<uint64_t>(p, p->off_totals);
+    }
+    return SJ_OK;
+}
+
 // Count pass of the enumeration: bucket every non-root relation and run the join-tree
 // DP from the leaves up; the root's totals land in the workspace.
 static sj_status enqueue_join(sj_plan_t *p) {
     hipStream_t s = p->ls;
     if (sj_status st = zero_region(p, 2)) return st;
-    // every non-root relation is bucketed on a branch of its own; after the branches join,
-    // the DP runs bottom-up on the launch stream
+    // every non-root relation is bucketed on a branch of its own, and a leaf's DP (which
+    // reads only its own buckets and scratch) follows there; after the branches join, the
+    // other DPs run bottom-up on the launch stream
     std::vector<int> inner;
     for (int j : p->postorder)
         if (j != p->root) inner.push_back(j);
@@ -1285,49 +1326,22 @@ static sj_status enqueue_join(sj_plan_t *p) {
         Buckets b = buckets_of(p, j);
         int sec = -1;   // L of a cyclic join is ordered by its closing column inside each bucket
         if (p->cyclic && j == p->L && p->cyc_cv != p->mycol[j]) sec = R.jidx(p->cyc_cv);
-        ProfScope ps(p, std::string("buckets:") + rel_name(j));
-        SJ_HIP(p->ctx, launch_build_buckets(list_rid(p, j, fl), lcols.data(), ncol, lcount, b.key_jcol, sec, b,
-                                            sort_scratch(p, j), dir_lookback(p, j), br[i]));
+        {
+            ProfScope ps(p, std::string("buckets:") + rel_name(j));
+            SJ_HIP(p->ctx, launch_build_buckets(list_rid(p, j, fl), lcols.data(), ncol, lcount, b.key_jcol, sec, b,
+                                                sort_scratch(p, j), dir_lookback(p, j), br[i]));
+        }
+        if (!p->children[j].empty()) continue;
+        DpArgs d;
+        if (sj_status st = dp_args(p, j, d)) return st;
+        ProfScope ps(p, std::string("dp:") + rel_name(j));
+        SJ_HIP(p->ctx, launch_dp(d, br[i]));
     }
     if (sj_status st = join_streams(p, static_cast<int>(inner.size()))) return st;
     for (int j : p->postorder) {
-        const int fl = p->final_list[j];
-        const Rel &R = p->rels[j];
-        const int ncol = static_cast<int>(R.jcols.size());
-        std::vector<const int32_t *> lcols(ncol);
-        for (int c = 0; c < ncol; ++c) lcols[c] = list_col(p, j, fl, c);
-        const uint32_t *lcount = at<uint32_t>(p, p->steps[p->final_step[j]].off_count);
-        DpArgs d{};
-        d.rel = static_cast<uint32_t>(j);
-        d.nchild = static_cast<int>(p->children[j].size());
-        if (d.nchild > kMaxJCols) return fail(p->ctx, SJ_ERR_UNSUPPORTED, "relation %d has more than %d children", j, kMaxJCols);
-        for (int c = 0; c < d.nchild; ++c) {
-            const int ch = p->children[j][c];
-            d.child_col[c] = R.jidx(p->pcol[ch]);
-            d.child[c] = buckets_of(p, ch);
-            d.blo[c] = at<uint32_t>(p, p->off_blo[j][c]);
-            d.bhi[c] = at<uint32_t>(p, p->off_bhi[j][c]);
-            if (p->cyclic && ch == p->L) d.skip_mask |= 1u << c;
-        }
-        d.tile_sums = at<uint64_t>(p, j == p->root ? p->off_tile_sums : p->jr[j].tsums);
-        if (j != p->root) {
-            const Buckets b = buckets_of(p, j);
-            d.n = b.n;
-            d.cap = b.cap;
-            d.rid = b.rid;
-            for (int c = 0; c < ncol; ++c) d.col[c] = b.col[c];
-            d.cw = b.cw;
-            d.cv = b.cv;
-            d.totals = nullptr;
-        } else {
-            d.n = lcount;
-            d.cap = R.nrows;
-            d.rid = list_rid(p, j, fl);
-            for (int c = 0; c < ncol; ++c) d.col[c] = lcols[c];
-            d.cw = at<uint64_t>(p, p->off_root_cw);
-            d.cv = at<uint64_t>(p, p->off_root_cv);
-            d.totals = at<uint64_t>(p, p->off_totals);
-        }
+        if (j != p->root && p->children[j].empty()) continue;   // weighed on its branch
+        DpArgs d;
+        if (sj_status st = dp_args(p, j, d)) return st;
         ProfScope ps(p, std::string("dp:") + rel_name(j));
         SJ_HIP(p->ctx, launch_dp(d, s));
     }
