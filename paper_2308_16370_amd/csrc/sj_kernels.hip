@@ -368,33 +368,49 @@ __global__ __launch_bounds__(kProbeBlock) void k_sieve_step(StepArgs a) {
                     if (flags & (1u << i)) wl[j++] = static_cast<uint16_t>(lane * kSieveItems + i);
             }
             wave_lds_sync();
+            // a lane keeps its list entries through every probe: the keys of all of them are
+            // loaded together (one column-load latency per batch), and an entry's liveness
+            // stays in registers from one probe to the next
+            constexpr int kLB = NCOL >= 3 ? 2 : kProbeBatch;   // list batch (registers for NCOL keys each)
+            for (uint32_t e0 = lane; e0 < total; e0 += 64u * kLB) {
+                bool live[kLB], live0[kLB];
+                uint16_t ent[kLB];
 #pragma unroll
-            for (int p = 0; p < kMaxProbe; ++p) {
-                if (p < a.nprobe && p != first && total) {
-                    const uint32_t nbp = *a.probe[p].nblocks;
-                    for (uint32_t e0 = lane; e0 < total; e0 += 64u * kProbeBatch) {
-                        int32_t keys[kProbeBatch];
-                        bool live[kProbeBatch];
-                        uint16_t ent[kProbeBatch];
+                for (int ii = 0; ii < kLB; ++ii) {
+                    const uint32_t e = e0 + ii * 64u;
+                    ent[ii] = e < total ? wl[e] : kListDead;
+                    live[ii] = !(ent[ii] & kListDead);
+                    live0[ii] = live[ii];
+                }
+                int32_t keys[NCOL][kLB];
 #pragma unroll
-                        for (int ii = 0; ii < kProbeBatch; ++ii) {
-                            const uint32_t e = e0 + ii * 64u;
-                            ent[ii] = e < total ? wl[e] : kListDead;
-                            live[ii] = !(ent[ii] & kListDead);
-                            keys[ii] = live[ii] ? pcol[p][wrow0 + (ent[ii] & (kWaveRows - 1))] : 0;
+                for (int c = 0; c < NCOL; ++c)
+#pragma unroll
+                    for (int ii = 0; ii < kLB; ++ii)
+                        keys[c][ii] = live[ii] ? a.col[c][wrow0 + (ent[ii] & (kWaveRows - 1))] : 0;
+#pragma unroll
+                for (int p = 0; p < kMaxProbe; ++p) {
+                    if (p < a.nprobe && p != first) {
+                        int32_t pk[kLB];
+#pragma unroll
+                        for (int ii = 0; ii < kLB; ++ii) {
+                            pk[ii] = keys[0][ii];
+#pragma unroll
+                            for (int c = 1; c < NCOL; ++c)
+                                if (a.probe_col[p] == c) pk[ii] = keys[c][ii];
                         }
-                        probe_global<kProbeBatch, KMAX>(a, a.probe[p].words, nbp,
-                                                        (p < kMaxCached) ? s_cache[p < kMaxCached ? p : 0] : nullptr,
-                                                        keys, live, wpb_shift, sh);
-#pragma unroll
-                        for (int ii = 0; ii < kProbeBatch; ++ii) {
-                            const uint32_t e = e0 + ii * 64u;
-                            if (e < total && !(ent[ii] & kListDead) && !live[ii]) wl[e] = ent[ii] | kListDead;
-                        }
+                        probe_global<kLB, KMAX>(a, a.probe[p].words, *a.probe[p].nblocks,
+                                                (p < kMaxCached) ? s_cache[p < kMaxCached ? p : 0] : nullptr,
+                                                pk, live, wpb_shift, sh);
                     }
-                    wave_lds_sync();
+                }
+#pragma unroll
+                for (int ii = 0; ii < kLB; ++ii) {
+                    const uint32_t e = e0 + ii * 64u;
+                    if (e < total && live0[ii] && !live[ii]) wl[e] = ent[ii] | kListDead;
                 }
             }
+            wave_lds_sync();
             {
                 uint32_t j = incl - cnt;
 #pragma unroll
