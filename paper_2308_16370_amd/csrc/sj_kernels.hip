@@ -434,6 +434,7 @@ __global__ __launch_bounds__(kProbeBlock) void k_sieve_step(StepArgs a) {
 template <int NCOL>
 __global__ __launch_bounds__(kProbeBlock) void k_sieve_compact(StepArgs a) {
     __shared__ uint32_t s_wave[kProbeBlock / 64];
+    __shared__ uint64_t s_wave64[kProbeBlock / 64];
     const bool list = a.src_rid != nullptr;
     const uint32_t n = list ? *a.src_count : a.src_rows;
     const uint32_t per = sieve_rows_per_group(n);
@@ -445,49 +446,66 @@ __global__ __launch_bounds__(kProbeBlock) void k_sieve_compact(StepArgs a) {
     uint32_t base = tot;
     if (blockIdx.x == gridDim.x - 1 && tid == 0) *a.out_count = base + a.counts[blockIdx.x];
     const uint32_t r_end = min(n, (blockIdx.x + 1) * per);
-    for (uint32_t t0 = blockIdx.x * per; t0 < r_end; t0 += kProbeTile) {
-        const uint32_t row0 = t0 + tid * kSieveItems;
-        const uint32_t flags = row0 < n ? a.bits[row0 >> 3] : 0u;
-        uint32_t ttot;
-        uint32_t o = base + block_excl_scan<kProbeBlock>(static_cast<uint32_t>(__builtin_popcount(flags)), s_wave, ttot);
-        base += ttot;
-        if (!flags) continue;
-        int32_t v[NCOL][kSieveItems];
-        uint32_t rid[kSieveItems];
-        if (row0 + kSieveItems <= n) {
+    // Four tiles share one block scan: their per-thread survivor counts are packed into
+    // 16-bit fields of one 64-bit value (a tile holds fewer than 2^16 rows), so sparse
+    // survivors cost a quarter of the barriers.
+    constexpr int kGroupTiles = 4;
+    static_assert(kProbeTile < (1 << 16), "a tile's survivor count fits 16 bits");
+    for (uint32_t g0 = blockIdx.x * per; g0 < r_end; g0 += kGroupTiles * kProbeTile) {
+        uint32_t fl[kGroupTiles];
+        uint64_t packed = 0;
 #pragma unroll
-            for (int c = 0; c < NCOL; ++c) {
-                const v4i *src = reinterpret_cast<const v4i *>(a.col[c] + row0);
-                const v4i x0 = src[0], x1 = src[1];
-                v[c][0] = x0.x; v[c][1] = x0.y; v[c][2] = x0.z; v[c][3] = x0.w;
-                v[c][4] = x1.x; v[c][5] = x1.y; v[c][6] = x1.z; v[c][7] = x1.w;
-            }
-            if (list) {
-                const v4u *src = reinterpret_cast<const v4u *>(a.src_rid + row0);
-                const v4u r0 = src[0], r1 = src[1];
-                rid[0] = r0.x; rid[1] = r0.y; rid[2] = r0.z; rid[3] = r0.w;
-                rid[4] = r1.x; rid[5] = r1.y; rid[6] = r1.z; rid[7] = r1.w;
+        for (int q = 0; q < kGroupTiles; ++q) {
+            const uint32_t r = g0 + q * kProbeTile + tid * kSieveItems;
+            fl[q] = r < r_end ? a.bits[r >> 3] : 0u;
+            packed |= static_cast<uint64_t>(__builtin_popcount(fl[q])) << (16 * q);
+        }
+        uint64_t ptot;
+        const uint64_t pex = block_excl_scan<kProbeBlock>(packed, s_wave64, ptot);
+#pragma unroll
+        for (int q = 0; q < kGroupTiles; ++q) {
+            const uint32_t row0 = g0 + q * kProbeTile + tid * kSieveItems;
+            const uint32_t flags = fl[q];
+            uint32_t o = base + static_cast<uint32_t>((pex >> (16 * q)) & 0xFFFFu);
+            base += static_cast<uint32_t>((ptot >> (16 * q)) & 0xFFFFu);
+            if (!flags) continue;
+            int32_t v[NCOL][kSieveItems];
+            uint32_t rid[kSieveItems];
+            if (row0 + kSieveItems <= n) {
+#pragma unroll
+                for (int c = 0; c < NCOL; ++c) {
+                    const v4i *src = reinterpret_cast<const v4i *>(a.col[c] + row0);
+                    const v4i x0 = src[0], x1 = src[1];
+                    v[c][0] = x0.x; v[c][1] = x0.y; v[c][2] = x0.z; v[c][3] = x0.w;
+                    v[c][4] = x1.x; v[c][5] = x1.y; v[c][6] = x1.z; v[c][7] = x1.w;
+                }
+                if (list) {
+                    const v4u *src = reinterpret_cast<const v4u *>(a.src_rid + row0);
+                    const v4u r0 = src[0], r1 = src[1];
+                    rid[0] = r0.x; rid[1] = r0.y; rid[2] = r0.z; rid[3] = r0.w;
+                    rid[4] = r1.x; rid[5] = r1.y; rid[6] = r1.z; rid[7] = r1.w;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < kSieveItems; ++i) rid[i] = row0 + i;
+                }
             } else {
 #pragma unroll
-                for (int i = 0; i < kSieveItems; ++i) rid[i] = row0 + i;
+                for (int i = 0; i < kSieveItems; ++i) {
+                    const uint32_t r = row0 + i;
+                    const bool in = r < n;
+#pragma unroll
+                    for (int c = 0; c < NCOL; ++c) v[c][i] = in ? a.col[c][r] : 0;
+                    rid[i] = in ? (list ? a.src_rid[r] : r) : 0u;
+                }
             }
-        } else {
 #pragma unroll
             for (int i = 0; i < kSieveItems; ++i) {
-                const uint32_t r = row0 + i;
-                const bool in = r < n;
+                if (flags & (1u << i)) {
+                    a.out_rid[o] = rid[i];
 #pragma unroll
-                for (int c = 0; c < NCOL; ++c) v[c][i] = in ? a.col[c][r] : 0;
-                rid[i] = in ? (list ? a.src_rid[r] : r) : 0u;
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < kSieveItems; ++i) {
-            if (flags & (1u << i)) {
-                a.out_rid[o] = rid[i];
-#pragma unroll
-                for (int c = 0; c < NCOL; ++c) a.out_col[c][o] = v[c][i];
-                ++o;
+                    for (int c = 0; c < NCOL; ++c) a.out_col[c][o] = v[c][i];
+                    ++o;
+                }
             }
         }
     }
