@@ -191,6 +191,13 @@ hipError_t launch_build_buckets(const uint32_t *list_rid, const int32_t *const *
 
 // Per-entry DP weights of a bucketed relation (or the root list), scanned into
 // cw/cv. child[c] is the bucketed child joined on list column child_col[c].
+// DP lookups in flight per thread: ITEMS entries times CH children, ITEMS * CH = kDpSlots.
+// A relation with more children takes fewer entries per thread (and smaller tiles of
+// kScanBlock * ITEMS entries), so all of its children are looked up together.
+constexpr int kDpSlots = 8;
+inline int dp_items(int nchild) { return nchild <= 1 ? 8 : nchild == 2 ? 4 : nchild <= 4 ? 2 : 1; }
+inline uint32_t dp_tile(int nchild) { return static_cast<uint32_t>(kScanBlock * dp_items(nchild)); }
+
 struct DpArgs {
     uint32_t rel;              // relation index (checksum factor)
     const uint32_t *n;         // device-side entries
@@ -205,7 +212,7 @@ struct DpArgs {
     uint32_t *blo[kMaxJCols];  // [cap] per child: first entry of the matching child bucket
     uint32_t *bhi[kMaxJCols];  // [cap] per child: one past its last entry (lo = hi: none)
     uint32_t skip_mask;        // children whose totals are not multiplied in (bounds still kept)
-    uint64_t *tile_sums;       // [2 * tiles(cap)]
+    uint64_t *tile_sums;       // [2 * ceil(cap / dp_tile(nchild))]
     uint64_t *totals;          // [2] result count and checksum, or nullptr
 };
 hipError_t launch_dp(const DpArgs &a, hipStream_t s);

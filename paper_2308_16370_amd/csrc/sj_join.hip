@@ -361,85 +361,125 @@ hipError_t launch_build_buckets(const uint32_t *list_rid, const int32_t *const *
 // ================================================================ DP weights
 // w(e) = prod over children c of W_c(key_c(e)), v(e) = f(rel, rid(e)) * prod V_c(...),
 // with W_c / V_c the totals of the child's bucket for that key (0 if absent).
-
-// The kScanItems entries of a thread go through each lookup stage together, so the
-// loads of a stage are independent and in flight at once (key, hash slot, directory
-// bounds, child prefix weights); a slot that holds another key (rare: the index is at
-// most half full) is resolved by linear probing afterwards. A thread's entries are
-// kScanBlock apart (entry tile * kScanTile + i * kScanBlock + thread), so the loads of
-// one stage are consecutive across a wave; only the tile's total is scanned here.
+//
+// A thread holds ITEMS entries and looks them up in CH = kDpSlots / ITEMS children at
+// once, so every lookup stage (key, hash slot, directory bounds, child prefix weights)
+// has kDpSlots independent loads in flight and the dependent chain is four stages per
+// group of CH children. A relation with one child takes 8 entries per thread; one with
+// four children takes 2 entries of all four children (dp_items). A slot that holds
+// another key (rare: the index is at most half full) is resolved by linear probing. A
+// thread's entries are kScanBlock apart (entry tile * tile size + i * kScanBlock +
+// thread), so the loads of one stage are consecutive across a wave; only the tile's
+// total is scanned here.
+template <int ITEMS>
 __device__ __forceinline__ void dp_entries(const DpArgs &a, const uint32_t *masks, uint32_t base, uint32_t n,
                                            uint64_t *w, uint64_t *v) {
+    constexpr int CH = kDpSlots / ITEMS;
+    static_assert(kMaxJCols % CH == 0, "child groups tile the child slots");
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
         const uint32_t e = base + i * kScanBlock;
         w[i] = 1;
         v[i] = e < n ? chk_factor(a.rel, a.rid[e]) : 0;
     }
 #pragma unroll
-    for (int c = 0; c < kMaxJCols; ++c) {
-        if (c < a.nchild) {
-            const int32_t *col = a.col[a.child_col[c]];
-            const uint64_t *slots = a.child[c].slots;
-            int32_t key[kScanItems];
-            uint32_t sl[kScanItems];
-            uint64_t sv[kScanItems];
+    for (int c0 = 0; c0 < kMaxJCols; c0 += CH) {
+        if (c0 < a.nchild) {
+            int32_t key[CH][ITEMS];
+            uint32_t sl[CH][ITEMS];
+            uint64_t sv[CH][ITEMS];
+            uint32_t lo[CH][ITEMS], hi[CH][ITEMS];
 #pragma unroll
-            for (int i = 0; i < kScanItems; ++i) key[i] = base + i * kScanBlock < n ? col[base + i * kScanBlock] : 0;
+            for (int cc = 0; cc < CH; ++cc) {
+                const int c = c0 + cc;
+                const int32_t *col = a.col[a.child_col[c]];
 #pragma unroll
-            for (int i = 0; i < kScanItems; ++i) {
-                sl[i] = slot_hash(key[i]) & masks[c];
-                sv[i] = slots[sl[i]];
-            }
-            uint32_t lo[kScanItems], hi[kScanItems];
-#pragma unroll
-            for (int i = 0; i < kScanItems; ++i) {
-                while (sv[i] != 0 && static_cast<uint32_t>(sv[i]) != static_cast<uint32_t>(key[i])) {
-                    sl[i] = (sl[i] + 1) & masks[c];
-                    sv[i] = slots[sl[i]];
-                }
-                const uint32_t d = static_cast<uint32_t>(sv[i] >> 32);   // directory index + 1, 0: absent
-                lo[i] = d ? a.child[c].dir_begin[d - 1] : 0u;
-                hi[i] = d ? a.child[c].dir_begin[d] : 0u;
-            }
-#pragma unroll
-            for (int i = 0; i < kScanItems; ++i) {
-                const uint32_t e = base + i * kScanBlock;
-                if (e < n) {
-                    a.blo[c][e] = lo[i];
-                    a.bhi[c][e] = hi[i];
+                for (int i = 0; i < ITEMS; ++i) {
+                    const uint32_t e = base + i * kScanBlock;
+                    key[cc][i] = (c < a.nchild && e < n) ? col[e] : 0;
                 }
             }
-            if (!(a.skip_mask & (1u << c))) {
-                const uint64_t *cw = a.child[c].cw, *cv = a.child[c].cv;
 #pragma unroll
-                for (int i = 0; i < kScanItems; ++i) {
-                    w[i] *= cw[hi[i]] - cw[lo[i]];
-                    v[i] *= cv[hi[i]] - cv[lo[i]];
+            for (int cc = 0; cc < CH; ++cc) {
+                const int c = c0 + cc;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    sl[cc][i] = 0;
+                    sv[cc][i] = 0;
+                    if (c < a.nchild) {
+                        sl[cc][i] = slot_hash(key[cc][i]) & masks[c];
+                        sv[cc][i] = a.child[c].slots[sl[cc][i]];
+                    }
+                }
+            }
+#pragma unroll
+            for (int cc = 0; cc < CH; ++cc) {
+                const int c = c0 + cc;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    lo[cc][i] = 0;
+                    hi[cc][i] = 0;
+                    if (c < a.nchild) {
+                        while (sv[cc][i] != 0 && static_cast<uint32_t>(sv[cc][i]) != static_cast<uint32_t>(key[cc][i])) {
+                            sl[cc][i] = (sl[cc][i] + 1) & masks[c];
+                            sv[cc][i] = a.child[c].slots[sl[cc][i]];
+                        }
+                        const uint32_t d = static_cast<uint32_t>(sv[cc][i] >> 32);   // directory index + 1, 0: absent
+                        lo[cc][i] = d ? a.child[c].dir_begin[d - 1] : 0u;
+                        hi[cc][i] = d ? a.child[c].dir_begin[d] : 0u;
+                    }
+                }
+            }
+#pragma unroll
+            for (int cc = 0; cc < CH; ++cc) {
+                const int c = c0 + cc;
+                if (c < a.nchild) {
+#pragma unroll
+                    for (int i = 0; i < ITEMS; ++i) {
+                        const uint32_t e = base + i * kScanBlock;
+                        if (e < n) {
+                            a.blo[c][e] = lo[cc][i];
+                            a.bhi[c][e] = hi[cc][i];
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int cc = 0; cc < CH; ++cc) {
+                const int c = c0 + cc;
+                if (c < a.nchild && !(a.skip_mask & (1u << c))) {
+                    const uint64_t *cw = a.child[c].cw, *cv = a.child[c].cv;
+#pragma unroll
+                    for (int i = 0; i < ITEMS; ++i) {
+                        w[i] *= cw[hi[cc][i]] - cw[lo[cc][i]];
+                        v[i] *= cv[hi[cc][i]] - cv[lo[cc][i]];
+                    }
                 }
             }
         }
     }
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i)
+    for (int i = 0; i < ITEMS; ++i)
         if (base + i * kScanBlock >= n) w[i] = v[i] = 0;
 }
 
 // Phase 1: per-entry weights into cw/cv (not yet scanned) and per-tile sums.
+template <int ITEMS>
 __global__ __launch_bounds__(kScanBlock) void k_dp_reduce(DpArgs a) {
+    constexpr uint32_t T = kScanBlock * ITEMS;
     __shared__ uint64_t s_w[kScanBlock / 64], s_v[kScanBlock / 64];
     const uint32_t n = *a.n;
-    const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
+    const uint32_t ntiles = (n + T - 1) / T;
     uint32_t masks[kMaxJCols];
 #pragma unroll
     for (int c = 0; c < kMaxJCols; ++c) masks[c] = c < a.nchild ? *a.child[c].slot_mask : 0u;
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t base = tile * kScanTile + threadIdx.x;
-        uint64_t w[kScanItems], v[kScanItems];
-        dp_entries(a, masks, base, n, w, v);
+        const uint32_t base = tile * T + threadIdx.x;
+        uint64_t w[ITEMS], v[ITEMS];
+        dp_entries<ITEMS>(a, masks, base, n, w, v);
         uint64_t sw = 0, sv = 0;
 #pragma unroll
-        for (int i = 0; i < kScanItems; ++i) {
+        for (int i = 0; i < ITEMS; ++i) {
             if (base + i * kScanBlock < n) {
                 a.cw[base + i * kScanBlock] = w[i];
                 a.cv[base + i * kScanBlock] = v[i];
@@ -458,11 +498,13 @@ __global__ __launch_bounds__(kScanBlock) void k_dp_reduce(DpArgs a) {
 }
 
 // Phase 2 (one block): exclusive scan of the tile sums; totals at cw[n], cv[n].
+template <int ITEMS>
 __global__ __launch_bounds__(kScanBlock) void k_dp_tiles(DpArgs a) {
+    constexpr uint32_t T = kScanBlock * ITEMS;
     __shared__ uint64_t s_w[kScanBlock / 64], s_v[kScanBlock / 64];
     __shared__ uint64_t s_carry[2];
     const uint32_t n = *a.n;
-    const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
+    const uint32_t ntiles = (n + T - 1) / T;
     if (threadIdx.x == 0) {
         s_carry[0] = 0;
         s_carry[1] = 0;
@@ -496,16 +538,18 @@ __global__ __launch_bounds__(kScanBlock) void k_dp_tiles(DpArgs a) {
 }
 
 // Phase 3: turn per-entry weights into exclusive prefixes.
+template <int ITEMS>
 __global__ __launch_bounds__(kScanBlock) void k_dp_down(DpArgs a) {
+    constexpr uint32_t T = kScanBlock * ITEMS;
     __shared__ uint64_t s_w[kScanBlock / 64], s_v[kScanBlock / 64];
     const uint32_t n = *a.n;
-    const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
+    const uint32_t ntiles = (n + T - 1) / T;
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t base = tile * kScanTile + threadIdx.x * kScanItems;
-        uint64_t w[kScanItems], v[kScanItems];
+        const uint32_t base = tile * T + threadIdx.x * ITEMS;
+        uint64_t w[ITEMS], v[ITEMS];
         uint64_t sw = 0, sv = 0;
 #pragma unroll
-        for (int i = 0; i < kScanItems; ++i) {
+        for (int i = 0; i < ITEMS; ++i) {
             const uint32_t e = base + i;
             w[i] = e < n ? a.cw[e] : 0;
             v[i] = e < n ? a.cv[e] : 0;
@@ -516,7 +560,7 @@ __global__ __launch_bounds__(kScanBlock) void k_dp_down(DpArgs a) {
         uint64_t ow = block_excl_scan<kScanBlock>(sw, s_w, tw) + a.tile_sums[2 * tile];
         uint64_t ov = block_excl_scan<kScanBlock>(sv, s_v, tv) + a.tile_sums[2 * tile + 1];
 #pragma unroll
-        for (int i = 0; i < kScanItems; ++i) {
+        for (int i = 0; i < ITEMS; ++i) {
             const uint32_t e = base + i;
             if (e < n) {
                 a.cw[e] = ow;
@@ -528,12 +572,24 @@ __global__ __launch_bounds__(kScanBlock) void k_dp_down(DpArgs a) {
     }
 }
 
-hipError_t launch_dp(const DpArgs &a, hipStream_t s) {
-    const uint32_t tiles = (a.cap + kScanTile - 1) / kScanTile;
+template <int ITEMS>
+static void launch_dp_items(const DpArgs &a, hipStream_t s) {
+    const uint32_t T = kScanBlock * ITEMS;
+    const uint32_t tiles = (a.cap + T - 1) / T;
     const uint32_t g = tiles == 0 ? 1 : (tiles < kPersistentBlocks ? tiles : kPersistentBlocks);
-    hipLaunchKernelGGL(k_dp_reduce, dim3(g), dim3(kScanBlock), 0, s, a);
-    hipLaunchKernelGGL(k_dp_tiles, dim3(1), dim3(kScanBlock), 0, s, a);
-    hipLaunchKernelGGL(k_dp_down, dim3(g), dim3(kScanBlock), 0, s, a);
+    hipLaunchKernelGGL(k_dp_reduce<ITEMS>, dim3(g), dim3(kScanBlock), 0, s, a);
+    hipLaunchKernelGGL(k_dp_tiles<ITEMS>, dim3(1), dim3(kScanBlock), 0, s, a);
+    hipLaunchKernelGGL(k_dp_down<ITEMS>, dim3(g), dim3(kScanBlock), 0, s, a);
+}
+
+hipError_t launch_dp(const DpArgs &a, hipStream_t s) {
+    if (a.nchild < 0 || a.nchild > kMaxJCols) return hipErrorInvalidValue;
+    switch (dp_items(a.nchild)) {
+    case 8: launch_dp_items<8>(a, s); break;
+    case 4: launch_dp_items<4>(a, s); break;
+    case 2: launch_dp_items<2>(a, s); break;
+    default: launch_dp_items<1>(a, s); break;
+    }
     return hipGetLastError();
 }
 

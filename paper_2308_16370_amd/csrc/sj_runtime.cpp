@@ -595,9 +595,11 @@ static void build_layout(sj_plan_t *p) {
         }
         r.shist = L.take(4ull * kRadixBins * std::max<uint32_t>(1, tiles_of(static_cast<uint32_t>(cap), kRadixTile)));
         r.sctl = L.take(4 * 32);
-        r.tsums = L.take(16ull * std::max<uint32_t>(1, tiles_of(static_cast<uint32_t>(cap), kScanTile)));
+        r.tsums = L.take(16ull * std::max<uint32_t>(1, tiles_of(static_cast<uint32_t>(cap),
+                                                                   dp_tile(static_cast<int>(p->children[j].size())))));
     }
-    p->off_tile_sums = L.take(16ull * std::max<uint32_t>(1, tiles_of(maxcap, kScanTile)));
+    p->off_tile_sums = L.take(16ull * std::max<uint32_t>(
+        1, tiles_of(maxcap, dp_tile(static_cast<int>(p->children[p->root].size())))));
     const uint64_t rc = p->rels[p->root].nrows;
     p->off_root_cw = L.take(8 * (rc + 1));
     p->off_root_cv = L.take(8 * (rc + 1));
