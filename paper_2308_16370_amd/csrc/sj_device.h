@@ -242,6 +242,32 @@ __device__ __forceinline__ uint32_t upper_bound_u64(const uint64_t *a, uint32_t 
     return lo;
 }
 
+// The same search by a whole wave (all 64 lanes, the same arguments): each round the
+// lanes read 64 evenly spaced pivots of [lo, hi) at once and a ballot keeps the part
+// that holds the answer, so a range of m entries takes about log64(m) dependent loads
+// instead of log2(m). Every lane returns the answer.
+__device__ __forceinline__ uint32_t wave_upper_bound_u64(const uint64_t *a, uint32_t lo, uint32_t hi, uint64_t x) {
+    const uint64_t lane = static_cast<uint64_t>(lane_id());
+    // invariant: the answer is in [lo, hi], and hi is either the end of the range or an
+    // index with a[hi] > x
+    while (hi - lo > 64u) {
+        const uint64_t step = (static_cast<uint64_t>(hi - lo) + 63u) / 64u;
+        const uint64_t idx = lo + lane * step;
+        const bool gt = idx < hi ? a[idx] > x : true;
+        const uint64_t m = __ballot(gt);
+        const uint64_t f = m ? static_cast<uint64_t>(__ffsll(static_cast<unsigned long long>(m)) - 1) : 64u;
+        if (f == 0) return lo;
+        const uint64_t nhi = lo + f * step;
+        const uint32_t nlo = static_cast<uint32_t>(lo + (f - 1) * step + 1);
+        hi = nhi < hi ? static_cast<uint32_t>(nhi) : hi;
+        lo = nlo;
+    }
+    const uint64_t idx = lo + lane;
+    const bool gt = idx < hi ? a[idx] > x : true;
+    const uint64_t m = __ballot(gt);
+    return m ? lo + static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(m)) - 1) : hi;
+}
+
 // ---- hash index over a bucketed relation's distinct keys ------------------------
 // Slot word: ((dir + 1) << 32) | key; 0 marks an empty slot (dir + 1 >= 1).
 

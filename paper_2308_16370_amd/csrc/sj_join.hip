@@ -744,9 +744,10 @@ __global__ __launch_bounds__(256) void k_materialize(MatArgs a) {
     for (uint64_t blk = blockIdx.x; blk * PER < count; blk += gridDim.x) {
         const uint64_t t0 = blk * PER;
         const uint64_t t1 = (t0 + PER < count) ? t0 + PER : count;
-        if (threadIdx.x < 2) {
-            const uint64_t o = threadIdx.x == 0 ? t0 : t1 - 1;
-            s_r[threadIdx.x] = upper_bound_u64(rcw, 0, root_n + 1, o) - 1;
+        if (threadIdx.x < 128) {   // wave 0 finds the root entry of t0, wave 1 that of t1 - 1
+            const int wv = threadIdx.x >> 6;
+            const uint32_t r = wave_upper_bound_u64(rcw, 0, root_n + 1, wv == 0 ? t0 : t1 - 1) - 1;
+            if (lane_id() == 0) s_r[wv] = r;
         }
         __syncthreads();
         const uint32_t r0 = s_r[0], r1 = s_r[1];
