@@ -18,11 +18,12 @@ constexpr int kSieveTile = kSieveBlock * kSieveItems;
 
 // Sieve scans (probe and compaction) run one 1024-thread workgroup per CU, so a
 // workgroup can hold a filter of up to kLdsFilterBytes in LDS; workgroup b owns a
-// contiguous run of tiles.
+// contiguous run of tiles. With the probe's static LDS (a 32 KB answer cache and 16 KB
+// of live-row lists) that stays within the 160 KB of a CU.
 constexpr int kProbeBlock = 1024;
 constexpr uint32_t kProbeGrid = 256;
 constexpr int kProbeTile = kProbeBlock * kSieveItems;
-constexpr uint32_t kLdsFilterBytes = 124 * 1024;
+constexpr uint32_t kLdsFilterBytes = 108 * 1024;
 
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;

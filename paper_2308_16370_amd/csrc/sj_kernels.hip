@@ -117,10 +117,10 @@ hipError_t launch_filter_update(const FilterUpdate &u, bool set, hipStream_t s) 
 // entry holds the remaining bits of c and two flags, so one 32-bit store publishes a
 // consistent entry and a tag match identifies the key exactly.
 #ifndef SJ_MAX_CACHED
-#define SJ_MAX_CACHED 2
+#define SJ_MAX_CACHED 1
 #endif
 #ifndef SJ_CACHE_LOG
-#define SJ_CACHE_LOG 11
+#define SJ_CACHE_LOG 13
 #endif
 #ifndef SJ_PROBE_BATCH
 #define SJ_PROBE_BATCH 4
