@@ -88,11 +88,22 @@ def test_valid_chain_plans():
     ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"root": 2}, sj.SJ_ERR_INVALID),
     ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"flags": 8}, sj.SJ_ERR_INVALID),
     ([(2**31, 2, None)] * 2, [(0, 1, 1, 0)], {}, sj.SJ_ERR_INVALID),
+    # nine children on one column: the root's step would probe nine filters
+    ([(10, 1, None)] * 10, [(0, 0, i, 0) for i in range(1, 10)], {}, sj.SJ_ERR_UNSUPPORTED),
+    # a relation joining on nine columns
+    ([(10, 9, None)] + [(10, 1, None)] * 9, [(0, i - 1, i, 0) for i in range(1, 10)], {}, sj.SJ_ERR_UNSUPPORTED),
 ])
 def test_invalid_plans(specs, edges, kw, code):
     st, p, ws, ctx, err = plan(specs, edges, **kw)
     assert st == code, err
     assert err
+
+
+def test_eight_children_accepted():
+    st, p, ws, ctx, err = plan([(10, 1, None)] * 9, [(0, 0, i, 0) for i in range(1, 9)])
+    assert st == 0, err
+    st, p, ws, ctx, err = plan([(10, 8, None)] + [(10, 1, None)] * 8, [(0, i - 1, i, 0) for i in range(1, 9)])
+    assert st == 0, err
 
 
 def test_misaligned_column_rejected():
