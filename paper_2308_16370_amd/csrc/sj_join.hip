@@ -497,7 +497,10 @@ __global__ __launch_bounds__(kScanBlock) void k_dp_reduce(DpArgs a) {
     }
 }
 
-// Phase 2 (one block): exclusive scan of the tile sums; totals at cw[n], cv[n].
+// Phase 2 (one block): exclusive scan of the tile sums; totals at cw[n], cv[n]. Each
+// thread takes kDpTileRun consecutive tile sums per round, so a round covers 2048 tiles.
+constexpr int kDpTileRun = 8;
+
 template <int ITEMS>
 __global__ __launch_bounds__(kScanBlock) void k_dp_tiles(DpArgs a) {
     constexpr uint32_t T = kScanBlock * ITEMS;
@@ -510,15 +513,29 @@ __global__ __launch_bounds__(kScanBlock) void k_dp_tiles(DpArgs a) {
         s_carry[1] = 0;
     }
     __syncthreads();
-    for (uint32_t t0 = 0; t0 < ntiles; t0 += kScanBlock) {
-        const uint32_t t = t0 + threadIdx.x;
-        const uint64_t w = t < ntiles ? a.tile_sums[2 * t] : 0, v = t < ntiles ? a.tile_sums[2 * t + 1] : 0;
+    for (uint32_t t0 = 0; t0 < ntiles; t0 += kScanBlock * kDpTileRun) {
+        const uint32_t tb = t0 + threadIdx.x * kDpTileRun;
+        uint64_t w[kDpTileRun], v[kDpTileRun], sw = 0, sv = 0;
+#pragma unroll
+        for (int j = 0; j < kDpTileRun; ++j) {
+            const uint32_t t = tb + j;
+            w[j] = t < ntiles ? a.tile_sums[2 * t] : 0;
+            v[j] = t < ntiles ? a.tile_sums[2 * t + 1] : 0;
+            sw += w[j];
+            sv += v[j];
+        }
         uint64_t tw, tv;
-        const uint64_t ow = block_excl_scan<kScanBlock>(w, s_w, tw);
-        const uint64_t ov = block_excl_scan<kScanBlock>(v, s_v, tv);
-        if (t < ntiles) {
-            a.tile_sums[2 * t] = s_carry[0] + ow;
-            a.tile_sums[2 * t + 1] = s_carry[1] + ov;
+        uint64_t ow = block_excl_scan<kScanBlock>(sw, s_w, tw) + s_carry[0];
+        uint64_t ov = block_excl_scan<kScanBlock>(sv, s_v, tv) + s_carry[1];
+#pragma unroll
+        for (int j = 0; j < kDpTileRun; ++j) {
+            const uint32_t t = tb + j;
+            if (t < ntiles) {
+                a.tile_sums[2 * t] = ow;
+                a.tile_sums[2 * t + 1] = ov;
+            }
+            ow += w[j];
+            ov += v[j];
         }
         __syncthreads();
         if (threadIdx.x == 0) {

@@ -63,3 +63,11 @@ def test_interior_relation_with_three_children():
     cnt, S = run(q)
     assert S[1].shape[0] > 20 * 512
     assert cnt > 20 * 512
+
+
+def test_tile_scan_over_several_rounds():
+    """Five children (one entry per thread, 256-entry tiles) and about 600K root
+    survivors: more than 2048 DP tiles, so the tile-sum scan takes several rounds."""
+    q = W.star(700_001, 5, 20011, 0.97, 0x5EED0D20)
+    cnt, S = run(q)
+    assert S[0].shape[0] > 2048 * 256
