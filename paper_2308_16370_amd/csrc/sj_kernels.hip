@@ -165,7 +165,7 @@ __device__ __forceinline__ void load_keys(const int32_t *col, uint32_t row0, uin
 // One probe of a batch of keys against a filter in memory, through the LDS answer
 // cache of probe slot `cslot` (no cache when cslot < 0). live[ii]: the key needs an
 // answer; on return, live[ii] is cleared for keys the filter rejects.
-template <int B, int KMAX>
+template <int B, int KMAX, bool EXACT>
 __device__ __forceinline__ void probe_global(const StepArgs &a, const uint32_t *words, uint32_t nb,
                                              uint32_t *cache, const int32_t *keys, bool *live,
                                              uint32_t wpb_shift, uint32_t sh) {
@@ -200,7 +200,7 @@ __device__ __forceinline__ void probe_global(const StepArgs &a, const uint32_t *
             const uint32_t *b = words + (static_cast<uint64_t>(blk[ii]) << wpb_shift);
 #pragma unroll
             for (int j = 0; j < KMAX; ++j)
-                if (j < a.k) w[ii][j] = b[((g[ii] * bf_mult(j)) >> sh) >> 5];
+                if (j < (EXACT ? KMAX : a.k)) w[ii][j] = b[((g[ii] * bf_mult(j)) >> sh) >> 5];
         }
     }
 #pragma unroll
@@ -209,7 +209,7 @@ __device__ __forceinline__ void probe_global(const StepArgs &a, const uint32_t *
             uint32_t ok = 1u;
 #pragma unroll
             for (int j = 0; j < KMAX; ++j)
-                if (j < a.k) ok &= w[ii][j] >> (((g[ii] * bf_mult(j)) >> sh) & 31u);
+                if (j < (EXACT ? KMAX : a.k)) ok &= w[ii][j] >> (((g[ii] * bf_mult(j)) >> sh) & 31u);
             ok &= 1u;
             if (!ok) live[ii] = false;
             if (cache) cache[cache_slot(kc[ii])] = cache_tag(kc[ii]) | kCacheValid | ok;
@@ -221,7 +221,10 @@ __device__ __forceinline__ void probe_global(const StepArgs &a, const uint32_t *
 // plus a dead flag.
 constexpr uint16_t kListDead = 0x8000;
 
-template <int NCOL, int KMAX>
+// KMAX bounds k; with EXACT, k == KMAX and the per-word guards fold away at compile time
+// (k = 2, 4 and 6 have such instances: the per-word checks of a general instance cost
+// about a tenth of a scan).
+template <int NCOL, int KMAX, bool EXACT>
 __global__ __launch_bounds__(kProbeBlock) void k_sieve_step(StepArgs a) {
     // keys whose k words are in flight together (fewer for k > 8, to stay in registers)
     constexpr int kProbeBatch = KMAX > 8 ? kProbeBatchMax / 2 : kProbeBatchMax;
@@ -329,14 +332,14 @@ __global__ __launch_bounds__(kProbeBlock) void k_sieve_step(StepArgs a) {
                         const uint32_t *b = s_filter + (h.block << wpb_shift);
 #pragma unroll
                         for (int j = 0; j < KMAX; ++j)
-                            if (j < a.k) w[ii][j] = b[((h.g * bf_mult(j)) >> sh) >> 5];
+                            if (j < (EXACT ? KMAX : a.k)) w[ii][j] = b[((h.g * bf_mult(j)) >> sh) >> 5];
                     }
 #pragma unroll
                     for (int ii = 0; ii < kProbeBatch; ++ii) {
                         uint32_t ok = 1u;
 #pragma unroll
                         for (int j = 0; j < KMAX; ++j)
-                            if (j < a.k) ok &= w[ii][j] >> (((g[ii] * bf_mult(j)) >> sh) & 31u);
+                            if (j < (EXACT ? KMAX : a.k)) ok &= w[ii][j] >> (((g[ii] * bf_mult(j)) >> sh) & 31u);
                         if (!(ok & 1u)) flags &= ~(1u << (i0 + ii));
                     }
                 }
@@ -347,7 +350,7 @@ __global__ __launch_bounds__(kProbeBlock) void k_sieve_step(StepArgs a) {
                     bool live[kProbeBatch];
 #pragma unroll
                     for (int ii = 0; ii < kProbeBatch; ++ii) live[ii] = (flags >> (i0 + ii)) & 1u;
-                    probe_global<kProbeBatch, KMAX>(a, a.probe[0].words, nb0, kMaxCached > 0 ? s_cache[0] : nullptr,
+                    probe_global<kProbeBatch, KMAX, EXACT>(a, a.probe[0].words, nb0, kMaxCached > 0 ? s_cache[0] : nullptr,
                                                     key + i0, live, wpb_shift, sh);
 #pragma unroll
                     for (int ii = 0; ii < kProbeBatch; ++ii)
@@ -399,7 +402,7 @@ __global__ __launch_bounds__(kProbeBlock) void k_sieve_step(StepArgs a) {
                             for (int c = 1; c < NCOL; ++c)
                                 if (a.probe_col[p] == c) pk[ii] = keys[c][ii];
                         }
-                        probe_global<kLB, KMAX>(a, a.probe[p].words, *a.probe[p].nblocks,
+                        probe_global<kLB, KMAX, EXACT>(a, a.probe[p].words, *a.probe[p].nblocks,
                                                 (p < kMaxCached) ? s_cache[p < kMaxCached ? p : 0] : nullptr,
                                                 pk, live, wpb_shift, sh);
                     }
@@ -511,13 +514,13 @@ __global__ __launch_bounds__(kProbeBlock) void k_sieve_compact(StepArgs a) {
     }
 }
 
-template <int KMAX>
+template <int KMAX, bool EXACT>
 static hipError_t launch_probe_k(const StepArgs &a, hipStream_t s) {
     const dim3 g(kProbeGrid), b(kProbeBlock);
     const size_t lds = 4ull * a.lds_words;
     switch (a.ncol) {
 #define SJ_PROBE_CASE(NC) \
-    case NC: hipLaunchKernelGGL((k_sieve_step<NC, KMAX>), g, b, lds, s, a); break;
+    case NC: hipLaunchKernelGGL((k_sieve_step<NC, KMAX, EXACT>), g, b, lds, s, a); break;
         SJ_PROBE_CASE(1) SJ_PROBE_CASE(2) SJ_PROBE_CASE(3) SJ_PROBE_CASE(4)
         SJ_PROBE_CASE(5) SJ_PROBE_CASE(6) SJ_PROBE_CASE(7) SJ_PROBE_CASE(8)
 #undef SJ_PROBE_CASE
@@ -528,7 +531,12 @@ static hipError_t launch_probe_k(const StepArgs &a, hipStream_t s) {
 
 hipError_t launch_sieve_probe(const StepArgs &a, uint32_t max_rows, hipStream_t s) {
     if (max_rows == 0) return hipSuccess;
-    return a.k <= 8 ? launch_probe_k<8>(a, s) : launch_probe_k<kMaxK>(a, s);
+    switch (a.k) {
+    case 2: return launch_probe_k<2, true>(a, s);
+    case 4: return launch_probe_k<4, true>(a, s);
+    case 6: return launch_probe_k<6, true>(a, s);
+    default: return a.k <= 8 ? launch_probe_k<8, false>(a, s) : launch_probe_k<kMaxK, false>(a, s);
+    }
 }
 
 hipError_t launch_sieve_compact(const StepArgs &a, uint32_t max_rows, hipStream_t s) {
