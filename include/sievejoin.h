@@ -118,6 +118,10 @@ typedef struct {
  * (a hipStream_t; NULL = the null stream). The stream stays caller-owned. */
 sj_status sj_ctx_create(int32_t device, void *hip_stream, sj_ctx **out);
 sj_status sj_ctx_set_stream(sj_ctx *ctx, void *hip_stream);
+/* Release the caller's context. Plans made on it keep it alive: it is freed when the
+ * caller has destroyed it and its last plan is destroyed, in either order (plans and
+ * contexts may be released by a garbage collector in any order). The caller must not
+ * use the handle after this call. */
 sj_status sj_ctx_destroy(sj_ctx *ctx);
 /* Text of the context's last error ("" if none); valid until the next call on ctx. */
 const char *sj_last_error(const sj_ctx *ctx);

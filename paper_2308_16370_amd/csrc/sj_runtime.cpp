@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -21,7 +22,14 @@ struct sj_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    std::atomic<int> refs{1};   // the creator's reference and one per plan
 };
+
+// A context lives until its creator has destroyed it and every plan made on it is gone,
+// so plans may be destroyed after their context in any order.
+static void ctx_release(sj_ctx *c) {
+    if (c && c->refs.fetch_sub(1, std::memory_order_acq_rel) == 1) delete c;
+}
 
 namespace {
 
@@ -231,6 +239,7 @@ sj_plan_s::~sj_plan_s() {
         (void)hipEventDestroy(r.b);
     }
     for (auto e : prof_free) (void)hipEventDestroy(e);
+    ctx_release(ctx);
 }
 
 // ---------------------------------------------------------------- errors
@@ -275,7 +284,7 @@ extern "C" sj_status sj_ctx_set_stream(sj_ctx *ctx, void *hip_stream) {
 }
 
 extern "C" sj_status sj_ctx_destroy(sj_ctx *ctx) {
-    delete ctx;
+    ctx_release(ctx);
     return SJ_OK;
 }
 
@@ -662,6 +671,7 @@ extern "C" sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, con
     sj_plan_t *p = new (std::nothrow) sj_plan_t;
     if (!p) return fail(ctx, SJ_ERR_INVALID, "out of host memory");
     p->ctx = ctx;
+    ctx->refs.fetch_add(1, std::memory_order_relaxed);
     p->n = nrels;
     p->opts = o;
     p->logB = (o.block_bits == 256) ? 8 : (o.block_bits == 512 ? 9 : 10);
@@ -999,6 +1009,9 @@ static sj_status check_exec(sj_plan_t *p, int need) {
         return fail(p->ctx, SJ_ERR_STATE, "call %s first", names[need]);
     }
     SJ_HIP(p->ctx, hipSetDevice(p->ctx->device));
+    // an error left by an earlier, unrelated HIP call would otherwise be reported by the
+    // launch checks of this call (sticky device errors still fail the launches)
+    (void)hipGetLastError();
     return SJ_OK;
 }
 

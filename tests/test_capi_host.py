@@ -106,6 +106,20 @@ def test_eight_children_accepted():
     assert st == 0, err
 
 
+def test_plans_outlive_their_context():
+    """A context destroyed before its plans stays valid for them (a garbage collector may
+    release the two in either order)."""
+    L = sj.lib()
+    st, p, ws, ctx, err = plan([(1000, 2, None)] * 3, [(0, 1, 1, 0), (1, 1, 2, 0)])
+    assert st == 0, err
+    st2, p2, _, _, _ = plan([(10, 2, None)] * 2, [(0, 1, 1, 0)])
+    assert L.sj_ctx_destroy(ctx) == 0
+    nf = ctypes.c_int32()
+    assert L.sj_filter_count(p, ctypes.byref(nf)) == 0 and nf.value == 4
+    assert L.sj_plan_destroy(p) == 0
+    assert L.sj_plan_destroy(p2) == 0
+
+
 def test_misaligned_column_rejected():
     L = sj.lib()
     ctx = ctypes.c_void_p()
