@@ -735,6 +735,8 @@ __global__ __launch_bounds__(kBuildBlock) void k_bfb_scatter(BuildArgs a) {
     }
 }
 
+// KMAX bounds k; with EXACT, k == KMAX (instances for k = 2, 4 and 6, as for the probes).
+template <int KMAX, bool EXACT>
 __global__ __launch_bounds__(kRegionThreads) void k_bfb_region(BuildArgs a) {
     extern __shared__ uint32_t s_words[];  // [region_blocks * words per block]
     const BfbShape sh = bfb_shape(a);
@@ -762,14 +764,14 @@ __global__ __launch_bounds__(kRegionThreads) void k_bfb_region(BuildArgs a) {
             }
             // read every word the batch touches first, then OR only the bits still clear:
             // heavy-hitter keys staged by many tiles find their bits set and cost no atomic
-            uint32_t w[U][kMaxK];
+            uint32_t w[U][KMAX];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (bb[u] != 0xFFFFFFFFu) {
                     const uint32_t *wb = s_words + (bb[u] << wpb_shift);
 #pragma unroll
-                    for (int j = 0; j < kMaxK; ++j)
-                        if (j < a.k) w[u][j] = wb[((gg[u] * bf_mult(j)) >> hs) >> 5];
+                    for (int j = 0; j < KMAX; ++j)
+                        if (j < (EXACT ? KMAX : a.k)) w[u][j] = wb[((gg[u] * bf_mult(j)) >> hs) >> 5];
                 }
             }
 #pragma unroll
@@ -777,8 +779,8 @@ __global__ __launch_bounds__(kRegionThreads) void k_bfb_region(BuildArgs a) {
                 if (bb[u] != 0xFFFFFFFFu) {
                     uint32_t *wb = s_words + (bb[u] << wpb_shift);
 #pragma unroll
-                    for (int j = 0; j < kMaxK; ++j) {
-                        if (j < a.k) {
+                    for (int j = 0; j < KMAX; ++j) {
+                        if (j < (EXACT ? KMAX : a.k)) {
                             const uint32_t p = (gg[u] * bf_mult(j)) >> hs;
                             const uint32_t bit = 1u << (p & 31u);
                             if (!(w[u][j] & bit)) atomicOr(wb + (p >> 5), bit);
@@ -816,7 +818,12 @@ hipError_t launch_filter_build_stage(const BuildArgs &a, int stage, hipStream_t 
             break;
         case 3: {
             const uint32_t rgrid = nreg_max == 0 ? 1 : (nreg_max < 2048 ? nreg_max : 2048);
-            hipLaunchKernelGGL(k_bfb_region, dim3(rgrid), dim3(kRegionThreads), lds_region, s, a);
+            switch (a.k) {
+            case 2: hipLaunchKernelGGL((k_bfb_region<2, true>), dim3(rgrid), dim3(kRegionThreads), lds_region, s, a); break;
+            case 4: hipLaunchKernelGGL((k_bfb_region<4, true>), dim3(rgrid), dim3(kRegionThreads), lds_region, s, a); break;
+            case 6: hipLaunchKernelGGL((k_bfb_region<6, true>), dim3(rgrid), dim3(kRegionThreads), lds_region, s, a); break;
+            default: hipLaunchKernelGGL((k_bfb_region<kMaxK, false>), dim3(rgrid), dim3(kRegionThreads), lds_region, s, a); break;
+            }
             break;
         }
         default: return hipErrorInvalidValue;
