@@ -86,6 +86,15 @@ def test_config2_reduced(passes):
     run_and_compare(q, bits_per_key=8, k=6, passes=passes, seed=3)
 
 
+@pytest.mark.parametrize("k", [2, 4, 6])
+def test_exact_k_instances(k):
+    """The probe and build kernels have instances for k = 2, 4 and 6 with k fixed at
+    compile time (other k use a general instance); every filter word, survivor and tuple
+    against the oracle at 100K rows per relation (many tiles per scan)."""
+    q = W.config2(scale=0.01)
+    run_and_compare(q, bits_per_key=8, k=k, seed=9)
+
+
 def test_star_reduced():
     q = W.config3(scale=0.01)
     plan, tup = run_and_compare(q, bits_per_key=8, k=6, seed=5)
