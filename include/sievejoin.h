@@ -113,6 +113,15 @@ typedef struct {
  * of the default intersection walk (see sj_join). The result is the same; for
  * comparisons. */
 #define SJ_FLAG_BINARY_CYCLES 4u
+/* Failure injection, for tests of error handling: the named phase fails with
+ * SJ_ERR_DEVICE, as a failed HIP call would, before it enqueues anything (no device
+ * fault is involved). FILTERS: sj_build_filters; SIEVE: sj_sieve; JOIN: sj_join and
+ * sj_join_async; RESULT: sj_result and sj_result_async. A server query submitted with
+ * one of these fails alone, with that status, while the others finish. */
+#define SJ_FLAG_FAULT_FILTERS 8u
+#define SJ_FLAG_FAULT_SIEVE 16u
+#define SJ_FLAG_FAULT_JOIN 32u
+#define SJ_FLAG_FAULT_RESULT 64u
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
  * (a hipStream_t; NULL = the null stream). The stream stays caller-owned. */
@@ -121,7 +130,9 @@ sj_status sj_ctx_set_stream(sj_ctx *ctx, void *hip_stream);
 /* Release the caller's context. Plans made on it keep it alive: it is freed when the
  * caller has destroyed it and its last plan is destroyed, in either order (plans and
  * contexts may be released by a garbage collector in any order). The caller must not
- * use the handle after this call. */
+ * use the handle after this call. Plans enqueue on the context's stream only inside
+ * their own calls: once the caller has destroyed that stream, a plan made on the context
+ * may still be destroyed (also one attached to a filter catalogue), but not used. */
 sj_status sj_ctx_destroy(sj_ctx *ctx);
 /* Text of the context's last error ("" if none); valid until the next call on ctx. */
 const char *sj_last_error(const sj_ctx *ctx);
@@ -167,10 +178,37 @@ sj_status sj_sieve(sj_plan_t *plan, uint64_t *survivors);
  * plan for the count too. */
 sj_status sj_join(sj_plan_t *plan, uint64_t *count, uint64_t *checksum);
 
-/* Materialise the result: count * nrels int32 row ids, row-major, into out_dev
- * (room for capacity_tuples tuples). Fails with SJ_ERR_CAPACITY, writing nothing,
- * if capacity_tuples < count. Asynchronous. */
-sj_status sj_result(sj_plan_t *plan, int32_t *out_dev, uint64_t capacity_tuples);
+/* What sj_result writes per result tuple (Section 2.2: the join result itself; the
+ * paper reports results or their count, Section 3.1):
+ *   SJ_RIDS    one int32 row id per relation, in relation-index order (width nrels);
+ *   SJ_VALUES  the tuple's values: output column q is column c_q of relation r_q at the
+ *              tuple's row of r_q, for the projection (r_q, c_q) set by
+ *              sj_plan_set_projection (width = its length). The default projection is
+ *              every column of every relation, relations in index order.
+ * Value tuples are the row-id tuples with each row id replaced by the row's values, in
+ * the same order. */
+#define SJ_RIDS 0
+#define SJ_VALUES 1
+#define SJ_MAX_PROJ 32
+
+/* Materialise the result: count tuples, row-major, `width` int32 words each (see
+ * SJ_RIDS / SJ_VALUES), into out_dev (room for capacity_tuples tuples). Fails with
+ * SJ_ERR_CAPACITY, writing nothing, if capacity_tuples < count; SJ_ERR_UNSUPPORTED if
+ * the value projection has more than SJ_MAX_PROJ columns. Asynchronous. */
+sj_status sj_result(sj_plan_t *plan, int32_t *out_dev, uint64_t capacity_tuples, int32_t mode);
+
+/* Set the columns SJ_VALUES writes: n (relation, column) pairs in rel_col[0 .. 2n), host
+ * memory, copied (0 <= n <= SJ_MAX_PROJ; n = 0 restores the default). SJ_ERR_GRAPH for a
+ * relation or column that does not exist. */
+sj_status sj_plan_set_projection(sj_plan_t *plan, const int32_t *rel_col, int32_t n);
+
+/* Device memory a query needs, for admission by footprint (batching and serving):
+ * *workspace_bytes the plan's workspace (known after sj_plan); *width the int32 words per
+ * result tuple in `mode`; *result_bytes the result's size in `mode`, known once the count
+ * is on the host (after sj_join or sj_join_wait; else SJ_ERR_STATE). Any output pointer
+ * may be NULL. Host-only. */
+sj_status sj_plan_footprint(const sj_plan_t *plan, int32_t mode, uint64_t *workspace_bytes, uint64_t *result_bytes,
+                            int32_t *width);
 
 /* Asynchronous variant of the enumeration (Section 2.2 step 2), for callers that do
  * not need the count on the host before the tuples (a whole query then runs without
@@ -179,15 +217,16 @@ sj_status sj_result(sj_plan_t *plan, int32_t *out_dev, uint64_t capacity_tuples)
  * only. Other cyclic plans return SJ_ERR_UNSUPPORTED (their count needs a host step).
  *   sj_join_async    enqueues the count pass; the count stays on the device.
  *   sj_result_async  enqueues the materialisation into out_dev (room for
- *                    capacity_tuples tuples): the kernels read the count on the device
- *                    and write nothing if it exceeds the capacity.
+ *                    capacity_tuples tuples, in `mode` as for sj_result): the kernels
+ *                    read the count on the device and write nothing if it exceeds the
+ *                    capacity.
  *   sj_join_wait     waits for the stream and returns count and checksum; with
  *                    result_status != NULL, also SJ_ERR_CAPACITY if the last
  *                    sj_result_async found its buffer too small (nothing was written),
  *                    else SJ_OK.
  * After sj_join_async, sj_result (the synchronous call) needs sj_join_wait first. */
 sj_status sj_join_async(sj_plan_t *plan);
-sj_status sj_result_async(sj_plan_t *plan, int32_t *out_dev, uint64_t capacity_tuples);
+sj_status sj_result_async(sj_plan_t *plan, int32_t *out_dev, uint64_t capacity_tuples, int32_t mode);
 sj_status sj_join_wait(sj_plan_t *plan, uint64_t *count, uint64_t *checksum, sj_status *result_status);
 
 sj_status sj_plan_destroy(sj_plan_t *plan);
@@ -268,7 +307,11 @@ sj_status sj_profile_reset(sj_plan_t *plan);
  * workspace fits in the free arena; the oldest queued query that fits goes first, so
  * a later one may pass a query that does not fit yet. Once the exact count is known
  * the result's bytes are taken from the arena (SJ_ERR_CAPACITY if they can never fit
- * beside the workspace, SJ_ERR_NOMEM if no memory frees up within 2 s). The workspace
+ * beside the workspace, SJ_ERR_NOMEM if no memory frees up within 2 s). While a running
+ * query waits for its result's memory, no query is admitted; if every running query
+ * waits (their workspaces fill the arena), the one admitted last frees its workspace and
+ * goes back to the head of the queue, so the others can finish (it runs again later,
+ * with the same result). The workspace
  * is freed when the query finishes; the result stays until sj_server_release. When no
  * query is running and no queued query fits for 2 s (the arena is held by results not
  * yet released), the oldest queued query fails with SJ_ERR_NOMEM, so every query
@@ -285,8 +328,9 @@ sj_status sj_profile_reset(sj_plan_t *plan);
 #define SJ_QUERY_DONE 2
 #define SJ_QUERY_FAILED 3
 
-#define SJ_RESULT_TUPLES 0 /* materialise the tuples into the arena */
+#define SJ_RESULT_TUPLES 0 /* materialise the row-id tuples into the arena (SJ_RIDS) */
 #define SJ_RESULT_COUNT 1  /* count and checksum only */
+#define SJ_RESULT_VALUES 2 /* materialise the value tuples (SJ_VALUES, default projection) */
 
 typedef struct sj_server sj_server;
 
@@ -294,10 +338,11 @@ typedef struct {
     int32_t state;           /* SJ_QUERY_* */
     sj_status status;        /* SJ_OK, or the error that failed the query */
     uint64_t count, checksum;
-    uint64_t result_offset;  /* byte offset of the count * nrels int32 tuples in the arena (DONE, tuples) */
+    uint64_t result_offset;  /* byte offset of the count * width int32 words in the arena (DONE, tuples) */
     uint64_t workspace_bytes;
     int64_t t_submit_ns, t_admit_ns, t_done_ns; /* steady clock; 0 until reached */
     int32_t slot;            /* worker that ran it, -1 before admission */
+    int32_t requeues;        /* times it gave its workspace back (see below) and was queued again */
     char error[160];         /* why the query failed ("" otherwise) */
 } sj_query_info;
 

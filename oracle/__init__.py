@@ -15,6 +15,8 @@ What it computes (arXiv 2308.16370):
 * ``bf_*``       -- the blocked Bloom filter (Section 2.1 step 1, Bloom's bit vector
   in its cache-blocked form) under the hash/bit-pattern reading stated in
   ``oracle.c``.
+* ``project``    -- value tuples from row-id tuples (the join result as values, each
+  row id replaced by its row's values in the chosen columns).
 * ``triangle_cycles`` -- count and checksum of the directed 3-cycle query by
   adjacency intersection (a textbook triangle count), independent of ``hash_join``.
 * ``sieve``      -- the pruning phase (Section 2.2): one backward pass from the
@@ -333,6 +335,23 @@ def triangle_cycles(src: np.ndarray, dst: np.ndarray, e1: Optional[Tuple[np.ndar
                                  ctypes.byref(chk)) != 0:
         raise MemoryError("orc_triangle_cycles")
     return int(cnt.value), int(chk.value)
+
+
+def default_projection(query) -> List[Tuple[int, int]]:
+    """Every column of every relation, relations in index order."""
+    return [(r, c) for r, rel in enumerate(query.rels) for c in range(len(rel.cols))]
+
+
+def project(query, tuples: np.ndarray, cols: Optional[Sequence[Tuple[int, int]]] = None) -> np.ndarray:
+    """Value tuples of a [count, nrels] row-id result: output column q holds column
+    cols[q][1] of relation cols[q][0] at the tuple's row of that relation (the join
+    result of Section 2.2 as values rather than row ids; default: every column of every
+    relation, relations in index order). int32 [count, len(cols)]."""
+    cols = default_projection(query) if cols is None else list(cols)
+    out = np.empty((tuples.shape[0], len(cols)), dtype=np.int32)
+    for q, (r, c) in enumerate(cols):
+        out[:, q] = np.asarray(query.rels[r].cols[c], dtype=np.int32)[tuples[:, r].astype(np.int64)]
+    return out
 
 
 def checksum_of(tuples: np.ndarray) -> int:

@@ -49,13 +49,17 @@ EXPORTED = ["sj_ctx_create", "sj_ctx_set_stream", "sj_ctx_destroy", "sj_last_err
             "sj_server_query", "sj_server_release", "sj_server_stats", "sj_server_last_error",
             "sj_server_destroy", "sj_fcache_create", "sj_plan_use_filter_cache", "sj_plan_filter_cached",
             "sj_fcache_invalidate", "sj_fcache_clear", "sj_fcache_stats", "sj_fcache_destroy",
-            "sj_server_use_filter_cache", "sj_filter_probe", "sj_filter_insert"]
+            "sj_server_use_filter_cache", "sj_filter_probe", "sj_filter_insert", "sj_plan_set_projection",
+            "sj_plan_footprint"]
 SJ_FLAG_PROFILE = 1
 SJ_FLAG_EAGER = 2
 SJ_FLAG_BINARY_CYCLES = 4
+SJ_FLAG_FAULT_FILTERS, SJ_FLAG_FAULT_SIEVE, SJ_FLAG_FAULT_JOIN, SJ_FLAG_FAULT_RESULT = 8, 16, 32, 64
+SJ_RIDS, SJ_VALUES = 0, 1
+SJ_MAX_PROJ = 32
 SJ_MAX_SLOTS = 16
 SJ_QUERY_QUEUED, SJ_QUERY_RUNNING, SJ_QUERY_DONE, SJ_QUERY_FAILED = 0, 1, 2, 3
-SJ_RESULT_TUPLES, SJ_RESULT_COUNT = 0, 1
+SJ_RESULT_TUPLES, SJ_RESULT_COUNT, SJ_RESULT_VALUES = 0, 1, 2
 
 
 class SjError(RuntimeError):
@@ -86,7 +90,7 @@ class _QueryInfo(ctypes.Structure):
                 ("checksum", ctypes.c_uint64), ("result_offset", ctypes.c_uint64),
                 ("workspace_bytes", ctypes.c_uint64), ("t_submit_ns", ctypes.c_int64),
                 ("t_admit_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64), ("slot", ctypes.c_int32),
-                ("error", ctypes.c_char * 160)]
+                ("requeues", ctypes.c_int32), ("error", ctypes.c_char * 160)]
 
 
 class _FcInfo(ctypes.Structure):
@@ -115,9 +119,9 @@ def lib():
             "sj_build_filters": [V],
             "sj_sieve": [V, P(u64)],
             "sj_join": [V, P(u64), P(u64)],
-            "sj_result": [V, V, u64],
+            "sj_result": [V, V, u64, i32],
             "sj_join_async": [V],
-            "sj_result_async": [V, V, u64],
+            "sj_result_async": [V, V, u64, i32],
             "sj_join_wait": [V, P(u64), P(u64), P(i32)],
             "sj_plan_destroy": [V],
             "sj_filter_count": [V, P(i32)],
@@ -144,6 +148,8 @@ def lib():
             "sj_server_use_filter_cache": [V, V],
             "sj_filter_probe": [V, i32, V, u64, V, P(u64)],
             "sj_filter_insert": [V, i32, V, u64, V, P(u64)],
+            "sj_plan_set_projection": [V, V, i32],
+            "sj_plan_footprint": [V, i32, P(u64), P(u64), P(i32)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -226,7 +232,8 @@ class Plan:
     def __init__(self, ctx: Context, rels: Sequence[Rel], edges: Sequence[Tuple[int, int, int, int]],
                  bits_per_key: int = 0, k: int = 0, block_bits: int = 0, passes: int = 0, seed: int = 0,
                  root: int = -1, workspace: Optional[torch.Tensor] = None, profile: bool = False,
-                 eager: bool = False, filter_cache: "Optional[FilterCache]" = None, binary_cycles: bool = False):
+                 eager: bool = False, filter_cache: "Optional[FilterCache]" = None, binary_cycles: bool = False,
+                 flags: int = 0):
         self.ctx = ctx
         self.block_bits = block_bits or 512
         self.nrels = len(rels)
@@ -235,7 +242,7 @@ class Plan:
         arr, earr, self._keep = _marshal(rels, edges)
         opts = _Opts(bits_per_key, k, block_bits, passes, seed & (2**64 - 1), root,
                      (SJ_FLAG_PROFILE if profile else 0) | (SJ_FLAG_EAGER if eager else 0) |
-                     (SJ_FLAG_BINARY_CYCLES if binary_cycles else 0))
+                     (SJ_FLAG_BINARY_CYCLES if binary_cycles else 0) | flags)
         wsb = ctypes.c_uint64()
         ctx._check(lib().sj_plan(ctx.handle, arr, len(rels), earr, len(edges), ctypes.byref(opts),
                                  ctypes.byref(self.handle), ctypes.byref(wsb)))
@@ -288,11 +295,12 @@ class Plan:
         self._check(lib().sj_join_async(self.handle))
         self.count = None
 
-    def result_async(self, out: torch.Tensor) -> torch.Tensor:
-        """Enqueue the materialisation into `out` (int32 [capacity, nrels]); nothing is
+    def result_async(self, out: torch.Tensor, mode: int = SJ_RIDS) -> torch.Tensor:
+        """Enqueue the materialisation into `out` (int32 [capacity, width]); nothing is
         written if the result does not fit (join_wait reports it)."""
-        cap = out.numel() // max(1, self.nrels)
-        self._check(lib().sj_result_async(self.handle, ctypes.c_void_p(out.data_ptr() if out.numel() else 0), cap))
+        cap = out.numel() // max(1, self.width(mode))
+        self._check(lib().sj_result_async(self.handle, ctypes.c_void_p(out.data_ptr() if out.numel() else 0), cap,
+                                          mode))
         return out
 
     def join_wait(self) -> Tuple[int, int, int]:
@@ -302,14 +310,36 @@ class Plan:
         self.count, self.checksum = int(c.value), int(k.value)
         return self.count, self.checksum, int(st.value)
 
-    def result(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    def result(self, out: Optional[torch.Tensor] = None, mode: int = SJ_RIDS) -> torch.Tensor:
+        """The result tuples: int32 [count, nrels] row ids (SJ_RIDS) or [count, width]
+        projected values (SJ_VALUES, see set_projection)."""
         if self.count is None:
             raise SjError(SJ_ERR_STATE, "call join() first")
+        w = self.width(mode)
         if out is None:
-            out = torch.empty((self.count, self.nrels), dtype=torch.int32, device="cuda:%d" % self.ctx.device)
-        cap = out.numel() // max(1, self.nrels)
-        self._check(lib().sj_result(self.handle, ctypes.c_void_p(out.data_ptr() if out.numel() else 0), cap))
+            out = torch.empty((self.count, w), dtype=torch.int32, device="cuda:%d" % self.ctx.device)
+        cap = out.numel() // max(1, w)
+        self._check(lib().sj_result(self.handle, ctypes.c_void_p(out.data_ptr() if out.numel() else 0), cap, mode))
         return out
+
+    def set_projection(self, cols: Sequence[Tuple[int, int]]) -> None:
+        """Columns SJ_VALUES writes: (relation, column) pairs ([] = every column of every relation)."""
+        flat = (ctypes.c_int32 * max(1, 2 * len(cols)))(*[int(x) for rc in cols for x in rc])
+        self._check(lib().sj_plan_set_projection(self.handle, flat, len(cols)))
+
+    def width(self, mode: int = SJ_RIDS) -> int:
+        w = ctypes.c_int32()
+        self._check(lib().sj_plan_footprint(self.handle, mode, None, None, ctypes.byref(w)))
+        return int(w.value)
+
+    def footprint(self, mode: int = SJ_RIDS) -> dict:
+        """Workspace bytes, result width and (once counted) result bytes in `mode`."""
+        ws, rb, w = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int32()
+        code = lib().sj_plan_footprint(self.handle, mode, ctypes.byref(ws), ctypes.byref(rb), ctypes.byref(w))
+        if code not in (SJ_OK, SJ_ERR_STATE):
+            self._check(code)
+        return {"workspace_bytes": int(ws.value), "width": int(w.value),
+                "result_bytes": int(rb.value) if code == SJ_OK else None}
 
     def run(self) -> Tuple[int, int, torch.Tensor]:
         self.build_filters()
@@ -462,15 +492,19 @@ class Server:
 
     def submit(self, rels: Sequence[Rel], edges: Sequence[Tuple[int, int, int, int]], bits_per_key: int = 0,
                k: int = 0, block_bits: int = 0, passes: int = 0, seed: int = 0, root: int = -1,
-               count_only: bool = False) -> int:
+               count_only: bool = False, values: bool = False, flags: int = 0) -> int:
+        """Queue a query; its result is row ids (default), values (all columns of every
+        relation, relation order) or the count only."""
         arr, earr, keep = _marshal(rels, edges)
-        opts = _Opts(bits_per_key, k, block_bits, passes, seed & (2**64 - 1), root, 0)
+        opts = _Opts(bits_per_key, k, block_bits, passes, seed & (2**64 - 1), root, flags)
         t = ctypes.c_uint64()
+        mode = SJ_RESULT_COUNT if count_only else (SJ_RESULT_VALUES if values else SJ_RESULT_TUPLES)
         code = lib().sj_server_submit(self.handle, arr, len(rels), earr, len(edges), ctypes.byref(opts),
-                                      SJ_RESULT_COUNT if count_only else SJ_RESULT_TUPLES, ctypes.byref(t))
+                                      mode, ctypes.byref(t))
         if code != SJ_OK:
             raise SjError(code, (lib().sj_server_last_error(self.handle) or b"").decode())
-        self._alive[int(t.value)] = (list(rels), len(rels), keep)
+        width = sum(len(r.cols) for r in rels) if values else len(rels)
+        self._alive[int(t.value)] = (list(rels), width, keep)
         return int(t.value)
 
     def info(self, ticket: int, wait: bool = False) -> dict:
@@ -481,18 +515,18 @@ class Server:
         return {"state": q.state, "status": q.status, "count": int(q.count), "checksum": int(q.checksum),
                 "result_offset": int(q.result_offset), "workspace_bytes": int(q.workspace_bytes),
                 "t_submit_ns": int(q.t_submit_ns), "t_admit_ns": int(q.t_admit_ns), "t_done_ns": int(q.t_done_ns),
-                "slot": int(q.slot), "error": q.error.decode()}
+                "slot": int(q.slot), "requeues": int(q.requeues), "error": q.error.decode()}
 
     def result(self, ticket: int) -> torch.Tensor:
         q = self.info(ticket, wait=True)
         if q["state"] != SJ_QUERY_DONE:
             raise SjError(q["status"], q["error"])
-        nrels = self._alive[ticket][1]
-        n = q["count"] * nrels
+        width = self._alive[ticket][1]
+        n = q["count"] * width
         if n == 0:
-            return torch.empty((0, nrels), dtype=torch.int32, device=self.arena.device)
+            return torch.empty((0, width), dtype=torch.int32, device=self.arena.device)
         off = q["result_offset"]
-        return self.arena[off: off + 4 * n].view(torch.int32).view(q["count"], nrels)
+        return self.arena[off: off + 4 * n].view(torch.int32).view(q["count"], width)
 
     def use_filter_cache(self, cache: Optional[FilterCache]) -> None:
         """Attach every query admitted from now on to `cache` (None: none)."""

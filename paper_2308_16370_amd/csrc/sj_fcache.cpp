@@ -7,8 +7,8 @@
 // ("published"). Unreferenced published entries are evicted least recently used
 // first when an allocation fails. Entries that are no longer visible (invalidated,
 // cleared, or private duplicates) are freed once unreferenced and once the device
-// work of every plan that used them has finished (each release records an event on
-// the releasing plan's stream).
+// work of every plan that used them has finished (each release hands over an event the
+// releasing plan recorded after its last use of the entry).
 #include "sj_fcache.h"
 
 #include <algorithm>
@@ -26,7 +26,7 @@ struct FcEntry {
     int refs = 0;
     bool published = false;
     hipEvent_t ready = nullptr;
-    std::vector<hipEvent_t> done;   // releasing plans' work on the entry
+    std::vector<FcEventRef> done;   // releasing plans' last uses of the entry
     uint64_t last_use = 0;
 };
 
@@ -52,12 +52,10 @@ constexpr uint64_t kHeader = 256;
 // Called with the lock held. `wait`: block until the entry's users are done; otherwise
 // free only if they already are. Returns whether the entry was freed.
 bool free_entry(sj_fcache *c, FcEntry *e, bool wait) {
-    for (hipEvent_t ev : e->done)
-        if (!wait && hipEventQuery(ev) == hipErrorNotReady) return false;
-    for (hipEvent_t ev : e->done) {
-        (void)hipEventSynchronize(ev);
-        (void)hipEventDestroy(ev);
-    }
+    for (const sj::FcEventRef &ev : e->done)
+        if (!wait && hipEventQuery(ev->ev) == hipErrorNotReady) return false;
+    for (const sj::FcEventRef &ev : e->done) (void)hipEventSynchronize(ev->ev);
+    e->done.clear();
     if (e->ready) {
         (void)hipEventSynchronize(e->ready);
         (void)hipEventDestroy(e->ready);
@@ -157,25 +155,12 @@ sj_status fc_publish(sj_fcache *c, FcEntry *e, hipStream_t stream) {
     return SJ_OK;
 }
 
-void fc_release(sj_fcache *c, FcEntry *e, hipStream_t stream) {
+void fc_release(sj_fcache *c, FcEntry *e, const FcEventRef &last_use) {
     std::lock_guard<std::mutex> lk(c->mu);
-    hipEvent_t ev = nullptr;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
-        if (hipEventRecord(ev, stream) == hipSuccess) {
-            e->done.push_back(ev);
-        } else {
-            (void)hipStreamSynchronize(stream);   // no event: the work is finished instead
-            (void)hipEventDestroy(ev);
-        }
-    } else {
-        (void)hipStreamSynchronize(stream);
-    }
-    // keep only the events of work still in flight
-    auto keep = std::remove_if(e->done.begin(), e->done.end(), [](hipEvent_t x) {
-        if (hipEventQuery(x) != hipSuccess) return false;
-        (void)hipEventDestroy(x);
-        return true;
-    });
+    if (last_use && std::find(e->done.begin(), e->done.end(), last_use) == e->done.end()) e->done.push_back(last_use);
+    // keep only the uses still in flight
+    auto keep = std::remove_if(e->done.begin(), e->done.end(),
+                               [](const FcEventRef &x) { return hipEventQuery(x->ev) == hipSuccess; });
     e->done.erase(keep, e->done.end());
     --e->refs;
     if (e->refs == 0 && !e->published) free_entry(c, e, false);

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -14,6 +15,19 @@
 namespace sj {
 
 struct FcEntry;
+
+// An event shared between a plan, which records its last use of catalogue entries on
+// it, and the entries the plan has released, which keep it until that work is done.
+struct FcEvent {
+    hipEvent_t ev = nullptr;
+    FcEvent() = default;
+    FcEvent(const FcEvent &) = delete;
+    FcEvent &operator=(const FcEvent &) = delete;
+    ~FcEvent() {
+        if (ev) (void)hipEventDestroy(ev);
+    }
+};
+using FcEventRef = std::shared_ptr<FcEvent>;
 
 struct FcGrant {
     FcEntry *entry = nullptr;   // null: not cached (no room)
@@ -31,9 +45,10 @@ FcGrant fc_acquire(sj_fcache *c, const std::string &sig, uint64_t max_words, con
 // entry visible to later lookups (unless an equal entry was published meanwhile, in
 // which case it stays private to the producer).
 sj_status fc_publish(sj_fcache *c, FcEntry *e, hipStream_t stream);
-// Drop a plan's reference. Work the plan enqueued on `stream` may still read the
-// entry; its memory is reused only after that work is done.
-void fc_release(sj_fcache *c, FcEntry *e, hipStream_t stream);
+// Drop a plan's reference. `last_use` (recorded after the plan's last work that may read
+// the entry; null if it enqueued none) must complete before the entry's memory is reused.
+// No stream is touched: the plan's stream may be gone by now.
+void fc_release(sj_fcache *c, FcEntry *e, const FcEventRef &last_use);
 int fc_device(const sj_fcache *c);
 
 }  // namespace sj

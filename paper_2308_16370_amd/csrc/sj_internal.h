@@ -222,6 +222,15 @@ hipError_t launch_dp(const DpArgs &a, hipStream_t s);
 // (position 0 is the root); its entries are the root's survivor list or a bucketed
 // relation's entries in bucket order.
 constexpr int kMatMaxRels = 16;
+// What the materialisation writes per tuple: row ids (n = 0: one per relation, in
+// relation-index order) or projected values (n columns: output column q is column
+// col[q] of relation rel[q] at the tuple's row of that relation).
+constexpr int kMaxProj = 32;
+struct Projection {
+    int n;
+    int rel[kMaxProj];
+    const int32_t *col[kMaxProj];
+};
 struct MatArgs {
     int nrels;
     int order[kMatMaxRels];        // relation index at each position
@@ -237,6 +246,7 @@ struct MatArgs {
     const uint64_t *count_dev;     // device-side total, or nullptr
     uint64_t capacity;             // tuples `out` holds: nothing is written if the total exceeds it
     int32_t *out;
+    Projection proj;               // row ids (proj.n = 0) or projected values
 };
 // Grid: enough blocks for min(count, capacity) tuples when the count is on the host;
 // a fixed persistent grid over the output when it is read on the device.

@@ -740,7 +740,11 @@ constexpr int mat_chunk() {
 // distinct banks); a leaf step then needs no memory access. The copy-out turns
 // entries into row ids with independent gathers and writes the tile with coalesced
 // 16-byte stores.
-template <int N>
+//
+// VAL: the copy-out writes projected values instead of row ids (a.proj.n columns per
+// tuple): output column q reads relation a.proj.rel[q]'s entry from the tile, its row
+// id, then that row's value in column a.proj.col[q].
+template <int N, bool VAL>
 __global__ __launch_bounds__(256) void k_materialize(MatArgs a) {
     constexpr int C = mat_chunk<N>();
     constexpr uint32_t ROW = C * N, PITCH = ROW + 1;
@@ -750,6 +754,8 @@ __global__ __launch_bounds__(256) void k_materialize(MatArgs a) {
     __shared__ uint32_t s_out[256 * PITCH];
     __shared__ uint32_t s_r[2];
     __shared__ const uint32_t *s_rid[N];   // row ids of output column q's position
+    __shared__ const int32_t *s_pcol[VAL ? kMaxProj : 1];
+    __shared__ uint32_t s_prel[VAL ? kMaxProj : 1];
     const uint64_t count = a.count_dev ? *a.count_dev : a.count;
     if (count > a.capacity) return;         // the caller's buffer is too small: write nothing
     const uint32_t root_n = *a.root_n;
@@ -757,6 +763,12 @@ __global__ __launch_bounds__(256) void k_materialize(MatArgs a) {
     if (threadIdx.x == 64) {
 #pragma unroll
         for (int x = 0; x < N; ++x) s_rid[a.order[x]] = a.rid[x];
+    }
+    if constexpr (VAL) {
+        if (threadIdx.x < static_cast<uint32_t>(a.proj.n)) {
+            s_pcol[threadIdx.x] = a.proj.col[threadIdx.x];
+            s_prel[threadIdx.x] = static_cast<uint32_t>(a.proj.rel[threadIdx.x]);
+        }
     }
     for (uint64_t blk = blockIdx.x; blk * PER < count; blk += gridDim.x) {
         const uint64_t t0 = blk * PER;
@@ -796,14 +808,26 @@ __global__ __launch_bounds__(256) void k_materialize(MatArgs a) {
         }
         __syncthreads();
         // word w of the block's output is word w % ROW of thread w / ROW's row
-        const uint64_t words = (t1 - t0) * N;
-        int32_t *dst = a.out + t0 * N;
+        const uint32_t W = VAL ? static_cast<uint32_t>(a.proj.n) : N;   // output words per tuple
+        const uint64_t words = (t1 - t0) * W;
+        int32_t *dst = a.out + t0 * W;
         for (uint32_t w = threadIdx.x * 4; w < words; w += 256 * 4) {
             int32_t v[4];
     #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const uint32_t ww = w + j;
-                v[j] = ww < words ? static_cast<int32_t>(s_rid[ww % N][s_out[(ww / ROW) * PITCH + ww % ROW]]) : 0;
+                if constexpr (VAL) {
+                    if (ww < words) {
+                        const uint32_t t = ww / W, q = ww - t * W, rel = s_prel[q];
+                        const uint32_t rid = s_rid[rel][s_out[(t / C) * PITCH + (t % C) * N + rel]];
+                        v[j] = s_pcol[q][rid];
+                    } else {
+                        v[j] = 0;
+                    }
+                } else {
+                    v[j] = ww < words ? static_cast<int32_t>(s_rid[ww % N][s_out[(ww / ROW) * PITCH + ww % ROW]])
+                                      : 0;
+                }
             }
             if (w + 4 <= words) {
                 *reinterpret_cast<int4 *>(dst + w) = make_int4(v[0], v[1], v[2], v[3]);
@@ -832,9 +856,16 @@ hipError_t launch_materialize(const MatArgs &a, hipStream_t s) {
     if (a.count_dev && blocks64 > kMatPersistentBlocks) blocks64 = kMatPersistentBlocks;
     if (blocks64 > 0x7fffffffull) return hipErrorInvalidValue;
     const dim3 g(static_cast<uint32_t>(blocks64));
+    if (a.proj.n < 0 || a.proj.n > kMaxProj) return hipErrorInvalidValue;
+    const bool val = a.proj.n > 0;
     switch (a.nrels) {
-#define SJ_MAT_CASE(NN) \
-    case NN: hipLaunchKernelGGL(k_materialize<NN>, g, dim3(256), 0, s, a); break;
+#define SJ_MAT_CASE(NN)                                                               \
+    case NN:                                                                          \
+        if (val)                                                                      \
+            hipLaunchKernelGGL((k_materialize<NN, true>), g, dim3(256), 0, s, a);     \
+        else                                                                          \
+            hipLaunchKernelGGL((k_materialize<NN, false>), g, dim3(256), 0, s, a);    \
+        break;
         SJ_MAT_CASE(1) SJ_MAT_CASE(2) SJ_MAT_CASE(3) SJ_MAT_CASE(4) SJ_MAT_CASE(5) SJ_MAT_CASE(6) SJ_MAT_CASE(7)
         SJ_MAT_CASE(8) SJ_MAT_CASE(9) SJ_MAT_CASE(10) SJ_MAT_CASE(11) SJ_MAT_CASE(12) SJ_MAT_CASE(13)
         SJ_MAT_CASE(14) SJ_MAT_CASE(15) SJ_MAT_CASE(16)
@@ -926,12 +957,25 @@ __global__ __launch_bounds__(256) void k_cyclic(CycArgs a) {
             uint32_t r0, r1;
             cyc_run<N>(a, st, r0, r1);
             if (r1 > r0) {
-                if (WRITE) {
+                if (WRITE && a.m.proj.n == 0) {
                     for (uint32_t j = r0; j < r1; ++j, ++o) {
                         int32_t *dst = a.out + o * a.nrels;
 #pragma unroll
                         for (int x = 0; x < N; ++x) dst[a.m.order[x]] = static_cast<int32_t>(a.m.rid[x][st.e[x]]);
                         dst[a.L_rel] = static_cast<int32_t>(a.Lrid[j]);
+                    }
+                } else if (WRITE) {   // projected values
+                    const uint32_t W = static_cast<uint32_t>(a.m.proj.n);
+                    for (uint32_t j = r0; j < r1; ++j, ++o) {
+                        int32_t *dst = a.out + o * W;
+                        for (uint32_t q = 0; q < W; ++q) {
+                            const int rel = a.m.proj.rel[q];
+                            uint32_t rid = a.Lrid[j];
+#pragma unroll
+                            for (int x = 0; x < N; ++x)
+                                if (a.m.order[x] == rel) rid = a.m.rid[x][st.e[x]];
+                            dst[q] = a.m.proj.col[q][rid];
+                        }
                     }
                 } else {
                     cnt += r1 - r0;

@@ -172,6 +172,11 @@ struct sj_plan_s {
     // filter catalogue (sj_plan_use_filter_cache)
     sj_fcache *fcache = nullptr;
     std::vector<hipEvent_t> fc_wait;     // readiness of reused entries not yet seen complete
+    // recorded on the context's stream after each call that may read or write catalogue
+    // entries, and handed to the catalogue when the plan lets go of them, so that releasing
+    // them never touches the stream (which the caller may have destroyed by then)
+    FcEventRef fc_last_use;
+    bool fc_used = false;
     void fc_detach();
     struct ProfAcc {
         std::string label;
@@ -197,8 +202,12 @@ struct sj_plan_s {
     // asynchronous count / result (sj_join_async, sj_result_async, sj_join_wait)
     bool count_on_host = false;          // p->count / p->checksum hold the last count pass
     bool async_result = false;           // a materialisation with a device-side count is queued
-    int32_t *res_out = nullptr;          // its buffer and capacity (the recorded graph uses them)
+    int32_t *res_out = nullptr;          // its buffer, capacity and mode (the recorded graph uses them)
     uint64_t res_cap = 0;
+    int32_t res_mode = SJ_RIDS;
+    // columns written per tuple in SJ_VALUES mode (relation, column); empty: every column
+    // of every relation, relations in index order
+    std::vector<std::pair<int, int>> proj;
     void drop_graphs();
     ~sj_plan_s();
 };
@@ -211,8 +220,9 @@ void sj_plan_s::drop_graphs() {
 }
 
 void sj_plan_s::fc_detach() {
+    const FcEventRef none;
     for (auto &f : filters) {
-        if (f.fc) fc_release(fcache, f.fc, ctx->stream);
+        if (f.fc) fc_release(fcache, f.fc, fc_used ? fc_last_use : none);
         f.fc = nullptr;
         f.ext_words = f.ext_nblocks = nullptr;
         f.fc_how = 0;
@@ -220,6 +230,20 @@ void sj_plan_s::fc_detach() {
     }
     fc_wait.clear();
     fcache = nullptr;
+    fc_last_use.reset();
+    fc_used = false;
+}
+
+// After a call that enqueued work which may use catalogue entries: record its end.
+static sj_status fc_mark_use(sj_plan_t *p) {
+    if (!p->fcache) return SJ_OK;
+    if (hipEventRecord(p->fc_last_use->ev, p->ctx->stream) != hipSuccess) {
+        // no record of the work: wait for it, so that releasing the entries is safe
+        if (hipStreamSynchronize(p->ctx->stream) != hipSuccess) return SJ_ERR_DEVICE;
+        return SJ_OK;
+    }
+    p->fc_used = true;
+    return SJ_OK;
 }
 
 sj_plan_s::~sj_plan_s() {
@@ -665,7 +689,9 @@ extern "C" sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, con
         return fail(ctx, SJ_ERR_INVALID, "block_bits must be 256, 512 or 1024");
     if (o.passes != 1 && o.passes != 2) return fail(ctx, SJ_ERR_INVALID, "passes must be 1 or 2");
     if (o.root >= nrels) return fail(ctx, SJ_ERR_INVALID, "root out of range");
-    if (o.flags & ~static_cast<uint32_t>(SJ_FLAG_PROFILE | SJ_FLAG_EAGER | SJ_FLAG_BINARY_CYCLES))
+    if (o.flags & ~static_cast<uint32_t>(SJ_FLAG_PROFILE | SJ_FLAG_EAGER | SJ_FLAG_BINARY_CYCLES |
+                                         SJ_FLAG_FAULT_FILTERS | SJ_FLAG_FAULT_SIEVE | SJ_FLAG_FAULT_JOIN |
+                                         SJ_FLAG_FAULT_RESULT))
         return fail(ctx, SJ_ERR_INVALID, "unknown flags");
 
     sj_plan_t *p = new (std::nothrow) sj_plan_t;
@@ -1002,6 +1028,12 @@ static sj_status zero_region(sj_plan_t *p, int ph) {
     return SJ_OK;
 }
 
+// Failure injection (SJ_FLAG_FAULT_*): the phase fails before it enqueues anything.
+static sj_status injected(sj_plan_t *p, uint32_t flag, const char *phase) {
+    if (!(p->opts.flags & flag)) return SJ_OK;
+    return fail(p->ctx, SJ_ERR_DEVICE, "%s failed: injected failure (SJ_FLAG_FAULT_*)", phase);
+}
+
 static sj_status check_exec(sj_plan_t *p, int need) {
     if (!p) return SJ_ERR_INVALID;
     if (p->state < need) {
@@ -1111,6 +1143,7 @@ static sj_status enqueue_build(sj_plan_t *p) {
 
 extern "C" sj_status sj_build_filters(sj_plan_t *p) {
     if (sj_status st = check_exec(p, kBound)) return st;
+    if (sj_status st = injected(p, SJ_FLAG_FAULT_FILTERS, "sj_build_filters")) return st;
     // reused catalogue entries: wait for their producers' builds (once seen complete, never again)
     for (size_t i = 0; i < p->fc_wait.size();) {
         if (hipEventQuery(p->fc_wait[i]) == hipSuccess) {
@@ -1134,6 +1167,7 @@ extern "C" sj_status sj_build_filters(sj_plan_t *p) {
         (void)hipGraphExecDestroy(p->gexec[0]);
         p->gexec[0] = nullptr;
     }
+    if (sj_status st = fc_mark_use(p)) return fail(p->ctx, st, "could not record the use of catalogue entries");
     p->state = kFiltered;
     return SJ_OK;
 }
@@ -1145,7 +1179,9 @@ static sj_status enqueue_sieve(sj_plan_t *p) {
 
 extern "C" sj_status sj_sieve(sj_plan_t *p, uint64_t *survivors) {
     if (sj_status st = check_exec(p, kFiltered)) return st;
+    if (sj_status st = injected(p, SJ_FLAG_FAULT_SIEVE, "sj_sieve")) return st;
     if (sj_status st = run_phase(p, 1, enqueue_sieve)) return st;
+    if (sj_status st = fc_mark_use(p)) return fail(p->ctx, st, "could not record the use of catalogue entries");
     p->state = kSieved;
     if (survivors) {
         std::vector<uint32_t> c(p->n);
@@ -1467,6 +1503,7 @@ static sj_status binary_cyclic_count(sj_plan_t *p, uint64_t tot[2]) {
 
 extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) {
     if (sj_status st = check_exec(p, kSieved)) return st;
+    if (sj_status st = injected(p, SJ_FLAG_FAULT_JOIN, "sj_join")) return st;
     if (!p->cyc_ok)
         return fail(p->ctx, SJ_ERR_UNSUPPORTED,
                     "cyclic join: every closing edge must end at the last relation of the preorder (relation %d), "
@@ -1498,6 +1535,7 @@ extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) 
 
 extern "C" sj_status sj_join_async(sj_plan_t *p) {
     if (sj_status st = check_exec(p, kSieved)) return st;
+    if (sj_status st = injected(p, SJ_FLAG_FAULT_JOIN, "sj_join_async")) return st;
     if (!p->cyc_ok || (p->cyclic && !p->tri))
         return fail(p->ctx, SJ_ERR_UNSUPPORTED, "this cyclic join counts in two host-driven steps: use sj_join");
     p->cyc_counted = false;
@@ -1508,26 +1546,59 @@ extern "C" sj_status sj_join_async(sj_plan_t *p) {
     return SJ_OK;
 }
 
+// Output words per tuple in `mode`: one row id per relation, or the projection's columns.
+static int result_width(const sj_plan_t *p, int32_t mode) {
+    if (mode == SJ_RIDS) return p->n;
+    if (!p->proj.empty()) return static_cast<int>(p->proj.size());
+    int w = 0;
+    for (const Rel &R : p->rels) w += static_cast<int>(R.cols.size());
+    return w;
+}
+
+// The materialisation's output description for `mode` (row ids: proj.n = 0).
+static sj_status projection_of(sj_plan_t *p, int32_t mode, Projection &pr) {
+    pr = Projection{};
+    if (mode == SJ_RIDS) return SJ_OK;
+    if (mode != SJ_VALUES) return fail(p->ctx, SJ_ERR_INVALID, "mode must be SJ_RIDS or SJ_VALUES");
+    std::vector<std::pair<int, int>> cols = p->proj;
+    if (cols.empty())
+        for (int r = 0; r < p->n; ++r)
+            for (size_t c = 0; c < p->rels[r].cols.size(); ++c) cols.emplace_back(r, static_cast<int>(c));
+    if (cols.size() > static_cast<size_t>(kMaxProj))
+        return fail(p->ctx, SJ_ERR_UNSUPPORTED, "a value projection of %zu columns (at most %d; see sj_plan_set_projection)",
+                    cols.size(), kMaxProj);
+    pr.n = static_cast<int>(cols.size());
+    for (int q = 0; q < pr.n; ++q) {
+        pr.rel[q] = cols[q].first;
+        pr.col[q] = p->rels[cols[q].first].cols[cols[q].second];
+    }
+    return SJ_OK;
+}
+
 static sj_status enqueue_result_async(sj_plan_t *p) {
     MatArgs m = mat_args(p, p->n);
     m.count_dev = at<uint64_t>(p, p->off_totals);
     m.capacity = p->res_cap;
     m.out = p->res_out;
+    if (sj_status st = projection_of(p, p->res_mode, m.proj)) return st;
     ProfScope ps(p, "materialize", -1, kProfResult);
     SJ_HIP(p->ctx, launch_materialize(m, p->ls));
     return SJ_OK;
 }
 
-extern "C" sj_status sj_result_async(sj_plan_t *p, int32_t *out, uint64_t capacity) {
+extern "C" sj_status sj_result_async(sj_plan_t *p, int32_t *out, uint64_t capacity, int32_t mode) {
     if (sj_status st = check_exec(p, kJoined)) return st;
+    if (sj_status st = injected(p, SJ_FLAG_FAULT_RESULT, "sj_result_async")) return st;
     if (p->cyclic) return fail(p->ctx, SJ_ERR_UNSUPPORTED, "cyclic joins: use sj_result");
+    if (mode != SJ_RIDS && mode != SJ_VALUES) return fail(p->ctx, SJ_ERR_INVALID, "mode must be SJ_RIDS or SJ_VALUES");
     if (capacity && !out) return fail(p->ctx, SJ_ERR_INVALID, "null output buffer");
     if (reinterpret_cast<uintptr_t>(out) % 16) return fail(p->ctx, SJ_ERR_INVALID, "output must be 16-byte aligned");
-    if (out != p->res_out || capacity != p->res_cap) {   // the recorded launch names the buffer
+    if (out != p->res_out || capacity != p->res_cap || mode != p->res_mode) {   // the recorded launch names them
         if (p->gexec[3]) (void)hipGraphExecDestroy(p->gexec[3]);
         p->gexec[3] = nullptr;
         p->res_out = out;
         p->res_cap = capacity;
+        p->res_mode = mode;
     }
     if (sj_status st = run_phase(p, 3, enqueue_result_async)) return st;
     p->async_result = true;
@@ -1553,8 +1624,11 @@ extern "C" sj_status sj_join_wait(sj_plan_t *p, uint64_t *count, uint64_t *check
     return SJ_OK;
 }
 
-extern "C" sj_status sj_result(sj_plan_t *p, int32_t *out, uint64_t capacity) {
+extern "C" sj_status sj_result(sj_plan_t *p, int32_t *out, uint64_t capacity, int32_t mode) {
     if (sj_status st = check_exec(p, kJoined)) return st;
+    if (sj_status st = injected(p, SJ_FLAG_FAULT_RESULT, "sj_result")) return st;
+    Projection pr;
+    if (sj_status st = projection_of(p, mode, pr)) return st;
     if (!p->count_on_host) return fail(p->ctx, SJ_ERR_STATE, "call sj_join_wait first (the count is on the device)");
     if (capacity < p->count)
         return fail(p->ctx, SJ_ERR_CAPACITY, "result has %llu tuples, buffer holds %llu",
@@ -1572,6 +1646,7 @@ extern "C" sj_status sj_result(sj_plan_t *p, int32_t *out, uint64_t capacity) {
                 return fail(p->ctx, SJ_ERR_DEVICE, "internal: the two cyclic count passes disagree");
         }
         CycArgs c = cyc_args(p, out);
+        c.m.proj = pr;
         ProfScope ps(p, "cyclic_write", -1, kProfResult);
         SJ_HIP(p->ctx, launch_cyclic_write(c, p->ctx->stream));
         return SJ_OK;
@@ -1580,8 +1655,41 @@ extern "C" sj_status sj_result(sj_plan_t *p, int32_t *out, uint64_t capacity) {
     m.count = p->count;
     m.capacity = capacity;
     m.out = out;
+    m.proj = pr;
+    p->res_mode = mode;   // for the profile's byte model
     ProfScope ps(p, "materialize", -1, kProfResult);
     SJ_HIP(p->ctx, launch_materialize(m, p->ctx->stream));
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_plan_set_projection(sj_plan_t *p, const int32_t *rel_col, int32_t n) {
+    if (!p) return SJ_ERR_INVALID;
+    if (n < 0 || n > kMaxProj || (n > 0 && !rel_col))
+        return fail(p->ctx, SJ_ERR_INVALID, "a projection has 0..%d columns", kMaxProj);
+    std::vector<std::pair<int, int>> cols;
+    for (int q = 0; q < n; ++q) {
+        const int r = rel_col[2 * q], c = rel_col[2 * q + 1];
+        if (r < 0 || r >= p->n || c < 0 || c >= static_cast<int>(p->rels[r].cols.size()))
+            return fail(p->ctx, SJ_ERR_GRAPH, "projection column %d: relation %d column %d does not exist", q, r, c);
+        cols.emplace_back(r, c);
+    }
+    p->proj = cols;
+    if (p->gexec[3] && p->res_mode == SJ_VALUES) {   // the recorded materialisation names the columns
+        (void)hipGraphExecDestroy(p->gexec[3]);
+        p->gexec[3] = nullptr;
+    }
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_plan_footprint(const sj_plan_t *p, int32_t mode, uint64_t *workspace_bytes,
+                                       uint64_t *result_bytes, int32_t *width) {
+    if (!p || (mode != SJ_RIDS && mode != SJ_VALUES)) return SJ_ERR_INVALID;
+    if (workspace_bytes) *workspace_bytes = p->ws_bytes;
+    if (width) *width = result_width(p, mode);
+    if (result_bytes) {
+        if (p->state < kJoined || !p->count_on_host) return fail(p->ctx, SJ_ERR_STATE, "the count is not known yet");
+        *result_bytes = p->count * 4ull * static_cast<uint64_t>(result_width(p, mode));
+    }
     return SJ_OK;
 }
 
@@ -1627,6 +1735,9 @@ extern "C" sj_status sj_plan_use_filter_cache(sj_plan_t *p, sj_fcache *cache) {
     if (p->state > kBound) p->state = kBound;
     if (!cache) return SJ_OK;
     SJ_HIP(p->ctx, hipSetDevice(p->ctx->device));
+    p->fc_last_use = std::make_shared<FcEvent>();
+    SJ_HIP(p->ctx, hipEventCreateWithFlags(&p->fc_last_use->ev, hipEventDisableTiming));
+    p->fc_used = false;
     p->fcache = cache;
     char opt[96];
     std::snprintf(opt, sizeof opt, "b%u,k%u,B%u,s%08x,p%u|", p->opts.bits_per_key, p->opts.k, p->opts.block_bits,
@@ -1689,6 +1800,7 @@ extern "C" sj_status sj_filter_copy(sj_plan_t *p, int32_t f, uint32_t *dst, uint
     if (capacity_words < words) return fail(p->ctx, SJ_ERR_CAPACITY, "filter has %llu words", static_cast<unsigned long long>(words));
     SJ_HIP(p->ctx, hipMemcpyAsync(dst, fwords(p, f), words * 4, hipMemcpyDeviceToDevice,
                                   p->ctx->stream));
+    if (sj_status st = fc_mark_use(p)) return fail(p->ctx, st, "could not record the use of catalogue entries");
     return SJ_OK;
 }
 
@@ -1716,6 +1828,7 @@ static sj_status filter_update(sj_plan_t *p, int32_t f, const int32_t *keys, uin
     hipStream_t s = p->ctx->stream;
     SJ_HIP(p->ctx, launch_zero(u.missing, 8, s));
     SJ_HIP(p->ctx, launch_filter_update(u, set, s));
+    if (sj_status st = fc_mark_use(p)) return fail(p->ctx, st, "could not record the use of catalogue entries");
     if (missing) {
         SJ_HIP(p->ctx, hipMemcpyAsync(missing, u.missing, 8, hipMemcpyDeviceToHost, s));
         SJ_HIP(p->ctx, hipStreamSynchronize(s));
@@ -1804,7 +1917,7 @@ extern "C" sj_status sj_profile_collect(sj_plan_t *p) {
             }
             acc.bytes = bytes;
         } else if (r.kind == kProfResult) {
-            acc.bytes = p->count * 4ull * p->n;   // result tuples written
+            acc.bytes = p->count * 4ull * static_cast<uint64_t>(result_width(p, p->res_mode));   // result written
         }
         p->prof_free.push_back(r.a);
         p->prof_free.push_back(r.b);

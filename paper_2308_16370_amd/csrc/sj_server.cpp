@@ -10,6 +10,7 @@
 // region is 256-byte aligned.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -48,6 +49,9 @@ struct Request {
 };
 
 constexpr int64_t kResultWaitNs = 2000000000;   // a result waits at most 2 s for arena memory
+// execute()'s answer when the query gave its workspace back to let others finish: the
+// worker queues it again (not an sj_status; never reported to the caller)
+constexpr sj_status kRequeue = 1;
 // With nothing running and no queued query fitting, memory can only come back from
 // results the caller releases; after this long the oldest queued query fails.
 constexpr int64_t kAdmitStallNs = 2000000000;
@@ -66,6 +70,10 @@ struct sj_server {
     sj_ctx *plan_ctx = nullptr;   // validates queries at submit (planning is host-only)
     uint64_t next_ticket = 1;
     int running = 0;
+    // running queries waiting for arena memory for their result; no query is admitted
+    // while one waits, so that memory freed goes to results first
+    std::vector<Request *> result_waiters;
+    uint64_t requeues = 0;
     int64_t stall_since = 0;      // when admission last found nothing running and nothing fitting
     bool stop = false;
     sj_status init_status = SJ_OK;
@@ -108,8 +116,10 @@ sj_status execute(sj_server *s, Request &r, sj_ctx *ctx, hipStream_t stream, std
     if ((st = sj_join(plan, &count, &checksum)) != SJ_OK) return done(st);
     r.info.count = count;
     r.info.checksum = checksum;
-    if (r.mode == SJ_RESULT_TUPLES && count > 0) {
-        const uint64_t need = count * r.rels.size() * sizeof(int32_t);
+    const int32_t rmode = r.mode == SJ_RESULT_VALUES ? SJ_VALUES : SJ_RIDS;
+    if (r.mode != SJ_RESULT_COUNT && count > 0) {
+        uint64_t need = 0;
+        if ((st = sj_plan_footprint(plan, rmode, nullptr, &need, nullptr)) != SJ_OK) return done(st);
         {
             std::unique_lock<std::mutex> lk(s->mu);
             if (round256(need) > s->arena.size() - round256(r.info.workspace_bytes))
@@ -117,17 +127,44 @@ sj_status execute(sj_server *s, Request &r, sj_ctx *ctx, hipStream_t stream, std
             // wait for memory that running queries or released results free up, for a bounded time
             const auto deadline = std::chrono::steady_clock::now() + std::chrono::nanoseconds(kResultWaitNs);
             bool got = s->arena.alloc(need, &r.res_off);
-            while (!got) {
-                const bool timed_out = s->cv.wait_until(lk, deadline) == std::cv_status::timeout;
-                got = s->arena.alloc(need, &r.res_off);
-                if (!got && timed_out)
-                    return done(SJ_ERR_NOMEM,
-                                "no arena memory for the result (" + std::to_string(need) + " bytes) within 2 s");
+            if (!got) {
+                s->result_waiters.push_back(&r);
+                s->cv.notify_all();   // the other waiters re-check whether everyone now waits
+                auto leave = [&] {
+                    s->result_waiters.erase(std::find(s->result_waiters.begin(), s->result_waiters.end(), &r));
+                    s->cv.notify_all();
+                };
+                while (!got) {
+                    // Every running query waits for result memory, so none can finish and free
+                    // its workspace: the one admitted last gives its workspace back and is
+                    // queued again (its result is the same when it runs later).
+                    if (s->running >= 2 && s->result_waiters.size() == static_cast<size_t>(s->running)) {
+                        const Request *young = s->result_waiters.front();
+                        for (const Request *w : s->result_waiters)
+                            if (w->info.t_admit_ns > young->info.t_admit_ns ||
+                                (w->info.t_admit_ns == young->info.t_admit_ns && w->ticket > young->ticket))
+                                young = w;
+                        if (young == &r) {
+                            leave();
+                            return done(kRequeue, "requeued");
+                        }
+                    }
+                    const auto now = std::chrono::steady_clock::now();
+                    s->cv.wait_until(lk, std::min(deadline, now + std::chrono::milliseconds(20)));
+                    got = s->arena.alloc(need, &r.res_off);
+                    if (!got && std::chrono::steady_clock::now() >= deadline) {
+                        leave();
+                        return done(SJ_ERR_NOMEM,
+                                    "no arena memory for the result (" + std::to_string(need) + " bytes) within 2 s");
+                    }
+                }
+                leave();
             }
             r.res_bytes = need;
             r.has_result = true;
         }
-        if ((st = sj_result(plan, reinterpret_cast<int32_t *>(s->base + r.res_off), count)) != SJ_OK) return done(st);
+        if ((st = sj_result(plan, reinterpret_cast<int32_t *>(s->base + r.res_off), count, rmode)) != SJ_OK)
+            return done(st);
         r.info.result_offset = r.res_off;
     }
     if (hipStreamSynchronize(stream) != hipSuccess) return done(SJ_ERR_DEVICE, "stream synchronisation failed");
@@ -150,7 +187,8 @@ void worker(sj_server *s, int slot) {
                     s->queue.pop_front();
                     break;
                 }
-                for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
+                // while a running query waits for result memory, nothing is admitted
+                for (auto it = s->queue.begin(); s->result_waiters.empty() && it != s->queue.end(); ++it) {
                     if (s->arena.alloc((*it)->info.workspace_bytes, &(*it)->ws_off)) {
                         r = *it;
                         s->queue.erase(it);
@@ -194,6 +232,23 @@ void worker(sj_server *s, int slot) {
         {
             std::lock_guard<std::mutex> lk(s->mu);
             s->arena.release(r->ws_off, r->info.workspace_bytes);
+            if (st == kRequeue) {   // back to the head of the queue, as if never admitted
+                r->info.state = SJ_QUERY_QUEUED;
+                r->info.slot = -1;
+                r->info.t_admit_ns = 0;
+                r->info.count = r->info.checksum = 0;
+                ++r->info.requeues;
+                ++s->requeues;
+                --s->running;
+                if (s->stop) {
+                    fail_request(*r, SJ_ERR_STATE, "server destroyed before the query was admitted again");
+                    r->info.t_done_ns = now_ns();
+                } else {
+                    s->queue.push_front(r);
+                }
+                s->cv.notify_all();
+                continue;
+            }
             if (st != SJ_OK) {
                 if (r->has_result) {
                     s->arena.release(r->res_off, r->res_bytes);
@@ -237,7 +292,9 @@ extern "C" sj_status sj_server_create(int32_t device, void *arena_dev, uint64_t 
 
 extern "C" sj_status sj_server_submit(sj_server *s, const sj_rel *rels, int32_t nrels, const sj_edge *edges,
                                       int32_t nedges, const sj_opts *opts, int32_t result_mode, uint64_t *ticket) {
-    if (!s || !ticket || (result_mode != SJ_RESULT_TUPLES && result_mode != SJ_RESULT_COUNT)) return SJ_ERR_INVALID;
+    if (!s || !ticket ||
+        (result_mode != SJ_RESULT_TUPLES && result_mode != SJ_RESULT_COUNT && result_mode != SJ_RESULT_VALUES))
+        return SJ_ERR_INVALID;
     if (nrels < 0 || nrels > SJ_MAX_RELS || nedges < 0 || nedges > SJ_MAX_EDGES || (nrels && !rels) ||
         (nedges && !edges))
         return SJ_ERR_INVALID;

@@ -86,7 +86,7 @@ def test_valid_chain_plans():
     ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"B": 384}, sj.SJ_ERR_INVALID),
     ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"passes": 3}, sj.SJ_ERR_INVALID),
     ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"root": 2}, sj.SJ_ERR_INVALID),
-    ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"flags": 8}, sj.SJ_ERR_INVALID),
+    ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"flags": 128}, sj.SJ_ERR_INVALID),
     ([(2**31, 2, None)] * 2, [(0, 1, 1, 0)], {}, sj.SJ_ERR_INVALID),
     # nine children on one column: the root's step would probe nine filters
     ([(10, 1, None)] * 10, [(0, 0, i, 0) for i in range(1, 10)], {}, sj.SJ_ERR_UNSUPPORTED),
@@ -139,9 +139,45 @@ def test_state_machine_and_workspace_size():
     assert L.sj_build_filters(p) == sj.SJ_ERR_STATE
     assert L.sj_sieve(p, None) == sj.SJ_ERR_STATE
     assert L.sj_join(p, None, None) == sj.SJ_ERR_STATE
-    assert L.sj_result(p, None, 0) == sj.SJ_ERR_STATE
+    assert L.sj_result(p, None, 0, sj.SJ_RIDS) == sj.SJ_ERR_STATE
     assert L.sj_bind_workspace(p, ctypes.c_void_p(FAKE), ws - 1) == sj.SJ_ERR_NOMEM
     assert L.sj_bind_workspace(p, ctypes.c_void_p(FAKE + 64), ws) == sj.SJ_ERR_INVALID
     assert L.sj_bind_workspace(p, ctypes.c_void_p(FAKE), ws) == 0
     assert L.sj_join(p, None, None) == sj.SJ_ERR_STATE
     assert L.sj_plan_destroy(p) == 0
+
+
+def test_projection_and_footprint():
+    """sj_plan_set_projection checks every (relation, column) pair and the width limit;
+    sj_plan_footprint reports the workspace at once and the result size only once the
+    count is known."""
+    st, p, ws, ctx, err = plan([(100, 2, None), (50, 3, None), (70, 1, None)], [(0, 1, 1, 0), (1, 2, 2, 0)])
+    assert st == 0
+    L = sj.lib()
+    w, wsb, rb = ctypes.c_int32(), ctypes.c_uint64(), ctypes.c_uint64()
+    assert L.sj_plan_footprint(p, sj.SJ_RIDS, ctypes.byref(wsb), None, ctypes.byref(w)) == 0
+    assert (w.value, wsb.value) == (3, ws)
+    assert L.sj_plan_footprint(p, sj.SJ_VALUES, None, None, ctypes.byref(w)) == 0
+    assert w.value == 6                                   # every column of every relation
+    assert L.sj_plan_footprint(p, sj.SJ_RIDS, None, ctypes.byref(rb), None) == sj.SJ_ERR_STATE
+    assert L.sj_plan_footprint(p, 7, None, None, ctypes.byref(w)) == sj.SJ_ERR_INVALID
+    pairs = (ctypes.c_int32 * 6)(0, 0, 1, 2, 2, 0)
+    assert L.sj_plan_set_projection(p, pairs, 3) == 0
+    assert L.sj_plan_footprint(p, sj.SJ_VALUES, None, None, ctypes.byref(w)) == 0 and w.value == 3
+    bad = (ctypes.c_int32 * 2)(1, 3)                       # relation 1 has three columns
+    assert L.sj_plan_set_projection(p, bad, 1) == sj.SJ_ERR_GRAPH
+    bad = (ctypes.c_int32 * 2)(3, 0)
+    assert L.sj_plan_set_projection(p, bad, 1) == sj.SJ_ERR_GRAPH
+    assert L.sj_plan_set_projection(p, pairs, sj.SJ_MAX_PROJ + 1) == sj.SJ_ERR_INVALID
+    assert L.sj_plan_set_projection(p, None, 0) == 0
+    assert L.sj_plan_footprint(p, sj.SJ_VALUES, None, None, ctypes.byref(w)) == 0 and w.value == 6
+    assert L.sj_plan_destroy(p) == 0
+
+
+def test_fault_flags_are_accepted_and_unknown_flags_refused():
+    for flag in (sj.SJ_FLAG_FAULT_FILTERS, sj.SJ_FLAG_FAULT_SIEVE, sj.SJ_FLAG_FAULT_JOIN, sj.SJ_FLAG_FAULT_RESULT):
+        st, p, ws, ctx, err = plan([(10, 1, None)] * 2, [(0, 0, 1, 0)], flags=flag)
+        assert st == 0, err
+        sj.lib().sj_plan_destroy(p)
+    st, p, ws, ctx, err = plan([(10, 1, None)] * 2, [(0, 0, 1, 0)], flags=128)
+    assert st == sj.SJ_ERR_INVALID

@@ -244,3 +244,33 @@ def test_server_workers_share_one_catalogue(chain5):
         srv.close()
     assert cache.stats()["pinned"] == 0
     cache.close()
+
+
+def test_plan_outlives_its_context_and_stream(chain5):
+    """A plan attached to the catalogue is destroyed after its context and after the
+    caller has destroyed the context's stream (a raw HIP stream): releasing its entries
+    must not touch that stream. Another query on the same catalogue then reuses the
+    entries and still equals the oracle."""
+    import ctypes
+    q, rels, ref = chain5
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipStreamCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+    hip.hipStreamDestroy.argtypes = [ctypes.c_void_p]
+    hip.hipStreamSynchronize.argtypes = [ctypes.c_void_p]
+    cache = sj.FilterCache(64 << 20)
+    stream = ctypes.c_void_p()
+    assert hip.hipStreamCreate(ctypes.byref(stream)) == 0
+    torch.cuda.synchronize()
+    ctx = sj.Context(0, stream=torch.cuda.ExternalStream(stream.value))
+    plan = sj.Plan(ctx, rels, q.edges, filter_cache=cache, **OPTS)
+    check(q, plan, ref)
+    assert hip.hipStreamSynchronize(stream) == 0
+    sj.lib().sj_ctx_destroy(ctx.handle)      # the caller's context first (the plan keeps it alive) ...
+    ctx.handle = None
+    assert hip.hipStreamDestroy(stream) == 0  # ... then its stream ...
+    del plan                                 # ... then the plan, which lets go of its entries
+    again = sj.Plan(sj.Context(0), rels, q.edges, filter_cache=cache, **OPTS)
+    assert set(bwd_how(again).values()) == {1}
+    check(q, again, ref)
+    del again
+    cache.close()

@@ -175,3 +175,76 @@ def test_unreleased_results_fail_the_next_query_instead_of_hanging(bigq):
         srv.release(t2)
     finally:
         srv.close()
+
+
+def test_full_arena_of_waiting_results_requeues_instead_of_failing(bigq):
+    """Two slots whose workspaces fill the arena but leave no room for a second result:
+    every running query ends up waiting for result memory, so the one admitted last gives
+    its workspace back and runs again later. Every query finishes DONE with the answer it
+    has alone (the client releases each result as soon as it is done)."""
+    m = bigq
+    ws = (m[5] + 255) // 256 * 256
+    res = (m[3][0] * len(m[1].rels) * 4 + 255) // 256 * 256
+    arena = 2 * ws + res - 256
+    srv = sj.Server(arena, slots=2)
+    try:
+        tickets = [srv.submit(m[2], m[1].edges, root=m[1].root, **OPTS) for _ in range(4)]
+        done = {}
+        deadline = time.time() + 120
+        while len(done) < len(tickets):
+            assert time.time() < deadline, "queries did not finish"
+            for t in tickets:
+                if t in done:
+                    continue
+                info = srv.info(t)
+                if info["state"] in (sj.SJ_QUERY_DONE, sj.SJ_QUERY_FAILED):
+                    assert info["state"] == sj.SJ_QUERY_DONE, info
+                    assert (info["count"], info["checksum"]) == m[3]
+                    done[t] = info
+                    srv.release(t)
+            time.sleep(0.001)
+        assert sum(i["requeues"] for i in done.values()) >= 1
+        assert srv.stats()["arena_used"] == 0
+    finally:
+        srv.close()
+
+
+@pytest.mark.parametrize("flag", [sj.SJ_FLAG_FAULT_FILTERS, sj.SJ_FLAG_FAULT_SIEVE, sj.SJ_FLAG_FAULT_JOIN,
+                                  sj.SJ_FLAG_FAULT_RESULT])
+def test_injected_device_error_fails_one_query_only(mix, flag):
+    """A query whose phase reports SJ_ERR_DEVICE (injected on the host, no device fault)
+    fails alone with that status and message; every other query in the mix finishes with
+    the count, checksum and tuples it has alone (which equal the oracle's)."""
+    bad = 3
+    srv = sj.Server(8 << 30, slots=4)
+    try:
+        tickets = [srv.submit(m[2], m[1].edges, root=m[1].root, flags=flag if i == bad else 0, **OPTS)
+                   for i, m in enumerate(mix)]
+        for i, (m, t) in enumerate(zip(mix, tickets)):
+            info = srv.info(t, wait=True)
+            if i == bad:
+                assert info["state"] == sj.SJ_QUERY_FAILED and info["status"] == sj.SJ_ERR_DEVICE, info
+                assert "injected" in info["error"]
+            else:
+                assert info["state"] == sj.SJ_QUERY_DONE, info
+                assert (info["count"], info["checksum"]) == m[3]
+                assert np.array_equal(srv.result(t).cpu().numpy(), m[4])
+            srv.release(t)
+        assert srv.stats()["arena_used"] == 0
+    finally:
+        srv.close()
+
+
+def test_served_value_tuples(mix):
+    """Queries served in value mode return the oracle's result projected to values."""
+    srv = sj.Server(8 << 30, slots=3)
+    try:
+        tickets = [srv.submit(m[2], m[1].edges, root=m[1].root, values=True, **OPTS) for m in mix[:8]]
+        for m, t in zip(mix[:8], tickets):
+            info = srv.info(t, wait=True)
+            assert info["state"] == sj.SJ_QUERY_DONE, info
+            want = oracle.project(m[1], m[4].astype(np.uint32))
+            assert np.array_equal(srv.result(t).cpu().numpy(), want)
+            srv.release(t)
+    finally:
+        srv.close()
