@@ -152,6 +152,19 @@ sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, const sj_edge 
 /* Give the plan its device workspace (256-byte aligned, >= workspace_bytes). */
 sj_status sj_bind_workspace(sj_plan_t *plan, void *workspace_dev, uint64_t bytes);
 
+/* For callers that cannot allocate device memory (code under graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): bind the plan to the library's
+ * static workspace instead of a caller buffer. It is one array of SJ_STATIC_WORKSPACE_BYTES
+ * per GPU, held by the library until the process ends; this call allocates nothing
+ * (no hipMalloc, no library allocation). Fails with SJ_ERR_NOMEM, binding nothing, if
+ * the plan's workspace_bytes exceed it. Every plan bound to it on one GPU shares it:
+ * plans bound to it must not run at the same time (their phases would race on it),
+ * and a plan's filters, survivors and count hold only until another plan bound to it
+ * runs a phase (each phase clears what it needs zeroed, so no clearing is needed
+ * between plans). The caller still passes the input columns and the result buffer. */
+#define SJ_STATIC_WORKSPACE_BYTES (64ull << 20)
+sj_status sj_bind_static_workspace(sj_plan_t *plan);
+
 /* Pruning phase, backward pass (Section 2.2 step 1): for every non-root relation
  * from the leaves toward the root, scan its rows, keep those whose child-edge keys
  * all pass the children's filters, and insert the survivors' parent-edge keys into

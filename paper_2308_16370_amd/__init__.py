@@ -50,13 +50,14 @@ EXPORTED = ["sj_ctx_create", "sj_ctx_set_stream", "sj_ctx_destroy", "sj_last_err
             "sj_server_destroy", "sj_fcache_create", "sj_plan_use_filter_cache", "sj_plan_filter_cached",
             "sj_fcache_invalidate", "sj_fcache_clear", "sj_fcache_stats", "sj_fcache_destroy",
             "sj_server_use_filter_cache", "sj_filter_probe", "sj_filter_insert", "sj_plan_set_projection",
-            "sj_plan_footprint"]
+            "sj_plan_footprint", "sj_bind_static_workspace"]
 SJ_FLAG_PROFILE = 1
 SJ_FLAG_EAGER = 2
 SJ_FLAG_BINARY_CYCLES = 4
 SJ_FLAG_FAULT_FILTERS, SJ_FLAG_FAULT_SIEVE, SJ_FLAG_FAULT_JOIN, SJ_FLAG_FAULT_RESULT = 8, 16, 32, 64
 SJ_RIDS, SJ_VALUES = 0, 1
 SJ_MAX_PROJ = 32
+SJ_STATIC_WORKSPACE_BYTES = 64 << 20
 SJ_MAX_SLOTS = 16
 SJ_QUERY_QUEUED, SJ_QUERY_RUNNING, SJ_QUERY_DONE, SJ_QUERY_FAILED = 0, 1, 2, 3
 SJ_RESULT_TUPLES, SJ_RESULT_COUNT, SJ_RESULT_VALUES = 0, 1, 2
@@ -150,6 +151,7 @@ def lib():
             "sj_filter_insert": [V, i32, V, u64, V, P(u64)],
             "sj_plan_set_projection": [V, V, i32],
             "sj_plan_footprint": [V, i32, P(u64), P(u64), P(i32)],
+            "sj_bind_static_workspace": [V],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -233,7 +235,7 @@ class Plan:
                  bits_per_key: int = 0, k: int = 0, block_bits: int = 0, passes: int = 0, seed: int = 0,
                  root: int = -1, workspace: Optional[torch.Tensor] = None, profile: bool = False,
                  eager: bool = False, filter_cache: "Optional[FilterCache]" = None, binary_cycles: bool = False,
-                 flags: int = 0):
+                 flags: int = 0, static_workspace: bool = False):
         self.ctx = ctx
         self.block_bits = block_bits or 512
         self.nrels = len(rels)
@@ -247,12 +249,16 @@ class Plan:
         ctx._check(lib().sj_plan(ctx.handle, arr, len(rels), earr, len(edges), ctypes.byref(opts),
                                  ctypes.byref(self.handle), ctypes.byref(wsb)))
         self.workspace_bytes = int(wsb.value)
-        if workspace is None:
+        if static_workspace:   # the library's static workspace: nothing is allocated
+            self.workspace = None
+            ctx._check(lib().sj_bind_static_workspace(self.handle))
+        elif workspace is None:
             workspace = torch.empty(max(256, self.workspace_bytes), dtype=torch.uint8,
                                     device="cuda:%d" % ctx.device)
-        self.workspace = workspace
-        ctx._check(lib().sj_bind_workspace(self.handle, ctypes.c_void_p(workspace.data_ptr()),
-                                           workspace.numel() * workspace.element_size()))
+        if not static_workspace:
+            self.workspace = workspace
+            ctx._check(lib().sj_bind_workspace(self.handle, ctypes.c_void_p(workspace.data_ptr()),
+                                               workspace.numel() * workspace.element_size()))
         self.count = None
         self.checksum = None
         self.filter_cache = None

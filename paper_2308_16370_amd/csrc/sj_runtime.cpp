@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -824,6 +825,48 @@ extern "C" sj_status sj_bind_workspace(sj_plan_t *p, void *ws, uint64_t bytes) {
     p->drop_graphs();   // recorded launches point into the previous workspace
     p->state = kBound;
     return SJ_OK;
+}
+
+// ---------------------------------------------------------------- static workspace
+
+// The workspace of sj_bind_static_workspace, for callers that cannot allocate device
+// memory: one array per GPU (each device the library runs on holds its own copy until
+// the process ends). Host code never uses the array's name as an address: the device
+// address comes from hipGetSymbolAddress, once per device.
+constexpr uint64_t kStaticWorkspaceBytes = 64ull << 20;
+constexpr int kStaticMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kStaticMaxDevices] = {};
+
+extern "C" sj_status sj_bind_static_workspace(sj_plan_t *p) {
+    if (!p) return SJ_ERR_INVALID;
+    const int dev = p->ctx->device;
+    if (dev >= kStaticMaxDevices) return fail(p->ctx, SJ_ERR_INVALID, "device %d: static workspaces exist for devices 0..%d",
+                                              dev, kStaticMaxDevices - 1);
+    if (p->ws_bytes > kStaticWorkspaceBytes)
+        return fail(p->ctx, SJ_ERR_NOMEM,
+                    "the plan needs %llu bytes of workspace; the static workspace holds %llu (bind a caller workspace "
+                    "with sj_bind_workspace instead)",
+                    static_cast<unsigned long long>(p->ws_bytes), static_cast<unsigned long long>(kStaticWorkspaceBytes));
+    void *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            int prev = 0;
+            SJ_HIP(p->ctx, hipGetDevice(&prev));
+            SJ_HIP(p->ctx, hipSetDevice(dev));
+            void *addr = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+            (void)hipSetDevice(prev);
+            if (e != hipSuccess || !addr)
+                return fail(p->ctx, SJ_ERR_DEVICE, "hipGetSymbolAddress of the static workspace failed: %s",
+                            hipGetErrorString(e));
+            g_scratch_ptr[dev] = addr;
+        }
+        ptr = g_scratch_ptr[dev];
+    }
+    return sj_bind_workspace(p, ptr, kStaticWorkspaceBytes);
 }
 
 extern "C" sj_status sj_plan_destroy(sj_plan_t *p) {

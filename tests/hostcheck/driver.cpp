@@ -449,6 +449,28 @@ void scenario_errors() {
     EXPECT(sj_join(r.plan, nullptr, nullptr) == SJ_ERR_STATE, "join before sieve");
 }
 
+void scenario_static() {
+    Query q = chain(3, 20000);
+    for (int rep = 0; rep < 2; ++rep) {
+        Run r;
+        OK(nullptr, sj_ctx_create(0, nullptr, &r.ctx));
+        sj_opts o{};
+        OK(r.ctx, sj_plan(r.ctx, q.rels.data(), 3, q.edges.data(), 2, &o, &r.plan, &r.wsb));
+        OK(r.ctx, sj_bind_static_workspace(r.plan));
+        OK(r.ctx, sj_build_filters(r.plan));
+        OK(r.ctx, sj_sieve(r.plan, nullptr));
+        uint64_t c, k;
+        OK(r.ctx, sj_join(r.plan, &c, &k));
+    }
+    Query big = chain(3, 2000000);
+    Run r;
+    OK(nullptr, sj_ctx_create(0, nullptr, &r.ctx));
+    sj_opts o{};
+    OK(r.ctx, sj_plan(r.ctx, big.rels.data(), 3, big.edges.data(), 2, &o, &r.plan, &r.wsb));
+    EXPECT(sj_bind_static_workspace(r.plan) == SJ_ERR_NOMEM, "a plan larger than the static workspace");
+    EXPECT(sj_build_filters(r.plan) == SJ_ERR_STATE, "nothing was bound");
+}
+
 struct Scenario {
     const char *name;
     void (*fn)();
@@ -457,7 +479,7 @@ const Scenario kScenarios[] = {
     {"chain", scenario_chain},   {"star", scenario_star},       {"bushy", scenario_bushy},
     {"binary", scenario_binary_tree}, {"chain12", scenario_chain12}, {"sixteen", scenario_sixteen},
     {"cycles", scenario_cycles}, {"updates", scenario_updates}, {"fcache", scenario_fcache},
-    {"server", scenario_server}, {"errors", scenario_errors},
+    {"server", scenario_server}, {"errors", scenario_errors}, {"static", scenario_static},
 };
 
 }  // namespace

@@ -417,6 +417,14 @@ hipError_t hipMemsetAsync(void *dst, int v, size_t bytes, hipStream_t s) {
     return hipSuccess;
 }
 
+// A __device__ variable's address: in a host-only build the variable itself is the
+// host-side stand-in, so its own address serves as the "device" memory.
+hipError_t hipGetSymbolAddress(void **ptr, const void *symbol) {
+    if (!ptr || !symbol) return hipErrorInvalidValue;
+    *ptr = const_cast<void *>(symbol);
+    return hipSuccess;
+}
+
 hipError_t hipMalloc(void **, size_t) {
     violation("%s", "hipMalloc called");
     return hipErrorOutOfMemory;
