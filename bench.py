@@ -27,9 +27,13 @@ The per-launch event timings come from a second plan on the same workspace that
 launches eagerly with an event pair around each kernel (the timed plan replays
 recorded graphs); the kernels and data are the same.
 
-configs       -- the star (100M-row fact table) and the full-size triangle (50M
-                 edges, 3-cycles counted by intersection), timed the same way
-                 (paper_2308_16370_amd/configbench.py).
+configs       -- the small 3-way chain's latency, the star (100M-row fact table), the
+                 full-size triangle (50M edges, 3-cycles counted by intersection) and
+                 the paper's synthetic join at its sizes (2e8 rows, 10^7 tuples), timed
+                 the same way (paper_2308_16370_amd/configbench.py).
+sieve_roofline -- every probe, compaction and filter-build launch of a step: their
+                 algorithmic bytes over their summed event-timed durations, against the
+                 60% target.
 filter_reuse  -- the same step on a plan attached to a filter catalogue, whose
                  backward filters are built once and then reused (their builds drop
                  out of the step); reported beside the headline value, which always
@@ -74,6 +78,39 @@ def load_traffic(label):
     if t.get("source_hash") != lib_source_hash() or t.get("label") != label:
         return None
     return t.get("bytes_per_launch")
+
+
+def host_cpu():
+    """The measuring host's CPU model and logical CPU count."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def copy_bandwidth(dev, mib: int = 1024, reps: int = 10):
+    """Device-to-device copy of `mib` MiB, timed with torch events on its stream: bytes
+    read plus bytes written per second (GB/s)."""
+    import torch
+    x = torch.empty(mib << 20, dtype=torch.uint8, device=dev)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) / 1e3 / reps
+    del x, y
+    return 2.0 * (mib << 20) / sec / 1e9
 
 
 def main():
@@ -181,6 +218,7 @@ def main():
     kernels = sorted(prof, key=lambda e: -e["total_ms"] / max(1, e["launches"]))
     modelled = [e for e in kernels if e["alg_bytes"] > 0]
     dom = modelled[0] if modelled else None
+    copy_gbs = copy_bandwidth(dev)
     roofline = None
     if dom:
         avg_s = dom["total_ms"] / dom["launches"] / 1e3
@@ -188,7 +226,19 @@ def main():
         traffic = load_traffic(dom["label"])
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom["label"],
-                    "alg_bytes_per_launch": dom["alg_bytes"], "avg_us": round(avg_s * 1e6, 2)}
+                    "alg_bytes_per_launch": dom["alg_bytes"], "avg_us": round(avg_s * 1e6, 2),
+                    "copy_kernel_gbs": round(copy_gbs, 1)}
+    # the sieve passes together (every probe, compaction and filter-build launch of a
+    # step): their algorithmic bytes over their summed event-timed durations
+    sieve = [e for e in prof if e["label"].split(":")[0] in ("probe", "compact", "bfb_hist", "bfb_scan",
+                                                              "bfb_scatter", "bfb_region", "count_pred")]
+    sieve_ms = sum(e["total_ms"] for e in sieve) / max(1, args.profile_steps)
+    sieve_bytes = sum(e["alg_bytes"] for e in sieve)
+    sieve_roofline = {"bound": "hbm", "achieved": round(sieve_bytes / (sieve_ms / 1e3) / 1e9, 1) if sieve_ms else None,
+                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "launches_per_step": len(sieve),
+                      "alg_bytes_per_step": sieve_bytes, "ms_per_step": round(sieve_ms, 4), "target_frac": 0.6}
+    if sieve_ms:
+        sieve_roofline["frac"] = round(sieve_roofline["achieved"] / HBM_PEAK_GBS, 4)
 
     # the same step with the backward filters held in a filter catalogue (built on the
     # first call, reused after): not the headline value, which builds every filter
@@ -230,7 +280,8 @@ def main():
         t = time.perf_counter() - t
         cpu = {"value": q.input_tuples / t, "unit": "tuples/s", "cores": 1, "kind": "oracle",
                "sample": "the full workload (4 x %d rows), single-threaded binary hash join, %.2f s"
-                         % (q.rels[0].nrows, t)}
+                         % (q.rels[0].nrows, t),
+               "host": host_cpu()}
         check = "count and checksum equal the oracle" if (rcnt, rchk) == (cnt, chk) else "MISMATCH"
         if check == "MISMATCH":
             print("# oracle mismatch: gpu %r oracle %r" % ((cnt, chk), (rcnt, rchk)), file=sys.stderr)
@@ -239,7 +290,10 @@ def main():
     if not args.no_configs:
         from paper_2308_16370_amd import configbench
         logf = lambda m: print(m, file=sys.stderr, flush=True)
-        configs = {"star": configbench.star(log=logf), "triangle": configbench.triangle(log=logf)}
+        configs = {"chain3": configbench.chain3_latency(log=logf), "star": configbench.star(log=logf),
+                   "triangle": configbench.triangle(log=logf), "psyn": configbench.psyn(log=logf),
+                   "bloomjoin_n2": configbench.bloomjoin(log=logf),
+                   "planner_chain4": configbench.planner_check(q, opts, log=logf)}
         tri = configs["triangle"]
         gold = os.path.join(ROOT, "tests", "golden", "triangle_cycles.json")
         tri["check"] = "no stored oracle value at this size"
@@ -279,6 +333,7 @@ def main():
                                % (q.rels[0].nrows, q.meta["domain"]),
                    "input_tuples": q.input_tuples, "result_tuples": cnt, "seed": args.seed},
         "roofline": roofline,
+        "sieve_roofline": sieve_roofline,
         "cpu_baseline": cpu,
         "check": check,
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},

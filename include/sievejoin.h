@@ -305,6 +305,13 @@ sj_status sj_profile_count(const sj_plan_t *plan, int32_t *n);
  *                       predicate column of a full scan) read;
  *   "bfb_scatter:..."   the keys read again, each kept key staged (4 bytes);
  *   "bfb_region:..."    the staged keys read, the filter written once;
+ *   "buckets:R<j>"      per sieved entry of relation j: an 8-byte (key, index) pair read
+ *                       and written per active radix pass, the row id and join columns
+ *                       gathered into bucket order (read and written), the key read for
+ *                       the directory; 16 bytes per distinct key (directory entry, slot);
+ *   "dp:R<j>"           per entry: its row id read; per child its key, the child's bucket
+ *                       bounds and prefix weights at them read (32 bytes), the bounds
+ *                       written (8 bytes); its own two prefix weights written (16 bytes);
  *   "materialize"       the result tuples written. */
 sj_status sj_profile_entry(const sj_plan_t *plan, int32_t i, const char **label, double *total_ms,
                            uint64_t *launches, uint64_t *alg_bytes);

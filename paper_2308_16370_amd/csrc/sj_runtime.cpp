@@ -916,7 +916,9 @@ static hipEvent_t prof_event(sj_plan_t *p) {
 
 // Records an event before the launches of its scope and one after them.
 // What a profiled launch group is, for its algorithmic-byte model.
-enum ProfKind { kProfOther = 0, kProfProbe = 1, kProfCompact = 2, kProfResult = 3, kProfBuild0 = 16 };
+// kProfBuckets and kProfDp carry the relation index in the record's `step` field.
+enum ProfKind { kProfOther = 0, kProfProbe = 1, kProfCompact = 2, kProfResult = 3, kProfBuckets = 4, kProfDp = 5,
+                kProfBuild0 = 16 };
 
 struct ProfScope {
     sj_plan_t *p;
@@ -1421,14 +1423,14 @@ static sj_status enqueue_join(sj_plan_t *p) {
         int sec = -1;   // L of a cyclic join is ordered by its closing column inside each bucket
         if (p->cyclic && j == p->L && p->cyc_cv != p->mycol[j]) sec = R.jidx(p->cyc_cv);
         {
-            ProfScope ps(p, std::string("buckets:") + rel_name(j));
+            ProfScope ps(p, std::string("buckets:") + rel_name(j), j, kProfBuckets);
             SJ_HIP(p->ctx, launch_build_buckets(list_rid(p, j, fl), lcols.data(), ncol, lcount, b.key_jcol, sec, b,
                                                 sort_scratch(p, j), dir_lookback(p, j), br[i]));
         }
         if (!p->children[j].empty()) continue;
         DpArgs d;
         if (sj_status st = dp_args(p, j, d)) return st;
-        ProfScope ps(p, std::string("dp:") + rel_name(j));
+        ProfScope ps(p, std::string("dp:") + rel_name(j), j, kProfDp);
         SJ_HIP(p->ctx, launch_dp(d, br[i]));
     }
     if (sj_status st = join_streams(p, static_cast<int>(inner.size()))) return st;
@@ -1436,7 +1438,7 @@ static sj_status enqueue_join(sj_plan_t *p) {
         if (j != p->root && p->children[j].empty()) continue;   // weighed on its branch
         DpArgs d;
         if (sj_status st = dp_args(p, j, d)) return st;
-        ProfScope ps(p, std::string("dp:") + rel_name(j));
+        ProfScope ps(p, std::string("dp:") + rel_name(j), j, kProfDp);
         SJ_HIP(p->ctx, launch_dp(d, s));
     }
     return SJ_OK;
@@ -1476,7 +1478,7 @@ static sj_status enqueue_tri(sj_plan_t *p) {
         bk[h] = buckets_of(p, j);
         bk[h].key_jcol = key_col[h];
         {
-            ProfScope ps(p, std::string("buckets:") + rel_name(j));
+            ProfScope ps(p, std::string("buckets:") + rel_name(j), j, kProfBuckets);
             SJ_HIP(p->ctx, launch_build_buckets(list_rid(p, j, fl), lcols.data(), ncol, bk[h].n, key_col[h], -1, bk[h],
                                                 sort_scratch(p, j), dir_lookback(p, j), br[h]));
         }
@@ -1919,7 +1921,31 @@ extern "C" sj_status sj_profile_collect(sj_plan_t *p) {
         auto &acc = p->prof_acc[r.label];
         acc.ms += ms;
         acc.n += 1;
-        if (r.step >= 0) {
+        if (r.kind == kProfBuckets || r.kind == kProfDp) {
+            // the join's byte models (per sieved entry n of relation j): bucketing reads and
+            // writes an 8-byte (key, index) pair per active radix pass, gathers the row id and
+            // join columns into bucket order (read and written once), reads each key for the
+            // directory and writes each distinct key's directory entry and hash slot (16 B);
+            // a DP reads each entry's row id, per child its key, the child's bucket bounds
+            // and the two prefix pairs at them (28 B), writes the bounds (8 B per child) and
+            // the entry's two prefix weights (16 B)
+            const int j = r.step;
+            const uint64_t ncol = p->rels[j].jcols.size();
+            uint32_t n = 0;
+            SJ_HIP(p->ctx, hipMemcpy(&n, at<uint32_t>(p, p->steps[p->final_step[j]].off_count), 4,
+                                     hipMemcpyDeviceToHost));
+            if (r.kind == kProfBuckets && j != p->root) {
+                uint32_t ctl[8] = {}, ndir = 0;
+                SJ_HIP(p->ctx, hipMemcpy(ctl, at<uint32_t>(p, p->jr[j].sctl), sizeof ctl, hipMemcpyDeviceToHost));
+                SJ_HIP(p->ctx, hipMemcpy(&ndir, at<uint32_t>(p, p->jr[j].ndir), 4, hipMemcpyDeviceToHost));
+                uint64_t passes = 0;
+                for (uint32_t c : ctl) passes += c ? 1 : 0;
+                acc.bytes = uint64_t(n) * (16 * passes + 8 * (1 + ncol) + 4) + uint64_t(ndir) * 16;
+            } else if (r.kind == kProfDp) {
+                const uint64_t nch = p->children[j].size();
+                acc.bytes = uint64_t(n) * (4 + nch * (4 + 28 + 8) + 16);
+            }
+        } else if (r.step >= 0) {
             const StepSpec &st = p->steps[r.step];
             const Rel &R = p->rels[st.rel];
             const uint64_t ncol = R.jcols.size();

@@ -10,6 +10,9 @@
         JSON: HBM bytes per launch of occurrence I of kernel NAME from FETCH_SIZE and
         WRITE_SIZE (KiB per dispatch), each scaled by bytes / counter of a plain copy
         kernel of N bytes read and N bytes written in the same run.
+
+    python -m paper_2308_16370_amd.profsum counters PASS1.db [PASS2.db ...] [--kernel SUBSTR]
+        Markdown: the mean of every PMC counter per (kernel, launch position in a step).
 """
 from __future__ import annotations
 
@@ -118,6 +121,42 @@ def cmd_traffic(args):
     print(json.dumps(out, indent=1))
 
 
+def cmd_counters(args):
+    """Markdown: per (kernel, occurrence in a step), the mean value of every PMC counter
+    found in the given databases (one rocprofv3 --pmc pass each)."""
+    cols = []
+    data = {}
+    for path in args.dbs:
+        db = sqlite3.connect(path)
+        names = [r[0] for r in db.execute("select distinct counter_name from pmc_events")]
+        for cn in names:
+            cols.append(cn)
+            steps, cur = [], []
+            for name, _, v in _counter_per_dispatch(db, cn):
+                cur.append((_short(name), v))
+                if args.step_end in name:
+                    steps.append(cur)
+                    cur = []
+            for st in steps[1:]:
+                seen = {}
+                for k, v in st:
+                    i = seen.get(k, 0)
+                    seen[k] = i + 1
+                    data.setdefault((k, i), {}).setdefault(cn, []).append(v)
+    out = []
+    if args.cmd:
+        out.append("Commands:\n\n" + "\n".join("    " + c for c in args.cmd) + "\n")
+    out.append("| kernel | occ | " + " | ".join(cols) + " |")
+    out.append("|---|---:|" + "---:|" * len(cols))
+    keys = sorted(data, key=lambda kv: (kv[0], kv[1]))
+    for k in keys:
+        if args.kernel and not any(x in k[0] for x in args.kernel):
+            continue
+        row = ["%.4g" % statistics.mean(data[k][c]) if c in data[k] else "" for c in cols]
+        out.append("| %s | %d | %s |" % (k[0], k[1], " | ".join(row)))
+    print("\n".join(out))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -138,6 +177,12 @@ def main(argv=None):
     t.add_argument("--step-end", default="k_materialize")
     t.add_argument("--cmd", default="")
     t.set_defaults(fn=cmd_traffic)
+    c = sub.add_parser("counters")
+    c.add_argument("dbs", nargs="+")
+    c.add_argument("--step-end", default="k_materialize")
+    c.add_argument("--kernel", action="append", default=[])
+    c.add_argument("--cmd", action="append", default=[])
+    c.set_defaults(fn=cmd_counters)
     args = ap.parse_args(argv)
     args.fn(args)
 

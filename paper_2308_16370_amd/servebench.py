@@ -5,13 +5,16 @@ pass of the whole mix warms up kernel loading and the workers first. Each query 
 first run alone with a count pass; a query whose count exceeds `count_cap` is
 redrawn. Filter options come from the autotuner's table per query. Then the same
 queries go through sj_server runs over one arena:
+  * alone         -- one slot, each query submitted when the previous one has
+                     finished: its latency is its own service time;
   * one_at_a_time -- one slot, every query submitted at once: the queries run one
-                     after the other, each with the whole GPU;
+                     after the other, each with the whole GPU (latency includes queueing);
   * burst         -- `slots` slots, every query submitted at once;
   * poisson_<f>   -- `slots` slots, Poisson arrivals at f times the one-at-a-time
                      service rate.
 A collector consumes each result as its query finishes (checks count and checksum
-against the alone run, then releases it). Latency is completion minus submission on
+against the alone run, which equals the oracle's stored value for the mix when
+tests/golden/serving_mix.json holds it, then releases it). Latency is completion minus submission on
 the server's clock; throughput counts input tuples over the span from the first
 submission to the last completion.
 """
@@ -28,7 +31,28 @@ def _pct(v: List[float], p: float) -> float:
     return float(np.percentile(np.asarray(v), p)) if v else float("nan")
 
 
+def load_store(seed: int, n: int, min_rows: int, max_rows: int, count_cap: int, path: Optional[str] = None):
+    """The stored oracle values of the mix ({index: entry}) if they were written for
+    exactly these parameters (tests/golden/serving_mix.json), else None."""
+    import json
+    import os
+    path = path or os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden",
+                                "serving_mix.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        doc = json.load(fh)
+    if (doc["seed"], doc["min_rows"], doc["max_rows"], doc["count_cap"]) != (seed, min_rows, max_rows, count_cap):
+        return None
+    if doc["n"] < n:
+        return None
+    return {q["index"]: q for q in doc["queries"]}
+
+
 def prepare(seed: int, n: int, min_rows: int, max_rows: int, count_cap: int, tuned: bool, log=print):
+    """Queries of the mix on the GPU, each run alone once. With the stored oracle values
+    of the mix, each query takes the stored draw, and its count and checksum alone must
+    equal the stored ones (`oracle` in each entry: the stored pair, else None)."""
     import torch
 
     import paper_2308_16370_amd as sj
@@ -39,7 +63,12 @@ def prepare(seed: int, n: int, min_rows: int, max_rows: int, count_cap: int, tun
     ctx = sj.Context(0)
     queries = []
     redraws = 0
+    store = load_store(seed, n, min_rows, max_rows, count_cap)
     for sp in S.serving_specs(seed, n=n, min_rows=min_rows, max_rows=max_rows):
+        if store is not None:
+            while sp.draw < store[sp.index]["draw"]:
+                sp = S.redraw(seed, sp, min_rows=min_rows, max_rows=max_rows)
+                redraws += 1
         while True:
             rel_t, edges = S.query_gpu(sp)
             rels = [sj.Rel(cols, pred) for cols, pred in rel_t]
@@ -55,16 +84,26 @@ def prepare(seed: int, n: int, min_rows: int, max_rows: int, count_cap: int, tun
             redraws += 1
             del rels, rel_t
             sp = S.redraw(seed, sp, min_rows=min_rows, max_rows=max_rows)
-        queries.append(dict(spec=sp, rels=rels, edges=edges, opts=opts, cc=cc))
+        ref = None
+        if store is not None:
+            ent = store[sp.index]
+            ref = (ent["count"], ent["checksum"])
+            if cc != ref:
+                raise RuntimeError("query %d alone: %r, the oracle's stored value %r" % (sp.index, cc, ref))
+        queries.append(dict(spec=sp, rels=rels, edges=edges, opts=opts, cc=cc, oracle=ref))
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    log("# mix: %d queries, %d input tuples, %d redraws" % (len(queries), sum(q["spec"].input_tuples for q in queries),
-                                                           redraws))
-    return queries, redraws
+    log("# mix: %d queries, %d input tuples, %d redraws, %s" % (
+        len(queries), sum(q["spec"].input_tuples for q in queries), redraws,
+        "every count and checksum alone equals the stored oracle value" if store is not None
+        else "no stored oracle values for this mix"))
+    return queries, redraws, store is not None
 
 
-def serve(queries, arena, slots: int, rate: Optional[float], seed: int = 1) -> Dict:
-    """Run the mix through a server; rate None: all at once, else Poisson arrivals."""
+def serve(queries, arena, slots: int, rate: Optional[float], seed: int = 1, sequential: bool = False) -> Dict:
+    """Run the mix through a server; rate None: all at once, else Poisson arrivals;
+    sequential: each query is submitted when the previous one has finished (its
+    latency is then its own service time, with no queueing)."""
     import paper_2308_16370_amd as sj
 
     srv = sj.Server(0, slots=slots, arena=arena)
@@ -78,6 +117,8 @@ def serve(queries, arena, slots: int, rate: Optional[float], seed: int = 1) -> D
             gaps = np.random.default_rng(seed).exponential(1.0 / rate, len(queries)) if rate else None
             at = 0.0
             for i, q in enumerate(queries):
+                if sequential and i > 0:
+                    srv.info(tickets[i - 1], wait=True)
                 if rate:
                     at += gaps[i]
                     d = t0 + at - time.perf_counter()
@@ -109,6 +150,8 @@ def serve(queries, arena, slots: int, rate: Optional[float], seed: int = 1) -> D
                     raise RuntimeError("query %d failed: %s" % (i, info["error"]))
                 if (info["count"], info["checksum"]) != queries[i]["cc"]:
                     mismatches += 1
+                if queries[i]["oracle"] is not None and (info["count"], info["checksum"]) != queries[i]["oracle"]:
+                    mismatches += 1
                 srv.release(t)
                 lat.append((info["t_done_ns"] - info["t_submit_ns"]) / 1e6)
                 admit.append((info["t_admit_ns"] - info["t_submit_ns"]) / 1e6)
@@ -131,14 +174,17 @@ def serve(queries, arena, slots: int, rate: Optional[float], seed: int = 1) -> D
 
 
 def run(seed: int = 0x5EED0005, n: int = 256, min_rows: int = 10_000, max_rows: int = 20_000_000,
-        slots: int = 8, arena_bytes: int = 24 << 30, lam=(0.8,), count_cap: int = 1 << 26, tuned: bool = True,
-        log=print) -> Dict:
+        slots: int = 8, arena_bytes: int = 24 << 30, lam=(0.5, 0.9, 1.2), count_cap: int = 1 << 26,
+        tuned: bool = True, log=print) -> Dict:
     import torch
 
-    queries, redraws = prepare(seed, n, min_rows, max_rows, count_cap, tuned, log)
+    queries, redraws, pinned = prepare(seed, n, min_rows, max_rows, count_cap, tuned, log)
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda:0")
     torch.cuda.synchronize()
     serve(queries, arena, slots, None)   # warm-up: first launches of every kernel, worker start-up
+    alone = serve(queries, arena, 1, None, sequential=True)
+    log("# alone (each submitted after the previous finished): p50 %.2f ms p99 %.2f ms" % (alone["p50_ms"],
+                                                                                          alone["p99_ms"]))
     one = serve(queries, arena, 1, None)
     log("# one at a time: %.3f s, p50 %.2f ms" % (one["span_s"], one["p50_ms"]))
     burst = serve(queries, arena, slots, None)
@@ -147,7 +193,10 @@ def run(seed: int = 0x5EED0005, n: int = 256, min_rows: int = 10_000, max_rows: 
     rate = one["queries_per_s"]
     out = {"queries": len(queries), "input_tuples": sum(q["spec"].input_tuples for q in queries),
            "rows_per_relation": [min_rows, max_rows], "redraws": redraws, "count_cap": count_cap,
-           "arena_bytes": arena_bytes, "autotuned": tuned, "one_at_a_time": one, "burst": burst,
+           "oracle_check": ("every query's count and checksum, alone and in each served run, equals the stored "
+                            "oracle value (tests/golden/serving_mix.json)") if pinned else
+                           "no stored oracle values for this mix (results compared with each query alone)",
+           "arena_bytes": arena_bytes, "autotuned": tuned, "alone": alone, "one_at_a_time": one, "burst": burst,
            "burst_speedup": round(burst["tuples_per_s"] / one["tuples_per_s"], 3)}
     for f in lam:
         r = serve(queries, arena, slots, f * rate, seed=int(f * 1000))

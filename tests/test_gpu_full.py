@@ -122,3 +122,34 @@ def test_triangle_count_at_large_scale_golden(case):
     plan.build_filters()
     plan.sieve()
     assert plan.join() == (case["count"], case["checksum"])
+
+
+def test_psyn_full_size():
+    """The paper's synthetic join at its comparison sizes (Section 3.1.1: M = 10^7,
+    r = 10^4, d = 10; 2e8 input rows). Count equals the closed form r * d^3 = 10^7, count
+    and checksum equal the oracle's join-tree DP (stored by tests/golden/make_psyn_golden.py),
+    and every one of the 10^7 tuples is checked: its three rows hold the same value, and
+    the tuples are strictly increasing (so distinct). Valid, distinct and as many as the
+    exact count, the tuples are exactly the result."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "psyn_full.json")))
+    q = W.psyn(g["M"], g["r"], g["d"], seed=g["seed"])
+    assert [r.nrows for r in q.rels] == g["rows"]
+    opts = dict(bits_per_key=8, k=6, block_bits=512, passes=2, seed=g["seed"])
+    plan = make_plan(q, **opts)
+    for _ in range(2):
+        plan.build_filters()
+        surv = plan.sieve(survivors=True)
+        cnt, chk = plan.join()
+        assert cnt == g["r"] * g["d"] ** 3 == g["count"]
+        assert chk == g["checksum"]
+        # no false negatives: the r shared values survive with their d rows each
+        assert all(s >= g["r"] * g["d"] for s in surv), surv
+    tup = plan.result()
+    vals = [plan.rels[i].cols[0][tup[:, i].long()] for i in range(3)]
+    assert bool(torch.equal(vals[0], vals[1])) and bool(torch.equal(vals[1], vals[2]))
+    t = tup.long()
+    d = t[1:] - t[:-1]
+    first = torch.where(d[:, 0] != 0, d[:, 0], torch.where(d[:, 1] != 0, d[:, 1], d[:, 2]))
+    assert bool((first > 0).all()), "tuples are not strictly increasing"

@@ -27,3 +27,20 @@ def test_config4_device_path_equals_numpy_path():
     b = W.config4(scale=1 / 256, device="cpu")
     for x, y in zip(a.rels[0].cols, b.rels[0].cols):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("index", range(10))
+def test_serving_query_gpu_path_equals_cpu_path(index):
+    """The serving mix's device path (run here on the CPU device) draws exactly the
+    columns of its numpy path, for chains and stars, skewed and uniform keys."""
+    from workloads import serving as S
+    sp = S.draw_spec(0x5EED0005, index, 0, min_rows=1000, max_rows=30_000)
+    if index == 0:
+        sp = S.QuerySpec(sp.index, 0, sp.kind, sp.rows, 0.0, sp.seed)   # uniform keys
+    q = S.query_cpu(sp)
+    rels, edges = S.query_gpu(sp, device="cpu")
+    assert edges == q.edges
+    for rel, (cols, pred) in zip(q.rels, rels):
+        assert pred == rel.pred
+        for a, b in zip(rel.cols, cols):
+            assert np.array_equal(a, b.numpy())

@@ -14,9 +14,11 @@ A query whose exact result count exceeds a cap is redrawn from the next stream o
 its seed chain (`redraw`).
 
 Columns are generated either with numpy on the CPU (`query_cpu`, for checks against
-the oracle) or with torch on the GPU (`query_gpu`, for large mixes); the two draw
-from different random streams but the same distributions. Nothing here computes any
-part of the join or the filters.
+the oracle) or with the large steps on the GPU (`query_gpu`, for large mixes). Both
+take the same numpy draws (uniforms, integers, permutations) and the same float64 Zipf
+CDF, so their columns are identical; `query_gpu` only moves the inverse-CDF searches and
+the permutation gathers to the device. Nothing here computes any part of the join or
+the filters.
 """
 from __future__ import annotations
 
@@ -26,7 +28,7 @@ from typing import List, Tuple
 
 import numpy as np
 
-from . import Query, Relation, rng_for, zipf_ranks
+from . import Query, Relation, _zipf_cdf, rng_for, zipf_ranks
 
 DOMAIN = 1 << 22
 KEEP = 0.10
@@ -106,40 +108,42 @@ def query_cpu(spec: QuerySpec) -> Query:
 
 # ---------------------------------------------------------------- torch (GPU)
 
-def _zipf_gpu(torch, g, n: int, domain: int, s: float, device):
+def _ranks_dev(torch, rng, n: int, domain: int, s: float, device):
+    """zipf_ranks(rng, n, domain, s) with the search on `device`: the same draws and CDF."""
     if s == 0.0:
-        return torch.randint(0, domain, (n,), generator=g, device=device)
-    w = torch.arange(1, domain + 1, dtype=torch.float64, device=device).pow_(-s)
-    cdf = torch.cumsum(w, 0)
-    cdf /= cdf[-1].clone()
-    u = torch.rand(n, generator=g, dtype=torch.float64, device=device)
-    return torch.searchsorted(cdf, u, right=True).clamp_(max=domain - 1)
+        return torch.from_numpy(rng.integers(0, domain, size=n, dtype=np.int64)).to(device)
+    cdf = torch.from_numpy(_zipf_cdf(domain, s)).to(device)
+    u = torch.from_numpy(rng.random(n)).to(device)
+    r = torch.searchsorted(cdf, u, right=True)
+    del u, cdf
+    return r.clamp_(max=domain - 1)
 
 
 def query_gpu(spec: QuerySpec, device="cuda:0"):
-    """(relations, edges) with relations as [(list of int32 device tensors, pred)]."""
+    """(relations, edges) with relations as [(list of int32 device tensors, pred)]; the
+    columns equal query_cpu(spec)'s."""
     import torch
-    g = torch.Generator(device=device)
-    g.manual_seed(spec.seed)
     n = len(spec.rows)
     rels = []
     if spec.kind == "chain":
         for t in range(n):
             cols = []
-            for _ in range(2):
-                r = _zipf_gpu(torch, g, spec.rows[t], DOMAIN, spec.s, device)
-                perm = torch.randperm(DOMAIN, generator=g, device=device)
+            for c in range(2):
+                r = _ranks_dev(torch, rng_for(spec.seed, t, c, 0), spec.rows[t], DOMAIN, spec.s, device)
+                perm = torch.from_numpy(rng_for(spec.seed, t, c, 1).permutation(DOMAIN)).to(device)
                 cols.append(perm[r].to(torch.int32).contiguous())
+                del r, perm
             rels.append((cols, None))
     else:
         fcols = []
         for j in range(1, n):
-            r = _zipf_gpu(torch, g, spec.rows[0], spec.rows[j], spec.s, device)
-            perm = torch.randperm(spec.rows[j], generator=g, device=device)
+            r = _ranks_dev(torch, rng_for(spec.seed, 0, j, 0), spec.rows[0], spec.rows[j], spec.s, device)
+            perm = torch.from_numpy(rng_for(spec.seed, 0, j, 1).permutation(spec.rows[j])).to(device)
             fcols.append(perm[r].to(torch.int32).contiguous())
+            del r, perm
         rels.append((fcols, None))
         for j in range(1, n):
-            pk = torch.randperm(spec.rows[j], generator=g, device=device).to(torch.int32)
-            attr = torch.randperm(spec.rows[j], generator=g, device=device).to(torch.int32)
+            pk = torch.from_numpy(rng_for(spec.seed, j, 0, 1).permutation(spec.rows[j]).astype(np.int32)).to(device)
+            attr = torch.from_numpy(rng_for(spec.seed, j, 1, 1).permutation(spec.rows[j]).astype(np.int32)).to(device)
             rels.append(([pk, attr], (1, 0, int(round(KEEP * spec.rows[j])))))
     return rels, spec.edges()
