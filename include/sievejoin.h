@@ -318,6 +318,26 @@ sj_status sj_profile_entry(const sj_plan_t *plan, int32_t i, const char **label,
 /* Collect, then zero every total. */
 sj_status sj_profile_reset(sj_plan_t *plan);
 
+/* ---- batches: many queries recorded into one graph (extension) ----
+ *
+ * A batch holds up to SJ_MAX_BATCH bound plans made on one context. sj_batch_submit
+ * enqueues the whole query of every plan (sj_build_filters, sj_sieve, sj_join_async and,
+ * for plans given an output, sj_result_async in `mode`) as one HIP graph in which the
+ * plans run side by side, and replays it on the context's stream; the graph is
+ * recorded on the first submit and again when the outputs, capacities or mode change.
+ * Each plan's count, checksum and result status then come from sj_join_wait, and are
+ * those of the plan run alone (the launches and their arguments are the same). Plans
+ * must be acyclic or 3-cycles (count only: give them no output), not profiled and not
+ * attached to a filter catalogue; they must stay alive and bound until the batch is
+ * destroyed, and must not be used on their own while a submit of the batch is running.
+ * out_dev may be NULL (counts only) or hold NULL entries. */
+
+#define SJ_MAX_BATCH 256
+typedef struct sj_batch sj_batch;
+sj_status sj_batch_create(sj_ctx *ctx, sj_plan_t *const *plans, int32_t n, sj_batch **out);
+sj_status sj_batch_submit(sj_batch *batch, int32_t *const *out_dev, const uint64_t *capacity_tuples, int32_t mode);
+sj_status sj_batch_destroy(sj_batch *batch);
+
 /* ---- serving: continuous admission of join queries (extension) ----
  *
  * A server runs many queries of the kind sj_plan accepts on one GPU at once. It owns

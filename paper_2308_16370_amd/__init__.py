@@ -50,7 +50,8 @@ EXPORTED = ["sj_ctx_create", "sj_ctx_set_stream", "sj_ctx_destroy", "sj_last_err
             "sj_server_destroy", "sj_fcache_create", "sj_plan_use_filter_cache", "sj_plan_filter_cached",
             "sj_fcache_invalidate", "sj_fcache_clear", "sj_fcache_stats", "sj_fcache_destroy",
             "sj_server_use_filter_cache", "sj_filter_probe", "sj_filter_insert", "sj_plan_set_projection",
-            "sj_plan_footprint", "sj_bind_static_workspace"]
+            "sj_plan_footprint", "sj_bind_static_workspace", "sj_batch_create", "sj_batch_submit",
+            "sj_batch_destroy"]
 SJ_FLAG_PROFILE = 1
 SJ_FLAG_EAGER = 2
 SJ_FLAG_BINARY_CYCLES = 4
@@ -152,6 +153,9 @@ def lib():
             "sj_plan_set_projection": [V, V, i32],
             "sj_plan_footprint": [V, i32, P(u64), P(u64), P(i32)],
             "sj_bind_static_workspace": [V],
+            "sj_batch_create": [V, V, i32, P(V)],
+            "sj_batch_submit": [V, V, V, i32],
+            "sj_batch_destroy": [V],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -423,6 +427,39 @@ class Plan:
         h = getattr(self, "handle", None)
         if h and _lib is not None:
             _lib.sj_plan_destroy(h)
+            self.handle = None
+
+
+class Batch:
+    """sj_batch: the whole query of every plan (all made on `ctx`) recorded into one graph
+    and replayed by submit(); each plan's count, checksum and status then come from its
+    join_wait(). The plans are kept alive by the batch."""
+
+    def __init__(self, ctx: Context, plans: Sequence[Plan]):
+        self.ctx = ctx
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        self.handle = ctypes.c_void_p()
+        ctx._check(lib().sj_batch_create(ctx.handle, arr, len(self.plans), ctypes.byref(self.handle)))
+
+    def submit(self, outs: Optional[Sequence[Optional[torch.Tensor]]] = None, mode: int = SJ_RIDS) -> None:
+        """Enqueue every plan's query; outs[i] (int32 [capacity, width] or None) receives
+        plan i's tuples."""
+        n = len(self.plans)
+        if outs is None:
+            self.ctx._check(lib().sj_batch_submit(self.handle, None, None, mode))
+            return
+        ptrs = (ctypes.c_void_p * n)(*[(o.data_ptr() if o is not None and o.numel() else None) for o in outs])
+        caps = (ctypes.c_uint64 * n)(*[(o.numel() // max(1, p.width(mode)) if o is not None else 0)
+                                       for o, p in zip(outs, self.plans)])
+        self.ctx._check(lib().sj_batch_submit(self.handle, ptrs, caps, mode))
+        for p in self.plans:
+            p.count = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.sj_batch_destroy(h)
             self.handle = None
 
 

@@ -1738,6 +1738,172 @@ extern "C" sj_status sj_plan_footprint(const sj_plan_t *p, int32_t mode, uint64_
     return SJ_OK;
 }
 
+// ---------------------------------------------------------------- batches
+
+// A batch records the whole query of every plan it holds (pruning, count pass, and the
+// materialisation with the count read on the device) into one HIP graph, the plans
+// side by side on lanes forked from one capture stream, and replays it on the
+// context's stream. Recorded on the first submit and again when the outputs change.
+struct sj_batch {
+    sj_ctx *ctx = nullptr;
+    std::vector<sj_plan_t *> plans;
+    std::vector<int32_t *> outs;
+    std::vector<uint64_t> caps;
+    int32_t mode = SJ_RIDS;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+    static constexpr int kLanes = 8;
+    hipStream_t lane[kLanes] = {};
+    hipEvent_t fork = nullptr, join[kLanes] = {};
+    ~sj_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (cap) (void)hipStreamDestroy(cap);
+        for (auto &l : lane)
+            if (l) (void)hipStreamDestroy(l);
+        for (auto &e : join)
+            if (e) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
+        ctx_release(ctx);
+    }
+};
+
+extern "C" sj_status sj_batch_create(sj_ctx *ctx, sj_plan_t *const *plans, int32_t n, sj_batch **out) {
+    if (!ctx || !out || n < 1 || n > SJ_MAX_BATCH || !plans) return fail(ctx, SJ_ERR_INVALID, "a batch holds 1..%d plans", SJ_MAX_BATCH);
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        sj_plan_t *p = plans[i];
+        if (!p) return fail(ctx, SJ_ERR_INVALID, "plan %d is null", i);
+        if (p->ctx != ctx) return fail(ctx, SJ_ERR_INVALID, "plan %d was made on another context", i);
+        if (p->state < kBound) return fail(ctx, SJ_ERR_STATE, "plan %d has no workspace (sj_bind_workspace first)", i);
+        if (p->profile || p->fcache)
+            return fail(ctx, SJ_ERR_UNSUPPORTED, "plan %d: profiling plans and plans attached to a filter catalogue "
+                                                 "are not batched", i);
+        if (!p->cyc_ok || (p->cyclic && !p->tri))
+            return fail(ctx, SJ_ERR_UNSUPPORTED, "plan %d: this cyclic join counts in two host-driven steps", i);
+        if (p->opts.flags & (SJ_FLAG_FAULT_FILTERS | SJ_FLAG_FAULT_SIEVE | SJ_FLAG_FAULT_JOIN | SJ_FLAG_FAULT_RESULT))
+            return fail(ctx, SJ_ERR_DEVICE, "plan %d: injected failure (SJ_FLAG_FAULT_*)", i);
+        for (int j = 0; j < i; ++j) {
+            if (plans[j] == p) return fail(ctx, SJ_ERR_INVALID, "plan %d appears twice", i);
+            const char *a0 = p->ws, *a1 = p->ws + p->ws_bytes, *b0 = plans[j]->ws, *b1 = plans[j]->ws + plans[j]->ws_bytes;
+            if (p->ws_bytes && plans[j]->ws_bytes && a0 < b1 && b0 < a1)
+                return fail(ctx, SJ_ERR_INVALID, "plans %d and %d share workspace memory (they run at the same time)",
+                            j, i);
+        }
+    }
+    sj_batch *b = new (std::nothrow) sj_batch;
+    if (!b) return fail(ctx, SJ_ERR_INVALID, "out of host memory");
+    b->ctx = ctx;
+    ctx->refs.fetch_add(1, std::memory_order_relaxed);
+    b->plans.assign(plans, plans + n);
+    *out = b;
+    return SJ_OK;
+}
+
+// Record every plan's query into one graph (called with b->outs, caps, mode set).
+static sj_status batch_record(sj_batch *b) {
+    sj_ctx *ctx = b->ctx;
+    if (!b->cap) {
+        SJ_HIP(ctx, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+        for (auto &l : b->lane) SJ_HIP(ctx, hipStreamCreateWithFlags(&l, hipStreamNonBlocking));
+        for (auto &e : b->join) SJ_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        SJ_HIP(ctx, hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    }
+    for (sj_plan_t *p : b->plans)
+        if (sj_status st = ensure_branches(p)) return st;
+    SJ_HIP(ctx, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    sj_status st = SJ_OK;
+    const int nl = static_cast<int>(std::min<size_t>(b->plans.size(), sj_batch::kLanes));
+    if (hipEventRecord(b->fork, b->cap) != hipSuccess) st = fail(ctx, SJ_ERR_DEVICE, "batch fork record failed");
+    for (int l = 0; st == SJ_OK && l < nl; ++l)
+        if (hipStreamWaitEvent(b->lane[l], b->fork, 0) != hipSuccess) st = fail(ctx, SJ_ERR_DEVICE, "batch fork failed");
+    for (size_t i = 0; st == SJ_OK && i < b->plans.size(); ++i) {
+        sj_plan_t *p = b->plans[i];
+        p->ls = b->lane[i % sj_batch::kLanes];
+        p->res_out = b->outs[i];
+        p->res_cap = b->caps[i];
+        p->res_mode = b->mode;
+        if ((st = enqueue_build(p)) != SJ_OK) break;
+        if ((st = enqueue_sieve(p)) != SJ_OK) break;
+        if ((st = p->tri ? enqueue_tri(p) : enqueue_join(p)) != SJ_OK) break;
+        if (!p->cyclic && b->outs[i] && (st = enqueue_result_async(p)) != SJ_OK) break;
+    }
+    for (int l = 0; st == SJ_OK && l < nl; ++l) {
+        if (hipEventRecord(b->join[l], b->lane[l]) != hipSuccess ||
+            hipStreamWaitEvent(b->cap, b->join[l], 0) != hipSuccess)
+            st = fail(ctx, SJ_ERR_DEVICE, "batch join failed");
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (st != SJ_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (st != SJ_OK) return st;
+        SJ_HIP(ctx, e);
+    }
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        b->exec = nullptr;
+        SJ_HIP(ctx, ei);
+    }
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_batch_submit(sj_batch *b, int32_t *const *out_dev, const uint64_t *capacity_tuples,
+                                     int32_t mode) {
+    if (!b) return SJ_ERR_INVALID;
+    sj_ctx *ctx = b->ctx;
+    if (mode != SJ_RIDS && mode != SJ_VALUES) return fail(ctx, SJ_ERR_INVALID, "mode must be SJ_RIDS or SJ_VALUES");
+    const size_t n = b->plans.size();
+    std::vector<int32_t *> outs(n, nullptr);
+    std::vector<uint64_t> caps(n, 0);
+    for (size_t i = 0; i < n; ++i) {
+        if (out_dev && out_dev[i]) {
+            if (b->plans[i]->cyclic)
+                return fail(ctx, SJ_ERR_UNSUPPORTED, "plan %zu is cyclic: its tuples need sj_result", i);
+            if (reinterpret_cast<uintptr_t>(out_dev[i]) % 16)
+                return fail(ctx, SJ_ERR_INVALID, "output %zu must be 16-byte aligned", i);
+            outs[i] = out_dev[i];
+            caps[i] = capacity_tuples ? capacity_tuples[i] : 0;
+        }
+        if (b->plans[i]->state < kBound) return fail(ctx, SJ_ERR_STATE, "plan %zu lost its workspace", i);
+    }
+    SJ_HIP(ctx, hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+    if (!b->exec || outs != b->outs || caps != b->caps || mode != b->mode) {
+        b->outs = outs;
+        b->caps = caps;
+        b->mode = mode;
+        if (sj_status st = batch_record(b)) {
+            if (b->exec) (void)hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
+            return st;
+        }
+    }
+    SJ_HIP(ctx, hipGraphLaunch(b->exec, ctx->stream));
+    for (size_t i = 0; i < n; ++i) {   // each plan now holds a device-side count (sj_join_wait)
+        sj_plan_t *p = b->plans[i];
+        p->cyc_counted = false;
+        p->count_on_host = false;
+        p->async_result = outs[i] != nullptr;
+        p->res_out = outs[i];
+        p->res_cap = caps[i];
+        p->res_mode = mode;
+        if (p->gexec[3]) {   // the plan's own recorded materialisation may name other outputs
+            (void)hipGraphExecDestroy(p->gexec[3]);
+            p->gexec[3] = nullptr;
+        }
+        p->state = kJoined;
+    }
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_batch_destroy(sj_batch *b) {
+    delete b;
+    return SJ_OK;
+}
+
 // ---------------------------------------------------------------- filter catalogue
 
 // Canonical signature of relation j's backward filter: everything its bits depend on.

@@ -11,7 +11,9 @@ queries go through sj_server runs over one arena:
                      after the other, each with the whole GPU (latency includes queueing);
   * burst         -- `slots` slots, every query submitted at once;
   * poisson_<f>   -- `slots` slots, Poisson arrivals at f times the one-at-a-time
-                     service rate.
+                     service rate;
+  * batched       -- batches of 16 queries, each recorded once into one graph and
+                     replayed (query templates served again), every result checked.
 A collector consumes each result as its query finishes (checks count and checksum
 against the alone run, which equals the oracle's stored value for the mix when
 tests/golden/serving_mix.json holds it, then releases it). Latency is completion minus submission on
@@ -173,12 +175,57 @@ def serve(queries, arena, slots: int, rate: Optional[float], seed: int = 1, sequ
             "equal_results": mismatches == 0}
 
 
+def batched(queries, batch: int = 16, reps: int = 3, log=print) -> Dict:
+    """The mix in batches of `batch` queries, each batch recorded once into one graph
+    (sj_batch: every query's filters, sieve, count and materialisation side by side) and
+    then replayed `reps` times; the mix's time is the sum of the batches' mean replay
+    times. Every query's count and checksum is checked after each replay (against its
+    alone run and the stored oracle value)."""
+    import torch
+
+    import paper_2308_16370_amd as sj
+
+    total_ms = 0.0
+    batch_ms = []
+    mismatches = 0
+    for b0 in range(0, len(queries), batch):
+        group = queries[b0:b0 + batch]
+        ctx = sj.Context(0)
+        plans = [sj.Plan(ctx, q["rels"], q["edges"], root=0, **q["opts"]) for q in group]
+        outs = [torch.empty((max(1, q["cc"][0]), len(q["rels"])), dtype=torch.int32, device="cuda:0") for q in group]
+        bt = sj.Batch(ctx, plans)
+        bt.submit(outs)                      # records the graph
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            bt.submit(outs)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) / reps * 1e3
+        for q, p in zip(group, plans):
+            got = p.join_wait()
+            if got[:2] != q["cc"] or got[2] != sj.SJ_OK or (q["oracle"] is not None and got[:2] != q["oracle"]):
+                mismatches += 1
+        batch_ms.append(ms)
+        total_ms += ms
+        del bt, plans, outs
+        torch.cuda.empty_cache()
+    tuples = sum(q["spec"].input_tuples for q in queries)
+    out = {"batch": batch, "batches": len(batch_ms), "span_s": round(total_ms / 1e3, 4),
+           "tuples_per_s": tuples / (total_ms / 1e3), "queries_per_s": round(len(queries) / (total_ms / 1e3), 2),
+           "batch_ms_p50": round(_pct(batch_ms, 50), 3), "batch_ms_p99": round(_pct(batch_ms, 99), 3),
+           "equal_results": mismatches == 0}
+    log("# batched (%d per graph): %.3f s for the mix, %.3g tuples/s" % (batch, out["span_s"], out["tuples_per_s"]))
+    return out
+
+
 def run(seed: int = 0x5EED0005, n: int = 256, min_rows: int = 10_000, max_rows: int = 20_000_000,
         slots: int = 8, arena_bytes: int = 24 << 30, lam=(0.5, 0.9, 1.2), count_cap: int = 1 << 26,
         tuned: bool = True, log=print) -> Dict:
     import torch
 
     queries, redraws, pinned = prepare(seed, n, min_rows, max_rows, count_cap, tuned, log)
+    batched(queries[:16], reps=1, log=lambda m: None)   # warm-up
+    bat = batched(queries, log=log)
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda:0")
     torch.cuda.synchronize()
     serve(queries, arena, slots, None)   # warm-up: first launches of every kernel, worker start-up
@@ -197,6 +244,7 @@ def run(seed: int = 0x5EED0005, n: int = 256, min_rows: int = 10_000, max_rows: 
                             "oracle value (tests/golden/serving_mix.json)") if pinned else
                            "no stored oracle values for this mix (results compared with each query alone)",
            "arena_bytes": arena_bytes, "autotuned": tuned, "alone": alone, "one_at_a_time": one, "burst": burst,
+           "batched": bat, "batched_speedup_over_alone": round(bat["tuples_per_s"] / alone["tuples_per_s"], 3),
            "burst_speedup": round(burst["tuples_per_s"] / one["tuples_per_s"], 3)}
     for f in lam:
         r = serve(queries, arena, slots, f * rate, seed=int(f * 1000))

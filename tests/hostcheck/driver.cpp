@@ -471,6 +471,55 @@ void scenario_static() {
     EXPECT(sj_build_filters(r.plan) == SJ_ERR_STATE, "nothing was bound");
 }
 
+void scenario_batch() {
+    std::vector<Query> qs;
+    qs.push_back(chain(3, 3000));
+    qs.push_back(star(4, 5000, 300));
+    qs.push_back(cycle(3, 800));
+    qs.push_back(chain(5, 700));
+    sj_ctx *ctx = nullptr;
+    OK(nullptr, sj_ctx_create(0, nullptr, &ctx));
+    std::vector<sj_plan_t *> plans;
+    std::vector<void *> mem;
+    for (auto &q : qs) {
+        sj_opts o{};
+        sj_plan_t *p = nullptr;
+        uint64_t wsb = 0;
+        OK(ctx, sj_plan(ctx, q.rels.data(), static_cast<int32_t>(q.rels.size()), q.edges.data(),
+                        static_cast<int32_t>(q.edges.size()), &o, &p, &wsb));
+        mem.push_back(dev_alloc(wsb));
+        OK(ctx, sj_bind_workspace(p, mem.back(), wsb));
+        plans.push_back(p);
+    }
+    sj_batch *b = nullptr;
+    OK(ctx, sj_batch_create(ctx, plans.data(), static_cast<int32_t>(plans.size()), &b));
+    std::vector<int32_t *> outs(plans.size(), nullptr);
+    std::vector<uint64_t> caps(plans.size(), 64);
+    for (size_t i = 0; i < plans.size(); ++i) {
+        if (i == 2) continue;   // the 3-cycle: count only
+        mem.push_back(dev_alloc(64 * 8 * 4));
+        outs[i] = static_cast<int32_t *>(mem.back());
+    }
+    for (int rep = 0; rep < 3; ++rep) {
+        OK(ctx, sj_batch_submit(b, outs.data(), caps.data(), rep == 2 ? SJ_VALUES : SJ_RIDS));
+        for (auto *p : plans) {
+            uint64_t c, k;
+            sj_status rs;
+            OK(ctx, sj_join_wait(p, &c, &k, &rs));
+        }
+    }
+    OK(ctx, sj_batch_submit(b, nullptr, nullptr, SJ_RIDS));
+    EXPECT(sj_batch_submit(b, outs.data(), caps.data(), 5) == SJ_ERR_INVALID, "bad mode");
+    outs[2] = outs[0];
+    EXPECT(sj_batch_submit(b, outs.data(), caps.data(), SJ_RIDS) == SJ_ERR_UNSUPPORTED, "cyclic tuples");
+    OK(ctx, sj_batch_destroy(b));
+    sj_plan_t *twice[2] = {plans[0], plans[0]};
+    EXPECT(sj_batch_create(ctx, twice, 2, &b) == SJ_ERR_INVALID, "a plan twice");
+    for (auto *p : plans) sj_plan_destroy(p);
+    sj_ctx_destroy(ctx);
+    for (void *m : mem) std::free(m);
+}
+
 struct Scenario {
     const char *name;
     void (*fn)();
@@ -480,6 +529,7 @@ const Scenario kScenarios[] = {
     {"binary", scenario_binary_tree}, {"chain12", scenario_chain12}, {"sixteen", scenario_sixteen},
     {"cycles", scenario_cycles}, {"updates", scenario_updates}, {"fcache", scenario_fcache},
     {"server", scenario_server}, {"errors", scenario_errors}, {"static", scenario_static},
+    {"batch", scenario_batch},
 };
 
 }  // namespace
