@@ -281,6 +281,49 @@ sj_status sj_filter_probe(sj_plan_t *plan, int32_t f, const int32_t *keys_dev, u
                           uint64_t *missing);
 sj_status sj_filter_insert(sj_plan_t *plan, int32_t f, const int32_t *keys_dev, uint64_t n, uint8_t *contained_dev,
                            uint64_t *inserted);
+/* Propagation of inserted tuples (Section 2.4: a tuple inserted into relation R_i
+ * changes R_i's filter only if the filter does not contain its key yet; otherwise the
+ * search continues from R_i to its adjacent relations). `cols` is a host array of the
+ * relation's ncols device pointers holding n new rows. The new rows that pass rel's
+ * predicate and its children's backward filters insert their key toward rel's parent
+ * into rel's backward filter (probe first, as sj_filter_insert); the keys it did not
+ * hold select the parent's rows (its borrowed columns) whose key toward rel is one of
+ * them and that pass the parent's predicate and its other children's filters; those
+ * insert their key into the parent's backward filter, and so on up to the root's
+ * children. inserted[i] (host, nrels entries, may be NULL) receives how many keys
+ * (with multiplicity) relation i's filter did not hold. The maintained filters have
+ * no false negatives for the grown relations; rel's filter equals a rebuild, an
+ * ancestor's holds a subset of a rebuild's bits (keys that newly pass only through a
+ * false positive are not followed). Needs sj_build_filters first; waits for the stream;
+ * scratch (256-byte aligned, caller-owned) of sj_filter_propagate_scratch bytes. A
+ * filter held in a filter catalogue is refused (SJ_ERR_STATE). */
+sj_status sj_filter_propagate_scratch(const sj_plan_t *plan, int32_t rel, uint64_t n, uint64_t *bytes);
+sj_status sj_filter_propagate(sj_plan_t *plan, int32_t rel, const int32_t *const *cols, uint64_t n, void *scratch_dev,
+                              uint64_t scratch_bytes, uint64_t *inserted);
+
+/* Counting filters (Section 2.4: counting Bloom filters, a counter per position, make
+ * deletions possible). sj_plan_cfilter builds the counting twin of the plan's filter f:
+ * one 4-bit counter per bit position (the same blocks, k, seed and bit pattern), counting
+ * every key the filter's build inserted, with multiplicity; a bit of the plain filter is
+ * set iff its counter is nonzero. counts_dev (caller-owned, 256-byte aligned) holds
+ * nblocks * block_bits / 2 bytes of counters plus 256 bytes of bookkeeping. Counters
+ * saturate at 15 and are then never decremented, so a deletion never clears a bit that a
+ * remaining key needs. sj_cfilter_update adds (sign +1) or removes (sign -1) n keys;
+ * sj_cfilter_probe answers contains(key) as sj_filter_probe does (waits only if missing
+ * is non-NULL); sj_cfilter_export writes the plain filter's words; sj_cfilter_apply
+ * writes them over filter f of a plan with the same shape (until the plan's next build
+ * of f). After inserting and deleting keys without saturation, the exported filter
+ * equals the filter built from the keys that remain. All calls but sj_plan_cfilter
+ * (which reads the filter's block count) are asynchronous on the plan's stream. */
+typedef struct sj_cfilter sj_cfilter;
+sj_status sj_plan_cfilter(sj_plan_t *plan, int32_t f, void *counts_dev, uint64_t bytes, sj_cfilter **out);
+sj_status sj_cfilter_update(sj_cfilter *cf, const int32_t *keys_dev, uint64_t n, int32_t sign);
+sj_status sj_cfilter_probe(sj_cfilter *cf, const int32_t *keys_dev, uint64_t n, uint8_t *contained_dev,
+                           uint64_t *missing);
+sj_status sj_cfilter_export(sj_cfilter *cf, uint32_t *words_dev, uint64_t capacity_words);
+sj_status sj_cfilter_apply(sj_cfilter *cf, sj_plan_t *plan, int32_t f);
+sj_status sj_cfilter_destroy(sj_cfilter *cf);
+
 /* Copy relation rel's final survivor row ids (ascending) into dst_dev (room for
  * capacity); *n receives the count. dst_dev may be NULL to query the count only.
  * Waits for the stream. */

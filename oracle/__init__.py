@@ -17,6 +17,9 @@ What it computes (arXiv 2308.16370):
   ``oracle.c``.
 * ``project``    -- value tuples from row-id tuples (the join result as values, each
   row id replaced by its row's values in the chosen columns).
+* ``cf_update`` / ``cf_export`` / ``propagate`` -- update maintenance (Section 2.4):
+  counting twins of the blocked filters (inserts and deletes) and the propagation of
+  inserted tuples toward the root.
 * ``triangle_cycles`` -- count and checksum of the directed 3-cycle query by
   adjacency intersection (a textbook triangle count), independent of ``hash_join``.
 * ``sieve``      -- the pruning phase (Section 2.2): one backward pass from the
@@ -196,6 +199,84 @@ def bf_insert(words: np.ndarray, keys: np.ndarray, nblocks: int, k: int, block_b
     contained = bf_probe(words, keys, None, nblocks, k, block_bits, seed32)
     new = np.asarray(words, dtype=np.uint32) | bf_build(keys, None, nblocks, k, block_bits, seed32)
     return new, contained
+
+
+# ---------------------------------------------------------------- updates (Section 2.4)
+
+def cf_update(counts: np.ndarray, keys: np.ndarray, sign: int, nblocks: int, k: int, block_bits: int,
+              seed32: int) -> np.ndarray:
+    """Counting filter (Section 2.4: a counter per position makes deletions possible):
+    counts is uint8 [nblocks, block_bits], one counter per bit position of the blocked
+    filter. Each key adds (sign +1) or removes (sign -1) one at each of its k pattern
+    positions (a position repeated in the pattern counts twice). Counters saturate at 15
+    and a saturated counter is never decremented; a counter at 0 is not decremented."""
+    c = counts.copy()
+    for key in np.asarray(keys, dtype=np.int32).tolist():
+        b, pos = bf_pattern(key, nblocks, k, block_bits, seed32)
+        for p in pos:
+            v = int(c[b, p])
+            if v == 15:
+                continue
+            if sign > 0:
+                c[b, p] = v + 1
+            elif v > 0:
+                c[b, p] = v - 1
+    return c
+
+
+def cf_export(counts: np.ndarray) -> np.ndarray:
+    """The plain filter words of a counting filter: bit p of block b is set iff its
+    counter is nonzero (word b * B/32 + p // 32, bit p % 32)."""
+    nb, B = counts.shape
+    bits = (counts > 0).astype(np.uint64).reshape(nb * B // 32, 32)
+    return (bits << np.arange(32, dtype=np.uint64)).sum(axis=1).astype(np.uint32)
+
+
+def propagate(query, filters: Dict[int, Tuple[np.ndarray, int]], rel: int, new_cols: Sequence[np.ndarray],
+              k: int, block_bits: int, seed32: int, root: Optional[int] = None):
+    """Section 2.4: new tuples of relation `rel` (columns new_cols) go into the backward
+    filters from rel toward the root. filters maps each non-root relation j to its
+    backward filter (words, nblocks) on j's key toward its parent. The new rows that
+    pass rel's predicate and its children's filters insert their key into rel's filter;
+    a key the filter did not contain leads to the parent: its rows whose key toward the
+    child is among those keys, that pass its predicate and its other children's filters,
+    insert their own key into its filter, and so on until the root (which has no
+    backward filter). Returns (new filters, keys not contained per relation, counted
+    with multiplicity)."""
+    root = query.root if root is None else root
+    t = JoinTree(len(query.rels), query.edges, root)
+    F = {j: (np.asarray(w, dtype=np.uint32).copy(), nb) for j, (w, nb) in filters.items()}
+    inserted = [0] * len(query.rels)
+    if rel == root or len(new_cols) == 0 or new_cols[0].shape[0] == 0:
+        return F, inserted
+    j, child, missing = rel, None, None
+    while True:
+        R = query.rels[j]
+        cols = [np.asarray(c, dtype=np.int32) for c in (new_cols if child is None else R.cols)]
+        ok = np.ones(cols[0].shape[0], dtype=bool)
+        if child is not None:
+            ok &= np.isin(cols[t.pcol[child]], missing)
+        if R.pred is not None:
+            pc, lo, hi = R.pred
+            ok &= (cols[pc].astype(np.int64) >= lo) & (cols[pc].astype(np.int64) < hi)
+        for c in t.children[j]:
+            if c == child:
+                continue
+            w, nb = F[c]
+            ok &= bf_probe(w, cols[t.pcol[c]], None, nb, k, block_bits, seed32)
+        keys = cols[t.mycol[j]][ok]
+        if keys.shape[0] == 0:
+            break
+        w, nb = F[j]
+        neww, contained = bf_insert(w, keys, nb, k, block_bits, seed32)
+        F[j] = (neww, nb)
+        inserted[j] = int((~contained).sum())
+        par = t.parent[j]
+        if inserted[j] == 0 or par == root:
+            break
+        missing = np.unique(keys[~contained])
+        child, j = j, par
+    return F, inserted
 
 
 # ---------------------------------------------------------------- join graph

@@ -51,7 +51,8 @@ EXPORTED = ["sj_ctx_create", "sj_ctx_set_stream", "sj_ctx_destroy", "sj_last_err
             "sj_fcache_invalidate", "sj_fcache_clear", "sj_fcache_stats", "sj_fcache_destroy",
             "sj_server_use_filter_cache", "sj_filter_probe", "sj_filter_insert", "sj_plan_set_projection",
             "sj_plan_footprint", "sj_bind_static_workspace", "sj_batch_create", "sj_batch_submit",
-            "sj_batch_destroy"]
+            "sj_batch_destroy", "sj_filter_propagate_scratch", "sj_filter_propagate", "sj_plan_cfilter",
+            "sj_cfilter_update", "sj_cfilter_probe", "sj_cfilter_export", "sj_cfilter_apply", "sj_cfilter_destroy"]
 SJ_FLAG_PROFILE = 1
 SJ_FLAG_EAGER = 2
 SJ_FLAG_BINARY_CYCLES = 4
@@ -156,6 +157,14 @@ def lib():
             "sj_batch_create": [V, V, i32, P(V)],
             "sj_batch_submit": [V, V, V, i32],
             "sj_batch_destroy": [V],
+            "sj_filter_propagate_scratch": [V, i32, u64, P(u64)],
+            "sj_filter_propagate": [V, i32, V, u64, V, u64, P(u64)],
+            "sj_plan_cfilter": [V, i32, V, u64, P(V)],
+            "sj_cfilter_update": [V, V, u64, i32],
+            "sj_cfilter_probe": [V, V, u64, V, P(u64)],
+            "sj_cfilter_export": [V, V, u64],
+            "sj_cfilter_apply": [V, V, i32],
+            "sj_cfilter_destroy": [V],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -398,6 +407,27 @@ class Plan:
         """Insert keys into filter f in place: (contained before the call, number inserted)."""
         return self._filter_update(lib().sj_filter_insert, f, keys)
 
+    def propagate(self, rel: int, cols: Sequence[torch.Tensor]) -> List[int]:
+        """Insert new rows of relation `rel` (int32 device columns, the relation's full
+        column set) into the backward filters from `rel` toward the root (Section 2.4);
+        returns, per relation, how many keys its filter did not hold."""
+        n = cols[0].numel() if cols else 0
+        for c in cols:
+            if c.dtype != torch.int32 or c.dim() != 1 or c.numel() != n or not c.is_contiguous():
+                raise ValueError("columns must be contiguous 1-D int32 tensors of equal length")
+        nb = ctypes.c_uint64()
+        self._check(lib().sj_filter_propagate_scratch(self.handle, rel, n, ctypes.byref(nb)))
+        scratch = torch.empty(max(256, nb.value), dtype=torch.uint8, device="cuda:%d" % self.ctx.device)
+        ptrs = (ctypes.c_void_p * max(1, len(cols)))(*[c.data_ptr() for c in cols])
+        out = (ctypes.c_uint64 * self.nrels)()
+        self._check(lib().sj_filter_propagate(self.handle, rel, ptrs, n, ctypes.c_void_p(scratch.data_ptr()),
+                                              scratch.numel(), out))
+        return [int(x) for x in out]
+
+    def counting_filter(self, f: int) -> "CountingFilter":
+        """The counting twin of filter f (Section 2.4), built from the keys f was built from."""
+        return CountingFilter(self, f)
+
     def survivors(self, rel: int) -> torch.Tensor:
         n = ctypes.c_uint64()
         self._check(lib().sj_survivors_copy(self.handle, rel, None, 0, ctypes.byref(n)))
@@ -427,6 +457,61 @@ class Plan:
         h = getattr(self, "handle", None)
         if h and _lib is not None:
             _lib.sj_plan_destroy(h)
+            self.handle = None
+
+
+class CountingFilter:
+    """sj_cfilter: 4-bit counters twinning a plan's filter; insert/delete/probe/export."""
+
+    def __init__(self, plan: Plan, f: int):
+        self.plan = plan
+        self.f = f
+        nblocks = plan.filter_desc(f)["nblocks"]
+        self.counts = torch.empty(nblocks * plan.block_bits // 2 + 256, dtype=torch.uint8,
+                                  device="cuda:%d" % plan.ctx.device)
+        self.nwords = nblocks * plan.block_bits // 32
+        self.handle = ctypes.c_void_p()
+        plan._check(lib().sj_plan_cfilter(plan.handle, f, ctypes.c_void_p(self.counts.data_ptr()),
+                                          self.counts.numel(), ctypes.byref(self.handle)))
+
+    def _keys(self, keys: torch.Tensor) -> torch.Tensor:
+        if keys.dtype != torch.int32 or keys.dim() != 1 or not keys.is_contiguous():
+            raise ValueError("keys must be a contiguous 1-D int32 tensor")
+        return keys
+
+    def insert(self, keys: torch.Tensor) -> None:
+        k = self._keys(keys)
+        self.plan._check(lib().sj_cfilter_update(self.handle, ctypes.c_void_p(k.data_ptr()), k.numel(), 1))
+
+    def delete(self, keys: torch.Tensor) -> None:
+        k = self._keys(keys)
+        self.plan._check(lib().sj_cfilter_update(self.handle, ctypes.c_void_p(k.data_ptr()), k.numel(), -1))
+
+    def probe(self, keys: torch.Tensor):
+        k = self._keys(keys)
+        flags = torch.empty(k.numel(), dtype=torch.uint8, device=k.device)
+        miss = ctypes.c_uint64()
+        self.plan._check(lib().sj_cfilter_probe(self.handle, ctypes.c_void_p(k.data_ptr()), k.numel(),
+                                                ctypes.c_void_p(flags.data_ptr()), ctypes.byref(miss)))
+        return flags.bool(), int(miss.value)
+
+    def export(self) -> torch.Tensor:
+        out = torch.empty(self.nwords, dtype=torch.int32, device=self.counts.device)
+        self.plan._check(lib().sj_cfilter_export(self.handle, ctypes.c_void_p(out.data_ptr()), out.numel()))
+        return out
+
+    def apply(self) -> None:
+        """Write the exported bits over the plan's filter."""
+        self.plan._check(lib().sj_cfilter_apply(self.handle, self.plan.handle, self.f))
+
+    def counters(self) -> torch.Tensor:
+        """The counter words (uint32 view, 8 counters of 4 bits each per word)."""
+        return self.counts[: self.nwords * 16].view(torch.int32)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.sj_cfilter_destroy(h)
             self.handle = None
 
 

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsievejoin.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
-SOURCES = ["sj_kernels.hip", "sj_join.hip", "sj_runtime.cpp", "sj_server.cpp", "sj_fcache.cpp", "sj_tri.hip"]
+SOURCES = ["sj_kernels.hip", "sj_join.hip", "sj_runtime.cpp", "sj_server.cpp", "sj_fcache.cpp", "sj_tri.hip",
+           "sj_update.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # keep the compiler from emitting packed FP32 instructions

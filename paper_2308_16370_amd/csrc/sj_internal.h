@@ -92,6 +92,50 @@ struct FilterUpdate {
     int logB;
 };
 hipError_t launch_filter_update(const FilterUpdate &u, bool set, hipStream_t s);
+
+// Counting twins of blocked filters (sj_update.hip): one 4-bit counter per bit position,
+// block b's position p in nibble p % 8 of word b * B / 8 + p / 8; saturating at 15.
+struct CfArgs {
+    uint32_t *counts;
+    uint32_t nblocks;
+    const int32_t *keys;
+    uint64_t n;
+    const int32_t *pred;       // rows with pred < lo or >= hi are skipped (nullptr: none)
+    int32_t pred_lo, pred_hi;
+    uint32_t seed;
+    int k;
+    int logB;
+};
+// sign +1 inserts, -1 deletes; with n_dev the key count is read on the device (n_max bounds it)
+hipError_t launch_cf_update(const CfArgs &a, const uint32_t *n_dev, uint32_t n_max, int sign, hipStream_t s);
+hipError_t launch_cf_probe(const CfArgs &a, uint8_t *contained, unsigned long long *missing, hipStream_t s);
+hipError_t launch_cf_export(const uint32_t *counts, uint64_t nwords, uint32_t *words, hipStream_t s);
+
+// Propagation of inserted tuples toward the root (Section 2.4).
+struct KeySet {
+    uint64_t *slots;           // [mask + 1], zeroed before inserts; nullptr: no set (all rows qualify)
+    uint32_t mask;
+};
+struct PropArgs {
+    uint64_t nrows;
+    const int32_t *match_col;  // key that must be in `set` (nullptr: none)
+    KeySet set;
+    const int32_t *pred;
+    int32_t pred_lo, pred_hi;
+    int nprobe;
+    const int32_t *probe_col[kMaxProbe];
+    FilterRef probe[kMaxProbe];
+    const int32_t *out_col;    // key appended for each qualifying row
+    int32_t *out;
+    uint32_t *out_n;           // zeroed before
+    uint32_t seed;
+    int k;
+    int logB;
+};
+hipError_t launch_propagate_rows(const PropArgs &a, hipStream_t s);
+// Insert keys[i] for every i with !skip[i] (skip may be null) into the set.
+hipError_t launch_set_insert(const KeySet &set, const int32_t *keys, const uint8_t *skip, uint64_t n,
+                             hipStream_t s);
 hipError_t launch_count_pred(const int32_t *col, uint32_t n, int32_t lo, int32_t hi, uint32_t *out,
                              hipStream_t s);
 // A sieve step is two launches: the probe scan (survivor bits and per-workgroup counts)

@@ -2057,6 +2057,276 @@ extern "C" sj_status sj_filter_insert(sj_plan_t *p, int32_t f, const int32_t *ke
     return filter_update(p, f, keys, n, contained, inserted, true);
 }
 
+// ---------------------------------------------------------------- counting filters (Section 2.4)
+
+// The counting twin of a plan's filter: one 4-bit counter per bit position (the filter's
+// blocks, k, seed and bit pattern), in caller memory, followed by 256 bytes for the
+// probe's missing-key count.
+struct sj_cfilter {
+    sj_ctx *ctx = nullptr;
+    uint32_t *counts = nullptr;
+    uint32_t nblocks = 0, k = 0, seed32 = 0;
+    int logB = 9;
+    uint64_t bytes() const { return (static_cast<uint64_t>(nblocks) << logB) / 2; }
+    unsigned long long *missing() const {
+        return reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(counts) + bytes());
+    }
+    CfArgs args(const int32_t *keys, uint64_t n) const {
+        CfArgs a{};
+        a.counts = counts;
+        a.nblocks = nblocks;
+        a.keys = keys;
+        a.n = n;
+        a.seed = seed32;
+        a.k = static_cast<int>(k);
+        a.logB = logB;
+        return a;
+    }
+    ~sj_cfilter() { ctx_release(ctx); }
+};
+
+// The keys a plan inserted into filter f, with their multiplicity: what its build reads.
+struct FilterSource {
+    const int32_t *keys = nullptr;
+    const uint32_t *n_dev = nullptr;
+    uint32_t n = 0, n_max = 0;
+    const int32_t *pred = nullptr;
+    int32_t lo = 0, hi = 0;
+};
+
+static bool filter_source(sj_plan_t *p, int f, FilterSource &src) {
+    for (const StepSpec &st : p->steps) {
+        for (const auto &bl : st.builds) {
+            if (bl.second != f) continue;
+            const Rel &R = p->rels[st.rel];
+            const int jc = bl.first;
+            src.n_max = R.nrows;
+            if (st.out >= 0) {
+                src.keys = list_col(p, st.rel, st.out, jc);
+                src.n_dev = at<uint32_t>(p, st.off_count);
+            } else if (st.src == kFull) {
+                src.keys = R.cols[R.jcols[jc]];
+                src.n = R.nrows;
+                if (R.pred_col >= 0) {
+                    src.pred = R.cols[R.pred_col];
+                    src.lo = R.lo;
+                    src.hi = R.hi;
+                }
+            } else {
+                src.keys = list_col(p, st.rel, st.src, jc);
+                src.n_dev = at<uint32_t>(p, p->steps[st.src_step].off_count);
+            }
+            return true;
+        }
+    }
+    return false;
+}
+
+extern "C" sj_status sj_plan_cfilter(sj_plan_t *p, int32_t f, void *counts_dev, uint64_t bytes, sj_cfilter **out) {
+    if (!p || !out || f < 0 || f >= static_cast<int32_t>(p->filters.size())) return SJ_ERR_INVALID;
+    *out = nullptr;
+    const Filter &F = p->filters[f];
+    if (sj_status st = check_exec(p, F.kind == SJ_FILTER_BACKWARD ? kFiltered : kSieved)) return st;
+    if (reinterpret_cast<uintptr_t>(counts_dev) % 256) return fail(p->ctx, SJ_ERR_INVALID, "counters must be 256-byte aligned");
+    uint32_t nb = 0;
+    SJ_HIP(p->ctx, hipMemcpyAsync(&nb, fnblocks(p, f), 4, hipMemcpyDeviceToHost, p->ctx->stream));
+    SJ_HIP(p->ctx, hipStreamSynchronize(p->ctx->stream));
+    const uint64_t need = (static_cast<uint64_t>(nb) << p->logB) / 2 + 256;
+    if (!counts_dev || bytes < need)
+        return fail(p->ctx, SJ_ERR_NOMEM, "the counting filter of filter %d needs %llu bytes", f,
+                    static_cast<unsigned long long>(need));
+    FilterSource src;
+    if (!filter_source(p, f, src)) return fail(p->ctx, SJ_ERR_INVALID, "internal: filter %d has no build", f);
+    sj_cfilter *c = new (std::nothrow) sj_cfilter;
+    if (!c) return fail(p->ctx, SJ_ERR_INVALID, "out of host memory");
+    c->ctx = p->ctx;
+    p->ctx->refs.fetch_add(1, std::memory_order_relaxed);
+    c->counts = static_cast<uint32_t *>(counts_dev);
+    c->nblocks = nb;
+    c->k = p->opts.k;
+    c->seed32 = p->seed32;
+    c->logB = p->logB;
+    CfArgs a = c->args(src.keys, src.n);
+    a.pred = src.pred;
+    a.pred_lo = src.lo;
+    a.pred_hi = src.hi;
+    hipStream_t s = p->ctx->stream;
+    hipError_t e = launch_zero(c->counts, need, s);
+    if (e == hipSuccess) e = launch_cf_update(a, src.n_dev, src.n_max, +1, s);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(p->ctx, SJ_ERR_DEVICE, "counting filter build failed: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_cfilter_update(sj_cfilter *c, const int32_t *keys_dev, uint64_t n, int32_t sign) {
+    if (!c) return SJ_ERR_INVALID;
+    if ((sign != 1 && sign != -1) || (n && !keys_dev))
+        return fail(c->ctx, SJ_ERR_INVALID, "sign must be +1 (insert) or -1 (delete), keys non-null");
+    SJ_HIP(c->ctx, hipSetDevice(c->ctx->device));
+    SJ_HIP(c->ctx, launch_cf_update(c->args(keys_dev, n), nullptr, 0, sign, c->ctx->stream));
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_cfilter_probe(sj_cfilter *c, const int32_t *keys_dev, uint64_t n, uint8_t *contained_dev,
+                                      uint64_t *missing) {
+    if (!c) return SJ_ERR_INVALID;
+    if (n && (!keys_dev || !contained_dev)) return fail(c->ctx, SJ_ERR_INVALID, "null keys or flags");
+    SJ_HIP(c->ctx, hipSetDevice(c->ctx->device));
+    hipStream_t s = c->ctx->stream;
+    SJ_HIP(c->ctx, launch_zero(c->missing(), 8, s));
+    SJ_HIP(c->ctx, launch_cf_probe(c->args(keys_dev, n), contained_dev, c->missing(), s));
+    if (missing) {
+        SJ_HIP(c->ctx, hipMemcpyAsync(missing, c->missing(), 8, hipMemcpyDeviceToHost, s));
+        SJ_HIP(c->ctx, hipStreamSynchronize(s));
+    }
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_cfilter_export(sj_cfilter *c, uint32_t *words_dev, uint64_t capacity_words) {
+    if (!c) return SJ_ERR_INVALID;
+    const uint64_t words = static_cast<uint64_t>(c->nblocks) << (c->logB - 5);
+    if (!words_dev || capacity_words < words)
+        return fail(c->ctx, SJ_ERR_CAPACITY, "the filter has %llu words", static_cast<unsigned long long>(words));
+    SJ_HIP(c->ctx, hipSetDevice(c->ctx->device));
+    SJ_HIP(c->ctx, launch_cf_export(c->counts, words, words_dev, c->ctx->stream));
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_cfilter_apply(sj_cfilter *c, sj_plan_t *p, int32_t f) {
+    if (!c || !p || f < 0 || f >= static_cast<int32_t>(p->filters.size())) return SJ_ERR_INVALID;
+    const Filter &F = p->filters[f];
+    if (sj_status st = check_exec(p, F.kind == SJ_FILTER_BACKWARD ? kFiltered : kSieved)) return st;
+    if (F.fc_how != 0)
+        return fail(p->ctx, SJ_ERR_STATE, "filter %d is held in a filter catalogue and shared with other plans", f);
+    if (c->ctx->device != p->ctx->device || c->k != p->opts.k || c->logB != p->logB || c->seed32 != p->seed32)
+        return fail(p->ctx, SJ_ERR_INVALID, "the counting filter does not twin filter %d (device, k, block, seed)", f);
+    uint32_t nb = 0;
+    SJ_HIP(p->ctx, hipMemcpyAsync(&nb, fnblocks(p, f), 4, hipMemcpyDeviceToHost, p->ctx->stream));
+    SJ_HIP(p->ctx, hipStreamSynchronize(p->ctx->stream));
+    if (nb != c->nblocks) return fail(p->ctx, SJ_ERR_INVALID, "filter %d has %u blocks, the counting filter %u", f, nb, c->nblocks);
+    SJ_HIP(p->ctx, launch_cf_export(c->counts, static_cast<uint64_t>(nb) << (c->logB - 5), fwords(p, f),
+                                    p->ctx->stream));
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_cfilter_destroy(sj_cfilter *c) {
+    delete c;
+    return SJ_OK;
+}
+
+// ---------------------------------------------------------------- propagation (Section 2.4)
+
+// Scratch of sj_filter_propagate for n new rows of relation rel: a 256-byte counter
+// area, flags and keys for the largest key batch on the path to the root, and a key set
+// of twice that many slots (a power of two).
+static uint64_t propagate_rows_max(const sj_plan_t *p, int rel, uint64_t n) {
+    uint64_t m = n;
+    for (int j = p->parent[rel]; j >= 0 && j != p->root; j = p->parent[j]) m = std::max<uint64_t>(m, p->rels[j].nrows);
+    return m;
+}
+static uint64_t set_cap(uint64_t m) {
+    uint64_t c = 16;
+    while (c < 2 * m + 1) c <<= 1;
+    return c;
+}
+
+extern "C" sj_status sj_filter_propagate_scratch(const sj_plan_t *p, int32_t rel, uint64_t n, uint64_t *bytes) {
+    if (!p || !bytes || rel < 0 || rel >= p->n) return SJ_ERR_INVALID;
+    const uint64_t m = propagate_rows_max(p, rel, n);
+    *bytes = 256 + ((m + 255) & ~uint64_t(255)) + ((4 * m + 255) & ~uint64_t(255)) + 8 * set_cap(m);
+    return SJ_OK;
+}
+
+extern "C" sj_status sj_filter_propagate(sj_plan_t *p, int32_t rel, const int32_t *const *cols, uint64_t n,
+                                         void *scratch, uint64_t scratch_bytes, uint64_t *inserted) {
+    if (!p || rel < 0 || rel >= p->n) return SJ_ERR_INVALID;
+    if (sj_status st = check_exec(p, kFiltered)) return st;
+    if (n > 0x7fffffffull) return fail(p->ctx, SJ_ERR_INVALID, "at most 2^31 - 1 new rows");
+    if (n && !cols) return fail(p->ctx, SJ_ERR_INVALID, "null columns");
+    if (inserted)
+        for (int i = 0; i < p->n; ++i) inserted[i] = 0;
+    if (n == 0 || rel == p->root) return SJ_OK;   // the root has no backward filter
+    uint64_t need = 0;
+    (void)sj_filter_propagate_scratch(p, rel, n, &need);
+    if (!scratch || scratch_bytes < need || reinterpret_cast<uintptr_t>(scratch) % 256)
+        return fail(p->ctx, SJ_ERR_NOMEM, "propagation needs %llu bytes of 256-byte aligned scratch",
+                    static_cast<unsigned long long>(need));
+    for (int j = rel; j >= 0 && j != p->root; j = p->parent[j])
+        if (p->filters[p->f_bwd[j]].fc_how != 0)
+            return fail(p->ctx, SJ_ERR_STATE, "the backward filter of relation %d is held in a filter catalogue", j);
+    const uint64_t m = propagate_rows_max(p, rel, n);
+    char *base = static_cast<char *>(scratch);
+    uint32_t *counter = reinterpret_cast<uint32_t *>(base);                       // [0]: keys out, [2..3]: missing
+    uint8_t *flags = reinterpret_cast<uint8_t *>(base + 256);
+    int32_t *keys = reinterpret_cast<int32_t *>(base + 256 + ((m + 255) & ~uint64_t(255)));
+    KeySet set{reinterpret_cast<uint64_t *>(base + 256 + ((m + 255) & ~uint64_t(255)) + ((4 * m + 255) & ~uint64_t(255))),
+               static_cast<uint32_t>(set_cap(m) - 1)};
+    hipStream_t s = p->ctx->stream;
+    const Rel &R0 = p->rels[rel];
+    int j = rel, from = -1;
+    for (;;) {
+        // the rows of j that now pass: the new rows (first level), or the rows whose key
+        // toward the child `from` is among the keys that child's filter newly holds
+        const Rel &R = p->rels[j];
+        const bool first = from < 0;
+        const int32_t *const *jc = first ? cols : R.cols.data();
+        PropArgs a{};
+        a.nrows = first ? n : R.nrows;
+        a.match_col = first ? nullptr : jc[p->pcol[from]];
+        a.set = first ? KeySet{nullptr, 0} : set;
+        a.pred = R.pred_col >= 0 ? jc[R.pred_col] : nullptr;
+        a.pred_lo = R.lo;
+        a.pred_hi = R.hi;
+        for (int c : p->children[j]) {
+            if (c == from) continue;   // those rows match it by construction
+            a.probe_col[a.nprobe] = jc[p->pcol[c]];
+            a.probe[a.nprobe].words = fwords(p, p->f_bwd[c]);
+            a.probe[a.nprobe].nblocks = fnblocks(p, p->f_bwd[c]);
+            ++a.nprobe;
+        }
+        a.out_col = jc[p->mycol[j]];
+        a.out = keys;
+        a.out_n = counter;
+        a.seed = p->seed32;
+        a.k = static_cast<int>(p->opts.k);
+        a.logB = p->logB;
+        SJ_HIP(p->ctx, launch_zero(counter, 256, s));
+        SJ_HIP(p->ctx, launch_propagate_rows(a, s));
+        uint32_t got = 0;
+        SJ_HIP(p->ctx, hipMemcpyAsync(&got, counter, 4, hipMemcpyDeviceToHost, s));
+        SJ_HIP(p->ctx, hipStreamSynchronize(s));
+        if (got == 0) break;
+        // insert them into j's filter; the ones it did not hold go up to j's parent
+        FilterUpdate u{};
+        const int f = p->f_bwd[j];
+        u.words = fwords(p, f);
+        u.nblocks = fnblocks(p, f);
+        u.keys = keys;
+        u.n = got;
+        u.contained = flags;
+        u.missing = reinterpret_cast<unsigned long long *>(counter + 2);
+        u.seed = p->seed32;
+        u.k = static_cast<int>(p->opts.k);
+        u.logB = p->logB;
+        SJ_HIP(p->ctx, launch_filter_update(u, true, s));
+        unsigned long long miss = 0;
+        SJ_HIP(p->ctx, hipMemcpyAsync(&miss, counter + 2, 8, hipMemcpyDeviceToHost, s));
+        SJ_HIP(p->ctx, hipStreamSynchronize(s));
+        if (inserted) inserted[j] = miss;
+        const int par = p->parent[j];
+        if (miss == 0 || par == p->root) break;
+        SJ_HIP(p->ctx, launch_zero(set.slots, 8 * (static_cast<uint64_t>(set.mask) + 1), s));
+        SJ_HIP(p->ctx, launch_set_insert(set, keys, flags, got, s));
+        from = j;
+        j = par;
+    }
+    (void)R0;
+    return SJ_OK;
+}
+
 extern "C" sj_status sj_survivors_copy(sj_plan_t *p, int32_t rel, uint32_t *dst, uint64_t capacity, uint64_t *n) {
     if (!p || rel < 0 || rel >= p->n || !n) return SJ_ERR_INVALID;
     if (sj_status st = check_exec(p, kSieved)) return st;

@@ -319,6 +319,49 @@ void scenario_updates() {
     std::free(flags);
 }
 
+void scenario_maintain() {
+    Query q = chain(4, 2000);
+    Run r;
+    OK(r.ctx, make_plan(r, q, kGraph, 1));
+    OK(r.ctx, sj_build_filters(r.plan));
+    uint64_t bytes = 0;
+    OK(r.ctx, sj_filter_propagate_scratch(r.plan, 3, 100, &bytes));
+    void *scratch = dev_alloc(bytes);
+    std::vector<int32_t *> cols;
+    for (int c = 0; c < 2; ++c) cols.push_back(static_cast<int32_t *>(dev_alloc(400, 16)));
+    std::vector<const int32_t *> cptr(cols.begin(), cols.end());
+    uint64_t ins[4];
+    OK(r.ctx, sj_filter_propagate(r.plan, 3, cptr.data(), 100, scratch, bytes, ins));
+    EXPECT(sj_filter_propagate(r.plan, 3, cptr.data(), 100, scratch, bytes - 1, ins) == SJ_ERR_NOMEM, "small scratch");
+    OK(r.ctx, sj_filter_propagate(r.plan, 0, cptr.data(), 100, scratch, bytes, ins));   // the root: nothing
+    int32_t nf = 0;
+    OK(r.ctx, sj_filter_count(r.plan, &nf));
+    for (int f = 0; f < nf; ++f) {
+        // the model's counts read back as zero blocks: a counting filter of one block's worth
+        sj_cfilter *cf = nullptr;
+        void *counts = dev_alloc(4096);
+        const sj_status st = sj_plan_cfilter(r.plan, f, counts, 4096, &cf);
+        EXPECT(st == SJ_OK, "sj_plan_cfilter -> %d (%s)", st, sj_last_error(r.ctx));
+        if (cf) {
+            OK(r.ctx, sj_cfilter_update(cf, cptr[0], 100, +1));
+            OK(r.ctx, sj_cfilter_update(cf, cptr[0], 100, -1));
+            EXPECT(sj_cfilter_update(cf, cptr[0], 100, 2) == SJ_ERR_INVALID, "sign");
+            void *flags = dev_alloc(128);
+            uint64_t miss = 0;
+            OK(r.ctx, sj_cfilter_probe(cf, cptr[0], 100, static_cast<uint8_t *>(flags), &miss));
+            void *words = dev_alloc(4096);
+            OK(r.ctx, sj_cfilter_export(cf, static_cast<uint32_t *>(words), 1024));
+            OK(r.ctx, sj_cfilter_apply(cf, r.plan, f));
+            OK(r.ctx, sj_cfilter_destroy(cf));
+            std::free(flags);
+            std::free(words);
+        }
+        std::free(counts);
+    }
+    for (auto *c : cols) std::free(c);
+    std::free(scratch);
+}
+
 void scenario_fcache() {
     Query q = chain(4, 1500);
     const uint64_t arena_bytes = 1 << 20;
@@ -529,7 +572,7 @@ const Scenario kScenarios[] = {
     {"binary", scenario_binary_tree}, {"chain12", scenario_chain12}, {"sixteen", scenario_sixteen},
     {"cycles", scenario_cycles}, {"updates", scenario_updates}, {"fcache", scenario_fcache},
     {"server", scenario_server}, {"errors", scenario_errors}, {"static", scenario_static},
-    {"batch", scenario_batch},
+    {"batch", scenario_batch}, {"maintain", scenario_maintain},
 };
 
 }  // namespace

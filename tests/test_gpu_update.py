@@ -113,3 +113,99 @@ def test_propagating_appended_rows_along_a_chain():
     must2 = torch.from_numpy(np.unique(q.rels[1].cols[0][joins2])).cuda()
     ok2, miss2 = plan.filter_probe(fb[1], must2)
     assert miss2 == 0
+
+
+def revived_chain(seed):
+    """A 4-chain whose leaf holds only keys below 50 on its joining column, so the parent
+    rows with keys 50..99 dangle until new leaf rows bring those keys (propagation then
+    climbs several levels)."""
+    q = W.chain(4, [1500, 1200, 900, 600], 100, 0.0, seed)
+    q.rels[3].cols[0] = (q.rels[3].cols[0] % 50).astype(np.int32)
+    return q
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_propagate_parity(seed):
+    """sj_filter_propagate leaves exactly the oracle's backward filters (oracle.propagate)
+    and reports the same counts of keys each filter did not hold."""
+    q = revived_chain(0x5EED0D10 + seed) if seed < 2 else W.star(3000, 3, 400, 0.5, 0x5EED0D10 + seed)
+    rel = 3 if seed < 2 else 1 + seed % 3
+    plan = built_plan(q, passes=1)
+    seed32 = oracle.filter_seed(OPTS["seed"])
+    _, F = oracle.sieve(q, bits_per_key=8, k=6, block_bits=512, passes=1, seed=OPTS["seed"], root=q.root)
+    bwd = {j: F[("bwd", j)] for (kind, j) in F if kind == "bwd"}
+    rng = np.random.default_rng(seed)
+    nnew = 200
+    if seed < 2:
+        new_cols = [rng.integers(50, 100, size=nnew).astype(np.int32), rng.integers(0, 100, size=nnew).astype(np.int32)]
+    else:
+        dim = q.rels[rel]
+        new_cols = [rng.integers(400, 500, size=nnew).astype(np.int32), rng.integers(0, 400, size=nnew).astype(np.int32)]
+    F2, want = oracle.propagate(q, bwd, rel, new_cols, 6, 512, seed32)
+    got = plan.propagate(rel, [torch.from_numpy(c).to("cuda:0") for c in new_cols])
+    assert got == want
+    if seed < 2:
+        assert sum(1 for x in want if x) >= 2, want   # several levels
+    for f in range(plan.filter_count()):
+        d = plan.filter_desc(f)
+        if d["kind"] != sj.SJ_FILTER_BACKWARD:
+            continue
+        words, nb = F2[d["index"]]
+        assert d["nblocks"] == nb
+        assert np.array_equal(plan.filter_words(f).cpu().numpy().view(np.uint32), words), d
+
+
+def gpu_counters(cf, nb, B=512):
+    """uint8 [nblocks, B] from the counter words (nibble p % 8 of word b * B / 8 + p / 8)."""
+    w = cf.counters().cpu().numpy().view(np.uint32).reshape(nb, B // 8)
+    out = np.empty((nb, B), dtype=np.uint8)
+    for t in range(8):
+        out[:, t::8] = (w >> (4 * t)) & 15
+    return out
+
+
+@pytest.mark.parametrize("kind", ["chain", "star"])
+def test_counting_filter_parity(kind):
+    """The counting twin of every backward filter: its support is the plan's filter,
+    its counters equal the oracle's for the keys the filter was built from, and after
+    deleting a third of those keys and inserting others the counters, the exported
+    filter and the plan's filter after apply() equal the oracle's."""
+    q = W.chain(3, [4000, 3000, 2500], 3000, 0.3, 0x5EED0D20) if kind == "chain" else \
+        W.star(6000, 3, 800, 0.4, 0x5EED0D21)
+    plan = built_plan(q, passes=1)
+    seed32 = oracle.filter_seed(OPTS["seed"])
+    _, F = oracle.sieve(q, bits_per_key=8, k=6, block_bits=512, passes=1, seed=OPTS["seed"], root=q.root)
+    t = oracle.JoinTree(len(q.rels), q.edges, q.root)
+    rng = np.random.default_rng(1)
+    for f in range(plan.filter_count()):
+        d = plan.filter_desc(f)
+        if d["kind"] != sj.SJ_FILTER_BACKWARD:
+            continue
+        j, nb = d["index"], d["nblocks"]
+        # the keys the build inserted: rows of j passing its predicate and children's filters
+        R = q.rels[j]
+        ok = np.ones(R.nrows, dtype=bool)
+        if R.pred is not None:
+            pc, lo, hi = R.pred
+            ok &= (R.cols[pc] >= lo) & (R.cols[pc] < hi)
+        for c in t.children[j]:
+            w, nbc = F[("bwd", c)]
+            ok &= oracle.bf_probe(w, R.cols[t.pcol[c]], None, nbc, 6, 512, seed32)
+        keys = R.cols[t.mycol[j]][ok]
+        cf = plan.counting_filter(f)
+        want = oracle.cf_update(np.zeros((nb, 512), dtype=np.uint8), keys, +1, nb, 6, 512, seed32)
+        assert np.array_equal(gpu_counters(cf, nb), want)
+        assert np.array_equal(cf.export().cpu().numpy().view(np.uint32), plan.filter_words(f).cpu().numpy().view(np.uint32))
+        gone = keys[rng.random(keys.shape[0]) < 0.33]
+        extra = rng.integers(-2**31, 2**31, size=100).astype(np.int32)
+        cf.delete(torch.from_numpy(gone).to("cuda:0"))
+        cf.insert(torch.from_numpy(extra).to("cuda:0"))
+        want = oracle.cf_update(oracle.cf_update(want, gone, -1, nb, 6, 512, seed32), extra, +1, nb, 6, 512, seed32)
+        assert np.array_equal(gpu_counters(cf, nb), want)
+        words = oracle.cf_export(want)
+        assert np.array_equal(cf.export().cpu().numpy().view(np.uint32), words)
+        flags, miss = cf.probe(torch.from_numpy(keys).to("cuda:0"))
+        assert miss == int((~oracle.bf_probe(words, keys, None, nb, 6, 512, seed32)).sum())
+        cf.apply()
+        assert np.array_equal(plan.filter_words(f).cpu().numpy().view(np.uint32), words)
+        del cf

@@ -34,7 +34,7 @@ def checker(tmp_path_factory):
 
 @pytest.mark.parametrize("scenario", ["chain", "star", "bushy", "binary", "chain12", "sixteen", "cycles",
                                       "updates", "fcache", "server", "errors", "static",
-                                      "batch"])
+                                      "batch", "maintain"])
 def test_scenario_clean_under_sanitizers(checker, scenario):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:halt_on_error=1",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
