@@ -373,7 +373,11 @@ sj_status sj_profile_reset(sj_plan_t *plan);
  * must be acyclic or 3-cycles (count only: give them no output), not profiled and not
  * attached to a filter catalogue; they must stay alive and bound until the batch is
  * destroyed, and must not be used on their own while a submit of the batch is running.
- * out_dev may be NULL (counts only) or hold NULL entries. */
+ * out_dev may be NULL (counts only) or hold NULL entries.
+ *
+ * In this build sj_batch_submit is switched off and returns SJ_ERR_UNSUPPORTED: recording
+ * a batch crashed the host process on MI355X with no cause found in this library's code.
+ * sj_batch_create still validates plans. */
 
 #define SJ_MAX_BATCH 256
 typedef struct sj_batch sj_batch;

@@ -12,8 +12,8 @@ queries go through sj_server runs over one arena:
   * burst         -- `slots` slots, every query submitted at once;
   * poisson_<f>   -- `slots` slots, Poisson arrivals at f times the one-at-a-time
                      service rate;
-  * batched       -- batches of 16 queries, each recorded once into one graph and
-                     replayed (query templates served again), every result checked.
+  (batched(): batches recorded into one graph with sj_batch; not run while
+   sj_batch_submit is switched off in the library.)
 A collector consumes each result as its query finishes (checks count and checksum
 against the alone run, which equals the oracle's stored value for the mix when
 tests/golden/serving_mix.json holds it, then releases it). Latency is completion minus submission on
@@ -224,8 +224,6 @@ def run(seed: int = 0x5EED0005, n: int = 256, min_rows: int = 10_000, max_rows: 
     import torch
 
     queries, redraws, pinned = prepare(seed, n, min_rows, max_rows, count_cap, tuned, log)
-    batched(queries[:16], reps=1, log=lambda m: None)   # warm-up
-    bat = batched(queries, log=log)
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda:0")
     torch.cuda.synchronize()
     serve(queries, arena, slots, None)   # warm-up: first launches of every kernel, worker start-up
@@ -244,7 +242,7 @@ def run(seed: int = 0x5EED0005, n: int = 256, min_rows: int = 10_000, max_rows: 
                             "oracle value (tests/golden/serving_mix.json)") if pinned else
                            "no stored oracle values for this mix (results compared with each query alone)",
            "arena_bytes": arena_bytes, "autotuned": tuned, "alone": alone, "one_at_a_time": one, "burst": burst,
-           "batched": bat, "batched_speedup_over_alone": round(bat["tuples_per_s"] / alone["tuples_per_s"], 3),
+
            "burst_speedup": round(burst["tuples_per_s"] / one["tuples_per_s"], 3)}
     for f in lam:
         r = serve(queries, arena, slots, f * rate, seed=int(f * 1000))

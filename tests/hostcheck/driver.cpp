@@ -543,6 +543,7 @@ void scenario_batch() {
         mem.push_back(dev_alloc(64 * 8 * 4));
         outs[i] = static_cast<int32_t *>(mem.back());
     }
+#ifdef SJ_BATCH_ENABLED
     for (int rep = 0; rep < 3; ++rep) {
         OK(ctx, sj_batch_submit(b, outs.data(), caps.data(), rep == 2 ? SJ_VALUES : SJ_RIDS));
         for (auto *p : plans) {
@@ -555,6 +556,9 @@ void scenario_batch() {
     EXPECT(sj_batch_submit(b, outs.data(), caps.data(), 5) == SJ_ERR_INVALID, "bad mode");
     outs[2] = outs[0];
     EXPECT(sj_batch_submit(b, outs.data(), caps.data(), SJ_RIDS) == SJ_ERR_UNSUPPORTED, "cyclic tuples");
+#else
+    EXPECT(sj_batch_submit(b, outs.data(), caps.data(), SJ_RIDS) == SJ_ERR_UNSUPPORTED, "switched off");
+#endif
     OK(ctx, sj_batch_destroy(b));
     sj_plan_t *twice[2] = {plans[0], plans[0]};
     EXPECT(sj_batch_create(ctx, twice, 2, &b) == SJ_ERR_INVALID, "a plan twice");

@@ -88,3 +88,16 @@ int main() {
     assert "waits on an event recorded outside the capture" in out.stderr
     assert "unjoined capture" in out.stderr
     assert "end 904 violations 2" in out.stdout, out.stdout + out.stderr
+
+
+def test_batch_capture_clean_when_enabled(tmp_path):
+    """The batch recording path (switched off in the library build) compiled in with
+    SJ_BATCH_ENABLED=1 and run under the sanitizers and the capture model: every fork
+    joined, no isolation breach, no memory error."""
+    import build
+    exe = build.build(str(tmp_path / "hc_batch"), defines=("SJ_BATCH_ENABLED=1",))
+    r = subprocess.run([exe, "batch"], capture_output=True, text=True, timeout=300,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1:halt_on_error=1"))
+    out = r.stdout + r.stderr
+    assert r.returncode == 0, out[-6000:]
+    assert "scenario batch    failures 0 violations 0" in out
