@@ -58,9 +58,18 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_ghist(KeySrc ks, const ui
 // Pass control: ctl[p] = pass p moves data (its digit is not constant); ctl[8 + p] =
 // where pass p reads (0: the list, 1: buffer 0, 2: buffer 1); ctl[16] = where the
 // sorted data ends up. One thread per pass finds whether a bin holds every key.
-__global__ void k_radix_ctl(const uint32_t *ghist, const uint32_t *n_ptr, int npasses, uint32_t *ctl) {
+// Also sizes the directory's hash index from the entry count (the distinct keys are at
+// most that many): the smallest power of two above twice the entries, within the
+// index's capacity, so the index is at most half full.
+__global__ void k_radix_ctl(const uint32_t *ghist, const uint32_t *n_ptr, int npasses, uint32_t *ctl,
+                            uint32_t *slot_mask, uint32_t slot_cap) {
     __shared__ uint32_t s_act[kRadixPasses];
     const uint32_t n = *n_ptr;
+    if (threadIdx.x == 0) {
+        uint32_t cap = 16;
+        while (cap < 2u * n + 1u && cap < slot_cap) cap <<= 1;
+        *slot_mask = (cap < slot_cap ? cap : slot_cap) - 1;
+    }
     const int p = threadIdx.x >> 5, l = threadIdx.x & 31;   // 32 threads per pass
     uint32_t mx = 0;
     if (p < npasses)
@@ -231,6 +240,8 @@ struct ListRef {
     int ncol;
 };
 
+// Gather the list into bucket order, and clear the directory's hash index (sized by
+// k_radix_ctl) for k_dir_heads, which fills it.
 __global__ void k_gather(ListRef l, const uint32_t *n_ptr, SortScratch ss, Buckets b) {
     const uint32_t n = *n_ptr;
     const uint32_t fin = ss.ctl[16];
@@ -240,6 +251,8 @@ __global__ void k_gather(ListRef l, const uint32_t *n_ptr, SortScratch ss, Bucke
         b.rid[e] = l.rid[li];
         for (int c = 0; c < l.ncol; ++c) b.col[c][e] = l.col[c][li];
     }
+    const uint32_t lim = *b.slot_mask + 1u;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < lim; i += gridDim.x * blockDim.x) b.slots[i] = 0;
 }
 
 // Directory: ordered compaction of the bucket heads (first entry of each key).
@@ -274,11 +287,18 @@ __global__ __launch_bounds__(kSieveBlock) void k_dir_heads(Buckets b, Lookback l
         }
         __syncthreads();
         uint32_t o = s_base + off;
+        const uint32_t mask = *b.slot_mask;
 #pragma unroll
         for (int i = 0; i < kSieveItems; ++i) {
             if (flags & (1u << i)) {
                 b.dir_begin[o] = e0 + i;
                 b.dir_key[o] = kv[i];
+                // the key's hash slot (the index was cleared by k_gather and is at most half full)
+                const uint64_t val = (static_cast<uint64_t>(o + 1) << 32) | static_cast<uint32_t>(kv[i]);
+                uint32_t sl = slot_hash(kv[i]) & mask;
+                while (atomicCAS(reinterpret_cast<unsigned long long *>(b.slots + sl), 0ull,
+                                 static_cast<unsigned long long>(val)) != 0ull)
+                    sl = (sl + 1) & mask;
                 ++o;
             }
         }
@@ -304,19 +324,6 @@ __global__ void k_slots_clear(Buckets b) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < lim; i += gridDim.x * blockDim.x) b.slots[i] = 0;
 }
 
-__global__ void k_dir_insert(Buckets b) {
-    const uint32_t nd = *b.ndir;
-    const uint32_t mask = *b.slot_mask;
-    for (uint32_t d = blockIdx.x * blockDim.x + threadIdx.x; d < nd; d += gridDim.x * blockDim.x) {
-        const int32_t key = b.dir_key[d];
-        const uint64_t val = (static_cast<uint64_t>(d + 1) << 32) | static_cast<uint32_t>(key);
-        uint32_t s = slot_hash(key) & mask;
-        while (atomicCAS(reinterpret_cast<unsigned long long *>(b.slots + s), 0ull,
-                         static_cast<unsigned long long>(val)) != 0ull)
-            s = (s + 1) & mask;
-    }
-}
-
 hipError_t launch_build_buckets(const uint32_t *list_rid, const int32_t *const *list_cols, int ncol,
                                 const uint32_t *list_count, int key_col, int sec_col, const Buckets &b,
                                 const SortScratch &ss, Lookback lb_dir, hipStream_t s) {
@@ -336,7 +343,8 @@ hipError_t launch_build_buckets(const uint32_t *list_rid, const int32_t *const *
     // few workgroups: every workgroup adds its histogram to the same 256 x passes counters
     hipLaunchKernelGGL(k_radix_ghist, dim3(grid_for(cap, 256 * 16, 128)), dim3(kRadixBlock), 0, s, ks,
                        list_count, ss.ghist);
-    hipLaunchKernelGGL(k_radix_ctl, dim3(1), dim3(256), 0, s, ss.ghist, list_count, npasses, ss.ctl);
+    hipLaunchKernelGGL(k_radix_ctl, dim3(1), dim3(256), 0, s, ss.ghist, list_count, npasses, ss.ctl, b.slot_mask,
+                       b.slot_cap);
     const uint32_t scan_len_max = kRadixBins * tiles;
     const uint32_t scan_grid = grid_for(scan_len_max, kScanTile, 256);
     for (int p = 0; p < npasses; ++p) {
@@ -349,12 +357,10 @@ hipError_t launch_build_buckets(const uint32_t *list_rid, const int32_t *const *
     l.rid = list_rid;
     l.ncol = ncol;
     for (int c = 0; c < kMaxJCols; ++c) l.col[c] = c < ncol ? list_cols[c] : nullptr;
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(cap, 256 * 4, 4096)), dim3(256), 0, s, l, list_count, ss, b);
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(cap > b.slot_cap / 2 ? cap : b.slot_cap / 2, 256 * 4, 4096)), dim3(256),
+                       0, s, l, list_count, ss, b);
     const uint32_t dgrid = grid_for(cap, kSieveTile, 256);   // each workgroup claims tiles from one counter
     hipLaunchKernelGGL(k_dir_heads, dim3(dgrid), dim3(kSieveBlock), 0, s, b, lb_dir);
-    hipLaunchKernelGGL(k_dir_mask, dim3(1), dim3(64), 0, s, b);
-    hipLaunchKernelGGL(k_slots_clear, dim3(grid_for(b.slot_cap, 256 * 8, 4096)), dim3(256), 0, s, b);
-    hipLaunchKernelGGL(k_dir_insert, dim3(grid_for(cap, 256 * 4, 4096)), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 
