@@ -18,7 +18,7 @@ import oracle
 import paper_2308_16370_amd as sj
 import workloads as W
 from workloads import serving as S
-from sjtest import to_device
+from sjtest import lexsort_rows, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -245,6 +245,39 @@ def test_served_value_tuples(mix):
             assert info["state"] == sj.SJ_QUERY_DONE, info
             want = oracle.project(m[1], m[4].astype(np.uint32))
             assert np.array_equal(srv.result(t).cpu().numpy(), want)
+            srv.release(t)
+    finally:
+        srv.close()
+
+
+def test_stored_mix_sample_served_equals_oracle():
+    """The measured serving mix at its stated sizes (rows in [10^4, 2*10^7]): its 24
+    smallest queries, served together, return the count and checksum that the oracle
+    stored for them (tests/golden/serving_mix.json, written by make_serving_golden.py
+    with oracle.join_tree_dp), and every tuple of oracle.hash_join (their results hold
+    at most a few thousand tuples)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "serving_mix.json")) as fh:
+        doc = json.load(fh)
+    ents = sorted(doc["queries"], key=lambda e: sum(e["rows"]))[:24]
+    specs = [S.draw_spec(doc["seed"], e["index"], e["draw"], min_rows=doc["min_rows"], max_rows=doc["max_rows"])
+             for e in ents]
+    for sp, e in zip(specs, ents):
+        assert (sp.kind, list(sp.rows)) == (e["kind"], list(e["rows"])), e["index"]
+    srv = sj.Server(8 << 30, slots=4)
+    try:
+        tickets = []
+        for sp in specs:
+            rel_t, edges = S.query_gpu(sp)
+            tickets.append(srv.submit([sj.Rel(c, p) for c, p in rel_t], edges, root=0, **OPTS))
+        for sp, e, t in zip(specs, ents, tickets):
+            info = srv.info(t, wait=True)
+            assert info["state"] == sj.SJ_QUERY_DONE, (e["index"], info)
+            assert (info["count"], info["checksum"]) == (e["count"], e["checksum"]), e["index"]
+            got = srv.result(t).cpu().numpy().astype(np.int64)
+            want, _, _ = oracle.hash_join(S.query_cpu(sp))
+            assert np.array_equal(lexsort_rows(got), lexsort_rows(np.asarray(want, dtype=np.int64))), e["index"]
             srv.release(t)
     finally:
         srv.close()
