@@ -22,6 +22,8 @@ What it computes (arXiv 2308.16370):
   inserted tuples toward the root.
 * ``triangle_cycles`` -- count and checksum of the directed 3-cycle query by
   adjacency intersection (a textbook triangle count), independent of ``hash_join``.
+* ``clique4``    -- count and checksum of the 4-clique query (Section 3.1.3) by a
+  generic join over its four variables, independent of ``hash_join``.
 * ``sieve``      -- the pruning phase (Section 2.2): one backward pass from the
   right-most relation to the root, each relation probed by the filters of the
   relations after it and building the filter on its own join attribute from its
@@ -100,6 +102,9 @@ def lib():
                                               ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64)]
             L.orc_triangle_cycles.restype = ctypes.c_int
+            L.orc_clique4.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64)]
+            L.orc_clique4.restype = ctypes.c_int
             L.orc_result_checksum.argtypes = [ctypes.c_void_p]
             L.orc_result_checksum.restype = ctypes.c_uint64
             L.orc_result_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
@@ -417,6 +422,90 @@ def triangle_cycles(src: np.ndarray, dst: np.ndarray, e1: Optional[Tuple[np.ndar
         raise MemoryError("orc_triangle_cycles")
     return int(cnt.value), int(chk.value)
 
+
+
+# ---------------------------------------------------------------- 4-cliques
+
+def clique4_roles(query, root: Optional[int] = None):
+    """The variables of a 4-clique query, or None if the query is not one.
+
+    Join edges put (relation, column) pairs into variables (classes of columns that
+    must be equal). A 4-clique query has six relations and four variables; every
+    relation joins on exactly two columns, of two different variables, and the six
+    relations hold the six different pairs. The root's two variables are a and b (its
+    lower join column first); c and d are the other two, ordered by their first
+    (relation, column). Returns [(relation, column of x, column of y)] for the pairs
+    (x, y) = ab, ac, ad, bc, bd, cd."""
+    root = query.root if root is None else root
+    if len(query.rels) != 6:
+        return None
+    up = {}
+
+    def find(u):
+        while up.setdefault(u, u) != u:
+            u = up[u]
+        return u
+
+    for a, ca, b, cb in query.edges:
+        ra, rb = find((a, ca)), find((b, cb))
+        if ra != rb:
+            up[max(ra, rb)] = min(ra, rb)
+    used = {}
+    for a, ca, b, cb in query.edges:
+        used.setdefault(a, set()).add(ca)
+        used.setdefault(b, set()).add(cb)
+    if sorted(used) != list(range(6)) or any(len(c) != 2 for c in used.values()):
+        return None
+    var = {u: find(u) for u in list(up)}
+    classes = sorted(set(var.values()))
+    if len(classes) != 4:
+        return None
+    pair_rel = {}
+    for r in range(6):
+        c0, c1 = sorted(used[r])
+        v0, v1 = var[(r, c0)], var[(r, c1)]
+        key = frozenset((v0, v1))
+        if v0 == v1 or key in pair_rel:
+            return None
+        pair_rel[key] = (r, {v0: c0, v1: c1})
+    c0, c1 = sorted(used[root])
+    A, B = var[(root, c0)], var[(root, c1)]
+    C, D = [v for v in classes if v not in (A, B)]
+    out = []
+    for x, y in ((A, B), (A, C), (A, D), (B, C), (B, D), (C, D)):
+        r, cols = pair_rel[frozenset((x, y))]
+        out.append((r, cols[x], cols[y]))
+    return out
+
+
+def clique4(query, root: Optional[int] = None) -> Tuple[int, int]:
+    """Count and checksum of a 4-clique query (Section 3.1.3) by a generic join over
+    its variables (oracle.c, section 5), each relation's rows restricted to its
+    predicate. Independent of ``hash_join``, which enumerates the same result along a
+    spanning tree and checks the closing edges."""
+    roles = clique4_roles(query, root)
+    if roles is None:
+        raise ValueError("not a 4-clique query")
+    keep = []
+    n = (ctypes.c_int64 * 6)()
+    xs = (ctypes.c_void_p * 6)()
+    ys = (ctypes.c_void_p * 6)()
+    ids = (ctypes.c_void_p * 6)()
+    rel = (ctypes.c_uint32 * 6)()
+    for i, (r, cx, cy) in enumerate(roles):
+        R = query.rels[r]
+        sel = eligible(R)
+        x = np.ascontiguousarray(np.asarray(R.cols[cx], dtype=np.int32)[sel])
+        y = np.ascontiguousarray(np.asarray(R.cols[cy], dtype=np.int32)[sel])
+        sid = np.ascontiguousarray(sel, dtype=np.uint32)
+        keep += [x, y, sid]
+        n[i] = sel.shape[0]
+        xs[i], ys[i], ids[i] = _ptr(x), _ptr(y), _ptr(sid)
+        rel[i] = r
+    cnt, chk = ctypes.c_int64(), ctypes.c_uint64()
+    if lib().orc_clique4(n, xs, ys, ids, rel, ctypes.byref(cnt), ctypes.byref(chk)) != 0:
+        raise MemoryError("orc_clique4")
+    return int(cnt.value), int(chk.value)
 
 def default_projection(query) -> List[Tuple[int, int]]:
     """Every column of every relation, relations in index order."""

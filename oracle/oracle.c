@@ -423,3 +423,131 @@ int orc_triangle_cycles(int64_t n, const int32_t *src, const int32_t *dst, int64
     *checksum = chk;
     return 0;
 }
+
+/* ---------------------------------------------------------------- 5. 4-cliques */
+
+/*
+ * The 4-clique query over six binary relations (Section 3.1.3 runs it on an edge
+ * list): relation XY holds pairs (x, y) of two of the four variables a, b, c, d, and
+ * a result tuple is one row of each of AB, AC, AD, BC, BD, CD that agree on every
+ * variable. Written as a generic join in the variable order a, b, c, d: for each AB
+ * row (a, b), each AC row with that a gives c and each AD row with that a gives d;
+ * BC, BD and CD then contribute every row holding (b, c), (b, d) and (c, d). Their
+ * rows are grouped per pair (count and sum of checksum factors), so one lookup stands
+ * for all of them. rel[6] are the relations' indices in the query (their checksum
+ * factors); each relation comes as n rows of (x, y, row id), x the earlier variable.
+ */
+typedef struct {
+    uint64_t key;   /* (x << 32) | y as unsigned words */
+    uint64_t cnt;
+    uint64_t fsum;
+} pairagg_t;
+
+static int u64_cmp(const void *x, const void *y)
+{
+    const uint64_t a = *(const uint64_t *)x, b = *(const uint64_t *)y;
+    return a < b ? -1 : (a > b);
+}
+
+static uint64_t pair_of(int32_t x, int32_t y)
+{
+    return ((uint64_t)(uint32_t)x << 32) | (uint32_t)y;
+}
+
+/* rows grouped per pair; returns the number of distinct pairs, -1 on no memory */
+static int64_t pairs_build(int64_t n, const int32_t *x, const int32_t *y, const uint32_t *id, uint32_t rel,
+                           pairagg_t **out)
+{
+    uint64_t *tmp = (uint64_t *)malloc((size_t)(n ? n : 1) * 2 * sizeof(uint64_t));
+    pairagg_t *p = (pairagg_t *)malloc((size_t)(n ? n : 1) * sizeof(pairagg_t));
+    if (!tmp || !p) {
+        free(tmp);
+        free(p);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; ++i) {   /* (pair, factor) records sorted by pair */
+        tmp[2 * i] = pair_of(x[i], y[i]);
+        tmp[2 * i + 1] = orc_chk_factor(rel, id[i]);
+    }
+    qsort(tmp, (size_t)n, 2 * sizeof(uint64_t), u64_cmp);
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (m == 0 || p[m - 1].key != tmp[2 * i]) {
+            p[m].key = tmp[2 * i];
+            p[m].cnt = 0;
+            p[m].fsum = 0;
+            ++m;
+        }
+        p[m - 1].cnt += 1;
+        p[m - 1].fsum += tmp[2 * i + 1];
+    }
+    free(tmp);
+    *out = p;
+    return m;
+}
+
+static const pairagg_t *pairs_find(const pairagg_t *p, int64_t m, uint64_t key)
+{
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (p[mid].key < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < m && p[lo].key == key) ? &p[lo] : 0;
+}
+
+int orc_clique4(const int64_t *n, const int32_t *const *x, const int32_t *const *y, const uint32_t *const *id,
+                const uint32_t *rel, int64_t *count, uint64_t *checksum)
+{
+    /* order: 0 AB, 1 AC, 2 AD, 3 BC, 4 BD, 5 CD */
+    adj_t *ac = (adj_t *)malloc((size_t)(n[1] ? n[1] : 1) * sizeof(adj_t));
+    adj_t *ad = (adj_t *)malloc((size_t)(n[2] ? n[2] : 1) * sizeof(adj_t));
+    pairagg_t *bc = 0, *bd = 0, *cd = 0;
+    const int64_t mbc = pairs_build(n[3], x[3], y[3], id[3], rel[3], &bc);
+    const int64_t mbd = pairs_build(n[4], x[4], y[4], id[4], rel[4], &bd);
+    const int64_t mcd = pairs_build(n[5], x[5], y[5], id[5], rel[5], &cd);
+    int rc = -1;
+    if (!ac || !ad || mbc < 0 || mbd < 0 || mcd < 0) goto done;
+    for (int64_t i = 0; i < n[1]; ++i) {
+        ac[i].key = x[1][i]; ac[i].nbr = y[1][i]; ac[i].id = id[1][i];
+    }
+    for (int64_t i = 0; i < n[2]; ++i) {
+        ad[i].key = x[2][i]; ad[i].nbr = y[2][i]; ad[i].id = id[2][i];
+    }
+    qsort(ac, (size_t)n[1], sizeof(adj_t), adj_cmp);
+    qsort(ad, (size_t)n[2], sizeof(adj_t), adj_cmp);
+    int64_t cnt = 0;
+    uint64_t chk = 0;
+    for (int64_t r = 0; r < n[0]; ++r) {
+        const int32_t a = x[0][r], b = y[0][r];
+        const uint64_t f0 = orc_chk_factor(rel[0], id[0][r]);
+        const int64_t i0 = adj_lower(ac, 0, n[1], a), i1 = adj_upper(ac, i0, n[1], a);
+        const int64_t j0 = adj_lower(ad, 0, n[2], a), j1 = adj_upper(ad, j0, n[2], a);
+        for (int64_t i = i0; i < i1; ++i) {
+            const int32_t c = ac[i].nbr;
+            const pairagg_t *pbc = pairs_find(bc, mbc, pair_of(b, c));
+            if (!pbc) continue;
+            const uint64_t f1 = f0 * orc_chk_factor(rel[1], ac[i].id) * pbc->fsum;
+            for (int64_t j = j0; j < j1; ++j) {
+                const int32_t d = ad[j].nbr;
+                const pairagg_t *pbd = pairs_find(bd, mbd, pair_of(b, d));
+                if (!pbd) continue;
+                const pairagg_t *pcd = pairs_find(cd, mcd, pair_of(c, d));
+                if (!pcd) continue;
+                cnt += (int64_t)(pbc->cnt * pbd->cnt * pcd->cnt);
+                chk += f1 * orc_chk_factor(rel[2], ad[j].id) * pbd->fsum * pcd->fsum;
+            }
+        }
+    }
+    *count = cnt;
+    *checksum = chk;
+    rc = 0;
+done:
+    free(ac);
+    free(ad);
+    free(bc);
+    free(bd);
+    free(cd);
+    return rc;
+}

@@ -19,6 +19,10 @@ shapes stand in for them):
                    are selected by a range predicate on a second attribute.
 * ``triangle``   -- one directed edge relation E(src, dst) used three times,
                    E1.dst = E2.src, E2.dst = E3.src, E3.dst = E1.src.
+* ``clique3`` / ``clique4`` -- one directed edge relation E(src, dst) used once per
+                   pair of vertex variables (a -> b, a -> c, b -> c for 3-cliques; the
+                   six pairs of a, b, c, d for 4-cliques): the clique queries of the
+                   paper's vote-network experiment (Section 3.1.3).
 * ``psyn``       -- the paper's controlled-intermediate benchmark (Section 3.1.1,
                    "Synthetic Workload"): unary R, S, T over overlapping integer
                    ranges, every value repeated d times.
@@ -34,7 +38,8 @@ import numpy as np
 
 __all__ = [
     "Relation", "Query", "rng_for", "zipf_ranks", "chain", "star", "triangle",
-    "psyn", "config1", "config2", "config3", "config4", "tiny_random",
+    "psyn", "clique3", "clique4", "config1", "config2", "config3", "config4", "config6",
+    "tiny_random",
 ]
 
 
@@ -238,6 +243,29 @@ def triangle(nedges: int, nverts: int, gamma: float, seed: int, name: str = "tri
     return Query(name, rels, edges, 0, dict(kind="triangle", nverts=nverts, gamma=gamma, seed=seed))
 
 
+
+def clique3(src: np.ndarray, dst: np.ndarray, name: str = "clique3") -> Query:
+    """E(a,b) join E(b,c) join E(a,c) over one edge list: relations AB, BC, AC with
+    AB.dst = BC.src, BC.dst = AC.dst and AC.src = AB.src."""
+    rels = [Relation(n, [src, dst]) for n in ("AB", "BC", "AC")]
+    edges = [(0, 1, 1, 0), (1, 1, 2, 1), (2, 0, 0, 0)]
+    return Query(name, rels, edges, 0, dict(kind="clique3"))
+
+
+# relations AB, AC, AD, BC, BD, CD (column 0: the earlier vertex, column 1: the later);
+# each vertex variable joins its three relations by two edges
+CLIQUE4_EDGES = [(0, 0, 1, 0), (0, 0, 2, 0),      # a
+                 (0, 1, 3, 0), (0, 1, 4, 0),      # b
+                 (1, 1, 3, 1), (1, 1, 5, 0),      # c
+                 (2, 1, 4, 1), (2, 1, 5, 1)]      # d
+
+
+def clique4(src: np.ndarray, dst: np.ndarray, name: str = "clique4") -> Query:
+    """The 4-clique query over one edge list: relations AB, AC, AD, BC, BD, CD, each
+    the edge list (x -> y for the pair xy), joined on the shared vertex variables."""
+    rels = [Relation(n, [src, dst]) for n in ("AB", "AC", "AD", "BC", "BD", "CD")]
+    return Query(name, rels, list(CLIQUE4_EDGES), 0, dict(kind="clique4"))
+
 def psyn(M: int, r: int, d: int, seed: int, name: str = "psyn") -> Query:
     """The paper's synthetic R join S join T (Section 3.1.1).
 
@@ -288,6 +316,16 @@ def config4(seed: int = 0x5EED0004, scale: float = 1.0, device: Optional[str] = 
     powerlaw_edges)."""
     return triangle(max(1, int(50_000_000 * scale)), max(8, int((1 << 22) * scale)), 2.1, seed, device=device)
 
+
+
+def config6(seed: int = 0x5EED0006, scale: float = 1.0, k: int = 4) -> Query:
+    """The k-clique query (k = 3 or 4) over a directed power-law (gamma 2.5) edge list of
+    103,663 edges on 7,066 vertices: the size of the paper's vote network (Section
+    3.1.3), which is not available here."""
+    src, dst = powerlaw_edges(max(1, int(103_663 * scale)), max(8, int(7_066 * scale)), 2.5, seed)
+    q = clique4(src, dst) if k == 4 else clique3(src, dst)
+    q.meta.update(nverts=max(8, int(7_066 * scale)), gamma=2.5, seed=seed)
+    return q
 
 def tiny_random(seed: int, kind: str = "any") -> Query:
     """Small random instances for brute-force checks: <=5 relations, <=48 rows, tiny domains.
