@@ -96,6 +96,17 @@ typedef struct {
     uint64_t seed;         /* filter hash seed (0 is a valid seed) */
     int32_t root;          /* -1: relation 0 (the left-most relation) */
     uint32_t flags;        /* SJ_FLAG_* bits; other bits must be 0 */
+    /* Launch shape of the sieve steps (tuning only: results do not depend on them). */
+    uint32_t probe_grid;   /* [256] workgroups of each probe and compaction launch
+                              (1024 threads each, a contiguous share of the rows per
+                              workgroup): a power of two, 64..1024 */
+    uint32_t probe_lds;    /* [0] LDS a probe sets aside for one filter (the smallest it
+                              reads whose size, known on the device only, fits):
+                              0: as much as its filters could need, up to 108 KiB;
+                              1: none, every filter is read through L2 (more
+                              workgroups then fit per compute unit);
+                              2: only when one of its filters fits at its largest
+                              possible size (so the LDS is always used) */
 } sj_opts;
 
 /* Record a HIP event pair around every launch group on the context's stream

@@ -85,7 +85,7 @@ class _Edge(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("bits_per_key", ctypes.c_uint32), ("k", ctypes.c_uint32), ("block_bits", ctypes.c_uint32),
                 ("passes", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("root", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("probe_grid", ctypes.c_uint32), ("probe_lds", ctypes.c_uint32)]
 
 
 class _QueryInfo(ctypes.Structure):
@@ -248,7 +248,7 @@ class Plan:
                  bits_per_key: int = 0, k: int = 0, block_bits: int = 0, passes: int = 0, seed: int = 0,
                  root: int = -1, workspace: Optional[torch.Tensor] = None, profile: bool = False,
                  eager: bool = False, filter_cache: "Optional[FilterCache]" = None, binary_cycles: bool = False,
-                 flags: int = 0, static_workspace: bool = False):
+                 flags: int = 0, static_workspace: bool = False, probe_grid: int = 0, probe_lds: int = 0):
         self.ctx = ctx
         self.block_bits = block_bits or 512
         self.nrels = len(rels)
@@ -257,7 +257,7 @@ class Plan:
         arr, earr, self._keep = _marshal(rels, edges)
         opts = _Opts(bits_per_key, k, block_bits, passes, seed & (2**64 - 1), root,
                      (SJ_FLAG_PROFILE if profile else 0) | (SJ_FLAG_EAGER if eager else 0) |
-                     (SJ_FLAG_BINARY_CYCLES if binary_cycles else 0) | flags)
+                     (SJ_FLAG_BINARY_CYCLES if binary_cycles else 0) | flags, probe_grid, probe_lds)
         wsb = ctypes.c_uint64()
         ctx._check(lib().sj_plan(ctx.handle, arr, len(rels), earr, len(edges), ctypes.byref(opts),
                                  ctypes.byref(self.handle), ctypes.byref(wsb)))

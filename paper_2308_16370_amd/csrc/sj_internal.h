@@ -21,7 +21,8 @@ constexpr int kSieveTile = kSieveBlock * kSieveItems;
 // contiguous run of tiles. With the probe's static LDS (a 32 KB answer cache and 16 KB
 // of live-row lists) that stays within the 160 KB of a CU.
 constexpr int kProbeBlock = 1024;
-constexpr uint32_t kProbeGrid = 256;
+constexpr uint32_t kProbeGrid = 256;       // default workgroups of a probe / compaction launch
+constexpr uint32_t kProbeGridMax = 1024;
 constexpr int kProbeTile = kProbeBlock * kSieveItems;
 constexpr uint32_t kLdsFilterBytes = 108 * 1024;
 
@@ -67,7 +68,8 @@ struct StepArgs {
     int32_t *out_col[kMaxJCols];
     uint32_t *out_count;       // device-side survivor count (written when out_rid != nullptr)
     uint8_t *bits;             // [ceil(rows / 8)] survivor flags of the scan, 8 rows per byte
-    uint32_t *counts;          // [kProbeGrid] survivors per workgroup
+    uint32_t *counts;          // [grid] survivors per workgroup
+    uint32_t grid;             // workgroups of the probe and compaction launches
     uint32_t lds_words;        // LDS words set aside for one probed filter (0: none)
     uint32_t seed;
     int k;
@@ -257,7 +259,7 @@ struct DpArgs {
     uint32_t *blo[kMaxJCols];  // [cap] per child: first entry of the matching child bucket
     uint32_t *bhi[kMaxJCols];  // [cap] per child: one past its last entry (lo = hi: none)
     uint32_t skip_mask;        // children whose totals are not multiplied in (bounds still kept)
-    uint64_t *tile_sums;       // [2 * ceil(cap / dp_tile(nchild))]
+    uint64_t *tile_sums;       // [2 * grid] per-run sums (grid <= ceil(cap / dp_tile(nchild)))
     uint64_t *totals;          // [2] result count and checksum, or nullptr
 };
 hipError_t launch_dp(const DpArgs &a, hipStream_t s);
@@ -346,6 +348,9 @@ struct PairHash {
     // membership bitmap in front of the table: 4 bits per slot in use (>= 8 per pair),
     // one bit per pair; a clear bit answers "absent" without touching the table
     uint32_t *sig;             // [cap / 8] words
+    // bucket position of the pair's first row ([cap + 1]); with the rows sorted by pair,
+    // the pair's rows are the bucket entries [pos, pos + count)
+    uint32_t *pos;
 };
 // Fill `h` from n_dev entries: pair (ca[e], cb[e]), checksum factor of (rel, rid[e]).
 hipError_t launch_pair_build(const PairHash &h, const uint32_t *n_dev, uint32_t cap_rows, const uint32_t *rid,
@@ -379,5 +384,48 @@ struct TriArgs {
     uint64_t *totals;          // [2] count, checksum
 };
 hipError_t launch_tri_count(const TriArgs &a, hipStream_t s);
+
+// 4-cliques by intersection: variables a, b (the root's two join columns), c and d; the
+// other five relations each hold one of the pairs ac, ad, bc, bd, cd. Index h below:
+// 0 ac, 1 ad, 2 bc, 3 bd, 4 cd.
+struct K4Group {               // a relation grouped by its earlier variable (a, a, b, b, c)
+    const uint64_t *slots;     // directory hash index: key -> directory entry
+    const uint32_t *mask, *begin, *rid;
+    const int32_t *other;      // per entry: the later variable (c, d, c, d, d)
+    uint32_t rel;
+};
+struct K4Args {
+    const uint32_t *n_root;
+    uint32_t root_cap;
+    const uint32_t *root_rid;
+    const int32_t *root_a, *root_b;
+    uint32_t rel_root;
+    K4Group g[5];
+    PairHash h[5];             // each relation's (earlier, later) pairs
+    uint32_t *w;               // [root_cap] first-level walk length | (walks bc) << 31
+    uint32_t *beg;             // [root_cap] first entry of the walked group
+    uint64_t *off;             // [root_cap + 1] exclusive prefix of walk lengths
+    uint64_t *tile_sums;       // [tiles(root_cap)]
+    uint64_t *part;            // [2 * kTriBlocks]
+    uint64_t *totals;          // [2] count, checksum
+};
+hipError_t launch_k4_count(const K4Args &a, hipStream_t s);
+
+// Write pass of 3-cycles and 4-cliques by intersection: the count pass's walk again,
+// once counting each lane's tuples and once writing them at the lane's offset (lanes
+// in order, each lane's tuples in walk order). Roles: root, P, L (3-cycles) or root,
+// ac, ad, bc, bd, cd (4-cliques).
+struct CliqueOut {
+    int32_t *out;              // [count, nrels] row ids in relation order, or [count, proj.n] values
+    uint64_t capacity;         // tuples `out` holds (>= count; checked again per tuple)
+    int nrels;
+    Projection proj;           // proj.n == 0: row ids
+    int role_rel[6];           // relation index of each role
+    uint64_t *lane_cnt;        // [kTriBlocks * 256] tuples of each lane
+    uint64_t *block_cnt;       // [kTriBlocks] tuples of each workgroup
+};
+constexpr uint32_t kEmitLanes = kTriBlocks * 256;
+hipError_t launch_tri_emit(const TriArgs &a, const CliqueOut &o, hipStream_t s);
+hipError_t launch_k4_emit(const K4Args &a, const CliqueOut &o, hipStream_t s);
 
 }  // namespace sj

@@ -469,21 +469,32 @@ __device__ __forceinline__ void dp_entries(const DpArgs &a, const uint32_t *mask
         if (base + i * kScanBlock >= n) w[i] = v[i] = 0;
 }
 
-// Phase 1: per-entry weights into cw/cv (not yet scanned) and per-tile sums.
+// Two launches. Workgroup b of the grid owns a contiguous run of tiles. (1) k_dp_reduce
+// writes every entry's weights into cw/cv (not yet scanned) and the run's sums into
+// tile_sums[2b], [2b + 1]. (2) k_dp_down adds the sums of the runs before its own (at
+// most the grid size of them, read by the whole workgroup) and scans its run tile by
+// tile; the last workgroup writes the totals at cw[n], cv[n].
+__device__ __forceinline__ void dp_run(uint32_t ntiles, uint32_t &t0, uint32_t &t1) {
+    const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    t0 = min(ntiles, blockIdx.x * per);
+    t1 = min(ntiles, t0 + per);
+}
+
 template <int ITEMS>
 __global__ __launch_bounds__(kScanBlock) void k_dp_reduce(DpArgs a) {
     constexpr uint32_t T = kScanBlock * ITEMS;
     __shared__ uint64_t s_w[kScanBlock / 64], s_v[kScanBlock / 64];
     const uint32_t n = *a.n;
-    const uint32_t ntiles = (n + T - 1) / T;
+    uint32_t t0, t1;
+    dp_run((n + T - 1) / T, t0, t1);
     uint32_t masks[kMaxJCols];
 #pragma unroll
     for (int c = 0; c < kMaxJCols; ++c) masks[c] = c < a.nchild ? *a.child[c].slot_mask : 0u;
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    uint64_t sw = 0, sv = 0;
+    for (uint32_t tile = t0; tile < t1; ++tile) {
         const uint32_t base = tile * T + threadIdx.x;
         uint64_t w[ITEMS], v[ITEMS];
         dp_entries<ITEMS>(a, masks, base, n, w, v);
-        uint64_t sw = 0, sv = 0;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             if (base + i * kScanBlock < n) {
@@ -493,81 +504,33 @@ __global__ __launch_bounds__(kScanBlock) void k_dp_reduce(DpArgs a) {
             sw += w[i];
             sv += v[i];
         }
-        uint64_t tw, tv;
-        block_excl_scan<kScanBlock>(sw, s_w, tw);
-        block_excl_scan<kScanBlock>(sv, s_v, tv);
-        if (threadIdx.x == 0) {
-            a.tile_sums[2 * tile] = tw;
-            a.tile_sums[2 * tile + 1] = tv;
-        }
+    }
+    uint64_t tw, tv;
+    block_excl_scan<kScanBlock>(sw, s_w, tw);
+    block_excl_scan<kScanBlock>(sv, s_v, tv);
+    if (threadIdx.x == 0) {
+        a.tile_sums[2 * blockIdx.x] = tw;
+        a.tile_sums[2 * blockIdx.x + 1] = tv;
     }
 }
 
-// Phase 2 (one block): exclusive scan of the tile sums; totals at cw[n], cv[n]. Each
-// thread takes kDpTileRun consecutive tile sums per round, so a round covers 2048 tiles.
-constexpr int kDpTileRun = 8;
-
-template <int ITEMS>
-__global__ __launch_bounds__(kScanBlock) void k_dp_tiles(DpArgs a) {
-    constexpr uint32_t T = kScanBlock * ITEMS;
-    __shared__ uint64_t s_w[kScanBlock / 64], s_v[kScanBlock / 64];
-    __shared__ uint64_t s_carry[2];
-    const uint32_t n = *a.n;
-    const uint32_t ntiles = (n + T - 1) / T;
-    if (threadIdx.x == 0) {
-        s_carry[0] = 0;
-        s_carry[1] = 0;
-    }
-    __syncthreads();
-    for (uint32_t t0 = 0; t0 < ntiles; t0 += kScanBlock * kDpTileRun) {
-        const uint32_t tb = t0 + threadIdx.x * kDpTileRun;
-        uint64_t w[kDpTileRun], v[kDpTileRun], sw = 0, sv = 0;
-#pragma unroll
-        for (int j = 0; j < kDpTileRun; ++j) {
-            const uint32_t t = tb + j;
-            w[j] = t < ntiles ? a.tile_sums[2 * t] : 0;
-            v[j] = t < ntiles ? a.tile_sums[2 * t + 1] : 0;
-            sw += w[j];
-            sv += v[j];
-        }
-        uint64_t tw, tv;
-        uint64_t ow = block_excl_scan<kScanBlock>(sw, s_w, tw) + s_carry[0];
-        uint64_t ov = block_excl_scan<kScanBlock>(sv, s_v, tv) + s_carry[1];
-#pragma unroll
-        for (int j = 0; j < kDpTileRun; ++j) {
-            const uint32_t t = tb + j;
-            if (t < ntiles) {
-                a.tile_sums[2 * t] = ow;
-                a.tile_sums[2 * t + 1] = ov;
-            }
-            ow += w[j];
-            ov += v[j];
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            s_carry[0] += tw;
-            s_carry[1] += tv;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        a.cw[n] = s_carry[0];
-        a.cv[n] = s_carry[1];
-        if (a.totals) {
-            a.totals[0] = s_carry[0];
-            a.totals[1] = s_carry[1];
-        }
-    }
-}
-
-// Phase 3: turn per-entry weights into exclusive prefixes.
+// Per-entry weights into exclusive prefixes, run by run.
 template <int ITEMS>
 __global__ __launch_bounds__(kScanBlock) void k_dp_down(DpArgs a) {
     constexpr uint32_t T = kScanBlock * ITEMS;
     __shared__ uint64_t s_w[kScanBlock / 64], s_v[kScanBlock / 64];
     const uint32_t n = *a.n;
-    const uint32_t ntiles = (n + T - 1) / T;
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    uint32_t t0, t1;
+    dp_run((n + T - 1) / T, t0, t1);
+    uint64_t pw = 0, pv = 0;   // sums of the runs before this one
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kScanBlock) {
+        pw += a.tile_sums[2 * b];
+        pv += a.tile_sums[2 * b + 1];
+    }
+    uint64_t cw0, cv0;
+    block_excl_scan<kScanBlock>(pw, s_w, cw0);
+    block_excl_scan<kScanBlock>(pv, s_v, cv0);
+    for (uint32_t tile = t0; tile < t1; ++tile) {
         const uint32_t base = tile * T + threadIdx.x * ITEMS;
         uint64_t w[ITEMS], v[ITEMS];
         uint64_t sw = 0, sv = 0;
@@ -580,8 +543,8 @@ __global__ __launch_bounds__(kScanBlock) void k_dp_down(DpArgs a) {
             sv += v[i];
         }
         uint64_t tw, tv;
-        uint64_t ow = block_excl_scan<kScanBlock>(sw, s_w, tw) + a.tile_sums[2 * tile];
-        uint64_t ov = block_excl_scan<kScanBlock>(sv, s_v, tv) + a.tile_sums[2 * tile + 1];
+        uint64_t ow = block_excl_scan<kScanBlock>(sw, s_w, tw) + cw0;
+        uint64_t ov = block_excl_scan<kScanBlock>(sv, s_v, tv) + cv0;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t e = base + i;
@@ -592,6 +555,17 @@ __global__ __launch_bounds__(kScanBlock) void k_dp_down(DpArgs a) {
             ow += w[i];
             ov += v[i];
         }
+        cw0 += tw;
+        cv0 += tv;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        // every run before this one, and its own: the totals (runs past the last tile are empty)
+        a.cw[n] = cw0;
+        a.cv[n] = cv0;
+        if (a.totals) {
+            a.totals[0] = cw0;
+            a.totals[1] = cv0;
+        }
     }
 }
 
@@ -601,7 +575,6 @@ static void launch_dp_items(const DpArgs &a, hipStream_t s) {
     const uint32_t tiles = (a.cap + T - 1) / T;
     const uint32_t g = tiles == 0 ? 1 : (tiles < kPersistentBlocks ? tiles : kPersistentBlocks);
     hipLaunchKernelGGL(k_dp_reduce<ITEMS>, dim3(g), dim3(kScanBlock), 0, s, a);
-    hipLaunchKernelGGL(k_dp_tiles<ITEMS>, dim3(1), dim3(kScanBlock), 0, s, a);
     hipLaunchKernelGGL(k_dp_down<ITEMS>, dim3(g), dim3(kScanBlock), 0, s, a);
 }
 

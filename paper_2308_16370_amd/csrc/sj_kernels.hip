@@ -100,7 +100,7 @@ hipError_t launch_filter_update(const FilterUpdate &u, bool set, hipStream_t s) 
 }
 
 // ---- the sieve step ------------------------------------------------------------------
-// Two passes with no inter-workgroup waiting. Workgroup b of kProbeGrid owns the rows
+// Two passes with no inter-workgroup waiting. Workgroup b of the grid owns the rows
 // [b * R, (b + 1) * R), R a multiple of kProbeTile. (1) k_sieve_step probes every row
 // and records a survivor bit per row and a survivor count per workgroup. (2)
 // k_sieve_compact sums the counts of the workgroups before it and writes its survivors
@@ -137,7 +137,7 @@ __device__ __forceinline__ uint32_t cache_slot(uint32_t c) { return c >> (32 - k
 __device__ __forceinline__ uint32_t cache_tag(uint32_t c) { return c << kCacheLog; }
 
 __device__ __forceinline__ uint32_t sieve_rows_per_group(uint32_t n) {
-    const uint32_t per = (n + kProbeGrid - 1) / kProbeGrid;
+    const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
     return (per + kProbeTile - 1) / kProbeTile * kProbeTile;
 }
 
@@ -516,7 +516,8 @@ __global__ __launch_bounds__(kProbeBlock) void k_sieve_compact(StepArgs a) {
 
 template <int KMAX, bool EXACT>
 static hipError_t launch_probe_k(const StepArgs &a, hipStream_t s) {
-    const dim3 g(kProbeGrid), b(kProbeBlock);
+    if (a.grid == 0 || a.grid > kProbeGridMax) return hipErrorInvalidValue;
+    const dim3 g(a.grid), b(kProbeBlock);
     const size_t lds = 4ull * a.lds_words;
     switch (a.ncol) {
 #define SJ_PROBE_CASE(NC) \
@@ -541,7 +542,8 @@ hipError_t launch_sieve_probe(const StepArgs &a, uint32_t max_rows, hipStream_t 
 
 hipError_t launch_sieve_compact(const StepArgs &a, uint32_t max_rows, hipStream_t s) {
     if (max_rows == 0 || !a.out_rid) return hipSuccess;
-    const dim3 g(kProbeGrid), b(kProbeBlock);
+    if (a.grid == 0 || a.grid > kProbeGridMax) return hipErrorInvalidValue;
+    const dim3 g(a.grid), b(kProbeBlock);
     switch (a.ncol) {
 #define SJ_COMPACT_CASE(NC) \
     case NC: hipLaunchKernelGGL((k_sieve_compact<NC>), g, b, 0, s, a); break;

@@ -155,9 +155,17 @@ struct sj_plan_s {
     bool cyc_counted = false;                // the binary cyclic count pass ran since the last sieve
     int tri_P = -1;
     uint64_t off_tri_w = 0, off_tri_beg = 0, off_tri_off = 0, off_tri_tiles = 0, off_tri_part = 0;
-    uint64_t pair_cap[2] = {0, 0};           // P's and L's pair hashes
-    uint64_t off_pair_slot[2] = {0, 0}, off_pair_msum[2] = {0, 0}, off_pair_mask[2] = {0, 0};
-    uint64_t off_pair_sig[2] = {0, 0};
+    // 4-cliques counted by intersection (sj_tri.hip): the relations holding the pairs
+    // ac, ad, bc, bd, cd of the variables (a, b: the root's join columns) and, per
+    // relation, the join-column indices of its earlier and later variable
+    bool k4 = false;
+    int k4_rel[5] = {-1, -1, -1, -1, -1}, k4_x[5] = {}, k4_y[5] = {};
+    static constexpr int kPairs = 5;         // pair hashes: P and L of a 3-cycle, or the five above
+    int pair_rel[kPairs] = {-1, -1, -1, -1, -1};
+    uint64_t pair_cap[kPairs] = {};
+    uint64_t off_pair_slot[kPairs] = {}, off_pair_msum[kPairs] = {}, off_pair_mask[kPairs] = {};
+    uint64_t off_pair_sig[kPairs] = {}, off_pair_pos[kPairs] = {};
+    uint64_t off_emit_lane = 0, off_emit_block = 0;   // write pass of 3-cycles and 4-cliques
     int state = kPlanned;
     uint64_t count = 0, checksum = 0;
     // event profiling (SJ_FLAG_PROFILE): one event pair per launch group
@@ -567,7 +575,7 @@ static void build_layout(sj_plan_t *p) {
     for (int b = 0; b < sj_plan_s::kSets; ++b) {
         const uint32_t br = std::max<uint32_t>(1, max_build_rows[b]);
         p->off_sbits[b] = L.take(max_rows[b] / 8 + 16);
-        p->off_scounts[b] = L.take(4ull * kProbeGrid);
+        p->off_scounts[b] = L.take(4ull * kProbeGridMax);
         p->off_bhist[b] = L.take(4 * max_hist[b]);
         p->off_stage[b] = L.take(4ull * br);
         p->off_keep[b] = L.take(8ull * ((uint64_t(br) + 2 * build_tile_of(br)) / 64 + 1));
@@ -621,7 +629,9 @@ static void build_layout(sj_plan_t *p) {
         if (j == p->root) continue;
         auto &r = p->jr[j];
         const uint64_t cap = std::max<uint32_t>(1, p->rels[j].nrows);
-        const bool two_word = p->cyclic && j == p->L;   // bucketed by (tree key, closing key)
+        // bucketed by two keys: (tree key, closing key) for L of a cyclic join, (key, key)
+        // pairs for the relations a 3-cycle or 4-clique walks
+        const bool two_word = (p->cyclic && j == p->L) || (p->tri && j == p->tri_P) || p->k4;
         for (int b = 0; b < 2; ++b) {
             r.sklo[b] = L.take(4 * cap);
             r.skhi[b] = two_word ? L.take(4 * cap) : 0;
@@ -648,25 +658,91 @@ static void build_layout(sj_plan_t *p) {
             p->off_bhi[j].push_back(L.take(4ull * p->rels[j].nrows));
         }
     }
-    if (p->tri) {
+    if (p->tri || p->k4) {
         const uint64_t rn = std::max<uint64_t>(1, rc);
         p->off_tri_w = L.take(4 * rn);
         p->off_tri_beg = L.take(4 * rn);
         p->off_tri_off = L.take(8 * (rc + 1));
         p->off_tri_tiles = L.take(8ull * std::max<uint32_t>(1, tiles_of(static_cast<uint32_t>(rc), kScanTile)));
         p->off_tri_part = L.take(16ull * kTriBlocks);
-        const int rel[2] = {p->tri_P, p->L};
-        for (int h = 0; h < 2; ++h) {
+        if (p->tri) {
+            p->pair_rel[0] = p->tri_P;
+            p->pair_rel[1] = p->L;
+        } else {
+            for (int h = 0; h < 5; ++h) p->pair_rel[h] = p->k4_rel[h];
+        }
+        for (int h = 0; h < sj_plan_s::kPairs; ++h) {
+            if (p->pair_rel[h] < 0) continue;
             uint64_t cap = 16;
-            while (cap < 2ull * p->rels[rel[h]].nrows + 1) cap <<= 1;
+            while (cap < 2ull * p->rels[p->pair_rel[h]].nrows + 1) cap <<= 1;
             p->pair_cap[h] = cap;
             p->off_pair_slot[h] = L.take(16 * (cap + 1));
             p->off_pair_msum[h] = L.take(8 * (cap + 1));
             p->off_pair_mask[h] = L.take(4);
             p->off_pair_sig[h] = L.take(4 * (cap / 8));
+            p->off_pair_pos[h] = L.take(4 * (cap + 1));
         }
+        p->off_emit_lane = L.take(8ull * kEmitLanes);
+        p->off_emit_block = L.take(8ull * kTriBlocks);
     }
     p->ws_bytes = L.top;
+}
+
+// A 4-clique query (Section 3.1.3): six relations that join on two columns each, the
+// join columns falling into four variables (the classes of columns the edges make
+// equal) so that every relation holds a different pair of them. The root's two join
+// columns are the variables a and b; c and d are the other two. Sets p->k4 and the
+// roles of the other five relations when the query has that shape.
+static void detect_k4(sj_plan_t *p) {
+    if (p->n != 6) return;
+    for (const Rel &R : p->rels)
+        if (R.jcols.size() != 2 || R.nrows >= (1u << 30)) return;
+    int up[12];
+    for (int i = 0; i < 12; ++i) up[i] = i;   // node: relation * 2 + join-column index
+    auto find = [&](int u) {
+        while (up[u] != u) u = up[u] = up[up[u]];
+        return u;
+    };
+    for (const sj_edge &e : p->edges) {
+        const int u = find(e.rel_a * 2 + p->rels[e.rel_a].jidx(e.col_a));
+        const int v = find(e.rel_b * 2 + p->rels[e.rel_b].jidx(e.col_b));
+        if (u != v) up[std::max(u, v)] = std::min(u, v);
+    }
+    int var[12], classes[12], nclass = 0;
+    for (int i = 0; i < 12; ++i) {
+        var[i] = find(i);
+        if (std::find(classes, classes + nclass, var[i]) == classes + nclass) classes[nclass++] = var[i];
+    }
+    if (nclass != 4) return;
+    for (int r = 0; r < 6; ++r) {
+        if (var[2 * r] == var[2 * r + 1]) return;
+        for (int q = 0; q < r; ++q)
+            if (std::min(var[2 * q], var[2 * q + 1]) == std::min(var[2 * r], var[2 * r + 1]) &&
+                std::max(var[2 * q], var[2 * q + 1]) == std::max(var[2 * r], var[2 * r + 1]))
+                return;   // two relations on the same pair
+    }
+    const int A = var[2 * p->root], B = var[2 * p->root + 1];
+    int others[2], no = 0;
+    for (int i = 0; i < 4; ++i)
+        if (classes[i] != A && classes[i] != B) others[no++] = classes[i];
+    const int C = others[0], D = others[1];
+    const int role[5][2] = {{A, C}, {A, D}, {B, C}, {B, D}, {C, D}};
+    for (int h = 0; h < 5; ++h) {
+        p->k4_rel[h] = -1;
+        for (int r = 0; r < 6; ++r) {
+            if (var[2 * r] == role[h][0] && var[2 * r + 1] == role[h][1]) {
+                p->k4_rel[h] = r;
+                p->k4_x[h] = 0;
+                p->k4_y[h] = 1;
+            } else if (var[2 * r] == role[h][1] && var[2 * r + 1] == role[h][0]) {
+                p->k4_rel[h] = r;
+                p->k4_x[h] = 1;
+                p->k4_y[h] = 0;
+            }
+        }
+        if (p->k4_rel[h] < 0) return;
+    }
+    p->k4 = true;
 }
 
 extern "C" sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, const sj_edge *edges, int32_t nedges,
@@ -690,6 +766,10 @@ extern "C" sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, con
         return fail(ctx, SJ_ERR_INVALID, "block_bits must be 256, 512 or 1024");
     if (o.passes != 1 && o.passes != 2) return fail(ctx, SJ_ERR_INVALID, "passes must be 1 or 2");
     if (o.root >= nrels) return fail(ctx, SJ_ERR_INVALID, "root out of range");
+    if (o.probe_grid == 0) o.probe_grid = kProbeGrid;
+    if (o.probe_grid < 64 || o.probe_grid > kProbeGridMax || (o.probe_grid & (o.probe_grid - 1)))
+        return fail(ctx, SJ_ERR_INVALID, "probe_grid must be a power of two, 64..%u", kProbeGridMax);
+    if (o.probe_lds > 2) return fail(ctx, SJ_ERR_INVALID, "probe_lds must be 0, 1 or 2");
     if (o.flags & ~static_cast<uint32_t>(SJ_FLAG_PROFILE | SJ_FLAG_EAGER | SJ_FLAG_BINARY_CYCLES |
                                          SJ_FLAG_FAULT_FILTERS | SJ_FLAG_FAULT_SIEVE | SJ_FLAG_FAULT_JOIN |
                                          SJ_FLAG_FAULT_RESULT))
@@ -800,6 +880,7 @@ extern "C" sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, con
             p->tri_P = P;
         }
     }
+    if (p->cyclic && !p->cyc_ok && !(o.flags & SJ_FLAG_BINARY_CYCLES)) detect_k4(p);
     p->region_blocks = kRegionBytes / (o.block_bits / 8);
     for (auto &f : p->filters) {
         const uint64_t nbm = f.max_words / (o.block_bits / 32);
@@ -976,9 +1057,15 @@ static sj_status run_step(sj_plan_t *p, StepSpec &st, hipStream_t s) {
         }
         // LDS for the smallest probed filter that fits (sizes are known on the device only)
         a.lds_words = 0;
-        for (auto &pr : st.probes)
-            a.lds_words = std::max<uint32_t>(a.lds_words, static_cast<uint32_t>(std::min<uint64_t>(
-                                                               p->filters[pr.second].max_words, kLdsFilterBytes / 4)));
+        if (p->opts.probe_lds != 1) {
+            for (auto &pr : st.probes) {
+                const uint64_t mw = p->filters[pr.second].max_words;
+                if (p->opts.probe_lds == 2 && mw > kLdsFilterBytes / 4) continue;
+                a.lds_words = std::max<uint32_t>(a.lds_words,
+                                                 static_cast<uint32_t>(std::min<uint64_t>(mw, kLdsFilterBytes / 4)));
+            }
+        }
+        a.grid = p->opts.probe_grid;
         a.bits = at<uint8_t>(p, p->off_sbits[set]);
         a.counts = at<uint32_t>(p, p->off_scounts[set]);
         a.seed = p->seed32;
@@ -1447,46 +1534,29 @@ static sj_status enqueue_join(sj_plan_t *p) {
 static PairHash pair_hash_of(sj_plan_t *p, int h) {
     PairHash ph{};
     ph.slot = at<PairSlot>(p, p->off_pair_slot[h]);
-    ph.rel = static_cast<uint32_t>(h == 0 ? p->tri_P : p->L);
+    ph.rel = static_cast<uint32_t>(p->pair_rel[h]);
     ph.msum = at<uint64_t>(p, p->off_pair_msum[h]);
     ph.cap = static_cast<uint32_t>(p->pair_cap[h]);
     ph.mask = at<uint32_t>(p, p->off_pair_mask[h]);
     ph.sig = at<uint32_t>(p, p->off_pair_sig[h]);
+    ph.pos = at<uint32_t>(p, p->off_pair_pos[h]);
     return ph;
 }
 
-// Count pass of a 3-cycle root - P - L - root by intersection: P grouped by its key
-// toward the root, L grouped by its closing column, both relations' (key, key) pair
-// hashes, then the balanced walk.
-static sj_status enqueue_tri(sj_plan_t *p) {
-    hipStream_t s = p->ls;
-    if (sj_status st = zero_region(p, 2)) return st;
+// The walk's arguments of a 3-cycle root - P - L - root: P grouped by its key toward
+// the root (x), L by its closing column (y), each sorted by its (key, z) pairs inside
+// the group; bk receives the two relations' buckets.
+static TriArgs tri_args(sj_plan_t *p, Buckets bk[2], int key_col[2], int z_col[2]) {
     const int r = p->root, P = p->tri_P, L = p->L;
     const Closing &cl = p->closing[0];
-    const int rel[2] = {P, L};
-    const int key_col[2] = {p->rels[P].jidx(p->mycol[P]), p->rels[L].jidx(cl.cv)};
-    const int z_col[2] = {p->rels[P].jidx(p->pcol[L]), p->rels[L].jidx(p->mycol[L])};
-    Buckets bk[2];
-    hipStream_t br[2];
-    if (sj_status st = fork_streams(p, 2, br)) return st;
+    key_col[0] = p->rels[P].jidx(p->mycol[P]);
+    key_col[1] = p->rels[L].jidx(cl.cv);
+    z_col[0] = p->rels[P].jidx(p->pcol[L]);
+    z_col[1] = p->rels[L].jidx(p->mycol[L]);
     for (int h = 0; h < 2; ++h) {
-        const int j = rel[h];
-        const int fl = p->final_list[j];
-        const int ncol = static_cast<int>(p->rels[j].jcols.size());
-        std::vector<const int32_t *> lcols(ncol);
-        for (int c = 0; c < ncol; ++c) lcols[c] = list_col(p, j, fl, c);
-        bk[h] = buckets_of(p, j);
+        bk[h] = buckets_of(p, h == 0 ? P : L);
         bk[h].key_jcol = key_col[h];
-        {
-            ProfScope ps(p, std::string("buckets:") + rel_name(j), j, kProfBuckets);
-            SJ_HIP(p->ctx, launch_build_buckets(list_rid(p, j, fl), lcols.data(), ncol, bk[h].n, key_col[h], -1, bk[h],
-                                                sort_scratch(p, j), dir_lookback(p, j), br[h]));
-        }
-        ProfScope ps(p, std::string("pairs:") + rel_name(j));
-        SJ_HIP(p->ctx, launch_pair_build(pair_hash_of(p, h), bk[h].n, bk[h].cap, bk[h].rid, bk[h].col[key_col[h]],
-                                         bk[h].col[z_col[h]], static_cast<uint32_t>(j), br[h]));
     }
-    if (sj_status st = join_streams(p, 2)) return st;
     TriArgs a{};
     const Rel &R = p->rels[r];
     const int fl = p->final_list[r];
@@ -1516,8 +1586,129 @@ static sj_status enqueue_tri(sj_plan_t *p) {
     a.tile_sums = at<uint64_t>(p, p->off_tri_tiles);
     a.part = at<uint64_t>(p, p->off_tri_part);
     a.totals = at<uint64_t>(p, p->off_totals);
+    return a;
+}
+
+// Count pass of a 3-cycle by intersection: the two relations bucketed and their pair
+// hashes built on two branches, then the balanced walk.
+static sj_status enqueue_tri(sj_plan_t *p) {
+    hipStream_t s = p->ls;
+    if (sj_status st = zero_region(p, 2)) return st;
+    Buckets bk[2];
+    int key_col[2], z_col[2];
+    const TriArgs a = tri_args(p, bk, key_col, z_col);
+    const int rel[2] = {p->tri_P, p->L};
+    hipStream_t br[2];
+    if (sj_status st = fork_streams(p, 2, br)) return st;
+    for (int h = 0; h < 2; ++h) {
+        const int j = rel[h];
+        const int fl = p->final_list[j];
+        const int ncol = static_cast<int>(p->rels[j].jcols.size());
+        std::vector<const int32_t *> lcols(ncol);
+        for (int c = 0; c < ncol; ++c) lcols[c] = list_col(p, j, fl, c);
+        {
+            ProfScope ps(p, std::string("buckets:") + rel_name(j), j, kProfBuckets);
+            SJ_HIP(p->ctx, launch_build_buckets(list_rid(p, j, fl), lcols.data(), ncol, bk[h].n, key_col[h],
+                                                z_col[h], bk[h], sort_scratch(p, j), dir_lookback(p, j), br[h]));
+        }
+        ProfScope ps(p, std::string("pairs:") + rel_name(j));
+        SJ_HIP(p->ctx, launch_pair_build(pair_hash_of(p, h), bk[h].n, bk[h].cap, bk[h].rid, bk[h].col[key_col[h]],
+                                         bk[h].col[z_col[h]], static_cast<uint32_t>(j), br[h]));
+    }
+    if (sj_status st = join_streams(p, 2)) return st;
     ProfScope ps(p, "tri_count");
     SJ_HIP(p->ctx, launch_tri_count(a, s));
+    return SJ_OK;
+}
+
+// The walk's arguments of a 4-clique: the five non-root relations grouped by their
+// earlier variable and sorted by their (earlier, later) pairs; bk receives their buckets.
+static K4Args k4_args(sj_plan_t *p, Buckets bk[5]) {
+    K4Args a{};
+    const int r = p->root;
+    const int fl = p->final_list[r];
+    a.n_root = at<uint32_t>(p, p->steps[p->final_step[r]].off_count);
+    a.root_cap = p->rels[r].nrows;
+    a.root_rid = list_rid(p, r, fl);
+    a.root_a = list_col(p, r, fl, 0);
+    a.root_b = list_col(p, r, fl, 1);
+    a.rel_root = static_cast<uint32_t>(r);
+    for (int h = 0; h < 5; ++h) {
+        bk[h] = buckets_of(p, p->k4_rel[h]);
+        bk[h].key_jcol = p->k4_x[h];
+        a.g[h].slots = bk[h].slots;
+        a.g[h].mask = bk[h].slot_mask;
+        a.g[h].begin = bk[h].dir_begin;
+        a.g[h].rid = bk[h].rid;
+        a.g[h].other = bk[h].col[p->k4_y[h]];
+        a.g[h].rel = static_cast<uint32_t>(p->k4_rel[h]);
+        a.h[h] = pair_hash_of(p, h);
+    }
+    a.w = at<uint32_t>(p, p->off_tri_w);
+    a.beg = at<uint32_t>(p, p->off_tri_beg);
+    a.off = at<uint64_t>(p, p->off_tri_off);
+    a.tile_sums = at<uint64_t>(p, p->off_tri_tiles);
+    a.part = at<uint64_t>(p, p->off_tri_part);
+    a.totals = at<uint64_t>(p, p->off_totals);
+    return a;
+}
+
+// Count pass of a 4-clique by intersection: the five non-root relations bucketed and
+// their pair hashes built on branch streams, then the two-level walk from the root's
+// survivors.
+static sj_status enqueue_k4(sj_plan_t *p) {
+    hipStream_t s = p->ls;
+    if (sj_status st = zero_region(p, 2)) return st;
+    Buckets bk[5];
+    const K4Args a = k4_args(p, bk);
+    hipStream_t br[sj_plan_s::kBranches];
+    if (sj_status st = fork_streams(p, sj_plan_s::kBranches, br)) return st;
+    for (int h = 0; h < 5; ++h) {
+        const int j = p->k4_rel[h];
+        const int fl = p->final_list[j];
+        const int ncol = static_cast<int>(p->rels[j].jcols.size());
+        std::vector<const int32_t *> lcols(ncol);
+        for (int c = 0; c < ncol; ++c) lcols[c] = list_col(p, j, fl, c);
+        hipStream_t bs = br[h % sj_plan_s::kBranches];
+        {
+            ProfScope ps(p, std::string("buckets:") + rel_name(j), j, kProfBuckets);
+            SJ_HIP(p->ctx, launch_build_buckets(list_rid(p, j, fl), lcols.data(), ncol, bk[h].n, p->k4_x[h],
+                                                p->k4_y[h], bk[h], sort_scratch(p, j), dir_lookback(p, j), bs));
+        }
+        ProfScope ps(p, std::string("pairs:") + rel_name(j));
+        SJ_HIP(p->ctx, launch_pair_build(pair_hash_of(p, h), bk[h].n, bk[h].cap, bk[h].rid, bk[h].col[p->k4_x[h]],
+                                         bk[h].col[p->k4_y[h]], static_cast<uint32_t>(j), bs));
+    }
+    if (sj_status st = join_streams(p, sj_plan_s::kBranches)) return st;
+    ProfScope ps(p, "k4_count");
+    SJ_HIP(p->ctx, launch_k4_count(a, s));
+    return SJ_OK;
+}
+
+// Write pass of a 3-cycle or 4-clique counted by intersection (the count pass's walk
+// and buckets are still in the workspace).
+static sj_status clique_write(sj_plan_t *p, int32_t *out, uint64_t capacity, const Projection &pr) {
+    CliqueOut o{};
+    o.out = out;
+    o.capacity = capacity;
+    o.nrels = p->n;
+    o.proj = pr;
+    o.lane_cnt = at<uint64_t>(p, p->off_emit_lane);
+    o.block_cnt = at<uint64_t>(p, p->off_emit_block);
+    ProfScope ps(p, "clique_write", -1, kProfResult);
+    if (p->tri) {
+        o.role_rel[0] = p->root;
+        o.role_rel[1] = p->tri_P;
+        o.role_rel[2] = p->L;
+        Buckets bk[2];
+        int key_col[2], z_col[2];
+        SJ_HIP(p->ctx, launch_tri_emit(tri_args(p, bk, key_col, z_col), o, p->ctx->stream));
+    } else {
+        o.role_rel[0] = p->root;
+        for (int h = 0; h < 5; ++h) o.role_rel[h + 1] = p->k4_rel[h];
+        Buckets bk[5];
+        SJ_HIP(p->ctx, launch_k4_emit(k4_args(p, bk), o, p->ctx->stream));
+    }
     return SJ_OK;
 }
 
@@ -1549,16 +1740,16 @@ static sj_status binary_cyclic_count(sj_plan_t *p, uint64_t tot[2]) {
 extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) {
     if (sj_status st = check_exec(p, kSieved)) return st;
     if (sj_status st = injected(p, SJ_FLAG_FAULT_JOIN, "sj_join")) return st;
-    if (!p->cyc_ok)
+    if (!p->cyc_ok && !p->k4)
         return fail(p->ctx, SJ_ERR_UNSUPPORTED,
                     "cyclic join: every closing edge must end at the last relation of the preorder (relation %d), "
-                    "on one column",
+                    "on one column, or the query must be a 4-clique",
                     p->L);
     hipStream_t s = p->ctx->stream;
     uint64_t tot[2] = {0, 0};
     p->cyc_counted = false;
-    if (p->tri) {
-        if (sj_status st = run_phase(p, 4, enqueue_tri)) return st;
+    if (p->tri || p->k4) {
+        if (sj_status st = run_phase(p, 4, p->tri ? enqueue_tri : enqueue_k4)) return st;
         SJ_HIP(p->ctx, hipMemcpyAsync(tot, at<uint64_t>(p, p->off_totals), 16, hipMemcpyDeviceToHost, s));
         SJ_HIP(p->ctx, hipStreamSynchronize(s));
     } else if (p->cyclic) {
@@ -1581,10 +1772,15 @@ extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) 
 extern "C" sj_status sj_join_async(sj_plan_t *p) {
     if (sj_status st = check_exec(p, kSieved)) return st;
     if (sj_status st = injected(p, SJ_FLAG_FAULT_JOIN, "sj_join_async")) return st;
-    if (!p->cyc_ok || (p->cyclic && !p->tri))
+    if (p->cyclic && !p->tri && !p->k4) {
+        if (!p->cyc_ok)
+            return fail(p->ctx, SJ_ERR_UNSUPPORTED, "cyclic join: this shape is not supported");
         return fail(p->ctx, SJ_ERR_UNSUPPORTED, "this cyclic join counts in two host-driven steps: use sj_join");
+    }
     p->cyc_counted = false;
-    if (sj_status st = p->tri ? run_phase(p, 4, enqueue_tri) : run_phase(p, 2, enqueue_join)) return st;
+    if (sj_status st = p->tri ? run_phase(p, 4, enqueue_tri)
+                              : p->k4 ? run_phase(p, 4, enqueue_k4) : run_phase(p, 2, enqueue_join))
+        return st;
     p->count_on_host = false;
     p->async_result = false;
     p->state = kJoined;
@@ -1681,10 +1877,11 @@ extern "C" sj_status sj_result(sj_plan_t *p, int32_t *out, uint64_t capacity, in
     if (p->count == 0) return SJ_OK;
     if (!out) return fail(p->ctx, SJ_ERR_INVALID, "null output buffer");
     if (reinterpret_cast<uintptr_t>(out) % 16) return fail(p->ctx, SJ_ERR_INVALID, "output must be 16-byte aligned");
+    if (p->tri || p->k4) return clique_write(p, out, capacity, pr);
     if (p->cyclic) {
         if (!p->cyc_counted) {
-            // the count came from the intersection walk: the write pass decodes the
-            // binary plan's count pass, which must reach the same total
+            // the binary count pass has not run since the last sieve: the write pass
+            // decodes its per-thread offsets, and it must reach the same total
             uint64_t tot[2] = {0, 0};
             if (sj_status st = binary_cyclic_count(p, tot)) return st;
             if (tot[0] != p->count || tot[1] != p->checksum)

@@ -1,4 +1,4 @@
-// Directed 3-cycles by intersection.
+// Directed 3-cycles and 4-cliques by intersection.
 //
 // Section 3.1.3 pairs the sieve with a multi-way (worst-case-optimal) join for the
 // cyclic query; this is that enumeration for the 3-cycle root - P - L - root. A result
@@ -59,6 +59,24 @@ __device__ __forceinline__ bool pair_find(const PairHash &h, uint32_t mask, uint
     return true;
 }
 
+// The pair's slot (h.cap for the spare one) and row count, or -1 when it is absent.
+__device__ __forceinline__ int64_t pair_slot_of(const PairHash &h, uint32_t mask, uint64_t key, uint32_t &c) {
+    const uint64_t hm = pair_mix(key);
+    const uint32_t b = pair_bit(hm, mask);
+    if (!((h.sig[b >> 5] >> (b & 31u)) & 1u)) return -1;
+    uint32_t s = key == kPairEmpty ? h.cap : pair_slot(hm, mask);
+    uint4 v;
+    while (true) {
+        v = *reinterpret_cast<const uint4 *>(h.slot + s);
+        const uint64_t k = (static_cast<uint64_t>(v.y) << 32) | v.x;
+        if (k == key) break;
+        if (k == kPairEmpty || s == h.cap) return -1;
+        s = (s + 1) & mask;
+    }
+    c = v.z;
+    return c == 0 ? -1 : static_cast<int64_t>(s);
+}
+
 __global__ void k_pair_mask(PairHash h, const uint32_t *n_dev) {
     static_assert(sizeof(PairSlot) == 16, "one 16-byte load per slot");
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -75,17 +93,19 @@ __global__ void k_pair_clear(PairHash h) {
     for (uint32_t i = t; i < lim; i += gridDim.x * blockDim.x) {
         h.slot[i] = empty;
         h.msum[i] = 0;
+        h.pos[i] = ~0u;
         if (i < lim / 8u) h.sig[i] = 0;   // 4 bits per slot: lim / 8 words
     }
     if (t == 0) {
         h.slot[h.cap] = empty;
         h.msum[h.cap] = 0;
+        h.pos[h.cap] = ~0u;
     }
 }
 
-// One insert per run of equal pairs in adjacent lanes (entries come grouped by their
-// first key, so repeated pairs are often neighbours); the run's count and factor sum
-// come from a wave prefix sum.
+// One insert per run of equal pairs in adjacent lanes (entries come sorted by pair, so
+// a pair's rows are consecutive); the run's count and factor sum come from a wave
+// prefix sum.
 __global__ __launch_bounds__(256) void k_pair_insert(PairHash h, const uint32_t *n_dev, const uint32_t *rid,
                                                      const int32_t *ca, const int32_t *cb, uint32_t rel) {
     const uint32_t n = *n_dev, mask = *h.mask;
@@ -129,8 +149,10 @@ __global__ __launch_bounds__(256) void k_pair_insert(PairHash h, const uint32_t 
                 s = (s + 1) & mask;
             }
         }
-        // the first rows to arrive leave their first row id (read when the pair has one row)
+        // the first rows to arrive leave their first row id (read when the pair has one row);
+        // the smallest bucket position among the runs is where the pair's rows start
         if (atomicAdd(&h.slot[s].cnt, c) == 0u) h.slot[s].rid = first_rid;
+        atomicMin(h.pos + s, g * 64 + static_cast<uint32_t>(start));
         atomicAdd(reinterpret_cast<unsigned long long *>(h.msum + s), static_cast<unsigned long long>(ms));
     }
 }
@@ -306,6 +328,387 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_final(TriArgs a, uint32_t n
     }
 }
 
+// ---- 4-cliques ------------------------------------------------------------------------
+// Generic join in the variable order a, b, c, d. For a root entry (a, b) the values c
+// come from intersecting ac's group of a with bc's group of b: the walk takes the
+// smaller group and looks each member up in the other relation's pair hash, as for
+// 3-cycles, and uses the same balanced chunks. For each c found, the values d lie in
+// the groups ad(a), bd(b) and cd(c): the smallest is walked and its members are looked
+// up in the other two pair hashes. Per tuple of variable values the rows multiply, so
+// a match adds the product of the pairs' row counts, and the checksum term is the
+// product of the walked rows' factors and the looked-up pairs' factor sums.
+
+__device__ __forceinline__ void k4_range(const K4Group &g, uint32_t mask, int32_t key, uint32_t &b, uint32_t &n) {
+    b = 0;
+    n = 0;
+    const int64_t d = dir_find(g.slots, mask, key);
+    if (d >= 0) {
+        b = g.begin[d];
+        n = g.begin[d + 1] - b;
+    }
+}
+
+// Phase 1: each root entry's first-level walk (the smaller of ac(a) and bc(b)).
+__global__ __launch_bounds__(kScanBlock) void k_k4_rows(K4Args a) {
+    __shared__ uint64_t s_w[kScanBlock / 64];
+    const uint32_t n = *a.n_root;
+    const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
+    const uint32_t m_ac = *a.g[0].mask, m_bc = *a.g[2].mask;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t base = tile * kScanTile + threadIdx.x * kScanItems;
+        uint64_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            const uint32_t e = base + i;
+            if (e >= n) continue;
+            uint32_t b1, n1, b2, n2;
+            k4_range(a.g[0], m_ac, a.root_a[e], b1, n1);
+            k4_range(a.g[2], m_bc, a.root_b[e], b2, n2);
+            const bool walk_bc = n2 < n1;
+            const uint32_t w = walk_bc ? n2 : n1;
+            a.w[e] = w | (walk_bc ? 0x80000000u : 0u);
+            a.beg[e] = walk_bc ? b2 : b1;
+            sum += w;
+        }
+        uint64_t tot;
+        block_excl_scan<kScanBlock>(sum, s_w, tot);
+        if (threadIdx.x == 0) a.tile_sums[tile] = tot;
+    }
+}
+
+// Second level: walk group W (1 ad, 3 bd, 4 cd) from entry wb, wn members, each giving
+// d; look (x, d) up in the other two pair hashes.
+template <int W>
+__device__ __forceinline__ void k4_second(const K4Args &a, const uint32_t *hm, uint32_t wb, uint32_t wn,
+                                          int32_t av, int32_t bv, int32_t cv, uint64_t &cnt, uint64_t &chk) {
+    constexpr int H1 = W == 1 ? 3 : 1;         // ad walked: bd, cd; bd walked: ad, cd; cd walked: ad, bd
+    constexpr int H2 = W == 4 ? 3 : 4;
+    const int32_t x1 = H1 == 3 ? bv : av;
+    const int32_t x2 = H2 == 3 ? bv : cv;
+    const K4Group &g = a.g[W];
+    for (uint32_t j = 0; j < wn; ++j) {
+        const uint32_t e = wb + j;
+        const int32_t d = g.other[e];
+        uint32_t c1, c2;
+        uint64_t s1, s2;
+        if (!pair_find(a.h[H1], hm[H1], pair_key(x1, d), c1, s1)) continue;
+        if (!pair_find(a.h[H2], hm[H2], pair_key(x2, d), c2, s2)) continue;
+        cnt += static_cast<uint64_t>(c1) * c2;
+        chk += chk_factor(g.rel, g.rid[e]) * s1 * s2;
+    }
+}
+
+__global__ __launch_bounds__(kTriThreads) void k_k4_count(K4Args a) {
+    __shared__ uint64_t s_c[kTriThreads / 64], s_k[kTriThreads / 64];
+    const uint32_t n = *a.n_root;
+    const uint64_t total = a.off[n];
+    constexpr uint64_t kWaveSteps = 64ull * kTriIters;
+    const uint64_t nchunks = (total + kWaveSteps - 1) / kWaveSteps;
+    uint32_t gm[5], hm[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        gm[i] = *a.g[i].mask;
+        hm[i] = *a.h[i].mask;
+    }
+    const uint32_t lane = static_cast<uint32_t>(lane_id());
+    uint64_t cnt = 0, chk = 0;
+    const uint64_t nwaves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
+    for (uint64_t c = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; c < nchunks; c += nwaves) {
+        uint64_t w = c * kWaveSteps + lane;
+        if (w >= total) continue;
+        uint32_t r = upper_bound_u64(a.off, 0, n, w) - 1;
+        uint64_t r_lo = a.off[r], r_hi = a.off[r + 1];
+        bool loaded = false, walk_bc = false;
+        uint32_t beg = 0, ad_b = 0, ad_n = 0, bd_b = 0, bd_n = 0;
+        int32_t av = 0, bv = 0;
+        uint64_t m0 = 0;
+        for (int it = 0; it < kTriIters && w < total; ++it, w += 64) {
+            if (w >= r_hi) {
+                uint32_t lo = r + 1, step = 1, hi = lo;
+                while (hi < n && a.off[hi + 1] <= w) {
+                    lo = hi + 1;
+                    hi = min(n - 1, hi + step);
+                    step <<= 1;
+                }
+                r = upper_bound_u64(a.off, lo, hi + 1, w) - 1;
+                r_lo = a.off[r];
+                r_hi = a.off[r + 1];
+                loaded = false;
+            }
+            if (!loaded) {
+                walk_bc = (a.w[r] >> 31) != 0;
+                beg = a.beg[r];
+                av = a.root_a[r];
+                bv = a.root_b[r];
+                m0 = chk_factor(a.rel_root, a.root_rid[r]);
+                k4_range(a.g[1], gm[1], av, ad_b, ad_n);
+                k4_range(a.g[3], gm[3], bv, bd_b, bd_n);
+                loaded = true;
+            }
+            if (ad_n == 0 || bd_n == 0) continue;
+            const uint32_t e = beg + static_cast<uint32_t>(w - r_lo);
+            int32_t cv;
+            uint64_t m1, s1;
+            uint32_t c1;
+            bool hit;
+            if (!walk_bc) {
+                cv = a.g[0].other[e];
+                m1 = chk_factor(a.g[0].rel, a.g[0].rid[e]);
+                hit = pair_find(a.h[2], hm[2], pair_key(bv, cv), c1, s1);
+            } else {
+                cv = a.g[2].other[e];
+                m1 = chk_factor(a.g[2].rel, a.g[2].rid[e]);
+                hit = pair_find(a.h[0], hm[0], pair_key(av, cv), c1, s1);
+            }
+            if (!hit) continue;
+            uint32_t cd_b, cd_n;
+            k4_range(a.g[4], gm[4], cv, cd_b, cd_n);
+            if (cd_n == 0) continue;
+            uint64_t c2 = 0, k2 = 0;
+            if (ad_n <= bd_n && ad_n <= cd_n)
+                k4_second<1>(a, hm, ad_b, ad_n, av, bv, cv, c2, k2);
+            else if (bd_n <= cd_n)
+                k4_second<3>(a, hm, bd_b, bd_n, av, bv, cv, c2, k2);
+            else
+                k4_second<4>(a, hm, cd_b, cd_n, av, bv, cv, c2, k2);
+            cnt += static_cast<uint64_t>(c1) * c2;
+            chk += m0 * m1 * s1 * k2;
+        }
+    }
+    uint64_t tc, tk;
+    block_excl_scan<kTriThreads>(cnt, s_c, tc);
+    block_excl_scan<kTriThreads>(chk, s_k, tk);
+    if (threadIdx.x == 0) {
+        a.part[2 * blockIdx.x] = tc;
+        a.part[2 * blockIdx.x + 1] = tk;
+    }
+}
+
+// ---- write pass (3-cycles and 4-cliques) ------------------------------------------------
+// Pass 0 counts each lane's tuples (and each workgroup's); pass 1 walks again and writes
+// a lane's tuples from its offset: the workgroups before it, then the lanes before it.
+// Both passes use the count pass's walk lengths and prefixes (still in the workspace).
+
+template <int NR>
+__device__ __forceinline__ void emit_tuple(const CliqueOut &o, uint64_t at, const uint32_t (&rr)[NR]) {
+    if (at >= o.capacity) return;
+    if (o.proj.n == 0) {
+        int32_t *dst = o.out + at * static_cast<uint64_t>(o.nrels);
+#pragma unroll
+        for (int i = 0; i < NR; ++i) dst[o.role_rel[i]] = static_cast<int32_t>(rr[i]);
+    } else {
+        int32_t *dst = o.out + at * static_cast<uint64_t>(o.proj.n);
+        for (int q = 0; q < o.proj.n; ++q) {
+            uint32_t rid = 0;
+#pragma unroll
+            for (int i = 0; i < NR; ++i)
+                if (o.proj.rel[q] == o.role_rel[i]) rid = rr[i];
+            dst[q] = o.proj.col[q][rid];
+        }
+    }
+}
+
+__device__ __forceinline__ uint64_t emit_base(const CliqueOut &o, uint64_t *s_tmp) {
+    uint64_t before = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += blockDim.x) before += o.block_cnt[b];
+    uint64_t blocks_before, t;
+    block_excl_scan<kTriThreads>(before, s_tmp, blocks_before);
+    const uint64_t lanes_before =
+        block_excl_scan<kTriThreads>(o.lane_cnt[blockIdx.x * blockDim.x + threadIdx.x], s_tmp, t);
+    return blocks_before + lanes_before;
+}
+
+__device__ __forceinline__ void emit_count_out(const CliqueOut &o, uint64_t cnt, uint64_t *s_tmp) {
+    o.lane_cnt[blockIdx.x * blockDim.x + threadIdx.x] = cnt;
+    uint64_t tot;
+    block_excl_scan<kTriThreads>(cnt, s_tmp, tot);
+    if (threadIdx.x == 0) o.block_cnt[blockIdx.x] = tot;
+}
+
+template <bool WRITE>
+__global__ __launch_bounds__(kTriThreads) void k_tri_emit(TriArgs a, CliqueOut o) {
+    __shared__ uint64_t s_tmp[kTriThreads / 64];
+    const uint32_t n = *a.n_root;
+    const uint64_t total = a.off[n];
+    constexpr uint64_t kWaveSteps = 64ull * kTriIters;
+    const uint64_t nchunks = (total + kWaveSteps - 1) / kWaveSteps;
+    const uint32_t pm = *a.HP.mask, lm = *a.HL.mask;
+    const uint32_t lane = static_cast<uint32_t>(lane_id());
+    uint64_t cnt = 0, cur = WRITE ? emit_base(o, s_tmp) : 0;
+    const uint64_t nwaves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
+    for (uint64_t c = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; c < nchunks; c += nwaves) {
+        uint64_t w = c * kWaveSteps + lane;
+        if (w >= total) continue;
+        uint32_t r = upper_bound_u64(a.off, 0, n, w) - 1;
+        uint64_t r_lo = a.off[r], r_hi = a.off[r + 1];
+        bool loaded = false, walk_l = false;
+        uint32_t beg = 0, rroot = 0;
+        int32_t x = 0, y = 0;
+        for (int it = 0; it < kTriIters && w < total; ++it, w += 64) {
+            if (w >= r_hi) {
+                uint32_t lo = r + 1, step = 1, hi = lo;
+                while (hi < n && a.off[hi + 1] <= w) {
+                    lo = hi + 1;
+                    hi = min(n - 1, hi + step);
+                    step <<= 1;
+                }
+                r = upper_bound_u64(a.off, lo, hi + 1, w) - 1;
+                r_lo = a.off[r];
+                r_hi = a.off[r + 1];
+                loaded = false;
+            }
+            if (!loaded) {
+                walk_l = (a.w[r] >> 31) != 0;
+                beg = a.beg[r];
+                x = a.root_x[r];
+                y = a.root_y[r];
+                rroot = a.root_rid[r];
+                loaded = true;
+            }
+            const uint32_t e = beg + static_cast<uint32_t>(w - r_lo);
+            uint32_t hc = 0;
+            const int64_t sl = walk_l ? pair_slot_of(a.HP, pm, pair_key(x, a.L_z[e]), hc)
+                                      : pair_slot_of(a.HL, lm, pair_key(y, a.P_z[e]), hc);
+            if (sl < 0) continue;
+            if (!WRITE) {
+                cnt += hc;
+                continue;
+            }
+            const uint32_t mine = walk_l ? a.L_rid[e] : a.P_rid[e];
+            const uint32_t p0 = walk_l ? a.HP.pos[sl] : a.HL.pos[sl];
+            const uint32_t *orid = walk_l ? a.P_rid : a.L_rid;
+            for (uint32_t j = 0; j < hc; ++j) {
+                const uint32_t other = orid[p0 + j];
+                const uint32_t rr[3] = {rroot, walk_l ? other : mine, walk_l ? mine : other};
+                emit_tuple<3>(o, cur++, rr);
+            }
+        }
+    }
+    if (!WRITE) emit_count_out(o, cnt, s_tmp);
+}
+
+// Second level of a 4-clique for the write pass: as k4_second, counting or writing every
+// row combination (the level-one rows come in as l1 rows at l1_pos in bucket l1_rid,
+// with the walked level-one row fixed).
+template <int W, bool WRITE>
+__device__ __forceinline__ void k4_second_emit(const K4Args &a, const CliqueOut &o, const uint32_t *hm, uint32_t wb,
+                                               uint32_t wn, int32_t av, int32_t bv, int32_t cv, uint64_t c1,
+                                               uint32_t (&rr)[6], bool l1_ac, const uint32_t *l1_rid,
+                                               uint32_t l1_pos, uint64_t &cnt, uint64_t &cur) {
+    constexpr int H1 = W == 1 ? 3 : 1;
+    constexpr int H2 = W == 4 ? 3 : 4;
+    const int32_t x1 = H1 == 3 ? bv : av;
+    const int32_t x2 = H2 == 3 ? bv : cv;
+    const K4Group &g = a.g[W];
+    for (uint32_t j = 0; j < wn; ++j) {
+        const uint32_t e = wb + j;
+        const int32_t d = g.other[e];
+        uint32_t cA = 0, cB = 0;
+        const int64_t sA = pair_slot_of(a.h[H1], hm[H1], pair_key(x1, d), cA);
+        if (sA < 0) continue;
+        const int64_t sB = pair_slot_of(a.h[H2], hm[H2], pair_key(x2, d), cB);
+        if (sB < 0) continue;
+        if (!WRITE) {
+            cnt += c1 * cA * cB;
+            continue;
+        }
+        // roles: 0 root, 1 ac, 2 ad, 3 bc, 4 bd, 5 cd; group / hash index h is role h + 1
+        rr[W + 1] = g.rid[e];
+        const uint32_t pA = a.h[H1].pos[sA], pB = a.h[H2].pos[sB];
+        for (uint64_t i1 = 0; i1 < c1; ++i1) {
+            const uint32_t r1 = l1_rid[l1_pos + i1];
+            if (l1_ac)
+                rr[1] = r1;
+            else
+                rr[3] = r1;
+            for (uint32_t iA = 0; iA < cA; ++iA) {
+                rr[H1 + 1] = a.g[H1].rid[pA + iA];
+                for (uint32_t iB = 0; iB < cB; ++iB) {
+                    rr[H2 + 1] = a.g[H2].rid[pB + iB];
+                    emit_tuple<6>(o, cur++, rr);
+                }
+            }
+        }
+    }
+}
+
+template <bool WRITE>
+__global__ __launch_bounds__(kTriThreads) void k_k4_emit(K4Args a, CliqueOut o) {
+    __shared__ uint64_t s_tmp[kTriThreads / 64];
+    const uint32_t n = *a.n_root;
+    const uint64_t total = a.off[n];
+    constexpr uint64_t kWaveSteps = 64ull * kTriIters;
+    const uint64_t nchunks = (total + kWaveSteps - 1) / kWaveSteps;
+    uint32_t gm[5], hm[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        gm[i] = *a.g[i].mask;
+        hm[i] = *a.h[i].mask;
+    }
+    const uint32_t lane = static_cast<uint32_t>(lane_id());
+    uint64_t cnt = 0, cur = WRITE ? emit_base(o, s_tmp) : 0;
+    const uint64_t nwaves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
+    for (uint64_t c = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; c < nchunks; c += nwaves) {
+        uint64_t w = c * kWaveSteps + lane;
+        if (w >= total) continue;
+        uint32_t r = upper_bound_u64(a.off, 0, n, w) - 1;
+        uint64_t r_lo = a.off[r], r_hi = a.off[r + 1];
+        bool loaded = false, walk_bc = false;
+        uint32_t beg = 0, ad_b = 0, ad_n = 0, bd_b = 0, bd_n = 0;
+        int32_t av = 0, bv = 0;
+        uint32_t rr[6] = {0, 0, 0, 0, 0, 0};
+        for (int it = 0; it < kTriIters && w < total; ++it, w += 64) {
+            if (w >= r_hi) {
+                uint32_t lo = r + 1, step = 1, hi = lo;
+                while (hi < n && a.off[hi + 1] <= w) {
+                    lo = hi + 1;
+                    hi = min(n - 1, hi + step);
+                    step <<= 1;
+                }
+                r = upper_bound_u64(a.off, lo, hi + 1, w) - 1;
+                r_lo = a.off[r];
+                r_hi = a.off[r + 1];
+                loaded = false;
+            }
+            if (!loaded) {
+                walk_bc = (a.w[r] >> 31) != 0;
+                beg = a.beg[r];
+                av = a.root_a[r];
+                bv = a.root_b[r];
+                rr[0] = a.root_rid[r];
+                k4_range(a.g[1], gm[1], av, ad_b, ad_n);
+                k4_range(a.g[3], gm[3], bv, bd_b, bd_n);
+                loaded = true;
+            }
+            if (ad_n == 0 || bd_n == 0) continue;
+            const uint32_t e = beg + static_cast<uint32_t>(w - r_lo);
+            // the walked level-one row is ac (walk over ac(a)) or bc; the other side's rows
+            // come from the pair hash
+            const int32_t cv = walk_bc ? a.g[2].other[e] : a.g[0].other[e];
+            uint32_t c1 = 0;
+            const int64_t s1 = walk_bc ? pair_slot_of(a.h[0], hm[0], pair_key(av, cv), c1)
+                                       : pair_slot_of(a.h[2], hm[2], pair_key(bv, cv), c1);
+            if (s1 < 0) continue;
+            uint32_t cd_b, cd_n;
+            k4_range(a.g[4], gm[4], cv, cd_b, cd_n);
+            if (cd_n == 0) continue;
+            if (walk_bc)
+                rr[3] = a.g[2].rid[e];
+            else
+                rr[1] = a.g[0].rid[e];
+            const uint32_t *l1_rid = walk_bc ? a.g[0].rid : a.g[2].rid;
+            const uint32_t l1_pos = walk_bc ? a.h[0].pos[s1] : a.h[2].pos[s1];
+            if (ad_n <= bd_n && ad_n <= cd_n)
+                k4_second_emit<1, WRITE>(a, o, hm, ad_b, ad_n, av, bv, cv, c1, rr, walk_bc, l1_rid, l1_pos, cnt, cur);
+            else if (bd_n <= cd_n)
+                k4_second_emit<3, WRITE>(a, o, hm, bd_b, bd_n, av, bv, cv, c1, rr, walk_bc, l1_rid, l1_pos, cnt, cur);
+            else
+                k4_second_emit<4, WRITE>(a, o, hm, cd_b, cd_n, av, bv, cv, c1, rr, walk_bc, l1_rid, l1_pos, cnt, cur);
+        }
+    }
+    if (!WRITE) emit_count_out(o, cnt, s_tmp);
+}
+
 uint32_t blocks_for(uint64_t items, uint32_t per_block, uint32_t cap) {
     const uint64_t g = (items + per_block - 1) / per_block;
     return g == 0 ? 1u : static_cast<uint32_t>(g < cap ? g : cap);
@@ -330,6 +733,37 @@ hipError_t launch_tri_count(const TriArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_tri_down, dim3(tiles), dim3(kScanBlock), 0, s, a);
     hipLaunchKernelGGL(k_tri_count, dim3(kTriBlocks), dim3(kTriThreads), 0, s, a);
     hipLaunchKernelGGL(k_tri_final, dim3(1), dim3(kTriThreads), 0, s, a, kTriBlocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_k4_count(const K4Args &a, hipStream_t s) {
+    TriArgs t{};   // the scan and the final sum read only these fields
+    t.n_root = a.n_root;
+    t.root_cap = a.root_cap;
+    t.w = a.w;
+    t.beg = a.beg;
+    t.off = a.off;
+    t.tile_sums = a.tile_sums;
+    t.part = a.part;
+    t.totals = a.totals;
+    const uint32_t tiles = blocks_for(a.root_cap, kScanTile, kPersistentBlocks);
+    hipLaunchKernelGGL(k_k4_rows, dim3(tiles), dim3(kScanBlock), 0, s, a);
+    hipLaunchKernelGGL(k_tri_tiles, dim3(1), dim3(kScanBlock), 0, s, t);
+    hipLaunchKernelGGL(k_tri_down, dim3(tiles), dim3(kScanBlock), 0, s, t);
+    hipLaunchKernelGGL(k_k4_count, dim3(kTriBlocks), dim3(kTriThreads), 0, s, a);
+    hipLaunchKernelGGL(k_tri_final, dim3(1), dim3(kTriThreads), 0, s, t, kTriBlocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_tri_emit(const TriArgs &a, const CliqueOut &o, hipStream_t s) {
+    hipLaunchKernelGGL(k_tri_emit<false>, dim3(kTriBlocks), dim3(kTriThreads), 0, s, a, o);
+    hipLaunchKernelGGL(k_tri_emit<true>, dim3(kTriBlocks), dim3(kTriThreads), 0, s, a, o);
+    return hipGetLastError();
+}
+
+hipError_t launch_k4_emit(const K4Args &a, const CliqueOut &o, hipStream_t s) {
+    hipLaunchKernelGGL(k_k4_emit<false>, dim3(kTriBlocks), dim3(kTriThreads), 0, s, a, o);
+    hipLaunchKernelGGL(k_k4_emit<true>, dim3(kTriBlocks), dim3(kTriThreads), 0, s, a, o);
     return hipGetLastError();
 }
 

@@ -161,6 +161,9 @@ sj_status make_plan(Run &r, Query &q, Mode mode, uint32_t passes = 2, uint32_t e
     return sj_bind_workspace(r.plan, r.ws, r.wsb);
 }
 
+// set while a 4-clique query runs (its count pass also runs asynchronously)
+bool g_clique = false;
+
 // plan -> filters -> sieve -> join -> result, `reps` times, then the asynchronous calls
 void full_run(const char *name, Query &q, Mode mode, int reps, uint32_t passes = 2, uint32_t flags = 0,
               bool expect_join_ok = true) {
@@ -200,7 +203,7 @@ void full_run(const char *name, Query &q, Mode mode, int reps, uint32_t passes =
         }
     }
     const bool cyclic = q.edges.size() >= q.rels.size();
-    if (!cyclic || (nrels == 3 && !(flags & SJ_FLAG_BINARY_CYCLES))) {
+    if (!cyclic || ((nrels == 3 || g_clique) && !(flags & SJ_FLAG_BINARY_CYCLES))) {
         OK(r.ctx, sj_build_filters(r.plan));
         OK(r.ctx, sj_sieve(r.plan, nullptr));
         st = sj_join_async(r.plan);
@@ -299,6 +302,20 @@ void scenario_cycles() {
     u.edge(0, 2, 2, 2);
     u.finish();
     all_modes("unsupported cycle", u, 2, 0, false);
+    // the 4-clique: relations ab, ac, ad, bc, bd, cd, each variable joining its three
+    // relations by two edges; counted and written by intersection (the binary plan
+    // refuses it)
+    Query k;
+    for (int i = 0; i < 6; ++i) k.add(400 + 50 * i, 2);
+    const int ke[8][4] = {{0, 0, 1, 0}, {0, 0, 2, 0}, {0, 1, 3, 0}, {0, 1, 4, 0},
+                          {1, 1, 3, 1}, {1, 1, 5, 0}, {2, 1, 4, 1}, {2, 1, 5, 1}};
+    for (const auto &e : ke) k.edge(e[0], e[1], e[2], e[3]);
+    k.finish();
+    g_clique = true;
+    all_modes("4-clique", k);
+    all_modes("4-clique one pass", k, 1);
+    g_clique = false;
+    all_modes("4-clique binary", k, 2, SJ_FLAG_BINARY_CYCLES, false);
 }
 
 void scenario_updates() {

@@ -56,7 +56,7 @@ def plan(specs, edges, **kw):
     arr, keep = mkrels(specs)
     earr = (sj._Edge * max(1, len(edges)))(*[sj._Edge(*e) for e in edges])
     o = sj._Opts(kw.get("bpk", 0), kw.get("k", 0), kw.get("B", 0), kw.get("passes", 0), 0, kw.get("root", -1),
-                 kw.get("flags", 0))
+                 kw.get("flags", 0), kw.get("probe_grid", 0), kw.get("probe_lds", 0))
     p = ctypes.c_void_p()
     ws = ctypes.c_uint64()
     st = L.sj_plan(ctx, arr, len(specs), earr, len(edges), ctypes.byref(o), ctypes.byref(p), ctypes.byref(ws))
@@ -181,3 +181,18 @@ def test_fault_flags_are_accepted_and_unknown_flags_refused():
         sj.lib().sj_plan_destroy(p)
     st, p, ws, ctx, err = plan([(10, 1, None)] * 2, [(0, 0, 1, 0)], flags=128)
     assert st == sj.SJ_ERR_INVALID
+
+
+def test_probe_launch_shape_options():
+    """probe_grid: a power of two in 64..1024 (0: the default); probe_lds: 0, 1 or 2."""
+    for g in (0, 64, 128, 256, 512, 1024):
+        for lds in (0, 1, 2):
+            st, p, ws, ctx, err = plan([(1000, 2, None)] * 3, [(0, 1, 1, 0), (1, 1, 2, 0)], probe_grid=g,
+                                       probe_lds=lds)
+            assert st == 0, (g, lds, err)
+            sj.lib().sj_plan_destroy(p)
+    for g in (32, 96, 2048):
+        st, p, ws, ctx, err = plan([(10, 1, None)] * 2, [(0, 0, 1, 0)], probe_grid=g)
+        assert st == sj.SJ_ERR_INVALID and "probe_grid" in err
+    st, p, ws, ctx, err = plan([(10, 1, None)] * 2, [(0, 0, 1, 0)], probe_lds=3)
+    assert st == sj.SJ_ERR_INVALID and "probe_lds" in err

@@ -2,8 +2,9 @@
 
 Every case is checked three ways: the intersection count, the binary plan's count
 (SJ_FLAG_BINARY_CYCLES) and the oracle's binary hash join agree on count and
-checksum, and the tuples (decoded from the binary plan's count pass, which sj_result
-runs after an intersection count) equal the oracle's. Cases: random small 3-cycles
+checksum, and the tuples written by the intersection walk and by the binary plan
+(each compared as a sorted multiset; the binary plan's also sorted in preorder) equal
+the oracle's. Cases: random small 3-cycles
 (empty relations, several columns, negative and extreme keys, repeated pairs), the
 pair whose 64-bit key equals the hash's empty marker, predicates, three different
 edge relations, the power-law triangle at reduced size, the asynchronous count,
@@ -50,9 +51,14 @@ def check_all(q, expect_tri=True):
     assert cc == (rcnt, rchk), (q.name, cc, (rcnt, rchk))
     assert cb == (rcnt, rchk)
     assert used_intersection(q, rels) == expect_tri
+    # the intersection walk writes the tuples (in walk order); the binary plan decodes its
+    # own count pass (sorted in preorder)
     tup = p.result().cpu().numpy().astype(np.uint32)
     assert np.array_equal(lexsort_rows(tup), lexsort_rows(ref))
-    check_sorted_in_preorder(q, tup)
+    pb, _ = counts(q, rels, binary_cycles=True)
+    tb = pb.result().cpu().numpy().astype(np.uint32)
+    assert np.array_equal(lexsort_rows(tb), lexsort_rows(ref))
+    check_sorted_in_preorder(q, tb)
     return rcnt
 
 
