@@ -28,9 +28,11 @@ launches eagerly with an event pair around each kernel (the timed plan replays
 recorded graphs); the kernels and data are the same.
 
 configs       -- the small 3-way chain's latency, the star (100M-row fact table), the
-                 full-size triangle (50M edges, 3-cycles counted by intersection) and
-                 the paper's synthetic join at its sizes (2e8 rows, 10^7 tuples), timed
-                 the same way (paper_2308_16370_amd/configbench.py).
+                 full-size triangle (50M edges, 3-cycles counted by intersection), the
+                 paper's synthetic join at its sizes (2e8 rows, 10^7 tuples), the n=2
+                 Bloomjoin, the planner's estimates, and the 3-clique and 4-clique
+                 queries on a vote-network-sized graph, timed the same way
+                 (paper_2308_16370_amd/configbench.py).
 sieve_roofline -- every probe, compaction and filter-build launch of a step: their
                  algorithmic bytes over their summed event-timed durations, against the
                  60% target.
@@ -295,7 +297,7 @@ def main():
         logf = lambda m: print(m, file=sys.stderr, flush=True)
         configs = {"chain3": configbench.chain3_latency(log=logf), "star": configbench.star(log=logf),
                    "triangle": configbench.triangle(log=logf), "psyn": configbench.psyn(log=logf),
-                   "bloomjoin_n2": configbench.bloomjoin(log=logf),
+                   "bloomjoin_n2": configbench.bloomjoin(log=logf), "cliques": configbench.cliques(log=logf),
                    "planner_chain4": configbench.planner_check(q, opts, log=logf)}
         tri = configs["triangle"]
         gold = os.path.join(ROOT, "tests", "golden", "triangle_cycles.json")

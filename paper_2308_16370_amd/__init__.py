@@ -620,11 +620,12 @@ class Server:
 
     def submit(self, rels: Sequence[Rel], edges: Sequence[Tuple[int, int, int, int]], bits_per_key: int = 0,
                k: int = 0, block_bits: int = 0, passes: int = 0, seed: int = 0, root: int = -1,
-               count_only: bool = False, values: bool = False, flags: int = 0) -> int:
+               count_only: bool = False, values: bool = False, flags: int = 0, probe_grid: int = 0,
+               probe_lds: int = 0) -> int:
         """Queue a query; its result is row ids (default), values (all columns of every
         relation, relation order) or the count only."""
         arr, earr, keep = _marshal(rels, edges)
-        opts = _Opts(bits_per_key, k, block_bits, passes, seed & (2**64 - 1), root, flags)
+        opts = _Opts(bits_per_key, k, block_bits, passes, seed & (2**64 - 1), root, flags, probe_grid, probe_lds)
         t = ctypes.c_uint64()
         mode = SJ_RESULT_COUNT if count_only else (SJ_RESULT_VALUES if values else SJ_RESULT_TUPLES)
         code = lib().sj_server_submit(self.handle, arr, len(rels), earr, len(edges), ctypes.byref(opts),

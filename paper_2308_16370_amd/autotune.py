@@ -1,19 +1,23 @@
-"""Filter-parameter autotuner for the batched / served query mix.
+"""Autotuner for the batched / served query mix: filter parameters and the sieve's
+partition of rows over workgroups.
 
 Bits per key, the number of hashes k and the block size trade filter size and probe
-cost against false positives, which surviving rows then cost in the join. The best
-choice depends on the query's shape, size and skew, so it is measured:
+cost against false positives, which surviving rows then cost in the join; the number
+of workgroups a sieve probe splits its rows over (each takes a contiguous share) trades
+parallelism against per-workgroup set-up for small relations. The best choice depends
+on the query's shape, size and skew, so it is measured:
 
     python -m paper_2308_16370_amd.autotune --out paper_2308_16370_amd/tuning.json
 
 draws sample queries from the batched workload's distributions (on the GPU), runs
-each with every candidate (bits_per_key, k, block_bits) and times the whole query
-(filters, sieve, count pass, materialisation) with the launches replayed as graphs.
-For each bucket (kind, decade of total input rows, low or high skew) it keeps the
-candidate with the least total time over the bucket's samples. `choose` reads the
-table; buckets it has not seen fall back to the nearest size decade of the same kind
-and skew, then to (8, 6, 512). Every candidate gives the same exact result, so the
-choice changes only the time.
+each with every candidate (bits_per_key, k, block_bits, probe_grid) and times the
+whole query the way the server runs it: a new plan, its launches made one by one
+(eager), filters, sieve, count pass and materialisation. For each bucket (kind,
+decade of total input rows, low or high skew) it keeps the candidate with the least
+total time over the bucket's samples. `choose` reads the table; buckets it has not
+seen fall back to the nearest size decade of the same kind and skew, then to the
+defaults. Every candidate gives the same exact result, so the choice changes only the
+time.
 """
 from __future__ import annotations
 
@@ -27,8 +31,9 @@ from typing import Dict, List, Optional, Tuple
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tuning.json")
-DEFAULT = (8, 6, 512)
-CANDIDATES = [(b, k, B) for b in (6, 8, 12, 16) for k in (2, 4, 6) for B in (256, 512) if k <= b]
+DEFAULT = (8, 6, 512, 256)
+CANDIDATES = [(b, k, B, g) for b in (6, 8, 12, 16) for k in (2, 4, 6) for B in (256, 512) for g in (128, 256)
+              if k <= b]
 
 _table_cache: Optional[dict] = None
 
@@ -51,38 +56,44 @@ def load(path: str = TABLE) -> dict:
     return _table_cache
 
 
-def choose(kind: str, input_rows: int, s: float, table: Optional[dict] = None) -> Tuple[int, int, int]:
-    """(bits_per_key, k, block_bits) for a query."""
+def choose(kind: str, input_rows: int, s: float, table: Optional[dict] = None) -> Tuple[int, int, int, int]:
+    """(bits_per_key, k, block_bits, probe_grid) for a query."""
     t = load() if table is None else table
     key = bucket(kind, input_rows, s)
-    if key in t:
-        return tuple(t[key]["best"])
-    kind_, dec, sk = key.split("/")
-    near = [(abs(int(k.split("/")[1]) - int(dec)), k) for k in t
-            if k.split("/")[0] == kind_ and k.split("/")[2] == sk]
-    if near:
-        return tuple(t[min(near)[1]]["best"])
-    return DEFAULT
+    if key not in t:
+        kind_, dec, sk = key.split("/")
+        near = [(abs(int(k.split("/")[1]) - int(dec)), k) for k in t
+                if k.split("/")[0] == kind_ and k.split("/")[2] == sk]
+        if not near:
+            return DEFAULT
+        key = min(near)[1]
+    best = list(t[key]["best"])
+    return tuple(best + list(DEFAULT[len(best):]))   # tables written before probe_grid: the default
 
 
 def _time_query(sj, torch, rels, edges, root, opts, reps: int) -> Tuple[float, Tuple[int, int]]:
+    """Seconds per query as the server runs it (a new eager plan each time)."""
     ctx = sj.Context(0)
-    plan = sj.Plan(ctx, rels, edges, root=root, **opts)
-    plan.build_filters()
-    plan.sieve()
-    cc = plan.join()
-    out = torch.empty((max(cc[0], 1), len(rels)), dtype=torch.int32, device="cuda:0")
-    plan.result(out)
+
+    def once(out=None):
+        plan = sj.Plan(ctx, rels, edges, root=root, eager=True, **opts)
+        plan.build_filters()
+        plan.sieve()
+        cc = plan.join()
+        if out is None:
+            out = torch.empty((max(cc[0], 1), len(rels)), dtype=torch.int32, device="cuda:0")
+        plan.result(out)
+        del plan
+        return cc, out
+
+    cc, out = once()
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(reps):
-        plan.build_filters()
-        plan.sieve()
-        plan.join()
-        plan.result(out)
+        once(out)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t) / reps
-    del plan, out
+    del out
     return dt, cc
 
 
@@ -105,7 +116,7 @@ def tune(seed: int, samples: int, min_rows: int, max_rows: int, reps: int, count
         ref = None
         skip = False
         for cand in CANDIDATES:
-            opts = dict(bits_per_key=cand[0], k=cand[1], block_bits=cand[2], passes=2, seed=1)
+            opts = dict(bits_per_key=cand[0], k=cand[1], block_bits=cand[2], probe_grid=cand[3], passes=2, seed=1)
             try:
                 dt, cc = _time_query(sj, torch, rels, edges, 0, opts, reps)
             except sj.SjError:
@@ -150,8 +161,9 @@ def main(argv=None):
     args = ap.parse_args(argv)
     buckets = tune(args.seed, args.samples, args.min_rows, args.max_rows, args.reps, args.count_cap,
                    log=lambda s: print(s, flush=True))
-    doc = {"about": "best (bits_per_key, k, block_bits) per (kind, decade of input rows, skew) bucket, "
-                    "measured by paper_2308_16370_amd.autotune",
+    doc = {"about": "best (bits_per_key, k, block_bits, probe_grid) per (kind, decade of input rows, skew) "
+                    "bucket, each query timed as the server runs it (new eager plan), measured by "
+                    "paper_2308_16370_amd.autotune",
            "candidates": [list(c) for c in CANDIDATES], "seed": args.seed, "samples": args.samples,
            "buckets": buckets}
     with open(args.out, "w") as fh:

@@ -126,6 +126,64 @@ def triangle(steps: int = 3, warmup: int = 1, scale: float = 1.0, binary_cycles:
             "result_tuples": ref[0], "checksum": ref[1], "intersection_walk_ms": round(walk_ms, 3)}
 
 
+def cliques(steps: int = 10, warmup: int = 2, log=print) -> Dict:
+    """The 3-clique and 4-clique queries of the paper's vote-network experiment (Section
+    3.1.3) on a power-law stand-in of the network's size (103,663 edges, 7,066 vertices):
+    whole query (filters, sieve, intersection count, tuples written), count and checksum
+    compared with the oracle's stored values (tests/golden/clique_wiki.json)."""
+    import json
+    import os
+
+    import torch
+
+    import paper_2308_16370_amd as sj
+    import workloads as W
+
+    g = None
+    gpath = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden",
+                         "clique_wiki.json")
+    if os.path.exists(gpath):
+        with open(gpath) as fh:
+            g = json.load(fh)
+    dev = torch.device("cuda:0")
+    ctx = sj.Context(0)
+    out = {}
+    for k in (3, 4):
+        q = W.config6(k=k)
+        cols = [torch.from_numpy(c).to(dev) for c in q.rels[0].cols]
+        rels = [sj.Rel(cols) for _ in q.rels]
+        plan = sj.Plan(ctx, rels, q.edges, bits_per_key=8, k=6, block_bits=512, passes=2, seed=q.meta["seed"])
+        plan.build_filters()
+        plan.sieve()
+        ref = plan.join()
+        buf = torch.empty((ref[0], len(q.rels)), dtype=torch.int32, device=dev)
+        got = []
+
+        def step():
+            plan.build_filters()
+            plan.sieve()
+            got.append(plan.join())
+            plan.result(buf)
+
+        dt = _timed(step, steps, warmup)
+        if any(x != ref for x in got):
+            raise RuntimeError("clique%d: the count changed between steps" % k)
+        key = "clique%d" % k
+        check = None
+        if g is not None and g["edges"] == q.rels[0].nrows and g["seed"] == q.meta["seed"]:
+            want = (g[key]["count"], g[key]["checksum"])
+            if ref != want:
+                raise RuntimeError("%s: %r, the oracle's stored value %r" % (key, ref, want))
+            check = "count and checksum equal the oracle's stored value (tests/golden/clique_wiki.json)"
+        out[key] = {"workload": "%d-clique over %d power-law edges (gamma 2.5) on %d vertices, intersection walk, "
+                                "tuples written" % (k, q.rels[0].nrows, q.meta["nverts"]),
+                    "input_tuples": q.input_tuples, "ms_per_query": round(dt * 1e3, 3),
+                    "result_tuples": ref[0], "checksum": ref[1], "check": check}
+        del plan, buf
+        torch.cuda.empty_cache()
+    return out
+
+
 def psyn(steps: int = 10, warmup: int = 2, M: int = 10_000_000, r: int = 10_000, d: int = 10,
          seed: int = 0x5EED0006, log=print) -> Dict:
     """The paper's synthetic R join S join T (Section 3.1.1) at its comparison sizes:
@@ -303,13 +361,13 @@ def bloomjoin(steps: int = 10, warmup: int = 2, log=print) -> Dict:
 
 
 def main(argv=None) -> int:
-    """python -m paper_2308_16370_amd.configbench star|triangle|psyn|chain3 [--steps K]
+    """python -m paper_2308_16370_amd.configbench star|triangle|psyn|chain3|bloomjoin|cliques [--steps K]
     [--scale F] [--binary-cycles]: one workload, one JSON line."""
     import argparse
     import json
     import sys
     ap = argparse.ArgumentParser(description="time one of the side workloads")
-    ap.add_argument("workload", choices=["star", "triangle", "psyn", "chain3", "bloomjoin"])
+    ap.add_argument("workload", choices=["star", "triangle", "psyn", "chain3", "bloomjoin", "cliques"])
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--scale", type=float, default=1.0, help="triangle: edges and vertices scaled together")
     ap.add_argument("--binary-cycles", action="store_true", help="triangle: count with the binary plan")
@@ -321,7 +379,7 @@ def main(argv=None) -> int:
     if args.workload == "chain3":
         kw = {} if args.steps is None else {"runs": args.steps}
     fn = {"star": star, "triangle": triangle, "psyn": psyn, "chain3": chain3_latency,
-          "bloomjoin": bloomjoin}[args.workload]
+          "bloomjoin": bloomjoin, "cliques": cliques}[args.workload]
     res = fn(log=log, **kw)
     print(json.dumps(res), flush=True)
     return 0

@@ -74,8 +74,8 @@ def prepare(seed: int, n: int, min_rows: int, max_rows: int, count_cap: int, tun
         while True:
             rel_t, edges = S.query_gpu(sp)
             rels = [sj.Rel(cols, pred) for cols, pred in rel_t]
-            b, k, B = autotune.choose(sp.kind, sp.input_tuples, sp.s) if tuned else autotune.DEFAULT
-            opts = dict(bits_per_key=b, k=k, block_bits=B, passes=2, seed=sp.seed & 0xFFFF)
+            b, k, B, g = autotune.choose(sp.kind, sp.input_tuples, sp.s) if tuned else autotune.DEFAULT
+            opts = dict(bits_per_key=b, k=k, block_bits=B, probe_grid=g, passes=2, seed=sp.seed & 0xFFFF)
             plan = sj.Plan(ctx, rels, edges, root=0, eager=True, **opts)
             plan.build_filters()
             plan.sieve()

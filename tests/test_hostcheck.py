@@ -5,7 +5,7 @@ server, the filter catalogue and the host side of every kernel launch wrapper) f
 host with both sanitizers and links it against a model of the HIP stream, event and
 graph-capture calls (tests/hostcheck/hip_model.cpp). The driver
 (tests/hostcheck/driver.cpp) runs every C ABI call sequence on chains, stars, bushy and
-binary trees of up to sixteen relations, 3- and 4-cycles and a refused cyclic shape, in
+binary trees of up to sixteen relations, 3- and 4-cycles, 4-cliques and a refused cyclic shape, in
 recorded-graph, eager and profiling modes, with the asynchronous calls, filter inserts,
 the filter catalogue (a plan destroyed after its context included) and a three-slot
 server. It fails on any sanitizer report, any call that fails unexpectedly, and any
