@@ -20,6 +20,9 @@ Printed: one JSON line with the contract's fields plus
                    HIP-event-timed average duration, against 8 TB/s HBM; traffic is the
                    HBM bytes per launch from the committed rocprofv3 counter summary
                    (profiles/traffic.json) when it was taken on the current sources;
+  launch_groups -- the modelled groups of several launches (each relation's bucketing:
+                   radix passes, gather and directory; each DP's two launches), longest
+                   first, with their bytes over their event-timed durations;
   cpu_baseline  -- the CPU oracle (plain single-threaded binary hash join) on the
                    same input, timed on this host.
 
@@ -55,6 +58,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# launch groups of the profiling plan that hold several kernels
+MULTI_LAUNCH = ("buckets", "dp", "pairs", "tri_count", "k4_count", "clique_write", "cyclic_count", "cyclic_write")
 
 
 def lib_source_hash():
@@ -221,8 +226,18 @@ def main():
     prof = pplan.profile()
     del pplan
     kernels = sorted(prof, key=lambda e: -e["total_ms"] / max(1, e["launches"]))
-    modelled = [e for e in kernels if e["alg_bytes"] > 0]
+    # the roofline is for one kernel (one launch per group, so that the rocprofv3 trace
+    # shows the same duration); groups of several launches (a relation's bucketing: the
+    # radix passes, gather and directory; a DP's two launches) are reported beside it
+    modelled = [e for e in kernels if e["alg_bytes"] > 0 and e["label"].split(":")[0] not in MULTI_LAUNCH]
     dom = modelled[0] if modelled else None
+    groups = []
+    for e in kernels:
+        if e["alg_bytes"] > 0 and e["label"].split(":")[0] in MULTI_LAUNCH:
+            avg_s = e["total_ms"] / max(1, e["launches"]) / 1e3
+            gbs = e["alg_bytes"] / avg_s / 1e9
+            groups.append({"label": e["label"], "avg_us": round(avg_s * 1e6, 2), "alg_bytes": e["alg_bytes"],
+                           "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
     copy_gbs = copy_bandwidth(dev)
     roofline = None
     if dom:
@@ -340,6 +355,7 @@ def main():
                    "probe_grid": args.probe_grid or 256, "probe_lds": args.probe_lds},
         "roofline": roofline,
         "sieve_roofline": sieve_roofline,
+        "launch_groups": groups[:8],
         "cpu_baseline": cpu,
         "check": check,
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
