@@ -132,6 +132,7 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0, help="append a plain copy of this many MiB")
     ap.add_argument("--no-serve", action="store_true", help="skip the batched / served query mix")
     ap.add_argument("--no-configs", action="store_true", help="skip the star and triangle workloads")
+    ap.add_argument("--passes", type=int, default=2, help="sieve passes: 1 (the paper's backward pass) or 2")
     ap.add_argument("--probe-grid", type=int, default=0, help="workgroups per sieve probe launch (0: library default)")
     ap.add_argument("--probe-lds", type=int, default=0, help="LDS filter reservation mode of the probes (0, 1, 2)")
     ap.add_argument("--serve-queries", type=int, default=256)
@@ -158,7 +159,7 @@ def main():
           file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     rels = [sj.Rel([torch.from_numpy(c).to(dev) for c in r.cols], r.pred) for r in q.rels]
-    opts = dict(bits_per_key=8, k=6, block_bits=512, passes=2, seed=args.seed, probe_grid=args.probe_grid,
+    opts = dict(bits_per_key=8, k=6, block_bits=512, passes=args.passes, seed=args.seed, probe_grid=args.probe_grid,
                 probe_lds=args.probe_lds)
     ctx = sj.Context(0)
     plan = sj.Plan(ctx, rels, q.edges, **opts)
@@ -349,8 +350,8 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": "chain4: 4 x %d rows, int32 keys Zipf(1.1) over %d, per-column permutation, "
-                               "blocked Bloom 8 bits/key k=6 512-bit blocks, 2 passes, tuples materialised"
-                               % (q.rels[0].nrows, q.meta["domain"]),
+                               "blocked Bloom 8 bits/key k=6 512-bit blocks, %d pass%s, tuples materialised"
+                               % (q.rels[0].nrows, q.meta["domain"], args.passes, "" if args.passes == 1 else "es"),
                    "input_tuples": q.input_tuples, "result_tuples": cnt, "seed": args.seed,
                    "probe_grid": args.probe_grid or 256, "probe_lds": args.probe_lds},
         "roofline": roofline,

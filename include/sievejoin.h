@@ -119,10 +119,9 @@ typedef struct {
  * the context's stream; the launches and their arguments are the same either way,
  * and so are the results. sj_bind_workspace drops the recorded graphs. */
 #define SJ_FLAG_EAGER 2u
-/* Count a 3-cycle query (three relations joined in a cycle) with the binary plan, which
- * expands every wedge of the spanning tree and then checks the closing edge, instead
- * of the default intersection walk (see sj_join). The result is the same; for
- * comparisons. */
+/* Count and write 3-cycle and 4-clique queries with the binary plan, which expands the
+ * spanning tree and then checks the closing edges, instead of the default intersection
+ * walk (see sj_join). The result is the same; for comparisons. */
 #define SJ_FLAG_BINARY_CYCLES 4u
 /* Failure injection, for tests of error handling: the named phase fails with
  * SJ_ERR_DEVICE, as a failed HIP call would, before it enqueues anything (no device
@@ -190,16 +189,22 @@ sj_status sj_sieve(sj_plan_t *plan, uint64_t *survivors);
 
 /* Enumeration phase, count pass (Section 2.2 step 2): hash tables on the sieved
  * relations, exact result size and checksum. Waits for the stream; count and
- * checksum are host pointers (either may be NULL). Acyclic graphs and cyclic
- * graphs whose closing edges all end at the last relation of the preorder, which
- * must be a leaf, are executed; other cyclic graphs return SJ_ERR_UNSUPPORTED.
- * A 3-cycle (root - P - L - root, one closing edge) is counted by intersection
- * (the multi-way join that Section 3.1.3 pairs with the sieve): for each root
- * survivor the smaller of P's rows joining it and L's rows closing on it is walked,
- * and each one's partner key is looked up in a hash of the other relation's
- * (key, key) pairs. Its tuples (sj_result) are still decoded from the binary plan's
- * count pass, which sj_result runs first. SJ_FLAG_BINARY_CYCLES selects the binary
- * plan for the count too. */
+ * checksum are host pointers (either may be NULL). Acyclic graphs, and cyclic graphs
+ * of at most 8 relations and 4 closing edges (Section 2.3), are executed; larger
+ * cyclic graphs return SJ_ERR_UNSUPPORTED. A cyclic graph runs the binary plan: the
+ * spanning tree without the last relation L of the preorder (a leaf) is enumerated,
+ * and each prefix is matched with L's rows below its parent that satisfy every
+ * closing edge. Two shapes are counted by intersection instead (the multi-way join
+ * that Section 3.1.3 pairs with the sieve), with their tuples written by the same
+ * walk (in walk order, not sorted):
+ *   3-cycle root - P - L - root: for each root survivor the smaller of P's rows
+ *     joining it and L's rows closing on it is walked, and each one's partner key is
+ *     looked up in a hash of the other relation's (key, key) pairs;
+ *   4-clique (six relations, one per pair of four variables a, b, c, d; the root's
+ *     two join columns are a and b): for each root row (a, b) the values c come from
+ *     the smaller of ac(a) and bc(b), and for each c the values d from the smallest of
+ *     ad(a), bd(b) and cd(c), each checked in the other relations' pair hashes.
+ * SJ_FLAG_BINARY_CYCLES selects the binary plan for these shapes too. */
 sj_status sj_join(sj_plan_t *plan, uint64_t *count, uint64_t *checksum);
 
 /* What sj_result writes per result tuple (Section 2.2: the join result itself; the
@@ -237,8 +242,9 @@ sj_status sj_plan_footprint(const sj_plan_t *plan, int32_t mode, uint64_t *works
 /* Asynchronous variant of the enumeration (Section 2.2 step 2), for callers that do
  * not need the count on the host before the tuples (a whole query then runs without
  * a host round trip; every phase is replayed as a recorded graph). sj_join_async takes
- * acyclic plans and 3-cycles counted by intersection; sj_result_async acyclic plans
- * only. Other cyclic plans return SJ_ERR_UNSUPPORTED (their count needs a host step).
+ * acyclic plans and the 3-cycles and 4-cliques counted by intersection; sj_result_async
+ * acyclic plans only. Other cyclic plans return SJ_ERR_UNSUPPORTED (their count needs
+ * a host step).
  *   sj_join_async    enqueues the count pass; the count stays on the device.
  *   sj_result_async  enqueues the materialisation into out_dev (room for
  *                    capacity_tuples tuples, in `mode` as for sj_result): the kernels

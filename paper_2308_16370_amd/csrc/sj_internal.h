@@ -312,9 +312,20 @@ struct CycArgs {
     const uint32_t *Lrid;
     const int32_t *Lclose;     // L's closing column in bucket order (ascending as u32 inside a bucket)
     const uint64_t *Lcv;       // exclusive prefix of L's checksum factors
+    // closing edges ending at L on the column L is sorted by: their values on the prefix
+    // must agree, and select the run of L's bucket that holds that value
     int nclose;
     int cpos[kMaxClose];       // position of each closing edge's other end
     const int32_t *ccol[kMaxClose];  // its closing column, entry-indexed
+    // closing edges ending at L on another column: checked on each entry of the run
+    int nextra;
+    int xpos[kMaxClose];
+    const int32_t *xcol[kMaxClose];  // the prefix side, entry-indexed
+    const int32_t *xL[kMaxClose];    // L's column, in L's bucket order
+    // closing edges between two prefix relations: checked on the prefix
+    int ninner;
+    int ipos[kMaxClose][2];
+    const int32_t *icol[kMaxClose][2];
     uint64_t wpre;             // number of prefixes
     uint32_t G;                // threads; thread t takes an even share of the prefixes
     uint64_t *cnt;             // [G] results per thread

@@ -878,8 +878,18 @@ __device__ __forceinline__ uint32_t upper_bound_u32(const int32_t *a, uint32_t l
     return lo;
 }
 
+// Entry of position pos in the current prefix.
+template <int N>
+__device__ __forceinline__ uint32_t entry_at(const MatState<N> &st, int pos) {
+    uint32_t e = st.e[0];
+#pragma unroll
+    for (int q = 1; q < N; ++q)
+        if (q == pos) e = st.e[q];
+    return e;
+}
+
 // The run of L entries matching the current prefix: [r0, r1) (empty if the closing
-// values disagree).
+// values disagree, or a closing edge between two prefix relations fails).
 template <int N>
 __device__ __forceinline__ void cyc_run(const CycArgs &a, const MatState<N> &st, uint32_t &r0, uint32_t &r1) {
     uint32_t ep = st.e[0];
@@ -889,6 +899,15 @@ __device__ __forceinline__ void cyc_run(const CycArgs &a, const MatState<N> &st,
     const uint32_t lo = a.Lblo[ep], hi = a.Lbhi[ep];
     r0 = r1 = lo;
     if (lo == hi) return;
+#pragma unroll
+    for (int c = 0; c < kMaxClose; ++c) {
+        if (c < a.ninner && a.icol[c][0][entry_at<N>(st, a.ipos[c][0])] != a.icol[c][1][entry_at<N>(st, a.ipos[c][1])])
+            return;
+    }
+    if (a.nclose == 0) {   // no closing edge ends at L: its whole bucket
+        r1 = hi;
+        return;
+    }
     uint32_t val = 0;
     bool agree = true;
 #pragma unroll
@@ -908,6 +927,28 @@ __device__ __forceinline__ void cyc_run(const CycArgs &a, const MatState<N> &st,
     if (!agree) return;
     r0 = lower_bound_u32(a.Lclose, lo, hi, val);
     r1 = upper_bound_u32(a.Lclose, r0, hi, val);
+}
+
+// One result tuple (the prefix and L's row lrid) at output index o.
+template <int N>
+__device__ __forceinline__ void cyc_write(const CycArgs &a, const MatState<N> &st, uint32_t lrid, uint64_t o) {
+    if (a.m.proj.n == 0) {
+        int32_t *dst = a.out + o * a.nrels;
+#pragma unroll
+        for (int x = 0; x < N; ++x) dst[a.m.order[x]] = static_cast<int32_t>(a.m.rid[x][st.e[x]]);
+        dst[a.L_rel] = static_cast<int32_t>(lrid);
+    } else {
+        const uint32_t W = static_cast<uint32_t>(a.m.proj.n);
+        int32_t *dst = a.out + o * W;
+        for (uint32_t q = 0; q < W; ++q) {
+            const int rel = a.m.proj.rel[q];
+            uint32_t rid = lrid;
+#pragma unroll
+            for (int x = 0; x < N; ++x)
+                if (a.m.order[x] == rel) rid = a.m.rid[x][st.e[x]];
+            dst[q] = a.m.proj.col[q][rid];
+        }
+    }
 }
 
 template <int N>
@@ -935,7 +976,27 @@ __global__ __launch_bounds__(256) void k_cyclic(CycArgs a) {
         for (uint64_t i = s;;) {
             uint32_t r0, r1;
             cyc_run<N>(a, st, r0, r1);
-            if (r1 > r0) {
+            if (r1 > r0 && a.nextra > 0) {
+                // closing edges at L on other columns: test each entry of the run
+                uint32_t xv[kMaxClose];
+#pragma unroll
+                for (int c = 0; c < kMaxClose; ++c)
+                    xv[c] = c < a.nextra ? static_cast<uint32_t>(a.xcol[c][entry_at<N>(st, a.xpos[c])]) : 0u;
+                const uint64_t pf = WRITE ? 0 : prefix_factor<N>(a, st);
+                for (uint32_t j = r0; j < r1; ++j) {
+                    bool ok = true;
+#pragma unroll
+                    for (int c = 0; c < kMaxClose; ++c)
+                        if (c < a.nextra && static_cast<uint32_t>(a.xL[c][j]) != xv[c]) ok = false;
+                    if (!ok) continue;
+                    if (!WRITE) {
+                        ++cnt;
+                        chk += pf * chk_factor(static_cast<uint32_t>(a.L_rel), a.Lrid[j]);
+                    } else {
+                        cyc_write<N>(a, st, a.Lrid[j], o++);
+                    }
+                }
+            } else if (r1 > r0) {
                 if (WRITE && a.m.proj.n == 0) {
                     for (uint32_t j = r0; j < r1; ++j, ++o) {
                         int32_t *dst = a.out + o * a.nrels;

@@ -865,11 +865,14 @@ extern "C" sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, con
     schedule_levels(p);
     p->L = p->preorder.back();
     p->cyclic = !p->closing.empty();
+    // The binary plan enumerates the spanning tree without L (the last relation of the
+    // preorder, a leaf) and matches L per prefix: L is sorted by the column of the first
+    // closing edge that ends at it, other closing edges at L are checked per entry, and
+    // closing edges between two other relations per prefix.
     if (p->closing.size() > static_cast<size_t>(kMaxClose) || (p->cyclic && nrels > 8)) p->cyc_ok = false;
-    for (const Closing &c : p->closing) {
-        if (c.v != p->L || (p->cyc_cv >= 0 && c.cv != p->cyc_cv)) p->cyc_ok = false;
-        p->cyc_cv = c.cv;
-    }
+    for (const Closing &c : p->closing)
+        if (c.v == p->L && p->cyc_cv < 0) p->cyc_cv = c.cv;
+    if (p->cyclic && nrels == 6 && !(o.flags & SJ_FLAG_BINARY_CYCLES)) detect_k4(p);
     if (p->cyclic && p->cyc_ok && nrels == 3 && p->closing.size() == 1 && !(o.flags & SJ_FLAG_BINARY_CYCLES)) {
         // the 3-cycle root - P - L - root: counted by intersection when the pair hashes fit
         const int r = p->root;
@@ -880,7 +883,6 @@ extern "C" sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, con
             p->tri_P = P;
         }
     }
-    if (p->cyclic && !p->cyc_ok && !(o.flags & SJ_FLAG_BINARY_CYCLES)) detect_k4(p);
     p->region_blocks = kRegionBytes / (o.block_bits / 8);
     for (auto &f : p->filters) {
         const uint64_t nbm = f.max_words / (o.block_bits / 32);
@@ -1397,17 +1399,27 @@ static CycArgs cyc_args(sj_plan_t *p, int32_t *out) {
     c.Lbhi = at<uint32_t>(p, p->off_bhi[P][ci]);
     const Buckets bl = buckets_of(p, L);
     c.Lrid = bl.rid;
-    c.Lclose = bl.col[p->rels[L].jidx(p->cyc_cv)];
+    c.Lclose = p->cyc_cv >= 0 ? bl.col[p->rels[L].jidx(p->cyc_cv)] : nullptr;
     c.Lcv = bl.cv;
-    c.nclose = static_cast<int>(p->closing.size());
-    for (int e = 0; e < c.nclose && e < kMaxClose; ++e) {
-        const Closing &cl = p->closing[e];
-        c.cpos[e] = pos[cl.u];
-        const int jc = p->rels[cl.u].jidx(cl.cu);
-        if (cl.u == p->root)
-            c.ccol[e] = list_col(p, cl.u, p->final_list[cl.u], jc);
-        else
-            c.ccol[e] = buckets_of(p, cl.u).col[jc];
+    // a prefix relation's join column, entry-indexed (the root's survivor list, else buckets)
+    auto ecol = [&](int rel, int col) -> const int32_t * {
+        const int jc = p->rels[rel].jidx(col);
+        return rel == p->root ? list_col(p, rel, p->final_list[rel], jc) : buckets_of(p, rel).col[jc];
+    };
+    for (const Closing &cl : p->closing) {
+        if (cl.v == L && cl.cv == p->cyc_cv) {
+            c.cpos[c.nclose] = pos[cl.u];
+            c.ccol[c.nclose++] = ecol(cl.u, cl.cu);
+        } else if (cl.v == L) {
+            c.xpos[c.nextra] = pos[cl.u];
+            c.xcol[c.nextra] = ecol(cl.u, cl.cu);
+            c.xL[c.nextra++] = bl.col[p->rels[L].jidx(cl.cv)];
+        } else {
+            c.ipos[c.ninner][0] = pos[cl.u];
+            c.ipos[c.ninner][1] = pos[cl.v];
+            c.icol[c.ninner][0] = ecol(cl.u, cl.cu);
+            c.icol[c.ninner++][1] = ecol(cl.v, cl.cv);
+        }
     }
     c.wpre = p->wpre;
     c.G = p->cyc_G;
@@ -1508,7 +1520,7 @@ static sj_status enqueue_join(sj_plan_t *p) {
         const uint32_t *lcount = at<uint32_t>(p, p->steps[p->final_step[j]].off_count);
         Buckets b = buckets_of(p, j);
         int sec = -1;   // L of a cyclic join is ordered by its closing column inside each bucket
-        if (p->cyclic && j == p->L && p->cyc_cv != p->mycol[j]) sec = R.jidx(p->cyc_cv);
+        if (p->cyclic && j == p->L && p->cyc_cv >= 0 && p->cyc_cv != p->mycol[j]) sec = R.jidx(p->cyc_cv);
         {
             ProfScope ps(p, std::string("buckets:") + rel_name(j), j, kProfBuckets);
             SJ_HIP(p->ctx, launch_build_buckets(list_rid(p, j, fl), lcols.data(), ncol, lcount, b.key_jcol, sec, b,
@@ -1741,10 +1753,8 @@ extern "C" sj_status sj_join(sj_plan_t *p, uint64_t *count, uint64_t *checksum) 
     if (sj_status st = check_exec(p, kSieved)) return st;
     if (sj_status st = injected(p, SJ_FLAG_FAULT_JOIN, "sj_join")) return st;
     if (!p->cyc_ok && !p->k4)
-        return fail(p->ctx, SJ_ERR_UNSUPPORTED,
-                    "cyclic join: every closing edge must end at the last relation of the preorder (relation %d), "
-                    "on one column, or the query must be a 4-clique",
-                    p->L);
+        return fail(p->ctx, SJ_ERR_UNSUPPORTED, "cyclic join with more than %d closing edges or more than 8 relations",
+                    kMaxClose);
     hipStream_t s = p->ctx->stream;
     uint64_t tot[2] = {0, 0};
     p->cyc_counted = false;

@@ -293,15 +293,25 @@ void scenario_cycles() {
     all_modes("triangle one pass", t, 1);
     Query c4 = cycle(4, 500);
     all_modes("4-cycle", c4);
-    // a chain 0-1-2-3 with a closing edge 0-2: it does not end at the last relation of the preorder
+    // a chain 0-1-2-3 with a closing edge 0-2 (between two relations before the last of
+    // the preorder: checked per prefix) and one 1-3 on another column of relation 3
     Query u;
     for (int i = 0; i < 4; ++i) u.add(300, 3);
     u.edge(0, 1, 1, 0);
     u.edge(1, 1, 2, 0);
     u.edge(2, 1, 3, 0);
     u.edge(0, 2, 2, 2);
+    u.edge(1, 2, 3, 2);
     u.finish();
-    all_modes("unsupported cycle", u, 2, 0, false);
+    all_modes("general cycles", u);
+    // more closing edges than the binary plan takes: refused
+    Query w;
+    for (int i = 0; i < 3; ++i) w.add(200, 6);
+    w.edge(0, 0, 1, 0);
+    w.edge(1, 1, 2, 0);
+    for (int c = 1; c <= 5; ++c) w.edge(0, c, 2, c);
+    w.finish();
+    all_modes("too many closing edges", w, 2, 0, false);
     // the 4-clique: relations ab, ac, ad, bc, bd, cd, each variable joining its three
     // relations by two edges; counted and written by intersection (the binary plan
     // refuses it)
@@ -315,7 +325,7 @@ void scenario_cycles() {
     all_modes("4-clique", k);
     all_modes("4-clique one pass", k, 1);
     g_clique = false;
-    all_modes("4-clique binary", k, 2, SJ_FLAG_BINARY_CYCLES, false);
+    all_modes("4-clique binary", k, 2, SJ_FLAG_BINARY_CYCLES);
 }
 
 void scenario_updates() {

@@ -13,8 +13,8 @@ stored value, with the 3-clique on the same graph (the 3-cycle path). The tuples
 come from the walk too (in walk order): at small sizes they equal the oracle's as
 a sorted multiset, in row ids and projected values; at the vote-network size every
 tuple satisfies every edge and their checksum is the oracle's. The binary plan
-(SJ_FLAG_BINARY_CYCLES) refuses the shape, and the asynchronous result refuses
-cyclic joins.
+(SJ_FLAG_BINARY_CYCLES) reaches the same count, checksum and tuples; the asynchronous
+result refuses cyclic joins.
 """
 import json
 import os
@@ -171,12 +171,14 @@ def test_async_count_graph_replays_and_refusals():
     with pytest.raises(sj.SjError) as e:
         p.result_async(torch.empty((want[0] + 1, 6), dtype=torch.int32, device="cuda:0"))
     assert e.value.code == sj.SJ_ERR_UNSUPPORTED
+    # the binary plan (spanning tree, closing edges checked per prefix and per entry of
+    # the last relation) reaches the same result, tuples sorted in preorder
     b = sj.Plan(sj.Context(0), rels, q.edges, binary_cycles=True, **OPTS)
     b.build_filters()
     b.sieve()
-    with pytest.raises(sj.SjError) as e:
-        b.join()
-    assert e.value.code == sj.SJ_ERR_UNSUPPORTED
+    assert b.join() == want
+    tb = b.result().cpu().numpy().astype(np.uint32)
+    assert np.array_equal(lexsort_rows(tb), lexsort_rows(ref))
 
 
 def test_vote_network_sized_cliques():
