@@ -41,7 +41,9 @@
  *   Tuples are written row-major, one int32 row id per relation in relation-index
  *   order, sorted lexicographically in the plan's enumeration order (relations in
  *   depth-first preorder from the root; for chains and stars listed root first,
- *   that is relation-index order).
+ *   that is relation-index order). Exception: 3-cycles and 4-cliques counted by
+ *   intersection (see sj_join) are written in the walk's order, the same in every
+ *   run but not sorted.
  */
 #ifndef SIEVEJOIN_H
 #define SIEVEJOIN_H
