@@ -227,6 +227,9 @@ def main():
     prof = pplan.profile()
     del pplan
     kernels = sorted(prof, key=lambda e: -e["total_ms"] / max(1, e["launches"]))
+    for e in kernels:
+        print("# launch group %-28s %8.2f us  %12d algorithmic bytes"
+              % (e["label"], e["total_ms"] / max(1, e["launches"]) * 1e3, e["alg_bytes"]), file=sys.stderr)
     # the roofline is for one kernel (one launch per group, so that the rocprofv3 trace
     # shows the same duration); groups of several launches (a relation's bucketing: the
     # radix passes, gather and directory; a DP's two launches) are reported beside it

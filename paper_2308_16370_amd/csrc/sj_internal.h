@@ -293,10 +293,30 @@ struct MatArgs {
     uint64_t capacity;             // tuples `out` holds: nothing is written if the total exceeds it
     int32_t *out;
     Projection proj;               // row ids (proj.n = 0) or projected values
+    // Factorised materialisation (launch_mat_table / launch_mat_output): position x's
+    // table of the tuples below each of its entries, for non-root positions with
+    // children (nullptr elsewhere): entry e's rows start at row cw[x][e], a row holds
+    // the row ids of x's subtree in preorder (subtree[x] words).
+    uint32_t *tab[kMatMaxRels];
+    uint64_t tab_words[kMatMaxRels];   // words tab[x] can hold
+    int subtree[kMatMaxRels];          // positions x .. x + subtree[x] - 1 form x's subtree
+    const uint32_t *n_ent[kMatMaxRels];   // device-side entry count of each position
+    int fact;                      // the factorised launches ran: launch_materialize then
+                                   // writes only if some table did not fit its scratch
 };
 // Grid: enough blocks for min(count, capacity) tuples when the count is on the host;
 // a fixed persistent grid over the output when it is read on the device.
 hipError_t launch_materialize(const MatArgs &a, hipStream_t s);
+// Factorised materialisation: the tables, deepest positions first (launch_mat_table for
+// each non-root position with children, in decreasing position order), then the output
+// as one expansion of the root (launch_mat_output). Usable when every position has at
+// most kFactMaxChild children and each table position has its scratch (mat_factorisable);
+// if some table does not fit its scratch, these launches write nothing and a following
+// launch_materialize (with fact = 1) writes the output instead.
+constexpr int kFactMaxChild = 4;
+bool mat_factorisable(const MatArgs &a);
+hipError_t launch_mat_table(const MatArgs &a, int x, hipStream_t s);
+hipError_t launch_mat_output(const MatArgs &a, hipStream_t s);
 
 // Cyclic joins whose closing edges all end at the last relation L of the preorder
 // (a leaf): the other relations form a tree (the "prefix") whose tuples are

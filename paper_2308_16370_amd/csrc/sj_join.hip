@@ -701,9 +701,26 @@ __device__ __forceinline__ void mat_advance(const MatArgs &a, MatState<N> &st, u
     }
 }
 
+// Whether every table of the factorised materialisation fits its scratch (the same
+// answer in every launch that asks).
+template <int N>
+__device__ bool mat_tables_fit(const MatArgs &a) {
+    bool ok = true;
+#pragma unroll
+    for (int x = 1; x < N; ++x) {
+        if (a.tab[x]) {
+            // rows are addressed with 32-bit bases, and the table must fit its scratch
+            const uint64_t rows = a.cw[x][*a.n_ent[x]];
+            if (rows >= (1ull << 32) || rows * static_cast<uint64_t>(a.subtree[x]) > a.tab_words[x]) ok = false;
+        }
+    }
+    return ok;
+}
+
 // Blocks of a materialisation whose count is read on the device (a grid-stride loop
 // over the output covers the rest).
 constexpr uint64_t kMatPersistentBlocks = 4096;
+constexpr uint64_t kMatFallbackBlocks = 512;
 
 // Tuples per thread: a thread's C tuples of N entries take at most 16 words of LDS.
 template <int N>
@@ -737,6 +754,7 @@ __global__ __launch_bounds__(256) void k_materialize(MatArgs a) {
     __shared__ uint32_t s_prel[VAL ? kMaxProj : 1];
     const uint64_t count = a.count_dev ? *a.count_dev : a.count;
     if (count > a.capacity) return;         // the caller's buffer is too small: write nothing
+    if (a.fact && mat_tables_fit<N>(a)) return;   // the factorised launches wrote the output
     const uint32_t root_n = *a.root_n;
     const uint64_t *rcw = a.cw[0];
     if (threadIdx.x == 64) {
@@ -833,6 +851,9 @@ hipError_t launch_materialize(const MatArgs &a, hipStream_t s) {
     if (tuples == 0) return hipSuccess;
     uint64_t blocks64 = (tuples + per - 1) / per;
     if (a.count_dev && blocks64 > kMatPersistentBlocks) blocks64 = kMatPersistentBlocks;
+    // after the factorised launches this decode writes only if a table did not fit:
+    // a small grid (the loop over the output covers the rest) keeps its launch short
+    if (a.fact && blocks64 > kMatFallbackBlocks) blocks64 = kMatFallbackBlocks;
     if (blocks64 > 0x7fffffffull) return hipErrorInvalidValue;
     const dim3 g(static_cast<uint32_t>(blocks64));
     if (a.proj.n < 0 || a.proj.n > kMaxProj) return hipErrorInvalidValue;
@@ -852,6 +873,313 @@ hipError_t launch_materialize(const MatArgs &a, hipStream_t s) {
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// ================================================================ factorised materialisation
+// The tuples below an entry e of position x are e's row id followed by, for each child
+// of x, the tuples below the child's bucket for e, combined as a mixed-radix number
+// (last child least significant). They depend on e alone, not on the parent entry that
+// reached it, so for each non-root position with children they are written once into a
+// table (entry e's rows at rows cw[x][e] .., a row holding the subtree's row ids in
+// preorder), deepest positions first. The output, like each table, is then a one-level
+// expansion: row o finds its entry e (the last with cw[e] <= o, searched in an LDS
+// window of the block's entries), and each child's part of the row is one row of the
+// child's table (a row id for a leaf) at the bucket's first prefix weight plus the
+// child's digit of o - cw[e]. A wave's lanes take consecutive rows, so the table reads
+// and the output writes are contiguous across the wave. Zipf-skewed chains repeat the
+// same heavy buckets below many parent entries; their tuples are read from a table
+// instead of being decoded again for every parent entry.
+//
+// A table takes its relation's sort scratch, which the join phase no longer needs.
+// Every launch checks that every table fits (the same answer in each); if one does
+// not, none is built and launch_materialize decodes the output instead.
+
+constexpr int kExpandC = 4;                         // rows per lane
+constexpr uint32_t kExpandPer = 256u * kExpandC;    // rows per block
+constexpr uint32_t kExpandWin = kExpandPer + 2;     // entries a block's LDS window holds
+static_assert(kExpandPer == 256u * 4u, "the row -> entry scan gives each thread four rows");
+
+// Expansion of position p (the output when OUT, p = 0; else p's table). NCH bounds the
+// children of p (LDS arrays); VAL writes projected values instead of row ids.
+//
+// A block owns kExpandPer consecutive rows. Its entries' prefix weights, row ids and
+// children's bucket bases (and bucket weights, for several children) are staged in LDS;
+// a row -> entry map of the block is filled by marking each entry's first row and a
+// block-wide maximum scan, so a row's entry is one LDS read. Lane l of a wave takes
+// rows l, l + 64, l + 128, l + 192 of the wave's 256, and issues the table reads of all
+// four before it writes any.
+template <int N, int NCH, bool OUT, bool VAL>
+__global__ __launch_bounds__(256) void k_mat_expand(MatArgs a, int p) {
+    __shared__ uint64_t s_cw[kExpandWin];
+    __shared__ uint32_t s_rid[kExpandWin];
+    __shared__ uint32_t s_base[NCH][kExpandWin];
+    __shared__ uint32_t s_w[NCH > 1 ? NCH : 1][NCH > 1 ? kExpandWin : 1];
+    __shared__ uint32_t s_ent[kExpandPer];
+    __shared__ uint32_t s_wave[256 / 64];
+    __shared__ uint32_t s_r[2];
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) s_ok = mat_tables_fit<N>(a) ? 1 : 0;
+    __syncthreads();
+    if (!s_ok) return;
+    uint64_t rows;
+    if constexpr (OUT) {
+        rows = a.count_dev ? *a.count_dev : a.count;
+        if (rows > a.capacity) return;      // the caller's buffer is too small: write nothing
+    } else {
+        rows = a.cw[p][*a.n_ent[p]];
+    }
+    const uint32_t n_p = *a.n_ent[p];
+    const uint64_t *cw = a.cw[p];
+    const uint32_t *rid = a.rid[p];
+    const uint32_t S = OUT ? 0u : static_cast<uint32_t>(a.subtree[p]);
+    uint32_t *tab_p = OUT ? nullptr : a.tab[p];
+    // p's children in position order: slot k of the LDS arrays
+    int nch = 0;
+    int cpos[NCH];
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) cpos[k] = N;
+#pragma unroll
+    for (int c = 1; c < N; ++c) {
+        if (c > p && a.parent_pos[c] == p) {
+#pragma unroll
+            for (int k = 0; k < NCH; ++k)
+                if (k == nch) cpos[k] = c;
+            ++nch;
+        }
+    }
+    const int lane = lane_id();
+    const uint32_t wrow = (threadIdx.x >> 6) * 64u * kExpandC;   // the wave's first row in the block
+    for (uint64_t blk = blockIdx.x; blk * kExpandPer < rows; blk += gridDim.x) {
+        const uint64_t t0 = blk * kExpandPer;
+        const uint64_t t1 = (t0 + kExpandPer < rows) ? t0 + kExpandPer : rows;
+        if (threadIdx.x < 128) {   // wave 0 finds the entry of t0, wave 1 that of t1 - 1
+            const int wv = threadIdx.x >> 6;
+            const uint32_t r = wave_upper_bound_u64(cw, 0, n_p + 1, wv == 0 ? t0 : t1 - 1) - 1;
+            if (lane == 0) s_r[wv] = r;
+        }
+        for (uint32_t j = threadIdx.x; j < kExpandPer; j += 256) s_ent[j] = 0;
+        __syncthreads();
+        const uint32_t r0 = s_r[0], r1 = s_r[1];
+        const uint32_t ne = r1 - r0 + 1;           // entries of the block's rows
+        const bool in_lds = ne + 1 <= kExpandWin;  // zero-weight entries can widen the range
+        if (in_lds) {
+            for (uint32_t i = threadIdx.x; i <= ne; i += 256) {
+                const uint64_t c0 = cw[r0 + i];
+                s_cw[i] = c0;
+                // entry i's first row (later entries of equal start have zero weight before it)
+                if (i > 0 && i < ne && c0 < t1) atomicMax(&s_ent[c0 - t0], i);
+                if (i < ne) {
+                    const uint32_t e = r0 + i;
+                    s_rid[i] = rid[e];
+#pragma unroll
+                    for (int k = 0; k < NCH; ++k) {
+                        if (k < nch) {
+                            const int c = cpos[k];
+                            const uint32_t lo = a.blo[c][e];
+                            if (a.is_leaf[c]) {
+                                s_base[k][i] = lo;
+                                if constexpr (NCH > 1) s_w[k][i] = a.bhi[c][e] - lo;
+                            } else {
+                                const uint64_t b = a.cw[c][lo];
+                                s_base[k][i] = static_cast<uint32_t>(b);
+                                if constexpr (NCH > 1) s_w[k][i] = static_cast<uint32_t>(a.cw[c][a.bhi[c][e]] - b);
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            // row -> entry: the running maximum of the marks (thread t holds rows 4t .. 4t + 3)
+            uint32_t m[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) m[q] = s_ent[threadIdx.x * 4 + q];
+#pragma unroll
+            for (int q = 1; q < 4; ++q) m[q] = max(m[q], m[q - 1]);
+            uint32_t x = m[3];
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t y = __shfl_up(x, d, 64);
+                if (lane >= d) x = max(x, y);
+            }
+            if (lane == 63) s_wave[threadIdx.x >> 6] = x;
+            uint32_t before = __shfl_up(x, 1, 64);
+            if (lane == 0) before = 0;
+            __syncthreads();
+#pragma unroll
+            for (int w = 0; w < 256 / 64; ++w)
+                if (w < static_cast<int>(threadIdx.x >> 6)) before = max(before, s_wave[w]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s_ent[threadIdx.x * 4 + q] = max(m[q], before);
+        }
+        __syncthreads();
+        // the lane's rows: entry, local index, and the children's rows
+        uint32_t wv[kExpandC][N];
+        uint64_t orow[kExpandC];
+        bool live[kExpandC];
+#pragma unroll
+        for (int i = 0; i < kExpandC; ++i) {
+            const uint64_t o = t0 + wrow + lane + 64u * i;
+            orow[i] = o;
+            live[i] = o < t1;
+#pragma unroll
+            for (int x = 0; x < N; ++x) wv[i][x] = 0;
+            if (!live[i]) continue;
+            uint64_t L;
+            uint32_t base[NCH], wdig[NCH];
+            if (in_lds) {
+                const uint32_t ei = s_ent[o - t0];
+                L = o - s_cw[ei];
+                wv[i][0] = s_rid[ei];
+#pragma unroll
+                for (int k = 0; k < NCH; ++k) {
+                    base[k] = s_base[k][ei];
+                    wdig[k] = NCH > 1 ? s_w[NCH > 1 ? k : 0][NCH > 1 ? ei : 0] : 0u;
+                }
+            } else {
+                const uint32_t e = upper_bound_u64(cw, r0, r1 + 2, o) - 1;
+                L = o - cw[e];
+                wv[i][0] = rid[e];
+#pragma unroll
+                for (int k = 0; k < NCH; ++k) {
+                    base[k] = 0;
+                    wdig[k] = 0;
+                    if (k < nch) {
+                        const int c = cpos[k];
+                        const uint32_t lo = a.blo[c][e];
+                        if (a.is_leaf[c]) {
+                            base[k] = lo;
+                            wdig[k] = a.bhi[c][e] - lo;
+                        } else {
+                            const uint64_t b = a.cw[c][lo];
+                            base[k] = static_cast<uint32_t>(b);
+                            wdig[k] = static_cast<uint32_t>(a.cw[c][a.bhi[c][e]] - b);
+                        }
+                    }
+                }
+            }
+            // wv[i][x - p] holds position x of p's subtree; the children's digits, last child least significant
+#pragma unroll
+            for (int k = NCH - 1; k >= 0; --k) {
+                if (k < nch) {
+                    uint64_t Lc;
+                    if (nch == 1) {
+                        Lc = L;
+                    } else {
+                        Lc = L % wdig[k];
+                        L /= wdig[k];
+                    }
+                    const int c = cpos[k];
+                    const uint64_t row = static_cast<uint64_t>(base[k]) + Lc;
+                    if (a.is_leaf[c]) {
+#pragma unroll
+                        for (int x = 1; x < N; ++x)
+                            if (x == c - p) wv[i][x] = a.rid[c][row];
+                    } else {
+                        const uint32_t Sc = static_cast<uint32_t>(a.subtree[c]);
+                        const uint32_t *src = a.tab[c] + row * Sc;
+#pragma unroll
+                        for (int x = 1; x < N; ++x)
+                            if (x >= c - p && x < c - p + static_cast<int>(Sc)) wv[i][x] = src[x - (c - p)];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kExpandC; ++i) {
+            if (!live[i]) continue;
+            const uint64_t o = orow[i];
+            if constexpr (OUT) {
+                if constexpr (VAL) {
+                    const uint32_t W = static_cast<uint32_t>(a.proj.n);
+                    int32_t *dst = a.out + o * W;
+                    for (uint32_t q = 0; q < W; ++q) {
+                        const int rel = a.proj.rel[q];
+                        uint32_t r = 0;
+#pragma unroll
+                        for (int x = 0; x < N; ++x)
+                            if (a.order[x] == rel) r = wv[i][x];
+                        dst[q] = a.proj.col[q][r];
+                    }
+                } else {
+                    // relation order: output word j is the position holding relation j
+                    uint32_t v[N];
+#pragma unroll
+                    for (int j = 0; j < N; ++j) {
+                        v[j] = 0;
+#pragma unroll
+                        for (int x = 0; x < N; ++x)
+                            if (a.order[x] == j) v[j] = wv[i][x];
+                    }
+                    int32_t *dst = a.out + o * N;
+                    if constexpr (N % 4 == 0) {
+#pragma unroll
+                        for (int j = 0; j < N; j += 4)
+                            *reinterpret_cast<int4 *>(dst + j) = make_int4(v[j], v[j + 1], v[j + 2], v[j + 3]);
+                    } else if constexpr (N % 2 == 0) {
+#pragma unroll
+                        for (int j = 0; j < N; j += 2) *reinterpret_cast<int2 *>(dst + j) = make_int2(v[j], v[j + 1]);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < N; ++j) dst[j] = static_cast<int32_t>(v[j]);
+                    }
+                }
+            } else {
+                uint32_t *dst = tab_p + o * S;
+#pragma unroll
+                for (int x = 0; x < N; ++x)
+                    if (x < static_cast<int>(S)) dst[x] = wv[i][x];
+            }
+        }
+        __syncthreads();   // s_r, s_ent and the window are reused by the next block of rows
+    }
+}
+
+bool mat_factorisable(const MatArgs &a) {
+    if (a.nrels < 1 || a.nrels > kMatMaxRels) return false;
+    for (int x = 0; x < a.nrels; ++x) {
+        if (a.nchild[x] > kFactMaxChild) return false;
+        if (x > 0 && !a.is_leaf[x] && (!a.tab[x] || a.subtree[x] < 2)) return false;
+        if (!a.n_ent[x]) return false;
+    }
+    return true;
+}
+
+template <int N, bool OUT, bool VAL>
+static void launch_expand_n(const MatArgs &a, int x, dim3 g, hipStream_t s) {
+    if (a.nchild[x] <= 1)
+        hipLaunchKernelGGL((k_mat_expand<N, 1, OUT, VAL>), g, dim3(256), 0, s, a, x);
+    else
+        hipLaunchKernelGGL((k_mat_expand<N, kFactMaxChild, OUT, VAL>), g, dim3(256), 0, s, a, x);
+}
+
+template <bool OUT, bool VAL>
+static hipError_t launch_expand(const MatArgs &a, int x, uint64_t rows_max, hipStream_t s) {
+    if (rows_max == 0) return hipSuccess;
+    uint64_t blocks64 = (rows_max + kExpandPer - 1) / kExpandPer;
+    if (blocks64 > kMatPersistentBlocks) blocks64 = kMatPersistentBlocks;
+    const dim3 g(static_cast<uint32_t>(blocks64));
+    switch (a.nrels) {
+#define SJ_EXP_CASE(NN) \
+    case NN: launch_expand_n<NN, OUT, VAL>(a, x, g, s); break;
+        SJ_EXP_CASE(1) SJ_EXP_CASE(2) SJ_EXP_CASE(3) SJ_EXP_CASE(4) SJ_EXP_CASE(5) SJ_EXP_CASE(6) SJ_EXP_CASE(7)
+        SJ_EXP_CASE(8) SJ_EXP_CASE(9) SJ_EXP_CASE(10) SJ_EXP_CASE(11) SJ_EXP_CASE(12) SJ_EXP_CASE(13)
+        SJ_EXP_CASE(14) SJ_EXP_CASE(15) SJ_EXP_CASE(16)
+#undef SJ_EXP_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mat_table(const MatArgs &a, int x, hipStream_t s) {
+    if (!mat_factorisable(a) || x <= 0 || x >= a.nrels || a.is_leaf[x]) return hipErrorInvalidValue;
+    return launch_expand<false, false>(a, x, a.tab_words[x] / static_cast<uint64_t>(a.subtree[x]), s);
+}
+
+hipError_t launch_mat_output(const MatArgs &a, hipStream_t s) {
+    if (!mat_factorisable(a)) return hipErrorInvalidValue;
+    if (a.proj.n < 0 || a.proj.n > kMaxProj) return hipErrorInvalidValue;
+    const uint64_t rows = a.count_dev ? a.capacity : min(a.count, a.capacity);
+    return a.proj.n > 0 ? launch_expand<true, true>(a, 0, rows, s) : launch_expand<true, false>(a, 0, rows, s);
 }
 
 // ================================================================ cyclic joins

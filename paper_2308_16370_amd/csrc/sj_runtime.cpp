@@ -1382,7 +1382,52 @@ static MatArgs mat_args(sj_plan_t *p, int npos) {
         }
     }
     m.root_n = at<uint32_t>(p, p->steps[p->final_step[root]].off_count);
+    // subtree sizes (preorder: x's subtree is x .. x + subtree[x] - 1) and the tables of
+    // the factorised materialisation, in each relation's sort scratch
+    for (int x = npos - 1; x >= 0; --x) {
+        m.subtree[x] = 1;
+        for (int y = x + 1; y < npos; ++y)
+            if (m.parent_pos[y] == x) m.subtree[x] += m.subtree[y];
+    }
+    for (int x = 0; x < npos; ++x) {
+        const int r = p->preorder[x];
+        m.n_ent[x] = at<uint32_t>(p, p->steps[p->final_step[r]].off_count);
+        if (x > 0 && !m.is_leaf[x]) {
+            const auto &jr = p->jr[r];
+            const uint64_t cap = std::max<uint32_t>(1, p->rels[r].nrows);
+            m.tab[x] = at<uint32_t>(p, jr.sklo[0]);
+            m.tab_words[x] = (jr.svals[1] + 4 * cap - jr.sklo[0]) / 4;
+        }
+    }
     return m;
+}
+
+// Materialisation of the whole tree: the factorised launches (tables, then the output,
+// then the decode, which writes only if some table did not fit) when the tree allows
+// them, else the decode alone.
+static sj_status launch_result(sj_plan_t *p, MatArgs &m, hipStream_t s) {
+    if (!mat_factorisable(m)) {
+        ProfScope ps(p, "materialize", -1, kProfResult);
+        SJ_HIP(p->ctx, launch_materialize(m, s));
+        return SJ_OK;
+    }
+    m.fact = 1;
+    bool tables = false;
+    for (int x = m.nrels - 1; x >= 1; --x) {
+        if (m.is_leaf[x]) continue;
+        tables = true;
+        ProfScope ps(p, "mat_table:" + rel_name(p->preorder[x]), -1, kProfOther);
+        SJ_HIP(p->ctx, launch_mat_table(m, x, s));
+    }
+    {
+        ProfScope ps(p, "materialize", -1, kProfResult);
+        SJ_HIP(p->ctx, launch_mat_output(m, s));
+    }
+    if (tables) {
+        ProfScope ps(p, "mat_fallback", -1, kProfOther);
+        SJ_HIP(p->ctx, launch_materialize(m, s));
+    }
+    return SJ_OK;
 }
 
 static CycArgs cyc_args(sj_plan_t *p, int32_t *out) {
@@ -1832,9 +1877,7 @@ static sj_status enqueue_result_async(sj_plan_t *p) {
     m.capacity = p->res_cap;
     m.out = p->res_out;
     if (sj_status st = projection_of(p, p->res_mode, m.proj)) return st;
-    ProfScope ps(p, "materialize", -1, kProfResult);
-    SJ_HIP(p->ctx, launch_materialize(m, p->ls));
-    return SJ_OK;
+    return launch_result(p, m, p->ls);
 }
 
 extern "C" sj_status sj_result_async(sj_plan_t *p, int32_t *out, uint64_t capacity, int32_t mode) {
@@ -1909,9 +1952,7 @@ extern "C" sj_status sj_result(sj_plan_t *p, int32_t *out, uint64_t capacity, in
     m.out = out;
     m.proj = pr;
     p->res_mode = mode;   // for the profile's byte model
-    ProfScope ps(p, "materialize", -1, kProfResult);
-    SJ_HIP(p->ctx, launch_materialize(m, p->ctx->stream));
-    return SJ_OK;
+    return launch_result(p, m, p->ctx->stream);
 }
 
 extern "C" sj_status sj_plan_set_projection(sj_plan_t *p, const int32_t *rel_col, int32_t n) {

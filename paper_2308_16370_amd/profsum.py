@@ -13,6 +13,12 @@
 
     python -m paper_2308_16370_amd.profsum counters PASS1.db [PASS2.db ...] [--kernel SUBSTR]
         Markdown: the mean of every PMC counter per (kernel, launch position in a step).
+
+    python -m paper_2308_16370_amd.profsum timeline RUN.db [--cmd TEXT]
+        Markdown: per steady step, the span from its first launch's start to its last
+        launch's end, the time some kernel runs (union of the launches' intervals) and
+        the sum of launch durations; then the launches of the median step in start
+        order, each with its start offset, duration and the idle time before it.
 """
 from __future__ import annotations
 
@@ -157,6 +163,60 @@ def cmd_counters(args):
     print("\n".join(out))
 
 
+def _union(iv):
+    """Total length covered by a list of (start, end) intervals."""
+    tot, cur_s, cur_e = 0, None, None
+    for a, b in sorted(iv):
+        if cur_e is None or a > cur_e:
+            if cur_e is not None:
+                tot += cur_e - cur_s
+            cur_s, cur_e = a, b
+        else:
+            cur_e = max(cur_e, b)
+    if cur_e is not None:
+        tot += cur_e - cur_s
+    return tot
+
+
+def cmd_timeline(args):
+    db = sqlite3.connect(args.db)
+    steps = _steps(_dispatches(db), args.step_end)[args.skip:]
+    if args.max_launches:
+        steps = [st for st in steps if len(st) <= args.max_launches]
+    out = []
+    if args.cmd:
+        out.append("Command: `%s`\n" % args.cmd)
+    if not steps:
+        print("no steady steps")
+        return
+    rows = []
+    for st in steps:
+        t0 = min(r[1] for r in st)
+        t1 = max(r[2] for r in st)
+        busy = _union([(r[1], r[2]) for r in st])
+        tot = sum(r[2] - r[1] for r in st)
+        rows.append((t1 - t0, busy, tot, len(st), st))
+    out.append("| step | launches | span us | busy us | idle us | sum of durations us |")
+    out.append("|---:|---:|---:|---:|---:|---:|")
+    for i, (span, busy, tot, n, _) in enumerate(rows):
+        out.append("| %d | %d | %.1f | %.1f | %.1f | %.1f |" % (i, n, span / 1e3, busy / 1e3, (span - busy) / 1e3,
+                                                                tot / 1e3))
+    med = sorted(rows, key=lambda r: r[0])[len(rows) // 2]
+    st = sorted(med[4], key=lambda r: r[1])
+    t0 = st[0][1]
+    out.append("")
+    out.append("Median step (span %.1f us), launches in start order:\n" % (med[0] / 1e3))
+    out.append("| # | kernel | grid | start us | duration us | idle before us |")
+    out.append("|---:|---|---:|---:|---:|---:|")
+    reach = t0
+    for i, (name, s, e, gx, wx) in enumerate(st):
+        idle = max(0, s - reach)
+        reach = max(reach, e)
+        out.append("| %d | %s | %d | %.1f | %.1f | %.1f |" % (i, _short(name), gx // max(wx, 1), (s - t0) / 1e3,
+                                                               (e - s) / 1e3, idle / 1e3))
+    print("\n".join(out))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -183,6 +243,13 @@ def main(argv=None):
     c.add_argument("--kernel", action="append", default=[])
     c.add_argument("--cmd", action="append", default=[])
     c.set_defaults(fn=cmd_counters)
+    tl = sub.add_parser("timeline")
+    tl.add_argument("db")
+    tl.add_argument("--cmd", default="")
+    tl.add_argument("--step-end", default="k_materialize")
+    tl.add_argument("--skip", type=int, default=1)
+    tl.add_argument("--max-launches", type=int, default=0)
+    tl.set_defaults(fn=cmd_timeline)
     args = ap.parse_args(argv)
     args.fn(args)
 
