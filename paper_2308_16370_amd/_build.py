@@ -23,6 +23,12 @@ def build(verbose: bool = False, out: str = LIB, defines=(), csrc: str = CSRC) -
 
     ``defines`` are extra ``-D`` tuning macros (the defaults are the tuned values);
     ``csrc`` is the source directory."""
+    def snapshot():
+        files = [os.path.join(csrc, f) for f in os.listdir(csrc)] + \
+                [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE)]
+        return {f: os.stat(f).st_mtime_ns for f in files if os.path.isfile(f)}
+
+    before = snapshot()
     with tempfile.TemporaryDirectory(prefix="sjbuild") as tmp:
         def compile_one(src):
             obj = os.path.join(tmp, os.path.splitext(src)[0] + ".o")
@@ -42,6 +48,11 @@ def build(verbose: bool = False, out: str = LIB, defines=(), csrc: str = CSRC) -
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("link failed:\n%s" % r.stderr[-4000:])
+        # a source edited while the objects compiled would leave objects built from
+        # different versions of the shared headers in one library: refuse it
+        if snapshot() != before:
+            os.remove(out_tmp)
+            raise RuntimeError("a source file changed during the build; build again")
         os.replace(out_tmp, out)
     return out
 

@@ -2630,7 +2630,7 @@ extern "C" sj_status sj_profile_collect(sj_plan_t *p) {
             SJ_HIP(p->ctx, hipMemcpy(&n, at<uint32_t>(p, p->steps[p->final_step[j]].off_count), 4,
                                      hipMemcpyDeviceToHost));
             if (r.kind == kProfBuckets && j != p->root) {
-                uint32_t ctl[8] = {}, ndir = 0;
+                uint32_t ctl[kRadixPasses] = {}, ndir = 0;
                 SJ_HIP(p->ctx, hipMemcpy(ctl, at<uint32_t>(p, p->jr[j].sctl), sizeof ctl, hipMemcpyDeviceToHost));
                 SJ_HIP(p->ctx, hipMemcpy(&ndir, at<uint32_t>(p, p->jr[j].ndir), 4, hipMemcpyDeviceToHost));
                 uint64_t passes = 0;
