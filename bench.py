@@ -82,9 +82,12 @@ def load_traffic(label):
         t = json.load(open(path))
     except Exception:
         return None
-    if t.get("source_hash") != lib_source_hash() or t.get("label") != label:
+    if t.get("source_hash") != lib_source_hash():
         return None
-    return t.get("bytes_per_launch")
+    for e in t.get("entries", [t]):
+        if e.get("label") == label:
+            return e.get("bytes_per_launch")
+    return None
 
 
 def host_cpu():
@@ -252,6 +255,19 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom["label"],
                     "alg_bytes_per_launch": dom["alg_bytes"], "avg_us": round(avg_s * 1e6, 2),
                     "copy_kernel_gbs": round(copy_gbs, 1)}
+    # the result: the materialisation's output launch (the expansion of the root), with
+    # the launches before it (the tables of the factorised materialisation, and the
+    # decode that writes only when a table does not fit its scratch)
+    result_roofline = None
+    res = next((e for e in prof if e["label"] == "materialize" and e["alg_bytes"] > 0), None)
+    if res:
+        avg_s = res["total_ms"] / res["launches"] / 1e3
+        ach = res["alg_bytes"] / avg_s / 1e9
+        result_roofline = {"bound": "hbm", "kernel": "materialize", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": res["alg_bytes"],
+                           "avg_us": round(avg_s * 1e6, 2), "traffic": load_traffic("materialize"),
+                           "other_launches_us": {e["label"]: round(e["total_ms"] / max(1, e["launches"]) * 1e3, 2)
+                                                 for e in prof if e["label"].startswith("mat_")}}
     # the sieve passes together (every probe, compaction and filter-build launch of a
     # step): their algorithmic bytes over their summed event-timed durations
     sieve = [e for e in prof if e["label"].split(":")[0] in ("probe", "compact", "bfb_hist", "bfb_scan",
@@ -359,6 +375,7 @@ def main():
                    "probe_grid": args.probe_grid or 256, "probe_lds": args.probe_lds},
         "roofline": roofline,
         "sieve_roofline": sieve_roofline,
+        "result_roofline": result_roofline,
         "launch_groups": groups[:8],
         "cpu_baseline": cpu,
         "check": check,

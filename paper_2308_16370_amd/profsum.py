@@ -5,11 +5,12 @@
         launches by their position inside a step (a step ends with the launch of the
         kernel named by --step-end), averaged over the steady steps.
 
-    python -m paper_2308_16370_amd.profsum traffic FETCH.db WRITE.db --kernel NAME
-            --occurrence I --copy-kernel NAME --copy-bytes N [--cmd TEXT]
-        JSON: HBM bytes per launch of occurrence I of kernel NAME from FETCH_SIZE and
-        WRITE_SIZE (KiB per dispatch), each scaled by bytes / counter of a plain copy
-        kernel of N bytes read and N bytes written in the same run.
+    python -m paper_2308_16370_amd.profsum traffic FETCH.db WRITE.db
+            --pick LABEL=KERNEL@I [--pick ...] --copy-kernel NAME --copy-bytes N [--cmd TEXT]
+        JSON: for each pick, HBM bytes per launch of occurrence I (in a step) of the
+        kernel whose name contains KERNEL, from FETCH_SIZE and WRITE_SIZE (KiB per
+        dispatch), each scaled by bytes / counter of a plain copy kernel of N bytes read
+        and N bytes written in the same run; with a hash of the kernel sources.
 
     python -m paper_2308_16370_amd.profsum counters PASS1.db [PASS2.db ...] [--kernel SUBSTR]
         Markdown: the mean of every PMC counter per (kernel, launch position in a step).
@@ -111,20 +112,40 @@ def _pick(vals, kernel: str, occurrence: int, step_end: str):
     return statistics.mean(picked) if picked else None, len(picked)
 
 
+def source_hash() -> str:
+    """Hash of the kernel sources (the same one bench.py compares)."""
+    import hashlib
+    import os
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def cmd_traffic(args):
-    out = {"command": args.cmd, "kernel": args.kernel, "occurrence": args.occurrence}
+    dbs = {}
     for counter, path in (("FETCH_SIZE", args.fetch_db), ("WRITE_SIZE", args.write_db)):
         db = sqlite3.connect(path)
         vals = _counter_per_dispatch(db, counter)
-        kv, n = _pick(vals, args.kernel, args.occurrence, args.step_end)
         copies = [v for name, _, v in vals if args.copy_kernel in name]
         cv = max(copies) if copies else None
-        scale = args.copy_bytes / (cv * 1024.0) if cv else None
-        out[counter] = {"kib_per_launch": kv, "launches": n, "copy_kib": cv,
-                        "scale": scale, "bytes_per_launch": kv * 1024.0 * scale if (kv and scale) else None}
-    f, w = out["FETCH_SIZE"]["bytes_per_launch"], out["WRITE_SIZE"]["bytes_per_launch"]
-    out["bytes_per_launch"] = f + w if (f is not None and w is not None) else None
-    print(json.dumps(out, indent=1))
+        dbs[counter] = (vals, cv, args.copy_bytes / (cv * 1024.0) if cv else None)
+    entries = []
+    for pick in args.pick:
+        label, rest = pick.split("=", 1)
+        kernel, occ = rest.rsplit("@", 1)
+        e = {"label": label, "kernel": kernel, "occurrence": int(occ)}
+        for counter, (vals, cv, scale) in dbs.items():
+            kv, n = _pick(vals, kernel, int(occ), args.step_end)
+            e[counter] = {"kib_per_launch": kv, "launches": n, "copy_kib": cv, "scale": scale,
+                          "bytes_per_launch": kv * 1024.0 * scale if (kv and scale) else None}
+        f, w = e["FETCH_SIZE"]["bytes_per_launch"], e["WRITE_SIZE"]["bytes_per_launch"]
+        e["bytes_per_launch"] = f + w if (f is not None and w is not None) else None
+        entries.append(e)
+    print(json.dumps({"command": args.cmd, "source_hash": source_hash(), "entries": entries}, indent=1))
 
 
 def cmd_counters(args):
@@ -230,8 +251,7 @@ def main(argv=None):
     t = sub.add_parser("traffic")
     t.add_argument("fetch_db")
     t.add_argument("write_db")
-    t.add_argument("--kernel", required=True)
-    t.add_argument("--occurrence", type=int, default=0)
+    t.add_argument("--pick", action="append", required=True, help="LABEL=KERNEL@OCCURRENCE")
     t.add_argument("--copy-kernel", default="copyBuffer")
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--step-end", default="k_materialize")
