@@ -130,6 +130,13 @@ __host__ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t
     return x < tall ? x * per + i : tall * per + (x - tall) * (per - 1) + i;
 }
 
+// Order a wave's LDS writes before its later LDS reads by other lanes of the wave.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T x) {
     const int lane = lane_id();

@@ -141,12 +141,6 @@ __device__ __forceinline__ uint32_t sieve_rows_per_group(uint32_t n) {
     return (per + kProbeTile - 1) / kProbeTile * kProbeTile;
 }
 
-// Order a wave's LDS writes before its later LDS reads by other lanes of the wave.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // The kSieveItems keys of rows row0 .. row0 + 7 of a column (0 past the end).
 __device__ __forceinline__ void load_keys(const int32_t *col, uint32_t row0, uint32_t n, bool full, int32_t *k) {

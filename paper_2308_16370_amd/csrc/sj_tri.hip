@@ -376,30 +376,148 @@ __global__ __launch_bounds__(kScanBlock) void k_k4_rows(K4Args a) {
     }
 }
 
-// Second level: walk group W (1 ad, 3 bd, 4 cd) from entry wb, wn members, each giving
-// d; look (x, d) up in the other two pair hashes.
+// Second level, balanced over the wave. A lane's first-level hit (root entry (a, b) and
+// c) names the smallest of the groups ad(a), bd(b), cd(c) to walk, a job of wn members;
+// on a power-law graph one hub's group can be thousands of members long, and a lane
+// walking it alone holds the other 63 idle. So each first-level round the wave lays its
+// jobs end to end (a prefix sum of their lengths) and lane l takes members l, l + 64, ...
+// of the concatenation: the job holding member t is the first whose inclusive prefix
+// exceeds t (a binary search over the wave's 64 prefixes in LDS). Every member's count
+// and checksum terms are products, so regrouping the sums changes nothing.
+struct K4Job {
+    uint64_t f;                // count: checksum factors of the root row, the walked level-one
+                               // row and the level-one pair's rows; write: the two row ids
+    int32_t av, bv, cv;
+    uint32_t wb, wn;           // the walked group's first entry and member count
+    uint32_t c1;               // rows of the level-one pair
+    uint32_t l1_pos;           // write: first of those rows in their group (pair-hash order)
+    uint8_t W;                 // walked group: 1 (ad), 3 (bd) or 4 (cd)
+    uint8_t walk_bc;           // the walked level-one row is bc's (else ac's)
+};
+
+// Member e of job jb, whose walked group is W: its d is looked up with (x1, d) in pair
+// hash H1 and (x2, d) in H2 (ad walked: bd, cd; bd walked: ad, cd; cd walked: ad, bd).
 template <int W>
-__device__ __forceinline__ void k4_second(const K4Args &a, const uint32_t *hm, uint32_t wb, uint32_t wn,
-                                          int32_t av, int32_t bv, int32_t cv, uint64_t &cnt, uint64_t &chk) {
-    constexpr int H1 = W == 1 ? 3 : 1;         // ad walked: bd, cd; bd walked: ad, cd; cd walked: ad, bd
-    constexpr int H2 = W == 4 ? 3 : 4;
-    const int32_t x1 = H1 == 3 ? bv : av;
-    const int32_t x2 = H2 == 3 ? bv : cv;
+__device__ __forceinline__ void k4_member_count(const K4Args &a, const K4Job &jb, uint32_t e, uint64_t &cnt,
+                                                uint64_t &chk) {
+    constexpr int H1 = W == 1 ? 3 : 1, H2 = W == 4 ? 3 : 4;
+    const int32_t x1 = H1 == 3 ? jb.bv : jb.av, x2 = H2 == 3 ? jb.bv : jb.cv;
     const K4Group &g = a.g[W];
-    for (uint32_t j = 0; j < wn; ++j) {
-        const uint32_t e = wb + j;
-        const int32_t d = g.other[e];
-        uint32_t c1, c2;
-        uint64_t s1, s2;
-        if (!pair_find(a.h[H1], hm[H1], pair_key(x1, d), c1, s1)) continue;
-        if (!pair_find(a.h[H2], hm[H2], pair_key(x2, d), c2, s2)) continue;
-        cnt += static_cast<uint64_t>(c1) * c2;
-        chk += chk_factor(g.rel, g.rid[e]) * s1 * s2;
-    }
+    const int32_t d = g.other[e];
+    uint32_t cA, cB;
+    uint64_t sA, sB;
+    if (!pair_find(a.h[H1], *a.h[H1].mask, pair_key(x1, d), cA, sA)) return;
+    if (!pair_find(a.h[H2], *a.h[H2].mask, pair_key(x2, d), cB, sB)) return;
+    cnt += static_cast<uint64_t>(jb.c1) * cA * cB;
+    chk += jb.f * chk_factor(g.rel, g.rid[e]) * sA * sB;
 }
+
+// The wave's jobs: the job holding member t and t's index in it.
+__device__ __forceinline__ uint32_t k4_job_of(const uint64_t *incl, uint64_t t) {
+    uint32_t lo = 0, hi = 64;   // first i with incl[i] > t
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (incl[mid] > t)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// The first level of step w (root entry r, member w - r_lo of its walked level-one
+// group): whether (a, b, c) closes, and the second-level job if it does. The root
+// entry's values and its ad, bd ranges are cached across the lane's steps.
+struct K4Cursor {
+    uint32_t r;
+    uint64_t r_lo, r_hi;
+    bool loaded, walk_bc;
+    uint32_t beg, ad_b, ad_n, bd_b, bd_n, root_rid;
+    int32_t av, bv;
+    uint64_t m0;
+};
+
+template <bool WRITE_IDS>
+__device__ __forceinline__ bool k4_first(const K4Args &a, const uint32_t *gm, const uint32_t *hm, uint32_t n,
+                                         uint64_t w, K4Cursor &q, K4Job &jb) {
+    if (w >= q.r_hi) {
+        uint32_t lo = q.r + 1, step = 1, hi = lo;
+        while (hi < n && a.off[hi + 1] <= w) {
+            lo = hi + 1;
+            hi = min(n - 1, hi + step);
+            step <<= 1;
+        }
+        q.r = upper_bound_u64(a.off, lo, hi + 1, w) - 1;
+        q.r_lo = a.off[q.r];
+        q.r_hi = a.off[q.r + 1];
+        q.loaded = false;
+    }
+    if (!q.loaded) {
+        q.walk_bc = (a.w[q.r] >> 31) != 0;
+        q.beg = a.beg[q.r];
+        q.av = a.root_a[q.r];
+        q.bv = a.root_b[q.r];
+        q.root_rid = a.root_rid[q.r];
+        q.m0 = WRITE_IDS ? 0 : chk_factor(a.rel_root, q.root_rid);
+        k4_range(a.g[1], gm[1], q.av, q.ad_b, q.ad_n);
+        k4_range(a.g[3], gm[3], q.bv, q.bd_b, q.bd_n);
+        q.loaded = true;
+    }
+    if (q.ad_n == 0 || q.bd_n == 0) return false;
+    const uint32_t e = q.beg + static_cast<uint32_t>(w - q.r_lo);
+    // the walked level-one row is ac's (walk over ac(a)) or bc's; the other side's rows
+    // come from the pair hash
+    const K4Group &g1 = a.g[q.walk_bc ? 2 : 0];
+    const int32_t cv = g1.other[e];
+    uint32_t c1 = 0;
+    int64_t s1;
+    uint64_t ms = 0;
+    if (WRITE_IDS) {
+        s1 = q.walk_bc ? pair_slot_of(a.h[0], hm[0], pair_key(q.av, cv), c1)
+                       : pair_slot_of(a.h[2], hm[2], pair_key(q.bv, cv), c1);
+    } else {
+        const bool hit = q.walk_bc ? pair_find(a.h[0], hm[0], pair_key(q.av, cv), c1, ms)
+                                   : pair_find(a.h[2], hm[2], pair_key(q.bv, cv), c1, ms);
+        s1 = hit ? 0 : -1;
+    }
+    if (s1 < 0) return false;
+    uint32_t cd_b, cd_n;
+    k4_range(a.g[4], gm[4], cv, cd_b, cd_n);
+    if (cd_n == 0) return false;
+    jb.av = q.av;
+    jb.bv = q.bv;
+    jb.cv = cv;
+    jb.c1 = c1;
+    jb.walk_bc = q.walk_bc ? 1 : 0;
+    if (q.ad_n <= q.bd_n && q.ad_n <= cd_n) {
+        jb.W = 1; jb.wb = q.ad_b; jb.wn = q.ad_n;
+    } else if (q.bd_n <= cd_n) {
+        jb.W = 3; jb.wb = q.bd_b; jb.wn = q.bd_n;
+    } else {
+        jb.W = 4; jb.wb = cd_b; jb.wn = cd_n;
+    }
+    if (WRITE_IDS) {
+        jb.f = static_cast<uint64_t>(q.root_rid) | (static_cast<uint64_t>(g1.rid[e]) << 32);
+        jb.l1_pos = q.walk_bc ? a.h[0].pos[s1] : a.h[2].pos[s1];
+    } else {
+        jb.f = q.m0 * chk_factor(g1.rel, g1.rid[e]) * ms;
+        jb.l1_pos = 0;
+    }
+    return true;
+}
+
+// One wave's chunk of first-level steps, kTriIters rounds of 64, each round's jobs walked
+// by the whole wave. MODE 0: count and checksum (acc0, acc1); 1: tuples per lane (acc0);
+// 2: the tuples written from acc1.
+template <int MODE>
+__device__ __forceinline__ void k4_chunk(const K4Args &a, const CliqueOut *o, const uint32_t *gm, const uint32_t *hm,
+                                         uint32_t n, uint64_t total, uint64_t c, K4Job *jobs, uint64_t *incl_s,
+                                         uint64_t &acc0, uint64_t &acc1);
 
 __global__ __launch_bounds__(kTriThreads) void k_k4_count(K4Args a) {
     __shared__ uint64_t s_c[kTriThreads / 64], s_k[kTriThreads / 64];
+    __shared__ K4Job s_job[kTriThreads / 64][64];
+    __shared__ uint64_t s_incl[kTriThreads / 64][64];
     const uint32_t n = *a.n_root;
     const uint64_t total = a.off[n];
     constexpr uint64_t kWaveSteps = 64ull * kTriIters;
@@ -410,71 +528,11 @@ __global__ __launch_bounds__(kTriThreads) void k_k4_count(K4Args a) {
         gm[i] = *a.g[i].mask;
         hm[i] = *a.h[i].mask;
     }
-    const uint32_t lane = static_cast<uint32_t>(lane_id());
+    const uint32_t wid = threadIdx.x >> 6;
     uint64_t cnt = 0, chk = 0;
     const uint64_t nwaves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
-    for (uint64_t c = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; c < nchunks; c += nwaves) {
-        uint64_t w = c * kWaveSteps + lane;
-        if (w >= total) continue;
-        uint32_t r = upper_bound_u64(a.off, 0, n, w) - 1;
-        uint64_t r_lo = a.off[r], r_hi = a.off[r + 1];
-        bool loaded = false, walk_bc = false;
-        uint32_t beg = 0, ad_b = 0, ad_n = 0, bd_b = 0, bd_n = 0;
-        int32_t av = 0, bv = 0;
-        uint64_t m0 = 0;
-        for (int it = 0; it < kTriIters && w < total; ++it, w += 64) {
-            if (w >= r_hi) {
-                uint32_t lo = r + 1, step = 1, hi = lo;
-                while (hi < n && a.off[hi + 1] <= w) {
-                    lo = hi + 1;
-                    hi = min(n - 1, hi + step);
-                    step <<= 1;
-                }
-                r = upper_bound_u64(a.off, lo, hi + 1, w) - 1;
-                r_lo = a.off[r];
-                r_hi = a.off[r + 1];
-                loaded = false;
-            }
-            if (!loaded) {
-                walk_bc = (a.w[r] >> 31) != 0;
-                beg = a.beg[r];
-                av = a.root_a[r];
-                bv = a.root_b[r];
-                m0 = chk_factor(a.rel_root, a.root_rid[r]);
-                k4_range(a.g[1], gm[1], av, ad_b, ad_n);
-                k4_range(a.g[3], gm[3], bv, bd_b, bd_n);
-                loaded = true;
-            }
-            if (ad_n == 0 || bd_n == 0) continue;
-            const uint32_t e = beg + static_cast<uint32_t>(w - r_lo);
-            int32_t cv;
-            uint64_t m1, s1;
-            uint32_t c1;
-            bool hit;
-            if (!walk_bc) {
-                cv = a.g[0].other[e];
-                m1 = chk_factor(a.g[0].rel, a.g[0].rid[e]);
-                hit = pair_find(a.h[2], hm[2], pair_key(bv, cv), c1, s1);
-            } else {
-                cv = a.g[2].other[e];
-                m1 = chk_factor(a.g[2].rel, a.g[2].rid[e]);
-                hit = pair_find(a.h[0], hm[0], pair_key(av, cv), c1, s1);
-            }
-            if (!hit) continue;
-            uint32_t cd_b, cd_n;
-            k4_range(a.g[4], gm[4], cv, cd_b, cd_n);
-            if (cd_n == 0) continue;
-            uint64_t c2 = 0, k2 = 0;
-            if (ad_n <= bd_n && ad_n <= cd_n)
-                k4_second<1>(a, hm, ad_b, ad_n, av, bv, cv, c2, k2);
-            else if (bd_n <= cd_n)
-                k4_second<3>(a, hm, bd_b, bd_n, av, bv, cv, c2, k2);
-            else
-                k4_second<4>(a, hm, cd_b, cd_n, av, bv, cv, c2, k2);
-            cnt += static_cast<uint64_t>(c1) * c2;
-            chk += m0 * m1 * s1 * k2;
-        }
-    }
+    for (uint64_t c = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; c < nchunks; c += nwaves)
+        k4_chunk<0>(a, nullptr, gm, hm, n, total, c, s_job[wid], s_incl[wid], cnt, chk);
     uint64_t tc, tk;
     block_excl_scan<kTriThreads>(cnt, s_c, tc);
     block_excl_scan<kTriThreads>(chk, s_k, tk);
@@ -587,54 +645,101 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_emit(TriArgs a, CliqueOut o
     if (!WRITE) emit_count_out(o, cnt, s_tmp);
 }
 
-// Second level of a 4-clique for the write pass: as k4_second, counting or writing every
-// row combination (the level-one rows come in as l1 rows at l1_pos in bucket l1_rid,
-// with the walked level-one row fixed).
+// The same member in the write pass: its tuple count (pass 0), or every row combination
+// written from `cur` (pass 1).
 template <int W, bool WRITE>
-__device__ __forceinline__ void k4_second_emit(const K4Args &a, const CliqueOut &o, const uint32_t *hm, uint32_t wb,
-                                               uint32_t wn, int32_t av, int32_t bv, int32_t cv, uint64_t c1,
-                                               uint32_t (&rr)[6], bool l1_ac, const uint32_t *l1_rid,
-                                               uint32_t l1_pos, uint64_t &cnt, uint64_t &cur) {
-    constexpr int H1 = W == 1 ? 3 : 1;
-    constexpr int H2 = W == 4 ? 3 : 4;
-    const int32_t x1 = H1 == 3 ? bv : av;
-    const int32_t x2 = H2 == 3 ? bv : cv;
+__device__ __forceinline__ void k4_member_emit(const K4Args &a, const CliqueOut &o, const K4Job &jb, uint32_t e,
+                                               uint64_t &cnt, uint64_t &cur) {
+    constexpr int H1 = W == 1 ? 3 : 1, H2 = W == 4 ? 3 : 4;
+    const int32_t x1 = H1 == 3 ? jb.bv : jb.av, x2 = H2 == 3 ? jb.bv : jb.cv;
     const K4Group &g = a.g[W];
-    for (uint32_t j = 0; j < wn; ++j) {
-        const uint32_t e = wb + j;
-        const int32_t d = g.other[e];
-        uint32_t cA = 0, cB = 0;
-        const int64_t sA = pair_slot_of(a.h[H1], hm[H1], pair_key(x1, d), cA);
-        if (sA < 0) continue;
-        const int64_t sB = pair_slot_of(a.h[H2], hm[H2], pair_key(x2, d), cB);
-        if (sB < 0) continue;
-        if (!WRITE) {
-            cnt += c1 * cA * cB;
-            continue;
-        }
-        // roles: 0 root, 1 ac, 2 ad, 3 bc, 4 bd, 5 cd; group / hash index h is role h + 1
-        rr[W + 1] = g.rid[e];
-        const uint32_t pA = a.h[H1].pos[sA], pB = a.h[H2].pos[sB];
-        for (uint64_t i1 = 0; i1 < c1; ++i1) {
-            const uint32_t r1 = l1_rid[l1_pos + i1];
-            if (l1_ac)
-                rr[1] = r1;
-            else
-                rr[3] = r1;
-            for (uint32_t iA = 0; iA < cA; ++iA) {
-                rr[H1 + 1] = a.g[H1].rid[pA + iA];
-                for (uint32_t iB = 0; iB < cB; ++iB) {
-                    rr[H2 + 1] = a.g[H2].rid[pB + iB];
-                    emit_tuple<6>(o, cur++, rr);
-                }
+    const int32_t d = g.other[e];
+    uint32_t cA = 0, cB = 0;
+    const int64_t sA = pair_slot_of(a.h[H1], *a.h[H1].mask, pair_key(x1, d), cA);
+    if (sA < 0) return;
+    const int64_t sB = pair_slot_of(a.h[H2], *a.h[H2].mask, pair_key(x2, d), cB);
+    if (sB < 0) return;
+    if (!WRITE) {
+        cnt += static_cast<uint64_t>(jb.c1) * cA * cB;
+        return;
+    }
+    // roles: 0 root, 1 ac, 2 ad, 3 bc, 4 bd, 5 cd; group / hash index h is role h + 1
+    uint32_t rr[6] = {static_cast<uint32_t>(jb.f), 0, 0, 0, 0, 0};
+    const uint32_t walked = static_cast<uint32_t>(jb.f >> 32);
+    rr[W + 1] = g.rid[e];
+    const uint32_t *l1_rid = jb.walk_bc ? a.g[0].rid : a.g[2].rid;
+    const uint32_t pA = a.h[H1].pos[sA], pB = a.h[H2].pos[sB];
+    for (uint32_t i1 = 0; i1 < jb.c1; ++i1) {
+        const uint32_t r1 = l1_rid[jb.l1_pos + i1];
+        rr[1] = jb.walk_bc ? r1 : walked;
+        rr[3] = jb.walk_bc ? walked : r1;
+        for (uint32_t iA = 0; iA < cA; ++iA) {
+            rr[H1 + 1] = a.g[H1].rid[pA + iA];
+            for (uint32_t iB = 0; iB < cB; ++iB) {
+                rr[H2 + 1] = a.g[H2].rid[pB + iB];
+                emit_tuple<6>(o, cur++, rr);
             }
         }
     }
 }
 
+template <int MODE>
+__device__ __forceinline__ void k4_chunk(const K4Args &a, const CliqueOut *o, const uint32_t *gm, const uint32_t *hm,
+                                         uint32_t n, uint64_t total, uint64_t c, K4Job *jobs, uint64_t *incl_s,
+                                         uint64_t &acc0, uint64_t &acc1) {
+    constexpr uint64_t kWaveSteps = 64ull * kTriIters;
+    const uint32_t lane = static_cast<uint32_t>(lane_id());
+    uint64_t w = c * kWaveSteps + lane;
+    K4Cursor q{};
+    if (w < total) {
+        q.r = upper_bound_u64(a.off, 0, n, w) - 1;
+        q.r_lo = a.off[q.r];
+        q.r_hi = a.off[q.r + 1];
+    }
+    for (int it = 0; it < kTriIters; ++it, w += 64) {
+        K4Job jb{};
+        const bool hit = w < total && k4_first<MODE != 0>(a, gm, hm, n, w, q, jb);
+        const uint64_t len = hit ? jb.wn : 0;
+        const uint64_t incl = wave_incl_scan(len);
+        const uint64_t T = __shfl(incl, 63, 64);
+        if (T == 0) continue;   // the same for every lane of the wave
+        jobs[lane] = jb;
+        incl_s[lane] = incl;
+        wave_lds_sync();
+        for (uint64_t t = lane; t < T; t += 64) {
+            const uint32_t i = k4_job_of(incl_s, t);
+            const K4Job &j = jobs[i];
+            const uint32_t e = j.wb + static_cast<uint32_t>(t - (incl_s[i] - j.wn));
+            if (MODE == 0) {
+                if (j.W == 1)
+                    k4_member_count<1>(a, j, e, acc0, acc1);
+                else if (j.W == 3)
+                    k4_member_count<3>(a, j, e, acc0, acc1);
+                else
+                    k4_member_count<4>(a, j, e, acc0, acc1);
+            } else {
+                if (j.W == 1)
+                    k4_member_emit<1, MODE == 2>(a, *o, j, e, acc0, acc1);
+                else if (j.W == 3)
+                    k4_member_emit<3, MODE == 2>(a, *o, j, e, acc0, acc1);
+                else
+                    k4_member_emit<4, MODE == 2>(a, *o, j, e, acc0, acc1);
+            }
+        }
+        wave_lds_sync();   // every lane is done with this round's jobs before they are replaced
+    }
+}
+
+// The 4-clique write pass: the count pass's walk, balanced the same way (so both of its
+// passes give each lane the same members); pass 0 counts each lane's tuples, pass 1
+// writes every row combination of each member from the lane's offset. A member's rows:
+// the root row, the walked level-one row, the level-one pair's c1 rows, the walked
+// group's row and the two looked-up pairs' rows.
 template <bool WRITE>
 __global__ __launch_bounds__(kTriThreads) void k_k4_emit(K4Args a, CliqueOut o) {
     __shared__ uint64_t s_tmp[kTriThreads / 64];
+    __shared__ K4Job s_job[kTriThreads / 64][64];
+    __shared__ uint64_t s_incl[kTriThreads / 64][64];
     const uint32_t n = *a.n_root;
     const uint64_t total = a.off[n];
     constexpr uint64_t kWaveSteps = 64ull * kTriIters;
@@ -645,67 +750,11 @@ __global__ __launch_bounds__(kTriThreads) void k_k4_emit(K4Args a, CliqueOut o) 
         gm[i] = *a.g[i].mask;
         hm[i] = *a.h[i].mask;
     }
-    const uint32_t lane = static_cast<uint32_t>(lane_id());
+    const uint32_t wid = threadIdx.x >> 6;
     uint64_t cnt = 0, cur = WRITE ? emit_base(o, s_tmp) : 0;
     const uint64_t nwaves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
-    for (uint64_t c = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; c < nchunks; c += nwaves) {
-        uint64_t w = c * kWaveSteps + lane;
-        if (w >= total) continue;
-        uint32_t r = upper_bound_u64(a.off, 0, n, w) - 1;
-        uint64_t r_lo = a.off[r], r_hi = a.off[r + 1];
-        bool loaded = false, walk_bc = false;
-        uint32_t beg = 0, ad_b = 0, ad_n = 0, bd_b = 0, bd_n = 0;
-        int32_t av = 0, bv = 0;
-        uint32_t rr[6] = {0, 0, 0, 0, 0, 0};
-        for (int it = 0; it < kTriIters && w < total; ++it, w += 64) {
-            if (w >= r_hi) {
-                uint32_t lo = r + 1, step = 1, hi = lo;
-                while (hi < n && a.off[hi + 1] <= w) {
-                    lo = hi + 1;
-                    hi = min(n - 1, hi + step);
-                    step <<= 1;
-                }
-                r = upper_bound_u64(a.off, lo, hi + 1, w) - 1;
-                r_lo = a.off[r];
-                r_hi = a.off[r + 1];
-                loaded = false;
-            }
-            if (!loaded) {
-                walk_bc = (a.w[r] >> 31) != 0;
-                beg = a.beg[r];
-                av = a.root_a[r];
-                bv = a.root_b[r];
-                rr[0] = a.root_rid[r];
-                k4_range(a.g[1], gm[1], av, ad_b, ad_n);
-                k4_range(a.g[3], gm[3], bv, bd_b, bd_n);
-                loaded = true;
-            }
-            if (ad_n == 0 || bd_n == 0) continue;
-            const uint32_t e = beg + static_cast<uint32_t>(w - r_lo);
-            // the walked level-one row is ac (walk over ac(a)) or bc; the other side's rows
-            // come from the pair hash
-            const int32_t cv = walk_bc ? a.g[2].other[e] : a.g[0].other[e];
-            uint32_t c1 = 0;
-            const int64_t s1 = walk_bc ? pair_slot_of(a.h[0], hm[0], pair_key(av, cv), c1)
-                                       : pair_slot_of(a.h[2], hm[2], pair_key(bv, cv), c1);
-            if (s1 < 0) continue;
-            uint32_t cd_b, cd_n;
-            k4_range(a.g[4], gm[4], cv, cd_b, cd_n);
-            if (cd_n == 0) continue;
-            if (walk_bc)
-                rr[3] = a.g[2].rid[e];
-            else
-                rr[1] = a.g[0].rid[e];
-            const uint32_t *l1_rid = walk_bc ? a.g[0].rid : a.g[2].rid;
-            const uint32_t l1_pos = walk_bc ? a.h[0].pos[s1] : a.h[2].pos[s1];
-            if (ad_n <= bd_n && ad_n <= cd_n)
-                k4_second_emit<1, WRITE>(a, o, hm, ad_b, ad_n, av, bv, cv, c1, rr, walk_bc, l1_rid, l1_pos, cnt, cur);
-            else if (bd_n <= cd_n)
-                k4_second_emit<3, WRITE>(a, o, hm, bd_b, bd_n, av, bv, cv, c1, rr, walk_bc, l1_rid, l1_pos, cnt, cur);
-            else
-                k4_second_emit<4, WRITE>(a, o, hm, cd_b, cd_n, av, bv, cv, c1, rr, walk_bc, l1_rid, l1_pos, cnt, cur);
-        }
-    }
+    for (uint64_t c = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; c < nchunks; c += nwaves)
+        k4_chunk<WRITE ? 2 : 1>(a, &o, gm, hm, n, total, c, s_job[wid], s_incl[wid], cnt, cur);
     if (!WRITE) emit_count_out(o, cnt, s_tmp);
 }
 
