@@ -413,6 +413,10 @@ struct TriArgs {
     uint64_t *tile_sums;       // [tiles(root_cap)]
     uint64_t *part;            // [2 * kTriBlocks] per-block count and checksum
     uint64_t *totals;          // [2] count, checksum
+    // the write pass's offsets: the count pass writes each lane's and each workgroup's
+    // tuple count (the write pass gives every lane the same walk steps)
+    uint64_t *lane_cnt;        // [kTriBlocks * 256]
+    uint64_t *block_cnt;       // [kTriBlocks]
 };
 hipError_t launch_tri_count(const TriArgs &a, hipStream_t s);
 
@@ -439,6 +443,8 @@ struct K4Args {
     uint64_t *tile_sums;       // [tiles(root_cap)]
     uint64_t *part;            // [2 * kTriBlocks]
     uint64_t *totals;          // [2] count, checksum
+    uint64_t *lane_cnt;        // [kTriBlocks * 256] tuples of each lane (written by the count pass)
+    uint64_t *block_cnt;       // [kTriBlocks] tuples of each workgroup
 };
 hipError_t launch_k4_count(const K4Args &a, hipStream_t s);
 

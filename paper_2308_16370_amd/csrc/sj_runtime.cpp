@@ -1637,6 +1637,8 @@ static TriArgs tri_args(sj_plan_t *p, Buckets bk[2], int key_col[2], int z_col[2
     a.rel_L = static_cast<uint32_t>(L);
     a.HP = pair_hash_of(p, 0);
     a.HL = pair_hash_of(p, 1);
+    a.lane_cnt = at<uint64_t>(p, p->off_emit_lane);
+    a.block_cnt = at<uint64_t>(p, p->off_emit_block);
     a.w = at<uint32_t>(p, p->off_tri_w);
     a.beg = at<uint32_t>(p, p->off_tri_beg);
     a.off = at<uint64_t>(p, p->off_tri_off);
@@ -1682,6 +1684,8 @@ static sj_status enqueue_tri(sj_plan_t *p) {
 // earlier variable and sorted by their (earlier, later) pairs; bk receives their buckets.
 static K4Args k4_args(sj_plan_t *p, Buckets bk[5]) {
     K4Args a{};
+    a.lane_cnt = at<uint64_t>(p, p->off_emit_lane);
+    a.block_cnt = at<uint64_t>(p, p->off_emit_block);
     const int r = p->root;
     const int fl = p->final_list[r];
     a.n_root = at<uint32_t>(p, p->steps[p->final_step[r]].off_count);
@@ -1742,8 +1746,8 @@ static sj_status enqueue_k4(sj_plan_t *p) {
     return SJ_OK;
 }
 
-// Write pass of a 3-cycle or 4-clique counted by intersection (the count pass's walk
-// and buckets are still in the workspace).
+// Write pass of a 3-cycle or 4-clique counted by intersection (the count pass's walk,
+// buckets and per-lane tuple counts are still in the workspace).
 static sj_status clique_write(sj_plan_t *p, int32_t *out, uint64_t capacity, const Projection &pr) {
     CliqueOut o{};
     o.out = out;

@@ -306,9 +306,11 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_count(TriArgs a) {
     uint64_t tc, tk;
     block_excl_scan<kTriThreads>(cnt, s_c, tc);
     block_excl_scan<kTriThreads>(chk, s_k, tk);
+    a.lane_cnt[blockIdx.x * blockDim.x + threadIdx.x] = cnt;   // the lane's tuples (hc per match)
     if (threadIdx.x == 0) {
         a.part[2 * blockIdx.x] = tc;
         a.part[2 * blockIdx.x + 1] = tk;
+        a.block_cnt[blockIdx.x] = tc;
     }
 }
 
@@ -507,8 +509,8 @@ __device__ __forceinline__ bool k4_first(const K4Args &a, const uint32_t *gm, co
 }
 
 // One wave's chunk of first-level steps, kTriIters rounds of 64, each round's jobs walked
-// by the whole wave. MODE 0: count and checksum (acc0, acc1); 1: tuples per lane (acc0);
-// 2: the tuples written from acc1.
+// by the whole wave. MODE 0: count and checksum (acc0, acc1); MODE 1: the tuples written
+// from acc1 (acc0 unused).
 template <int MODE>
 __device__ __forceinline__ void k4_chunk(const K4Args &a, const CliqueOut *o, const uint32_t *gm, const uint32_t *hm,
                                          uint32_t n, uint64_t total, uint64_t c, K4Job *jobs, uint64_t *incl_s,
@@ -536,16 +538,19 @@ __global__ __launch_bounds__(kTriThreads) void k_k4_count(K4Args a) {
     uint64_t tc, tk;
     block_excl_scan<kTriThreads>(cnt, s_c, tc);
     block_excl_scan<kTriThreads>(chk, s_k, tk);
+    a.lane_cnt[blockIdx.x * blockDim.x + threadIdx.x] = cnt;   // the lane's tuples (c1 cA cB per match)
     if (threadIdx.x == 0) {
         a.part[2 * blockIdx.x] = tc;
         a.part[2 * blockIdx.x + 1] = tk;
+        a.block_cnt[blockIdx.x] = tc;
     }
 }
 
 // ---- write pass (3-cycles and 4-cliques) ------------------------------------------------
-// Pass 0 counts each lane's tuples (and each workgroup's); pass 1 walks again and writes
-// a lane's tuples from its offset: the workgroups before it, then the lanes before it.
-// Both passes use the count pass's walk lengths and prefixes (still in the workspace).
+// The count pass gives every lane the same walk steps as the write pass and records each
+// lane's and each workgroup's tuple count; the write pass walks again and writes a lane's
+// tuples from its offset: the workgroups before it, then the lanes before it. It uses the
+// count pass's walk lengths, prefixes and tuple counts (still in the workspace).
 
 template <int NR>
 __device__ __forceinline__ void emit_tuple(const CliqueOut &o, uint64_t at, const uint32_t (&rr)[NR]) {
@@ -576,14 +581,6 @@ __device__ __forceinline__ uint64_t emit_base(const CliqueOut &o, uint64_t *s_tm
     return blocks_before + lanes_before;
 }
 
-__device__ __forceinline__ void emit_count_out(const CliqueOut &o, uint64_t cnt, uint64_t *s_tmp) {
-    o.lane_cnt[blockIdx.x * blockDim.x + threadIdx.x] = cnt;
-    uint64_t tot;
-    block_excl_scan<kTriThreads>(cnt, s_tmp, tot);
-    if (threadIdx.x == 0) o.block_cnt[blockIdx.x] = tot;
-}
-
-template <bool WRITE>
 __global__ __launch_bounds__(kTriThreads) void k_tri_emit(TriArgs a, CliqueOut o) {
     __shared__ uint64_t s_tmp[kTriThreads / 64];
     const uint32_t n = *a.n_root;
@@ -592,7 +589,7 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_emit(TriArgs a, CliqueOut o
     const uint64_t nchunks = (total + kWaveSteps - 1) / kWaveSteps;
     const uint32_t pm = *a.HP.mask, lm = *a.HL.mask;
     const uint32_t lane = static_cast<uint32_t>(lane_id());
-    uint64_t cnt = 0, cur = WRITE ? emit_base(o, s_tmp) : 0;
+    uint64_t cur = emit_base(o, s_tmp);
     const uint64_t nwaves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
     for (uint64_t c = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; c < nchunks; c += nwaves) {
         uint64_t w = c * kWaveSteps + lane;
@@ -628,10 +625,6 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_emit(TriArgs a, CliqueOut o
             const int64_t sl = walk_l ? pair_slot_of(a.HP, pm, pair_key(x, a.L_z[e]), hc)
                                       : pair_slot_of(a.HL, lm, pair_key(y, a.P_z[e]), hc);
             if (sl < 0) continue;
-            if (!WRITE) {
-                cnt += hc;
-                continue;
-            }
             const uint32_t mine = walk_l ? a.L_rid[e] : a.P_rid[e];
             const uint32_t p0 = walk_l ? a.HP.pos[sl] : a.HL.pos[sl];
             const uint32_t *orid = walk_l ? a.P_rid : a.L_rid;
@@ -642,14 +635,12 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_emit(TriArgs a, CliqueOut o
             }
         }
     }
-    if (!WRITE) emit_count_out(o, cnt, s_tmp);
 }
 
-// The same member in the write pass: its tuple count (pass 0), or every row combination
-// written from `cur` (pass 1).
-template <int W, bool WRITE>
+// The same member in the write pass: every row combination written from `cur`.
+template <int W>
 __device__ __forceinline__ void k4_member_emit(const K4Args &a, const CliqueOut &o, const K4Job &jb, uint32_t e,
-                                               uint64_t &cnt, uint64_t &cur) {
+                                               uint64_t &cur) {
     constexpr int H1 = W == 1 ? 3 : 1, H2 = W == 4 ? 3 : 4;
     const int32_t x1 = H1 == 3 ? jb.bv : jb.av, x2 = H2 == 3 ? jb.bv : jb.cv;
     const K4Group &g = a.g[W];
@@ -659,10 +650,6 @@ __device__ __forceinline__ void k4_member_emit(const K4Args &a, const CliqueOut 
     if (sA < 0) return;
     const int64_t sB = pair_slot_of(a.h[H2], *a.h[H2].mask, pair_key(x2, d), cB);
     if (sB < 0) return;
-    if (!WRITE) {
-        cnt += static_cast<uint64_t>(jb.c1) * cA * cB;
-        return;
-    }
     // roles: 0 root, 1 ac, 2 ad, 3 bc, 4 bd, 5 cd; group / hash index h is role h + 1
     uint32_t rr[6] = {static_cast<uint32_t>(jb.f), 0, 0, 0, 0, 0};
     const uint32_t walked = static_cast<uint32_t>(jb.f >> 32);
@@ -719,23 +706,22 @@ __device__ __forceinline__ void k4_chunk(const K4Args &a, const CliqueOut *o, co
                     k4_member_count<4>(a, j, e, acc0, acc1);
             } else {
                 if (j.W == 1)
-                    k4_member_emit<1, MODE == 2>(a, *o, j, e, acc0, acc1);
+                    k4_member_emit<1>(a, *o, j, e, acc1);
                 else if (j.W == 3)
-                    k4_member_emit<3, MODE == 2>(a, *o, j, e, acc0, acc1);
+                    k4_member_emit<3>(a, *o, j, e, acc1);
                 else
-                    k4_member_emit<4, MODE == 2>(a, *o, j, e, acc0, acc1);
+                    k4_member_emit<4>(a, *o, j, e, acc1);
             }
         }
         wave_lds_sync();   // every lane is done with this round's jobs before they are replaced
     }
 }
 
-// The 4-clique write pass: the count pass's walk, balanced the same way (so both of its
-// passes give each lane the same members); pass 0 counts each lane's tuples, pass 1
-// writes every row combination of each member from the lane's offset. A member's rows:
+// The 4-clique write pass: the count pass's walk, balanced the same way (so each lane
+// gets the members whose tuples the count pass counted for it), writing every row
+// combination of each member from the lane's offset. A member's rows:
 // the root row, the walked level-one row, the level-one pair's c1 rows, the walked
 // group's row and the two looked-up pairs' rows.
-template <bool WRITE>
 __global__ __launch_bounds__(kTriThreads) void k_k4_emit(K4Args a, CliqueOut o) {
     __shared__ uint64_t s_tmp[kTriThreads / 64];
     __shared__ K4Job s_job[kTriThreads / 64][64];
@@ -751,11 +737,10 @@ __global__ __launch_bounds__(kTriThreads) void k_k4_emit(K4Args a, CliqueOut o) 
         hm[i] = *a.h[i].mask;
     }
     const uint32_t wid = threadIdx.x >> 6;
-    uint64_t cnt = 0, cur = WRITE ? emit_base(o, s_tmp) : 0;
+    uint64_t unused = 0, cur = emit_base(o, s_tmp);
     const uint64_t nwaves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) >> 6;
     for (uint64_t c = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6; c < nchunks; c += nwaves)
-        k4_chunk<WRITE ? 2 : 1>(a, &o, gm, hm, n, total, c, s_job[wid], s_incl[wid], cnt, cur);
-    if (!WRITE) emit_count_out(o, cnt, s_tmp);
+        k4_chunk<1>(a, &o, gm, hm, n, total, c, s_job[wid], s_incl[wid], unused, cur);
 }
 
 uint32_t blocks_for(uint64_t items, uint32_t per_block, uint32_t cap) {
@@ -805,14 +790,12 @@ hipError_t launch_k4_count(const K4Args &a, hipStream_t s) {
 }
 
 hipError_t launch_tri_emit(const TriArgs &a, const CliqueOut &o, hipStream_t s) {
-    hipLaunchKernelGGL(k_tri_emit<false>, dim3(kTriBlocks), dim3(kTriThreads), 0, s, a, o);
-    hipLaunchKernelGGL(k_tri_emit<true>, dim3(kTriBlocks), dim3(kTriThreads), 0, s, a, o);
+    hipLaunchKernelGGL(k_tri_emit, dim3(kTriBlocks), dim3(kTriThreads), 0, s, a, o);
     return hipGetLastError();
 }
 
 hipError_t launch_k4_emit(const K4Args &a, const CliqueOut &o, hipStream_t s) {
-    hipLaunchKernelGGL(k_k4_emit<false>, dim3(kTriBlocks), dim3(kTriThreads), 0, s, a, o);
-    hipLaunchKernelGGL(k_k4_emit<true>, dim3(kTriBlocks), dim3(kTriThreads), 0, s, a, o);
+    hipLaunchKernelGGL(k_k4_emit, dim3(kTriBlocks), dim3(kTriThreads), 0, s, a, o);
     return hipGetLastError();
 }
 
