@@ -2,12 +2,12 @@
 
 Independent sieve steps of one dependency level run on branch streams with a scratch
 set each; a step alone in its level builds its filters on separate branches; every
-non-root relation is bucketed and weighed on a branch of its own. There are four
-branches, so wider shapes share them. The cases:
+non-root relation is bucketed on a branch of its own, a leaf's DP following its buckets
+there, and the other DPs run bottom-up on the launch stream once the branches have
+joined. There are four branches, so wider shapes share them. The cases:
 - a star of seven dimensions: seven steps per level, and seven builds in the root step;
-- a bushy tree three levels deep;
-- a twelve-relation chain: eleven relations bucketed on four branches, each DP
-  waiting on its child's.
+- a bushy tree three levels deep (skipped: see its reason);
+- a twelve-relation chain: eleven relations bucketed on four shared branches.
 Each case runs through recorded graphs (three replays), eagerly, and with profiling
 (everything on one stream). Filters, survivors, count, checksum and tuples must equal
 the oracle's every time.
