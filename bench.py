@@ -138,6 +138,8 @@ def main():
     ap.add_argument("--passes", type=int, default=2, help="sieve passes: 1 (the paper's backward pass) or 2")
     ap.add_argument("--probe-grid", type=int, default=0, help="workgroups per sieve probe launch (0: library default)")
     ap.add_argument("--probe-lds", type=int, default=0, help="LDS filter reservation mode of the probes (0, 1, 2)")
+    ap.add_argument("--sieve-two-launches", action="store_true",
+                    help="each sieve step as a probe and a compaction launch (SJ_FLAG_SIEVE_TWO_LAUNCHES)")
     ap.add_argument("--serve-queries", type=int, default=256)
     ap.add_argument("--serve-max-rows", type=int, default=20_000_000)
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -163,7 +165,7 @@ def main():
     dev = torch.device("cuda:0")
     rels = [sj.Rel([torch.from_numpy(c).to(dev) for c in r.cols], r.pred) for r in q.rels]
     opts = dict(bits_per_key=8, k=6, block_bits=512, passes=args.passes, seed=args.seed, probe_grid=args.probe_grid,
-                probe_lds=args.probe_lds)
+                probe_lds=args.probe_lds, flags=sj.SJ_FLAG_SIEVE_TWO_LAUNCHES if args.sieve_two_launches else 0)
     ctx = sj.Context(0)
     plan = sj.Plan(ctx, rels, q.edges, **opts)
 
@@ -372,7 +374,8 @@ def main():
                                "blocked Bloom 8 bits/key k=6 512-bit blocks, %d pass%s, tuples materialised"
                                % (q.rels[0].nrows, q.meta["domain"], args.passes, "" if args.passes == 1 else "es"),
                    "input_tuples": q.input_tuples, "result_tuples": cnt, "seed": args.seed,
-                   "probe_grid": args.probe_grid or 256, "probe_lds": args.probe_lds},
+                   "probe_grid": args.probe_grid or 256, "probe_lds": args.probe_lds,
+                   "sieve_launches_per_step": 2 if args.sieve_two_launches else 1},
         "roofline": roofline,
         "sieve_roofline": sieve_roofline,
         "result_roofline": result_roofline,

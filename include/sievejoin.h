@@ -134,6 +134,11 @@ typedef struct {
 #define SJ_FLAG_FAULT_SIEVE 16u
 #define SJ_FLAG_FAULT_JOIN 32u
 #define SJ_FLAG_FAULT_RESULT 64u
+/* Run each sieve step that writes a survivor list as two launches (probe, then the
+ * list from the probe's per-row bits and per-workgroup counts) instead of one launch
+ * whose workgroups learn their output offsets by a look-back over the workgroups
+ * before them. The survivor lists are the same; for comparisons. */
+#define SJ_FLAG_SIEVE_TWO_LAUNCHES 128u
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
  * (a hipStream_t; NULL = the null stream). The stream stays caller-owned. */

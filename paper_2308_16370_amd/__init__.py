@@ -57,6 +57,7 @@ SJ_FLAG_PROFILE = 1
 SJ_FLAG_EAGER = 2
 SJ_FLAG_BINARY_CYCLES = 4
 SJ_FLAG_FAULT_FILTERS, SJ_FLAG_FAULT_SIEVE, SJ_FLAG_FAULT_JOIN, SJ_FLAG_FAULT_RESULT = 8, 16, 32, 64
+SJ_FLAG_SIEVE_TWO_LAUNCHES = 128
 SJ_RIDS, SJ_VALUES = 0, 1
 SJ_MAX_PROJ = 32
 SJ_STATIC_WORKSPACE_BYTES = 64 << 20

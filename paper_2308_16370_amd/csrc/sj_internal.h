@@ -68,7 +68,8 @@ struct StepArgs {
     int32_t *out_col[kMaxJCols];
     uint32_t *out_count;       // device-side survivor count (written when out_rid != nullptr)
     uint8_t *bits;             // [ceil(rows / 8)] survivor flags of the scan, 8 rows per byte
-    uint32_t *counts;          // [grid] survivors per workgroup
+    uint32_t *counts;          // [grid] survivors per workgroup (two-launch form)
+    Lookback lb;               // one-launch form: [grid] status words and the ticket counter, zeroed before
     uint32_t grid;             // workgroups of the probe and compaction launches
     uint32_t lds_words;        // LDS words set aside for one probed filter (0: none)
     uint32_t seed;
@@ -144,6 +145,8 @@ hipError_t launch_count_pred(const int32_t *col, uint32_t n, int32_t lo, int32_t
 // and, when the step writes a survivor list, the compaction.
 hipError_t launch_sieve_probe(const StepArgs &a, uint32_t max_rows, hipStream_t s);
 hipError_t launch_sieve_compact(const StepArgs &a, uint32_t max_rows, hipStream_t s);
+// probe and survivor list in one launch (a.out_rid and a.lb required)
+hipError_t launch_sieve_fused(const StepArgs &a, uint32_t max_rows, hipStream_t s);
 
 // Partitioned build of one filter from a key column (full column with an optional
 // predicate, or a survivor-list column with a device-side length).

@@ -100,13 +100,14 @@ hipError_t launch_filter_update(const FilterUpdate &u, bool set, hipStream_t s) 
 }
 
 // ---- the sieve step ------------------------------------------------------------------
-// Two passes with no inter-workgroup waiting. Workgroup b of the grid owns the rows
-// [b * R, (b + 1) * R), R a multiple of kProbeTile. (1) k_sieve_step probes every row
-// and records a survivor bit per row and a survivor count per workgroup. (2)
-// k_sieve_compact sums the counts of the workgroups before it and writes its survivors
-// (row id and join columns, ascending row order) from the bits. (A single pass with a
-// dynamic tile counter and look-back would put thousands of same-address atomics, about
-// 11 ns each on MI355X and serialised, on the critical path.)
+// Workgroup b of the grid owns the rows [b * R, (b + 1) * R), R a multiple of
+// kProbeTile. k_sieve_step probes every row and records a survivor bit per row; then it
+// writes its survivors (row id and join columns, ascending row order) after those of
+// workgroups 0 .. b-1, whose count it learns by a decoupled look-back over the grid's
+// workgroups (one ticket and one status word per workgroup, so a few hundred atomics
+// per launch rather than one per tile). Without a survivor list to write (or as two
+// launches, for comparison) it records a survivor count per workgroup and
+// k_sieve_compact writes the survivors in a second launch.
 //
 // A probe touches one filter block: the k words of all items of a batch are loaded
 // before any is tested, so a thread keeps many independent loads in flight.
@@ -211,6 +212,78 @@ __device__ __forceinline__ void probe_global(const StepArgs &a, const uint32_t *
     }
 }
 
+// Survivors of rows [r0, r_end) (a workgroup's share; survivor bits in a.bits), written
+// from output position `base` on in ascending row order.
+template <int NCOL>
+__device__ __forceinline__ void sieve_write_survivors(const StepArgs &a, uint32_t r0, uint32_t r_end, uint32_t n,
+                                                      uint32_t base, uint64_t *s_wave64) {
+    const bool list = a.src_rid != nullptr;
+    const int tid = threadIdx.x;
+    // Four tiles share one block scan: their per-thread survivor counts are packed into
+    // 16-bit fields of one 64-bit value (a tile holds fewer than 2^16 rows), so sparse
+    // survivors cost a quarter of the barriers.
+    constexpr int kGroupTiles = 4;
+    static_assert(kProbeTile < (1 << 16), "a tile's survivor count fits 16 bits");
+    for (uint32_t g0 = r0; g0 < r_end; g0 += kGroupTiles * kProbeTile) {
+        uint32_t fl[kGroupTiles];
+        uint64_t packed = 0;
+#pragma unroll
+        for (int q = 0; q < kGroupTiles; ++q) {
+            const uint32_t r = g0 + q * kProbeTile + tid * kSieveItems;
+            fl[q] = r < r_end ? a.bits[r >> 3] : 0u;
+            packed |= static_cast<uint64_t>(__builtin_popcount(fl[q])) << (16 * q);
+        }
+        uint64_t ptot;
+        const uint64_t pex = block_excl_scan<kProbeBlock>(packed, s_wave64, ptot);
+#pragma unroll
+        for (int q = 0; q < kGroupTiles; ++q) {
+            const uint32_t row0 = g0 + q * kProbeTile + tid * kSieveItems;
+            const uint32_t flags = fl[q];
+            uint32_t o = base + static_cast<uint32_t>((pex >> (16 * q)) & 0xFFFFu);
+            base += static_cast<uint32_t>((ptot >> (16 * q)) & 0xFFFFu);
+            if (!flags) continue;
+            int32_t v[NCOL][kSieveItems];
+            uint32_t rid[kSieveItems];
+            if (row0 + kSieveItems <= n) {
+#pragma unroll
+                for (int c = 0; c < NCOL; ++c) {
+                    const v4i *src = reinterpret_cast<const v4i *>(a.col[c] + row0);
+                    const v4i x0 = src[0], x1 = src[1];
+                    v[c][0] = x0.x; v[c][1] = x0.y; v[c][2] = x0.z; v[c][3] = x0.w;
+                    v[c][4] = x1.x; v[c][5] = x1.y; v[c][6] = x1.z; v[c][7] = x1.w;
+                }
+                if (list) {
+                    const v4u *src = reinterpret_cast<const v4u *>(a.src_rid + row0);
+                    const v4u r0v = src[0], r1v = src[1];
+                    rid[0] = r0v.x; rid[1] = r0v.y; rid[2] = r0v.z; rid[3] = r0v.w;
+                    rid[4] = r1v.x; rid[5] = r1v.y; rid[6] = r1v.z; rid[7] = r1v.w;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < kSieveItems; ++i) rid[i] = row0 + i;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < kSieveItems; ++i) {
+                    const uint32_t r = row0 + i;
+                    const bool in = r < n;
+#pragma unroll
+                    for (int c = 0; c < NCOL; ++c) v[c][i] = in ? a.col[c][r] : 0;
+                    rid[i] = in ? (list ? a.src_rid[r] : r) : 0u;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kSieveItems; ++i) {
+                if (flags & (1u << i)) {
+                    a.out_rid[o] = rid[i];
+#pragma unroll
+                    for (int c = 0; c < NCOL; ++c) a.out_col[c][o] = v[c][i];
+                    ++o;
+                }
+            }
+        }
+    }
+}
+
 // A wave's list of live rows: entry = the row's index inside the wave's rows (9 bits)
 // plus a dead flag.
 constexpr uint16_t kListDead = 0x8000;
@@ -218,12 +291,17 @@ constexpr uint16_t kListDead = 0x8000;
 // KMAX bounds k; with EXACT, k == KMAX and the per-word guards fold away at compile time
 // (k = 2, 4 and 6 have such instances: the per-word checks of a general instance cost
 // about a tenth of a scan).
-template <int NCOL, int KMAX, bool EXACT>
+template <int NCOL, int KMAX, bool EXACT, bool FUSED>
 __global__ __launch_bounds__(kProbeBlock) void k_sieve_step(StepArgs a) {
     // keys whose k words are in flight together (fewer for k > 8, to stay in registers)
     constexpr int kProbeBatch = KMAX > 8 ? kProbeBatchMax / 2 : kProbeBatchMax;
     constexpr int kWaveRows = 64 * kSieveItems;
     __shared__ uint32_t s_wave[kProbeBlock / 64];
+    __shared__ uint32_t s_ticket, s_base;
+    __shared__ uint64_t s_wave64[kProbeBlock / 64];
+    // FUSED: the rows a workgroup owns follow the order in which workgroups started (a
+    // ticket), so every workgroup it waits for below is already running
+    if (FUSED && threadIdx.x == 0) s_ticket = atomicAdd(a.lb.counter, 1u);
     __shared__ uint32_t s_cache[kMaxCached > 0 ? kMaxCached : 1][1 << kCacheLog];
     __shared__ uint16_t s_list[kProbeBlock / 64][kWaveRows];
     extern __shared__ v4u s_filter4[];   // [a.lds_words / 4]
@@ -270,7 +348,8 @@ __global__ __launch_bounds__(kProbeBlock) void k_sieve_step(StepArgs a) {
     const bool list = a.src_rid != nullptr;
     const uint32_t n = list ? *a.src_count : a.src_rows;
     const uint32_t per = sieve_rows_per_group(n);
-    const uint32_t r_end = min(n, (blockIdx.x + 1) * per);
+    const uint32_t wg = FUSED ? s_ticket : blockIdx.x;
+    const uint32_t r_end = min(n, (wg + 1) * per);
     const int tid = threadIdx.x;
     const int lane = lane_id();
     uint16_t *wl = s_list[tid >> 6];
@@ -284,11 +363,11 @@ __global__ __launch_bounds__(kProbeBlock) void k_sieve_step(StepArgs a) {
         if (p == first) fcol = pcol[p];
     int32_t nxt[kSieveItems];
     {
-        const uint32_t t0 = blockIdx.x * per, row0 = t0 + tid * kSieveItems;
+        const uint32_t t0 = wg * per, row0 = t0 + tid * kSieveItems;
         if (t0 < r_end && a.nprobe > 0) load_keys(fcol, row0, n, row0 + kSieveItems <= n, nxt);
     }
 
-    for (uint32_t t0 = blockIdx.x * per; t0 < r_end; t0 += kProbeTile) {
+    for (uint32_t t0 = wg * per; t0 < r_end; t0 += kProbeTile) {
         const uint32_t row0 = t0 + tid * kSieveItems;
         const uint32_t wrow0 = t0 + (tid & ~63) * kSieveItems;   // the wave's first row
         const bool full = row0 + kSieveItems <= n;
@@ -423,7 +502,20 @@ __global__ __launch_bounds__(kProbeBlock) void k_sieve_step(StepArgs a) {
     }
     uint32_t tot;
     block_excl_scan<kProbeBlock>(survivors, s_wave, tot);
-    if (tid == 0) a.counts[blockIdx.x] = tot;
+    if (!FUSED) {
+        if (tid == 0) a.counts[blockIdx.x] = tot;
+        return;
+    }
+    // the survivors of the workgroups before this one (decoupled look-back over the
+    // tickets), then this workgroup's survivors from the bits it wrote
+    if (tid < 64) {
+        const uint32_t b = lookback32_wave(a.lb.status, wg, tot);
+        if (tid == 0) s_base = b;
+    }
+    __syncthreads();
+    const uint32_t base = s_base;
+    if (wg == gridDim.x - 1 && tid == 0) *a.out_count = base + tot;
+    sieve_write_survivors<NCOL>(a, wg * per, r_end, n, base, s_wave64);
 }
 
 
@@ -440,82 +532,18 @@ __global__ __launch_bounds__(kProbeBlock) void k_sieve_compact(StepArgs a) {
     for (uint32_t g = tid; g < blockIdx.x; g += kProbeBlock) before += a.counts[g];
     uint32_t tot;
     block_excl_scan<kProbeBlock>(before, s_wave, tot);
-    uint32_t base = tot;
-    if (blockIdx.x == gridDim.x - 1 && tid == 0) *a.out_count = base + a.counts[blockIdx.x];
-    const uint32_t r_end = min(n, (blockIdx.x + 1) * per);
-    // Four tiles share one block scan: their per-thread survivor counts are packed into
-    // 16-bit fields of one 64-bit value (a tile holds fewer than 2^16 rows), so sparse
-    // survivors cost a quarter of the barriers.
-    constexpr int kGroupTiles = 4;
-    static_assert(kProbeTile < (1 << 16), "a tile's survivor count fits 16 bits");
-    for (uint32_t g0 = blockIdx.x * per; g0 < r_end; g0 += kGroupTiles * kProbeTile) {
-        uint32_t fl[kGroupTiles];
-        uint64_t packed = 0;
-#pragma unroll
-        for (int q = 0; q < kGroupTiles; ++q) {
-            const uint32_t r = g0 + q * kProbeTile + tid * kSieveItems;
-            fl[q] = r < r_end ? a.bits[r >> 3] : 0u;
-            packed |= static_cast<uint64_t>(__builtin_popcount(fl[q])) << (16 * q);
-        }
-        uint64_t ptot;
-        const uint64_t pex = block_excl_scan<kProbeBlock>(packed, s_wave64, ptot);
-#pragma unroll
-        for (int q = 0; q < kGroupTiles; ++q) {
-            const uint32_t row0 = g0 + q * kProbeTile + tid * kSieveItems;
-            const uint32_t flags = fl[q];
-            uint32_t o = base + static_cast<uint32_t>((pex >> (16 * q)) & 0xFFFFu);
-            base += static_cast<uint32_t>((ptot >> (16 * q)) & 0xFFFFu);
-            if (!flags) continue;
-            int32_t v[NCOL][kSieveItems];
-            uint32_t rid[kSieveItems];
-            if (row0 + kSieveItems <= n) {
-#pragma unroll
-                for (int c = 0; c < NCOL; ++c) {
-                    const v4i *src = reinterpret_cast<const v4i *>(a.col[c] + row0);
-                    const v4i x0 = src[0], x1 = src[1];
-                    v[c][0] = x0.x; v[c][1] = x0.y; v[c][2] = x0.z; v[c][3] = x0.w;
-                    v[c][4] = x1.x; v[c][5] = x1.y; v[c][6] = x1.z; v[c][7] = x1.w;
-                }
-                if (list) {
-                    const v4u *src = reinterpret_cast<const v4u *>(a.src_rid + row0);
-                    const v4u r0 = src[0], r1 = src[1];
-                    rid[0] = r0.x; rid[1] = r0.y; rid[2] = r0.z; rid[3] = r0.w;
-                    rid[4] = r1.x; rid[5] = r1.y; rid[6] = r1.z; rid[7] = r1.w;
-                } else {
-#pragma unroll
-                    for (int i = 0; i < kSieveItems; ++i) rid[i] = row0 + i;
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < kSieveItems; ++i) {
-                    const uint32_t r = row0 + i;
-                    const bool in = r < n;
-#pragma unroll
-                    for (int c = 0; c < NCOL; ++c) v[c][i] = in ? a.col[c][r] : 0;
-                    rid[i] = in ? (list ? a.src_rid[r] : r) : 0u;
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < kSieveItems; ++i) {
-                if (flags & (1u << i)) {
-                    a.out_rid[o] = rid[i];
-#pragma unroll
-                    for (int c = 0; c < NCOL; ++c) a.out_col[c][o] = v[c][i];
-                    ++o;
-                }
-            }
-        }
-    }
+    if (blockIdx.x == gridDim.x - 1 && tid == 0) *a.out_count = tot + a.counts[blockIdx.x];
+    sieve_write_survivors<NCOL>(a, blockIdx.x * per, min(n, (blockIdx.x + 1) * per), n, tot, s_wave64);
 }
 
-template <int KMAX, bool EXACT>
+template <int KMAX, bool EXACT, bool FUSED>
 static hipError_t launch_probe_k(const StepArgs &a, hipStream_t s) {
     if (a.grid == 0 || a.grid > kProbeGridMax) return hipErrorInvalidValue;
     const dim3 g(a.grid), b(kProbeBlock);
     const size_t lds = 4ull * a.lds_words;
     switch (a.ncol) {
 #define SJ_PROBE_CASE(NC) \
-    case NC: hipLaunchKernelGGL((k_sieve_step<NC, KMAX, EXACT>), g, b, lds, s, a); break;
+    case NC: hipLaunchKernelGGL((k_sieve_step<NC, KMAX, EXACT, FUSED>), g, b, lds, s, a); break;
         SJ_PROBE_CASE(1) SJ_PROBE_CASE(2) SJ_PROBE_CASE(3) SJ_PROBE_CASE(4)
         SJ_PROBE_CASE(5) SJ_PROBE_CASE(6) SJ_PROBE_CASE(7) SJ_PROBE_CASE(8)
 #undef SJ_PROBE_CASE
@@ -524,14 +552,25 @@ static hipError_t launch_probe_k(const StepArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <bool FUSED>
+static hipError_t launch_probe_any(const StepArgs &a, hipStream_t s) {
+    switch (a.k) {
+    case 2: return launch_probe_k<2, true, FUSED>(a, s);
+    case 4: return launch_probe_k<4, true, FUSED>(a, s);
+    case 6: return launch_probe_k<6, true, FUSED>(a, s);
+    default: return a.k <= 8 ? launch_probe_k<8, false, FUSED>(a, s) : launch_probe_k<kMaxK, false, FUSED>(a, s);
+    }
+}
+
 hipError_t launch_sieve_probe(const StepArgs &a, uint32_t max_rows, hipStream_t s) {
     if (max_rows == 0) return hipSuccess;
-    switch (a.k) {
-    case 2: return launch_probe_k<2, true>(a, s);
-    case 4: return launch_probe_k<4, true>(a, s);
-    case 6: return launch_probe_k<6, true>(a, s);
-    default: return a.k <= 8 ? launch_probe_k<8, false>(a, s) : launch_probe_k<kMaxK, false>(a, s);
-    }
+    return launch_probe_any<false>(a, s);
+}
+
+hipError_t launch_sieve_fused(const StepArgs &a, uint32_t max_rows, hipStream_t s) {
+    if (max_rows == 0) return hipSuccess;
+    if (!a.out_rid || !a.lb.status || !a.lb.counter) return hipErrorInvalidValue;
+    return launch_probe_any<true>(a, s);
 }
 
 hipError_t launch_sieve_compact(const StepArgs &a, uint32_t max_rows, hipStream_t s) {

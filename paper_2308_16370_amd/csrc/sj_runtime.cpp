@@ -77,6 +77,7 @@ struct StepSpec {
     uint64_t off_count = 0;
     uint32_t max_rows = 0;
     std::vector<uint64_t> off_bstatus, off_bcounter, off_btotal;   // per build
+    uint64_t off_pstatus = 0, off_pcounter = 0;                   // look-back of the one-launch scan
     int level = 0;             // steps of one phase and level are independent of each other
     int branch = 0;            // its branch stream and scratch set inside the level
     bool alone = false;        // the only step of its level: its builds take a branch each
@@ -551,6 +552,8 @@ static void build_layout(sj_plan_t *p) {
             s.max_rows = p->rels[s.rel].nrows;
             max_rows[s.branch] = std::max(max_rows[s.branch], s.max_rows);
             s.off_count = L.take(4);
+            s.off_pstatus = L.take(8ull * kProbeGridMax);
+            s.off_pcounter = L.take(4);
             s.off_bstatus.clear();
             s.off_bcounter.clear();
             s.off_btotal.clear();
@@ -772,7 +775,7 @@ extern "C" sj_status sj_plan(sj_ctx *ctx, const sj_rel *rels, int32_t nrels, con
     if (o.probe_lds > 2) return fail(ctx, SJ_ERR_INVALID, "probe_lds must be 0, 1 or 2");
     if (o.flags & ~static_cast<uint32_t>(SJ_FLAG_PROFILE | SJ_FLAG_EAGER | SJ_FLAG_BINARY_CYCLES |
                                          SJ_FLAG_FAULT_FILTERS | SJ_FLAG_FAULT_SIEVE | SJ_FLAG_FAULT_JOIN |
-                                         SJ_FLAG_FAULT_RESULT))
+                                         SJ_FLAG_FAULT_RESULT | SJ_FLAG_SIEVE_TWO_LAUNCHES))
         return fail(ctx, SJ_ERR_INVALID, "unknown flags");
 
     sj_plan_t *p = new (std::nothrow) sj_plan_t;
@@ -1001,7 +1004,7 @@ static hipEvent_t prof_event(sj_plan_t *p) {
 // What a profiled launch group is, for its algorithmic-byte model.
 // kProfBuckets and kProfDp carry the relation index in the record's `step` field.
 enum ProfKind { kProfOther = 0, kProfProbe = 1, kProfCompact = 2, kProfResult = 3, kProfBuckets = 4, kProfDp = 5,
-                kProfBuild0 = 16 };
+                kProfScan = 6, kProfBuild0 = 16 };
 
 struct ProfScope {
     sj_plan_t *p;
@@ -1070,13 +1073,19 @@ static sj_status run_step(sj_plan_t *p, StepSpec &st, hipStream_t s) {
         a.grid = p->opts.probe_grid;
         a.bits = at<uint8_t>(p, p->off_sbits[set]);
         a.counts = at<uint32_t>(p, p->off_scounts[set]);
+        a.lb.status = at<uint64_t>(p, st.off_pstatus);
+        a.lb.counter = at<uint32_t>(p, st.off_pcounter);
         a.seed = p->seed32;
         a.k = static_cast<int>(p->opts.k);
         a.logB = p->logB;
         const std::string tag = std::string(st.phase == 0 ? "bwd" : "sieve") + ":" + rel_name(st.rel) + ":" +
                                 std::to_string(&st - p->steps.data());
         const int si = static_cast<int>(&st - p->steps.data());
-        if (a.nprobe > 0 || st.out >= 0) {
+        if (st.out >= 0 && !(p->opts.flags & SJ_FLAG_SIEVE_TWO_LAUNCHES)) {
+            // probe and survivor list in one launch
+            ProfScope ps(p, "probe:" + tag, si, kProfScan);
+            SJ_HIP(p->ctx, launch_sieve_fused(a, st.max_rows, s));
+        } else if (a.nprobe > 0 || st.out >= 0) {
             {
                 ProfScope ps(p, "probe:" + tag, si, kProfProbe);
                 SJ_HIP(p->ctx, launch_sieve_probe(a, st.max_rows, s));
@@ -2655,19 +2664,23 @@ extern "C" sj_status sj_profile_collect(sj_plan_t *p) {
             if (st.out >= 0) SJ_HIP(p->ctx, hipMemcpy(&nout, at<uint32_t>(p, st.off_count), 4, hipMemcpyDeviceToHost));
             const uint64_t fbytes = p->opts.block_bits / 8;
             uint64_t bytes = 0;
+            // the probe: probed columns (+ the predicate column of a full scan) read, each
+            // probed filter read once; the survivor list: each survivor's columns (+ row id
+            // of a list source) read and its row id and columns written; between the two
+            // launches of the two-launch form, one survivor bit per row written and read
+            uint32_t used = 0;
+            for (auto &pr : st.probes) used |= 1u << pr.first;
+            const uint64_t pcols = __builtin_popcount(used) + (!listsrc && R.pred_col >= 0 ? 1 : 0);
+            uint64_t probe_bytes = uint64_t(nin) * 4 * pcols;
+            for (auto &pr : st.probes) probe_bytes += uint64_t(nb[pr.second]) * fbytes;
+            const uint64_t list_bytes = uint64_t(nout) * 4 * (ncol + (listsrc ? 1 : 0)) + uint64_t(nout) * 4 * (ncol + 1);
+            const uint64_t bit_bytes = (uint64_t(nin) + 7) / 8;
             if (r.kind == kProfProbe) {
-                // probed columns (+ the predicate column of a full scan) read, survivor
-                // bits written, each probed filter read once
-                uint32_t used = 0;
-                for (auto &pr : st.probes) used |= 1u << pr.first;
-                const uint64_t cols = __builtin_popcount(used) + (!listsrc && R.pred_col >= 0 ? 1 : 0);
-                bytes = uint64_t(nin) * 4 * cols + (uint64_t(nin) + 7) / 8;
-                for (auto &pr : st.probes) bytes += uint64_t(nb[pr.second]) * fbytes;
+                bytes = probe_bytes + bit_bytes;
             } else if (r.kind == kProfCompact) {
-                // survivor bits read; each survivor's columns (+ row id of a list source)
-                // read and its row id and columns written
-                bytes = (uint64_t(nin) + 7) / 8 + uint64_t(nout) * 4 * (ncol + (listsrc ? 1 : 0)) +
-                        uint64_t(nout) * 4 * (ncol + 1);
+                bytes = bit_bytes + list_bytes;
+            } else if (r.kind == kProfScan) {
+                bytes = probe_bytes + list_bytes;
             } else if (r.kind >= kProfBuild0) {
                 // keys read once (with the predicate column of a full scan): by the count and
                 // the scatter stages; the staged keys: written by the scatter, read by the

@@ -86,7 +86,7 @@ def test_valid_chain_plans():
     ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"B": 384}, sj.SJ_ERR_INVALID),
     ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"passes": 3}, sj.SJ_ERR_INVALID),
     ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"root": 2}, sj.SJ_ERR_INVALID),
-    ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"flags": 128}, sj.SJ_ERR_INVALID),
+    ([(10, 2, None)] * 2, [(0, 1, 1, 0)], {"flags": 256}, sj.SJ_ERR_INVALID),
     ([(2**31, 2, None)] * 2, [(0, 1, 1, 0)], {}, sj.SJ_ERR_INVALID),
     # nine children on one column: the root's step would probe nine filters
     ([(10, 1, None)] * 10, [(0, 0, i, 0) for i in range(1, 10)], {}, sj.SJ_ERR_UNSUPPORTED),
@@ -175,11 +175,12 @@ def test_projection_and_footprint():
 
 
 def test_fault_flags_are_accepted_and_unknown_flags_refused():
-    for flag in (sj.SJ_FLAG_FAULT_FILTERS, sj.SJ_FLAG_FAULT_SIEVE, sj.SJ_FLAG_FAULT_JOIN, sj.SJ_FLAG_FAULT_RESULT):
+    for flag in (sj.SJ_FLAG_FAULT_FILTERS, sj.SJ_FLAG_FAULT_SIEVE, sj.SJ_FLAG_FAULT_JOIN, sj.SJ_FLAG_FAULT_RESULT,
+                 sj.SJ_FLAG_SIEVE_TWO_LAUNCHES):
         st, p, ws, ctx, err = plan([(10, 1, None)] * 2, [(0, 0, 1, 0)], flags=flag)
         assert st == 0, err
         sj.lib().sj_plan_destroy(p)
-    st, p, ws, ctx, err = plan([(10, 1, None)] * 2, [(0, 0, 1, 0)], flags=128)
+    st, p, ws, ctx, err = plan([(10, 1, None)] * 2, [(0, 0, 1, 0)], flags=256)
     assert st == sj.SJ_ERR_INVALID
 
 

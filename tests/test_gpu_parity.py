@@ -15,8 +15,8 @@ from sjtest import check_sieve, check_sorted_in_preorder, lexsort_rows, make_pla
 pytestmark = pytest.mark.gpu
 
 
-def run_and_compare(q, bits_per_key=8, k=6, block_bits=512, passes=2, seed=7, sieve=True):
-    plan = make_plan(q, bits_per_key=bits_per_key, k=k, block_bits=block_bits, passes=passes, seed=seed)
+def run_and_compare(q, bits_per_key=8, k=6, block_bits=512, passes=2, seed=7, sieve=True, **opts):
+    plan = make_plan(q, bits_per_key=bits_per_key, k=k, block_bits=block_bits, passes=passes, seed=seed, **opts)
     plan.build_filters()
     plan.sieve()
     if sieve:
@@ -91,6 +91,19 @@ def test_exact_k_instances(k):
     against the oracle at 100K rows per relation (many tiles per scan)."""
     q = W.config2(scale=0.01)
     run_and_compare(q, bits_per_key=8, k=k, seed=9)
+
+
+@pytest.mark.parametrize("two_launches", [False, True])
+@pytest.mark.parametrize("grid", [64, 256, 1024])
+def test_sieve_scan_launch_forms(two_launches, grid):
+    """A sieve step that writes a survivor list runs as one launch (each workgroup takes a
+    ticket and finds its output offset by a look-back over the workgroups before it) or,
+    with SJ_FLAG_SIEVE_TWO_LAUNCHES, as a probe and a compaction launch; both against the
+    oracle's survivors and tuples, over grids of 64 to 1024 workgroups (1024 workgroups
+    do not all fit on the device at once) and ragged row counts."""
+    q = W.config2(scale=0.013)
+    run_and_compare(q, bits_per_key=8, k=6, seed=11, probe_grid=grid,
+                    flags=sj.SJ_FLAG_SIEVE_TWO_LAUNCHES if two_launches else 0)
 
 
 def test_star_reduced():
