@@ -364,10 +364,15 @@ sj_status sj_profile_count(const sj_plan_t *plan, int32_t *n);
 /* Label i (valid until the plan is destroyed), its total milliseconds and launch
  * count, and the algorithmic bytes of its last launch (0 where not modelled). Labels
  * name one kernel each where a byte model exists:
- *   "probe:..."         probed columns (and the predicate column of a full scan) read,
- *                       one survivor bit per row written, each probed filter read once;
- *   "compact:..."       survivor bits read, each survivor's columns (and the row id of
- *                       a survivor-list source) read, its row id and columns written;
+ *   "probe:..."         a sieve step: probed columns (and the predicate column of a
+ *                       full scan) read, each probed filter read once; each survivor's
+ *                       columns (and the row id of a survivor-list source) read, its row
+ *                       id and columns written. With SJ_FLAG_SIEVE_TWO_LAUNCHES (or for
+ *                       a step that writes no list) the probe launch alone: the probe's
+ *                       reads and one survivor bit per row written;
+ *   "compact:..."       (SJ_FLAG_SIEVE_TWO_LAUNCHES) survivor bits read, each survivor's
+ *                       columns (and row id of a list source) read, its row id and
+ *                       columns written;
  *   "bfb_hist:..."      filter build, region counts: the inserted keys (and the
  *                       predicate column of a full scan) read;
  *   "bfb_scatter:..."   the keys read again, each kept key staged (4 bytes);

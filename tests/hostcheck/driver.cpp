@@ -249,6 +249,7 @@ void scenario_chain() {
     Query q = chain(4, 1000);
     all_modes("chain4", q);
     all_modes("chain4 one pass", q, 1);
+    all_modes("chain4 sieve in two launches", q, 2, SJ_FLAG_SIEVE_TWO_LAUNCHES);
     Query e = chain(2, 0);   // empty relations
     all_modes("empty chain", e);
 }
