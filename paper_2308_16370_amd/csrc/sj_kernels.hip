@@ -124,11 +124,20 @@ hipError_t launch_filter_update(const FilterUpdate &u, bool set, hipStream_t s) 
 #define SJ_CACHE_LOG 13
 #endif
 #ifndef SJ_PROBE_BATCH
-#define SJ_PROBE_BATCH 4
+#define SJ_PROBE_BATCH 2
+#endif
+#ifndef SJ_LDS_BATCH
+#define SJ_LDS_BATCH 2
+#endif
+#ifndef SJ_LIST_BATCH
+#define SJ_LIST_BATCH 2
 #endif
 constexpr int kMaxCached = SJ_MAX_CACHED;
 constexpr int kCacheLog = SJ_CACHE_LOG;
-constexpr int kProbeBatchMax = SJ_PROBE_BATCH;
+constexpr int kProbeBatchMax = SJ_PROBE_BATCH;   // keys per batch of the first probe from memory
+constexpr int kLdsBatchMax = SJ_LDS_BATCH;       // ... of the first probe from an LDS filter
+constexpr int kListBatchMax = SJ_LIST_BATCH;     // list entries per batch of the later probes
+static_assert(kProbeBatchMax >= 1 && kLdsBatchMax >= 1 && kListBatchMax >= 1, "probe batches");
 constexpr uint32_t kCacheMul = 0x9E3779B1u;
 constexpr uint32_t kCacheOk = 1u, kCacheValid = 2u;
 constexpr uint32_t kCacheFlags = (1u << kCacheLog) - 1u;
@@ -294,7 +303,9 @@ constexpr uint16_t kListDead = 0x8000;
 template <int NCOL, int KMAX, bool EXACT, bool FUSED>
 __global__ __launch_bounds__(kProbeBlock) void k_sieve_step(StepArgs a) {
     // keys whose k words are in flight together (fewer for k > 8, to stay in registers)
-    constexpr int kProbeBatch = KMAX > 8 ? kProbeBatchMax / 2 : kProbeBatchMax;
+    constexpr int kProbeBatch = KMAX > 8 && kProbeBatchMax > 1 ? kProbeBatchMax / 2 : kProbeBatchMax;
+    constexpr int kLdsBatch = KMAX > 8 && kLdsBatchMax > 1 ? kLdsBatchMax / 2 : kLdsBatchMax;
+    static_assert(kSieveItems % kProbeBatch == 0 && kSieveItems % kLdsBatch == 0, "batches split a lane's rows");
     constexpr int kWaveRows = 64 * kSieveItems;
     __shared__ uint32_t s_wave[kProbeBlock / 64];
     __shared__ uint32_t s_ticket, s_base;
@@ -396,10 +407,10 @@ __global__ __launch_bounds__(kProbeBlock) void k_sieve_step(StepArgs a) {
             if (pl >= 0) {
                 // the LDS filter: all k words of a batch's keys are read before any is tested
 #pragma unroll
-                for (int i0 = 0; i0 < kSieveItems; i0 += kProbeBatch) {
-                    uint32_t w[kProbeBatch][KMAX], g[kProbeBatch];
+                for (int i0 = 0; i0 < kSieveItems; i0 += kLdsBatch) {
+                    uint32_t w[kLdsBatch][KMAX], g[kLdsBatch];
 #pragma unroll
-                    for (int ii = 0; ii < kProbeBatch; ++ii) {
+                    for (int ii = 0; ii < kLdsBatch; ++ii) {
                         const BfKey h = bf_hash(key[i0 + ii], a.seed, nb_l);
                         g[ii] = h.g;
                         const uint32_t *b = s_filter + (h.block << wpb_shift);
@@ -408,7 +419,7 @@ __global__ __launch_bounds__(kProbeBlock) void k_sieve_step(StepArgs a) {
                             if (j < (EXACT ? KMAX : a.k)) w[ii][j] = b[((h.g * bf_mult(j)) >> sh) >> 5];
                     }
 #pragma unroll
-                    for (int ii = 0; ii < kProbeBatch; ++ii) {
+                    for (int ii = 0; ii < kLdsBatch; ++ii) {
                         uint32_t ok = 1u;
 #pragma unroll
                         for (int j = 0; j < KMAX; ++j)
@@ -447,7 +458,8 @@ __global__ __launch_bounds__(kProbeBlock) void k_sieve_step(StepArgs a) {
             // a lane keeps its list entries through every probe: the keys of all of them are
             // loaded together (one column-load latency per batch), and an entry's liveness
             // stays in registers from one probe to the next
-            constexpr int kLB = NCOL >= 3 ? 2 : kProbeBatch;   // list batch (registers for NCOL keys each)
+            constexpr int kLB = NCOL >= 3 ? (kListBatchMax < 2 ? kListBatchMax : 2)
+                                          : (KMAX > 8 && kListBatchMax > 1 ? kListBatchMax / 2 : kListBatchMax);   // list batch (registers for NCOL keys each)
             for (uint32_t e0 = lane; e0 < total; e0 += 64u * kLB) {
                 bool live[kLB], live0[kLB];
                 uint16_t ent[kLB];
