@@ -36,6 +36,22 @@ constexpr int kRadixPasses = 64 / kRadixBits;   // a 64-bit composite key at mos
 constexpr int kRadixBlock = 256;
 constexpr int kRadixItems = 8;
 constexpr int kRadixTile = kRadixBlock * kRadixItems;
+// Lists of up to kRadixSmallN entries are sorted in tiles of kRadixItemsSmall items per
+// thread: more workgroups take part (a 390K-entry list is 762 tiles instead of 191),
+// while larger lists keep the larger tiles and their smaller per-tile histograms.
+constexpr int kRadixItemsSmall = 2;
+constexpr uint32_t kRadixSmallN = 1u << 20;
+__host__ __device__ inline uint32_t radix_tile(uint32_t n) {
+    return n <= kRadixSmallN ? static_cast<uint32_t>(kRadixBlock * kRadixItemsSmall) : static_cast<uint32_t>(kRadixTile);
+}
+// The most tiles a list of any n <= cap entries takes.
+__host__ __device__ inline uint32_t radix_tiles_max(uint32_t cap) {
+    const uint32_t small = cap < kRadixSmallN ? cap : kRadixSmallN;
+    const uint32_t ts = kRadixBlock * kRadixItemsSmall;
+    const uint32_t a = (small + ts - 1) / ts;
+    const uint32_t b = (cap + kRadixTile - 1) / kRadixTile;
+    return a > b ? a : b;
+}
 
 constexpr int kPersistentBlocks = 256 * 8;  // 256 CUs, a few resident blocks each
 

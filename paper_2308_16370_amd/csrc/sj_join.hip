@@ -113,7 +113,9 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_hist(int pass, KeySrc ks,
     if (!ss.ctl[pass]) return;
     __shared__ uint32_t h[kRadixBins];
     const uint32_t n = *n_ptr;
-    const uint32_t ntiles = (n + kRadixTile - 1) / kRadixTile;
+    const uint32_t T = radix_tile(n);
+    const int items = static_cast<int>(T / kRadixBlock);
+    const uint32_t ntiles = (n + T - 1) / T;
     const RadixIo io = radix_io(ss, ks, pass);
     const uint32_t *w = pass < 4 ? io.slo : io.shi;
     const int shift = (pass & 3) * kRadixBits;
@@ -123,8 +125,8 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_hist(int pass, KeySrc ks,
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kRadixItems; ++i) {
-            const uint32_t e = tile * kRadixTile + i * kRadixBlock + threadIdx.x;
-            if (e < n) atomicAdd(&h[(w[e] >> shift) & (kRadixBins - 1)], 1u);
+            const uint32_t e = tile * T + i * kRadixBlock + threadIdx.x;
+            if (i < items && e < n) atomicAdd(&h[(w[e] >> shift) & (kRadixBins - 1)], 1u);
         }
         __syncthreads();
         ss.hist[threadIdx.x * ntiles + tile] = h[threadIdx.x];
@@ -132,14 +134,16 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_hist(int pass, KeySrc ks,
     }
 }
 
-// Exclusive scan in place of data[0 .. mul * ceil(n / div)), u32, decoupled look-back.
+// Exclusive scan in place of data[0 .. mul * ceil(n / div)), u32, decoupled look-back
+// (div 0: the radix sort's tile for n entries).
 __global__ __launch_bounds__(kScanBlock) void k_scan_u32(uint32_t *data, const uint32_t *n_ptr, uint32_t div,
                                                          uint32_t mul, const uint32_t *active, Lookback lb) {
     if (active && !*active) return;
     __shared__ uint32_t s_tile, s_base;
     __shared__ uint32_t s_wave[kScanBlock / 64];
     const uint32_t n = *n_ptr;
-    const uint32_t len = mul * ((n + div - 1) / div);
+    const uint32_t d = div ? div : radix_tile(n);
+    const uint32_t len = mul * ((n + d - 1) / d);
     const uint32_t ntiles = (len + kScanTile - 1) / kScanTile;
     while (true) {
         if (threadIdx.x == 0) s_tile = atomicAdd(lb.counter, 1u);
@@ -183,7 +187,9 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(int pass, KeySrc 
     __shared__ uint32_t s_run[kRadixBins];
     __shared__ uint32_t s_cnt[kWaves][kRadixBins];
     const uint32_t n = *n_ptr;
-    const uint32_t ntiles = (n + kRadixTile - 1) / kRadixTile;
+    const uint32_t T = radix_tile(n);
+    const int items = static_cast<int>(T / kRadixBlock);
+    const uint32_t ntiles = (n + T - 1) / T;
     const RadixIo io = radix_io(ss, ks, pass);
     const int shift = (pass & 3) * kRadixBits;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -195,8 +201,8 @@ __global__ __launch_bounds__(kRadixBlock) void k_radix_scatter(int pass, KeySrc 
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) s_cnt[w][tid] = 0;
         __syncthreads();
-        for (int i = 0; i < kRadixItems; ++i) {
-            const uint32_t e = tile * kRadixTile + i * kRadixBlock + tid;
+        for (int i = 0; i < items; ++i) {
+            const uint32_t e = tile * T + i * kRadixBlock + tid;
             const bool valid = e < n;
             const uint32_t klo = valid ? io.slo[e] : 0u;
             const uint32_t khi = (valid && io.shi) ? io.shi[e] : 0u;
@@ -338,7 +344,7 @@ hipError_t launch_build_buckets(const uint32_t *list_rid, const int32_t *const *
     ks.lo = list_cols[sec_col >= 0 ? sec_col : key_col];
     ks.hi = sec_col >= 0 ? list_cols[key_col] : nullptr;
     const int npasses = sec_col >= 0 ? 8 : 4;
-    const uint32_t tiles = (cap + kRadixTile - 1) / kRadixTile;
+    const uint32_t tiles = radix_tiles_max(cap);
     const uint32_t tgrid = tiles < kPersistentBlocks ? tiles : kPersistentBlocks;
     // few workgroups: every workgroup adds its histogram to the same 256 x passes counters
     hipLaunchKernelGGL(k_radix_ghist, dim3(grid_for(cap, 256 * 16, 128)), dim3(kRadixBlock), 0, s, ks,
@@ -349,8 +355,8 @@ hipError_t launch_build_buckets(const uint32_t *list_rid, const int32_t *const *
     const uint32_t scan_grid = grid_for(scan_len_max, kScanTile, 256);
     for (int p = 0; p < npasses; ++p) {
         hipLaunchKernelGGL(k_radix_hist, dim3(tgrid), dim3(kRadixBlock), 0, s, p, ks, ss, list_count);
-        hipLaunchKernelGGL(k_scan_u32, dim3(scan_grid), dim3(kScanBlock), 0, s, ss.hist, list_count,
-                           static_cast<uint32_t>(kRadixTile), static_cast<uint32_t>(kRadixBins), ss.ctl + p, ss.lb[p]);
+        hipLaunchKernelGGL(k_scan_u32, dim3(scan_grid), dim3(kScanBlock), 0, s, ss.hist, list_count, 0u,
+                           static_cast<uint32_t>(kRadixBins), ss.ctl + p, ss.lb[p]);
         hipLaunchKernelGGL(k_radix_scatter, dim3(tgrid), dim3(kRadixBlock), 0, s, p, ks, ss, list_count);
     }
     ListRef l;

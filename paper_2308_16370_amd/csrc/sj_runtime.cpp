@@ -593,7 +593,7 @@ static void build_layout(sj_plan_t *p) {
         auto &r = p->jr[j];
         const uint32_t cap = p->rels[j].nrows;
         r.ghist = L.take(4ull * kRadixPasses * kRadixBins);
-        const uint32_t htiles = tiles_of(kRadixBins * tiles_of(cap, kRadixTile), kScanTile);
+        const uint32_t htiles = tiles_of(kRadixBins * radix_tiles_max(cap), kScanTile);
         for (int q = 0; q < kRadixPasses; ++q) {
             r.lb_hist[q] = L.take(8ull * std::max<uint32_t>(1, htiles));
             r.lb_hist_ctr[q] = L.take(4);
@@ -640,7 +640,7 @@ static void build_layout(sj_plan_t *p) {
             r.skhi[b] = two_word ? L.take(4 * cap) : 0;
             r.svals[b] = L.take(4 * cap);
         }
-        r.shist = L.take(4ull * kRadixBins * std::max<uint32_t>(1, tiles_of(static_cast<uint32_t>(cap), kRadixTile)));
+        r.shist = L.take(4ull * kRadixBins * std::max<uint32_t>(1, radix_tiles_max(static_cast<uint32_t>(cap))));
         r.sctl = L.take(4 * 32);
         r.tsums = L.take(16ull * std::max<uint32_t>(1, tiles_of(static_cast<uint32_t>(cap),
                                                                    dp_tile(static_cast<int>(p->children[j].size())))));
