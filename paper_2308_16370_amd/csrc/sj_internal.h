@@ -257,11 +257,13 @@ hipError_t launch_build_buckets(const uint32_t *list_rid, const int32_t *const *
 
 // Per-entry DP weights of a bucketed relation (or the root list), scanned into
 // cw/cv. child[c] is the bucketed child joined on list column child_col[c].
-// DP lookups in flight per thread: ITEMS entries times CH children, ITEMS * CH = kDpSlots.
-// A relation with more children takes fewer entries per thread (and smaller tiles of
-// kScanBlock * ITEMS entries), so all of its children are looked up together.
+// A thread holds ITEMS entries (tiles of kScanBlock * ITEMS entries) and looks them up
+// in up to CH = kDpSlots / ITEMS children at once. Few entries per thread spread a
+// relation of a few hundred thousand entries over many more workgroups than CUs: a
+// relation with one child takes 2 entries per thread, one with more children 1 entry
+// with all of its children looked up together.
 constexpr int kDpSlots = 8;
-inline int dp_items(int nchild) { return nchild <= 1 ? 8 : nchild == 2 ? 4 : nchild <= 4 ? 2 : 1; }
+inline int dp_items(int nchild) { return nchild <= 1 ? 2 : 1; }
 inline uint32_t dp_tile(int nchild) { return static_cast<uint32_t>(kScanBlock * dp_items(nchild)); }
 
 struct DpArgs {

@@ -376,9 +376,10 @@ hipError_t launch_build_buckets(const uint32_t *list_rid, const int32_t *const *
 //
 // A thread holds ITEMS entries and looks them up in CH = kDpSlots / ITEMS children at
 // once, so every lookup stage (key, hash slot, directory bounds, child prefix weights)
-// has kDpSlots independent loads in flight and the dependent chain is four stages per
-// group of CH children. A relation with one child takes 8 entries per thread; one with
-// four children takes 2 entries of all four children (dp_items). A slot that holds
+// has up to kDpSlots independent loads in flight and the dependent chain is four stages
+// per group of CH children. A relation with one child takes 2 entries per thread; one
+// with more children 1 entry of all its children (dp_items): small tiles keep every CU
+// busy on the relations of a few hundred thousand entries a sieve leaves. A slot that holds
 // another key (rare: the index is at most half full) is resolved by linear probing. A
 // thread's entries are kScanBlock apart (entry tile * tile size + i * kScanBlock +
 // thread), so the loads of one stage are consecutive across a wave; only the tile's
@@ -587,8 +588,6 @@ static void launch_dp_items(const DpArgs &a, hipStream_t s) {
 hipError_t launch_dp(const DpArgs &a, hipStream_t s) {
     if (a.nchild < 0 || a.nchild > kMaxJCols) return hipErrorInvalidValue;
     switch (dp_items(a.nchild)) {
-    case 8: launch_dp_items<8>(a, s); break;
-    case 4: launch_dp_items<4>(a, s); break;
     case 2: launch_dp_items<2>(a, s); break;
     default: launch_dp_items<1>(a, s); break;
     }
