@@ -106,6 +106,22 @@ def test_sieve_scan_launch_forms(two_launches, grid):
                     flags=sj.SJ_FLAG_SIEVE_TWO_LAUNCHES if two_launches else 0)
 
 
+@pytest.mark.parametrize("n1", [(1 << 20) - 1, 1 << 20, (1 << 20) + 1])
+def test_bucket_sort_tile_boundary(n1):
+    """The radix sort of a bucketed relation takes 512-entry tiles up to 2^20 entries and
+    2048-entry tiles above, chosen on the device from the sieved count. R0 holds every key
+    of a 2^19-key domain once, so every row of R1 survives and R1's bucketed list is
+    exactly n1 entries: filters, survivors, count, checksum and tuples against the oracle
+    on both sides of the switch."""
+    rng = np.random.default_rng(n1)
+    d = 1 << 19
+    r0 = W.Relation("R0", [rng.permutation(d).astype(np.int32)])
+    r1 = W.Relation("R1", [rng.integers(0, d, n1).astype(np.int32)])
+    q = W.Query("tile_boundary", [r0, r1], [(0, 0, 1, 0)], 0)
+    plan, tup = run_and_compare(q, seed=3)
+    assert tup.shape[0] == n1
+
+
 def test_star_reduced():
     q = W.config3(scale=0.01)
     plan, tup = run_and_compare(q, bits_per_key=8, k=6, seed=5)
